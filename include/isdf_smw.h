@@ -1,0 +1,185 @@
+/*
+ * isdf_smw.h -- C ABI of the MI355X (gfx950) ISDF-SMW dielectric-inverse library.
+ *
+ * The library computes the inverse of the symmetrised dielectric matrix
+ *     eps~ = I - V^{1/2} chi0 V^{1/2}
+ * in a plane-wave basis, with chi0 = f M_vc W M_vc^H built from the
+ * valence-conduction pair products M_vc(r; i, j) = conj(psi_i(r)) psi_j(r)
+ * (paper, Sec. 2, eq. matrices and eq. Omega) and W = diag(w_ij),
+ * w_ij = Delta_ij / (Delta_ij^2 + omega^2), Delta_ij = eps_i - eps_j < 0
+ * (omega = 0: the static Omega^{-1}; omega > 0: the imaginary-frequency
+ * weight that follows from the two pole terms of eq. Hedin_fourier).
+ *
+ * The method (paper, Sec. "ISDF" and Sec. "SMW formula combined with ISDF",
+ * eq. epsilon_with_SMW, and the matrix K of Sec. "Cubic scaling algorithm"):
+ *   1. ISDF fit: M_vc ~ Theta C, C(mu; i, j) = conj(psi_i(r_mu)) psi_j(r_mu)
+ *      (eq. ISDF, eq. MatrixExpressionISDF), Theta the least-squares fit
+ *      Theta (C C^H) = M_vc C^H, whose two factors are Hadamard products of
+ *      orbital Gram blocks (the identity of eq. Hadamard);
+ *   2. core M = f C W C^H (eq. COmegaCstar times f), N_mu x N_mu;
+ *   3. Coulomb-weighted U = V^{1/2} (F Theta) on the plane-wave list, with F
+ *      the unitary grid DFT, and U^H U = Theta^H V Theta;
+ *   4. SMW: eps~^{-1} = I + U (M^{-1} - U^H U)^{-1} U^H.
+ *
+ * Conventions shared by every entry point
+ *   - All functions return isdf_status.  No exception crosses the ABI.
+ *   - "device" pointers are HIP device memory on the handle's device; "host"
+ *     pointers are ordinary host memory, read before the call returns.
+ *   - The caller owns every input, output and workspace buffer.  The library
+ *     allocates no device memory after isdf_create and frees no caller memory.
+ *   - Work is enqueued on the handle's stream.  Entry points that produce a
+ *     result synchronise that stream once at the end to read the device status
+ *     word; outputs are unspecified when the return value is not ISDF_OK.
+ *   - Argument errors are found on the host before anything is enqueued
+ *     (ISDF_E_ARG, message in isdf_last_error).
+ *   - Complex numbers are interleaved (re, im) pairs of double.
+ *   - Orbitals: psi is Nr x N column-major, i.e. psi[n * Nr + k] = psi_n(r_k),
+ *     a (N, Nr) C-contiguous array; states 0..nv-1 occupied, nv..nv+nc-1
+ *     empty; grid index k = i0 + n0 (i1 + n1 i2).  Columns should be
+ *     orthonormal in the plain grid inner product (quadrature weights are
+ *     dropped, as in the paper; v_scale restores physical units).
+ *   - Plane waves: miller is ng x 3 int32 (m_x, m_y, m_z), each component in
+ *     [-n_d/2, n_d/2), distinct; G = 2 pi B m with B the reciprocal basis of
+ *     the cell rows.  V(G) = v_scale 4 pi / |G|^2 and V(0) = 0.
+ *   - Calls on one handle must not overlap in time; different handles may be
+ *     used from different host threads.
+ */
+#ifndef ISDF_SMW_H
+#define ISDF_SMW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct isdf_handle_s* isdf_handle;
+
+typedef enum {
+  ISDF_OK = 0,
+  ISDF_E_ARG = -1,         /* invalid argument (host check, nothing enqueued) */
+  ISDF_E_NOT_PD = -2,      /* a Hermitian matrix that must be positive definite was not */
+  ISDF_E_DEVICE = -3,      /* HIP runtime error */
+  ISDF_E_WORKSPACE = -4,   /* workspace NULL, too small or misaligned (256 B) */
+  ISDF_E_UNSUPPORTED = -5  /* valid request this build does not implement */
+} isdf_status;
+
+typedef enum {
+  ISDF_FP64 = 0,    /* every contraction in FP64 on MFMA */
+  ISDF_FP32 = 1,    /* large contractions in FP32 on MFMA, FP32 accumulation; N_mu x N_mu core in FP64 */
+  ISDF_BF16X3 = 2   /* large contractions as three BF16 products (hi*hi + hi*lo + lo*hi), FP32 accumulation; core in FP64 */
+} isdf_precision;
+
+typedef struct {
+  int32_t n[3];          /* FFT grid; Nr = n[0] n[1] n[2]; each in [2, 1024] */
+  double cell[9];        /* lattice vectors as rows, Bohr */
+  int32_t nv, nc;        /* occupied / empty state counts, both >= 1 */
+  int32_t is_complex;    /* 0: psi is real float64; 1: psi is complex128 */
+  double pair_factor;    /* f in chi0 = f M W M^H; the paper's value is 2 */
+  double v_scale;        /* Coulomb prefactor; Nr / cell volume for unit-norm grid orbitals */
+  int32_t prec;          /* isdf_precision */
+  int32_t refine_steps;  /* FP64 iterative-refinement steps on the core solve, 0..8 */
+} isdf_problem;
+
+typedef struct {
+  double stage_ms[8];        /* filled when want_timing != 0: gather+S^{-1}, Z, DFT, U, core M,
+                                FP64 core algebra, U T, output */
+  double refine_residual[9]; /* ||L^H - A X_k||_F / ||L^H||_F for k = 0..refine_steps (last frequency) */
+  double min_pivot;          /* smallest Cholesky / pivot-block diagonal seen (last frequency) */
+  int32_t want_timing;       /* input: 1 to record per-stage HIP events (adds host syncs) */
+  int32_t n_refine_reported; /* number of valid refine_residual entries */
+} isdf_report;
+
+/* Create a handle bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = default stream).  Allocates only a small pinned
+ * host staging buffer and a few events.  Errors: ISDF_E_ARG (h NULL or bad
+ * device), ISDF_E_DEVICE. */
+isdf_status isdf_create(isdf_handle* h, int device, void* hip_stream);
+
+/* Destroy a handle; waits for its stream.  NULL is accepted. */
+isdf_status isdf_destroy(isdf_handle h);
+
+/* Rebind the handle to another stream on the same device. */
+isdf_status isdf_set_stream(isdf_handle h, void* hip_stream);
+
+/* Device workspace bytes needed by isdf_eps_inv and the stage calls for this
+ * problem, n_mu interpolation points, ng plane waves and n_omega frequencies
+ * (0 = static).  Host only; does not need a handle or a GPU. */
+isdf_status isdf_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t ng,
+                                 int32_t n_omega, size_t* bytes);
+
+/* The first ng Miller vectors of the grid, ordered by (|m|^2, m_x, m_y, m_z)
+ * ascending, each component in [-n_d/2, n_d/2).  Host only.  miller_out: host,
+ * ng x 3 int32, caller-allocated. */
+isdf_status isdf_gvectors(const isdf_problem* prob, int32_t ng, int32_t* miller_out);
+
+/* eps~^{-1} for each requested frequency (paper: eq. epsilon_with_SMW with
+ * the ISDF pair products; steps 1-4 above, all on the GPU).
+ *   psi       device, Nr x N (see conventions), float64 or complex128 per is_complex
+ *   energies  host, N doubles (Hartree); max over occupied < min over empty
+ *   mu_idx    host, n_mu distinct grid indices in [0, Nr); 1 <= n_mu <= nv*nc
+ *   miller    host, ng x 3 int32, distinct, in range; 1 <= ng <= Nr
+ *   omega     host, n_omega imaginary frequencies (Hartree, >= 0); NULL with
+ *             n_omega = 0 means one static (omega = 0) result
+ *   workspace device, >= isdf_workspace_bytes(...), 256-byte aligned
+ *   eps_inv   device out, max(n_omega, 1) x ng x ng complex128, C order:
+ *             eps_inv[w][g][g'] = eps~^{-1}(G_g, G_g') at omega_w.  Exactly
+ *             Hermitian (lower triangle computed, upper mirrored).
+ *   rep       host out, optional (NULL)
+ * Errors: ISDF_E_ARG, ISDF_E_WORKSPACE, ISDF_E_NOT_PD (C C^H or -M not
+ * positive definite, e.g. points that make C rank deficient), ISDF_E_DEVICE. */
+isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* psi,
+                         const double* energies, const int32_t* mu_idx, int32_t n_mu,
+                         const int32_t* miller, int32_t ng, const double* omega,
+                         int32_t n_omega, void* workspace, size_t ws_bytes, void* eps_inv,
+                         isdf_report* rep);
+
+/* Step 1 alone: Theta in real space (eq. ISDF, least-squares fit).
+ *   theta  device out, N_mu x Nr complex128 C order: theta[mu][k] = Theta(r_k, mu).
+ * Other arguments as for isdf_eps_inv. */
+isdf_status isdf_fit_theta(isdf_handle h, const isdf_problem* prob, const void* psi,
+                           const int32_t* mu_idx, int32_t n_mu, void* workspace,
+                           size_t ws_bytes, void* theta);
+
+/* Step 2 alone: the core M = f C W C^H (eq. COmegaCstar times f) at one frequency.
+ *   m_out  device out, N_mu x N_mu complex128 C order (Hermitian, negative definite). */
+isdf_status isdf_core_m(isdf_handle h, const isdf_problem* prob, const void* psi,
+                        const double* energies, const int32_t* mu_idx, int32_t n_mu,
+                        double omega, void* workspace, size_t ws_bytes, void* m_out);
+
+/* Steps 1 and 3: U = V^{1/2} (F Theta) restricted to the plane-wave list.
+ *   u_out  device out, ng x N_mu complex128 C order: u[g][mu]. */
+isdf_status isdf_coulomb_u(isdf_handle h, const isdf_problem* prob, const void* psi,
+                           const int32_t* mu_idx, int32_t n_mu, const int32_t* miller,
+                           int32_t ng, void* workspace, size_t ws_bytes, void* u_out);
+
+/* Step 4 alone: eps~^{-1} = I + U (M^{-1} - U^H U)^{-1} U^H from given U and M
+ * (eq. epsilon_with_SMW, symmetrised).
+ *   u      device, ng x N_mu complex128 C order
+ *   m      device, N_mu x N_mu complex128 C order, Hermitian negative definite
+ *   eps_inv device out, ng x ng complex128. */
+isdf_status isdf_smw_apply(isdf_handle h, const isdf_problem* prob, const void* u,
+                           const void* m, int32_t n_mu, int32_t ng, void* workspace,
+                           size_t ws_bytes, void* eps_inv, isdf_report* rep);
+
+/* Host-only check of every host-side argument of isdf_eps_inv (problem, energies,
+ * points, plane waves, frequencies); no GPU or handle needed.  Returns the
+ * status isdf_eps_inv would return for these arguments before enqueueing
+ * anything; msg (optional, host, msg_len bytes) receives the error text. */
+isdf_status isdf_check_inputs(const isdf_problem* prob, const double* energies,
+                              const int32_t* mu_idx, int32_t n_mu, const int32_t* miller,
+                              int32_t ng, const double* omega, int32_t n_omega, char* msg,
+                              size_t msg_len);
+
+/* Last error message of this handle ("" if none).  Valid until the next call. */
+const char* isdf_last_error(isdf_handle h);
+
+/* Library version string. */
+const char* isdf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISDF_SMW_H */

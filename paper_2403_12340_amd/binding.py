@@ -1,0 +1,318 @@
+"""ctypes binding of libisdfsmw.so (C ABI in include/isdf_smw.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory (inputs, outputs, workspace) and the
+HIP stream.  There is no fallback: if the library is not built, or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libisdfsmw.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "isdf_smw.h")
+
+OK, E_ARG, E_NOT_PD, E_DEVICE, E_WORKSPACE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "ISDF_OK", -1: "ISDF_E_ARG", -2: "ISDF_E_NOT_PD", -3: "ISDF_E_DEVICE",
+                -4: "ISDF_E_WORKSPACE", -5: "ISDF_E_UNSUPPORTED"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+class IsdfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("cell", ctypes.c_double * 9), ("nv", ctypes.c_int32),
+                ("nc", ctypes.c_int32), ("is_complex", ctypes.c_int32), ("pair_factor", ctypes.c_double),
+                ("v_scale", ctypes.c_double), ("prec", ctypes.c_int32), ("refine_steps", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("stage_ms", ctypes.c_double * 8), ("refine_residual", ctypes.c_double * 9),
+                ("min_pivot", ctypes.c_double), ("want_timing", ctypes.c_int32),
+                ("n_refine_reported", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run python -m paper_2403_12340_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+        pi32, pdbl, pprob = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Problem)
+        prep = ctypes.POINTER(Report)
+        sig = {
+            "isdf_create": [ctypes.POINTER(vp), ctypes.c_int, vp],
+            "isdf_destroy": [vp],
+            "isdf_set_stream": [vp, vp],
+            "isdf_workspace_bytes": [pprob, i32, i32, i32, ctypes.POINTER(sz)],
+            "isdf_gvectors": [pprob, i32, pi32],
+            "isdf_check_inputs": [pprob, pdbl, pi32, i32, pi32, i32, pdbl, i32, ctypes.c_char_p, sz],
+            "isdf_eps_inv": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, pdbl, i32, vp, sz, vp, prep],
+            "isdf_fit_theta": [vp, pprob, vp, pi32, i32, vp, sz, vp],
+            "isdf_core_m": [vp, pprob, vp, pdbl, pi32, i32, dbl, vp, sz, vp],
+            "isdf_coulomb_u": [vp, pprob, vp, pi32, i32, pi32, i32, vp, sz, vp],
+            "isdf_smw_apply": [vp, pprob, vp, vp, i32, i32, vp, sz, vp, prep],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.isdf_last_error.argtypes = [vp]
+        L.isdf_last_error.restype = ctypes.c_char_p
+        L.isdf_version.argtypes = []
+        L.isdf_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions the C header declares."""
+    import re
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:isdf_status|const char\*)\s+(isdf_\w+)\s*\(", txt, re.M)))
+
+
+def make_problem(n, cell, nv, nc, *, is_complex=True, pair_factor=2.0, v_scale=None,
+                 prec="fp64", refine_steps=0) -> Problem:
+    p = Problem()
+    n = (n, n, n) if np.isscalar(n) else tuple(n)
+    for d in range(3):
+        p.n[d] = int(n[d])
+    cell = np.asarray(cell, dtype=np.float64).reshape(3, 3)
+    for i in range(9):
+        p.cell[i] = float(cell.ravel()[i])
+    p.nv, p.nc = int(nv), int(nc)
+    p.is_complex = 1 if is_complex else 0
+    p.pair_factor = float(pair_factor)
+    if v_scale is None:
+        v_scale = n[0] * n[1] * n[2] / abs(np.linalg.det(cell))
+    p.v_scale = float(v_scale)
+    p.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    p.refine_steps = int(refine_steps)
+    return p
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def workspace_bytes(prob: Problem, n_mu: int, ng: int, n_omega: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().isdf_workspace_bytes(ctypes.byref(prob), n_mu, ng, n_omega, ctypes.byref(out))
+    if st != OK:
+        raise IsdfError(st, "isdf_workspace_bytes rejected the problem")
+    return int(out.value)
+
+
+def gvectors(prob: Problem, ng: int) -> np.ndarray:
+    out = np.zeros((ng, 3), dtype=np.int32)
+    st = lib().isdf_gvectors(ctypes.byref(prob), ng, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if st != OK:
+        raise IsdfError(st, "isdf_gvectors failed")
+    return out
+
+
+def check_inputs(prob: Problem, energies, mu_idx, miller, omegas=None) -> tuple[int, str]:
+    e, pe = _f64(energies)
+    mu, pmu = _i32(mu_idx)
+    mi, pmi = _i32(miller)
+    om = np.zeros(0) if omegas is None else np.asarray(omegas, dtype=np.float64)
+    om, pom = _f64(om)
+    buf = ctypes.create_string_buffer(512)
+    st = lib().isdf_check_inputs(ctypes.byref(prob), pe, pmu, len(mu), pmi, len(mi), pom if len(om) else None,
+                                 len(om), buf, 512)
+    return st, buf.value.decode()
+
+
+class Handle:
+    """Library handle bound to one device; the stream is refreshed from torch on every call."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = device
+        h = ctypes.c_void_p()
+        st = lib().isdf_create(ctypes.byref(h), device, ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream))
+        if st != OK:
+            raise IsdfError(st, "isdf_create failed (no GPU?)")
+        self.h = h
+
+    def sync_stream(self):
+        import torch
+        lib().isdf_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def check(self, st: int, what: str):
+        if st != OK:
+            raise IsdfError(st, f"{what}: {lib().isdf_last_error(self.h).decode()}")
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().isdf_destroy(self.h)
+        except Exception:
+            pass
+
+
+_handles: dict[int, Handle] = {}
+
+
+def handle(device: int = 0) -> Handle:
+    if device not in _handles:
+        _handles[device] = Handle(device)
+    h = _handles[device]
+    h.sync_stream()
+    return h
+
+
+def _workspace(nbytes: int, device, ws=None):
+    import torch
+    if ws is not None and ws.numel() >= nbytes + 256:
+        buf = ws
+    else:
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+@dataclass
+class Result:
+    eps_inv: "object"      # torch complex128 (n_omega or 1, ng, ng)
+    report: Report
+
+
+def _check_psi(psi_t, prob):
+    import torch
+    if not isinstance(psi_t, torch.Tensor) or psi_t.device.type != "cuda":
+        raise TypeError("psi_t must be a CUDA (HIP) torch tensor")
+    nr = prob.n[0] * prob.n[1] * prob.n[2]
+    if tuple(psi_t.shape) != (prob.nv + prob.nc, nr) or not psi_t.is_contiguous():
+        raise ValueError(f"psi_t must be contiguous with shape (N, Nr) = ({prob.nv + prob.nc}, {nr})")
+    want = torch.complex128 if prob.is_complex else torch.float64
+    if psi_t.dtype != want:
+        raise TypeError(f"psi_t dtype must be {want}")
+
+
+def eps_inv(psi_t, energies, mu_idx, miller, prob: Problem, omegas=None, *, out=None, workspace=None,
+            timing=False) -> Result:
+    """eps~^{-1} on the plane-wave list (one matrix per frequency; static if omegas is None)."""
+    import torch
+    _check_psi(psi_t, prob)
+    dev = psi_t.device
+    h = handle(dev.index or 0)
+    e, pe = _f64(energies)
+    mu, pmu = _i32(mu_idx)
+    mi, pmi = _i32(miller)
+    om = np.zeros(0) if omegas is None else np.asarray(omegas, dtype=np.float64)
+    om, pom = _f64(om)
+    nw = max(len(om), 1)
+    ng = len(mi)
+    nbytes = workspace_bytes(prob, len(mu), ng, len(om))
+    wsbuf, wsptr = _workspace(nbytes, dev, workspace)
+    if out is None:
+        out = torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev)
+    rep = Report()
+    rep.want_timing = 1 if timing else 0
+    st = lib().isdf_eps_inv(h.h, ctypes.byref(prob), ctypes.c_void_p(psi_t.data_ptr()), pe, pmu, len(mu), pmi, ng,
+                            pom if len(om) else None, len(om), ctypes.c_void_p(wsptr), nbytes,
+                            ctypes.c_void_p(out.data_ptr()), ctypes.byref(rep))
+    h.check(st, "isdf_eps_inv")
+    return Result(out, rep)
+
+
+def fit_theta(psi_t, mu_idx, prob: Problem, workspace=None):
+    """Theta in real space, returned as (N_mu, Nr) complex128: theta[mu, k] = Theta(r_k, mu)."""
+    import torch
+    _check_psi(psi_t, prob)
+    dev = psi_t.device
+    h = handle(dev.index or 0)
+    mu, pmu = _i32(mu_idx)
+    nr = prob.n[0] * prob.n[1] * prob.n[2]
+    nbytes = workspace_bytes(prob, len(mu), 1, 0)
+    wsbuf, wsptr = _workspace(nbytes, dev, workspace)
+    out = torch.empty((len(mu), nr), dtype=torch.complex128, device=dev)
+    st = lib().isdf_fit_theta(h.h, ctypes.byref(prob), ctypes.c_void_p(psi_t.data_ptr()), pmu, len(mu),
+                              ctypes.c_void_p(wsptr), nbytes, ctypes.c_void_p(out.data_ptr()))
+    h.check(st, "isdf_fit_theta")
+    return out
+
+
+def core_m(psi_t, energies, mu_idx, prob: Problem, omega=0.0, workspace=None):
+    """Core f C W C^H as (N_mu, N_mu) complex128."""
+    import torch
+    _check_psi(psi_t, prob)
+    dev = psi_t.device
+    h = handle(dev.index or 0)
+    e, pe = _f64(energies)
+    mu, pmu = _i32(mu_idx)
+    nbytes = workspace_bytes(prob, len(mu), 1, 0)
+    wsbuf, wsptr = _workspace(nbytes, dev, workspace)
+    out = torch.empty((len(mu), len(mu)), dtype=torch.complex128, device=dev)
+    st = lib().isdf_core_m(h.h, ctypes.byref(prob), ctypes.c_void_p(psi_t.data_ptr()), pe, pmu, len(mu),
+                           float(omega), ctypes.c_void_p(wsptr), nbytes, ctypes.c_void_p(out.data_ptr()))
+    h.check(st, "isdf_core_m")
+    return out
+
+
+def coulomb_u(psi_t, mu_idx, miller, prob: Problem, workspace=None):
+    """U = V^{1/2} F Theta on the plane-wave list as (NG, N_mu) complex128."""
+    import torch
+    _check_psi(psi_t, prob)
+    dev = psi_t.device
+    h = handle(dev.index or 0)
+    mu, pmu = _i32(mu_idx)
+    mi, pmi = _i32(miller)
+    nbytes = workspace_bytes(prob, len(mu), len(mi), 0)
+    wsbuf, wsptr = _workspace(nbytes, dev, workspace)
+    out = torch.empty((len(mi), len(mu)), dtype=torch.complex128, device=dev)
+    st = lib().isdf_coulomb_u(h.h, ctypes.byref(prob), ctypes.c_void_p(psi_t.data_ptr()), pmu, len(mu), pmi,
+                              len(mi), ctypes.c_void_p(wsptr), nbytes, ctypes.c_void_p(out.data_ptr()))
+    h.check(st, "isdf_coulomb_u")
+    return out
+
+
+def smw_apply(u, m, prob: Problem, workspace=None, timing=False) -> Result:
+    """eps~^{-1} = I + U (M^{-1} - U^H U)^{-1} U^H from device U (NG, N_mu) and M (N_mu, N_mu)."""
+    import torch
+    ng, nmu = u.shape
+    if u.dtype != torch.complex128 or m.dtype != torch.complex128 or tuple(m.shape) != (nmu, nmu):
+        raise ValueError("u must be (NG, N_mu) and m (N_mu, N_mu), both complex128")
+    u, m = u.contiguous(), m.contiguous()
+    dev = u.device
+    h = handle(dev.index or 0)
+    nbytes = workspace_bytes(prob, nmu, ng, 0)
+    wsbuf, wsptr = _workspace(nbytes, dev, workspace)
+    out = torch.empty((1, ng, ng), dtype=torch.complex128, device=dev)
+    rep = Report()
+    rep.want_timing = 1 if timing else 0
+    st = lib().isdf_smw_apply(h.h, ctypes.byref(prob), ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                              nmu, ng, ctypes.c_void_p(wsptr), nbytes, ctypes.c_void_p(out.data_ptr()),
+                              ctypes.byref(rep))
+    h.check(st, "isdf_smw_apply")
+    return Result(out, rep)
+
+
+def problem_for(inp, prec="fp64", refine_steps=0, v_scale=None) -> Problem:
+    """Problem description for a synthetic input set (synth.Inputs)."""
+    return make_problem(inp.n, inp.cell, inp.nv, inp.nc, is_complex=inp.is_complex,
+                        v_scale=inp.v_scale if v_scale is None else v_scale, prec=prec,
+                        refine_steps=refine_steps)

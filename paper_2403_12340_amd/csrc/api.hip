@@ -1,0 +1,851 @@
+// C ABI of the ISDF-SMW dielectric-inverse library (see include/isdf_smw.h).
+//
+// Host side only: argument validation, the workspace layout, the pruned-DFT
+// index bookkeeping and the order of kernel launches.  Every arithmetic step
+// of the method runs in the HIP kernels of this library.
+//
+// Pipeline of isdf_eps_inv (paper: eq. ISDF, eq. COmegaCstar, eq. epsilon_with_SMW):
+//   pm   = psi at the points                                  (gather)
+//   S^T  = conj(Pv) * Qc at the points, FP64                  (zpair; S = C C^H)
+//   Sw   = -(S^T)^{-1}, FP64                                  (sweep)
+//   Zt   = (M_vc C^H)^T, N_mu x Nr                            (zpair, mode precision)
+//   ZG   = unitary DFT of the Zt rows on the plane-wave list  (dft_xy, dft_z)
+//   U    = diag(sqrt V) ZG S^{-1}  (= V^{1/2} F Theta: the least-squares fit is
+//          applied after the transform, F (Z S^{-1}) = (F Z) S^{-1})
+//   G    = U^H U                                              (Theta^H V Theta)
+//   per frequency:
+//     -M = f C W C^H negated, L = chol(-M)                    (core, potrf)
+//     A  = I + L^H G L,  X = A^{-1} L^H (+ FP64 refinement)   (sweep, GEMMs)
+//     T  = L X            (so the SMW kernel (M^{-1} - G)^{-1} = -T)
+//     eps~^{-1} = I - (U T) U^H                               (Hermitian output GEMM)
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/isdf_smw.h"
+#include "internal.h"
+
+using namespace isdf;
+
+struct isdf_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t ev[10] = {};
+  std::string err;
+};
+
+namespace {
+
+const size_t ALIGN = 256;
+inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct StatusBlock {
+  int status;
+  int pad;
+  double min_pivot;
+  double res[10];
+  double lh2;
+  double partial[1024];
+};
+
+struct Problem {
+  int n0, n1, n2, nv, nc, ns, nmu, ng, nomega;
+  long nr;
+  bool cplx;
+  Prec prec;
+  bool m32;  // large contractions stored in complex64
+  double f, v_scale;
+  int refine;
+  double recip[9];
+};
+
+// pruned-DFT index lists derived from the Miller list (host bookkeeping)
+struct DftIndex {
+  std::vector<int> xl, yl, zl, d_ax, d_by, g_d, g_cz;
+};
+
+DftIndex dft_index(const int32_t* miller, int ng) {
+  DftIndex ix;
+  std::set<int> xs, ys, zs;
+  std::set<std::pair<int, int>> ds;
+  for (int g = 0; g < ng; ++g) {
+    xs.insert(miller[3 * g]);
+    ys.insert(miller[3 * g + 1]);
+    zs.insert(miller[3 * g + 2]);
+    ds.insert({miller[3 * g], miller[3 * g + 1]});
+  }
+  ix.xl.assign(xs.begin(), xs.end());
+  ix.yl.assign(ys.begin(), ys.end());
+  ix.zl.assign(zs.begin(), zs.end());
+  std::map<int, int> xi, yi, zi;
+  for (size_t i = 0; i < ix.xl.size(); ++i) xi[ix.xl[i]] = (int)i;
+  for (size_t i = 0; i < ix.yl.size(); ++i) yi[ix.yl[i]] = (int)i;
+  for (size_t i = 0; i < ix.zl.size(); ++i) zi[ix.zl[i]] = (int)i;
+  std::map<std::pair<int, int>, int> di;
+  for (const auto& p : ds) {
+    di[p] = (int)ix.d_ax.size();
+    ix.d_ax.push_back(xi[p.first]);
+    ix.d_by.push_back(yi[p.second]);
+  }
+  ix.g_d.resize(ng);
+  ix.g_cz.resize(ng);
+  for (int g = 0; g < ng; ++g) {
+    ix.g_d[g] = di[{miller[3 * g], miller[3 * g + 1]}];
+    ix.g_cz[g] = zi[miller[3 * g + 2]];
+  }
+  return ix;
+}
+
+// Workspace layout.  Offsets in bytes from the workspace base.
+struct Layout {
+  size_t psi_c = 0, pm = 0, mu = 0, e = 0, w = 0, s = 0, lin = 0, zt = 0, tabs = 0, t2 = 0, zg = 0,
+         u = 0, l = 0, g = 0, gl = 0, a = 0, acopy = 0, lh = 0, x = 0, rres = 0, t = 0, status = 0,
+         miller = 0, recip = 0, sqrtv = 0, idx = 0, total = 0;
+  size_t twx = 0, twy = 0, twz = 0;  // inside tabs
+  size_t part = 0, w1 = 0;           // alias into the zt region
+  int kx = 0, ky = 0, kz = 0, nd = 0, nsplit = 1;
+};
+
+Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
+  Layout L;
+  const size_t z = 16, el = P.m32 ? 8 : 16;
+  const size_t nmu2 = (size_t)P.nmu * P.nmu;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += up(std::max<size_t>(bytes, 1)); return o; };
+  L.kx = kx; L.ky = ky; L.kz = kz; L.nd = nd;
+  L.nsplit = core_splits(P.nmu, P.nv);
+  L.status = take(sizeof(StatusBlock));
+  L.psi_c = P.cplx ? 0 : take((size_t)P.ns * P.nr * z);
+  L.pm = take((size_t)P.ns * P.nmu * z);
+  L.mu = take((size_t)P.nmu * 4);
+  L.e = take((size_t)P.ns * 8);
+  L.w = take((size_t)P.nv * P.nc * 8);
+  L.miller = take((size_t)P.ng * 3 * 4);
+  L.recip = take(9 * 8);
+  L.sqrtv = take((size_t)P.ng * 8);
+  L.idx = take((size_t)(kx + ky + kz + 2 * nd + 2 * P.ng) * 4);
+  L.twx = take((size_t)kx * P.n0 * el);
+  L.twy = take((size_t)ky * P.n1 * el);
+  L.twz = take((size_t)kz * P.n2 * el);
+  L.tabs = L.twx;
+  L.s = take(nmu2 * z);
+  L.lin = take(linalg_scratch_bytes(P.nmu));
+  L.t2 = take((size_t)P.nmu * P.n2 * nd * el);
+  L.zg = take((size_t)P.nmu * P.ng * el);
+  L.u = take((size_t)P.ng * P.nmu * el);
+  L.l = take(nmu2 * z);
+  L.g = take(nmu2 * z);
+  L.gl = take(nmu2 * z);
+  L.a = take(nmu2 * z);
+  L.acopy = take(nmu2 * z);
+  L.lh = take(nmu2 * z);
+  L.x = take(nmu2 * z);
+  L.rres = take(nmu2 * z);
+  L.t = take(nmu2 * z);
+  // big region: Zt (N_mu x Nr), later reused for the core partial sums and U T
+  const size_t zt_bytes = (size_t)P.nmu * P.nr * el;
+  const size_t part_bytes = (size_t)L.nsplit * nmu2 * el;
+  const size_t w1_bytes = (size_t)P.ng * P.nmu * el;
+  L.zt = take(std::max(zt_bytes, std::max(part_bytes, w1_bytes)));
+  L.part = L.zt;
+  L.w1 = L.zt;
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) { return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off); }
+
+isdf_status fail(isdf_handle h, isdf_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(h, ISDF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+isdf_status check_problem(isdf_handle h, const isdf_problem* pr, Problem& P) {
+  if (!pr) return fail(h, ISDF_E_ARG, "problem is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (pr->n[d] < 2 || pr->n[d] > 1024) return fail(h, ISDF_E_ARG, "grid size out of range [2, 1024]");
+  if (pr->nv < 1 || pr->nc < 1) return fail(h, ISDF_E_ARG, "nv and nc must be >= 1");
+  if (!(pr->pair_factor > 0.0) || !std::isfinite(pr->pair_factor)) return fail(h, ISDF_E_ARG, "pair_factor must be positive");
+  if (!(pr->v_scale > 0.0) || !std::isfinite(pr->v_scale)) return fail(h, ISDF_E_ARG, "v_scale must be positive");
+  if (pr->refine_steps < 0 || pr->refine_steps > 8) return fail(h, ISDF_E_ARG, "refine_steps must be in [0, 8]");
+  if (pr->prec != ISDF_FP64 && pr->prec != ISDF_FP32 && pr->prec != ISDF_BF16X3) return fail(h, ISDF_E_ARG, "unknown precision");
+  if (pr->is_complex != 0 && pr->is_complex != 1) return fail(h, ISDF_E_ARG, "is_complex must be 0 or 1");
+  const double* c = pr->cell;
+  const double det = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) + c[2] * (c[3] * c[7] - c[4] * c[6]);
+  if (!(std::fabs(det) > 1e-12) || !std::isfinite(det)) return fail(h, ISDF_E_ARG, "cell is singular");
+  P.n0 = pr->n[0]; P.n1 = pr->n[1]; P.n2 = pr->n[2];
+  P.nr = (long)P.n0 * P.n1 * P.n2;
+  P.nv = pr->nv; P.nc = pr->nc; P.ns = pr->nv + pr->nc;
+  P.cplx = pr->is_complex == 1;
+  P.prec = (Prec)pr->prec;
+  P.m32 = P.prec != P64;
+  P.f = pr->pair_factor;
+  P.v_scale = pr->v_scale;
+  P.refine = pr->refine_steps;
+  // reciprocal basis rows b_i = 2 pi (cell^{-1})^T rows
+  const double inv[9] = {(c[4] * c[8] - c[5] * c[7]) / det, -(c[1] * c[8] - c[2] * c[7]) / det, (c[1] * c[5] - c[2] * c[4]) / det,
+                         -(c[3] * c[8] - c[5] * c[6]) / det, (c[0] * c[8] - c[2] * c[6]) / det, -(c[0] * c[5] - c[2] * c[3]) / det,
+                         (c[3] * c[7] - c[4] * c[6]) / det, -(c[0] * c[7] - c[1] * c[6]) / det, (c[0] * c[4] - c[1] * c[3]) / det};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P.recip[3 * i + j] = 2.0 * M_PI * inv[3 * j + i];
+  return ISDF_OK;
+}
+
+isdf_status check_points(isdf_handle h, const Problem& P, const int32_t* mu, int nmu) {
+  if (!mu) return fail(h, ISDF_E_ARG, "mu_idx is NULL");
+  if (nmu < 1) return fail(h, ISDF_E_ARG, "n_mu must be >= 1");
+  if ((long)nmu > (long)P.nv * P.nc) return fail(h, ISDF_E_ARG, "n_mu exceeds nv*nc (core would be singular)");
+  if ((long)nmu > P.nr) return fail(h, ISDF_E_ARG, "n_mu exceeds Nr");
+  std::vector<int32_t> s(mu, mu + nmu);
+  std::sort(s.begin(), s.end());
+  if (s.front() < 0 || s.back() >= P.nr) return fail(h, ISDF_E_ARG, "mu_idx out of range");
+  for (int i = 1; i < nmu; ++i)
+    if (s[i] == s[i - 1]) return fail(h, ISDF_E_ARG, "mu_idx has duplicate points");
+  return ISDF_OK;
+}
+
+isdf_status check_energies(isdf_handle h, const Problem& P, const double* e) {
+  if (!e) return fail(h, ISDF_E_ARG, "energies is NULL");
+  double vmax = -INFINITY, cmin = INFINITY;
+  for (int i = 0; i < P.ns; ++i) {
+    if (!std::isfinite(e[i])) return fail(h, ISDF_E_ARG, "energies must be finite");
+    if (i < P.nv) vmax = std::max(vmax, e[i]);
+    else cmin = std::min(cmin, e[i]);
+  }
+  if (!(vmax < cmin)) return fail(h, ISDF_E_ARG, "no gap: max occupied energy >= min empty energy");
+  return ISDF_OK;
+}
+
+isdf_status check_miller(isdf_handle h, const Problem& P, const int32_t* m, int ng) {
+  if (!m) return fail(h, ISDF_E_ARG, "miller is NULL");
+  if (ng < 1 || (long)ng > P.nr) return fail(h, ISDF_E_ARG, "ng must be in [1, Nr]");
+  const int n[3] = {P.n0, P.n1, P.n2};
+  std::set<long> seen;
+  for (int g = 0; g < ng; ++g) {
+    long key = 0;
+    for (int d = 0; d < 3; ++d) {
+      const int v = m[3 * g + d];
+      if (v < -(n[d] / 2) || v >= n[d] - n[d] / 2) return fail(h, ISDF_E_ARG, "miller index out of [-n/2, n/2)");
+      key = key * 2048 + (v + 1024);
+    }
+    if (!seen.insert(key).second) return fail(h, ISDF_E_ARG, "miller list has duplicates");
+  }
+  return ISDF_OK;
+}
+
+isdf_status check_ws(isdf_handle h, void* ws, size_t have, size_t need) {
+  if (!ws) return fail(h, ISDF_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % ALIGN) return fail(h, ISDF_E_WORKSPACE, "workspace not 256-byte aligned");
+  if (have < need) return fail(h, ISDF_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  return ISDF_OK;
+}
+
+// Stage host arrays through the handle's pinned buffer into device memory.
+struct Uploader {
+  isdf_handle h;
+  std::vector<std::pair<const void*, size_t>> src;
+  std::vector<void*> dst;
+  void add(void* d, const void* s, size_t bytes) { if (bytes) { src.push_back({s, bytes}); dst.push_back(d); } }
+  isdf_status run() {
+    size_t total = 0;
+    for (auto& s : src) total += up(s.second);
+    // the previous call's copies out of the pinned buffer must be complete
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (total > h->pinned_bytes) {
+      if (h->pinned) HIPCHK(hipHostFree(h->pinned));
+      h->pinned = nullptr;
+      h->pinned_bytes = 0;
+      HIPCHK(hipHostMalloc(&h->pinned, total, hipHostMallocDefault));
+      h->pinned_bytes = total;
+    }
+    size_t off = 0;
+    for (size_t i = 0; i < src.size(); ++i) {
+      char* p = reinterpret_cast<char*>(h->pinned) + off;
+      std::memcpy(p, src[i].first, src[i].second);
+      HIPCHK(hipMemcpyAsync(dst[i], p, src[i].second, hipMemcpyHostToDevice, h->stream));
+      off += up(src[i].second);
+    }
+    return ISDF_OK;
+  }
+};
+
+struct Timer {
+  isdf_handle h;
+  bool on;
+  int k = 0;
+  void mark() { if (on && k < 10) (void)hipEventRecord(h->ev[k++], h->stream); }
+};
+
+// ---- shared pieces of the pipeline --------------------------------------------------------
+struct Run {
+  isdf_handle h;
+  Problem P;
+  Layout L;
+  void* ws;
+  const void* psi;      // complex128 view of the orbitals (device)
+  StatusBlock* sb;
+  hipStream_t st;
+};
+
+isdf_status prepare_psi(Run& R, const void* psi) {
+  isdf_handle h = R.h;
+  if (R.P.cplx) {
+    R.psi = psi;
+  } else {
+    void* pc = at<char>(R.ws, R.L.psi_c);
+    HIPCHK(widen_real((const double*)psi, pc, (long)R.P.ns * R.P.nr, R.st));
+    R.psi = pc;
+  }
+  return ISDF_OK;
+}
+
+isdf_status stage_points_and_s(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  void* pm = at<char>(R.ws, R.L.pm);
+  HIPCHK(gather_points(R.psi, P.nr, P.ns, at<int>(R.ws, R.L.mu), P.nmu, pm, R.st));
+  void* s = at<char>(R.ws, R.L.s);
+  HIPCHK(zpair(P64, P.nmu, P.nmu, P.nv, P.ns, pm, P.nmu, pm, P.nmu, s, P.nmu, false, R.st));
+  HIPCHK(sweep_inverse(P.nmu, s, at<char>(R.ws, R.L.lin), &R.sb->status, R.st));
+  return ISDF_OK;
+}
+
+isdf_status stage_z(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  HIPCHK(zpair(cp, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm), P.nmu, R.psi, P.nr,
+               at<char>(R.ws, R.L.zt), P.nr, P.m32, R.st));
+  return ISDF_OK;
+}
+
+DftPlan make_plan(Run& R) {
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  DftPlan p;
+  p.n0 = P.n0; p.n1 = P.n1; p.n2 = P.n2; p.nmu = P.nmu; p.ng = P.ng;
+  p.kx = L.kx; p.ky = L.ky; p.nd = L.nd; p.kz = L.kz;
+  p.twx = at<char>(R.ws, L.twx);
+  p.twy = at<char>(R.ws, L.twy);
+  p.twz = at<char>(R.ws, L.twz);
+  int* ib = at<int>(R.ws, L.idx);
+  // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ng] g_cz[ng]
+  p.d_ax = ib + L.kx + L.ky + L.kz;
+  p.d_by = p.d_ax + L.nd;
+  p.g_d = p.d_by + L.nd;
+  p.g_cz = p.g_d + P.ng;
+  return p;
+}
+
+isdf_status stage_dft(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  DftPlan p = make_plan(R);
+  int* ib = at<int>(R.ws, L.idx);
+  HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), R.st));
+  HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), R.st));
+  HIPCHK(dft_twiddles(ib + L.kx + L.ky, L.kz, P.n2, P.m32, at<char>(R.ws, L.twz), R.st));
+  HIPCHK(dft_xy(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), R.st));
+  HIPCHK(dft_z(cp, p, at<char>(R.ws, L.t2), at<char>(R.ws, L.zg), R.st));
+  return ISDF_OK;
+}
+
+isdf_status stage_u(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  HIPCHK(coulomb_sqrt(at<int>(R.ws, L.miller), P.ng, at<double>(R.ws, L.recip), P.v_scale,
+                      at<double>(R.ws, L.sqrtv), R.st));
+  // U(g, nu) = sqrtv_g sum_mu ZG(g, mu) S^{-1}(mu, nu),  S^{-1}(mu, nu) = -Sw[nu][mu]
+  GemmDesc d;
+  d.M = P.ng; d.N = P.nmu; d.K = P.nmu;
+  d.A = at<char>(R.ws, L.zg); d.sam = 1; d.sak = P.ng; d.a32 = P.m32;
+  d.B = at<char>(R.ws, L.s); d.sbk = 1; d.sbn = P.nmu;
+  d.C = at<char>(R.ws, L.u); d.ldc = P.nmu; d.c32 = P.m32;
+  d.alpha = -1.0; d.row_scale = at<double>(R.ws, L.sqrtv);
+  HIPCHK(gemm(cp, d, R.st));
+  return ISDF_OK;
+}
+
+isdf_status stage_gram(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  GemmDesc d;  // G = U^H U
+  d.M = d.N = P.nmu; d.K = P.ng;
+  d.A = at<char>(R.ws, R.L.u); d.sam = 1; d.sak = P.nmu; d.conjA = true; d.a32 = P.m32;
+  d.B = at<char>(R.ws, R.L.u); d.sbk = P.nmu; d.sbn = 1; d.b32 = P.m32;
+  d.C = at<char>(R.ws, R.L.g); d.ldc = P.nmu;
+  d.herm = true;
+  HIPCHK(gemm(cp, d, R.st));
+  return ISDF_OK;
+}
+
+isdf_status stage_core(Run& R, double omega, void* m_out) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  double* w = at<double>(R.ws, R.L.w);
+  HIPCHK(pair_weights(at<double>(R.ws, R.L.e), P.nv, P.nc, omega, w, R.st));
+  void* part = at<char>(R.ws, R.L.part);
+  HIPCHK(core_partial(cp, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), P.nmu, w, part, R.L.nsplit, R.st));
+  HIPCHK(core_reduce(cp, P.nmu, part, R.L.nsplit, P.f, m_out, m_out ? nullptr : at<char>(R.ws, R.L.l), R.st));
+  return ISDF_OK;
+}
+
+// from -M in L-buffer and G: T = L (I + L^H G L)^{-1} L^H
+isdf_status stage_core_algebra(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const int n = P.nmu;
+  const long n2 = (long)n * n;
+  void* Lb = at<char>(R.ws, L.l);
+  HIPCHK(potrf(n, Lb, nullptr, &R.sb->status, R.st));
+  HIPCHK(diag_min(Lb, n, &R.sb->min_pivot, R.st));
+  GemmDesc d;
+  d.M = d.N = d.K = n;
+  d.A = at<char>(R.ws, L.g); d.sam = n; d.sak = 1;
+  d.B = Lb; d.sbk = n; d.sbn = 1;
+  d.C = at<char>(R.ws, L.gl); d.ldc = n;
+  HIPCHK(gemm(P64, d, R.st));                       // GL = G L
+  GemmDesc e;
+  e.M = e.N = e.K = n;
+  e.A = Lb; e.sam = 1; e.sak = n; e.conjA = true;  // L^H
+  e.B = at<char>(R.ws, L.gl); e.sbk = n; e.sbn = 1;
+  e.C = at<char>(R.ws, L.a); e.ldc = n; e.diag_add = 1.0;
+  HIPCHK(gemm(P64, e, R.st));                       // A = I + L^H G L
+  if (P.refine > 0) HIPCHK(convert_z(at<char>(R.ws, L.a), false, at<char>(R.ws, L.acopy), false, n2, R.st));
+  HIPCHK(sweep_inverse(n, at<char>(R.ws, L.a), at<char>(R.ws, L.lin), &R.sb->status, R.st));  // Aw = -A^{-1}
+  HIPCHK(conj_transpose(n, Lb, at<char>(R.ws, L.lh), R.st));
+  GemmDesc x;
+  x.M = x.N = x.K = n;
+  x.A = at<char>(R.ws, L.a); x.sam = n; x.sak = 1;
+  x.B = at<char>(R.ws, L.lh); x.sbk = n; x.sbn = 1;
+  x.C = at<char>(R.ws, L.x); x.ldc = n; x.alpha = -1.0;
+  HIPCHK(gemm(P64, x, R.st));                       // X = A^{-1} L^H
+  if (P.refine > 0) HIPCHK(frob2(at<char>(R.ws, L.lh), n2, R.sb->partial, &R.sb->lh2, R.st));
+  for (int k = 0; k < P.refine; ++k) {
+    HIPCHK(convert_z(at<char>(R.ws, L.lh), false, at<char>(R.ws, L.rres), false, n2, R.st));
+    GemmDesc r;
+    r.M = r.N = r.K = n;
+    r.A = at<char>(R.ws, L.acopy); r.sam = n; r.sak = 1;
+    r.B = at<char>(R.ws, L.x); r.sbk = n; r.sbn = 1;
+    r.C = at<char>(R.ws, L.rres); r.ldc = n; r.alpha = -1.0; r.beta = 1.0;
+    HIPCHK(gemm(P64, r, R.st));                     // Rres = L^H - A X
+    HIPCHK(frob2(at<char>(R.ws, L.rres), n2, R.sb->partial, &R.sb->res[k], R.st));
+    GemmDesc c;
+    c.M = c.N = c.K = n;
+    c.A = at<char>(R.ws, L.a); c.sam = n; c.sak = 1;
+    c.B = at<char>(R.ws, L.rres); c.sbk = n; c.sbn = 1;
+    c.C = at<char>(R.ws, L.x); c.ldc = n; c.alpha = -1.0; c.beta = 1.0;
+    HIPCHK(gemm(P64, c, R.st));                     // X += A^{-1} Rres
+  }
+  if (P.refine > 0) {  // residual after the last correction
+    HIPCHK(convert_z(at<char>(R.ws, L.lh), false, at<char>(R.ws, L.rres), false, n2, R.st));
+    GemmDesc r;
+    r.M = r.N = r.K = n;
+    r.A = at<char>(R.ws, L.acopy); r.sam = n; r.sak = 1;
+    r.B = at<char>(R.ws, L.x); r.sbk = n; r.sbn = 1;
+    r.C = at<char>(R.ws, L.rres); r.ldc = n; r.alpha = -1.0; r.beta = 1.0;
+    HIPCHK(gemm(P64, r, R.st));
+    HIPCHK(frob2(at<char>(R.ws, L.rres), n2, R.sb->partial, &R.sb->res[P.refine], R.st));
+  }
+  GemmDesc t;
+  t.M = t.N = t.K = n;
+  t.A = Lb; t.sam = n; t.sak = 1;
+  t.B = at<char>(R.ws, L.x); t.sbk = n; t.sbn = 1;
+  t.C = at<char>(R.ws, L.t); t.ldc = n;
+  HIPCHK(gemm(P64, t, R.st));                       // T = L X
+  return ISDF_OK;
+}
+
+isdf_status stage_out(Run& R, void* out, Timer& tm) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  GemmDesc d;  // W1 = U T
+  d.M = P.ng; d.N = P.nmu; d.K = P.nmu;
+  d.A = at<char>(R.ws, L.u); d.sam = P.nmu; d.sak = 1; d.a32 = P.m32;
+  d.B = at<char>(R.ws, L.t); d.sbk = P.nmu; d.sbn = 1;
+  d.C = at<char>(R.ws, L.w1); d.ldc = P.nmu; d.c32 = P.m32;
+  HIPCHK(gemm(cp, d, R.st));
+  tm.mark();
+  GemmDesc o;  // eps~^{-1} = I - W1 U^H
+  o.M = o.N = P.ng; o.K = P.nmu;
+  o.A = at<char>(R.ws, L.w1); o.sam = P.nmu; o.sak = 1; o.a32 = P.m32;
+  o.B = at<char>(R.ws, L.u); o.sbk = 1; o.sbn = P.nmu; o.conjB = true; o.b32 = P.m32;
+  o.C = out; o.ldc = P.ng;
+  o.alpha = -1.0; o.diag_add = 1.0; o.herm = true;
+  HIPCHK(gemm(cp, o, R.st));
+  return ISDF_OK;
+}
+
+isdf_status begin(isdf_handle h, const isdf_problem* prob, Problem& P, int nmu, int ng, int nomega) {
+  isdf_status s = check_problem(h, prob, P);
+  if (s != ISDF_OK) return s;
+  P.nmu = nmu;
+  P.ng = ng;
+  P.nomega = nomega;
+  if (P.prec == PBF3) return fail(h, ISDF_E_UNSUPPORTED, "BF16x3 precision is not available in this build");
+  if (!dft_supported(P.n0, P.n1, P.prec == P64 ? P64 : P32))
+    return fail(h, ISDF_E_UNSUPPORTED, "grid plane n0*n1 too large for the LDS-resident DFT slab");
+  return ISDF_OK;
+}
+
+isdf_status finish(Run& R, isdf_report* rep, Timer& tm) {
+  isdf_handle h = R.h;
+  StatusBlock hs;
+  HIPCHK(hipMemcpyAsync(&hs, R.sb, offsetof(StatusBlock, partial), hipMemcpyDeviceToHost, R.st));
+  HIPCHK(hipStreamSynchronize(R.st));
+  if (rep) {
+    rep->min_pivot = hs.min_pivot;
+    rep->n_refine_reported = R.P.refine > 0 ? R.P.refine + 1 : 0;
+    for (int k = 0; k < 9; ++k)
+      rep->refine_residual[k] = (k < rep->n_refine_reported && hs.lh2 > 0) ? std::sqrt(hs.res[k] / hs.lh2) : 0.0;
+    if (tm.on) {
+      for (int k = 0; k < 8; ++k) rep->stage_ms[k] = 0.0;
+      for (int k = 0; k + 1 < tm.k && k < 8; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
+        rep->stage_ms[k] = ms;
+      }
+    }
+  }
+  if (hs.status & 1) return fail(h, ISDF_E_NOT_PD, "a matrix that must be Hermitian positive definite is not (S = C C^H, -M or I + L^H G L)");
+  h->err.clear();
+  return ISDF_OK;
+}
+
+isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const void* psi,
+                         const int32_t* mu_idx, int n_mu, const int32_t* miller, int ng,
+                         const double* energies, int nomega, void* ws, size_t ws_bytes, Uploader& up_,
+                         DftIndex& ix, std::vector<int>& idxbuf) {
+  if (!h) return ISDF_E_ARG;
+  isdf_status s = begin(h, prob, R.P, n_mu, ng, nomega);
+  if (s != ISDF_OK) return s;
+  if (!psi) return fail(h, ISDF_E_ARG, "psi is NULL");
+  s = check_points(h, R.P, mu_idx, n_mu);
+  if (s != ISDF_OK) return s;
+  if (miller) {
+    s = check_miller(h, R.P, miller, ng);
+    if (s != ISDF_OK) return s;
+    ix = dft_index(miller, ng);
+  } else {
+    ix.xl = ix.yl = ix.zl = {0};
+    ix.d_ax = ix.d_by = {0};
+  }
+  if (energies) {
+    s = check_energies(h, R.P, energies);
+    if (s != ISDF_OK) return s;
+  }
+  R.L = make_layout(R.P, (int)ix.xl.size(), (int)ix.yl.size(), (int)ix.zl.size(), (int)ix.d_ax.size());
+  s = check_ws(h, ws, ws_bytes, R.L.total);
+  if (s != ISDF_OK) return s;
+  R.h = h;
+  R.ws = ws;
+  R.st = h->stream;
+  R.sb = at<StatusBlock>(ws, R.L.status);
+  up_.h = h;
+  up_.add(at<char>(ws, R.L.mu), mu_idx, (size_t)n_mu * 4);
+  if (energies) up_.add(at<char>(ws, R.L.e), energies, (size_t)R.P.ns * 8);
+  if (miller) {
+    up_.add(at<char>(ws, R.L.miller), miller, (size_t)ng * 12);
+    idxbuf.clear();
+    for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz})
+      idxbuf.insert(idxbuf.end(), v->begin(), v->end());
+    up_.add(at<char>(ws, R.L.idx), idxbuf.data(), idxbuf.size() * 4);
+    up_.add(at<char>(ws, R.L.recip), R.P.recip, 9 * 8);
+  }
+  return ISDF_OK;
+}
+
+isdf_status clear_status(Run& R) {
+  isdf_handle h = R.h;
+  HIPCHK(hipMemsetAsync(R.sb, 0, offsetof(StatusBlock, partial), R.st));
+  return ISDF_OK;
+}
+
+}  // namespace
+
+#define TRY(x) do { isdf_status s_ = (x); if (s_ != ISDF_OK) return s_; } while (0)
+
+extern "C" {
+
+const char* isdf_version(void) { return "isdf-smw-gfx950 0.1"; }
+
+isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
+  if (!out) return ISDF_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return ISDF_E_ARG;
+  isdf_handle h = new isdf_handle_s;
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
+  for (auto& e : h->ev)
+    if (hipEventCreate(&e) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
+  h->pinned_bytes = 1 << 20;
+  if (hipHostMalloc(&h->pinned, h->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return ISDF_E_DEVICE;
+  }
+  *out = h;
+  return ISDF_OK;
+}
+
+isdf_status isdf_destroy(isdf_handle h) {
+  if (!h) return ISDF_OK;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& e : h->ev) if (e) (void)hipEventDestroy(e);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return ISDF_OK;
+}
+
+isdf_status isdf_set_stream(isdf_handle h, void* stream) {
+  if (!h) return ISDF_E_ARG;
+  h->stream = (hipStream_t)stream;
+  return ISDF_OK;
+}
+
+const char* isdf_last_error(isdf_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+isdf_status isdf_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t ng, int32_t n_omega,
+                                 size_t* bytes) {
+  if (!bytes) return ISDF_E_ARG;
+  Problem P;
+  isdf_status s = check_problem(nullptr, prob, P);
+  if (s != ISDF_OK) return s;
+  if (n_mu < 1 || ng < 1 || n_omega < 0) return ISDF_E_ARG;
+  P.nmu = n_mu;
+  P.ng = ng;
+  P.nomega = n_omega;
+  // worst-case DFT bookkeeping for ng vectors: every list at most min(ng, n_d), pairs at most ng
+  const int kx = std::min(ng, P.n0), ky = std::min(ng, P.n1), kz = std::min(ng, P.n2);
+  const int nd = (int)std::min<long>(ng, (long)P.n0 * P.n1);
+  *bytes = make_layout(P, kx, ky, kz, nd).total;
+  return ISDF_OK;
+}
+
+isdf_status isdf_check_inputs(const isdf_problem* prob, const double* energies, const int32_t* mu_idx,
+                              int32_t n_mu, const int32_t* miller, int32_t ng, const double* omega,
+                              int32_t n_omega, char* msg, size_t msg_len) {
+  isdf_handle_s tmp;
+  isdf_handle h = &tmp;
+  auto ret = [&](isdf_status s) {
+    if (msg && msg_len) {
+      std::strncpy(msg, tmp.err.c_str(), msg_len - 1);
+      msg[msg_len - 1] = 0;
+    }
+    return s;
+  };
+  Problem P;
+  isdf_status s = begin(h, prob, P, n_mu, ng, n_omega);
+  if (s != ISDF_OK) return ret(s);
+  if (n_omega < 0 || (n_omega > 0 && !omega)) return ret(fail(h, ISDF_E_ARG, "omega list invalid"));
+  for (int k = 0; k < n_omega; ++k)
+    if (!(omega[k] >= 0.0) || !std::isfinite(omega[k])) return ret(fail(h, ISDF_E_ARG, "omega must be finite and >= 0"));
+  if ((s = check_points(h, P, mu_idx, n_mu)) != ISDF_OK) return ret(s);
+  if ((s = check_miller(h, P, miller, ng)) != ISDF_OK) return ret(s);
+  if ((s = check_energies(h, P, energies)) != ISDF_OK) return ret(s);
+  return ret(ISDF_OK);
+}
+
+isdf_status isdf_gvectors(const isdf_problem* prob, int32_t ng, int32_t* miller_out) {
+  Problem P;
+  isdf_status s = check_problem(nullptr, prob, P);
+  if (s != ISDF_OK) return s;
+  if (!miller_out || ng < 1 || (long)ng > P.nr) return ISDF_E_ARG;
+  struct M { long m2; int x, y, z; };
+  std::vector<M> all;
+  all.reserve(P.nr);
+  for (int x = -(P.n0 / 2); x < P.n0 - P.n0 / 2; ++x)
+    for (int y = -(P.n1 / 2); y < P.n1 - P.n1 / 2; ++y)
+      for (int z = -(P.n2 / 2); z < P.n2 - P.n2 / 2; ++z)
+        all.push_back({(long)x * x + (long)y * y + (long)z * z, x, y, z});
+  std::partial_sort(all.begin(), all.begin() + ng, all.end(), [](const M& a, const M& b) {
+    if (a.m2 != b.m2) return a.m2 < b.m2;
+    if (a.x != b.x) return a.x < b.x;
+    if (a.y != b.y) return a.y < b.y;
+    return a.z < b.z;
+  });
+  for (int g = 0; g < ng; ++g) {
+    miller_out[3 * g] = all[g].x;
+    miller_out[3 * g + 1] = all[g].y;
+    miller_out[3 * g + 2] = all[g].z;
+  }
+  return ISDF_OK;
+}
+
+isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* psi, const double* energies,
+                         const int32_t* mu_idx, int32_t n_mu, const int32_t* miller, int32_t ng,
+                         const double* omega, int32_t n_omega, void* workspace, size_t ws_bytes,
+                         void* eps_inv, isdf_report* rep) {
+  if (!h) return ISDF_E_ARG;
+  if (n_omega < 0 || (n_omega > 0 && !omega)) return fail(h, ISDF_E_ARG, "omega list invalid");
+  for (int k = 0; k < n_omega; ++k)
+    if (!(omega[k] >= 0.0) || !std::isfinite(omega[k])) return fail(h, ISDF_E_ARG, "omega must be finite and >= 0");
+  if (!eps_inv) return fail(h, ISDF_E_ARG, "eps_inv is NULL");
+  if (!energies) return fail(h, ISDF_E_ARG, "energies is NULL");
+  if (!miller) return fail(h, ISDF_E_ARG, "miller is NULL");
+  Run R;
+  Uploader upl;
+  DftIndex ix;
+  std::vector<int> idxbuf;
+  TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, energies, n_omega, workspace, ws_bytes, upl, ix, idxbuf));
+  HIPCHK(hipSetDevice(h->device));
+  TRY(upl.run());
+  TRY(clear_status(R));
+  Timer tm{h, rep && rep->want_timing != 0};
+  tm.mark();
+  TRY(prepare_psi(R, psi));
+  TRY(stage_points_and_s(R));
+  tm.mark();
+  TRY(stage_z(R));
+  tm.mark();
+  TRY(stage_dft(R));
+  tm.mark();
+  TRY(stage_u(R));
+  TRY(stage_gram(R));
+  tm.mark();
+  const int nw = std::max(n_omega, 1);
+  for (int k = 0; k < nw; ++k) {
+    const double om = n_omega ? omega[k] : 0.0;
+    Timer dummy{h, false};
+    Timer& t = (k == nw - 1) ? tm : dummy;
+    TRY(stage_core(R, om, nullptr));
+    t.mark();
+    TRY(stage_core_algebra(R));
+    t.mark();
+    void* out = reinterpret_cast<char*>(eps_inv) + (size_t)k * ng * ng * 16;
+    TRY(stage_out(R, out, t));
+    t.mark();
+  }
+  return finish(R, rep, tm);
+}
+
+isdf_status isdf_fit_theta(isdf_handle h, const isdf_problem* prob, const void* psi, const int32_t* mu_idx,
+                           int32_t n_mu, void* workspace, size_t ws_bytes, void* theta) {
+  if (!h) return ISDF_E_ARG;
+  if (!theta) return fail(h, ISDF_E_ARG, "theta is NULL");
+  Run R;
+  Uploader upl;
+  DftIndex ix;
+  std::vector<int> idxbuf;
+  TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, nullptr, 1, nullptr, 0, workspace, ws_bytes, upl, ix, idxbuf));
+  HIPCHK(hipSetDevice(h->device));
+  TRY(upl.run());
+  TRY(clear_status(R));
+  TRY(prepare_psi(R, psi));
+  TRY(stage_points_and_s(R));
+  TRY(stage_z(R));
+  const Problem& P = R.P;
+  // Theta^T(nu, r) = sum_mu S^{-1}(mu, nu) Zt(mu, r), S^{-1}(mu, nu) = -Sw[nu][mu]
+  GemmDesc d;
+  d.M = P.nmu; d.N = (int)P.nr; d.K = P.nmu;
+  d.A = at<char>(workspace, R.L.s); d.sam = P.nmu; d.sak = 1;
+  d.B = at<char>(workspace, R.L.zt); d.sbk = P.nr; d.sbn = 1; d.b32 = P.m32;
+  d.C = theta; d.ldc = P.nr; d.alpha = -1.0;
+  HIPCHK(gemm(P.prec == P64 ? P64 : P32, d, R.st));
+  Timer tm{h, false};
+  return finish(R, nullptr, tm);
+}
+
+isdf_status isdf_core_m(isdf_handle h, const isdf_problem* prob, const void* psi, const double* energies,
+                        const int32_t* mu_idx, int32_t n_mu, double omega, void* workspace,
+                        size_t ws_bytes, void* m_out) {
+  if (!h) return ISDF_E_ARG;
+  if (!m_out) return fail(h, ISDF_E_ARG, "m_out is NULL");
+  if (!energies) return fail(h, ISDF_E_ARG, "energies is NULL");
+  if (!(omega >= 0.0) || !std::isfinite(omega)) return fail(h, ISDF_E_ARG, "omega must be finite and >= 0");
+  Run R;
+  Uploader upl;
+  DftIndex ix;
+  std::vector<int> idxbuf;
+  TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, nullptr, 1, energies, 0, workspace, ws_bytes, upl, ix, idxbuf));
+  HIPCHK(hipSetDevice(h->device));
+  TRY(upl.run());
+  TRY(clear_status(R));
+  TRY(prepare_psi(R, psi));
+  HIPCHK(gather_points(R.psi, R.P.nr, R.P.ns, at<int>(workspace, R.L.mu), R.P.nmu, at<char>(workspace, R.L.pm), R.st));
+  TRY(stage_core(R, omega, m_out));
+  Timer tm{h, false};
+  return finish(R, nullptr, tm);
+}
+
+isdf_status isdf_coulomb_u(isdf_handle h, const isdf_problem* prob, const void* psi, const int32_t* mu_idx,
+                           int32_t n_mu, const int32_t* miller, int32_t ng, void* workspace,
+                           size_t ws_bytes, void* u_out) {
+  if (!h) return ISDF_E_ARG;
+  if (!u_out) return fail(h, ISDF_E_ARG, "u_out is NULL");
+  if (!miller) return fail(h, ISDF_E_ARG, "miller is NULL");
+  Run R;
+  Uploader upl;
+  DftIndex ix;
+  std::vector<int> idxbuf;
+  TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, nullptr, 0, workspace, ws_bytes, upl, ix, idxbuf));
+  HIPCHK(hipSetDevice(h->device));
+  TRY(upl.run());
+  TRY(clear_status(R));
+  TRY(prepare_psi(R, psi));
+  TRY(stage_points_and_s(R));
+  TRY(stage_z(R));
+  TRY(stage_dft(R));
+  TRY(stage_u(R));
+  HIPCHK(convert_z(at<char>(workspace, R.L.u), R.P.m32, u_out, false, (long)ng * n_mu, R.st));
+  Timer tm{h, false};
+  return finish(R, nullptr, tm);
+}
+
+isdf_status isdf_smw_apply(isdf_handle h, const isdf_problem* prob, const void* u, const void* m,
+                           int32_t n_mu, int32_t ng, void* workspace, size_t ws_bytes, void* eps_inv,
+                           isdf_report* rep) {
+  if (!h) return ISDF_E_ARG;
+  if (!u || !m || !eps_inv) return fail(h, ISDF_E_ARG, "u, m and eps_inv must be non-NULL");
+  Run R;
+  TRY(begin(h, prob, R.P, n_mu, ng, 0));
+  if (n_mu < 1 || ng < 1) return fail(h, ISDF_E_ARG, "n_mu and ng must be >= 1");
+  R.L = make_layout(R.P, 1, 1, 1, 1);
+  TRY(check_ws(h, workspace, ws_bytes, R.L.total));
+  R.h = h; R.ws = workspace; R.st = h->stream;
+  R.sb = at<StatusBlock>(workspace, R.L.status);
+  HIPCHK(hipSetDevice(h->device));
+  TRY(clear_status(R));
+  Timer tm{h, rep && rep->want_timing != 0};
+  tm.mark();
+  HIPCHK(convert_z(u, false, at<char>(workspace, R.L.u), R.P.m32, (long)ng * n_mu, R.st));
+  HIPCHK(scale_z(m, at<char>(workspace, R.L.l), (long)n_mu * n_mu, -1.0, R.st));  // -M
+  tm.mark();
+  tm.mark();
+  tm.mark();
+  TRY(stage_gram(R));
+  tm.mark();
+  tm.mark();
+  TRY(stage_core_algebra(R));
+  tm.mark();
+  TRY(stage_out(R, eps_inv, tm));
+  tm.mark();
+  return finish(R, rep, tm);
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// Grid-side kernels: orbitals at the interpolation points, pair weights, the
+// Coulomb factor, and the unitary 3-D DFT of the N_mu real-space columns
+// sampled on the plane-wave list.
+//
+// The DFT is pruned to the frequencies the plane-wave list needs: with the
+// sphere of NG vectors spanning kx of the n0 x-frequencies, the transform runs
+//   x:  T1[y][a]   = sum_x Z[z][y][x] twx[a][x]          (kx of n0 outputs)
+//   y:  T2[z][d]   = sum_y T1[y][a_d] twy[b_d][y]         (only (x, y) pairs in use)
+//   z:  ZG[g]      = sum_z T2[z][d_g] twz[c_g][z]          (only listed vectors)
+// Stages x and y run in one kernel per (point, z-plane) slab held in LDS
+// (one coalesced read of the slab); stage z reads the small T2.  Each
+// twiddle table carries its 1/sqrt(n) so the product is unitary.
+#include "internal.h"
+#include "tile.h"
+
+#include <cmath>
+
+namespace isdf {
+
+__global__ void widen_kernel(const double* src, z64* dst, long count) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = z64{src[i], 0.0};
+}
+
+hipError_t widen_real(const double* src, void* dst, long count, hipStream_t st) {
+  hipLaunchKernelGGL(widen_kernel, dim3(cdiv(count, 256)), dim3(256), 0, st, src, (z64*)dst, count);
+  return hipGetLastError();
+}
+
+// pm[n][mu] = psi[n * nr + mu_idx[mu]]
+__global__ void gather_kernel(const z64* psi, long nr, int ns, const int* mu, int nmu, z64* pm) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  if (m < nmu && n < ns) pm[(long)n * nmu + m] = psi[(long)n * nr + mu[m]];
+}
+
+hipError_t gather_points(const void* psi, long nr, int ns, const int* mu, int nmu, void* pm,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(gather_kernel, dim3(cdiv(nmu, 256), ns), dim3(256), 0, st, (const z64*)psi, nr,
+                     ns, mu, nmu, (z64*)pm);
+  return hipGetLastError();
+}
+
+// w[i][j] = D / (D^2 + omega^2), D = e_i - e_{nv + j}
+__global__ void weights_kernel(const double* e, int nv, int nc, double omega, double* w) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)nv * nc) return;
+  const int i = (int)(idx / nc), j = (int)(idx % nc);
+  const double d = e[i] - e[nv + j];
+  w[idx] = d / (d * d + omega * omega);
+}
+
+hipError_t pair_weights(const double* e, int nv, int nc, double omega, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(weights_kernel, dim3(cdiv((long)nv * nc, 256)), dim3(256), 0, st, e, nv, nc, omega, w);
+  return hipGetLastError();
+}
+
+// sqrt(V(G)) = sqrt(v_scale 4 pi / |G|^2), 0 at G = 0; G = sum_d m_d b_d, b_d rows of recip (2 pi included)
+__global__ void coulomb_kernel(const int* miller, int ng, const double* recip, double v_scale,
+                               double* sqrtv) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const double m0 = miller[3 * g], m1 = miller[3 * g + 1], m2 = miller[3 * g + 2];
+  double g2 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double gc = m0 * recip[c] + m1 * recip[3 + c] + m2 * recip[6 + c];
+    g2 += gc * gc;
+  }
+  sqrtv[g] = (g2 > 0.0) ? sqrt(v_scale * 4.0 * M_PI / g2) : 0.0;
+}
+
+hipError_t coulomb_sqrt(const int* miller, int ng, const double* recip, double v_scale, double* sqrtv,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(coulomb_kernel, dim3(cdiv(ng, 256)), dim3(256), 0, st, miller, ng, recip, v_scale, sqrtv);
+  return hipGetLastError();
+}
+
+// tw[a][x] = exp(-2 pi i m_a x / n) / sqrt(n), phase reduced exactly mod n first
+template <typename T>
+__global__ void twiddle_kernel(const int* mlist, int nm, int n, cx<T>* tw) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nm * n) return;
+  const int a = idx / n, x = idx % n;
+  long ph = ((long)mlist[a] * x) % n;
+  if (ph < 0) ph += n;
+  double s, c;
+  sincospi(-2.0 * (double)ph / (double)n, &s, &c);
+  const double sc = 1.0 / sqrt((double)n);
+  tw[idx] = cx<T>{(T)(c * sc), (T)(s * sc)};
+}
+
+hipError_t dft_twiddles(const int* mlist, int nm, int n, bool f32, void* tw, hipStream_t st) {
+  if (f32) hipLaunchKernelGGL((twiddle_kernel<float>), dim3(cdiv(nm * n, 256)), dim3(256), 0, st, mlist, nm, n, (c32*)tw);
+  else hipLaunchKernelGGL((twiddle_kernel<double>), dim3(cdiv(nm * n, 256)), dim3(256), 0, st, mlist, nm, n, (z64*)tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+static size_t xy_lds_bytes(const DftPlan& p) {
+  return sizeof(cx<T>) * ((size_t)p.n0 * p.n1 + (size_t)p.n1 * p.kx + (size_t)p.kx * p.n0 +
+                          (size_t)p.ky * p.n1);
+}
+
+// one workgroup per (z-plane, point)
+template <typename T>
+__global__ __launch_bounds__(256) void dft_xy_kernel(DftPlan p, const cx<T>* zt, cx<T>* t2) {
+  extern __shared__ unsigned char lds_raw[];
+  cx<T>* S = reinterpret_cast<cx<T>*>(lds_raw);          // [n1][n0]
+  cx<T>* T1 = S + p.n0 * p.n1;                           // [n1][kx]
+  cx<T>* TX = T1 + p.n1 * p.kx;                          // [kx][n0]
+  cx<T>* TY = TX + p.kx * p.n0;                          // [ky][n1]
+  const int z = blockIdx.x, mu = blockIdx.y;
+  const int tid = threadIdx.x;
+  const long slab = ((long)mu * p.n2 + z) * p.n1 * p.n0;
+  const cx<T>* twx = reinterpret_cast<const cx<T>*>(p.twx);
+  const cx<T>* twy = reinterpret_cast<const cx<T>*>(p.twy);
+  for (int i = tid; i < p.n0 * p.n1; i += 256) S[i] = zt[slab + i];
+  for (int i = tid; i < p.kx * p.n0; i += 256) TX[i] = twx[i];
+  for (int i = tid; i < p.ky * p.n1; i += 256) TY[i] = twy[i];
+  __syncthreads();
+  for (int i = tid; i < p.n1 * p.kx; i += 256) {
+    const int y = i / p.kx, a = i % p.kx;
+    const cx<T>* row = S + y * p.n0;
+    const cx<T>* tw = TX + a * p.n0;
+    T sr = 0, si = 0;
+    for (int x = 0; x < p.n0; ++x) {
+      sr += row[x].re * tw[x].re - row[x].im * tw[x].im;
+      si += row[x].re * tw[x].im + row[x].im * tw[x].re;
+    }
+    T1[i] = cx<T>{sr, si};
+  }
+  __syncthreads();
+  cx<T>* out = t2 + ((long)mu * p.n2 + z) * p.nd;
+  for (int d = tid; d < p.nd; d += 256) {
+    const int a = p.d_ax[d], b = p.d_by[d];
+    const cx<T>* tw = TY + b * p.n1;
+    T sr = 0, si = 0;
+    for (int y = 0; y < p.n1; ++y) {
+      const cx<T> v = T1[y * p.kx + a];
+      sr += v.re * tw[y].re - v.im * tw[y].im;
+      si += v.re * tw[y].im + v.im * tw[y].re;
+    }
+    out[d] = cx<T>{sr, si};
+  }
+}
+
+bool dft_supported(int n0, int n1, Prec compute) {
+  const size_t elem = compute == P64 ? 16 : 8;
+  // worst case kx = n0, ky = n1
+  return elem * ((size_t)n0 * n1 * 2 + (size_t)n0 * n0 + (size_t)n1 * n1) <= 160 * 1024;
+}
+
+hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st) {
+  const dim3 grid(p.n2, p.nmu);
+  if (compute == P64) {
+    const size_t lds = xy_lds_bytes<double>(p);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_xy_kernel<double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((dft_xy_kernel<double>), grid, dim3(256), lds, st, p, (const z64*)zt, (z64*)t2);
+  } else {
+    const size_t lds = xy_lds_bytes<float>(p);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_xy_kernel<float>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((dft_xy_kernel<float>), grid, dim3(256), lds, st, p, (const c32*)zt, (c32*)t2);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void dft_z_kernel(DftPlan p, const cx<T>* t2, cx<T>* zg) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mu = blockIdx.y;
+  if (g >= p.ng) return;
+  const int d = p.g_d[g], c = p.g_cz[g];
+  const cx<T>* twz = reinterpret_cast<const cx<T>*>(p.twz) + (long)c * p.n2;
+  const cx<T>* col = t2 + (long)mu * p.n2 * p.nd + d;
+  T sr = 0, si = 0;
+  for (int z = 0; z < p.n2; ++z) {
+    const cx<T> v = col[(long)z * p.nd];
+    sr += v.re * twz[z].re - v.im * twz[z].im;
+    si += v.re * twz[z].im + v.im * twz[z].re;
+  }
+  zg[(long)mu * p.ng + g] = cx<T>{sr, si};
+}
+
+hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, hipStream_t st) {
+  const dim3 grid(cdiv(p.ng, 256), p.nmu);
+  if (compute == P64)
+    hipLaunchKernelGGL((dft_z_kernel<double>), grid, dim3(256), 0, st, p, (const z64*)t2, (z64*)zg);
+  else
+    hipLaunchKernelGGL((dft_z_kernel<float>), grid, dim3(256), 0, st, p, (const c32*)t2, (c32*)zg);
+  return hipGetLastError();
+}
+
+}  // namespace isdf

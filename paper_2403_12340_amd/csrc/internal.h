@@ -1,0 +1,84 @@
+// Host-side launch interface between the C-ABI layer (api.hip) and the kernels.
+// Every launcher enqueues on `st` and returns the launch status.  Matrices are
+// row-major complex (interleaved) unless stated otherwise; "z" = complex128,
+// "c" = complex64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace isdf {
+
+enum Prec { P64 = 0, P32 = 1, PBF3 = 2 };
+
+// ----- generic complex GEMM:  C = alpha * diag(rs) * op(A) op(B) + beta * C + diag_add * I
+struct GemmDesc {
+  int M = 0, N = 0, K = 0;
+  const void* A = nullptr; long sam = 0, sak = 0; bool conjA = false; bool a32 = false;
+  const void* B = nullptr; long sbk = 0, sbn = 0; bool conjB = false; bool b32 = false;
+  void* C = nullptr; long ldc = 0; bool c32 = false;
+  double alpha = 1.0, beta = 0.0, diag_add = 0.0;
+  const double* row_scale = nullptr;  // device, length M, optional
+  bool herm = false;                  // only lower tiles; upper mirrored as conj
+  // sweep epilogue (FP64 only): rows/cols [sw_k0, sw_k0 + sw_kn) come from the panel R
+  bool sweep = false; int sw_k0 = 0, sw_kn = 0; const void* R = nullptr; long ldr = 0;
+};
+// Compute precision: P64 -> f64 MFMA; P32 -> f32 MFMA.
+hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st);
+
+// ----- orbital pair Gram (step 1):  out[mu][c] = conj(Pv(mu, c)) * Qc(mu, c)
+//   Pv(mu, c) = sum_{i < nv} conj(pm[i][mu]) b[i][c],  Qc(mu, c) = sum_{nv <= j < ns} conj(pm[j][mu]) b[j][c]
+//   pm: [ns][ldp] complex128 (orbitals at the points), b: [ns][ldb] complex128, out [M][ldo]
+hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
+                 long ldb, void* out, long ldo, bool out32, hipStream_t st);
+
+// ----- core (step 2): partial sums over occupied ranges of
+//   M(mu, nu) = sum_{i, j} conj(a_i(mu)) b_j(mu) w_ij a_i(nu) conj(b_j(nu))
+// pm: [ns][ldp] complex128; w: [nv][nc] double; part: nsplit x nmu x nmu complex (f64 or f32 per compute)
+int core_splits(int nmu, int nv);
+hipError_t core_partial(Prec compute, int nmu, int nv, int nc, const void* pm, long ldp,
+                        const double* w, void* part, int nsplit, hipStream_t st);
+// M_out = scale * sum_s part[s]; writes complex128 (and optionally -M into negm)
+hipError_t core_reduce(Prec compute, int nmu, const void* part, int nsplit, double scale, void* m_out,
+                       void* negm_out, hipStream_t st);
+
+// ----- small FP64 dense algebra, row-major n x n complex128, ld = n
+// In-place lower Cholesky A = L L^H; the strict upper triangle is zeroed.
+hipError_t potrf(int n, void* a, void* scratch, int* status, hipStream_t st);
+// In-place Hermitian positive definite sweep: A <- -A^{-1}.  scratch: 2 * 64 * n complex128.
+hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st);
+size_t linalg_scratch_bytes(int n);
+
+// ----- grid / plane-wave helpers
+hipError_t widen_real(const double* src, void* dst, long count, hipStream_t st);
+hipError_t gather_points(const void* psi, long nr, int ns, const int* mu, int nmu, void* pm,
+                         hipStream_t st);
+hipError_t pair_weights(const double* e, int nv, int nc, double omega, double* w, hipStream_t st);
+hipError_t coulomb_sqrt(const int* miller, int ng, const double* recip /*3x3 rows*/, double v_scale,
+                        double* sqrtv, hipStream_t st);
+// DFT tables: twiddles tw[a][x] = exp(-2 pi i m_a x / n) / sqrt(n) for a list of m values
+hipError_t dft_twiddles(const int* mlist, int nm, int n, bool f32, void* tw, hipStream_t st);
+struct DftPlan {
+  int n0, n1, n2, nmu, ng;
+  int kx, ky, nd, kz;      // kept x- and y-frequencies, distinct (x, y) pairs, kept z-frequencies
+  const void* twx;         // kx x n0
+  const void* twy;         // ky x n1 (indexed by d_y)
+  const void* twz;         // kz x n2
+  const int* d_ax;         // nd: index into twx list for pair d
+  const int* d_by;         // nd: index into twy list for pair d
+  const int* g_d;          // ng: pair index of plane wave g
+  const int* g_cz;         // ng: index into twz list of plane wave g
+};
+// zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][n2][nd] -> zg: [nmu][ng]
+hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);
+hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, hipStream_t st);
+bool dft_supported(int n0, int n1, Prec compute);
+
+hipError_t conj_transpose(int n, const void* a, void* at, hipStream_t st);   // at = a^H (z64)
+hipError_t convert_z(const void* src, bool src32, void* dst, bool dst32, long count, hipStream_t st);
+hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStream_t st);  // z64
+// out[0] += ||a||_F^2 over count complex128, deterministic (single pass of block partials)
+hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st);
+hipError_t diag_min(const void* a, int n, double* out, hipStream_t st);
+
+}  // namespace isdf

@@ -1,0 +1,278 @@
+// Step 1 and step 2 contractions with operands generated on the fly.
+//
+// zpair:  out(mu, c) = conj(Pv(mu, c)) * Qc(mu, c), the least-squares right-hand
+//   side of the ISDF fit in factored form (Hadamard product of two orbital
+//   Gram blocks): Pv = conj(Psi_v(r_mu)) Psi_v^T, Qc = conj(Psi_c(r_mu)) Psi_c^T.
+//   Both blocks are accumulated in registers by one kernel (two K phases) and
+//   multiplied in the epilogue, so neither Gram block ever reaches HBM.
+//
+// core:  M(mu, nu) = sum_{i in v, j in c} C(mu; i, j) w_ij conj(C(nu; i, j)) with
+//   C(mu; i, j) = conj(psi_i(r_mu)) psi_j(r_mu) (eq. COmegaCstar): a HERK with
+//   K = Nv Nc whose operands are built tile by tile in LDS from the orbitals at
+//   the points (Khatri-Rao on the fly), never stored.  Only lower tiles are
+//   computed (mirrored), and the occupied index is split across workgroups with
+//   a deterministic fixed-order reduction.
+#include "internal.h"
+#include "tile.h"
+
+#include <cmath>
+
+namespace isdf {
+
+// ----------------------------------------------------------------------------
+// shared K loop: acc += A(m, k) B(k, n) over [0, K) with x-contiguous operands
+// ----------------------------------------------------------------------------
+template <typename T, class TL>
+__device__ __forceinline__ void kloop_xx(cx<T>* smem, const z64* A, long lda, const z64* B, long ldb,
+                                         int m0, int n0, int M, int N, int K, T ca, T cb,
+                                         typename TL::acc_t (&acc)[TL::FM][TL::FN], int tid,
+                                         int wm0, int wn0, int lane) {
+  Stager<T, double, TL::BM, TL::BK, TL::NT, true> sa;
+  Stager<T, double, TL::BN, TL::BK, TL::NT, true> sb;
+  const int nk = (K + TL::BK - 1) / TL::BK;
+  if (nk == 0) return;
+  sa.fetch(A, 1, lda, m0, 0, M, K, ca, tid);
+  sb.fetch(B, 1, ldb, n0, 0, N, K, cb, tid);
+  __syncthreads();
+  sa.store(smem, TL::LDA, tid);
+  sb.store(smem + TL::AS, TL::LDB, tid);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) {
+      sa.fetch(A, 1, lda, m0, (kt + 1) * TL::BK, M, K, ca, tid);
+      sb.fetch(B, 1, ldb, n0, (kt + 1) * TL::BK, N, K, cb, tid);
+    }
+    cx<T>* sc = smem + cur * (TL::AS + TL::BS);
+    cx<T>* sn = smem + (cur ^ 1) * (TL::AS + TL::BS);
+    tile_mma<T, TL>(sc, sc + TL::AS, acc, wm0, wn0, lane);
+    if (kt + 1 < nk) {
+      sa.store(sn, TL::LDA, tid);
+      sb.store(sn + TL::AS, TL::LDB, tid);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, typename SO, class TL>
+__global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int ns, const z64* pm,
+                                                       long ldp, const z64* b, long ldb, SO* out,
+                                                       long ldo, int ntm, int total) {
+  __shared__ cx<T> smem[2 * (TL::AS + TL::BS)];
+  const int id = xcd_remap(blockIdx.x, total);
+  if (id >= total) return;
+  const int bm = id % ntm, bn = id / ntm;
+  const int m0 = bm * TL::BM, n0 = bn * TL::BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave % TL::WGM) * TL::WTM, wn0 = (wave / TL::WGM) * TL::WTN;
+
+  typename TL::acc_t accp[TL::FM][TL::FN], accq[TL::FM][TL::FN];
+  zero_acc<TL>(accp);
+  zero_acc<TL>(accq);
+  kloop_xx<T, TL>(smem, pm, ldp, b, ldb, m0, n0, M, N, nv, (T)-1, (T)1, accp, tid, wm0, wn0, lane);
+  kloop_xx<T, TL>(smem, pm + (long)nv * ldp, ldp, b + (long)nv * ldb, ldb, m0, n0, M, N, ns - nv,
+                  (T)-1, (T)1, accq, tid, wm0, wn0, lane);
+
+  const int rc = lane & 15, part = rc & 1;
+#pragma unroll
+  for (int fm = 0; fm < TL::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < TL::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T po = accp[fm][fn][v], qo = accq[fm][fn][v];
+        const T px = xor1(po), qx = xor1(qo);
+        // conj(P) Q: re = Pr Qr + Pi Qi, im = Pr Qi - Pi Qr
+        const T val = part == 0 ? (po * qo + px * qx) : (px * qo - po * qx);
+        const int row = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, v);
+        const int col = n0 + wn0 + fn * 8 + (rc >> 1);
+        if (row < M && col < N) out[((long)row * ldo + col) * 2 + part] = (SO)val;
+      }
+}
+
+typedef Tile<double, 64, 64, 16, 2, 2> TZ64;
+typedef Tile<float, 64, 64, 32, 2, 2> TZ32;
+
+template <typename T, typename SO, class TL>
+static hipError_t zpair_launch(int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
+                               long ldb, void* out, long ldo, hipStream_t st) {
+  const int ntm = (int)cdiv(M, TL::BM), ntn = (int)cdiv(N, TL::BN);
+  const int total = ntm * ntn;
+  if (total == 0) return hipSuccess;
+  const unsigned grid = 8u * (unsigned)((total + 7) / 8);
+  hipLaunchKernelGGL((zpair_kernel<T, SO, TL>), dim3(grid), dim3(TL::NT), 0, st, M, N, nv, ns,
+                     (const z64*)pm, ldp, (const z64*)b, ldb, (SO*)out, ldo, ntm, total);
+  return hipGetLastError();
+}
+
+hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
+                 long ldb, void* out, long ldo, bool out32, hipStream_t st) {
+  if (compute == P64) {
+    if (out32) return hipErrorInvalidValue;
+    return zpair_launch<double, double, TZ64>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+  }
+  if (out32) return zpair_launch<float, float, TZ32>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+  return zpair_launch<float, double, TZ32>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+}
+
+// ----------------------------------------------------------------------------
+// core
+// ----------------------------------------------------------------------------
+template <typename T, class TL>
+__global__ __launch_bounds__(TL::NT) void core_kernel(int nmu, int nv, int nc, const z64* pm, long ldp,
+                                                      const double* w, cx<T>* part, int nsplit,
+                                                      int total) {
+  __shared__ cx<T> smem[2 * (TL::AS + TL::BS)];
+  static_assert(TL::BM == TL::BN, "square tiles");
+  static_assert(TL::NT % TL::BM == 0, "thread map");
+  const int id = xcd_remap(blockIdx.x, total);
+  if (id >= total) return;
+  int r = (int)((sqrt(8.0 * id + 1.0) - 1.0) * 0.5);
+  while (r * (r + 1) / 2 > id) --r;
+  while ((r + 1) * (r + 2) / 2 <= id) ++r;
+  const int bm = r, bn = id - r * (r + 1) / 2;
+  const int m0 = bm * TL::BM, n0 = bn * TL::BN;
+  const int split = blockIdx.y;
+  const int i0 = (int)((long)split * nv / nsplit), i1 = (int)((long)(split + 1) * nv / nsplit);
+  const int ni = i1 - i0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave % TL::WGM) * TL::WTM, wn0 = (wave / TL::WGM) * TL::WTN;
+
+  // thread map: x = tid % BM (point within tile), kk = tid / BM + e * (NT / BM)
+  constexpr int KSTEP = TL::NT / TL::BM;
+  constexpr int E = TL::BK / KSTEP;
+  const int x = tid % TL::BM, kb = tid / TL::BM;
+  const int gm = m0 + x, gn = n0 + x;
+  const bool okm = gm < nmu, okn = gn < nmu;
+  const z64* pc = pm + (long)nv * ldp;
+
+  typename TL::acc_t acc[TL::FM][TL::FN];
+  zero_acc<TL>(acc);
+
+  const int njc = (nc + TL::BK - 1) / TL::BK;
+  const int S = njc * ni;
+  cx<T> bm_r[E], bn_r[E];   // conj-free orbital values b_j at this thread's points
+  cx<T> va[E], vb[E];       // staged A / B elements
+  int cur_jc = -1;
+
+  auto produce = [&](int s) {
+    const int jc = s / ni, i = i0 + s % ni;
+    if (jc != cur_jc) {
+      cur_jc = jc;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int j = jc * TL::BK + kb + e * KSTEP;
+        cx<T> zm{0, 0}, zn{0, 0};
+        if (j < nc) {
+          if (okm) zm = cvt<T>(pc[(long)j * ldp + gm]);
+          if (okn) zn = cvt<T>(pc[(long)j * ldp + gn]);
+        }
+        bm_r[e] = zm;
+        bn_r[e] = zn;
+      }
+    }
+    const cx<T> am = okm ? cvt<T>(pm[(long)i * ldp + gm]) : cx<T>{0, 0};
+    const cx<T> an = okn ? cvt<T>(pm[(long)i * ldp + gn]) : cx<T>{0, 0};
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = jc * TL::BK + kb + e * KSTEP;
+      const T wij = (j < nc) ? (T)w[(long)i * nc + j] : (T)0;
+      cx<T> t = cmulc(am, bm_r[e]);           // conj(a_i(mu)) b_j(mu)
+      va[e] = cx<T>{t.re * wij, t.im * wij};
+      vb[e] = cmul(an, cconj(bn_r[e]));       // a_i(nu) conj(b_j(nu))
+    }
+  };
+  auto store = [&](cx<T>* buf) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kk = kb + e * KSTEP;
+      buf[kk * TL::LDA + x] = va[e];
+      buf[TL::AS + kk * TL::LDB + x] = vb[e];
+    }
+  };
+
+  if (S > 0) {
+    produce(0);
+    store(smem);
+    __syncthreads();
+    for (int s = 0; s < S; ++s) {
+      const int cur = s & 1;
+      if (s + 1 < S) produce(s + 1);
+      cx<T>* sc = smem + cur * (TL::AS + TL::BS);
+      tile_mma<T, TL>(sc, sc + TL::AS, acc, wm0, wn0, lane);
+      if (s + 1 < S) store(smem + (cur ^ 1) * (TL::AS + TL::BS));
+      __syncthreads();
+    }
+  }
+
+  T* out = reinterpret_cast<T*>(part + (long)split * nmu * nmu);
+  const int rc = lane & 15, pp = rc & 1;
+#pragma unroll
+  for (int fm = 0; fm < TL::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < TL::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, v);
+        const int col = n0 + wn0 + fn * 8 + (rc >> 1);
+        if (row >= nmu || col >= nmu) continue;
+        const T val = acc[fm][fn][v];
+        if (bm == bn && row < col) continue;
+        out[((long)row * nmu + col) * 2 + pp] = val;
+        if (row > col) out[((long)col * nmu + row) * 2 + pp] = pp ? -val : val;
+      }
+}
+
+typedef Tile<double, 64, 64, 16, 2, 2> TC64;
+typedef Tile<float, 64, 64, 32, 2, 2> TC32;
+
+int core_splits(int nmu, int nv) {
+  const int nt = (nmu + 63) / 64;
+  const int tiles = nt * (nt + 1) / 2;
+  int s = (1024 + tiles - 1) / tiles;
+  if (s > nv) s = nv;
+  if (s < 1) s = 1;
+  return s;
+}
+
+hipError_t core_partial(Prec compute, int nmu, int nv, int nc, const void* pm, long ldp,
+                        const double* w, void* part, int nsplit, hipStream_t st) {
+  const int nt = (nmu + 63) / 64;
+  const int total = nt * (nt + 1) / 2;
+  const unsigned gx = 8u * (unsigned)((total + 7) / 8);
+  if (compute == P64) {
+    hipLaunchKernelGGL((core_kernel<double, TC64>), dim3(gx, nsplit), dim3(TC64::NT), 0, st, nmu, nv,
+                       nc, (const z64*)pm, ldp, w, (z64*)part, nsplit, total);
+  } else {
+    hipLaunchKernelGGL((core_kernel<float, TC32>), dim3(gx, nsplit), dim3(TC32::NT), 0, st, nmu, nv,
+                       nc, (const z64*)pm, ldp, w, (c32*)part, nsplit, total);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void core_reduce_kernel(long n2, const T* part, int nsplit, double scale, double* m_out,
+                                   double* negm) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;  // real index over 2 n2
+  if (idx >= 2 * n2) return;
+  double s = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += (double)part[(long)k * 2 * n2 + idx];
+  s *= scale;
+  if (m_out) m_out[idx] = s;
+  if (negm) negm[idx] = -s;
+}
+
+hipError_t core_reduce(Prec compute, int nmu, const void* part, int nsplit, double scale, void* m_out,
+                       void* negm_out, hipStream_t st) {
+  const long n2 = (long)nmu * nmu;
+  const unsigned grid = cdiv(2 * n2, 256);
+  if (compute == P64)
+    hipLaunchKernelGGL((core_reduce_kernel<double>), dim3(grid), dim3(256), 0, st, n2,
+                       (const double*)part, nsplit, scale, (double*)m_out, (double*)negm_out);
+  else
+    hipLaunchKernelGGL((core_reduce_kernel<float>), dim3(grid), dim3(256), 0, st, n2,
+                       (const float*)part, nsplit, scale, (double*)m_out, (double*)negm_out);
+  return hipGetLastError();
+}
+
+}  // namespace isdf

@@ -1,0 +1,98 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+function, and its host-side logic (plane-wave list, workspace sizing, argument
+validation) behaves as documented."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2403_12340_amd as isdf
+import synth
+
+
+def test_library_exports_every_declared_symbol():
+    lib = isdf.lib()
+    names = isdf.header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.isdf_version().startswith(b"isdf-smw-gfx950")
+
+
+@pytest.mark.parametrize("name", ["tiny", "cfg0", "mid", "cfg1"])
+def test_gvectors_match_generator(name):
+    c = synth.CONFIGS[name]
+    n = c["n"]
+    prob = isdf.make_problem(n, np.eye(3) * synth.box_length(c["nv"]), c["nv"], c["nc"])
+    got = isdf.gvectors(prob, c["ng"])
+    np.testing.assert_array_equal(got, synth.miller_list(n, c["ng"]))
+
+
+def test_workspace_bytes_monotone_and_validated():
+    prob = isdf.make_problem(48, np.eye(3) * 20.0, 64, 256)
+    a = isdf.workspace_bytes(prob, 640, 4096)
+    b = isdf.workspace_bytes(prob, 700, 4096)
+    c = isdf.workspace_bytes(prob, 640, 5000)
+    assert 0 < a < b and a < c
+    # FP32 stores the large intermediates in complex64: smaller
+    p32 = isdf.make_problem(48, np.eye(3) * 20.0, 64, 256, prec="fp32")
+    assert isdf.workspace_bytes(p32, 640, 4096) < a
+    out = ctypes.c_size_t(0)
+    bad = isdf.make_problem(48, np.eye(3) * 20.0, 64, 256)
+    bad.nv = 0
+    assert isdf.lib().isdf_workspace_bytes(ctypes.byref(bad), 640, 4096, 0, ctypes.byref(out)) == isdf.binding.E_ARG
+    assert isdf.lib().isdf_workspace_bytes(ctypes.byref(prob), 0, 4096, 0, ctypes.byref(out)) == isdf.binding.E_ARG
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return synth.make_inputs("cfg0")
+
+
+def test_check_inputs_accepts_valid(cfg0):
+    prob = isdf.problem_for(cfg0)
+    assert isdf.check_inputs(prob, cfg0.energies, cfg0.mu_idx, cfg0.miller) == (0, "")
+    assert isdf.check_inputs(prob, cfg0.energies, cfg0.mu_idx, cfg0.miller, omegas=[0.0, 0.1, 3.0])[0] == 0
+
+
+def test_check_inputs_rejects(cfg0):
+    x = cfg0
+    prob = isdf.problem_for(x)
+    E = isdf.binding.E_ARG
+
+    def st(**kw):
+        args = dict(energies=x.energies, mu_idx=x.mu_idx, miller=x.miller, omegas=None)
+        args.update(kw)
+        p = kw.pop("prob", prob)
+        return isdf.check_inputs(p, args["energies"], args["mu_idx"], args["miller"], args["omegas"])
+
+    dup = x.mu_idx.copy(); dup[3] = dup[2]
+    assert st(mu_idx=dup) == (E, "mu_idx has duplicate points")
+    oob = x.mu_idx.copy(); oob[0] = x.nr
+    assert st(mu_idx=oob)[0] == E
+    assert st(mu_idx=np.arange(x.nv * x.nc + 1))[0] == E
+    e = x.energies.copy(); e[x.nv - 1] = e[x.nv] + 0.01
+    assert st(energies=e)[1].startswith("no gap")
+    e = x.energies.copy(); e[0] = np.nan
+    assert st(energies=e)[0] == E
+    m = x.miller.copy(); m[5] = m[4]
+    assert st(miller=m)[1] == "miller list has duplicates"
+    m = x.miller.copy(); m[7, 0] = x.n // 2
+    assert st(miller=m)[0] == E
+    assert st(omegas=[0.1, -1.0])[0] == E
+    p = isdf.problem_for(x); p.n[1] = 1
+    assert st(prob=p)[0] == E
+    p = isdf.problem_for(x); p.refine_steps = 9
+    assert st(prob=p)[0] == E
+    p = isdf.problem_for(x); p.cell[0] = 0.0; p.cell[4] = 0.0
+    assert st(prob=p)[0] == E
+
+
+def test_create_without_gpu_is_an_error():
+    """No GPU here: creating a handle must fail cleanly, never fall back to the CPU."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert isdf.lib().isdf_create(ctypes.byref(h), 0, None) != 0
+    assert isdf.lib().isdf_eps_inv(None, None, None, None, None, 0, None, 0, None, 0, None, 0, None, None) == isdf.binding.E_ARG

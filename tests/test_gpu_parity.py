@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars (element-wise on the same seeded inputs):
+  FP64 path: relative Frobenius error of eps~^{-1} <= 1e-10 (stated target);
+  FP32 path: relative Frobenius error of eps~^{-1} <= 1e-6 (stated target for the
+             mixed path).  Stage outputs in FP32 (Theta, U, M) are checked at
+             1e-4 relative: FP32 rounding (6e-8) times the conditioning of the
+             least-squares fit (cond(C C^H) up to ~1e3 at these sizes).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_12340_amd as isdf
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank"]
+TOL_EPS = {"fp64": 1e-10, "fp32": 1e-6}
+TOL_STAGE = {"fp64": 1e-10, "fp32": 1e-4}
+
+_inputs = {}
+_stages = {}
+
+
+def get_inputs(name):
+    if name not in _inputs:
+        _inputs[name] = synth.make_inputs(name)
+    return _inputs[name]
+
+
+def get_stages(name):
+    if name not in _stages:
+        _stages[name] = oracle.isdf_stages(get_inputs(name))
+    return _stages[name]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def relf(got, ref):
+    return np.linalg.norm(got - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", SMALL)
+def test_theta(name, prec):
+    inp = get_inputs(name)
+    print(f"[theta] case={name} prec={prec}", flush=True)
+    got = isdf.fit_theta(dev(inp.psi_t), inp.mu_idx, isdf.problem_for(inp, prec)).cpu().numpy().T
+    ref = get_stages(name)["theta"]
+    assert relf(got, ref) <= TOL_STAGE[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", SMALL)
+def test_core(name, prec):
+    inp = get_inputs(name)
+    print(f"[core] case={name} prec={prec}", flush=True)
+    got = isdf.core_m(dev(inp.psi_t), inp.energies, inp.mu_idx, isdf.problem_for(inp, prec)).cpu().numpy()
+    ref = get_stages(name)["m"]
+    assert relf(got, ref) <= TOL_STAGE[prec] * 1e-2
+    assert np.abs(got - got.conj().T).max() == 0.0  # lower computed, upper mirrored
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", SMALL)
+def test_coulomb_u(name, prec):
+    inp = get_inputs(name)
+    print(f"[u] case={name} prec={prec}", flush=True)
+    got = isdf.coulomb_u(dev(inp.psi_t), inp.mu_idx, inp.miller, isdf.problem_for(inp, prec)).cpu().numpy()
+    ref = get_stages(name)["u"]
+    assert relf(got, ref) <= TOL_STAGE[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", SMALL)
+def test_smw_apply(name, prec):
+    """Step 4 alone from the oracle's U and M, against the dense-LU inverse."""
+    inp = get_inputs(name)
+    st = get_stages(name)
+    print(f"[smw] case={name} prec={prec}", flush=True)
+    res = isdf.smw_apply(dev(st["u"]), dev(st["m"]), isdf.problem_for(inp, prec))
+    got = res.eps_inv[0].cpu().numpy()
+    ref = oracle.eps_inv_isdf(inp, stages=st)
+    assert relf(got, ref) <= TOL_EPS[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", SMALL)
+def test_eps_inv(name, prec):
+    inp = get_inputs(name)
+    print(f"[eps_inv] case={name} prec={prec}", flush=True)
+    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, isdf.problem_for(inp, prec))
+    got = res.eps_inv[0].cpu().numpy()
+    ref = oracle.eps_inv_isdf(inp, stages=get_stages(name))
+    eye = np.eye(inp.ng)
+    err = relf(got, ref)
+    err_screen = np.linalg.norm(got - ref) / np.linalg.norm(ref - eye)
+    print(f"  rel-F {err:.3e}  max-abs {np.abs(got - ref).max():.3e}  rel-F(eps^-1 - I) {err_screen:.3e}")
+    assert err <= TOL_EPS[prec]
+    assert np.array_equal(got, got.conj().T)             # exactly Hermitian
+    e0 = np.zeros(inp.ng); e0[0] = 1.0
+    assert np.array_equal(got[0], e0) and np.array_equal(got[:, 0], e0)  # V(0) = 0
+
+
+def test_fullrank_equals_exact_definition():
+    """N_mu = Nv Nc: the GPU ISDF-SMW result equals chi0 from all pairs + dense LU."""
+    inp = get_inputs("fullrank")
+    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, isdf.problem_for(inp, "fp64"))
+    got = res.eps_inv[0].cpu().numpy()
+    ref = oracle.eps_inv_exact(inp)
+    assert relf(got, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_frequencies(prec):
+    inp = synth.make_inputs("mid", n_omega=4)
+    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, isdf.problem_for(inp, prec),
+                       omegas=inp.omegas)
+    got = res.eps_inv.cpu().numpy()
+    st = get_stages("mid")
+    for k, om in enumerate(inp.omegas):
+        stw = dict(st)
+        stw["m"] = oracle.core_matrix(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, omega=om)
+        ref = oracle.eps_inv_isdf(inp, stages=stw)
+        assert relf(got[k], ref) <= TOL_EPS[prec], (k, om)
+
+
+def test_refinement_reports_residual():
+    inp = get_inputs("mid")
+    prob = isdf.problem_for(inp, "fp32", refine_steps=2)
+    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, prob)
+    rep = res.report
+    assert rep.n_refine_reported == 3
+    r = [rep.refine_residual[k] for k in range(3)]
+    assert all(np.isfinite(r)) and r[-1] < 1e-13
+    got = res.eps_inv[0].cpu().numpy()
+    assert relf(got, oracle.eps_inv_isdf(inp, stages=get_stages("mid"))) <= TOL_EPS["fp32"]
+
+
+def test_deterministic():
+    inp = get_inputs("mid")
+    prob = isdf.problem_for(inp, "fp32")
+    a = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, prob).eps_inv.cpu()
+    b = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, prob).eps_inv.cpu()
+    assert torch.equal(a, b)
+
+
+def test_side_stream():
+    inp = get_inputs("cfg0")
+    prob = isdf.problem_for(inp, "fp64")
+    psi = dev(inp.psi_t)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        res = isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob)
+    torch.cuda.synchronize()
+    got = res.eps_inv[0].cpu().numpy()
+    assert relf(got, oracle.eps_inv_isdf(inp, stages=get_stages("cfg0"))) <= 1e-10
+
+
+def test_error_paths():
+    inp = get_inputs("cfg0")
+    prob = isdf.problem_for(inp, "fp64")
+    psi = dev(inp.psi_t)
+    bad_mu = inp.mu_idx.copy(); bad_mu[1] = bad_mu[0]
+    with pytest.raises(isdf.IsdfError) as e:
+        isdf.eps_inv(psi, inp.energies, bad_mu, inp.miller, prob)
+    assert e.value.status == -1
+    e2 = inp.energies.copy(); e2[0] = e2[-1] + 1.0
+    with pytest.raises(isdf.IsdfError) as e:
+        isdf.eps_inv(psi, e2, inp.mu_idx, inp.miller, prob)
+    assert e.value.status == -1
+    # every orbital vanishes at one interpolation point -> C has a zero row -> S singular
+    psi0 = inp.psi_t.copy(); psi0[:, inp.mu_idx[5]] = 0.0
+    with pytest.raises(isdf.IsdfError) as e:
+        isdf.eps_inv(dev(psi0), inp.energies, inp.mu_idx, inp.miller, prob)
+    assert e.value.status == -2
+    # the library still works afterwards
+    res = isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob)
+    assert relf(res.eps_inv[0].cpu().numpy(), oracle.eps_inv_isdf(inp, stages=get_stages("cfg0"))) <= 1e-10
