@@ -108,6 +108,7 @@ __global__ __launch_bounds__(TL::NT) void gemm_kernel(GemmP p) {
         if (part == 0 && row == col) val += p.diag_add;
         if (p.beta != 0.0) val += p.beta * (double)Cr[off];
         if (p.herm && bm == bn && row < col) continue;
+        if (p.herm && row == col && part == 1) val = 0.0;  // Hermitian: real diagonal
         Cr[off] = (SC)val;
         if (p.herm && row > col) Cr[((long)col * p.ldc + row) * 2 + part] = (SC)(part ? -val : val);
       }

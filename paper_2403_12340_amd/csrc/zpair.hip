@@ -216,7 +216,7 @@ __global__ __launch_bounds__(TL::NT) void core_kernel(int nmu, int nv, int nc, c
         const int row = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, v);
         const int col = n0 + wn0 + fn * 8 + (rc >> 1);
         if (row >= nmu || col >= nmu) continue;
-        const T val = acc[fm][fn][v];
+        const T val = (row == col && pp == 1) ? (T)0 : acc[fm][fn][v];  // Hermitian: real diagonal
         if (bm == bn && row < col) continue;
         out[((long)row * nmu + col) * 2 + pp] = val;
         if (row > col) out[((long)col * nmu + row) * 2 + pp] = pp ? -val : val;
