@@ -148,7 +148,9 @@ def main():
                                "fp64": round(total_flops / (results["fp64"]["ms_per_step"] * 1e-3) / 1e12, 2)},
         "stage_ms": {"mixed": [round(x, 4) for x in m["stage_ms"]],
                      "fp64": [round(x, 4) for x in results["fp64"]["stage_ms"]],
-                     "names": ["gather+S^-1", "Z", "DFT", "U+G", "core M", "FP64 core", "U T", "output"]},
+                     "names": ["gather", "Z", "DFT", "U+G (waits S^-1)", "FP64 core solve (waits M^-1)",
+                               "U T", "output", "-"],
+                     "note": "intervals on the caller's stream; S^-1, M and M^-1 overlap on a side stream"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -79,14 +79,17 @@ typedef struct {
   double pair_factor;    /* f in chi0 = f M W M^H; the paper's value is 2 */
   double v_scale;        /* Coulomb prefactor; Nr / cell volume for unit-norm grid orbitals */
   int32_t prec;          /* isdf_precision */
-  int32_t refine_steps;  /* FP64 iterative-refinement steps on the core solve, 0..8 */
+  int32_t refine_steps;  /* FP64 Newton refinement steps T <- T + T (I - H T) on the core inverse, 0..8 */
 } isdf_problem;
 
 typedef struct {
-  double stage_ms[8];        /* filled when want_timing != 0: gather+S^{-1}, Z, DFT, U, core M,
-                                FP64 core algebra, U T, output */
-  double refine_residual[9]; /* ||L^H - A X_k||_F / ||L^H||_F for k = 0..refine_steps (last frequency) */
-  double min_pivot;          /* smallest Cholesky / pivot-block diagonal seen (last frequency) */
+  double stage_ms[8];        /* filled when want_timing != 0, intervals on the caller's stream:
+                                gather, Z, DFT, U and U^H U (incl. waiting for S^{-1}),
+                                FP64 core solve (incl. waiting for M^{-1}), U T, output, unused.
+                                S^{-1}, M and M^{-1} run concurrently on a library-owned stream. */
+  double refine_residual[9]; /* ||I - H T_k||_F / sqrt(N_mu) for k = 0..refine_steps (last frequency),
+                                H = U^H U - M^{-1}, T_k the k-th Newton-refined H^{-1} */
+  double min_pivot;          /* smallest diagonal entry of H (last frequency) */
   int32_t want_timing;       /* input: 1 to record per-stage HIP events (adds host syncs) */
   int32_t n_refine_reported; /* number of valid refine_residual entries */
 } isdf_report;

@@ -14,9 +14,8 @@
 //          applied after the transform, F (Z S^{-1}) = (F Z) S^{-1})
 //   G    = U^H U                                              (Theta^H V Theta)
 //   per frequency:
-//     -M = f C W C^H negated, L = chol(-M)                    (core, potrf)
-//     A  = I + L^H G L,  X = A^{-1} L^H (+ FP64 refinement)   (sweep, GEMMs)
-//     T  = L X            (so the SMW kernel (M^{-1} - G)^{-1} = -T)
+//     M  = f C W C^H                                          (core)
+//     T  = (G - M^{-1})^{-1}, two FP64 Hermitian sweeps       (so (M^{-1} - G)^{-1} = -T)
 //     eps~^{-1} = I - (U T) U^H                               (Hermitian output GEMM)
 #include <algorithm>
 #include <cmath>
@@ -34,10 +33,13 @@ using namespace isdf;
 
 struct isdf_handle_s {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // caller's stream (main branch)
+  hipStream_t side = nullptr;     // library-owned stream for the independent branch, default priority
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
-  hipEvent_t ev[10] = {};
+  hipEvent_t ev[10] = {};         // stage timing (main stream)
+  hipEvent_t fork = nullptr, s_ready = nullptr, join = nullptr;
+  hipEvent_t m_ready[2] = {}, m_used[2] = {};
   std::string err;
 };
 
@@ -73,32 +75,31 @@ struct DftIndex {
 
 DftIndex dft_index(const int32_t* miller, int ng) {
   DftIndex ix;
-  std::set<int> xs, ys, zs;
-  std::set<std::pair<int, int>> ds;
+  auto uniq = [](std::vector<int> v) { std::sort(v.begin(), v.end()); v.erase(std::unique(v.begin(), v.end()), v.end()); return v; };
+  std::vector<int> xs(ng), ys(ng), zs(ng);
+  std::vector<long> ds(ng);
+  auto pairkey = [](int x, int y) { return (long)(x + 1024) * 4096 + (y + 1024); };
   for (int g = 0; g < ng; ++g) {
-    xs.insert(miller[3 * g]);
-    ys.insert(miller[3 * g + 1]);
-    zs.insert(miller[3 * g + 2]);
-    ds.insert({miller[3 * g], miller[3 * g + 1]});
+    xs[g] = miller[3 * g];
+    ys[g] = miller[3 * g + 1];
+    zs[g] = miller[3 * g + 2];
+    ds[g] = pairkey(xs[g], ys[g]);
   }
-  ix.xl.assign(xs.begin(), xs.end());
-  ix.yl.assign(ys.begin(), ys.end());
-  ix.zl.assign(zs.begin(), zs.end());
-  std::map<int, int> xi, yi, zi;
-  for (size_t i = 0; i < ix.xl.size(); ++i) xi[ix.xl[i]] = (int)i;
-  for (size_t i = 0; i < ix.yl.size(); ++i) yi[ix.yl[i]] = (int)i;
-  for (size_t i = 0; i < ix.zl.size(); ++i) zi[ix.zl[i]] = (int)i;
-  std::map<std::pair<int, int>, int> di;
-  for (const auto& p : ds) {
-    di[p] = (int)ix.d_ax.size();
-    ix.d_ax.push_back(xi[p.first]);
-    ix.d_by.push_back(yi[p.second]);
+  ix.xl = uniq(xs);
+  ix.yl = uniq(ys);
+  ix.zl = uniq(zs);
+  std::sort(ds.begin(), ds.end());
+  ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
+  auto pos = [](const std::vector<int>& v, int x) { return (int)(std::lower_bound(v.begin(), v.end(), x) - v.begin()); };
+  for (long k : ds) {
+    ix.d_ax.push_back(pos(ix.xl, (int)(k / 4096) - 1024));
+    ix.d_by.push_back(pos(ix.yl, (int)(k % 4096) - 1024));
   }
   ix.g_d.resize(ng);
   ix.g_cz.resize(ng);
   for (int g = 0; g < ng; ++g) {
-    ix.g_d[g] = di[{miller[3 * g], miller[3 * g + 1]}];
-    ix.g_cz[g] = zi[miller[3 * g + 2]];
+    ix.g_d[g] = (int)(std::lower_bound(ds.begin(), ds.end(), pairkey(xs[g], ys[g])) - ds.begin());
+    ix.g_cz[g] = pos(ix.zl, zs[g]);
   }
   return ix;
 }
@@ -109,7 +110,9 @@ struct Layout {
          u = 0, l = 0, g = 0, gl = 0, a = 0, acopy = 0, lh = 0, x = 0, rres = 0, t = 0, status = 0,
          miller = 0, recip = 0, sqrtv = 0, idx = 0, total = 0;
   size_t twx = 0, twy = 0, twz = 0;  // inside tabs
-  size_t part = 0, w1 = 0;           // alias into the zt region
+  size_t w1 = 0;                     // aliases the zt region
+  size_t zt_bytes = 0;               // size of the zt region
+  size_t part = 0, l2 = 0, lin2 = 0; // core partial sums; second -M buffer and sweep scratch
   int kx = 0, ky = 0, kz = 0, nd = 0, nsplit = 1;
 };
 
@@ -124,13 +127,14 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.status = take(sizeof(StatusBlock));
   L.psi_c = P.cplx ? 0 : take((size_t)P.ns * P.nr * z);
   L.pm = take((size_t)P.ns * P.nmu * z);
+  // host-supplied arrays, adjacent so that one copy uploads them all
   L.mu = take((size_t)P.nmu * 4);
   L.e = take((size_t)P.ns * 8);
-  L.w = take((size_t)P.nv * P.nc * 8);
   L.miller = take((size_t)P.ng * 3 * 4);
   L.recip = take(9 * 8);
-  L.sqrtv = take((size_t)P.ng * 8);
   L.idx = take((size_t)(kx + ky + kz + 2 * nd + 2 * P.ng) * 4);
+  L.w = take((size_t)P.nv * P.nc * 8);
+  L.sqrtv = take((size_t)P.ng * 8);
   L.twx = take((size_t)kx * P.n0 * el);
   L.twy = take((size_t)ky * P.n1 * el);
   L.twz = take((size_t)kz * P.n2 * el);
@@ -141,6 +145,9 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.zg = take((size_t)P.nmu * P.ng * el);
   L.u = take((size_t)P.ng * P.nmu * el);
   L.l = take(nmu2 * z);
+  L.l2 = take(nmu2 * z);
+  L.lin2 = take(linalg_scratch_bytes(P.nmu));
+  L.part = take((size_t)L.nsplit * nmu2 * el);
   L.g = take(nmu2 * z);
   L.gl = take(nmu2 * z);
   L.a = take(nmu2 * z);
@@ -150,11 +157,12 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.rres = take(nmu2 * z);
   L.t = take(nmu2 * z);
   // big region: Zt (N_mu x Nr), later reused for the core partial sums and U T
+  // big region: Zt (N_mu x Nr); once the DFT has consumed it, reused for the
+  // split-K partial sums of U^H U and for U T
   const size_t zt_bytes = (size_t)P.nmu * P.nr * el;
-  const size_t part_bytes = (size_t)L.nsplit * nmu2 * el;
   const size_t w1_bytes = (size_t)P.ng * P.nmu * el;
-  L.zt = take(std::max(zt_bytes, std::max(part_bytes, w1_bytes)));
-  L.part = L.zt;
+  L.zt_bytes = std::max(zt_bytes, w1_bytes);
+  L.zt = take(L.zt_bytes);
   L.w1 = L.zt;
   L.total = off;
   return L;
@@ -235,7 +243,7 @@ isdf_status check_miller(isdf_handle h, const Problem& P, const int32_t* m, int 
   if (!m) return fail(h, ISDF_E_ARG, "miller is NULL");
   if (ng < 1 || (long)ng > P.nr) return fail(h, ISDF_E_ARG, "ng must be in [1, Nr]");
   const int n[3] = {P.n0, P.n1, P.n2};
-  std::set<long> seen;
+  std::vector<long> keys(ng);
   for (int g = 0; g < ng; ++g) {
     long key = 0;
     for (int d = 0; d < 3; ++d) {
@@ -243,8 +251,11 @@ isdf_status check_miller(isdf_handle h, const Problem& P, const int32_t* m, int 
       if (v < -(n[d] / 2) || v >= n[d] - n[d] / 2) return fail(h, ISDF_E_ARG, "miller index out of [-n/2, n/2)");
       key = key * 2048 + (v + 1024);
     }
-    if (!seen.insert(key).second) return fail(h, ISDF_E_ARG, "miller list has duplicates");
+    keys[g] = key;
   }
+  std::sort(keys.begin(), keys.end());
+  for (int g = 1; g < ng; ++g)
+    if (keys[g] == keys[g - 1]) return fail(h, ISDF_E_ARG, "miller list has duplicates");
   return ISDF_OK;
 }
 
@@ -255,16 +266,21 @@ isdf_status check_ws(isdf_handle h, void* ws, size_t have, size_t need) {
   return ISDF_OK;
 }
 
-// Stage host arrays through the handle's pinned buffer into device memory.
+// Stage host arrays through the handle's pinned buffer into device memory with a
+// single copy: the destinations are workspace regions, packed into the pinned
+// buffer at their workspace offsets relative to the first one.
 struct Uploader {
   isdf_handle h;
-  std::vector<std::pair<const void*, size_t>> src;
-  std::vector<void*> dst;
-  void add(void* d, const void* s, size_t bytes) { if (bytes) { src.push_back({s, bytes}); dst.push_back(d); } }
+  void* ws = nullptr;
+  struct Item { size_t off; const void* src; size_t bytes; };
+  std::vector<Item> items;
+  void add(size_t off, const void* s, size_t bytes) { if (bytes) items.push_back({off, s, bytes}); }
   isdf_status run() {
-    size_t total = 0;
-    for (auto& s : src) total += up(s.second);
-    // the previous call's copies out of the pinned buffer must be complete
+    if (items.empty()) return ISDF_OK;
+    size_t lo = items[0].off, hi = 0;
+    for (auto& it : items) { lo = std::min(lo, it.off); hi = std::max(hi, it.off + it.bytes); }
+    const size_t total = hi - lo;
+    // the previous call's copy out of the pinned buffer must be complete
     HIPCHK(hipStreamSynchronize(h->stream));
     if (total > h->pinned_bytes) {
       if (h->pinned) HIPCHK(hipHostFree(h->pinned));
@@ -273,13 +289,9 @@ struct Uploader {
       HIPCHK(hipHostMalloc(&h->pinned, total, hipHostMallocDefault));
       h->pinned_bytes = total;
     }
-    size_t off = 0;
-    for (size_t i = 0; i < src.size(); ++i) {
-      char* p = reinterpret_cast<char*>(h->pinned) + off;
-      std::memcpy(p, src[i].first, src[i].second);
-      HIPCHK(hipMemcpyAsync(dst[i], p, src[i].second, hipMemcpyHostToDevice, h->stream));
-      off += up(src[i].second);
-    }
+    char* base = reinterpret_cast<char*>(h->pinned);
+    for (auto& it : items) std::memcpy(base + (it.off - lo), it.src, it.bytes);
+    HIPCHK(hipMemcpyAsync(reinterpret_cast<char*>(ws) + lo, base, total, hipMemcpyHostToDevice, h->stream));
     return ISDF_OK;
   }
 };
@@ -299,6 +311,8 @@ struct Run {
   void* ws;
   const void* psi;      // complex128 view of the orbitals (device)
   StatusBlock* sb;
+  const void* tmat = nullptr;  // T (times talpha) after the core algebra
+  double talpha = 1.0;
   hipStream_t st;
 };
 
@@ -314,14 +328,21 @@ isdf_status prepare_psi(Run& R, const void* psi) {
   return ISDF_OK;
 }
 
-isdf_status stage_points_and_s(Run& R) {
+isdf_status stage_points(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  HIPCHK(gather_points(R.psi, P.nr, P.ns, at<int>(R.ws, R.L.mu), P.nmu, at<char>(R.ws, R.L.pm), R.st));
+  return ISDF_OK;
+}
+
+// S^T at the points (FP64) and Sw = -(S^T)^{-1}, on stream st with sweep scratch lin
+isdf_status stage_s(Run& R, hipStream_t st, size_t lin) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   void* pm = at<char>(R.ws, R.L.pm);
-  HIPCHK(gather_points(R.psi, P.nr, P.ns, at<int>(R.ws, R.L.mu), P.nmu, pm, R.st));
   void* s = at<char>(R.ws, R.L.s);
-  HIPCHK(zpair(P64, P.nmu, P.nmu, P.nv, P.ns, pm, P.nmu, pm, P.nmu, s, P.nmu, false, R.st));
-  HIPCHK(sweep_inverse(P.nmu, s, at<char>(R.ws, R.L.lin), &R.sb->status, R.st));
+  HIPCHK(zpair(P64, P.nmu, P.nmu, P.nv, P.ns, pm, P.nmu, pm, P.nmu, s, P.nmu, false, st));
+  HIPCHK(sweep_inverse(P.nmu, s, at<char>(R.ws, lin), &R.sb->status, st));
   return ISDF_OK;
 }
 
@@ -395,86 +416,69 @@ isdf_status stage_gram(Run& R) {
   d.B = at<char>(R.ws, R.L.u); d.sbk = P.nmu; d.sbn = 1; d.b32 = P.m32;
   d.C = at<char>(R.ws, R.L.g); d.ldc = P.nmu;
   d.herm = true;
+  d.split_ws = at<char>(R.ws, R.L.zt);    // Z^T region, free once the DFT has run
+  d.split_ws_bytes = R.L.zt_bytes;
   HIPCHK(gemm(cp, d, R.st));
   return ISDF_OK;
 }
 
-isdf_status stage_core(Run& R, double omega, void* m_out) {
+// core M at one frequency: written to m_out (if given) and/or -M to negm
+isdf_status stage_core(Run& R, double omega, void* m_out, void* negm, hipStream_t st) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Prec cp = P.prec == P64 ? P64 : P32;
   double* w = at<double>(R.ws, R.L.w);
-  HIPCHK(pair_weights(at<double>(R.ws, R.L.e), P.nv, P.nc, omega, w, R.st));
+  HIPCHK(pair_weights(at<double>(R.ws, R.L.e), P.nv, P.nc, omega, w, st));
   void* part = at<char>(R.ws, R.L.part);
-  HIPCHK(core_partial(cp, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), P.nmu, w, part, R.L.nsplit, R.st));
-  HIPCHK(core_reduce(cp, P.nmu, part, R.L.nsplit, P.f, m_out, m_out ? nullptr : at<char>(R.ws, R.L.l), R.st));
+  HIPCHK(core_partial(cp, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), P.nmu, w, part, R.L.nsplit, st));
+  HIPCHK(core_reduce(cp, P.nmu, part, R.L.nsplit, P.f, m_out, negm, st));
   return ISDF_OK;
 }
 
-// from -M in L-buffer and G: T = L (I + L^H G L)^{-1} L^H
-isdf_status stage_core_algebra(Run& R) {
+// SMW core from -M (in the L buffer) and G = U^H U, all FP64:
+//   M^{-1} = sweep(-M),  H = G - M^{-1} (Hermitian positive definite),
+//   T = H^{-1} = -sweep(H)  (so the SMW kernel (M^{-1} - G)^{-1} = -T),
+//   optional Newton refinement T <- T + T (I - H T) with residuals ||I - H T||_F / sqrt(n).
+// Mi holds M^{-1} (the sweep of -M); `used` (optional) is recorded once Mi has been read.
+isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Layout& L = R.L;
   const int n = P.nmu;
   const long n2 = (long)n * n;
-  void* Lb = at<char>(R.ws, L.l);
-  HIPCHK(potrf(n, Lb, nullptr, &R.sb->status, R.st));
-  HIPCHK(diag_min(Lb, n, &R.sb->min_pivot, R.st));
-  GemmDesc d;
-  d.M = d.N = d.K = n;
-  d.A = at<char>(R.ws, L.g); d.sam = n; d.sak = 1;
-  d.B = Lb; d.sbk = n; d.sbn = 1;
-  d.C = at<char>(R.ws, L.gl); d.ldc = n;
-  HIPCHK(gemm(P64, d, R.st));                       // GL = G L
-  GemmDesc e;
-  e.M = e.N = e.K = n;
-  e.A = Lb; e.sam = 1; e.sak = n; e.conjA = true;  // L^H
-  e.B = at<char>(R.ws, L.gl); e.sbk = n; e.sbn = 1;
-  e.C = at<char>(R.ws, L.a); e.ldc = n; e.diag_add = 1.0;
-  HIPCHK(gemm(P64, e, R.st));                       // A = I + L^H G L
-  if (P.refine > 0) HIPCHK(convert_z(at<char>(R.ws, L.a), false, at<char>(R.ws, L.acopy), false, n2, R.st));
-  HIPCHK(sweep_inverse(n, at<char>(R.ws, L.a), at<char>(R.ws, L.lin), &R.sb->status, R.st));  // Aw = -A^{-1}
-  HIPCHK(conj_transpose(n, Lb, at<char>(R.ws, L.lh), R.st));
-  GemmDesc x;
-  x.M = x.N = x.K = n;
-  x.A = at<char>(R.ws, L.a); x.sam = n; x.sak = 1;
-  x.B = at<char>(R.ws, L.lh); x.sbk = n; x.sbn = 1;
-  x.C = at<char>(R.ws, L.x); x.ldc = n; x.alpha = -1.0;
-  HIPCHK(gemm(P64, x, R.st));                       // X = A^{-1} L^H
-  if (P.refine > 0) HIPCHK(frob2(at<char>(R.ws, L.lh), n2, R.sb->partial, &R.sb->lh2, R.st));
-  for (int k = 0; k < P.refine; ++k) {
-    HIPCHK(convert_z(at<char>(R.ws, L.lh), false, at<char>(R.ws, L.rres), false, n2, R.st));
-    GemmDesc r;
+  void* H = at<char>(R.ws, L.a);
+  HIPCHK(axpby(at<char>(R.ws, L.g), 1.0, Mi, -1.0, H, n2, R.st));                   // H = G - M^{-1}
+  if (used) HIPCHK(hipEventRecord(used, R.st));
+  HIPCHK(diag_min(H, n, &R.sb->min_pivot, R.st));
+  if (P.refine > 0) HIPCHK(convert_z(H, false, at<char>(R.ws, L.acopy), false, n2, R.st));
+  HIPCHK(sweep_inverse(n, H, at<char>(R.ws, L.lin), &R.sb->status, R.st));          // -T
+  R.tmat = H;
+  R.talpha = -1.0;
+  if (P.refine == 0) return ISDF_OK;
+  void* T = at<char>(R.ws, L.t);
+  void* T2 = at<char>(R.ws, L.x);
+  void* Rr = at<char>(R.ws, L.rres);
+  HIPCHK(scale_z(H, T, n2, -1.0, R.st));
+  for (int k = 0; k <= P.refine; ++k) {
+    GemmDesc r;  // Rr = I - H T
     r.M = r.N = r.K = n;
     r.A = at<char>(R.ws, L.acopy); r.sam = n; r.sak = 1;
-    r.B = at<char>(R.ws, L.x); r.sbk = n; r.sbn = 1;
-    r.C = at<char>(R.ws, L.rres); r.ldc = n; r.alpha = -1.0; r.beta = 1.0;
-    HIPCHK(gemm(P64, r, R.st));                     // Rres = L^H - A X
-    HIPCHK(frob2(at<char>(R.ws, L.rres), n2, R.sb->partial, &R.sb->res[k], R.st));
-    GemmDesc c;
-    c.M = c.N = c.K = n;
-    c.A = at<char>(R.ws, L.a); c.sam = n; c.sak = 1;
-    c.B = at<char>(R.ws, L.rres); c.sbk = n; c.sbn = 1;
-    c.C = at<char>(R.ws, L.x); c.ldc = n; c.alpha = -1.0; c.beta = 1.0;
-    HIPCHK(gemm(P64, c, R.st));                     // X += A^{-1} Rres
-  }
-  if (P.refine > 0) {  // residual after the last correction
-    HIPCHK(convert_z(at<char>(R.ws, L.lh), false, at<char>(R.ws, L.rres), false, n2, R.st));
-    GemmDesc r;
-    r.M = r.N = r.K = n;
-    r.A = at<char>(R.ws, L.acopy); r.sam = n; r.sak = 1;
-    r.B = at<char>(R.ws, L.x); r.sbk = n; r.sbn = 1;
-    r.C = at<char>(R.ws, L.rres); r.ldc = n; r.alpha = -1.0; r.beta = 1.0;
+    r.B = T; r.sbk = n; r.sbn = 1;
+    r.C = Rr; r.ldc = n; r.alpha = -1.0; r.diag_add = 1.0;
     HIPCHK(gemm(P64, r, R.st));
-    HIPCHK(frob2(at<char>(R.ws, L.rres), n2, R.sb->partial, &R.sb->res[P.refine], R.st));
+    HIPCHK(frob2(Rr, n2, R.sb->partial, &R.sb->res[k], R.st));
+    if (k == P.refine) break;
+    HIPCHK(convert_z(T, false, T2, false, n2, R.st));
+    GemmDesc c;  // T2 = T + T Rr
+    c.M = c.N = c.K = n;
+    c.A = T; c.sam = n; c.sak = 1;
+    c.B = Rr; c.sbk = n; c.sbn = 1;
+    c.C = T2; c.ldc = n; c.beta = 1.0;
+    HIPCHK(gemm(P64, c, R.st));
+    std::swap(T, T2);
   }
-  GemmDesc t;
-  t.M = t.N = t.K = n;
-  t.A = Lb; t.sam = n; t.sak = 1;
-  t.B = at<char>(R.ws, L.x); t.sbk = n; t.sbn = 1;
-  t.C = at<char>(R.ws, L.t); t.ldc = n;
-  HIPCHK(gemm(P64, t, R.st));                       // T = L X
+  R.tmat = T;
+  R.talpha = 1.0;
   return ISDF_OK;
 }
 
@@ -486,8 +490,9 @@ isdf_status stage_out(Run& R, void* out, Timer& tm) {
   GemmDesc d;  // W1 = U T
   d.M = P.ng; d.N = P.nmu; d.K = P.nmu;
   d.A = at<char>(R.ws, L.u); d.sam = P.nmu; d.sak = 1; d.a32 = P.m32;
-  d.B = at<char>(R.ws, L.t); d.sbk = P.nmu; d.sbn = 1;
+  d.B = R.tmat; d.sbk = P.nmu; d.sbn = 1;
   d.C = at<char>(R.ws, L.w1); d.ldc = P.nmu; d.c32 = P.m32;
+  d.alpha = R.talpha;
   HIPCHK(gemm(cp, d, R.st));
   tm.mark();
   GemmDesc o;  // eps~^{-1} = I - W1 U^H
@@ -507,8 +512,6 @@ isdf_status begin(isdf_handle h, const isdf_problem* prob, Problem& P, int nmu, 
   P.ng = ng;
   P.nomega = nomega;
   if (P.prec == PBF3) return fail(h, ISDF_E_UNSUPPORTED, "BF16x3 precision is not available in this build");
-  if (!dft_supported(P.n0, P.n1, P.prec == P64 ? P64 : P32))
-    return fail(h, ISDF_E_UNSUPPORTED, "grid plane n0*n1 too large for the LDS-resident DFT slab");
   return ISDF_OK;
 }
 
@@ -521,7 +524,7 @@ isdf_status finish(Run& R, isdf_report* rep, Timer& tm) {
     rep->min_pivot = hs.min_pivot;
     rep->n_refine_reported = R.P.refine > 0 ? R.P.refine + 1 : 0;
     for (int k = 0; k < 9; ++k)
-      rep->refine_residual[k] = (k < rep->n_refine_reported && hs.lh2 > 0) ? std::sqrt(hs.res[k] / hs.lh2) : 0.0;
+      rep->refine_residual[k] = k < rep->n_refine_reported ? std::sqrt(hs.res[k] / (double)R.P.nmu) : 0.0;
     if (tm.on) {
       for (int k = 0; k < 8; ++k) rep->stage_ms[k] = 0.0;
       for (int k = 0; k + 1 < tm.k && k < 8; ++k) {
@@ -550,6 +553,8 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
     s = check_miller(h, R.P, miller, ng);
     if (s != ISDF_OK) return s;
     ix = dft_index(miller, ng);
+    if (!dft_supported(R.P.n0, R.P.n1, (int)ix.xl.size(), (int)ix.yl.size(), R.P.prec == P64 ? P64 : P32))
+      return fail(h, ISDF_E_UNSUPPORTED, "grid plane too large for the LDS-resident DFT slab");
   } else {
     ix.xl = ix.yl = ix.zl = {0};
     ix.d_ax = ix.d_by = {0};
@@ -566,15 +571,16 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
   R.st = h->stream;
   R.sb = at<StatusBlock>(ws, R.L.status);
   up_.h = h;
-  up_.add(at<char>(ws, R.L.mu), mu_idx, (size_t)n_mu * 4);
-  if (energies) up_.add(at<char>(ws, R.L.e), energies, (size_t)R.P.ns * 8);
+  up_.ws = ws;
+  up_.add(R.L.mu, mu_idx, (size_t)n_mu * 4);
+  if (energies) up_.add(R.L.e, energies, (size_t)R.P.ns * 8);
   if (miller) {
-    up_.add(at<char>(ws, R.L.miller), miller, (size_t)ng * 12);
+    up_.add(R.L.miller, miller, (size_t)ng * 12);
     idxbuf.clear();
     for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz})
       idxbuf.insert(idxbuf.end(), v->begin(), v->end());
-    up_.add(at<char>(ws, R.L.idx), idxbuf.data(), idxbuf.size() * 4);
-    up_.add(at<char>(ws, R.L.recip), R.P.recip, 9 * 8);
+    up_.add(R.L.idx, idxbuf.data(), idxbuf.size() * 4);
+    up_.add(R.L.recip, R.P.recip, 9 * 8);
   }
   return ISDF_OK;
 }
@@ -604,6 +610,10 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
   if (hipSetDevice(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
+  for (hipEvent_t* e : {&h->fork, &h->s_ready, &h->join, &h->m_ready[0], &h->m_ready[1], &h->m_used[0], &h->m_used[1]})
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
+  // default priority, non-blocking with respect to the legacy default stream
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   h->pinned_bytes = 1 << 20;
   if (hipHostMalloc(&h->pinned, h->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
     delete h;
@@ -616,7 +626,13 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
 isdf_status isdf_destroy(isdf_handle h) {
   if (!h) return ISDF_OK;
   (void)hipStreamSynchronize(h->stream);
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
   for (auto& e : h->ev) if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {h->fork, h->s_ready, h->join, h->m_ready[0], h->m_ready[1], h->m_used[0], h->m_used[1]})
+    if (e) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return ISDF_OK;
@@ -719,28 +735,49 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
   Timer tm{h, rep && rep->want_timing != 0};
   tm.mark();
   TRY(prepare_psi(R, psi));
-  TRY(stage_points_and_s(R));
+  TRY(stage_points(R));
+  // Fork: the side stream computes S^{-1} and, per frequency, M and M^{-1}
+  // (double-buffered), while this stream runs Z, the DFT, U and G.  Work is
+  // enqueued frequency by frequency so that every stream wait is enqueued after
+  // the event record it waits for.
+  hipStream_t side = h->side;
+  HIPCHK(hipEventRecord(h->fork, R.st));
+  HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
+  const int nw = std::max(n_omega, 1);
+  void* mbuf[2] = {at<char>(workspace, R.L.l), at<char>(workspace, R.L.l2)};
+  auto side_core = [&](int k) -> isdf_status {
+    if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
+    TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
+    HIPCHK(sweep_inverse(R.P.nmu, mbuf[k & 1], at<char>(workspace, R.L.lin2), &R.sb->status, side));  // M^{-1}
+    HIPCHK(hipEventRecord(h->m_ready[k & 1], side));
+    return ISDF_OK;
+  };
+  TRY(stage_s(R, side, R.L.lin2));
+  HIPCHK(hipEventRecord(h->s_ready, side));
+  TRY(side_core(0));
+  if (nw > 1) TRY(side_core(1));
   tm.mark();
   TRY(stage_z(R));
   tm.mark();
   TRY(stage_dft(R));
   tm.mark();
+  HIPCHK(hipStreamWaitEvent(R.st, h->s_ready, 0));
   TRY(stage_u(R));
   TRY(stage_gram(R));
   tm.mark();
-  const int nw = std::max(n_omega, 1);
   for (int k = 0; k < nw; ++k) {
-    const double om = n_omega ? omega[k] : 0.0;
     Timer dummy{h, false};
     Timer& t = (k == nw - 1) ? tm : dummy;
-    TRY(stage_core(R, om, nullptr));
-    t.mark();
-    TRY(stage_core_algebra(R));
+    HIPCHK(hipStreamWaitEvent(R.st, h->m_ready[k & 1], 0));
+    TRY(stage_core_algebra(R, mbuf[k & 1], h->m_used[k & 1]));
+    if (k + 2 < nw) TRY(side_core(k + 2));
     t.mark();
     void* out = reinterpret_cast<char*>(eps_inv) + (size_t)k * ng * ng * 16;
     TRY(stage_out(R, out, t));
     t.mark();
   }
+  HIPCHK(hipEventRecord(h->join, side));
+  HIPCHK(hipStreamWaitEvent(R.st, h->join, 0));
   return finish(R, rep, tm);
 }
 
@@ -757,7 +794,8 @@ isdf_status isdf_fit_theta(isdf_handle h, const isdf_problem* prob, const void* 
   TRY(upl.run());
   TRY(clear_status(R));
   TRY(prepare_psi(R, psi));
-  TRY(stage_points_and_s(R));
+  TRY(stage_points(R));
+  TRY(stage_s(R, R.st, R.L.lin));
   TRY(stage_z(R));
   const Problem& P = R.P;
   // Theta^T(nu, r) = sum_mu S^{-1}(mu, nu) Zt(mu, r), S^{-1}(mu, nu) = -Sw[nu][mu]
@@ -788,7 +826,7 @@ isdf_status isdf_core_m(isdf_handle h, const isdf_problem* prob, const void* psi
   TRY(clear_status(R));
   TRY(prepare_psi(R, psi));
   HIPCHK(gather_points(R.psi, R.P.nr, R.P.ns, at<int>(workspace, R.L.mu), R.P.nmu, at<char>(workspace, R.L.pm), R.st));
-  TRY(stage_core(R, omega, m_out));
+  TRY(stage_core(R, omega, m_out, nullptr, R.st));
   Timer tm{h, false};
   return finish(R, nullptr, tm);
 }
@@ -808,7 +846,8 @@ isdf_status isdf_coulomb_u(isdf_handle h, const isdf_problem* prob, const void* 
   TRY(upl.run());
   TRY(clear_status(R));
   TRY(prepare_psi(R, psi));
-  TRY(stage_points_and_s(R));
+  TRY(stage_points(R));
+  TRY(stage_s(R, R.st, R.L.lin));
   TRY(stage_z(R));
   TRY(stage_dft(R));
   TRY(stage_u(R));
@@ -835,13 +874,12 @@ isdf_status isdf_smw_apply(isdf_handle h, const isdf_problem* prob, const void* 
   tm.mark();
   HIPCHK(convert_z(u, false, at<char>(workspace, R.L.u), R.P.m32, (long)ng * n_mu, R.st));
   HIPCHK(scale_z(m, at<char>(workspace, R.L.l), (long)n_mu * n_mu, -1.0, R.st));  // -M
-  tm.mark();
+  HIPCHK(sweep_inverse(n_mu, at<char>(workspace, R.L.l), at<char>(workspace, R.L.lin), &R.sb->status, R.st));
   tm.mark();
   tm.mark();
   TRY(stage_gram(R));
   tm.mark();
-  tm.mark();
-  TRY(stage_core_algebra(R));
+  TRY(stage_core_algebra(R, at<char>(workspace, R.L.l), nullptr));
   tm.mark();
   TRY(stage_out(R, eps_inv, tm));
   tm.mark();

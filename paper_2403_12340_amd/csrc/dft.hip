@@ -95,48 +95,65 @@ hipError_t dft_twiddles(const int* mlist, int nm, int n, bool f32, void* tw, hip
   return hipGetLastError();
 }
 
+// LDS rows are padded to an odd number of complex elements so that lanes
+// reading different rows hit different banks.
+__host__ __device__ inline int odd_pad(int n) { return n | 1; }
+
 template <typename T>
 static size_t xy_lds_bytes(const DftPlan& p) {
-  return sizeof(cx<T>) * ((size_t)p.n0 * p.n1 + (size_t)p.n1 * p.kx + (size_t)p.kx * p.n0 +
-                          (size_t)p.ky * p.n1);
+  const size_t s0 = odd_pad(p.n0 + 1) , s1 = odd_pad(p.n1 + 1), sk = odd_pad(p.kx);
+  return sizeof(cx<T>) * ((size_t)p.n1 * s0 + (size_t)p.kx * s0 + (size_t)p.n1 * sk + (size_t)p.ky * s1);
 }
 
 // one workgroup per (z-plane, point)
 template <typename T>
 __global__ __launch_bounds__(256) void dft_xy_kernel(DftPlan p, const cx<T>* zt, cx<T>* t2) {
   extern __shared__ unsigned char lds_raw[];
-  cx<T>* S = reinterpret_cast<cx<T>*>(lds_raw);          // [n1][n0]
-  cx<T>* T1 = S + p.n0 * p.n1;                           // [n1][kx]
-  cx<T>* TX = T1 + p.n1 * p.kx;                          // [kx][n0]
-  cx<T>* TY = TX + p.kx * p.n0;                          // [ky][n1]
+  const int s0 = odd_pad(p.n0 + 1), s1 = odd_pad(p.n1 + 1), sk = odd_pad(p.kx);
+  cx<T>* S = reinterpret_cast<cx<T>*>(lds_raw);          // [n1][s0]   slab Z[z][y][x]
+  cx<T>* TX = S + p.n1 * s0;                             // [kx][s0]   x twiddles
+  cx<T>* T1 = TX + p.kx * s0;                            // [n1][sk]   after the x stage
+  cx<T>* TY = T1 + p.n1 * sk;                            // [ky][s1]   y twiddles
   const int z = blockIdx.x, mu = blockIdx.y;
   const int tid = threadIdx.x;
   const long slab = ((long)mu * p.n2 + z) * p.n1 * p.n0;
   const cx<T>* twx = reinterpret_cast<const cx<T>*>(p.twx);
   const cx<T>* twy = reinterpret_cast<const cx<T>*>(p.twy);
-  for (int i = tid; i < p.n0 * p.n1; i += 256) S[i] = zt[slab + i];
-  for (int i = tid; i < p.kx * p.n0; i += 256) TX[i] = twx[i];
-  for (int i = tid; i < p.ky * p.n1; i += 256) TY[i] = twy[i];
+  for (int i = tid; i < p.n0 * p.n1; i += 256) S[(i / p.n0) * s0 + i % p.n0] = zt[slab + i];
+  for (int i = tid; i < p.kx * p.n0; i += 256) TX[(i / p.n0) * s0 + i % p.n0] = twx[i];
+  for (int i = tid; i < p.ky * p.n1; i += 256) TY[(i / p.n1) * s1 + i % p.n1] = twy[i];
   __syncthreads();
-  for (int i = tid; i < p.n1 * p.kx; i += 256) {
-    const int y = i / p.kx, a = i % p.kx;
-    const cx<T>* row = S + y * p.n0;
-    const cx<T>* tw = TX + a * p.n0;
-    T sr = 0, si = 0;
+  // x stage: each thread produces 4 rows y0..y0+3 of one kept frequency a
+  const int ny4 = (p.n1 + 3) / 4;
+  for (int w = tid; w < ny4 * p.kx; w += 256) {
+    const int a = w % p.kx, y0 = (w / p.kx) * 4;
+    const int nr = min(4, p.n1 - y0);
+    T sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+    const cx<T>* tw = TX + a * s0;
     for (int x = 0; x < p.n0; ++x) {
-      sr += row[x].re * tw[x].re - row[x].im * tw[x].im;
-      si += row[x].re * tw[x].im + row[x].im * tw[x].re;
+      const cx<T> t = tw[x];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r < nr) {
+          const cx<T> v = S[(y0 + r) * s0 + x];
+          sr[r] += v.re * t.re - v.im * t.im;
+          si[r] += v.re * t.im + v.im * t.re;
+        }
+      }
     }
-    T1[i] = cx<T>{sr, si};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (r < nr) T1[(y0 + r) * sk + a] = cx<T>{sr[r], si[r]};
   }
   __syncthreads();
+  // y stage: only the (x, y) frequency pairs in use
   cx<T>* out = t2 + ((long)mu * p.n2 + z) * p.nd;
   for (int d = tid; d < p.nd; d += 256) {
     const int a = p.d_ax[d], b = p.d_by[d];
-    const cx<T>* tw = TY + b * p.n1;
+    const cx<T>* tw = TY + b * s1;
     T sr = 0, si = 0;
     for (int y = 0; y < p.n1; ++y) {
-      const cx<T> v = T1[y * p.kx + a];
+      const cx<T> v = T1[y * sk + a];
       sr += v.re * tw[y].re - v.im * tw[y].im;
       si += v.re * tw[y].im + v.im * tw[y].re;
     }
@@ -144,10 +161,11 @@ __global__ __launch_bounds__(256) void dft_xy_kernel(DftPlan p, const cx<T>* zt,
   }
 }
 
-bool dft_supported(int n0, int n1, Prec compute) {
-  const size_t elem = compute == P64 ? 16 : 8;
-  // worst case kx = n0, ky = n1
-  return elem * ((size_t)n0 * n1 * 2 + (size_t)n0 * n0 + (size_t)n1 * n1) <= 160 * 1024;
+bool dft_supported(int n0, int n1, int kx, int ky, Prec compute) {
+  DftPlan p{};
+  p.n0 = n0; p.n1 = n1; p.kx = kx; p.ky = ky;
+  const size_t bytes = compute == P64 ? xy_lds_bytes<double>(p) : xy_lds_bytes<float>(p);
+  return bytes <= 160 * 1024;
 }
 
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st) {

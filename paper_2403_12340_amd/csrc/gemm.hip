@@ -1,10 +1,11 @@
 // Generic complex GEMM on 16x16x4 MFMA (f64 or f32), LDS double-buffered.
 //   C = alpha * diag(row_scale) * op(A) op(B) + beta * C + diag_add * I
 // with an optional Hermitian mode (lower tiles only, upper written as the
-// conjugate mirror) and a sweep epilogue used by the in-place HPD inverse.
+// conjugate mirror).
 #include "internal.h"
 #include "tile.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace isdf {
@@ -17,11 +18,12 @@ struct GemmP {
   double alpha, beta, diag_add;
   const double* rs;
   int herm;
-  int k0, kn; const void* R; long ldr;
   int ntm, ntn, total;
+  int kchunk;   // split-K: split s covers k in [s * kchunk, (s + 1) * kchunk)
+  void* part;   // split-K partial sums [split][M][N] complex (compute type), or null
 };
 
-template <typename T, typename SA, typename SB, typename SC, class TL, bool AMC, bool BNC, bool SWEEP>
+template <typename T, typename SA, typename SB, typename SC, class TL, bool AMC, bool BNC>
 __global__ __launch_bounds__(TL::NT) void gemm_kernel(GemmP p) {
   __shared__ cx<T> smem[2 * (TL::AS + TL::BS)];
   int bm, bn;
@@ -53,29 +55,32 @@ __global__ __launch_bounds__(TL::NT) void gemm_kernel(GemmP p) {
   typename TL::acc_t acc[TL::FM][TL::FN];
   zero_acc<TL>(acc);
 
-  const int nk = (p.K + TL::BK - 1) / TL::BK;
-  sa.fetch(A, p.sam, p.sak, m0, 0, p.M, p.K, (T)p.ca, tid);
-  sb.fetch(B, p.sbn, p.sbk, n0, 0, p.N, p.K, (T)p.cb, tid);
-  sa.store(smem, TL::LDA, tid);
-  sb.store(smem + TL::AS, TL::LDB, tid);
+  const int kb = blockIdx.y * p.kchunk;
+  const int ke = min(p.K, kb + p.kchunk);
+  const int nk = ke > kb ? (ke - kb + TL::BK - 1) / TL::BK : 0;
+  sa.fetch(A, p.sam, p.sak, m0, kb, p.M, ke, tid);
+  sb.fetch(B, p.sbn, p.sbk, n0, kb, p.N, ke, tid);
+  sa.store(smem, TL::LDA, (T)p.ca, tid);
+  sb.store(smem + TL::AS, TL::LDB, (T)p.cb, tid);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      sa.fetch(A, p.sam, p.sak, m0, (kt + 1) * TL::BK, p.M, p.K, (T)p.ca, tid);
-      sb.fetch(B, p.sbn, p.sbk, n0, (kt + 1) * TL::BK, p.N, p.K, (T)p.cb, tid);
+      sa.fetch(A, p.sam, p.sak, m0, kb + (kt + 1) * TL::BK, p.M, ke, tid);
+      sb.fetch(B, p.sbn, p.sbk, n0, kb + (kt + 1) * TL::BK, p.N, ke, tid);
     }
     cx<T>* sc = smem + cur * (TL::AS + TL::BS);
     cx<T>* sn = smem + (cur ^ 1) * (TL::AS + TL::BS);
     tile_mma<T, TL>(sc, sc + TL::AS, acc, wm0, wn0, lane);
     if (kt + 1 < nk) {
-      sa.store(sn, TL::LDA, tid);
-      sb.store(sn + TL::AS, TL::LDB, tid);
+      sa.store(sn, TL::LDA, (T)p.ca, tid);
+      sb.store(sn + TL::AS, TL::LDB, (T)p.cb, tid);
     }
     __syncthreads();
   }
 
   SC* Cr = reinterpret_cast<SC*>(p.C);
+  T* Pr = reinterpret_cast<T*>(p.part) + (long)blockIdx.y * p.M * p.N * 2;
   const int rc = lane & 15, part = rc & 1;
 #pragma unroll
   for (int fm = 0; fm < TL::FM; ++fm)
@@ -86,23 +91,14 @@ __global__ __launch_bounds__(TL::NT) void gemm_kernel(GemmP p) {
         const int row = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, v);
         const int col = n0 + wn0 + fn * 8 + (rc >> 1);
         if (row >= p.M || col >= p.N) continue;
-        const long off = ((long)row * p.ldc + col) * 2 + part;
-        double val = (double)acc[fm][fn][v];
-        if (SWEEP) {
-          const bool rk = row >= p.k0 && row < p.k0 + p.kn;
-          const bool ck = col >= p.k0 && col < p.k0 + p.kn;
-          const double* R = reinterpret_cast<const double*>(p.R);
-          if (rk) {
-            val = R[((long)(row - p.k0) * p.ldr + col) * 2 + part];
-          } else if (ck) {
-            const double x = R[((long)(col - p.k0) * p.ldr + row) * 2 + part];
-            val = part ? -x : x;
-          } else {
-            val = (double)Cr[off] - val;
-          }
-          Cr[off] = (SC)val;
+        if (p.part) {  // raw partial sum; the reduction applies the epilogue
+          if (p.herm && bm == bn && row < col) continue;
+          Pr[((long)row * p.N + col) * 2 + part] = acc[fm][fn][v];
+          if (p.herm && row > col) Pr[((long)col * p.N + row) * 2 + part] = part ? -acc[fm][fn][v] : acc[fm][fn][v];
           continue;
         }
+        const long off = ((long)row * p.ldc + col) * 2 + part;
+        double val = (double)acc[fm][fn][v];
         val *= p.alpha;
         if (p.rs) val *= p.rs[row];
         if (part == 0 && row == col) val += p.diag_add;
@@ -114,10 +110,32 @@ __global__ __launch_bounds__(TL::NT) void gemm_kernel(GemmP p) {
       }
 }
 
+// Fixed-order reduction of split-K partial sums plus the epilogue.
+template <typename T, typename SC>
+__global__ void splitk_reduce_kernel(GemmP p, int nsplit) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;  // real index over M N 2
+  const long mn2 = (long)p.M * p.N * 2;
+  if (idx >= mn2) return;
+  const int part = (int)(idx & 1);
+  const long e = idx >> 1;
+  const int row = (int)(e / p.N), col = (int)(e % p.N);
+  const T* P = reinterpret_cast<const T*>(p.part);
+  double v = 0.0;
+  for (int s = 0; s < nsplit; ++s) v += (double)P[(long)s * mn2 + idx];
+  v *= p.alpha;
+  if (p.rs) v *= p.rs[row];
+  if (part == 0 && row == col) v += p.diag_add;
+  SC* Cr = reinterpret_cast<SC*>(p.C);
+  const long off = ((long)row * p.ldc + col) * 2 + part;
+  if (p.beta != 0.0) v += p.beta * (double)Cr[off];
+  if (p.herm && row == col && part == 1) v = 0.0;
+  Cr[off] = (SC)v;
+}
+
 typedef Tile<double, 64, 64, 16, 2, 2> Tile64;
 typedef Tile<float, 64, 64, 32, 2, 2> Tile32;
 
-template <typename T, typename SA, typename SB, typename SC, class TL, bool AMC, bool BNC, bool SW>
+template <typename T, typename SA, typename SB, typename SC, class TL, bool AMC, bool BNC>
 static hipError_t launch(const GemmDesc& d, hipStream_t st) {
   GemmP p;
   p.M = d.M; p.N = d.N; p.K = d.K;
@@ -126,29 +144,45 @@ static hipError_t launch(const GemmDesc& d, hipStream_t st) {
   p.C = d.C; p.ldc = d.ldc;
   p.alpha = d.alpha; p.beta = d.beta; p.diag_add = d.diag_add; p.rs = d.row_scale;
   p.herm = d.herm ? 1 : 0;
-  p.k0 = d.sw_k0; p.kn = d.sw_kn; p.R = d.R; p.ldr = d.ldr;
   p.ntm = (int)cdiv(d.M, TL::BM);
   p.ntn = (int)cdiv(d.N, TL::BN);
   if (d.herm) p.total = p.ntm * (p.ntm + 1) / 2;
   else p.total = p.ntm * p.ntn;
   if (p.total == 0) return hipSuccess;
+  int nsplit = 1;
+  if (d.split_ws) {
+    // enough workgroups to fill the chip, each split at least 4 K tiles deep
+    nsplit = (512 + p.total - 1) / p.total;
+    nsplit = std::min(nsplit, std::max(1, d.K / (4 * TL::BK)));
+    nsplit = std::min(nsplit, 16);
+    const size_t need = (size_t)nsplit * d.M * d.N * 2 * sizeof(T);
+    while (nsplit > 1 && (size_t)nsplit * d.M * d.N * 2 * sizeof(T) > d.split_ws_bytes) --nsplit;
+    (void)need;
+  }
+  p.kchunk = nsplit > 1 ? (int)cdiv(cdiv(d.K, nsplit), TL::BK) * TL::BK : std::max(d.K, 1);
+  nsplit = nsplit > 1 ? (int)cdiv(d.K, p.kchunk) : 1;
+  p.part = nsplit > 1 ? d.split_ws : nullptr;
   const unsigned grid = 8u * (unsigned)((p.total + 7) / 8);
-  hipLaunchKernelGGL((gemm_kernel<T, SA, SB, SC, TL, AMC, BNC, SW>), dim3(grid), dim3(TL::NT), 0, st, p);
+  hipLaunchKernelGGL((gemm_kernel<T, SA, SB, SC, TL, AMC, BNC>), dim3(grid, nsplit), dim3(TL::NT), 0, st, p);
+  if (nsplit > 1) {
+    const long mn2 = (long)d.M * d.N * 2;
+    hipLaunchKernelGGL((splitk_reduce_kernel<T, SC>), dim3(cdiv(mn2, 256)), dim3(256), 0, st, p, nsplit);
+  }
   return hipGetLastError();
 }
 
-template <typename T, typename SA, typename SB, typename SC, class TL, bool SW>
+template <typename T, typename SA, typename SB, typename SC, class TL>
 static hipError_t by_layout(const GemmDesc& d, hipStream_t st) {
   const bool amc = (d.sam == 1), bnc = (d.sbn == 1);
-  if (amc && bnc) return launch<T, SA, SB, SC, TL, true, true, SW>(d, st);
-  if (amc && !bnc) return launch<T, SA, SB, SC, TL, true, false, SW>(d, st);
-  if (!amc && bnc) return launch<T, SA, SB, SC, TL, false, true, SW>(d, st);
-  return launch<T, SA, SB, SC, TL, false, false, SW>(d, st);
+  if (amc && bnc) return launch<T, SA, SB, SC, TL, true, true>(d, st);
+  if (amc && !bnc) return launch<T, SA, SB, SC, TL, true, false>(d, st);
+  if (!amc && bnc) return launch<T, SA, SB, SC, TL, false, true>(d, st);
+  return launch<T, SA, SB, SC, TL, false, false>(d, st);
 }
 
 template <typename SA, typename SB, typename SC>
 static hipError_t f32_types(const GemmDesc& d, hipStream_t st) {
-  return by_layout<float, SA, SB, SC, Tile32, false>(d, st);
+  return by_layout<float, SA, SB, SC, Tile32>(d, st);
 }
 
 hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st) {
@@ -157,10 +191,8 @@ hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st) {
   if (!(d.sam == 1 || d.sak == 1) || !(d.sbk == 1 || d.sbn == 1)) return hipErrorInvalidValue;
   if (compute == P64) {
     if (d.a32 || d.b32 || d.c32) return hipErrorInvalidValue;
-    if (d.sweep) return by_layout<double, double, double, double, Tile64, true>(d, st);
-    return by_layout<double, double, double, double, Tile64, false>(d, st);
+    return by_layout<double, double, double, double, Tile64>(d, st);
   }
-  if (d.sweep) return hipErrorInvalidValue;
   if (d.a32) {
     if (d.b32) return d.c32 ? f32_types<float, float, float>(d, st) : f32_types<float, float, double>(d, st);
     return d.c32 ? f32_types<float, double, float>(d, st) : f32_types<float, double, double>(d, st);

@@ -20,8 +20,9 @@ struct GemmDesc {
   double alpha = 1.0, beta = 0.0, diag_add = 0.0;
   const double* row_scale = nullptr;  // device, length M, optional
   bool herm = false;                  // only lower tiles; upper mirrored as conj
-  // sweep epilogue (FP64 only): rows/cols [sw_k0, sw_k0 + sw_kn) come from the panel R
-  bool sweep = false; int sw_k0 = 0, sw_kn = 0; const void* R = nullptr; long ldr = 0;
+  // optional split-K scratch (device): when set, K is split across workgroups and the
+  // partial sums are reduced in a fixed order by a second kernel
+  void* split_ws = nullptr; size_t split_ws_bytes = 0;
 };
 // Compute precision: P64 -> f64 MFMA; P32 -> f32 MFMA.
 hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st);
@@ -43,9 +44,7 @@ hipError_t core_reduce(Prec compute, int nmu, const void* part, int nsplit, doub
                        void* negm_out, hipStream_t st);
 
 // ----- small FP64 dense algebra, row-major n x n complex128, ld = n
-// In-place lower Cholesky A = L L^H; the strict upper triangle is zeroed.
-hipError_t potrf(int n, void* a, void* scratch, int* status, hipStream_t st);
-// In-place Hermitian positive definite sweep: A <- -A^{-1}.  scratch: 2 * 64 * n complex128.
+// In-place Hermitian positive definite sweep: A <- -A^{-1}.  scratch: linalg_scratch_bytes(n).
 hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st);
 size_t linalg_scratch_bytes(int n);
 
@@ -72,10 +71,11 @@ struct DftPlan {
 // zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][n2][nd] -> zg: [nmu][ng]
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);
 hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, hipStream_t st);
-bool dft_supported(int n0, int n1, Prec compute);
+bool dft_supported(int n0, int n1, int kx, int ky, Prec compute);  // LDS fits
 
 hipError_t conj_transpose(int n, const void* a, void* at, hipStream_t st);   // at = a^H (z64)
 hipError_t convert_z(const void* src, bool src32, void* dst, bool dst32, long count, hipStream_t st);
+hipError_t axpby(const void* A, double a, const void* B, double b, void* C, long count, hipStream_t st);  // z64
 hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStream_t st);  // z64
 // out[0] += ||a||_F^2 over count complex128, deterministic (single pass of block partials)
 hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st);

@@ -1,15 +1,9 @@
 // FP64 dense algebra on the N_mu x N_mu core (row-major complex128, ld = n).
 //
-//   potrf          blocked right-looking Cholesky A = L L^H (panel width 32):
-//                  one kernel factors the diagonal block in LDS, inverts it and
-//                  forms the sub-diagonal panel L_ik = A_ik L_kk^{-H}; the
-//                  trailing update is an MFMA GEMM on the lower tiles.
 //   sweep_inverse  blocked Gauss-Jordan sweep of a Hermitian positive definite
-//                  matrix, A <- -A^{-1}: per 32-wide pivot block, one kernel
-//                  inverts the pivot block and forms the row panel R = P A_k:,
-//                  then one MFMA GEMM applies A_ij -= A_ik P A_kj to the whole
-//                  matrix with the pivot row/column taken from R.
-// A non-positive or non-finite pivot sets bit 0 of *status (ISDF_E_NOT_PD).
+//                  matrix, A <- -A^{-1}, one kernel per 32-wide pivot block.
+// A non-positive or non-finite pivot sets bit 0 of *status (ISDF_E_NOT_PD);
+// the pivots of a Hermitian positive definite matrix stay positive throughout.
 #include "internal.h"
 #include "tile.h"
 
@@ -24,195 +18,200 @@ __device__ __forceinline__ z64 zdiv(z64 a, z64 b) {
   return z64{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-__global__ __launch_bounds__(256) void potrf_panel_kernel(int n, z64* a, int k0, int kn, int* status) {
-  __shared__ z64 D[NB][NB + 1];
-  __shared__ z64 X[NB][NB + 1];
-  __shared__ z64 P[NB][NB + 1];
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < kn * kn; idx += 256) {
-    const int r = idx / kn, c = idx % kn;
-    D[r][c] = (r >= c) ? a[(long)(k0 + r) * n + k0 + c] : z64{0.0, 0.0};
-  }
-  __syncthreads();
-  for (int c = 0; c < kn; ++c) {
-    if (tid == 0) {
-      double d = D[c][c].re;
-      if (!(d > 0.0) || !isfinite(d)) {
-        atomicOr(status, 1);
-        d = 1.0;
-      }
-      D[c][c] = z64{sqrt(d), 0.0};
-    }
-    __syncthreads();
-    const double piv = D[c][c].re;
-    for (int r = c + 1 + tid; r < kn; r += 256) D[r][c] = z64{D[r][c].re / piv, D[r][c].im / piv};
-    __syncthreads();
-    const int m = kn - c - 1;
-    for (int idx = tid; idx < m * m; idx += 256) {
-      const int r = c + 1 + idx / m, s = c + 1 + idx % m;
-      if (s <= r) {
-        const z64 x = cmul(D[r][c], cconj(D[s][c]));
-        D[r][s].re -= x.re;
-        D[r][s].im -= x.im;
-      }
-    }
-    __syncthreads();
-  }
-  // X = L_kk^{-1}, one column per thread (forward substitution)
-  if (tid < kn) {
-    const int col = tid;
-    for (int r = 0; r < kn; ++r) {
-      if (r < col) { X[r][col] = z64{0.0, 0.0}; continue; }
-      z64 s = (r == col) ? z64{1.0, 0.0} : z64{0.0, 0.0};
-      for (int t = col; t < r; ++t) {
-        const z64 x = cmul(D[r][t], X[t][col]);
-        s.re -= x.re;
-        s.im -= x.im;
-      }
-      X[r][col] = zdiv(s, D[r][r]);
-    }
-  }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int idx = tid; idx < kn * kn; idx += 256) {
-      const int r = idx / kn, c = idx % kn;
-      a[(long)(k0 + r) * n + k0 + c] = (r >= c) ? D[r][c] : z64{0.0, 0.0};
-    }
-    // strict upper part of this block row right of the diagonal block
-    const int w = n - k0 - kn;
-    for (long idx = tid; idx < (long)kn * w; idx += 256) {
-      const int r = (int)(idx / w), c = (int)(idx % w);
-      a[(long)(k0 + r) * n + k0 + kn + c] = z64{0.0, 0.0};
-    }
-    return;
-  }
-  const int rb0 = k0 + kn + (blockIdx.x - 1) * NB;
-  const int nr = min(NB, n - rb0);
-  if (nr <= 0) return;
-  for (int idx = tid; idx < nr * kn; idx += 256) {
-    const int r = idx / kn, c = idx % kn;
-    P[r][c] = a[(long)(rb0 + r) * n + k0 + c];
-  }
-  __syncthreads();
-  // L_ik = A_ik X^H
-  for (int idx = tid; idx < nr * kn; idx += 256) {
-    const int r = idx / kn, c = idx % kn;
-    z64 s{0.0, 0.0};
-    for (int t = 0; t <= c; ++t) {
-      const z64 x = cmul(P[r][t], cconj(X[c][t]));
-      s.re += x.re;
-      s.im += x.im;
-    }
-    a[(long)(rb0 + r) * n + k0 + c] = s;
-  }
-}
+// One pivot step of the sweep as a single kernel.  With pivot rows
+// k = [k0, k0 + kn) and P = A_kk^{-1}, the swept matrix is
+//   A'_kj = P A_kj (j outside k),  A'_ik = A_ik P = (P A_ki)^H (i outside k),
+//   A'_kk = -P,  A'_ij = A_ij - A_ik P A_kj = A_ij - conj(A_ki)^T (P A_kj).
+// Every workgroup owns one 64 x 64 output tile: it inverts the pivot block in
+// LDS by Gauss-Jordan (no pivoting: Hermitian positive definite), forms the
+// slices of R = P A_k: it needs, and applies the rank-kn update with MFMA.
+// Input and output are different buffers, so no workgroup reads what another
+// one writes.
+typedef Tile<double, 64, 64, NB, 2, 2> TS;
 
-hipError_t potrf(int n, void* a, void* scratch, int* status, hipStream_t st) {
-  (void)scratch;
-  z64* A = (z64*)a;
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int kn = min(NB, n - k0);
-    const int rest = n - k0 - kn;
-    const int nblk = 1 + (rest + NB - 1) / NB;
-    hipLaunchKernelGGL(potrf_panel_kernel, dim3(nblk), dim3(256), 0, st, n, A, k0, kn, status);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (rest > 0) {
-      GemmDesc d;
-      d.M = d.N = rest;
-      d.K = kn;
-      d.A = A + (long)(k0 + kn) * n + k0; d.sam = n; d.sak = 1;
-      d.B = A + (long)(k0 + kn) * n + k0; d.sbk = 1; d.sbn = n; d.conjB = true;
-      d.C = A + (long)(k0 + kn) * n + k0 + kn; d.ldc = n;
-      d.alpha = -1.0; d.beta = 1.0; d.herm = true;
-      e = gemm(P64, d, st);
-      if (e != hipSuccess) return e;
-    }
-  }
-  return hipSuccess;
-}
+__global__ __launch_bounds__(256) void sweep_step_kernel(int n, const z64* __restrict__ ain,
+                                                         z64* __restrict__ aout, int k0, int kn,
+                                                         int* status, int ntm, int total) {
+  __shared__ z64 W[NB][NB + 1];   // pivot block (identity-padded to NB x NB), inverted in place
+  __shared__ z64 colp[NB], rowp[NB], colp2[NB], rowp2[NB];
+  __shared__ z64 As[TS::AS];   // [t][i] = conj(A[k0 + t][m0 + i])   (A operand, k-major)
+  __shared__ z64 Bs[TS::BS];   // [t][j] = (P A_k:)[t][n0 + j]        (B operand, k-major)
+  __shared__ z64 Ri[NB][64 + 1];  // (P A_k:)[t][m0 + i], only for tiles meeting the pivot columns
+  const int id = xcd_remap(blockIdx.x, total);
+  if (id >= total) return;
+  const int bm = id % ntm, bn = id / ntm;
+  const int m0 = bm * 64, n0 = bn * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool need_ri = (n0 < k0 + kn) && (n0 + 64 > k0);
+  const int wm0 = (wave % TS::WGM) * TS::WTM, wn0 = (wave / TS::WGM) * TS::WTN;
+  const int rc = lane & 15, part = rc & 1;
+  const double* ainr = reinterpret_cast<const double*>(ain);
 
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void sweep_panel_kernel(int n, const z64* a, int k0, int kn, z64* R,
-                                                          z64* Old, int* status) {
-  __shared__ z64 W[NB][NB + 1];
-  __shared__ z64 colp[NB];
-  __shared__ z64 Pan[NB][64 + 1];
-  const int tid = threadIdx.x;
-  const int c0 = blockIdx.x * 64;
-  for (int idx = tid; idx < kn * kn; idx += 256) {
-    const int r = idx / kn, c = idx % kn;
-    W[r][c] = a[(long)(k0 + r) * n + k0 + c];
+  // this lane's old tile values, loaded first so their latency hides behind the pivot inversion
+  double cold[TS::FM][TS::FN][4];
+#pragma unroll
+  for (int fm = 0; fm < TS::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < TS::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm0 + fm * 16 + Mfma<double>::row(lane, v);
+        const int col = n0 + wn0 + fn * 8 + (rc >> 1);
+        const long off = (row < n && col < n) ? ((long)row * n + col) * 2 + part : 0;
+        cold[fm][fn][v] = ainr[off];
+      }
+#pragma unroll
+  for (int e = 0; e < NB * NB / 256; ++e) {
+    const int idx = tid + 256 * e, r = idx / NB, c = idx % NB;
+    W[r][c] = (r < kn && c < kn) ? ain[(long)(k0 + r) * n + k0 + c] : z64{r == c ? 1.0 : 0.0, 0.0};
+  }
+  // raw pivot rows at this tile's columns (into Bs) and rows (into As, conjugated later)
+#pragma unroll
+  for (int e = 0; e < NB * 64 / 256; ++e) {
+    const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
+    z64 vj{0.0, 0.0}, vi{0.0, 0.0};
+    if (t < kn) {
+      if (n0 + c < n) vj = ain[(long)(k0 + t) * n + n0 + c];
+      if (m0 + c < n) vi = ain[(long)(k0 + t) * n + m0 + c];
+    }
+    Bs[t * TS::LDB + c] = vj;
+    As[t * TS::LDA + c] = vi;
   }
   __syncthreads();
-  // in-place Gauss-Jordan inverse of the pivot block (Hermitian positive definite: no pivoting)
-  for (int p = 0; p < kn; ++p) {
-    const z64 piv = W[p][p];
-    bool bad = !(piv.re > 0.0) || !isfinite(piv.re) || !isfinite(piv.im);
+  // Gauss-Jordan on the padded block, one barrier per pivot: while eliminating
+  // pivot p, the threads that write row p+1 and column p+1 also store them in
+  // the next pivot's (double-buffered) row / column arrays.
+  if (tid < NB) {
+    rowp[tid] = W[0][tid];
+    colp[tid] = W[tid][0];
+  }
+  __syncthreads();
+  for (int p = 0; p < NB; ++p) {
+    z64* rowc = (p & 1) ? rowp2 : rowp;
+    z64* colc = (p & 1) ? colp2 : colp;
+    z64* rown = (p & 1) ? rowp : rowp2;
+    z64* coln = (p & 1) ? colp : colp2;
+    const z64 piv = rowc[p];
+    const bool bad = !(piv.re > 0.0) || !isfinite(piv.re) || !isfinite(piv.im);
     const z64 d = bad ? z64{1.0, 0.0} : zdiv(z64{1.0, 0.0}, piv);
-    if (bad && tid == 0) atomicOr(status, 1);
-    __syncthreads();
-    if (tid < kn) {
-      colp[tid] = W[tid][p];
-      W[p][tid] = (tid == p) ? d : cmul(W[p][tid], d);
-    }
-    __syncthreads();
-    for (int idx = tid; idx < kn * kn; idx += 256) {
-      const int r = idx / kn, j = idx % kn;
-      if (r == p) continue;
-      const z64 base = (j == p) ? z64{0.0, 0.0} : W[r][j];
-      const z64 x = cmul(colp[r], W[p][j]);
-      W[r][j] = z64{base.re - x.re, base.im - x.im};
+    if (bad && tid == 0 && id == 0) atomicOr(status, 1);
+#pragma unroll
+    for (int e = 0; e < NB * NB / 256; ++e) {
+      const int idx = tid + 256 * e, r = idx / NB, j = idx % NB;
+      const z64 rj = (j == p) ? d : cmul(rowc[j], d);   // scaled pivot row
+      z64 nv;
+      if (r == p) {
+        nv = rj;
+      } else {
+        const z64 base = (j == p) ? z64{0.0, 0.0} : W[r][j];
+        const z64 x = cmul(colc[r], rj);
+        nv = z64{base.re - x.re, base.im - x.im};
+      }
+      W[r][j] = nv;
+      if (r == p + 1) rown[j] = nv;
+      if (j == p + 1) coln[r] = nv;
     }
     __syncthreads();
   }
-  const int nc = min(64, n - c0);
-  for (int idx = tid; idx < kn * nc; idx += 256) {
-    const int t = idx / nc, c = idx % nc;
-    Pan[t][c] = a[(long)(k0 + t) * n + c0 + c];
-  }
-  __syncthreads();
-  for (int idx = tid; idx < kn * nc; idx += 256) {
-    const int t = idx / nc, c = idx % nc;
-    const int gc = c0 + c;
-    Old[(long)t * n + gc] = Pan[t][c];
-    z64 s{0.0, 0.0};
-    if (gc >= k0 && gc < k0 + kn) {
-      s = z64{-W[t][gc - k0].re, -W[t][gc - k0].im};
-    } else {
-      for (int u = 0; u < kn; ++u) {
-        const z64 x = cmul(W[t][u], Pan[u][c]);
-        s.re += x.re;
-        s.im += x.im;
+  // R slices: thread (column c = tid % 64, rows t = tid / 64 + 4 s)
+  {
+    const int c = tid & 63, g = tid >> 6;
+    z64 rj[NB / 4], ri[NB / 4];
+#pragma unroll
+    for (int s2 = 0; s2 < NB / 4; ++s2) { rj[s2] = z64{0.0, 0.0}; ri[s2] = z64{0.0, 0.0}; }
+    for (int u = 0; u < kn; ++u) {
+      const z64 bj = Bs[u * TS::LDB + c];
+#pragma unroll
+      for (int s2 = 0; s2 < NB / 4; ++s2) {
+        const z64 w = W[g + 4 * s2][u];
+        rj[s2].re += w.re * bj.re - w.im * bj.im;
+        rj[s2].im += w.re * bj.im + w.im * bj.re;
       }
     }
-    R[(long)t * n + gc] = s;
+    if (need_ri) {
+      for (int u = 0; u < kn; ++u) {
+        const z64 bi = As[u * TS::LDA + c];
+#pragma unroll
+        for (int s2 = 0; s2 < NB / 4; ++s2) {
+          const z64 w = W[g + 4 * s2][u];
+          ri[s2].re += w.re * bi.re - w.im * bi.im;
+          ri[s2].im += w.re * bi.im + w.im * bi.re;
+        }
+      }
+    }
+    __syncthreads();  // all reads of the raw panels are done
+#pragma unroll
+    for (int s2 = 0; s2 < NB / 4; ++s2) {
+      const int t = g + 4 * s2;
+      if (t < kn) {
+        const int gj = n0 + c;
+        Bs[t * TS::LDB + c] = (gj >= k0 && gj < k0 + kn) ? z64{-W[t][gj - k0].re, -W[t][gj - k0].im} : rj[s2];
+        const int gi = m0 + c;
+        if (need_ri) Ri[t][c] = (gi >= k0 && gi < k0 + kn) ? z64{-W[t][gi - k0].re, -W[t][gi - k0].im} : ri[s2];
+        As[t * TS::LDA + c] = cconj(As[t * TS::LDA + c]);
+      }
+    }
   }
+  __syncthreads();
+  TS::acc_t acc[TS::FM][TS::FN];
+  zero_acc<TS>(acc);
+  tile_mma<double, TS>(As, Bs, acc, wm0, wn0, lane);
+  double* aoutr = reinterpret_cast<double*>(aout);
+#pragma unroll
+  for (int fm = 0; fm < TS::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < TS::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm0 + fm * 16 + Mfma<double>::row(lane, v);
+        const int col = n0 + wn0 + fn * 8 + (rc >> 1);
+        if (row >= n || col >= n) continue;
+        const long off = ((long)row * n + col) * 2 + part;
+        double val;
+        if (row >= k0 && row < k0 + kn) {
+          const z64 r = Bs[(row - k0) * TS::LDB + (col - n0)];
+          val = part ? r.im : r.re;
+        } else if (col >= k0 && col < k0 + kn) {
+          const z64 r = Ri[col - k0][row - m0];
+          val = part ? -r.im : r.re;
+        } else {
+          val = cold[fm][fn][v] - acc[fm][fn][v];
+        }
+        aoutr[off] = val;
+      }
 }
 
-size_t linalg_scratch_bytes(int n) { return (size_t)2 * NB * n * sizeof(z64); }
+size_t linalg_scratch_bytes(int n) { return (size_t)n * n * sizeof(z64); }
 
 hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st) {
-  z64* A = (z64*)a;
-  z64* R = (z64*)scratch;
-  z64* Old = R + (long)NB * n;
+  z64* bufs[2] = {(z64*)a, (z64*)scratch};
+  const int ntm = (n + 63) / 64;
+  const int total = ntm * ntm;
+  const unsigned grid = 8u * (unsigned)((total + 7) / 8);
+  int cur = 0;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kn = min(NB, n - k0);
-    hipLaunchKernelGGL(sweep_panel_kernel, dim3(cdiv(n, 64)), dim3(256), 0, st, n, (const z64*)A, k0,
-                       kn, R, Old, status);
+    hipLaunchKernelGGL(sweep_step_kernel, dim3(grid), dim3(256), 0, st, n, (const z64*)bufs[cur],
+                       bufs[cur ^ 1], k0, kn, status, ntm, total);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    GemmDesc d;
-    d.M = d.N = n;
-    d.K = kn;
-    d.A = Old; d.sam = 1; d.sak = n; d.conjA = true;
-    d.B = R; d.sbk = n; d.sbn = 1;
-    d.C = A; d.ldc = n;
-    d.sweep = true; d.sw_k0 = k0; d.sw_kn = kn; d.R = R; d.ldr = n;
-    e = gemm(P64, d, st);
-    if (e != hipSuccess) return e;
+    cur ^= 1;
   }
+  if (cur == 1) return convert_z(scratch, false, a, false, (long)n * n, st);
   return hipSuccess;
+}
+
+// C = a * A + b * B elementwise (complex128, count elements)
+__global__ void axpby_kernel(const double* A, double a, const double* B, double b, double* C, long count2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count2) C[i] = a * A[i] + b * B[i];
+}
+
+hipError_t axpby(const void* A, double a, const void* B, double b, void* C, long count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpby_kernel, dim3(cdiv(2 * count, 256)), dim3(256), 0, st, (const double*)A, a,
+                     (const double*)B, b, (double*)C, 2 * count);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -33,38 +33,41 @@ struct Tile {
 
 // Global -> registers -> LDS staging of one BK x BX operand tile stored [k][x].
 // Source element (x, k) lives at base[x * sx + k * sk]; XCONTIG says sx == 1
-// (else sk == 1).  Out-of-range elements are zero.  Source type S is converted
-// to the compute type T; `csign` = -1 conjugates.
+// (else sk == 1).  fetch() issues every load unconditionally (out-of-range
+// elements read element 0 and are masked later), keeping the raw source values
+// in registers, so the loads stay in flight while the MFMA step of the previous
+// tile runs; store() masks, converts to the compute type T and writes LDS.
 template <typename T, typename S, int BX, int BK, int NT, bool XCONTIG>
 struct Stager {
   static constexpr int E = (BX * BK + NT - 1) / NT;
-  cx<T> r[E];
+  static_assert(E <= 32, "valid mask is 32 bits");
+  cx<S> raw[E];
+  uint32_t valid;
 
   __device__ __forceinline__ void fetch(const cx<S>* __restrict__ base, long sx, long sk, int x0,
-                                        int k0, int X, int K, T csign, int tid) {
+                                        int k0, int X, int K, int tid) {
+    valid = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      int idx = tid + e * NT;
+      const int idx = tid + e * NT;
       int x, k;
       if (XCONTIG) { x = idx % BX; k = idx / BX; } else { k = idx % BK; x = idx / BK; }
-      int gx = x0 + x, gk = k0 + k;
-      cx<T> v{(T)0, (T)0};
-      if (idx < BX * BK && gx < X && gk < K) {
-        cx<S> s = base[(long)gx * sx + (long)gk * sk];
-        v.re = (T)s.re;
-        v.im = csign * (T)s.im;
-      }
-      r[e] = v;
+      const int gx = x0 + x, gk = k0 + k;
+      const bool ok = (idx < BX * BK) && gx < X && gk < K;
+      const long off = ok ? (long)gx * sx + (long)gk * sk : 0;
+      raw[e] = base[off];
+      valid |= (ok ? 1u : 0u) << e;
     }
   }
-  __device__ __forceinline__ void store(cx<T>* lds, int ld, int tid) const {
+  __device__ __forceinline__ void store(cx<T>* lds, int ld, T csign, int tid) const {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      int idx = tid + e * NT;
+      const int idx = tid + e * NT;
       if (idx >= BX * BK) break;
       int x, k;
       if (XCONTIG) { x = idx % BX; k = idx / BX; } else { k = idx % BK; x = idx / BK; }
-      lds[k * ld + x] = r[e];
+      const bool ok = (valid >> e) & 1u;
+      lds[k * ld + x] = cx<T>{ok ? (T)raw[e].re : (T)0, ok ? csign * (T)raw[e].im : (T)0};
     }
   }
 };

@@ -31,24 +31,24 @@ __device__ __forceinline__ void kloop_xx(cx<T>* smem, const z64* A, long lda, co
   Stager<T, double, TL::BN, TL::BK, TL::NT, true> sb;
   const int nk = (K + TL::BK - 1) / TL::BK;
   if (nk == 0) return;
-  sa.fetch(A, 1, lda, m0, 0, M, K, ca, tid);
-  sb.fetch(B, 1, ldb, n0, 0, N, K, cb, tid);
+  sa.fetch(A, 1, lda, m0, 0, M, K, tid);
+  sb.fetch(B, 1, ldb, n0, 0, N, K, tid);
   __syncthreads();
-  sa.store(smem, TL::LDA, tid);
-  sb.store(smem + TL::AS, TL::LDB, tid);
+  sa.store(smem, TL::LDA, ca, tid);
+  sb.store(smem + TL::AS, TL::LDB, cb, tid);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      sa.fetch(A, 1, lda, m0, (kt + 1) * TL::BK, M, K, ca, tid);
-      sb.fetch(B, 1, ldb, n0, (kt + 1) * TL::BK, N, K, cb, tid);
+      sa.fetch(A, 1, lda, m0, (kt + 1) * TL::BK, M, K, tid);
+      sb.fetch(B, 1, ldb, n0, (kt + 1) * TL::BK, N, K, tid);
     }
     cx<T>* sc = smem + cur * (TL::AS + TL::BS);
     cx<T>* sn = smem + (cur ^ 1) * (TL::AS + TL::BS);
     tile_mma<T, TL>(sc, sc + TL::AS, acc, wm0, wn0, lane);
     if (kt + 1 < nk) {
-      sa.store(sn, TL::LDA, tid);
-      sb.store(sn + TL::AS, TL::LDB, tid);
+      sa.store(sn, TL::LDA, ca, tid);
+      sb.store(sn + TL::AS, TL::LDB, cb, tid);
     }
     __syncthreads();
   }
@@ -146,58 +146,63 @@ __global__ __launch_bounds__(TL::NT) void core_kernel(int nmu, int nv, int nc, c
   const bool okm = gm < nmu, okn = gn < nmu;
   const z64* pc = pm + (long)nv * ldp;
 
-  typename TL::acc_t acc[TL::FM][TL::FN];
-  zero_acc<TL>(acc);
-
   const int njc = (nc + TL::BK - 1) / TL::BK;
   const int S = njc * ni;
-  cx<T> bm_r[E], bn_r[E];   // conj-free orbital values b_j at this thread's points
-  cx<T> va[E], vb[E];       // staged A / B elements
-  int cur_jc = -1;
+  // Raw operands of the next stage, loaded before the MFMA step of the current
+  // one (addresses clamped to valid memory, masked when formed).
+  z64 bm_raw[E], bn_raw[E];   // b_j at this thread's points (reloaded when the j block changes)
+  double w_raw[E];
+  z64 am_raw, an_raw;
+  int cur_jc = -1, nxt_jc = 0;
+  const long pmo = okm ? gm : 0, pno = okn ? gn : 0;
 
-  auto produce = [&](int s) {
+  auto fetch = [&](int s) {
     const int jc = s / ni, i = i0 + s % ni;
     if (jc != cur_jc) {
-      cur_jc = jc;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int j = jc * TL::BK + kb + e * KSTEP;
-        cx<T> zm{0, 0}, zn{0, 0};
-        if (j < nc) {
-          if (okm) zm = cvt<T>(pc[(long)j * ldp + gm]);
-          if (okn) zn = cvt<T>(pc[(long)j * ldp + gn]);
-        }
-        bm_r[e] = zm;
-        bn_r[e] = zn;
+        const long jo = (j < nc) ? (long)j * ldp : 0;
+        bm_raw[e] = pc[jo + pmo];
+        bn_raw[e] = pc[jo + pno];
       }
+      cur_jc = jc;
     }
-    const cx<T> am = okm ? cvt<T>(pm[(long)i * ldp + gm]) : cx<T>{0, 0};
-    const cx<T> an = okn ? cvt<T>(pm[(long)i * ldp + gn]) : cx<T>{0, 0};
+    nxt_jc = jc;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = jc * TL::BK + kb + e * KSTEP;
-      const T wij = (j < nc) ? (T)w[(long)i * nc + j] : (T)0;
-      cx<T> t = cmulc(am, bm_r[e]);           // conj(a_i(mu)) b_j(mu)
-      va[e] = cx<T>{t.re * wij, t.im * wij};
-      vb[e] = cmul(an, cconj(bn_r[e]));       // a_i(nu) conj(b_j(nu))
+      w_raw[e] = w[(long)i * nc + ((j < nc) ? j : 0)];
     }
+    am_raw = pm[(long)i * ldp + pmo];
+    an_raw = pm[(long)i * ldp + pno];
   };
   auto store = [&](cx<T>* buf) {
+    const cx<T> am = okm ? cvt<T>(am_raw) : cx<T>{0, 0};
+    const cx<T> an = okn ? cvt<T>(an_raw) : cx<T>{0, 0};
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int kk = kb + e * KSTEP;
-      buf[kk * TL::LDA + x] = va[e];
-      buf[TL::AS + kk * TL::LDB + x] = vb[e];
+      const bool okj = nxt_jc * TL::BK + kk < nc;
+      const T wij = okj ? (T)w_raw[e] : (T)0;
+      const cx<T> bmv = okm ? cvt<T>(bm_raw[e]) : cx<T>{0, 0};
+      const cx<T> bnv = okn ? cvt<T>(bn_raw[e]) : cx<T>{0, 0};
+      const cx<T> t = cmulc(am, bmv);                       // conj(a_i(mu)) b_j(mu)
+      buf[kk * TL::LDA + x] = cx<T>{t.re * wij, t.im * wij};
+      const cx<T> u = cmul(an, cconj(bnv));                 // a_i(nu) conj(b_j(nu))
+      buf[TL::AS + kk * TL::LDB + x] = okj ? u : cx<T>{0, 0};
     }
   };
 
+  typename TL::acc_t acc[TL::FM][TL::FN];
+  zero_acc<TL>(acc);
   if (S > 0) {
-    produce(0);
+    fetch(0);
     store(smem);
     __syncthreads();
     for (int s = 0; s < S; ++s) {
       const int cur = s & 1;
-      if (s + 1 < S) produce(s + 1);
+      if (s + 1 < S) fetch(s + 1);
       cx<T>* sc = smem + cur * (TL::AS + TL::BS);
       tile_mma<T, TL>(sc, sc + TL::AS, acc, wm0, wn0, lane);
       if (s + 1 < S) store(smem + (cur ^ 1) * (TL::AS + TL::BS));
