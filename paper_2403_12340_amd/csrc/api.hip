@@ -113,6 +113,7 @@ struct Layout {
   size_t w1 = 0;                     // aliases the zt region
   size_t zt_bytes = 0;               // size of the zt region
   size_t part = 0, l2 = 0, lin2 = 0; // core partial sums; second -M buffer and sweep scratch
+  size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (mixed precision only)
   int kx = 0, ky = 0, kz = 0, nd = 0, nsplit = 1;
 };
 
@@ -127,6 +128,10 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.status = take(sizeof(StatusBlock));
   L.psi_c = P.cplx ? 0 : take((size_t)P.ns * P.nr * z);
   L.pm = take((size_t)P.ns * P.nmu * z);
+  if (P.m32) {
+    L.psi32 = take((size_t)P.ns * P.nr * 8);
+    L.pm32 = take((size_t)P.ns * P.nmu * 8);
+  }
   // host-supplied arrays, adjacent so that one copy uploads them all
   L.mu = take((size_t)P.nmu * 4);
   L.e = take((size_t)P.ns * 8);
@@ -341,7 +346,7 @@ isdf_status stage_s(Run& R, hipStream_t st, size_t lin) {
   const Problem& P = R.P;
   void* pm = at<char>(R.ws, R.L.pm);
   void* s = at<char>(R.ws, R.L.s);
-  HIPCHK(zpair(P64, P.nmu, P.nmu, P.nv, P.ns, pm, P.nmu, pm, P.nmu, s, P.nmu, false, st));
+  HIPCHK(zpair(P64, P.nmu, P.nmu, P.nv, P.ns, pm, P.nmu, pm, P.nmu, false, s, P.nmu, false, st));
   HIPCHK(sweep_inverse(P.nmu, s, at<char>(R.ws, lin), &R.sb->status, st));
   return ISDF_OK;
 }
@@ -349,9 +354,16 @@ isdf_status stage_s(Run& R, hipStream_t st, size_t lin) {
 isdf_status stage_z(Run& R) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
-  const Prec cp = P.prec == P64 ? P64 : P32;
-  HIPCHK(zpair(cp, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm), P.nmu, R.psi, P.nr,
-               at<char>(R.ws, R.L.zt), P.nr, P.m32, R.st));
+  if (P.prec == P64) {
+    HIPCHK(zpair(P64, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm), P.nmu, R.psi, P.nr, false,
+                 at<char>(R.ws, R.L.zt), P.nr, false, R.st));
+    return ISDF_OK;
+  }
+  // mixed: one pass to complex64 halves the bytes the contraction streams
+  HIPCHK(convert_z(R.psi, false, at<char>(R.ws, R.L.psi32), true, (long)P.ns * P.nr, R.st));
+  HIPCHK(convert_z(at<char>(R.ws, R.L.pm), false, at<char>(R.ws, R.L.pm32), true, (long)P.ns * P.nmu, R.st));
+  HIPCHK(zpair(P32, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm32), P.nmu, at<char>(R.ws, R.L.psi32),
+               P.nr, true, at<char>(R.ws, R.L.zt), P.nr, true, R.st));
   return ISDF_OK;
 }
 

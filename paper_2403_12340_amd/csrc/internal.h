@@ -29,9 +29,10 @@ hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st);
 
 // ----- orbital pair Gram (step 1):  out[mu][c] = conj(Pv(mu, c)) * Qc(mu, c)
 //   Pv(mu, c) = sum_{i < nv} conj(pm[i][mu]) b[i][c],  Qc(mu, c) = sum_{nv <= j < ns} conj(pm[j][mu]) b[j][c]
-//   pm: [ns][ldp] complex128 (orbitals at the points), b: [ns][ldb] complex128, out [M][ldo]
+//   pm: [ns][ldp] (orbitals at the points), b: [ns][ldb], both complex64 if in32 else complex128;
+//   out [M][ldo] complex64 if out32 else complex128
 hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
-                 long ldb, void* out, long ldo, bool out32, hipStream_t st);
+                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st);
 
 // ----- core (step 2): partial sums over occupied ranges of
 //   M(mu, nu) = sum_{i, j} conj(a_i(mu)) b_j(mu) w_ij a_i(nu) conj(b_j(nu))

@@ -13,6 +13,17 @@ namespace isdf {
 
 constexpr int NB = 32;
 
+// 1 / z via the hardware reciprocal of |z|^2 refined by two Newton steps
+// (relative error at the level of a few ulp, ample for pivots of a Hermitian
+// positive definite elimination).
+__device__ __forceinline__ z64 zrcp(z64 z) {
+  const double s = z.re * z.re + z.im * z.im;
+  double x = __builtin_amdgcn_rcp(s);
+  x = x * (2.0 - s * x);
+  x = x * (2.0 - s * x);
+  return z64{z.re * x, -z.im * x};
+}
+
 __device__ __forceinline__ z64 zdiv(z64 a, z64 b) {
   const double d = b.re * b.re + b.im * b.im;
   return z64{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
@@ -28,12 +39,13 @@ __device__ __forceinline__ z64 zdiv(z64 a, z64 b) {
 // Input and output are different buffers, so no workgroup reads what another
 // one writes.
 typedef Tile<double, 64, 64, NB, 2, 2> TS;
+typedef Tile<double, NB, 64, NB, 2, 2> TP;   // P (NB x NB, k-major in W) times a NB x 64 panel
 
 __global__ __launch_bounds__(256) void sweep_step_kernel(int n, const z64* __restrict__ ain,
                                                          z64* __restrict__ aout, int k0, int kn,
                                                          int* status, int ntm, int total) {
-  __shared__ z64 W[NB][NB + 1];   // pivot block (identity-padded to NB x NB), inverted in place
-  __shared__ z64 colp[NB], rowp[NB], colp2[NB], rowp2[NB];
+  __shared__ z64 W[NB][NB + 1];   // P = inverse of the (identity-padded) pivot block
+  __shared__ z64 rowb[2][NB], colb[2][NB];
   __shared__ z64 As[TS::AS];   // [t][i] = conj(A[k0 + t][m0 + i])   (A operand, k-major)
   __shared__ z64 Bs[TS::BS];   // [t][j] = (P A_k:)[t][n0 + j]        (B operand, k-major)
   __shared__ z64 Ri[NB][64 + 1];  // (P A_k:)[t][m0 + i], only for tiles meeting the pivot columns
@@ -60,10 +72,14 @@ __global__ __launch_bounds__(256) void sweep_step_kernel(int n, const z64* __res
         const long off = (row < n && col < n) ? ((long)row * n + col) * 2 + part : 0;
         cold[fm][fn][v] = ainr[off];
       }
+  // pivot block: thread owns column j = tid % 32 of rows r_e = tid / 32 + 8 e (registers)
+  constexpr int EW = NB * NB / 256;
+  const int gj = tid % NB, gr = tid / NB;
+  z64 w[EW];
 #pragma unroll
-  for (int e = 0; e < NB * NB / 256; ++e) {
-    const int idx = tid + 256 * e, r = idx / NB, c = idx % NB;
-    W[r][c] = (r < kn && c < kn) ? ain[(long)(k0 + r) * n + k0 + c] : z64{r == c ? 1.0 : 0.0, 0.0};
+  for (int e = 0; e < EW; ++e) {
+    const int r = gr + 8 * e;
+    w[e] = (r < kn && gj < kn) ? ain[(long)(k0 + r) * n + k0 + gj] : z64{r == gj ? 1.0 : 0.0, 0.0};
   }
   // raw pivot rows at this tile's columns (into Bs) and rows (into As, conjugated later)
 #pragma unroll
@@ -77,79 +93,73 @@ __global__ __launch_bounds__(256) void sweep_step_kernel(int n, const z64* __res
     Bs[t * TS::LDB + c] = vj;
     As[t * TS::LDA + c] = vi;
   }
-  __syncthreads();
-  // Gauss-Jordan on the padded block, one barrier per pivot: while eliminating
-  // pivot p, the threads that write row p+1 and column p+1 also store them in
-  // the next pivot's (double-buffered) row / column arrays.
-  if (tid < NB) {
-    rowp[tid] = W[0][tid];
-    colp[tid] = W[tid][0];
-  }
-  __syncthreads();
+  // Gauss-Jordan in registers: per pivot, the owners publish row p and column p
+  // (double-buffered), one barrier, then every thread updates its own elements.
+  bool bad_any = false;
+#pragma unroll 1
   for (int p = 0; p < NB; ++p) {
-    z64* rowc = (p & 1) ? rowp2 : rowp;
-    z64* colc = (p & 1) ? colp2 : colp;
-    z64* rown = (p & 1) ? rowp : rowp2;
-    z64* coln = (p & 1) ? colp : colp2;
-    const z64 piv = rowc[p];
-    const bool bad = !(piv.re > 0.0) || !isfinite(piv.re) || !isfinite(piv.im);
-    const z64 d = bad ? z64{1.0, 0.0} : zdiv(z64{1.0, 0.0}, piv);
-    if (bad && tid == 0 && id == 0) atomicOr(status, 1);
+    const int b = p & 1;
 #pragma unroll
-    for (int e = 0; e < NB * NB / 256; ++e) {
-      const int idx = tid + 256 * e, r = idx / NB, j = idx % NB;
-      const z64 rj = (j == p) ? d : cmul(rowc[j], d);   // scaled pivot row
-      z64 nv;
-      if (r == p) {
-        nv = rj;
-      } else {
-        const z64 base = (j == p) ? z64{0.0, 0.0} : W[r][j];
-        const z64 x = cmul(colc[r], rj);
-        nv = z64{base.re - x.re, base.im - x.im};
-      }
-      W[r][j] = nv;
-      if (r == p + 1) rown[j] = nv;
-      if (j == p + 1) coln[r] = nv;
+    for (int e = 0; e < EW; ++e) {
+      if (gr + 8 * e == p) rowb[b][gj] = w[e];
+      if (gj == p) colb[b][gr + 8 * e] = w[e];
     }
     __syncthreads();
+    const z64 piv = rowb[b][p];
+    const bool bad = !(piv.re > 0.0) || !isfinite(piv.re) || !isfinite(piv.im);
+    bad_any |= bad;
+    const z64 d = bad ? z64{1.0, 0.0} : zrcp(piv);
+    const z64 rv = rowb[b][gj];
+    const z64 rs = cmul(rv, d);
+    const z64 rj = (gj == p) ? d : rs;   // scaled pivot row at this thread's column
+    z64 cv[EW];
+#pragma unroll
+    for (int e = 0; e < EW; ++e) cv[e] = colb[b][gr + 8 * e];
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+      const z64 x = cmul(cv[e], rj);
+      const double br = (gj == p) ? 0.0 : w[e].re, bi = (gj == p) ? 0.0 : w[e].im;
+      const bool own = (gr + 8 * e == p);
+      w[e] = z64{own ? rj.re : br - x.re, own ? rj.im : bi - x.im};
+    }
   }
-  // R slices: thread (column c = tid % 64, rows t = tid / 64 + 4 s)
+  if (bad_any && tid == 0 && id == 0) atomicOr(status, 1);
+  // P stored transposed, W[u][t] = P[t][u]: the k-major A operand of P (.) below
+#pragma unroll
+  for (int e = 0; e < EW; ++e) W[gj][gr + 8 * e] = w[e];
+  __syncthreads();
+  // Row-panel slices with MFMA: Rj = P A_k(:, tile columns), Ri = P A_k(:, tile rows)
   {
-    const int c = tid & 63, g = tid >> 6;
-    z64 rj[NB / 4], ri[NB / 4];
-#pragma unroll
-    for (int s2 = 0; s2 < NB / 4; ++s2) { rj[s2] = z64{0.0, 0.0}; ri[s2] = z64{0.0, 0.0}; }
-    for (int u = 0; u < kn; ++u) {
-      const z64 bj = Bs[u * TS::LDB + c];
-#pragma unroll
-      for (int s2 = 0; s2 < NB / 4; ++s2) {
-        const z64 w = W[g + 4 * s2][u];
-        rj[s2].re += w.re * bj.re - w.im * bj.im;
-        rj[s2].im += w.re * bj.im + w.im * bj.re;
-      }
-    }
+    const int pm0 = (wave % TP::WGM) * TP::WTM, pn0 = (wave / TP::WGM) * TP::WTN;
+    TP::acc_t rj[TP::FM][TP::FN], ri[TP::FM][TP::FN];
+    zero_acc<TP>(rj);
+    tile_mma<double, TP>(&W[0][0], Bs, rj, pm0, pn0, lane);
     if (need_ri) {
-      for (int u = 0; u < kn; ++u) {
-        const z64 bi = As[u * TS::LDA + c];
-#pragma unroll
-        for (int s2 = 0; s2 < NB / 4; ++s2) {
-          const z64 w = W[g + 4 * s2][u];
-          ri[s2].re += w.re * bi.re - w.im * bi.im;
-          ri[s2].im += w.re * bi.im + w.im * bi.re;
-        }
-      }
+      zero_acc<TP>(ri);
+      tile_mma<double, TP>(&W[0][0], As, ri, pm0, pn0, lane);
     }
-    __syncthreads();  // all reads of the raw panels are done
+    __syncthreads();  // every wave is done reading the raw panels
+    double* Bsr = reinterpret_cast<double*>(Bs);
+    double* Rir = reinterpret_cast<double*>(&Ri[0][0]);
 #pragma unroll
-    for (int s2 = 0; s2 < NB / 4; ++s2) {
-      const int t = g + 4 * s2;
-      if (t < kn) {
-        const int gj = n0 + c;
-        Bs[t * TS::LDB + c] = (gj >= k0 && gj < k0 + kn) ? z64{-W[t][gj - k0].re, -W[t][gj - k0].im} : rj[s2];
-        const int gi = m0 + c;
-        if (need_ri) Ri[t][c] = (gi >= k0 && gi < k0 + kn) ? z64{-W[t][gi - k0].re, -W[t][gi - k0].im} : ri[s2];
-        As[t * TS::LDA + c] = cconj(As[t * TS::LDA + c]);
+    for (int fn = 0; fn < TP::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int t = pm0 + Mfma<double>::row(lane, v);
+        const int c = pn0 + fn * 8 + (rc >> 1);
+        const int gjc = n0 + c, gic = m0 + c;
+        // pivot columns take -P
+        const z64 pj = W[(gjc - k0) & (NB - 1)][t];
+        const z64 pi = W[(gic - k0) & (NB - 1)][t];
+        const bool jp = gjc >= k0 && gjc < k0 + kn, ip = gic >= k0 && gic < k0 + kn;
+        Bsr[(t * TS::LDB + c) * 2 + part] = jp ? -(part ? pj.im : pj.re) : rj[0][fn][v];
+        if (need_ri) Rir[(t * (64 + 1) + c) * 2 + part] = ip ? -(part ? pi.im : pi.re) : ri[0][fn][v];
       }
+    // conjugate the raw pivot rows at this tile's rows into the A operand of the update
+#pragma unroll
+    for (int e = 0; e < NB * 64 / 256; ++e) {
+      const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
+      As[t * TS::LDA + c].im = -As[t * TS::LDA + c].im;
     }
   }
   __syncthreads();

@@ -22,13 +22,13 @@ namespace isdf {
 // ----------------------------------------------------------------------------
 // shared K loop: acc += A(m, k) B(k, n) over [0, K) with x-contiguous operands
 // ----------------------------------------------------------------------------
-template <typename T, class TL>
-__device__ __forceinline__ void kloop_xx(cx<T>* smem, const z64* A, long lda, const z64* B, long ldb,
+template <typename T, typename S, class TL>
+__device__ __forceinline__ void kloop_xx(cx<T>* smem, const cx<S>* A, long lda, const cx<S>* B, long ldb,
                                          int m0, int n0, int M, int N, int K, T ca, T cb,
                                          typename TL::acc_t (&acc)[TL::FM][TL::FN], int tid,
                                          int wm0, int wn0, int lane) {
-  Stager<T, double, TL::BM, TL::BK, TL::NT, true> sa;
-  Stager<T, double, TL::BN, TL::BK, TL::NT, true> sb;
+  Stager<T, S, TL::BM, TL::BK, TL::NT, true> sa;
+  Stager<T, S, TL::BN, TL::BK, TL::NT, true> sb;
   const int nk = (K + TL::BK - 1) / TL::BK;
   if (nk == 0) return;
   sa.fetch(A, 1, lda, m0, 0, M, K, tid);
@@ -54,9 +54,9 @@ __device__ __forceinline__ void kloop_xx(cx<T>* smem, const z64* A, long lda, co
   }
 }
 
-template <typename T, typename SO, class TL>
-__global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int ns, const z64* pm,
-                                                       long ldp, const z64* b, long ldb, SO* out,
+template <typename T, typename S, typename SO, class TL>
+__global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int ns, const cx<S>* pm,
+                                                       long ldp, const cx<S>* b, long ldb, SO* out,
                                                        long ldo, int ntm, int total) {
   __shared__ cx<T> smem[2 * (TL::AS + TL::BS)];
   const int id = xcd_remap(blockIdx.x, total);
@@ -69,9 +69,9 @@ __global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int
   typename TL::acc_t accp[TL::FM][TL::FN], accq[TL::FM][TL::FN];
   zero_acc<TL>(accp);
   zero_acc<TL>(accq);
-  kloop_xx<T, TL>(smem, pm, ldp, b, ldb, m0, n0, M, N, nv, (T)-1, (T)1, accp, tid, wm0, wn0, lane);
-  kloop_xx<T, TL>(smem, pm + (long)nv * ldp, ldp, b + (long)nv * ldb, ldb, m0, n0, M, N, ns - nv,
-                  (T)-1, (T)1, accq, tid, wm0, wn0, lane);
+  kloop_xx<T, S, TL>(smem, pm, ldp, b, ldb, m0, n0, M, N, nv, (T)-1, (T)1, accp, tid, wm0, wn0, lane);
+  kloop_xx<T, S, TL>(smem, pm + (long)nv * ldp, ldp, b + (long)nv * ldb, ldb, m0, n0, M, N, ns - nv,
+                     (T)-1, (T)1, accq, tid, wm0, wn0, lane);
 
   const int rc = lane & 15, part = rc & 1;
 #pragma unroll
@@ -91,28 +91,33 @@ __global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int
 }
 
 typedef Tile<double, 64, 64, 16, 2, 2> TZ64;
-typedef Tile<float, 64, 64, 32, 2, 2> TZ32;
+// FP32: 128 points x 64 grid columns per workgroup, 8 waves of 32 x 32
+typedef Tile<float, 128, 64, 16, 4, 2> TZ32;
 
-template <typename T, typename SO, class TL>
+template <typename T, typename S, typename SO, class TL>
 static hipError_t zpair_launch(int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
                                long ldb, void* out, long ldo, hipStream_t st) {
   const int ntm = (int)cdiv(M, TL::BM), ntn = (int)cdiv(N, TL::BN);
   const int total = ntm * ntn;
   if (total == 0) return hipSuccess;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
-  hipLaunchKernelGGL((zpair_kernel<T, SO, TL>), dim3(grid), dim3(TL::NT), 0, st, M, N, nv, ns,
-                     (const z64*)pm, ldp, (const z64*)b, ldb, (SO*)out, ldo, ntm, total);
+  hipLaunchKernelGGL((zpair_kernel<T, S, SO, TL>), dim3(grid), dim3(TL::NT), 0, st, M, N, nv, ns,
+                     (const cx<S>*)pm, ldp, (const cx<S>*)b, ldb, (SO*)out, ldo, ntm, total);
   return hipGetLastError();
 }
 
 hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
-                 long ldb, void* out, long ldo, bool out32, hipStream_t st) {
+                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st) {
   if (compute == P64) {
-    if (out32) return hipErrorInvalidValue;
-    return zpair_launch<double, double, TZ64>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+    if (out32 || in32) return hipErrorInvalidValue;
+    return zpair_launch<double, double, double, TZ64>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
   }
-  if (out32) return zpair_launch<float, float, TZ32>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
-  return zpair_launch<float, double, TZ32>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+  if (in32) {
+    if (out32) return zpair_launch<float, float, float, TZ32>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+    return zpair_launch<float, float, double, TZ32>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+  }
+  if (out32) return zpair_launch<float, double, float, TZ32>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+  return zpair_launch<float, double, double, TZ32>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
 }
 
 // ----------------------------------------------------------------------------
