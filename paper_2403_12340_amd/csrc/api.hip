@@ -7,16 +7,17 @@
 // Pipeline of isdf_eps_inv (paper: eq. ISDF, eq. COmegaCstar, eq. epsilon_with_SMW):
 //   pm   = psi at the points                                  (gather)
 //   S^T  = conj(Pv) * Qc at the points, FP64                  (zpair; S = C C^H)
-//   Sw   = -(S^T)^{-1}, FP64                                  (sweep)
 //   Zt   = (M_vc C^H)^T, N_mu x Nr                            (zpair, mode precision)
-//   ZG   = unitary DFT of the Zt rows on the plane-wave list  (dft_xy, dft_z)
-//   U    = diag(sqrt V) ZG S^{-1}  (= V^{1/2} F Theta: the least-squares fit is
-//          applied after the transform, F (Z S^{-1}) = (F Z) S^{-1})
-//   G    = U^H U                                              (Theta^H V Theta)
-//   per frequency:
+//   X^T  = (V^{1/2} F Z)^T on the plane-wave list              (dft_xy, dft_z)
+//   G    = X^H X                                              (Hermitian GEMM, split-K)
+//   per frequency (side stream, overlapping the above):
 //     M  = f C W C^H                                          (core)
-//     T  = (G - M^{-1})^{-1}, two FP64 Hermitian sweeps       (so (M^{-1} - G)^{-1} = -T)
-//     eps~^{-1} = I - (U T) U^H                               (Hermitian output GEMM)
+//     K  = S M^{-1} S, FP64 sweep of -M and two GEMMs
+//   T  = (G - K)^{-1}, FP64 sweep
+//   eps~^{-1} = I - (X T) X^H                                 (Hermitian output GEMM)
+// Since Theta = Z S^{-1} and U = V^{1/2} F Theta = X S^{-1}, eq. epsilon_with_SMW gives
+//   U (M^{-1} - U^H U)^{-1} U^H = X (S M^{-1} S - X^H X)^{-1} X^H,
+// so the least-squares fit enters only through S M^{-1} S and S^{-1} is never formed.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -38,7 +39,7 @@ struct isdf_handle_s {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t ev[10] = {};         // stage timing (main stream)
-  hipEvent_t fork = nullptr, s_ready = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   hipEvent_t m_ready[2] = {}, m_used[2] = {};
   std::string err;
 };
@@ -112,7 +113,7 @@ struct Layout {
   size_t twx = 0, twy = 0, twz = 0;  // inside tabs
   size_t w1 = 0;                     // aliases the zt region
   size_t zt_bytes = 0;               // size of the zt region
-  size_t part = 0, l2 = 0, lin2 = 0; // core partial sums; second -M buffer and sweep scratch
+  size_t part = 0, l2 = 0, lin2 = 0, q = 0;  // core partials; second -M buffer, sweep scratch, S M^-1 S scratch
   size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (mixed precision only)
   int kx = 0, ky = 0, kz = 0, nd = 0, nsplit = 1;
 };
@@ -152,6 +153,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.l = take(nmu2 * z);
   L.l2 = take(nmu2 * z);
   L.lin2 = take(linalg_scratch_bytes(P.nmu));
+  L.q = take(nmu2 * z);
   L.part = take((size_t)L.nsplit * nmu2 * el);
   L.g = take(nmu2 * z);
   L.gl = take(nmu2 * z);
@@ -340,14 +342,34 @@ isdf_status stage_points(Run& R) {
   return ISDF_OK;
 }
 
-// S^T at the points (FP64) and Sw = -(S^T)^{-1}, on stream st with sweep scratch lin
-isdf_status stage_s(Run& R, hipStream_t st, size_t lin) {
+// S^T = conj(S) at the points (FP64) into the s buffer; with invert, Sw = -(S^T)^{-1} in place
+isdf_status stage_s(Run& R, hipStream_t st, size_t lin, bool invert) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   void* pm = at<char>(R.ws, R.L.pm);
   void* s = at<char>(R.ws, R.L.s);
   HIPCHK(zpair(P64, P.nmu, P.nmu, P.nv, P.ns, pm, P.nmu, pm, P.nmu, false, s, P.nmu, false, st));
-  HIPCHK(sweep_inverse(P.nmu, s, at<char>(R.ws, lin), &R.sb->status, st));
+  if (invert) HIPCHK(sweep_inverse(P.nmu, s, at<char>(R.ws, lin), &R.sb->status, st));
+  return ISDF_OK;
+}
+
+// K = S M^{-1} S in place of M^{-1} (mi), with S = conj(S^T) from the s buffer; q is scratch
+isdf_status stage_smis(Run& R, void* mi, void* q, hipStream_t st) {
+  isdf_handle h = R.h;
+  const int n = R.P.nmu;
+  const void* sk = at<char>(R.ws, R.L.s);
+  GemmDesc a;  // q = M^{-1} S
+  a.M = a.N = a.K = n;
+  a.A = mi; a.sam = n; a.sak = 1;
+  a.B = sk; a.sbk = n; a.sbn = 1; a.conjB = true;
+  a.C = q; a.ldc = n;
+  HIPCHK(gemm(P64, a, st));
+  GemmDesc b;  // mi = S q
+  b.M = b.N = b.K = n;
+  b.A = sk; b.sam = n; b.sak = 1; b.conjA = true;
+  b.B = q; b.sbk = n; b.sbn = 1;
+  b.C = mi; b.ldc = n;
+  HIPCHK(gemm(P64, b, st));
   return ISDF_OK;
 }
 
@@ -385,47 +407,57 @@ DftPlan make_plan(Run& R) {
   return p;
 }
 
-isdf_status stage_dft(Run& R) {
+// Unitary DFT of the N_mu rows of Z^T on the plane-wave list.  With scaled = true the
+// result is X^T = (V^{1/2} F Z)^T, [mu][g] in the zg buffer.
+isdf_status stage_dft(Run& R, bool scaled) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Layout& L = R.L;
   const Prec cp = P.prec == P64 ? P64 : P32;
   DftPlan p = make_plan(R);
   int* ib = at<int>(R.ws, L.idx);
+  HIPCHK(coulomb_sqrt(at<int>(R.ws, L.miller), P.ng, at<double>(R.ws, L.recip), P.v_scale,
+                      at<double>(R.ws, L.sqrtv), R.st));
   HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), R.st));
   HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), R.st));
   HIPCHK(dft_twiddles(ib + L.kx + L.ky, L.kz, P.n2, P.m32, at<char>(R.ws, L.twz), R.st));
   HIPCHK(dft_xy(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), R.st));
-  HIPCHK(dft_z(cp, p, at<char>(R.ws, L.t2), at<char>(R.ws, L.zg), R.st));
+  HIPCHK(dft_z(cp, p, at<char>(R.ws, L.t2), at<char>(R.ws, L.zg), scaled ? at<double>(R.ws, L.sqrtv) : nullptr, R.st));
   return ISDF_OK;
 }
 
+// U = X S^{-1} (stage entry only): U(g, nu) = sum_mu Xt[mu][g] S^{-1}(mu, nu), S^{-1}(mu, nu) = -Sw[nu][mu]
 isdf_status stage_u(Run& R) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Layout& L = R.L;
   const Prec cp = P.prec == P64 ? P64 : P32;
-  HIPCHK(coulomb_sqrt(at<int>(R.ws, L.miller), P.ng, at<double>(R.ws, L.recip), P.v_scale,
-                      at<double>(R.ws, L.sqrtv), R.st));
-  // U(g, nu) = sqrtv_g sum_mu ZG(g, mu) S^{-1}(mu, nu),  S^{-1}(mu, nu) = -Sw[nu][mu]
   GemmDesc d;
   d.M = P.ng; d.N = P.nmu; d.K = P.nmu;
   d.A = at<char>(R.ws, L.zg); d.sam = 1; d.sak = P.ng; d.a32 = P.m32;
   d.B = at<char>(R.ws, L.s); d.sbk = 1; d.sbn = P.nmu;
   d.C = at<char>(R.ws, L.u); d.ldc = P.nmu; d.c32 = P.m32;
-  d.alpha = -1.0; d.row_scale = at<double>(R.ws, L.sqrtv);
+  d.alpha = -1.0;
   HIPCHK(gemm(cp, d, R.st));
   return ISDF_OK;
 }
 
-isdf_status stage_gram(Run& R) {
+// An NG x N_mu plane-wave basis B(g, mu) = base[g * sg + mu * smu] in mode precision:
+// X (from X^T, sg = 1, smu = NG) or U (row-major, sg = N_mu, smu = 1).
+struct Basis {
+  const void* base;
+  long sg, smu;
+};
+
+// G = B^H B (Hermitian, split-K over the plane waves)
+isdf_status stage_gram(Run& R, const Basis& b) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Prec cp = P.prec == P64 ? P64 : P32;
-  GemmDesc d;  // G = U^H U
+  GemmDesc d;
   d.M = d.N = P.nmu; d.K = P.ng;
-  d.A = at<char>(R.ws, R.L.u); d.sam = 1; d.sak = P.nmu; d.conjA = true; d.a32 = P.m32;
-  d.B = at<char>(R.ws, R.L.u); d.sbk = P.nmu; d.sbn = 1; d.b32 = P.m32;
+  d.A = b.base; d.sam = b.smu; d.sak = b.sg; d.conjA = true; d.a32 = P.m32;
+  d.B = b.base; d.sbk = b.sg; d.sbn = b.smu; d.b32 = P.m32;
   d.C = at<char>(R.ws, R.L.g); d.ldc = P.nmu;
   d.herm = true;
   d.split_ws = at<char>(R.ws, R.L.zt);    // Z^T region, free once the DFT has run
@@ -447,11 +479,12 @@ isdf_status stage_core(Run& R, double omega, void* m_out, void* negm, hipStream_
   return ISDF_OK;
 }
 
-// SMW core from -M (in the L buffer) and G = U^H U, all FP64:
-//   M^{-1} = sweep(-M),  H = G - M^{-1} (Hermitian positive definite),
-//   T = H^{-1} = -sweep(H)  (so the SMW kernel (M^{-1} - G)^{-1} = -T),
-//   optional Newton refinement T <- T + T (I - H T) with residuals ||I - H T||_F / sqrt(n).
-// Mi holds M^{-1} (the sweep of -M); `used` (optional) is recorded once Mi has been read.
+// SMW core, all FP64: H = G - K (Hermitian positive definite), T = H^{-1} = -sweep(H),
+// optional Newton refinement T <- T + T (I - H T) with residuals ||I - H T||_F / sqrt(n).
+// With B the plane-wave basis of stage_gram, eps~^{-1} = I - B T B^H.
+//   B = U (= X S^{-1}):  G = U^H U, K = M^{-1}
+//   B = X (= V^{1/2} F Z): G = X^H X, K = S M^{-1} S   (S^{-1} never formed)
+// `used` (optional) is recorded once K has been read.
 isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
@@ -459,7 +492,7 @@ isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   const int n = P.nmu;
   const long n2 = (long)n * n;
   void* H = at<char>(R.ws, L.a);
-  HIPCHK(axpby(at<char>(R.ws, L.g), 1.0, Mi, -1.0, H, n2, R.st));                   // H = G - M^{-1}
+  HIPCHK(axpby(at<char>(R.ws, L.g), 1.0, Mi, -1.0, H, n2, R.st));                   // H = G - K
   if (used) HIPCHK(hipEventRecord(used, R.st));
   HIPCHK(diag_min(H, n, &R.sb->min_pivot, R.st));
   if (P.refine > 0) HIPCHK(convert_z(H, false, at<char>(R.ws, L.acopy), false, n2, R.st));
@@ -494,23 +527,23 @@ isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   return ISDF_OK;
 }
 
-isdf_status stage_out(Run& R, void* out, Timer& tm) {
+isdf_status stage_out(Run& R, const Basis& b, void* out, Timer& tm) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Layout& L = R.L;
   const Prec cp = P.prec == P64 ? P64 : P32;
-  GemmDesc d;  // W1 = U T
+  GemmDesc d;  // W1 = B T
   d.M = P.ng; d.N = P.nmu; d.K = P.nmu;
-  d.A = at<char>(R.ws, L.u); d.sam = P.nmu; d.sak = 1; d.a32 = P.m32;
+  d.A = b.base; d.sam = b.sg; d.sak = b.smu; d.a32 = P.m32;
   d.B = R.tmat; d.sbk = P.nmu; d.sbn = 1;
   d.C = at<char>(R.ws, L.w1); d.ldc = P.nmu; d.c32 = P.m32;
   d.alpha = R.talpha;
   HIPCHK(gemm(cp, d, R.st));
   tm.mark();
-  GemmDesc o;  // eps~^{-1} = I - W1 U^H
+  GemmDesc o;  // eps~^{-1} = I - W1 B^H
   o.M = o.N = P.ng; o.K = P.nmu;
   o.A = at<char>(R.ws, L.w1); o.sam = P.nmu; o.sak = 1; o.a32 = P.m32;
-  o.B = at<char>(R.ws, L.u); o.sbk = 1; o.sbn = P.nmu; o.conjB = true; o.b32 = P.m32;
+  o.B = b.base; o.sbk = b.smu; o.sbn = b.sg; o.conjB = true; o.b32 = P.m32;
   o.C = out; o.ldc = P.ng;
   o.alpha = -1.0; o.diag_add = 1.0; o.herm = true;
   HIPCHK(gemm(cp, o, R.st));
@@ -622,7 +655,7 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
   if (hipSetDevice(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
-  for (hipEvent_t* e : {&h->fork, &h->s_ready, &h->join, &h->m_ready[0], &h->m_ready[1], &h->m_used[0], &h->m_used[1]})
+  for (hipEvent_t* e : {&h->fork, &h->join, &h->m_ready[0], &h->m_ready[1], &h->m_used[0], &h->m_used[1]})
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   // default priority, non-blocking with respect to the legacy default stream
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
@@ -643,7 +676,7 @@ isdf_status isdf_destroy(isdf_handle h) {
     (void)hipStreamDestroy(h->side);
   }
   for (auto& e : h->ev) if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {h->fork, h->s_ready, h->join, h->m_ready[0], h->m_ready[1], h->m_used[0], h->m_used[1]})
+  for (hipEvent_t e : {h->fork, h->join, h->m_ready[0], h->m_ready[1], h->m_used[0], h->m_used[1]})
     if (e) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
@@ -748,10 +781,12 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
   tm.mark();
   TRY(prepare_psi(R, psi));
   TRY(stage_points(R));
-  // Fork: the side stream computes S^{-1} and, per frequency, M and M^{-1}
-  // (double-buffered), while this stream runs Z, the DFT, U and G.  Work is
-  // enqueued frequency by frequency so that every stream wait is enqueued after
-  // the event record it waits for.
+  // Fork: the side stream forms S = C C^H and, per frequency, M, M^{-1} and
+  // K = S M^{-1} S (double-buffered), while this stream runs Z, the DFT to
+  // X = V^{1/2} F Z and X^H X.  Then eps~^{-1} = I - X (X^H X - K)^{-1} X^H, which
+  // equals eq. epsilon_with_SMW with U = X S^{-1}; S^{-1} is never formed.
+  // Work is enqueued frequency by frequency so that every stream wait is
+  // enqueued after the event record it waits for.
   hipStream_t side = h->side;
   HIPCHK(hipEventRecord(h->fork, R.st));
   HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
@@ -761,21 +796,20 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
     if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
     TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
     HIPCHK(sweep_inverse(R.P.nmu, mbuf[k & 1], at<char>(workspace, R.L.lin2), &R.sb->status, side));  // M^{-1}
+    TRY(stage_smis(R, mbuf[k & 1], at<char>(workspace, R.L.q), side));                                 // S M^{-1} S
     HIPCHK(hipEventRecord(h->m_ready[k & 1], side));
     return ISDF_OK;
   };
-  TRY(stage_s(R, side, R.L.lin2));
-  HIPCHK(hipEventRecord(h->s_ready, side));
+  TRY(stage_s(R, side, R.L.lin2, false));
   TRY(side_core(0));
   if (nw > 1) TRY(side_core(1));
   tm.mark();
   TRY(stage_z(R));
   tm.mark();
-  TRY(stage_dft(R));
+  TRY(stage_dft(R, true));
   tm.mark();
-  HIPCHK(hipStreamWaitEvent(R.st, h->s_ready, 0));
-  TRY(stage_u(R));
-  TRY(stage_gram(R));
+  const Basis xb{at<char>(workspace, R.L.zg), 1, (long)ng};
+  TRY(stage_gram(R, xb));
   tm.mark();
   for (int k = 0; k < nw; ++k) {
     Timer dummy{h, false};
@@ -785,7 +819,7 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
     if (k + 2 < nw) TRY(side_core(k + 2));
     t.mark();
     void* out = reinterpret_cast<char*>(eps_inv) + (size_t)k * ng * ng * 16;
-    TRY(stage_out(R, out, t));
+    TRY(stage_out(R, xb, out, t));
     t.mark();
   }
   HIPCHK(hipEventRecord(h->join, side));
@@ -807,7 +841,7 @@ isdf_status isdf_fit_theta(isdf_handle h, const isdf_problem* prob, const void* 
   TRY(clear_status(R));
   TRY(prepare_psi(R, psi));
   TRY(stage_points(R));
-  TRY(stage_s(R, R.st, R.L.lin));
+  TRY(stage_s(R, R.st, R.L.lin, true));
   TRY(stage_z(R));
   const Problem& P = R.P;
   // Theta^T(nu, r) = sum_mu S^{-1}(mu, nu) Zt(mu, r), S^{-1}(mu, nu) = -Sw[nu][mu]
@@ -859,9 +893,9 @@ isdf_status isdf_coulomb_u(isdf_handle h, const isdf_problem* prob, const void* 
   TRY(clear_status(R));
   TRY(prepare_psi(R, psi));
   TRY(stage_points(R));
-  TRY(stage_s(R, R.st, R.L.lin));
+  TRY(stage_s(R, R.st, R.L.lin, true));
   TRY(stage_z(R));
-  TRY(stage_dft(R));
+  TRY(stage_dft(R, true));
   TRY(stage_u(R));
   HIPCHK(convert_z(at<char>(workspace, R.L.u), R.P.m32, u_out, false, (long)ng * n_mu, R.st));
   Timer tm{h, false};
@@ -889,11 +923,12 @@ isdf_status isdf_smw_apply(isdf_handle h, const isdf_problem* prob, const void* 
   HIPCHK(sweep_inverse(n_mu, at<char>(workspace, R.L.l), at<char>(workspace, R.L.lin), &R.sb->status, R.st));
   tm.mark();
   tm.mark();
-  TRY(stage_gram(R));
+  const Basis ub{at<char>(workspace, R.L.u), (long)n_mu, 1};
+  TRY(stage_gram(R, ub));
   tm.mark();
   TRY(stage_core_algebra(R, at<char>(workspace, R.L.l), nullptr));
   tm.mark();
-  TRY(stage_out(R, eps_inv, tm));
+  TRY(stage_out(R, ub, eps_inv, tm));
   tm.mark();
   return finish(R, rep, tm);
 }

@@ -98,52 +98,67 @@ hipError_t dft_twiddles(const int* mlist, int nm, int n, bool f32, void* tw, hip
 // LDS rows are padded to an odd number of complex elements so that lanes
 // reading different rows hit different banks.
 __host__ __device__ inline int odd_pad(int n) { return n | 1; }
+__host__ __device__ inline int up16(int n) { return (n + 15) / 16 * 16; }
+
+// x stage as an MFMA product per slab: T1 (y x a) = Z^T-slab (y x x) . TW^T (x x a),
+// y up to 64 rows (4 waves of 16), a in chunks of 32 columns, x in 16-deep steps.
+template <typename T>
+using TileX = Tile<T, 64, 32, 16, 4, 1>;
 
 template <typename T>
 static size_t xy_lds_bytes(const DftPlan& p) {
-  const size_t s0 = odd_pad(p.n0 + 1) , s1 = odd_pad(p.n1 + 1), sk = odd_pad(p.kx);
-  return sizeof(cx<T>) * ((size_t)p.n1 * s0 + (size_t)p.kx * s0 + (size_t)p.n1 * sk + (size_t)p.ky * s1);
+  typedef TileX<T> TL;
+  const size_t k16 = up16(p.n0), s1 = odd_pad(p.n1 + 1), sk = odd_pad(p.kx);
+  return sizeof(cx<T>) * (k16 * TL::LDA + k16 * TL::LDB + (size_t)p.n1 * sk + (size_t)p.ky * s1);
 }
 
 // one workgroup per (z-plane, point)
 template <typename T>
 __global__ __launch_bounds__(256) void dft_xy_kernel(DftPlan p, const cx<T>* zt, cx<T>* t2) {
+  typedef TileX<T> TL;
   extern __shared__ unsigned char lds_raw[];
-  const int s0 = odd_pad(p.n0 + 1), s1 = odd_pad(p.n1 + 1), sk = odd_pad(p.kx);
-  cx<T>* S = reinterpret_cast<cx<T>*>(lds_raw);          // [n1][s0]   slab Z[z][y][x]
-  cx<T>* TX = S + p.n1 * s0;                             // [kx][s0]   x twiddles
-  cx<T>* T1 = TX + p.kx * s0;                            // [n1][sk]   after the x stage
-  cx<T>* TY = T1 + p.n1 * sk;                            // [ky][s1]   y twiddles
+  const int k16 = up16(p.n0), s1 = odd_pad(p.n1 + 1), sk = odd_pad(p.kx);
+  cx<T>* As = reinterpret_cast<cx<T>*>(lds_raw);   // [x][y] slab, k-major A operand
+  cx<T>* Bs = As + k16 * TL::LDA;                   // [x][a] twiddle chunk, k-major B operand
+  cx<T>* T1 = Bs + k16 * TL::LDB;                   // [y][sk]  after the x stage
+  cx<T>* TY = T1 + p.n1 * sk;                       // [ky][s1] y twiddles
   const int z = blockIdx.x, mu = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long slab = ((long)mu * p.n2 + z) * p.n1 * p.n0;
   const cx<T>* twx = reinterpret_cast<const cx<T>*>(p.twx);
   const cx<T>* twy = reinterpret_cast<const cx<T>*>(p.twy);
-  for (int i = tid; i < p.n0 * p.n1; i += 256) S[(i / p.n0) * s0 + i % p.n0] = zt[slab + i];
-  for (int i = tid; i < p.kx * p.n0; i += 256) TX[(i / p.n0) * s0 + i % p.n0] = twx[i];
-  for (int i = tid; i < p.ky * p.n1; i += 256) TY[(i / p.n1) * s1 + i % p.n1] = twy[i];
+  const cx<T> zero{(T)0, (T)0};
+  for (int i = tid; i < k16 * 64; i += 256) {       // transpose the slab into [x][y], zero padded
+    const int x = i / 64, y = i % 64;
+    As[x * TL::LDA + y] = zero;
+  }
   __syncthreads();
-  // x stage: each thread produces 4 rows y0..y0+3 of one kept frequency a
-  const int ny4 = (p.n1 + 3) / 4;
-  for (int w = tid; w < ny4 * p.kx; w += 256) {
-    const int a = w % p.kx, y0 = (w / p.kx) * 4;
-    const int nr = min(4, p.n1 - y0);
-    T sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
-    const cx<T>* tw = TX + a * s0;
-    for (int x = 0; x < p.n0; ++x) {
-      const cx<T> t = tw[x];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (r < nr) {
-          const cx<T> v = S[(y0 + r) * s0 + x];
-          sr[r] += v.re * t.re - v.im * t.im;
-          si[r] += v.re * t.im + v.im * t.re;
-        }
-      }
+  for (int i = tid; i < p.n0 * p.n1; i += 256) As[(i % p.n0) * TL::LDA + i / p.n0] = zt[slab + i];
+  for (int i = tid; i < p.ky * p.n1; i += 256) TY[(i / p.n1) * s1 + i % p.n1] = twy[i];
+  const int wm0 = wave * TL::WTM;
+  const int rc = lane & 15, part = rc & 1;
+  for (int a0 = 0; a0 < p.kx; a0 += 32) {
+    __syncthreads();
+    for (int i = tid; i < k16 * 32; i += 256) {
+      const int x = i / 32, a = i % 32;
+      const bool ok = x < p.n0 && a0 + a < p.kx;
+      const cx<T> t = twx[ok ? (a0 + a) * p.n0 + x : 0];
+      Bs[x * TL::LDB + a] = cx<T>{ok ? t.re : (T)0, ok ? t.im : (T)0};
     }
+    __syncthreads();
+    typename TL::acc_t acc[TL::FM][TL::FN];
+    zero_acc<TL>(acc);
+    for (int kc = 0; kc < k16; kc += 16)
+      tile_mma<T, TL>(As + kc * TL::LDA, Bs + kc * TL::LDB, acc, wm0, 0, lane);
+    T* T1r = reinterpret_cast<T*>(T1);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (r < nr) T1[(y0 + r) * sk + a] = cx<T>{sr[r], si[r]};
+    for (int fn = 0; fn < TL::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int y = wm0 + Mfma<T>::row(lane, v);
+        const int a = a0 + fn * 8 + (rc >> 1);
+        if (y < p.n1 && a < p.kx) T1r[(y * sk + a) * 2 + part] = acc[0][fn][v];
+      }
   }
   __syncthreads();
   // y stage: only the (x, y) frequency pairs in use
@@ -162,6 +177,7 @@ __global__ __launch_bounds__(256) void dft_xy_kernel(DftPlan p, const cx<T>* zt,
 }
 
 bool dft_supported(int n0, int n1, int kx, int ky, Prec compute) {
+  if (n1 > 64 || n0 > 64) return false;  // one 64-row MFMA tile per slab
   DftPlan p{};
   p.n0 = n0; p.n1 = n1; p.kx = kx; p.ky = ky;
   const size_t bytes = compute == P64 ? xy_lds_bytes<double>(p) : xy_lds_bytes<float>(p);
@@ -187,7 +203,7 @@ hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipS
 }
 
 template <typename T>
-__global__ void dft_z_kernel(DftPlan p, const cx<T>* t2, cx<T>* zg) {
+__global__ void dft_z_kernel(DftPlan p, const cx<T>* t2, cx<T>* zg, const double* scale) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int mu = blockIdx.y;
   if (g >= p.ng) return;
@@ -200,15 +216,17 @@ __global__ void dft_z_kernel(DftPlan p, const cx<T>* t2, cx<T>* zg) {
     sr += v.re * twz[z].re - v.im * twz[z].im;
     si += v.re * twz[z].im + v.im * twz[z].re;
   }
-  zg[(long)mu * p.ng + g] = cx<T>{sr, si};
+  const T sc = scale ? (T)scale[g] : (T)1;
+  zg[(long)mu * p.ng + g] = cx<T>{sr * sc, si * sc};
 }
 
-hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, hipStream_t st) {
+hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, const double* scale,
+                 hipStream_t st) {
   const dim3 grid(cdiv(p.ng, 256), p.nmu);
   if (compute == P64)
-    hipLaunchKernelGGL((dft_z_kernel<double>), grid, dim3(256), 0, st, p, (const z64*)t2, (z64*)zg);
+    hipLaunchKernelGGL((dft_z_kernel<double>), grid, dim3(256), 0, st, p, (const z64*)t2, (z64*)zg, scale);
   else
-    hipLaunchKernelGGL((dft_z_kernel<float>), grid, dim3(256), 0, st, p, (const c32*)t2, (c32*)zg);
+    hipLaunchKernelGGL((dft_z_kernel<float>), grid, dim3(256), 0, st, p, (const c32*)t2, (c32*)zg, scale);
   return hipGetLastError();
 }
 

@@ -69,9 +69,10 @@ struct DftPlan {
   const int* g_d;          // ng: pair index of plane wave g
   const int* g_cz;         // ng: index into twz list of plane wave g
 };
-// zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][n2][nd] -> zg: [nmu][ng]
+// zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][n2][nd] -> zg: [nmu][ng] (times scale[g] if given)
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);
-hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, hipStream_t st);
+hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, const double* scale,
+                 hipStream_t st);
 bool dft_supported(int n0, int n1, int kx, int ky, Prec compute);  // LDS fits
 
 hipError_t conj_transpose(int n, const void* a, void* at, hipStream_t st);   // at = a^H (z64)
