@@ -9,7 +9,15 @@ orbitals (seeded synthetic inputs, see synth/).  The headline value is the
 mixed path (FP32 MFMA contractions, FP64 core); the FP64 path is timed beside
 it, and both are compared with the FP64 CPU oracle.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--only fp32|fp64]
+    python bench.py --summarize KERNEL_TRACE_DB [--pmc-fetch DB --pmc-write DB]
+
+The --summarize mode turns rocprofv3 databases (rocpd SQLite) into the text
+summaries kept under profiles/: per-kernel dispatch count and average / total
+duration, and, given the FETCH_SIZE and WRITE_SIZE counter runs, the HBM bytes
+per dispatch of the pair-Gram kernel, calibrated against the complex128 ->
+complex64 copy of the orbitals (a plain streaming kernel of known size) that
+runs in the same process.
 """
 from __future__ import annotations
 
@@ -29,27 +37,129 @@ HBM_PEAK = 8000.0                       # GB/s
 
 
 def flops_model(inp):
-    """Algorithmic flops per build (complex MAC = 8 real flops), per stage."""
+    """Algorithmic flops per build (complex MAC = 8 real flops), per step of the path."""
     nr, nv, nc, nmu, ng = inp.nr, inp.nv, inp.nc, inp.nmu, inp.ng
     n = nv + nc
+    kx = len(np.unique(inp.miller[:, 0]))
+    nd = len(np.unique(inp.miller[:, :2], axis=0))
     return {
-        "zpair": 8.0 * nmu * nr * n,                 # Z = conj(Pv) * Qc, both Gram blocks
-        "core": 8.0 * nmu * nmu * nv * nc / 2,        # HERK half of f C W C^H
-        "u": 8.0 * ng * nmu * nmu,                    # U = sqrt(V) ZG S^-1
-        "gram": 8.0 * ng * nmu * nmu / 2,             # U^H U (HERK half)
-        "w1": 8.0 * ng * nmu * nmu,                   # U T
-        "out": 8.0 * ng * ng * nmu / 2,               # I - W1 U^H (Hermitian half)
+        "zpair": 8.0 * nmu * nr * n,                  # Z = conj(Pv) * Qc: both pair Grams over the grid
+        "s": 8.0 * nmu * nmu * n,                     # S = C C^H (Hadamard form)
+        "core": 8.0 * nmu * nmu * nv * nc / 2,        # M = f C W C^H, Hermitian half
+        "dft": 8.0 * nmu * inp.n * (inp.n * inp.n * kx + inp.n * nd + ng),  # pruned x, y, z stages
+        "gram": 8.0 * ng * nmu * nmu / 2,             # X^H X, Hermitian half
+        "inverses": 8.0 * 2 * nmu ** 3,               # M^{-1} and H^{-1} (Gauss-Jordan sweeps)
+        "k": 8.0 * 2 * nmu ** 3,                      # K = S M^{-1} S
+        "w": 8.0 * ng * nmu * nmu,                    # W = X H^{-1}
+        "out": 8.0 * ng * ng * nmu / 2,               # I - W X^H, Hermitian half
     }
+
+
+ZPAIR_SOURCES = ["zpair.hip", "tile.h", "common.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zpair_fp32_48cubed_nmu640_traffic.txt")
+
+
+def zpair_source_hash():
+    """SHA-256 over the sources the pair-Gram kernel is compiled from."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in ZPAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_2403_12340_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the pair-Gram kernel from the committed counter summary,
+    or None when the kernel's sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for ln in fh:
+            parts = ln.split()
+            if len(parts) == 2 and parts[0] in ("TRAFFIC_BYTES_PER_LAUNCH", "SOURCE_SHA256"):
+                vals[parts[0]] = parts[1]
+    if vals.get("SOURCE_SHA256") != zpair_source_hash() or "TRAFFIC_BYTES_PER_LAUNCH" not in vals:
+        return None
+    return float(vals["TRAFFIC_BYTES_PER_LAUNCH"])
+
+
+def _kernel_stats(db):
+    import sqlite3
+    c = sqlite3.connect(db)
+    return c.execute("select name, count(*), avg(end - start), sum(end - start) from kernels "
+                     "group by name order by sum(end - start) desc").fetchall()
+
+
+def _pmc_per_dispatch(db, counter):
+    """[(kernel name, grid size, counter value)] per dispatch from a rocprofv3 --pmc database."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    cols = [r[1] for r in c.execute("pragma table_info(counters_collection)")]
+    rows = c.execute("select * from counters_collection").fetchall()
+    out = []
+    for r in rows:
+        d = dict(zip(cols, r))
+        name = d.get("kernel_name") or d.get("name")
+        cname = d.get("counter_name")
+        if cname is not None and cname != counter:
+            continue
+        grid = d.get("grid_size") or d.get("grid_size_x") or d.get("grid_x") or 0
+        out.append((name, int(grid or 0), float(d.get("value") or d.get("counter_value") or 0.0)))
+    return out
+
+
+def summarize(args):
+    lines = []
+    stats = _kernel_stats(args.summarize)
+    tot = sum(r[3] for r in stats) or 1
+    lines.append(f"kernel trace: {args.summarize}")
+    lines.append(f"{'kernel':<100} {'calls':>6} {'avg_us':>10} {'total_ms':>10} {'share':>6}")
+    for name, cnt, avg, ssum in stats[:30]:
+        lines.append(f"{name[:100]:<100} {cnt:>6} {avg / 1e3:>10.1f} {ssum / 1e6:>10.3f} {100 * ssum / tot:>5.1f}%")
+    if args.pmc_fetch and args.pmc_write:
+        import synth
+        inp = synth.make_inputs(args.config) if args.config else None
+        res = {}
+        for key, db, ctr in (("fetch", args.pmc_fetch, "FETCH_SIZE"), ("write", args.pmc_write, "WRITE_SIZE")):
+            rows = _pmc_per_dispatch(db, ctr)
+            copy = [v for n, g, v in rows if "convert_kernel<double, float>" in n]
+            zp = [v for n, g, v in rows if "zpair_kernel<float" in n and g > 1 << 20]
+            res[key] = (max(copy) if copy else None, sum(zp) / len(zp) if zp else None, len(zp))
+        nbytes = inp.nv + inp.nc
+        exp_fetch = nbytes * inp.nr * 16.0   # copy reads complex128
+        exp_write = nbytes * inp.nr * 8.0    # and writes complex64
+        f_fetch = exp_fetch / (res["fetch"][0] * 1024.0)
+        f_write = exp_write / (res["write"][0] * 1024.0)
+        zf = res["fetch"][1] * 1024.0 * f_fetch
+        zw = res["write"][1] * 1024.0 * f_write
+        lines.append("")
+        lines.append(f"HBM traffic of zpair_kernel<float> (pair-Gram, {args.config}), from FETCH_SIZE / WRITE_SIZE (KiB per dispatch)")
+        lines.append(f"  calibration copy (orbitals complex128 -> complex64): expected fetch {exp_fetch:.4e} B, "
+                     f"write {exp_write:.4e} B; counter factors fetch {f_fetch:.4f}, write {f_write:.4f}")
+        lines.append(f"  zpair dispatches: {res['fetch'][2]} / {res['write'][2]}; calibrated fetch {zf:.4e} B, write {zw:.4e} B, "
+                     f"total {zf + zw:.4e} B per dispatch")
+        lines.append(f"TRAFFIC_BYTES_PER_LAUNCH {zf + zw:.6e}")
+        lines.append(f"SOURCE_SHA256 {zpair_source_hash()}")
+    print("\n".join(lines))
 
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--summarize", default=None, help="rocpd database of a --kernel-trace run")
+    ap.add_argument("--pmc-fetch", default=None)
+    ap.add_argument("--pmc-write", default=None)
+    ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
@@ -66,7 +176,7 @@ def main():
     psi = torch.from_numpy(inp.psi_t).to(dev)
     results = {}
     outs = {}
-    for prec in ("fp32", "fp64"):
+    for prec in (("fp32", "fp64") if args.only is None else (args.only,)):
         prob = isdf.problem_for(inp, prec=prec)
         nbytes = isdf.workspace_bytes(prob, inp.nmu, inp.ng, 0)
         ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
@@ -92,15 +202,20 @@ def main():
         print(f"[bench] {prec}: {dt * 1e3:.3f} ms/build  stages(ms) {np.round(stages, 3).tolist()}",
               file=sys.stderr, flush=True)
 
+    if args.only is not None:
+        print(json.dumps({"only": args.only, **results[args.only]}))
+        return
     fl = flops_model(inp)
     total_flops = sum(fl.values())
     m = results["fp32"]
-    # dominant kernel: the pair-Gram kernel (stage 1 = Z) in the mixed path
+    # dominant kernel: the pair-Gram kernel; stage 1 brackets exactly its one launch
+    # (HIP events on the library's stream, the stream the kernel runs on)
     z_ms = m["stage_ms"][1]
     achieved = fl["zpair"] / (z_ms * 1e-3) / 1e12
-    roofline = {"kernel": "zpair_kernel<float> (Z = conj(Pv) * Qc, N_mu x Nr x N)", "bound": "mfma",
+    traffic = recorded_traffic()
+    roofline = {"kernel": "zpair_kernel<float> (Z = conj(Pv) * Qc over N_mu x Nr x (Nv + Nc))", "bound": "mfma",
                 "achieved": round(achieved, 2), "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK["fp32"], 4), "traffic": None,
+                "frac": round(achieved / PEAK["fp32"], 4), "traffic": traffic,
                 "flops_per_launch": fl["zpair"], "avg_ms": round(z_ms, 4)}
     z64_ms = results["fp64"]["stage_ms"][1]
     fp64_z = fl["zpair"] / (z64_ms * 1e-3) / 1e12
@@ -148,9 +263,9 @@ def main():
                                "fp64": round(total_flops / (results["fp64"]["ms_per_step"] * 1e-3) / 1e12, 2)},
         "stage_ms": {"mixed": [round(x, 4) for x in m["stage_ms"]],
                      "fp64": [round(x, 4) for x in results["fp64"]["stage_ms"]],
-                     "names": ["gather", "Z", "DFT", "U+G (waits S^-1)", "FP64 core solve (waits M^-1)",
-                               "U T", "output", "-"],
-                     "note": "intervals on the caller's stream; S^-1, M and M^-1 overlap on a side stream"},
+                     "names": ["gather + operand conversion", "Z (pair-Gram kernel)", "DFT to X", "X^H X",
+                               "core solve (waits for K = S M^-1 S)", "W = X H^-1", "output", "-"],
+                     "note": "intervals on the caller's stream; S, M, M^-1 and K run on a second stream"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -83,12 +83,18 @@ typedef struct {
 } isdf_problem;
 
 typedef struct {
-  double stage_ms[8];        /* filled when want_timing != 0, intervals on the caller's stream:
-                                gather, Z, DFT, U and U^H U (incl. waiting for S^{-1}),
-                                FP64 core solve (incl. waiting for M^{-1}), U T, output, unused.
-                                S^{-1}, M and M^{-1} run concurrently on a library-owned stream. */
+  double stage_ms[8];        /* filled when want_timing != 0: HIP-event intervals on the caller's stream.
+                                isdf_eps_inv: [0] point gather and operand conversion, [1] the pair
+                                product Z (exactly one kernel launch), [2] DFT to X = V^{1/2} F Z,
+                                [3] X^H X, [4] core solve (waits for K = S M^{-1} S from the
+                                library's second stream, H = X^H X - K, H^{-1}, refinement),
+                                [5] W = X H^{-1}, [6] output, [7] unused.
+                                S, M, M^{-1} and K run concurrently on a library-owned stream.
+                                isdf_smw_apply: [0] input conversion and M^{-1}, [1] zero,
+                                [2] U^H U, [3] core solve, [4] U T, [5] output. */
   double refine_residual[9]; /* ||I - H T_k||_F / sqrt(N_mu) for k = 0..refine_steps (last frequency),
-                                H = U^H U - M^{-1}, T_k the k-th Newton-refined H^{-1} */
+                                T_k the k-th Newton-refined H^{-1}; H = X^H X - S M^{-1} S
+                                (isdf_eps_inv) or U^H U - M^{-1} (isdf_smw_apply) */
   double min_pivot;          /* smallest diagonal entry of H (last frequency) */
   int32_t want_timing;       /* input: 1 to record per-stage HIP events (adds host syncs) */
   int32_t n_refine_reported; /* number of valid refine_residual entries */

@@ -373,6 +373,18 @@ isdf_status stage_smis(Run& R, void* mi, void* q, hipStream_t st) {
   return ISDF_OK;
 }
 
+// Operands of the pair product.  Mixed precision: one streaming pass to complex64
+// halves the bytes the contraction reads.
+isdf_status stage_z_operands(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  if (P.prec == P64) return ISDF_OK;
+  HIPCHK(convert_z(R.psi, false, at<char>(R.ws, R.L.psi32), true, (long)P.ns * P.nr, R.st));
+  HIPCHK(convert_z(at<char>(R.ws, R.L.pm), false, at<char>(R.ws, R.L.pm32), true, (long)P.ns * P.nmu, R.st));
+  return ISDF_OK;
+}
+
+// Z^T [mu][r] by the pair-Gram kernel (one launch).
 isdf_status stage_z(Run& R) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
@@ -381,9 +393,6 @@ isdf_status stage_z(Run& R) {
                  at<char>(R.ws, R.L.zt), P.nr, false, R.st));
     return ISDF_OK;
   }
-  // mixed: one pass to complex64 halves the bytes the contraction streams
-  HIPCHK(convert_z(R.psi, false, at<char>(R.ws, R.L.psi32), true, (long)P.ns * P.nr, R.st));
-  HIPCHK(convert_z(at<char>(R.ws, R.L.pm), false, at<char>(R.ws, R.L.pm32), true, (long)P.ns * P.nmu, R.st));
   HIPCHK(zpair(P32, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm32), P.nmu, at<char>(R.ws, R.L.psi32),
                P.nr, true, at<char>(R.ws, R.L.zt), P.nr, true, R.st));
   return ISDF_OK;
@@ -803,6 +812,7 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
   TRY(stage_s(R, side, R.L.lin2, false));
   TRY(side_core(0));
   if (nw > 1) TRY(side_core(1));
+  TRY(stage_z_operands(R));
   tm.mark();
   TRY(stage_z(R));
   tm.mark();
@@ -842,6 +852,7 @@ isdf_status isdf_fit_theta(isdf_handle h, const isdf_problem* prob, const void* 
   TRY(prepare_psi(R, psi));
   TRY(stage_points(R));
   TRY(stage_s(R, R.st, R.L.lin, true));
+  TRY(stage_z_operands(R));
   TRY(stage_z(R));
   const Problem& P = R.P;
   // Theta^T(nu, r) = sum_mu S^{-1}(mu, nu) Zt(mu, r), S^{-1}(mu, nu) = -Sw[nu][mu]
@@ -894,6 +905,7 @@ isdf_status isdf_coulomb_u(isdf_handle h, const isdf_problem* prob, const void* 
   TRY(prepare_psi(R, psi));
   TRY(stage_points(R));
   TRY(stage_s(R, R.st, R.L.lin, true));
+  TRY(stage_z_operands(R));
   TRY(stage_z(R));
   TRY(stage_dft(R, true));
   TRY(stage_u(R));
