@@ -162,7 +162,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+              "sharding across GPUs is a design note, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

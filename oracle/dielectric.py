@@ -23,7 +23,7 @@ density fitting"):
     Delta / (Delta^2 + omega^2), Delta = eps_i - eps_j; at omega = 0 this is
     1 / Delta, the static Omega^{-1}.
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
   * quadrature weights are dropped as in the paper (Sec. 2), the grid DFT is
     unitary, and v_scale = Nr / Omega_cell restores the grid-independent
     physical screening for unit-norm grid orbitals;

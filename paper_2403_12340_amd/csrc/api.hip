@@ -108,7 +108,7 @@ DftIndex dft_index(const int32_t* miller, int ng) {
 // Workspace layout.  Offsets in bytes from the workspace base.
 struct Layout {
   size_t psi_c = 0, pm = 0, mu = 0, e = 0, w = 0, s = 0, lin = 0, zt = 0, tabs = 0, t2 = 0, zg = 0,
-         u = 0, l = 0, g = 0, gl = 0, a = 0, acopy = 0, lh = 0, x = 0, rres = 0, t = 0, status = 0,
+         u = 0, l = 0, g = 0, a = 0, acopy = 0, x = 0, rres = 0, t = 0, status = 0,
          miller = 0, recip = 0, sqrtv = 0, idx = 0, total = 0;
   size_t twx = 0, twy = 0, twz = 0;  // inside tabs
   size_t w1 = 0;                     // aliases the zt region
@@ -156,14 +156,11 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.q = take(nmu2 * z);
   L.part = take((size_t)L.nsplit * nmu2 * el);
   L.g = take(nmu2 * z);
-  L.gl = take(nmu2 * z);
   L.a = take(nmu2 * z);
   L.acopy = take(nmu2 * z);
-  L.lh = take(nmu2 * z);
   L.x = take(nmu2 * z);
   L.rres = take(nmu2 * z);
   L.t = take(nmu2 * z);
-  // big region: Zt (N_mu x Nr), later reused for the core partial sums and U T
   // big region: Zt (N_mu x Nr); once the DFT has consumed it, reused for the
   // split-K partial sums of U^H U and for U T
   const size_t zt_bytes = (size_t)P.nmu * P.nr * el;

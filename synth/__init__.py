@@ -10,7 +10,7 @@ are not available, so these stand in for them with the same ratios:
 Nr / Ne between 100 and 1000 (abstract) and N_mu = k_mu sqrt(Nv Nc) with
 k_mu of order ten (ISDF section).
 
-Recipe (the same in the design doc):
+Recipe:
   * grid: n^3 points in a cubic box of side L = 10.26 (Nv/8)^(1/3) Bohr
     (the Si conventional cell at constant density); grid index
     k = i0 + n*(i1 + n*i2), i0 fastest (x).
