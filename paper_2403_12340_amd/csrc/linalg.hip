@@ -1,7 +1,7 @@
 // FP64 dense algebra on the N_mu x N_mu core (row-major complex128, ld = n).
 //
 //   sweep_inverse  blocked Gauss-Jordan sweep of a Hermitian positive definite
-//                  matrix, A <- -A^{-1}, one kernel per 32-wide pivot block.
+//                  matrix, A <- -A^{-1}, two kernels per 32-wide pivot block.
 // A non-positive or non-finite pivot sets bit 0 of *status (ISDF_E_NOT_PD);
 // the pivots of a Hermitian positive definite matrix stay positive throughout.
 #include "internal.h"
@@ -13,181 +13,186 @@ namespace isdf {
 
 constexpr int NB = 32;
 
-// 1 / z via the hardware reciprocal of |z|^2 refined by two Newton steps
-// (relative error at the level of a few ulp, ample for pivots of a Hermitian
-// positive definite elimination).
-__device__ __forceinline__ z64 zrcp(z64 z) {
-  const double s = z.re * z.re + z.im * z.im;
-  double x = __builtin_amdgcn_rcp(s);
-  x = x * (2.0 - s * x);
-  x = x * (2.0 - s * x);
-  return z64{z.re * x, -z.im * x};
+// 1 / x for a positive pivot: hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double drcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  r = r * (2.0 - x * r);
+  return r;
 }
 
-__device__ __forceinline__ z64 zdiv(z64 a, z64 b) {
-  const double d = b.re * b.re + b.im * b.im;
-  return z64{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
-}
-
-// One pivot step of the sweep as a single kernel.  With pivot rows
-// k = [k0, k0 + kn) and P = A_kk^{-1}, the swept matrix is
-//   A'_kj = P A_kj (j outside k),  A'_ik = A_ik P = (P A_ki)^H (i outside k),
-//   A'_kk = -P,  A'_ij = A_ij - A_ik P A_kj = A_ij - conj(A_ki)^T (P A_kj).
-// Every workgroup owns one 64 x 64 output tile: it inverts the pivot block in
-// LDS by Gauss-Jordan (no pivoting: Hermitian positive definite), forms the
-// slices of R = P A_k: it needs, and applies the rank-kn update with MFMA.
-// Input and output are different buffers, so no workgroup reads what another
-// one writes.
-typedef Tile<double, 64, 64, NB, 2, 2> TS;
+// One 32-pivot step of the sweep is two kernels.  With pivot rows
+// k = [k0, k0 + kn), P = A_kk^{-1} and R = P A_k: (kn x n),
+//   A'_kj = R_j (j outside k),  A'_kk = -P,
+//   A'_ik = A_ik P = (P A_ki)^H = R_i^H (i outside k; A stays Hermitian),
+//   A'_ij = A_ij - A_ik P A_kj = A_ij - sum_t conj(A[k0 + t][i]) R[t][j].
+// sweep_panel_kernel writes the pivot rows and columns of A' (one workgroup per
+// 64-column block), sweep_update_kernel the rest.  Input and output are
+// different buffers, so no workgroup reads what another one writes.
+//
+// The pivot block is inverted by in-register Gauss-Jordan.  After pivots
+// 0..p-1 the working block B satisfies B[r][j] = s conj(B[j][r]) with s = -1
+// exactly when one of r, j is already a pivot, so row p alone carries what
+// every thread needs: the column value is B[r][p] = s conj(B[p][r]).  One row
+// broadcast and one barrier per pivot.
 typedef Tile<double, NB, 64, NB, 2, 2> TP;   // P (NB x NB, k-major in W) times a NB x 64 panel
 
-__global__ __launch_bounds__(256) void sweep_step_kernel(int n, const z64* __restrict__ ain,
-                                                         z64* __restrict__ aout, int k0, int kn,
-                                                         int* status, int ntm, int total) {
-  __shared__ z64 W[NB][NB + 1];   // P = inverse of the (identity-padded) pivot block
-  __shared__ z64 rowb[2][NB], colb[2][NB];
-  __shared__ z64 As[TS::AS];   // [t][i] = conj(A[k0 + t][m0 + i])   (A operand, k-major)
-  __shared__ z64 Bs[TS::BS];   // [t][j] = (P A_k:)[t][n0 + j]        (B operand, k-major)
-  __shared__ z64 Ri[NB][64 + 1];  // (P A_k:)[t][m0 + i], only for tiles meeting the pivot columns
-  const int id = xcd_remap(blockIdx.x, total);
-  if (id >= total) return;
-  const int bm = id % ntm, bn = id / ntm;
-  const int m0 = bm * 64, n0 = bn * 64;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_panel_kernel(int n, const z64* __restrict__ ain,
+                                                          z64* __restrict__ aout, int k0, int kn,
+                                                          int* status) {
+  __shared__ z64 W[NB][NB + 1];      // W[u][t] = P[t][u]: the k-major A operand of P (.)
+  __shared__ z64 rowb[2][NB];        // pivot row broadcast, double-buffered
+  __shared__ z64 Bs[NB * (64 + 1)];  // pivot rows at this block's columns, then R
+  const int c0 = blockIdx.x * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool need_ri = (n0 < k0 + kn) && (n0 + 64 > k0);
-  const int wm0 = (wave % TS::WGM) * TS::WTM, wn0 = (wave / TS::WGM) * TS::WTN;
-  const int rc = lane & 15, part = rc & 1;
-  const double* ainr = reinterpret_cast<const double*>(ain);
-
-  // this lane's old tile values, loaded first so their latency hides behind the pivot inversion
-  double cold[TS::FM][TS::FN][4];
-#pragma unroll
-  for (int fm = 0; fm < TS::FM; ++fm)
-#pragma unroll
-    for (int fn = 0; fn < TS::FN; ++fn)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm0 + fm * 16 + Mfma<double>::row(lane, v);
-        const int col = n0 + wn0 + fn * 8 + (rc >> 1);
-        const long off = (row < n && col < n) ? ((long)row * n + col) * 2 + part : 0;
-        cold[fm][fn][v] = ainr[off];
-      }
-  // pivot block: thread owns column j = tid % 32 of rows r_e = tid / 32 + 8 e (registers)
+  // pivot block first: Gauss-Jordan waits only for these loads.
+  // Thread owns column gj of rows gr + 8 e (identity padding beyond kn).
   constexpr int EW = NB * NB / 256;
   const int gj = tid % NB, gr = tid / NB;
   z64 w[EW];
 #pragma unroll
   for (int e = 0; e < EW; ++e) {
     const int r = gr + 8 * e;
-    w[e] = (r < kn && gj < kn) ? ain[(long)(k0 + r) * n + k0 + gj] : z64{r == gj ? 1.0 : 0.0, 0.0};
+    const bool ok = r < kn && gj < kn;
+    const z64 v = ain[ok ? (long)(k0 + r) * n + k0 + gj : 0];
+    w[e] = ok ? v : z64{r == gj ? 1.0 : 0.0, 0.0};
   }
-  // raw pivot rows at this tile's columns (into Bs) and rows (into As, conjugated later)
+  // raw pivot rows at this block's columns, kept in registers until the inversion is done
+  constexpr int EB = NB * 64 / 256;
+  z64 braw[EB];
 #pragma unroll
-  for (int e = 0; e < NB * 64 / 256; ++e) {
+  for (int e = 0; e < EB; ++e) {
     const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
-    z64 vj{0.0, 0.0}, vi{0.0, 0.0};
-    if (t < kn) {
-      if (n0 + c < n) vj = ain[(long)(k0 + t) * n + n0 + c];
-      if (m0 + c < n) vi = ain[(long)(k0 + t) * n + m0 + c];
-    }
-    Bs[t * TS::LDB + c] = vj;
-    As[t * TS::LDA + c] = vi;
+    const bool ok = t < kn && c0 + c < n;
+    braw[e] = ain[ok ? (long)(k0 + t) * n + c0 + c : 0];
   }
-  // Gauss-Jordan in registers: per pivot, the owners publish row p and column p
-  // (double-buffered), one barrier, then every thread updates its own elements.
   bool bad_any = false;
-#pragma unroll 1
+#pragma unroll
   for (int p = 0; p < NB; ++p) {
     const int b = p & 1;
-#pragma unroll
-    for (int e = 0; e < EW; ++e) {
-      if (gr + 8 * e == p) rowb[b][gj] = w[e];
-      if (gj == p) colb[b][gr + 8 * e] = w[e];
-    }
+    if (gr == (p & 7)) rowb[b][gj] = w[p >> 3];
     __syncthreads();
-    const z64 piv = rowb[b][p];
-    const bool bad = !(piv.re > 0.0) || !isfinite(piv.re) || !isfinite(piv.im);
+    const double piv = rowb[b][p].re;
+    const bool bad = !(piv > 0.0) || !isfinite(piv);
     bad_any |= bad;
-    const z64 d = bad ? z64{1.0, 0.0} : zrcp(piv);
+    const double d = bad ? 1.0 : drcp(piv);
     const z64 rv = rowb[b][gj];
-    const z64 rs = cmul(rv, d);
-    const z64 rj = (gj == p) ? d : rs;   // scaled pivot row at this thread's column
-    z64 cv[EW];
-#pragma unroll
-    for (int e = 0; e < EW; ++e) cv[e] = colb[b][gr + 8 * e];
+    const z64 rj = (gj == p) ? z64{d, 0.0} : z64{rv.re * d, rv.im * d};  // scaled pivot row here
 #pragma unroll
     for (int e = 0; e < EW; ++e) {
-      const z64 x = cmul(cv[e], rj);
+      const int r = gr + 8 * e;
+      const z64 pr = rowb[b][r];                 // B[p][r]
+      const double sg = (r < p) ? -1.0 : 1.0;    // B[r][p] = sg conj(B[p][r])
+      const z64 cv{sg * pr.re, -sg * pr.im};
+      const z64 x = cmul(cv, rj);
       const double br = (gj == p) ? 0.0 : w[e].re, bi = (gj == p) ? 0.0 : w[e].im;
-      const bool own = (gr + 8 * e == p);
+      const bool own = (r == p);
       w[e] = z64{own ? rj.re : br - x.re, own ? rj.im : bi - x.im};
     }
   }
-  if (bad_any && tid == 0 && id == 0) atomicOr(status, 1);
-  // P stored transposed, W[u][t] = P[t][u]: the k-major A operand of P (.) below
+  if (bad_any && tid == 0 && blockIdx.x == 0) atomicOr(status, 1);
 #pragma unroll
   for (int e = 0; e < EW; ++e) W[gj][gr + 8 * e] = w[e];
-  __syncthreads();
-  // Row-panel slices with MFMA: Rj = P A_k(:, tile columns), Ri = P A_k(:, tile rows)
-  {
-    const int pm0 = (wave % TP::WGM) * TP::WTM, pn0 = (wave / TP::WGM) * TP::WTN;
-    TP::acc_t rj[TP::FM][TP::FN], ri[TP::FM][TP::FN];
-    zero_acc<TP>(rj);
-    tile_mma<double, TP>(&W[0][0], Bs, rj, pm0, pn0, lane);
-    if (need_ri) {
-      zero_acc<TP>(ri);
-      tile_mma<double, TP>(&W[0][0], As, ri, pm0, pn0, lane);
-    }
-    __syncthreads();  // every wave is done reading the raw panels
-    double* Bsr = reinterpret_cast<double*>(Bs);
-    double* Rir = reinterpret_cast<double*>(&Ri[0][0]);
 #pragma unroll
-    for (int fn = 0; fn < TP::FN; ++fn)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int t = pm0 + Mfma<double>::row(lane, v);
-        const int c = pn0 + fn * 8 + (rc >> 1);
-        const int gjc = n0 + c, gic = m0 + c;
-        // pivot columns take -P
-        const z64 pj = W[(gjc - k0) & (NB - 1)][t];
-        const z64 pi = W[(gic - k0) & (NB - 1)][t];
-        const bool jp = gjc >= k0 && gjc < k0 + kn, ip = gic >= k0 && gic < k0 + kn;
-        Bsr[(t * TS::LDB + c) * 2 + part] = jp ? -(part ? pj.im : pj.re) : rj[0][fn][v];
-        if (need_ri) Rir[(t * (64 + 1) + c) * 2 + part] = ip ? -(part ? pi.im : pi.re) : ri[0][fn][v];
-      }
-    // conjugate the raw pivot rows at this tile's rows into the A operand of the update
-#pragma unroll
-    for (int e = 0; e < NB * 64 / 256; ++e) {
-      const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
-      As[t * TS::LDA + c].im = -As[t * TS::LDA + c].im;
-    }
+  for (int e = 0; e < EB; ++e) {
+    const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
+    const bool ok = t < kn && c0 + c < n;
+    Bs[t * (64 + 1) + c] = ok ? braw[e] : z64{0.0, 0.0};
   }
   __syncthreads();
-  TS::acc_t acc[TS::FM][TS::FN];
-  zero_acc<TS>(acc);
-  tile_mma<double, TS>(As, Bs, acc, wm0, wn0, lane);
+  // R = P A_k(:, block columns) with MFMA
+  const int pm0 = (wave % TP::WGM) * TP::WTM, pn0 = (wave / TP::WGM) * TP::WTN;
+  const int rc = lane & 15, part = rc & 1;
+  TP::acc_t racc[TP::FM][TP::FN];
+  zero_acc<TP>(racc);
+  tile_mma<double, TP>(&W[0][0], Bs, racc, pm0, pn0, lane);
+  __syncthreads();  // every wave is done reading the raw panel
+  double* Bsr = reinterpret_cast<double*>(Bs);
+#pragma unroll
+  for (int fn = 0; fn < TP::FN; ++fn)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int t = pm0 + Mfma<double>::row(lane, v);
+      const int c = pn0 + fn * 8 + (rc >> 1);
+      const int gc = c0 + c;
+      const bool piv_col = gc >= k0 && gc < k0 + kn;
+      const z64 pv = W[(gc - k0) & (NB - 1)][t];  // P[t][gc - k0]
+      Bsr[(t * (64 + 1) + c) * 2 + part] = piv_col ? -(part ? pv.im : pv.re) : racc[0][fn][v];
+    }
+  __syncthreads();
+  // pivot rows: A'[k0 + t][c0 + c] (coalesced along c)
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
+    if (t < kn && c0 + c < n) aout[(long)(k0 + t) * n + c0 + c] = Bs[t * (64 + 1) + c];
+  }
+  // pivot columns: A'[i][k0 + t] = conj(R[t][i]) for rows i of this block outside k (coalesced along t)
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    const int idx = tid + 256 * e, t = idx & (NB - 1), c = idx / NB;
+    const int i = c0 + c;
+    if (t < kn && i < n && !(i >= k0 && i < k0 + kn)) aout[(long)i * n + k0 + t] = cconj(Bs[t * (64 + 1) + c]);
+  }
+}
+
+// Rank-kn update of every element outside the pivot rows and columns.
+typedef Tile<double, 64, 32, 16, 2, 2> TU;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_update_kernel(int n, const z64* __restrict__ ain,
+                                                           z64* __restrict__ aout, int k0, int kn,
+                                                           int ntm, int total) {
+  __shared__ z64 As[TU::AS];  // [t][i] = conj(A[k0 + t][m0 + i])
+  __shared__ z64 Bs[TU::BS];  // [t][j] = R[t][n0 + j] (the pivot rows of A')
+  const int id = xcd_remap(blockIdx.x, total);
+  if (id >= total) return;
+  const int bm = id % ntm, bn = id / ntm;
+  const int m0 = bm * TU::BM, n0 = bn * TU::BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave % TU::WGM) * TU::WTM, wn0 = (wave / TU::WGM) * TU::WTN;
+  const int rc = lane & 15, part = rc & 1;
+  Stager<double, double, TU::BM, TU::BK, TU::NT, true> sa;
+  Stager<double, double, TU::BN, TU::BK, TU::NT, true> sb;
+  sa.fetch(ain + (long)k0 * n, 1, n, m0, 0, n, kn, tid);
+  sb.fetch(aout + (long)k0 * n, 1, n, n0, 0, n, kn, tid);
+  const double* ainr = reinterpret_cast<const double*>(ain);
+  double cold[TU::FM][TU::FN][4];
+#pragma unroll
+  for (int fm = 0; fm < TU::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < TU::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm0 + fm * 16 + Mfma<double>::row(lane, v);
+        const int col = n0 + wn0 + fn * 8 + (rc >> 1);
+        // 32-bit byte offsets from the uniform base: one address register per load
+        const unsigned off = (row < n && col < n) ? ((unsigned)(row * n + col) * 2u + part) * 8u : 0u;
+        cold[fm][fn][v] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(ainr) + off);
+      }
+  TU::acc_t acc[TU::FM][TU::FN];
+  zero_acc<TU>(acc);
+  for (int kc = 0; kc < kn; kc += TU::BK) {
+    sa.store(As, TU::LDA, -1.0, tid);
+    sb.store(Bs, TU::LDB, 1.0, tid);
+    __syncthreads();
+    if (kc + TU::BK < kn) {
+      sa.fetch(ain + (long)k0 * n, 1, n, m0, kc + TU::BK, n, kn, tid);
+      sb.fetch(aout + (long)k0 * n, 1, n, n0, kc + TU::BK, n, kn, tid);
+    }
+    tile_mma<double, TU>(As, Bs, acc, wm0, wn0, lane);
+    __syncthreads();
+  }
   double* aoutr = reinterpret_cast<double*>(aout);
 #pragma unroll
-  for (int fm = 0; fm < TS::FM; ++fm)
+  for (int fm = 0; fm < TU::FM; ++fm)
 #pragma unroll
-    for (int fn = 0; fn < TS::FN; ++fn)
+    for (int fn = 0; fn < TU::FN; ++fn)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm0 + fm * 16 + Mfma<double>::row(lane, v);
         const int col = n0 + wn0 + fn * 8 + (rc >> 1);
         if (row >= n || col >= n) continue;
-        const long off = ((long)row * n + col) * 2 + part;
-        double val;
-        if (row >= k0 && row < k0 + kn) {
-          const z64 r = Bs[(row - k0) * TS::LDB + (col - n0)];
-          val = part ? r.im : r.re;
-        } else if (col >= k0 && col < k0 + kn) {
-          const z64 r = Ri[col - k0][row - m0];
-          val = part ? -r.im : r.re;
-        } else {
-          val = cold[fm][fn][v] - acc[fm][fn][v];
-        }
-        aoutr[off] = val;
+        if ((row >= k0 && row < k0 + kn) || (col >= k0 && col < k0 + kn)) continue;
+        aoutr[((long)row * n + col) * 2 + part] = cold[fm][fn][v] - acc[fm][fn][v];
       }
 }
 
@@ -195,15 +200,20 @@ size_t linalg_scratch_bytes(int n) { return (size_t)n * n * sizeof(z64); }
 
 hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st) {
   z64* bufs[2] = {(z64*)a, (z64*)scratch};
-  const int ntm = (n + 63) / 64;
-  const int total = ntm * ntm;
+  const int npb = (n + 63) / 64;                  // panel workgroups
+  const int ntm = (n + TU::BM - 1) / TU::BM, ntn = (n + TU::BN - 1) / TU::BN;
+  const int total = ntm * ntn;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
   int cur = 0;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kn = min(NB, n - k0);
-    hipLaunchKernelGGL(sweep_step_kernel, dim3(grid), dim3(256), 0, st, n, (const z64*)bufs[cur],
-                       bufs[cur ^ 1], k0, kn, status, ntm, total);
+    hipLaunchKernelGGL(sweep_panel_kernel, dim3(npb), dim3(256), 0, st, n, (const z64*)bufs[cur],
+                       bufs[cur ^ 1], k0, kn, status);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sweep_update_kernel, dim3(grid), dim3(256), 0, st, n, (const z64*)bufs[cur],
+                       bufs[cur ^ 1], k0, kn, ntm, total);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;
   }
