@@ -55,6 +55,7 @@ extern "C" {
 #endif
 
 typedef struct isdf_handle_s* isdf_handle;
+typedef struct isdf_plan_s* isdf_plan;
 
 typedef enum {
   ISDF_OK = 0,
@@ -171,6 +172,55 @@ isdf_status isdf_coulomb_u(isdf_handle h, const isdf_problem* prob, const void* 
 isdf_status isdf_smw_apply(isdf_handle h, const isdf_problem* prob, const void* u,
                            const void* m, int32_t n_mu, int32_t ng, void* workspace,
                            size_t ws_bytes, void* eps_inv, isdf_report* rep);
+
+/* ---- Plans: the same path as isdf_eps_inv, set up once, enqueued many times ----
+ *
+ * A plan holds everything about a problem that does not change between calls:
+ * the validated problem, the interpolation points, the plane-wave list, the
+ * pruned-DFT index tables and the workspace layout.  isdf_plan_create checks
+ * these inputs on the host (same rules as isdf_eps_inv), builds the tables and
+ * copies them to a small device buffer owned by the plan (the only device
+ * allocation the library makes; freed by isdf_plan_destroy).
+ *
+ * isdf_plan_eps_inv then only enqueues work on the handle's stream: no host
+ * synchronisation, no host-to-device copy, so a loop of calls keeps the GPU
+ * busy back to back.  Errors found on the device (no gap in the energies, a
+ * matrix that is not positive definite) accumulate in the plan's status and
+ * are returned by the next isdf_plan_sync, which waits for the stream, then
+ * clears the status.  Calls of one plan must not overlap on different streams,
+ * and each call's workspace must not be in use by another call still in flight
+ * (calls on one stream are ordered, so one workspace can serve a whole loop). */
+
+/* Create a plan for `prob` with n_mu points mu_idx, ng plane waves miller and
+ * n_omega frequencies per call (0 = static); arguments as for isdf_eps_inv
+ * (host arrays, copied).  Errors: ISDF_E_ARG, ISDF_E_UNSUPPORTED, ISDF_E_DEVICE. */
+isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int32_t* mu_idx,
+                             int32_t n_mu, const int32_t* miller, int32_t ng, int32_t n_omega,
+                             isdf_plan* plan);
+
+/* Destroy a plan (waits for the handle's stream).  NULL is accepted. */
+isdf_status isdf_plan_destroy(isdf_plan plan);
+
+/* Device workspace bytes one isdf_plan_eps_inv call needs. */
+isdf_status isdf_plan_workspace_bytes(isdf_plan plan, size_t* bytes);
+
+/* Enqueue eps~^{-1} for the plan's problem (paper: eq. epsilon_with_SMW with the
+ * ISDF pair products, the same kernels as isdf_eps_inv).
+ *   psi       device, as for isdf_eps_inv
+ *   energies  DEVICE, N doubles (Hartree); the gap is checked on the device
+ *   omega     host, the plan's n_omega frequencies (read during the call); NULL if 0
+ *   workspace device, >= isdf_plan_workspace_bytes, 256-byte aligned
+ *   eps_inv   device out, max(n_omega, 1) x ng x ng complex128, as for isdf_eps_inv
+ * Returns host-side argument errors (ISDF_E_ARG, ISDF_E_WORKSPACE) at once;
+ * device-side ones at the next isdf_plan_sync. */
+isdf_status isdf_plan_eps_inv(isdf_plan plan, const void* psi, const double* energies,
+                              const double* omega, void* workspace, size_t ws_bytes, void* eps_inv);
+
+/* Wait for the handle's stream and return the first error any call enqueued
+ * since the previous sync found on the device: ISDF_E_ARG (energies without a
+ * gap or not finite), ISDF_E_NOT_PD; then clear it.  rep (optional) receives
+ * the last call's min_pivot and refinement residuals (no stage times). */
+isdf_status isdf_plan_sync(isdf_plan plan, isdf_report* rep);
 
 /* Host-only check of every host-side argument of isdf_eps_inv (problem, energies,
  * points, plane waves, frequencies); no GPU or handle needed.  Returns the

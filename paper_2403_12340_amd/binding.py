@@ -67,6 +67,11 @@ def lib() -> ctypes.CDLL:
             "isdf_core_m": [vp, pprob, vp, pdbl, pi32, i32, dbl, vp, sz, vp],
             "isdf_coulomb_u": [vp, pprob, vp, pi32, i32, pi32, i32, vp, sz, vp],
             "isdf_smw_apply": [vp, pprob, vp, vp, i32, i32, vp, sz, vp, prep],
+            "isdf_plan_create": [vp, pprob, pi32, i32, pi32, i32, i32, ctypes.POINTER(vp)],
+            "isdf_plan_destroy": [vp],
+            "isdf_plan_workspace_bytes": [vp, ctypes.POINTER(sz)],
+            "isdf_plan_eps_inv": [vp, vp, vp, pdbl, vp, sz, vp],
+            "isdf_plan_sync": [vp, prep],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -309,6 +314,71 @@ def smw_apply(u, m, prob: Problem, workspace=None, timing=False) -> Result:
                               ctypes.byref(rep))
     h.check(st, "isdf_smw_apply")
     return Result(out, rep)
+
+
+class Plan:
+    """isdf_plan_*: validated once, then enqueue-only calls (no host sync per call).
+
+    energies are passed as a device float64 tensor; device-side errors surface
+    at sync()."""
+
+    def __init__(self, prob: Problem, mu_idx, miller, n_omega: int = 0, device: int = 0):
+        self.h = handle(device)
+        self.device = device
+        self.prob = prob
+        mu, pmu = _i32(mu_idx)
+        mi, pmi = _i32(miller)
+        self.nmu, self.ng, self.n_omega = len(mu), len(mi), int(n_omega)
+        p = ctypes.c_void_p()
+        self.h.check(lib().isdf_plan_create(self.h.h, ctypes.byref(prob), pmu, len(mu), pmi, len(mi),
+                                            self.n_omega, ctypes.byref(p)), "isdf_plan_create")
+        self.p = p
+        out = ctypes.c_size_t(0)
+        self.h.check(lib().isdf_plan_workspace_bytes(self.p, ctypes.byref(out)), "isdf_plan_workspace_bytes")
+        self.workspace_bytes = int(out.value)
+
+    def new_workspace(self):
+        import torch
+        return torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def new_output(self):
+        import torch
+        return torch.empty((max(self.n_omega, 1), self.ng, self.ng), dtype=torch.complex128,
+                           device=f"cuda:{self.device}")
+
+    def eps_inv_async(self, psi_t, energies_dev, out, workspace, omegas=None):
+        import torch
+        _check_psi(psi_t, self.prob)
+        if (not isinstance(energies_dev, torch.Tensor) or energies_dev.device.type != "cuda"
+                or energies_dev.dtype != torch.float64 or energies_dev.numel() != self.prob.nv + self.prob.nc
+                or not energies_dev.is_contiguous()):
+            raise TypeError("energies must be a contiguous device float64 tensor of N values")
+        if out.dtype != torch.complex128 or tuple(out.shape) != (max(self.n_omega, 1), self.ng, self.ng):
+            raise ValueError("out must be complex128 of shape (max(n_omega, 1), ng, ng)")
+        om = np.zeros(0) if omegas is None else np.asarray(omegas, dtype=np.float64)
+        if len(om) != self.n_omega:
+            raise ValueError(f"the plan was made for {self.n_omega} frequencies")
+        om, pom = _f64(om)
+        self.h.sync_stream()
+        wsbuf, wsptr = _workspace(self.workspace_bytes, psi_t.device, workspace)
+        st = lib().isdf_plan_eps_inv(self.p, ctypes.c_void_p(psi_t.data_ptr()),
+                                     ctypes.c_void_p(energies_dev.data_ptr()), pom if len(om) else None,
+                                     ctypes.c_void_p(wsptr), self.workspace_bytes, ctypes.c_void_p(out.data_ptr()))
+        self.h.check(st, "isdf_plan_eps_inv")
+        return out
+
+    def sync(self) -> Report:
+        rep = Report()
+        self.h.sync_stream()
+        self.h.check(lib().isdf_plan_sync(self.p, ctypes.byref(rep)), "isdf_plan_sync")
+        return rep
+
+    def __del__(self):
+        try:
+            if getattr(self, "p", None):
+                lib().isdf_plan_destroy(self.p)
+        except Exception:
+            pass
 
 
 def problem_for(inp, prec="fp64", refine_steps=0, v_scale=None) -> Problem:

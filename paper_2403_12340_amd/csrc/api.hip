@@ -32,6 +32,8 @@
 
 using namespace isdf;
 
+struct isdf_plan_s;
+
 struct isdf_handle_s {
   int device = 0;
   hipStream_t stream = nullptr;   // caller's stream (main branch)
@@ -315,6 +317,12 @@ struct Run {
   void* ws;
   const void* psi;      // complex128 view of the orbitals (device)
   StatusBlock* sb;
+  // read-only tables: workspace regions (per-call upload) or a plan's own buffer
+  const int* mu = nullptr;
+  const double* e = nullptr;      // energies (device)
+  const int* miller = nullptr;
+  const double* recip = nullptr;
+  const int* idx = nullptr;       // pruned-DFT index lists
   const void* tmat = nullptr;  // T (times talpha) after the core algebra
   double talpha = 1.0;
   hipStream_t st;
@@ -335,7 +343,7 @@ isdf_status prepare_psi(Run& R, const void* psi) {
 isdf_status stage_points(Run& R) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
-  HIPCHK(gather_points(R.psi, P.nr, P.ns, at<int>(R.ws, R.L.mu), P.nmu, at<char>(R.ws, R.L.pm), R.st));
+  HIPCHK(gather_points(R.psi, P.nr, P.ns, R.mu, P.nmu, at<char>(R.ws, R.L.pm), R.st));
   return ISDF_OK;
 }
 
@@ -404,7 +412,7 @@ DftPlan make_plan(Run& R) {
   p.twx = at<char>(R.ws, L.twx);
   p.twy = at<char>(R.ws, L.twy);
   p.twz = at<char>(R.ws, L.twz);
-  int* ib = at<int>(R.ws, L.idx);
+  const int* ib = R.idx;
   // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ng] g_cz[ng]
   p.d_ax = ib + L.kx + L.ky + L.kz;
   p.d_by = p.d_ax + L.nd;
@@ -421,8 +429,8 @@ isdf_status stage_dft(Run& R, bool scaled) {
   const Layout& L = R.L;
   const Prec cp = P.prec == P64 ? P64 : P32;
   DftPlan p = make_plan(R);
-  int* ib = at<int>(R.ws, L.idx);
-  HIPCHK(coulomb_sqrt(at<int>(R.ws, L.miller), P.ng, at<double>(R.ws, L.recip), P.v_scale,
+  const int* ib = R.idx;
+  HIPCHK(coulomb_sqrt(R.miller, P.ng, R.recip, P.v_scale,
                       at<double>(R.ws, L.sqrtv), R.st));
   HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), R.st));
   HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), R.st));
@@ -478,7 +486,7 @@ isdf_status stage_core(Run& R, double omega, void* m_out, void* negm, hipStream_
   const Problem& P = R.P;
   const Prec cp = P.prec == P64 ? P64 : P32;
   double* w = at<double>(R.ws, R.L.w);
-  HIPCHK(pair_weights(at<double>(R.ws, R.L.e), P.nv, P.nc, omega, w, st));
+  HIPCHK(pair_weights(R.e, P.nv, P.nc, omega, w, st));
   void* part = at<char>(R.ws, R.L.part);
   HIPCHK(core_partial(cp, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), P.nmu, w, part, R.L.nsplit, st));
   HIPCHK(core_reduce(cp, P.nmu, part, R.L.nsplit, P.f, m_out, negm, st));
@@ -566,16 +574,29 @@ isdf_status begin(isdf_handle h, const isdf_problem* prob, Problem& P, int nmu, 
   return ISDF_OK;
 }
 
+// Device status bits: 1 = a matrix that must be Hermitian positive definite is
+// not; 2 = the energies have no gap (or are not finite), found on the device.
+enum { ST_NOT_PD = 1, ST_NO_GAP = 2 };
+
+isdf_status report_status(isdf_handle h, const StatusBlock& hs, const Problem& P, isdf_report* rep) {
+  if (rep) {
+    rep->min_pivot = hs.min_pivot;
+    rep->n_refine_reported = P.refine > 0 ? P.refine + 1 : 0;
+    for (int k = 0; k < 9; ++k)
+      rep->refine_residual[k] = k < rep->n_refine_reported ? std::sqrt(hs.res[k] / (double)P.nmu) : 0.0;
+  }
+  if (hs.status & ST_NO_GAP) return fail(h, ISDF_E_ARG, "no gap: max occupied energy >= min empty energy (or energies not finite)");
+  if (hs.status & ST_NOT_PD) return fail(h, ISDF_E_NOT_PD, "a matrix that must be Hermitian positive definite is not (S = C C^H, -M or X^H X - S M^{-1} S)");
+  h->err.clear();
+  return ISDF_OK;
+}
+
 isdf_status finish(Run& R, isdf_report* rep, Timer& tm) {
   isdf_handle h = R.h;
   StatusBlock hs;
   HIPCHK(hipMemcpyAsync(&hs, R.sb, offsetof(StatusBlock, partial), hipMemcpyDeviceToHost, R.st));
   HIPCHK(hipStreamSynchronize(R.st));
   if (rep) {
-    rep->min_pivot = hs.min_pivot;
-    rep->n_refine_reported = R.P.refine > 0 ? R.P.refine + 1 : 0;
-    for (int k = 0; k < 9; ++k)
-      rep->refine_residual[k] = k < rep->n_refine_reported ? std::sqrt(hs.res[k] / (double)R.P.nmu) : 0.0;
     if (tm.on) {
       for (int k = 0; k < 8; ++k) rep->stage_ms[k] = 0.0;
       for (int k = 0; k + 1 < tm.k && k < 8; ++k) {
@@ -585,9 +606,7 @@ isdf_status finish(Run& R, isdf_report* rep, Timer& tm) {
       }
     }
   }
-  if (hs.status & 1) return fail(h, ISDF_E_NOT_PD, "a matrix that must be Hermitian positive definite is not (S = C C^H, -M or I + L^H G L)");
-  h->err.clear();
-  return ISDF_OK;
+  return report_status(h, hs, R.P, rep);
 }
 
 isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const void* psi,
@@ -621,6 +640,11 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
   R.ws = ws;
   R.st = h->stream;
   R.sb = at<StatusBlock>(ws, R.L.status);
+  R.mu = at<int>(ws, R.L.mu);
+  R.e = at<double>(ws, R.L.e);
+  R.miller = at<int>(ws, R.L.miller);
+  R.recip = at<double>(ws, R.L.recip);
+  R.idx = at<int>(ws, R.L.idx);
   up_.h = h;
   up_.ws = ws;
   up_.add(R.L.mu, mu_idx, (size_t)n_mu * 4);
@@ -642,9 +666,66 @@ isdf_status clear_status(Run& R) {
   return ISDF_OK;
 }
 
+#define TRY(x) do { isdf_status s_ = (x); if (s_ != ISDF_OK) return s_; } while (0)
+
+// Enqueue the whole path on the handle's stream (and its second stream, joined
+// back before returning).  No host synchronisation; the status block collects
+// error bits.
+isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_omega, void* eps_inv,
+                            Timer& tm) {
+  isdf_handle h = R.h;
+  const int ng = R.P.ng;
+  TRY(prepare_psi(R, psi));
+  TRY(stage_points(R));
+  // Fork: the side stream forms S = C C^H and, per frequency, M, M^{-1} and
+  // K = S M^{-1} S (double-buffered), while this stream runs Z, the DFT to
+  // X = V^{1/2} F Z and X^H X.  Then eps~^{-1} = I - X (X^H X - K)^{-1} X^H, which
+  // equals eq. epsilon_with_SMW with U = X S^{-1}; S^{-1} is never formed.
+  // Work is enqueued frequency by frequency so that every stream wait is
+  // enqueued after the event record it waits for.
+  hipStream_t side = h->side;
+  HIPCHK(hipEventRecord(h->fork, R.st));
+  HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
+  const int nw = std::max(n_omega, 1);
+  void* mbuf[2] = {at<char>(R.ws, R.L.l), at<char>(R.ws, R.L.l2)};
+  auto side_core = [&](int k) -> isdf_status {
+    if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
+    TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
+    HIPCHK(sweep_inverse(R.P.nmu, mbuf[k & 1], at<char>(R.ws, R.L.lin2), &R.sb->status, side));  // M^{-1}
+    TRY(stage_smis(R, mbuf[k & 1], at<char>(R.ws, R.L.q), side));                                 // S M^{-1} S
+    HIPCHK(hipEventRecord(h->m_ready[k & 1], side));
+    return ISDF_OK;
+  };
+  TRY(stage_s(R, side, R.L.lin2, false));
+  TRY(side_core(0));
+  if (nw > 1) TRY(side_core(1));
+  TRY(stage_z_operands(R));
+  tm.mark();
+  TRY(stage_z(R));
+  tm.mark();
+  TRY(stage_dft(R, true));
+  tm.mark();
+  const Basis xb{at<char>(R.ws, R.L.zg), 1, (long)ng};
+  TRY(stage_gram(R, xb));
+  tm.mark();
+  for (int k = 0; k < nw; ++k) {
+    Timer dummy{h, false};
+    Timer& t = (k == nw - 1) ? tm : dummy;
+    HIPCHK(hipStreamWaitEvent(R.st, h->m_ready[k & 1], 0));
+    TRY(stage_core_algebra(R, mbuf[k & 1], h->m_used[k & 1]));
+    if (k + 2 < nw) TRY(side_core(k + 2));
+    t.mark();
+    void* out = reinterpret_cast<char*>(eps_inv) + (size_t)k * ng * ng * 16;
+    TRY(stage_out(R, xb, out, t));
+    t.mark();
+  }
+  HIPCHK(hipEventRecord(h->join, side));
+  HIPCHK(hipStreamWaitEvent(R.st, h->join, 0));
+  return ISDF_OK;
+}
+
 }  // namespace
 
-#define TRY(x) do { isdf_status s_ = (x); if (s_ != ISDF_OK) return s_; } while (0)
 
 extern "C" {
 
@@ -785,52 +866,7 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
   TRY(clear_status(R));
   Timer tm{h, rep && rep->want_timing != 0};
   tm.mark();
-  TRY(prepare_psi(R, psi));
-  TRY(stage_points(R));
-  // Fork: the side stream forms S = C C^H and, per frequency, M, M^{-1} and
-  // K = S M^{-1} S (double-buffered), while this stream runs Z, the DFT to
-  // X = V^{1/2} F Z and X^H X.  Then eps~^{-1} = I - X (X^H X - K)^{-1} X^H, which
-  // equals eq. epsilon_with_SMW with U = X S^{-1}; S^{-1} is never formed.
-  // Work is enqueued frequency by frequency so that every stream wait is
-  // enqueued after the event record it waits for.
-  hipStream_t side = h->side;
-  HIPCHK(hipEventRecord(h->fork, R.st));
-  HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
-  const int nw = std::max(n_omega, 1);
-  void* mbuf[2] = {at<char>(workspace, R.L.l), at<char>(workspace, R.L.l2)};
-  auto side_core = [&](int k) -> isdf_status {
-    if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
-    TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
-    HIPCHK(sweep_inverse(R.P.nmu, mbuf[k & 1], at<char>(workspace, R.L.lin2), &R.sb->status, side));  // M^{-1}
-    TRY(stage_smis(R, mbuf[k & 1], at<char>(workspace, R.L.q), side));                                 // S M^{-1} S
-    HIPCHK(hipEventRecord(h->m_ready[k & 1], side));
-    return ISDF_OK;
-  };
-  TRY(stage_s(R, side, R.L.lin2, false));
-  TRY(side_core(0));
-  if (nw > 1) TRY(side_core(1));
-  TRY(stage_z_operands(R));
-  tm.mark();
-  TRY(stage_z(R));
-  tm.mark();
-  TRY(stage_dft(R, true));
-  tm.mark();
-  const Basis xb{at<char>(workspace, R.L.zg), 1, (long)ng};
-  TRY(stage_gram(R, xb));
-  tm.mark();
-  for (int k = 0; k < nw; ++k) {
-    Timer dummy{h, false};
-    Timer& t = (k == nw - 1) ? tm : dummy;
-    HIPCHK(hipStreamWaitEvent(R.st, h->m_ready[k & 1], 0));
-    TRY(stage_core_algebra(R, mbuf[k & 1], h->m_used[k & 1]));
-    if (k + 2 < nw) TRY(side_core(k + 2));
-    t.mark();
-    void* out = reinterpret_cast<char*>(eps_inv) + (size_t)k * ng * ng * 16;
-    TRY(stage_out(R, xb, out, t));
-    t.mark();
-  }
-  HIPCHK(hipEventRecord(h->join, side));
-  HIPCHK(hipStreamWaitEvent(R.st, h->join, 0));
+  TRY(enqueue_eps_inv(R, psi, omega, n_omega, eps_inv, tm));
   return finish(R, rep, tm);
 }
 
@@ -879,7 +915,7 @@ isdf_status isdf_core_m(isdf_handle h, const isdf_problem* prob, const void* psi
   TRY(upl.run());
   TRY(clear_status(R));
   TRY(prepare_psi(R, psi));
-  HIPCHK(gather_points(R.psi, R.P.nr, R.P.ns, at<int>(workspace, R.L.mu), R.P.nmu, at<char>(workspace, R.L.pm), R.st));
+  HIPCHK(gather_points(R.psi, R.P.nr, R.P.ns, R.mu, R.P.nmu, at<char>(workspace, R.L.pm), R.st));
   TRY(stage_core(R, omega, m_out, nullptr, R.st));
   Timer tm{h, false};
   return finish(R, nullptr, tm);
@@ -940,6 +976,116 @@ isdf_status isdf_smw_apply(isdf_handle h, const isdf_problem* prob, const void* 
   TRY(stage_out(R, ub, eps_inv, tm));
   tm.mark();
   return finish(R, rep, tm);
+}
+
+// ---- plans: validated, uploaded once; enqueue-only execution -------------------------------
+struct isdf_plan_s {
+  isdf_handle h = nullptr;
+  Problem P;
+  Layout L;
+  int n_omega = 0;
+  void* dev = nullptr;  // status block, point indices, Miller list, reciprocal basis, DFT tables
+  size_t off_mu = 0, off_miller = 0, off_recip = 0, off_idx = 0;
+};
+
+isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int32_t* mu_idx, int32_t n_mu,
+                             const int32_t* miller, int32_t ng, int32_t n_omega, isdf_plan* out) {
+  if (!h || !out) return ISDF_E_ARG;
+  *out = nullptr;
+  if (n_omega < 0) return fail(h, ISDF_E_ARG, "n_omega must be >= 0");
+  Problem P;
+  TRY(begin(h, prob, P, n_mu, ng, n_omega));
+  TRY(check_points(h, P, mu_idx, n_mu));
+  TRY(check_miller(h, P, miller, ng));
+  DftIndex ix = dft_index(miller, ng);
+  if (!dft_supported(P.n0, P.n1, (int)ix.xl.size(), (int)ix.yl.size(), P.prec == P64 ? P64 : P32))
+    return fail(h, ISDF_E_UNSUPPORTED, "grid plane too large for the LDS-resident DFT slab");
+  std::vector<int> idxbuf;
+  for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz})
+    idxbuf.insert(idxbuf.end(), v->begin(), v->end());
+  isdf_plan pl = new isdf_plan_s;
+  pl->h = h;
+  pl->P = P;
+  pl->n_omega = n_omega;
+  pl->L = make_layout(P, (int)ix.xl.size(), (int)ix.yl.size(), (int)ix.zl.size(), (int)ix.d_ax.size());
+  size_t off = up(sizeof(StatusBlock));
+  pl->off_mu = off; off += up((size_t)n_mu * 4);
+  pl->off_miller = off; off += up((size_t)ng * 12);
+  pl->off_recip = off; off += up(9 * 8);
+  pl->off_idx = off; off += up(idxbuf.size() * 4);
+  std::vector<char> host(off, 0);
+  std::memcpy(host.data() + pl->off_mu, mu_idx, (size_t)n_mu * 4);
+  std::memcpy(host.data() + pl->off_miller, miller, (size_t)ng * 12);
+  std::memcpy(host.data() + pl->off_recip, P.recip, 9 * 8);
+  std::memcpy(host.data() + pl->off_idx, idxbuf.data(), idxbuf.size() * 4);
+  auto bail = [&](hipError_t e) {
+    if (pl->dev) (void)hipFree(pl->dev);
+    delete pl;
+    return fail(h, ISDF_E_DEVICE, std::string("plan setup: ") + hipGetErrorString(e));
+  };
+  hipError_t e = hipSetDevice(h->device);
+  if (e == hipSuccess) e = hipMalloc(&pl->dev, off);
+  if (e == hipSuccess) e = hipMemcpy(pl->dev, host.data(), off, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(e);
+  *out = pl;
+  h->err.clear();
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_destroy(isdf_plan pl) {
+  if (!pl) return ISDF_OK;
+  (void)hipSetDevice(pl->h->device);
+  (void)hipStreamSynchronize(pl->h->stream);
+  if (pl->dev) (void)hipFree(pl->dev);
+  delete pl;
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_workspace_bytes(isdf_plan pl, size_t* bytes) {
+  if (!pl || !bytes) return ISDF_E_ARG;
+  *bytes = pl->L.total;
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_eps_inv(isdf_plan pl, const void* psi, const double* energies, const double* omega,
+                              void* workspace, size_t ws_bytes, void* eps_inv) {
+  if (!pl) return ISDF_E_ARG;
+  isdf_handle h = pl->h;
+  if (!psi) return fail(h, ISDF_E_ARG, "psi is NULL");
+  if (!energies) return fail(h, ISDF_E_ARG, "energies is NULL");
+  if (!eps_inv) return fail(h, ISDF_E_ARG, "eps_inv is NULL");
+  if (pl->n_omega > 0 && !omega) return fail(h, ISDF_E_ARG, "omega list invalid");
+  for (int k = 0; k < pl->n_omega; ++k)
+    if (!(omega[k] >= 0.0) || !std::isfinite(omega[k])) return fail(h, ISDF_E_ARG, "omega must be finite and >= 0");
+  TRY(check_ws(h, workspace, ws_bytes, pl->L.total));
+  Run R;
+  R.h = h;
+  R.P = pl->P;
+  R.L = pl->L;
+  R.ws = workspace;
+  R.st = h->stream;
+  char* d = reinterpret_cast<char*>(pl->dev);
+  R.sb = reinterpret_cast<StatusBlock*>(d);
+  R.mu = reinterpret_cast<const int*>(d + pl->off_mu);
+  R.e = energies;
+  R.miller = reinterpret_cast<const int*>(d + pl->off_miller);
+  R.recip = reinterpret_cast<const double*>(d + pl->off_recip);
+  R.idx = reinterpret_cast<const int*>(d + pl->off_idx);
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(check_gap(energies, R.P.nv, R.P.nc, &R.sb->status, ST_NO_GAP, R.st));
+  Timer none{h, false};
+  return enqueue_eps_inv(R, psi, omega, pl->n_omega, eps_inv, none);
+}
+
+isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {
+  if (!pl) return ISDF_E_ARG;
+  isdf_handle h = pl->h;
+  StatusBlock hs;
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipMemcpyAsync(&hs, pl->dev, offsetof(StatusBlock, partial), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(zero_fill(pl->dev, offsetof(StatusBlock, partial), h->stream));
+  return report_status(h, hs, pl->P, rep);
 }
 
 }  // extern "C"

@@ -55,6 +55,39 @@ hipError_t pair_weights(const double* e, int nv, int nc, double omega, double* w
   return hipGetLastError();
 }
 
+// Device-side gap check for energies that never reach the host: sets `bit` in
+// *status unless every energy is finite and max(occupied) < min(empty).
+// One workgroup; a fixed-shape tree reduction in LDS.
+__global__ __launch_bounds__(256) void gap_kernel(const double* e, int nv, int nc, int* status, int bit) {
+  __shared__ double vmax[256], cmin[256];
+  __shared__ int nonfinite[256];
+  const int t = threadIdx.x;
+  double a = -INFINITY, b = INFINITY;
+  int bad = 0;
+  for (int i = t; i < nv + nc; i += 256) {
+    const double x = e[i];
+    bad |= !isfinite(x);
+    if (i < nv) a = fmax(a, x);
+    else b = fmin(b, x);
+  }
+  vmax[t] = a; cmin[t] = b; nonfinite[t] = bad;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      vmax[t] = fmax(vmax[t], vmax[t + s]);
+      cmin[t] = fmin(cmin[t], cmin[t + s]);
+      nonfinite[t] |= nonfinite[t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0 && (nonfinite[0] || !(vmax[0] < cmin[0]))) atomicOr(status, bit);
+}
+
+hipError_t check_gap(const double* e, int nv, int nc, int* status, int bit, hipStream_t st) {
+  hipLaunchKernelGGL(gap_kernel, dim3(1), dim3(256), 0, st, e, nv, nc, status, bit);
+  return hipGetLastError();
+}
+
 // sqrt(V(G)) = sqrt(v_scale 4 pi / |G|^2), 0 at G = 0; G = sum_d m_d b_d, b_d rows of recip (2 pi included)
 __global__ void coulomb_kernel(const int* miller, int ng, const double* recip, double v_scale,
                                double* sqrtv) {

@@ -54,6 +54,8 @@ hipError_t widen_real(const double* src, void* dst, long count, hipStream_t st);
 hipError_t gather_points(const void* psi, long nr, int ns, const int* mu, int nmu, void* pm,
                          hipStream_t st);
 hipError_t pair_weights(const double* e, int nv, int nc, double omega, double* w, hipStream_t st);
+// sets `bit` in *status unless the energies are finite with max(e[0:nv]) < min(e[nv:nv+nc])
+hipError_t check_gap(const double* e, int nv, int nc, int* status, int bit, hipStream_t st);
 hipError_t coulomb_sqrt(const int* miller, int ng, const double* recip /*3x3 rows*/, double v_scale,
                         double* sqrtv, hipStream_t st);
 // DFT tables: twiddles tw[a][x] = exp(-2 pi i m_a x / n) / sqrt(n) for a list of m values
@@ -78,6 +80,7 @@ bool dft_supported(int n0, int n1, int kx, int ky, Prec compute);  // LDS fits
 hipError_t conj_transpose(int n, const void* a, void* at, hipStream_t st);   // at = a^H (z64)
 hipError_t convert_z(const void* src, bool src32, void* dst, bool dst32, long count, hipStream_t st);
 hipError_t axpby(const void* A, double a, const void* B, double b, void* C, long count, hipStream_t st);  // z64
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);  // kernel clear, bytes % 4 == 0
 hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStream_t st);  // z64
 // out[0] += ||a||_F^2 over count complex128, deterministic (single pass of block partials)
 hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st);

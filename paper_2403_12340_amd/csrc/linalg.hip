@@ -221,6 +221,20 @@ hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t
   return hipSuccess;
 }
 
+// Zero `bytes` bytes (a multiple of 4) with a kernel, so that the clear can sit in
+// a captured graph.
+__global__ void zero_kernel(uint32_t* p, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t st) {
+  const long n = (long)(bytes / 4);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
 // C = a * A + b * B elementwise (complex128, count elements)
 __global__ void axpby_kernel(const double* A, double a, const double* B, double b, double* C, long count2) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;

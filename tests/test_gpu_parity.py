@@ -190,3 +190,65 @@ def test_error_paths():
     # the library still works afterwards
     res = isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob)
     assert relf(res.eps_inv[0].cpu().numpy(), oracle.eps_inv_isdf(inp, stages=get_stages("cfg0"))) <= 1e-10
+
+
+def _plan_case(name, prec, n_omega=0):
+    inp = synth.make_inputs(name, n_omega=n_omega) if n_omega else get_inputs(name)
+    prob = isdf.problem_for(inp, prec)
+    plan = isdf.Plan(prob, inp.mu_idx, inp.miller, n_omega=n_omega)
+    return inp, prob, plan
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plan_matches_direct(prec):
+    """Enqueue-only plan calls (back to back on one workspace, one sync) give the
+    direct call's result bit for bit."""
+    inp, prob, plan = _plan_case("mid", prec)
+    print(f"[plan] case=mid prec={prec}", flush=True)
+    psi = dev(inp.psi_t)
+    direct = isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob).eps_inv.cpu()
+    e = dev(inp.energies)
+    ws = plan.new_workspace()
+    outs = [plan.new_output() for _ in range(3)]
+    for o in outs:
+        plan.eps_inv_async(psi, e, o, ws)
+    rep = plan.sync()
+    assert rep.min_pivot > 0
+    for o in outs:
+        assert torch.equal(o.cpu(), direct)
+
+
+def test_plan_frequencies():
+    inp, prob, plan = _plan_case("mid", "fp32", n_omega=4)
+    psi = dev(inp.psi_t)
+    direct = isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob, omegas=inp.omegas).eps_inv.cpu()
+    out = plan.new_output()
+    plan.eps_inv_async(psi, dev(inp.energies), out, plan.new_workspace(), omegas=inp.omegas)
+    plan.sync()
+    assert torch.equal(out.cpu(), direct)
+
+
+def test_plan_device_errors_surface_at_sync():
+    inp, prob, plan = _plan_case("cfg0", "fp64")
+    psi = dev(inp.psi_t)
+    ws, out = plan.new_workspace(), plan.new_output()
+    ref = oracle.eps_inv_isdf(inp, stages=get_stages("cfg0"))
+    # energies without a gap: found by the device check, reported at sync
+    e_bad = inp.energies.copy(); e_bad[0] = e_bad[-1] + 1.0
+    plan.eps_inv_async(psi, dev(e_bad), out, ws)
+    with pytest.raises(isdf.IsdfError) as err:
+        plan.sync()
+    assert err.value.status == -1
+    # the status was cleared: a good call syncs cleanly and is correct
+    plan.eps_inv_async(psi, dev(inp.energies), out, ws)
+    plan.sync()
+    assert relf(out[0].cpu().numpy(), ref) <= 1e-10
+    # C rank deficient (all orbitals vanish at one point): not positive definite
+    psi0 = inp.psi_t.copy(); psi0[:, inp.mu_idx[5]] = 0.0
+    plan.eps_inv_async(dev(psi0), dev(inp.energies), out, ws)
+    with pytest.raises(isdf.IsdfError) as err:
+        plan.sync()
+    assert err.value.status == -2
+    # host-side argument errors are immediate
+    with pytest.raises(ValueError):
+        plan.eps_inv_async(psi, dev(inp.energies), out, ws, omegas=[0.1])
