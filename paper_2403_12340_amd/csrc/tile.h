@@ -72,6 +72,23 @@ struct Stager {
   }
 };
 
+// Expanded B staging for the single-precision kernels: each complex b is stored
+// as the four floats (re, im, -im, re), i.e. both rows 2k and 2k + 1 of the real
+// block form, so a lane reads its B'' element with no sign fix-up.
+template <typename S, int BX, int BK, int NT>
+__device__ __forceinline__ void store_b4(const Stager<float, S, BX, BK, NT, true>& sg, float* lds, int ld4,
+                                         float csign, int tid) {
+#pragma unroll
+  for (int e = 0; e < Stager<float, S, BX, BK, NT, true>::E; ++e) {
+    const int idx = tid + e * NT;
+    if (idx >= BX * BK) break;
+    const int x = idx % BX, k = idx / BX;
+    const bool ok = (sg.valid >> e) & 1u;
+    const float re = ok ? (float)sg.raw[e].re : 0.f, im = ok ? csign * (float)sg.raw[e].im : 0.f;
+    *reinterpret_cast<f4*>(lds + (k * ld4 + x) * 4) = f4{re, im, -im, re};
+  }
+}
+
 // One BK-deep step of the wave's FM x FN block of MFMAs on LDS tiles.
 template <typename T, class TL>
 __device__ __forceinline__ void tile_mma(const cx<T>* __restrict__ As, const cx<T>* __restrict__ Bs,
@@ -95,6 +112,49 @@ __device__ __forceinline__ void tile_mma(const cx<T>* __restrict__ As, const cx<
     for (int fm = 0; fm < TL::FM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < TL::FN; ++fn) acc[fm][fn] = Mfma<T>::op(a[fm], b[fn], acc[fm][fn]);
+  }
+}
+
+// The same step, software-pipelined: the LDS fragments of step kk + 1 are read
+// while the MFMAs of step kk run, so the LDS latency hides behind matrix work
+// within one wave (the scheduling groups interleave one read per MFMA).
+template <typename T, class TL>
+__device__ __forceinline__ void tile_mma_pipe(const cx<T>* __restrict__ As, const cx<T>* __restrict__ Bs,
+                                              typename TL::acc_t (&acc)[TL::FM][TL::FN], int wm0,
+                                              int wn0, int lane) {
+  constexpr int KK = TL::BK / 2;
+  constexpr int NR = TL::FM + TL::FN;
+  const int i = lane & 15, q = lane >> 4;
+  const int bpart = ((q & 1) == (i & 1)) ? 0 : 1;
+  const T bsign = ((q & 1) == 1 && (i & 1) == 0) ? (T)-1 : (T)1;
+  const T* ap = reinterpret_cast<const T*>(As) + ((q >> 1) * TL::LDA + wm0 + i) * 2 + (q & 1);
+  const T* bp = reinterpret_cast<const T*>(Bs) + ((q >> 1) * TL::LDB + wn0 + (i >> 1)) * 2 + bpart;
+  T a[2][TL::FM], b[2][TL::FN];
+#pragma unroll
+  for (int fm = 0; fm < TL::FM; ++fm) a[0][fm] = ap[fm * 32];
+#pragma unroll
+  for (int fn = 0; fn < TL::FN; ++fn) b[0][fn] = bsign * bp[fn * 16];
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) {
+    const int c = kk & 1;
+    if (kk + 1 < KK) {
+#pragma unroll
+      for (int fm = 0; fm < TL::FM; ++fm) a[c ^ 1][fm] = ap[(kk + 1) * 4 * TL::LDA + fm * 32];
+#pragma unroll
+      for (int fn = 0; fn < TL::FN; ++fn) b[c ^ 1][fn] = bsign * bp[(kk + 1) * 4 * TL::LDB + fn * 16];
+    }
+#pragma unroll
+    for (int fm = 0; fm < TL::FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < TL::FN; ++fn) acc[fm][fn] = Mfma<T>::op(a[c][fm], b[c][fn], acc[fm][fn]);
+    if (kk + 1 < KK) {
+#pragma unroll
+      for (int r = 0; r < NR && r < TL::FM * TL::FN; ++r) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+      }
+      if (TL::FM * TL::FN > NR) __builtin_amdgcn_sched_group_barrier(0x008, TL::FM * TL::FN - NR, 0);
+    }
   }
 }
 

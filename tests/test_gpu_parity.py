@@ -17,7 +17,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank"]
+SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank", "tiles"]
 TOL_EPS = {"fp64": 1e-10, "fp32": 1e-6}
 TOL_STAGE = {"fp64": 1e-10, "fp32": 1e-4}
 
@@ -252,3 +252,24 @@ def test_plan_device_errors_surface_at_sync():
     # host-side argument errors are immediate
     with pytest.raises(ValueError):
         plan.eps_inv_async(psi, dev(inp.energies), out, ws, omegas=[0.1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_48cubed(prec):
+    """The benchmark workload itself (48^3, 64/256 states, 640 points, 4096 plane
+    waves), every element of eps~^{-1} against the oracle, in the launch
+    configuration the benchmark times (plan, enqueue-only calls)."""
+    name = "cfg1"
+    inp = get_inputs(name)
+    print(f"[full] case={name} prec={prec}", flush=True)
+    prob = isdf.problem_for(inp, prec)
+    plan = isdf.Plan(prob, inp.mu_idx, inp.miller)
+    out = plan.new_output()
+    plan.eps_inv_async(dev(inp.psi_t), dev(inp.energies), out, plan.new_workspace())
+    plan.sync()
+    got = out[0].cpu().numpy()
+    ref = oracle.eps_inv_isdf(inp, stages=get_stages(name))
+    err = relf(got, ref)
+    print(f"  rel-F {err:.3e}  max-abs {np.abs(got - ref).max():.3e}", flush=True)
+    assert err <= TOL_EPS[prec], err
+    assert np.array_equal(got, got.conj().T)
