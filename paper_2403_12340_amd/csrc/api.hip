@@ -73,7 +73,7 @@ struct Problem {
 
 // pruned-DFT index lists derived from the Miller list (host bookkeeping)
 struct DftIndex {
-  std::vector<int> xl, yl, zl, d_ax, d_by, g_d, g_cz;
+  std::vector<int> xl, yl, zl, d_ax, d_by, g_d, g_cz, dmap;
 };
 
 DftIndex dft_index(const int32_t* miller, int ng) {
@@ -98,6 +98,8 @@ DftIndex dft_index(const int32_t* miller, int ng) {
     ix.d_ax.push_back(pos(ix.xl, (int)(k / 4096) - 1024));
     ix.d_by.push_back(pos(ix.yl, (int)(k % 4096) - 1024));
   }
+  ix.dmap.assign(ix.xl.size() * ix.yl.size(), -1);
+  for (size_t d = 0; d < ix.d_ax.size(); ++d) ix.dmap[(size_t)ix.d_ax[d] * ix.yl.size() + ix.d_by[d]] = (int)d;
   ix.g_d.resize(ng);
   ix.g_cz.resize(ng);
   for (int g = 0; g < ng; ++g) {
@@ -140,7 +142,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.e = take((size_t)P.ns * 8);
   L.miller = take((size_t)P.ng * 3 * 4);
   L.recip = take(9 * 8);
-  L.idx = take((size_t)(kx + ky + kz + 2 * nd + 2 * P.ng) * 4);
+  L.idx = take((size_t)(kx + ky + kz + 2 * nd + 2 * P.ng + kx * ky) * 4);
   L.w = take((size_t)P.nv * P.nc * 8);
   L.sqrtv = take((size_t)P.ng * 8);
   L.twx = take((size_t)kx * P.n0 * el);
@@ -413,11 +415,12 @@ DftPlan make_plan(Run& R) {
   p.twy = at<char>(R.ws, L.twy);
   p.twz = at<char>(R.ws, L.twz);
   const int* ib = R.idx;
-  // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ng] g_cz[ng]
+  // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ng] g_cz[ng] dmap[kx][ky]
   p.d_ax = ib + L.kx + L.ky + L.kz;
   p.d_by = p.d_ax + L.nd;
   p.g_d = p.d_by + L.nd;
   p.g_cz = p.g_d + P.ng;
+  p.dmap = p.g_cz + P.ng;
   return p;
 }
 
@@ -628,6 +631,7 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
   } else {
     ix.xl = ix.yl = ix.zl = {0};
     ix.d_ax = ix.d_by = {0};
+    ix.dmap = {-1};
   }
   if (energies) {
     s = check_energies(h, R.P, energies);
@@ -652,7 +656,7 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
   if (miller) {
     up_.add(R.L.miller, miller, (size_t)ng * 12);
     idxbuf.clear();
-    for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz})
+    for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz, &ix.dmap})
       idxbuf.insert(idxbuf.end(), v->begin(), v->end());
     up_.add(R.L.idx, idxbuf.data(), idxbuf.size() * 4);
     up_.add(R.L.recip, R.P.recip, 9 * 8);
@@ -1001,7 +1005,7 @@ isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int3
   if (!dft_supported(P.n0, P.n1, (int)ix.xl.size(), (int)ix.yl.size(), P.prec == P64 ? P64 : P32))
     return fail(h, ISDF_E_UNSUPPORTED, "grid plane too large for the LDS-resident DFT slab");
   std::vector<int> idxbuf;
-  for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz})
+  for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz, &ix.dmap})
     idxbuf.insert(idxbuf.end(), v->begin(), v->end());
   isdf_plan pl = new isdf_plan_s;
   pl->h = h;

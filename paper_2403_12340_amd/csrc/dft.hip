@@ -11,6 +11,8 @@
 // (one coalesced read of the slab); stage z reads the small T2.  Each
 // twiddle table carries its 1/sqrt(n) so the product is unitary.
 #include "internal.h"
+
+#include <algorithm>
 #include "tile.h"
 
 #include <cmath>
@@ -128,113 +130,179 @@ hipError_t dft_twiddles(const int* mlist, int nm, int n, bool f32, void* tw, hip
   return hipGetLastError();
 }
 
-// LDS rows are padded to an odd number of complex elements so that lanes
-// reading different rows hit different banks.
-__host__ __device__ inline int odd_pad(int n) { return n | 1; }
 __host__ __device__ inline int up16(int n) { return (n + 15) / 16 * 16; }
 
-// x stage as an MFMA product per slab: T1 (y x a) = Z^T-slab (y x x) . TW^T (x x a),
-// y up to 64 rows (4 waves of 16), a in chunks of 32 columns, x in 16-deep steps.
+// One workgroup walks `zb` consecutive z-planes (slabs) of one point.  Per slab
+// (n1 x n0: y rows, x contiguous):
+//   x stage  T1^T (a x y) = TWX (a x x) . slab^T (x x y)    MFMA, 2 x 2 waves
+//   y stage  T2   (a x b) = T1^T (a x y) . TWY^T (y x b)    MFMA, 2 x 2 waves
+// and only the (a, b) pairs of the plane-wave list are stored, z-contiguous:
+// t2[mu][d][z].  a and b run in chunks of 32.  The slab is copied into LDS as
+// it lies in memory ([y][x], read as an n-major B operand); T1 overwrites it as
+// [y][a] (the k-major A operand of the y stage); the twiddle chunks [x][a] and
+// [y][b] stay resident across slabs, the next slab is prefetched into registers
+// under the MFMAs, and each lane's pair indices are looked up once.  Every LDS
+// value outside the live ranges is finite (zeroed once, then only data) and the
+// twiddle padding is zero, so padded rows and columns contribute exactly zero.
 template <typename T>
-using TileX = Tile<T, 64, 32, 16, 4, 1>;
+using TileXS = Tile<T, 32, 64, 16, 2, 2>;  // x stage: M a (32), N y (64), K x
+template <typename T>
+using TileYS = Tile<T, 32, 32, 16, 2, 2>;  // y stage: M a (32), N b (32), K y; LDA = LDB = 33
+
+constexpr int XY_NT = 256;
+constexpr int XY_LDS = 65;                 // slab row stride (complex): n-major B operand of the x stage
 
 template <typename T>
-static size_t xy_lds_bytes(const DftPlan& p) {
-  typedef TileX<T> TL;
-  const size_t k16 = up16(p.n0), s1 = odd_pad(p.n1 + 1), sk = odd_pad(p.kx);
-  return sizeof(cx<T>) * (k16 * TL::LDA + k16 * TL::LDB + (size_t)p.n1 * sk + (size_t)p.ky * s1);
+static size_t xy_lds_bytes() {
+  return sizeof(cx<T>) * (64 * XY_LDS + 2 * 64 * 33);
 }
 
-// one workgroup per (z-plane, point)
-template <typename T>
-__global__ __launch_bounds__(256) void dft_xy_kernel(DftPlan p, const cx<T>* zt, cx<T>* t2) {
-  typedef TileX<T> TL;
+// PF = slab elements per thread held in registers (n0 n1 <= 256 PF)
+template <typename T, int PF>
+__global__ __launch_bounds__(XY_NT) void dft_xy_kernel(DftPlan p, const cx<T>* __restrict__ zt,
+                                                       cx<T>* __restrict__ t2, int zb) {
+  typedef TileXS<T> TX;
+  typedef TileYS<T> TY;
+  static_assert(TX::LDA == 33 && TY::LDA == 33 && TY::LDB == 33, "chunk strides");
   extern __shared__ unsigned char lds_raw[];
-  const int k16 = up16(p.n0), s1 = odd_pad(p.n1 + 1), sk = odd_pad(p.kx);
-  cx<T>* As = reinterpret_cast<cx<T>*>(lds_raw);   // [x][y] slab, k-major A operand
-  cx<T>* Bs = As + k16 * TL::LDA;                   // [x][a] twiddle chunk, k-major B operand
-  cx<T>* T1 = Bs + k16 * TL::LDB;                   // [y][sk]  after the x stage
-  cx<T>* TY = T1 + p.n1 * sk;                       // [ky][s1] y twiddles
-  const int z = blockIdx.x, mu = blockIdx.y;
+  cx<T>* Ss = reinterpret_cast<cx<T>*>(lds_raw);   // slab [y][x] (stride 65), then T1 [y][a] (stride 33)
+  cx<T>* Xs = Ss + 64 * XY_LDS;                     // TWX^T chunk [x][a]: A operand of the x stage
+  cx<T>* Ys = Xs + 64 * 33;                         // TWY^T chunk [y][b]: B operand of the y stage
+  const int nzb = (p.n2 + zb - 1) / zb;
+  const int mu = blockIdx.x / nzb, z0 = (blockIdx.x % nzb) * zb, z1 = min(p.n2, z0 + zb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long slab = ((long)mu * p.n2 + z) * p.n1 * p.n0;
+  const int x16 = up16(p.n0), y16 = up16(p.n1);
+  const int nslab = p.n0 * p.n1;
+  const bool one_chunk = p.kx <= 32 && p.ky <= 32;
   const cx<T>* twx = reinterpret_cast<const cx<T>*>(p.twx);
   const cx<T>* twy = reinterpret_cast<const cx<T>*>(p.twy);
-  const cx<T> zero{(T)0, (T)0};
-  for (int i = tid; i < k16 * 64; i += 256) {       // transpose the slab into [x][y], zero padded
-    const int x = i / 64, y = i % 64;
-    As[x * TL::LDA + y] = zero;
-  }
-  __syncthreads();
-  for (int i = tid; i < p.n0 * p.n1; i += 256) As[(i % p.n0) * TL::LDA + i / p.n0] = zt[slab + i];
-  for (int i = tid; i < p.ky * p.n1; i += 256) TY[(i / p.n1) * s1 + i % p.n1] = twy[i];
-  const int wm0 = wave * TL::WTM;
+  for (int i = tid; i < 64 * XY_LDS; i += XY_NT) Ss[i] = cx<T>{(T)0, (T)0};
+  auto load_chunk = [&](cx<T>* dst, const cx<T>* tw, int nk, int kpad, int nlist, int c0) {
+    // dst[k][c] = tw[(c0 + c) * nk + k] for k < nk and c0 + c < nlist, else 0
+    for (int i = tid; i < kpad * 32; i += XY_NT) {
+      const int k = i / 32, c = i % 32;
+      const bool ok = k < nk && c0 + c < nlist;
+      const cx<T> v = tw[ok ? (c0 + c) * nk + k : 0];
+      dst[k * 33 + c] = cx<T>{ok ? v.re : (T)0, ok ? v.im : (T)0};  // component selects stay in registers
+    }
+  };
+  const int wm0 = (wave % 2) * 16, xn0 = (wave / 2) * TX::WTN, yn0 = (wave / 2) * TY::WTN;
   const int rc = lane & 15, part = rc & 1;
-  for (int a0 = 0; a0 < p.kx; a0 += 32) {
-    __syncthreads();
-    for (int i = tid; i < k16 * 32; i += 256) {
-      const int x = i / 32, a = i % 32;
-      const bool ok = x < p.n0 && a0 + a < p.kx;
-      const cx<T> t = twx[ok ? (a0 + a) * p.n0 + x : 0];
-      Bs[x * TL::LDB + a] = cx<T>{ok ? t.re : (T)0, ok ? t.im : (T)0};
+  // this lane's y-stage outputs (a, b) -> pair index, for the single-chunk case
+  int dl[TY::FN][4];
+#pragma unroll
+  for (int fn = 0; fn < TY::FN; ++fn)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = wm0 + Mfma<T>::row(lane, v), b = yn0 + fn * 8 + (rc >> 1);
+      dl[fn][v] = (one_chunk && a < p.kx && b < p.ky) ? p.dmap[a * p.ky + b] : -1;
     }
-    __syncthreads();
-    typename TL::acc_t acc[TL::FM][TL::FN];
-    zero_acc<TL>(acc);
-    for (int kc = 0; kc < k16; kc += 16)
-      tile_mma<T, TL>(As + kc * TL::LDA, Bs + kc * TL::LDB, acc, wm0, 0, lane);
-    T* T1r = reinterpret_cast<T*>(T1);
+  T pfr[PF], pfi[PF];  // slab prefetch (split re / im keeps it in registers)
+  if (z0 < z1) {
+    const cx<T>* src = zt + ((long)mu * p.n2 + z0) * nslab;
 #pragma unroll
-    for (int fn = 0; fn < TL::FN; ++fn)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int y = wm0 + Mfma<T>::row(lane, v);
-        const int a = a0 + fn * 8 + (rc >> 1);
-        if (y < p.n1 && a < p.kx) T1r[(y * sk + a) * 2 + part] = acc[0][fn][v];
-      }
+    for (int e = 0; e < PF; ++e) {
+      const int i = tid + e * XY_NT;
+      const cx<T> v = src[i < nslab ? i : 0];
+      pfr[e] = v.re; pfi[e] = v.im;
+    }
   }
-  __syncthreads();
-  // y stage: only the (x, y) frequency pairs in use
-  cx<T>* out = t2 + ((long)mu * p.n2 + z) * p.nd;
-  for (int d = tid; d < p.nd; d += 256) {
-    const int a = p.d_ax[d], b = p.d_by[d];
-    const cx<T>* tw = TY + b * s1;
-    T sr = 0, si = 0;
-    for (int y = 0; y < p.n1; ++y) {
-      const cx<T> v = T1[y * sk + a];
-      sr += v.re * tw[y].re - v.im * tw[y].im;
-      si += v.re * tw[y].im + v.im * tw[y].re;
+  T* ssr = reinterpret_cast<T*>(Ss);
+  for (int z = z0; z < z1; ++z) {
+    __syncthreads();  // previous slab's y stage is done with Ss
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int i = tid + e * XY_NT;
+      if (i < nslab) Ss[(i / p.n0) * XY_LDS + i % p.n0] = cx<T>{pfr[e], pfi[e]};
     }
-    out[d] = cx<T>{sr, si};
+    if (z + 1 < z1) {  // next slab into registers, under this slab's MFMAs
+      const cx<T>* src = zt + ((long)mu * p.n2 + z + 1) * nslab;
+#pragma unroll
+      for (int e = 0; e < PF; ++e) {
+        const int i = tid + e * XY_NT;
+        const cx<T> v = src[i < nslab ? i : 0];
+        pfr[e] = v.re; pfi[e] = v.im;
+      }
+    }
+    for (int a0 = 0; a0 < p.kx; a0 += 32) {
+      if (z == z0 || !one_chunk) load_chunk(Xs, twx, p.n0, x16, p.kx, a0);
+      __syncthreads();
+      // x stage for rows a in [a0, a0 + 32): acc = TWX . slab^T (rows a, columns y)
+      typename TX::acc_t acc[TX::FM][TX::FN];
+      zero_acc<TX>(acc);
+      for (int kc = 0; kc < x16; kc += 16) tile_mma_bn<T, TX>(Xs + kc * 33, Ss + kc, XY_LDS, acc, wm0, xn0, lane);
+      __syncthreads();  // every wave is done reading the slab
+#pragma unroll
+      for (int fn = 0; fn < TX::FN; ++fn)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = wm0 + Mfma<T>::row(lane, v);
+          const int y = xn0 + fn * 8 + (rc >> 1);
+          ssr[(y * 33 + a) * 2 + part] = acc[0][fn][v];  // T1[y][a]
+        }
+      for (int b0 = 0; b0 < p.ky; b0 += 32) {
+        if (z == z0 || !one_chunk) load_chunk(Ys, twy, p.n1, y16, p.ky, b0);
+        __syncthreads();
+        typename TY::acc_t acc2[TY::FM][TY::FN];
+        zero_acc<TY>(acc2);
+        for (int kc = 0; kc < y16; kc += 16) tile_mma<T, TY>(Ss + kc * 33, Ys + kc * 33, acc2, wm0, yn0, lane);
+        T* t2r = reinterpret_cast<T*>(t2);
+#pragma unroll
+        for (int fn = 0; fn < TY::FN; ++fn)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            int d = dl[fn][v];
+            if (!one_chunk) {
+              const int a = a0 + wm0 + Mfma<T>::row(lane, v), b = b0 + yn0 + fn * 8 + (rc >> 1);
+              d = (a < p.kx && b < p.ky) ? p.dmap[a * p.ky + b] : -1;
+            }
+            if (d >= 0) t2r[(((long)mu * p.nd + d) * p.n2 + z) * 2 + part] = acc2[0][fn][v];
+          }
+        if (b0 + 32 < p.ky) __syncthreads();  // Ys is reloaded for the next chunk
+      }
+      if (a0 + 32 < p.kx) {
+        __syncthreads();  // T1 chunk consumed: restore the slab for the next row chunk
+        for (int i = tid; i < nslab; i += XY_NT) Ss[(i / p.n0) * XY_LDS + i % p.n0] = zt[((long)mu * p.n2 + z) * nslab + i];
+      }
+    }
   }
 }
 
 bool dft_supported(int n0, int n1, int kx, int ky, Prec compute) {
-  if (n1 > 64 || n0 > 64) return false;  // one 64-row MFMA tile per slab
-  DftPlan p{};
-  p.n0 = n0; p.n1 = n1; p.kx = kx; p.ky = ky;
-  const size_t bytes = compute == P64 ? xy_lds_bytes<double>(p) : xy_lds_bytes<float>(p);
+  (void)kx; (void)ky;  // any list length: the x and y stages run in chunks of 32 frequencies
+  if (n1 > 64 || n0 > 64) return false;  // one 64 x 64 slab per MFMA tile
+  const size_t bytes = compute == P64 ? xy_lds_bytes<double>() : xy_lds_bytes<float>();
   return bytes <= 160 * 1024;
 }
 
+template <typename T, int PF>
+static void xy_launch(const DftPlan& p, const void* zt, void* t2, int zb, dim3 grid, hipStream_t st) {
+  const size_t lds = xy_lds_bytes<T>();
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_xy_kernel<T, PF>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((dft_xy_kernel<T, PF>), grid, dim3(XY_NT), lds, st, p, (const cx<T>*)zt, (cx<T>*)t2, zb);
+}
+
+template <typename T>
+static void xy_dispatch(const DftPlan& p, const void* zt, void* t2, int zb, dim3 grid, hipStream_t st) {
+  const int nslab = p.n0 * p.n1;
+  if (nslab <= 4 * XY_NT) xy_launch<T, 4>(p, zt, t2, zb, grid, st);
+  else if (nslab <= 9 * XY_NT) xy_launch<T, 9>(p, zt, t2, zb, grid, st);
+  else xy_launch<T, 16>(p, zt, t2, zb, grid, st);
+}
+
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st) {
-  const dim3 grid(p.n2, p.nmu);
-  if (compute == P64) {
-    const size_t lds = xy_lds_bytes<double>(p);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_xy_kernel<double>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((dft_xy_kernel<double>), grid, dim3(256), lds, st, p, (const z64*)zt, (z64*)t2);
-  } else {
-    const size_t lds = xy_lds_bytes<float>(p);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_xy_kernel<float>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((dft_xy_kernel<float>), grid, dim3(256), lds, st, p, (const c32*)zt, (c32*)t2);
-  }
+  if (p.n0 > 64 || p.n1 > 64) return hipErrorInvalidValue;
+  const int zb = std::min(p.n2, 8);
+  const int nzb = (p.n2 + zb - 1) / zb;
+  const dim3 grid((unsigned)(p.nmu * nzb));
+  if (compute == P64) xy_dispatch<double>(p, zt, t2, zb, grid, st);
+  else xy_dispatch<float>(p, zt, t2, zb, grid, st);
   return hipGetLastError();
 }
 
+// z stage: zg[mu][g] = scale[g] sum_z t2[mu][d_g][z] twz[c_g][z], one thread per
+// (g, point), reading the z-contiguous line of its pair with independent loads.
 template <typename T>
 __global__ void dft_z_kernel(DftPlan p, const cx<T>* t2, cx<T>* zg, const double* scale) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -242,15 +310,24 @@ __global__ void dft_z_kernel(DftPlan p, const cx<T>* t2, cx<T>* zg, const double
   if (g >= p.ng) return;
   const int d = p.g_d[g], c = p.g_cz[g];
   const cx<T>* twz = reinterpret_cast<const cx<T>*>(p.twz) + (long)c * p.n2;
-  const cx<T>* col = t2 + (long)mu * p.n2 * p.nd + d;
-  T sr = 0, si = 0;
-  for (int z = 0; z < p.n2; ++z) {
-    const cx<T> v = col[(long)z * p.nd];
-    sr += v.re * twz[z].re - v.im * twz[z].im;
-    si += v.re * twz[z].im + v.im * twz[z].re;
+  const cx<T>* line = t2 + ((long)mu * p.nd + d) * p.n2;
+  T sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+  int z = 0;
+  for (; z + 4 <= p.n2; z += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const cx<T> v = line[z + u], w = twz[z + u];
+      sr[u] += v.re * w.re - v.im * w.im;
+      si[u] += v.re * w.im + v.im * w.re;
+    }
+  }
+  for (; z < p.n2; ++z) {
+    const cx<T> v = line[z], w = twz[z];
+    sr[0] += v.re * w.re - v.im * w.im;
+    si[0] += v.re * w.im + v.im * w.re;
   }
   const T sc = scale ? (T)scale[g] : (T)1;
-  zg[(long)mu * p.ng + g] = cx<T>{sr * sc, si * sc};
+  zg[(long)mu * p.ng + g] = cx<T>{((sr[0] + sr[1]) + (sr[2] + sr[3])) * sc, ((si[0] + si[1]) + (si[2] + si[3])) * sc};
 }
 
 hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, const double* scale,

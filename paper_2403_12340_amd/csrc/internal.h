@@ -70,8 +70,9 @@ struct DftPlan {
   const int* d_by;         // nd: index into twy list for pair d
   const int* g_d;          // ng: pair index of plane wave g
   const int* g_cz;         // ng: index into twz list of plane wave g
+  const int* dmap;         // kx x ky: pair index d of (x-frequency a, y-frequency b), or -1
 };
-// zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][n2][nd] -> zg: [nmu][ng] (times scale[g] if given)
+// zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][nd][n2] -> zg: [nmu][ng] (times scale[g] if given)
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);
 hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, const double* scale,
                  hipStream_t st);

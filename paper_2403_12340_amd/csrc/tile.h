@@ -115,46 +115,29 @@ __device__ __forceinline__ void tile_mma(const cx<T>* __restrict__ As, const cx<
   }
 }
 
-// The same step, software-pipelined: the LDS fragments of step kk + 1 are read
-// while the MFMAs of step kk run, so the LDS latency hides behind matrix work
-// within one wave (the scheduling groups interleave one read per MFMA).
+// The same step with B stored n-major: element (k, n) of the B tile at
+// Bs[n * ldbn + k] (for operands that arrive row-major in n).
 template <typename T, class TL>
-__device__ __forceinline__ void tile_mma_pipe(const cx<T>* __restrict__ As, const cx<T>* __restrict__ Bs,
-                                              typename TL::acc_t (&acc)[TL::FM][TL::FN], int wm0,
-                                              int wn0, int lane) {
-  constexpr int KK = TL::BK / 2;
-  constexpr int NR = TL::FM + TL::FN;
+__device__ __forceinline__ void tile_mma_bn(const cx<T>* __restrict__ As, const cx<T>* __restrict__ Bs, int ldbn,
+                                            typename TL::acc_t (&acc)[TL::FM][TL::FN], int wm0, int wn0,
+                                            int lane) {
+  const T* Ar = reinterpret_cast<const T*>(As);
+  const T* Br = reinterpret_cast<const T*>(Bs);
   const int i = lane & 15, q = lane >> 4;
   const int bpart = ((q & 1) == (i & 1)) ? 0 : 1;
   const T bsign = ((q & 1) == 1 && (i & 1) == 0) ? (T)-1 : (T)1;
-  const T* ap = reinterpret_cast<const T*>(As) + ((q >> 1) * TL::LDA + wm0 + i) * 2 + (q & 1);
-  const T* bp = reinterpret_cast<const T*>(Bs) + ((q >> 1) * TL::LDB + wn0 + (i >> 1)) * 2 + bpart;
-  T a[2][TL::FM], b[2][TL::FN];
 #pragma unroll
-  for (int fm = 0; fm < TL::FM; ++fm) a[0][fm] = ap[fm * 32];
+  for (int kk = 0; kk < TL::BK / 2; ++kk) {
+    const int k = 2 * kk + (q >> 1);
+    T a[TL::FM], b[TL::FN];
 #pragma unroll
-  for (int fn = 0; fn < TL::FN; ++fn) b[0][fn] = bsign * bp[fn * 16];
+    for (int fm = 0; fm < TL::FM; ++fm) a[fm] = Ar[(k * TL::LDA + wm0 + fm * 16 + i) * 2 + (q & 1)];
 #pragma unroll
-  for (int kk = 0; kk < KK; ++kk) {
-    const int c = kk & 1;
-    if (kk + 1 < KK) {
-#pragma unroll
-      for (int fm = 0; fm < TL::FM; ++fm) a[c ^ 1][fm] = ap[(kk + 1) * 4 * TL::LDA + fm * 32];
-#pragma unroll
-      for (int fn = 0; fn < TL::FN; ++fn) b[c ^ 1][fn] = bsign * bp[(kk + 1) * 4 * TL::LDB + fn * 16];
-    }
+    for (int fn = 0; fn < TL::FN; ++fn) b[fn] = bsign * Br[((wn0 + fn * 8 + (i >> 1)) * ldbn + k) * 2 + bpart];
 #pragma unroll
     for (int fm = 0; fm < TL::FM; ++fm)
 #pragma unroll
-      for (int fn = 0; fn < TL::FN; ++fn) acc[fm][fn] = Mfma<T>::op(a[c][fm], b[c][fn], acc[fm][fn]);
-    if (kk + 1 < KK) {
-#pragma unroll
-      for (int r = 0; r < NR && r < TL::FM * TL::FN; ++r) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
-      }
-      if (TL::FM * TL::FN > NR) __builtin_amdgcn_sched_group_barrier(0x008, TL::FM * TL::FN - NR, 0);
-    }
+      for (int fn = 0; fn < TL::FN; ++fn) acc[fm][fn] = Mfma<T>::op(a[fm], b[fn], acc[fm][fn]);
   }
 }
 
