@@ -549,6 +549,20 @@ isdf_status stage_out(Run& R, const Basis& b, void* out, Timer& tm) {
   const Problem& P = R.P;
   const Layout& L = R.L;
   const Prec cp = P.prec == P64 ? P64 : P32;
+  if (P.m32 && b.sg == 1 && b.smu == P.ng && gemm32_fits(P.nmu, P.ng, P.nmu, b.base, P.ng, b.base, P.ng) &&
+      gemm32_fits(P.ng, P.ng, P.nmu, at<char>(R.ws, L.w1), P.ng, b.base, P.ng)) {
+    // Mixed path with the basis stored [point][plane wave] (X^T): both products
+    // have k-major operands.  W^T = talpha T^T X^T, then eps~^{-1} = I - W X^H.
+    // T goes to complex64 in the refinement-residual buffer (free by now).
+    void* t32 = at<char>(R.ws, L.rres);
+    void* wt = at<char>(R.ws, L.w1);
+    HIPCHK(convert_z(R.tmat, false, t32, true, (long)P.nmu * P.nmu, R.st));
+    HIPCHK(gemm32_kmajor(P.nmu, P.ng, P.nmu, t32, P.nmu, false, b.base, P.ng, false, wt, P.ng, false,
+                         R.talpha, R.st));
+    tm.mark();
+    HIPCHK(gemm32_kmajor(P.ng, P.ng, P.nmu, wt, P.ng, false, b.base, P.ng, true, out, P.ng, true, -1.0, R.st));
+    return ISDF_OK;
+  }
   GemmDesc d;  // W1 = B T
   d.M = P.ng; d.N = P.nmu; d.K = P.nmu;
   d.A = b.base; d.sam = b.sg; d.sak = b.smu; d.a32 = P.m32;

@@ -26,6 +26,16 @@ struct GemmDesc {
 };
 // Compute precision: P64 -> f64 MFMA; P32 -> f32 MFMA.
 hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st);
+// Single-precision complex GEMM with k-major operands, full tiles only
+// (M % 128 = N % 64 = K % 16 = 0, even leading dimensions, 16-byte aligned bases;
+// otherwise hipErrorNotSupported and nothing is launched):
+//   A(m, k) = A[k lda + m], B(k, n) = B[k ldb + n] (complex64, optionally conjugated)
+//   herm_identity = false: C[m][n] = alpha (A B)[m][n], complex64, ldc
+//   herm_identity = true (M = N): C = I + alpha A B, complex128, lower triangle
+//     computed and mirrored (the product must be Hermitian), diagonal real
+hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conjA, const void* B, long ldb,
+                         bool conjB, void* C, long ldc, bool herm_identity, double alpha, hipStream_t st);
+bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, long ldb);
 
 // ----- orbital pair Gram (step 1):  out[mu][c] = conj(Pv(mu, c)) * Qc(mu, c)
 //   Pv(mu, c) = sum_{i < nv} conj(pm[i][mu]) b[i][c],  Qc(mu, c) = sum_{nv <= j < ns} conj(pm[j][mu]) b[j][c]

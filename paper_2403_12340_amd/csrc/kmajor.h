@@ -1,0 +1,146 @@
+// Single-precision complex GEMM engine for k-major operands on gfx950 (shared
+// by the pair-Gram kernel and the output GEMMs).
+//
+// C (M x N) += A (M x K) B (K x N) with A(m, k) at A[k * lda + m] and B(k, n) at
+// B[k * ldb + n] (complex64), on f32 16x16x4 MFMA via the real block form of
+// the complex product (see tile.h).  A workgroup of 8 waves owns a 128 x 64
+// tile; each wave a 32 x 32 block.
+#pragma once
+
+#include "tile.h"
+
+namespace isdf {
+
+// A is staged as interleaved complex rows padded to 2 LDA = 32 (mod 64) floats;
+// B in the expanded four-float form, rows padded to 4 LDB = 32 (mod 64) floats,
+// so lanes 0-31 and 32-63 of each LDS read fall on disjoint banks.  The K loop
+// is double-buffered in LDS and the fragments of the next MFMA step are read
+// while the current one runs.
+struct ZL {
+  static constexpr int BM = 128, BN = 64, BK = 16, WGM = 4, WGN = 2, NT = 512;
+  static constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 16, FN = WTN / 8;
+  static constexpr int LDA = BM + 16;     // complex per A row
+  static constexpr int LDB = BN + 8;      // four-float groups per B row
+  static constexpr int AS = BK * LDA * 2;  // floats per A stage
+  static constexpr int BS = BK * LDB * 4;  // floats per B stage
+};
+
+__device__ __forceinline__ void zl_mma(const float* __restrict__ Af, const float* __restrict__ Bf,
+                                       f4 (&acc)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
+  constexpr int KK = ZL::BK / 2;
+  const int i = lane & 15, q = lane >> 4;
+  const float* ap = Af + ((q >> 1) * ZL::LDA + wm0 + i) * 2 + (q & 1);
+  const float* bp = Bf + ((q >> 1) * ZL::LDB + wn0 + (i >> 1)) * 4 + 2 * (q & 1) + (i & 1);
+  float a[2][ZL::FM], b[2][ZL::FN];
+#pragma unroll
+  for (int fm = 0; fm < ZL::FM; ++fm) a[0][fm] = ap[fm * 32];
+#pragma unroll
+  for (int fn = 0; fn < ZL::FN; ++fn) b[0][fn] = bp[fn * 32];
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) {
+    const int c = kk & 1;
+    if (kk + 1 < KK) {
+#pragma unroll
+      for (int fm = 0; fm < ZL::FM; ++fm) a[c ^ 1][fm] = ap[(kk + 1) * 4 * ZL::LDA + fm * 32];
+#pragma unroll
+      for (int fn = 0; fn < ZL::FN; ++fn) b[c ^ 1][fn] = bp[(kk + 1) * 8 * ZL::LDB + fn * 32];
+    }
+#pragma unroll
+    for (int fm = 0; fm < ZL::FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = Mfma<float>::op(a[c][fm], b[c][fn], acc[fm][fn]);
+    // issue order: the next step's LDS reads between this step's MFMAs
+    if (kk + 1 < KK) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, ZL::FM * ZL::FN - 3, 0);
+    }
+  }
+}
+
+// Interior tiles: every K tile full, so no bounds logic at all.  Each thread
+// moves two complex values per 16-byte load at offsets fixed for the whole
+// kernel (only the uniform tile base advances), and the two LDS stages are
+// addressed statically (the K loop is unrolled by two).
+struct ZFetch {
+  uint32_t aoff0, aoff1, boff;  // byte offsets of this thread's loads from the tile base
+  int ax, ak, bx, bk;           // its positions in the A (16 x 128) and B (16 x 64) tiles
+  f4 ra0, ra1, rb;              // staged data of one K tile
+  __device__ __forceinline__ void init(int tid, long ldp, long ldb) {
+    ax = 2 * (tid & 63); ak = tid >> 6; bx = 2 * (tid & 31); bk = tid >> 5;
+    aoff0 = (uint32_t)((ak * ldp + ax) * 8);
+    aoff1 = (uint32_t)(((ak + 8) * ldp + ax) * 8);
+    boff = (uint32_t)((bk * ldb + bx) * 8);
+  }
+  // K tile t of the tile at (m0, n0): rows [16 t, 16 t + 16) of both k-major operands
+  __device__ __forceinline__ void fetch(const c32* pm, long ldp, const c32* b, long ldb, int m0, int n0, int t) {
+    const long kr = (long)t * ZL::BK;
+    const char* pa = reinterpret_cast<const char*>(pm + kr * ldp + m0);
+    const char* pb = reinterpret_cast<const char*>(b + kr * ldb + n0);
+    ra0 = *reinterpret_cast<const f4*>(pa + aoff0);
+    ra1 = *reinterpret_cast<const f4*>(pa + aoff1);
+    rb = *reinterpret_cast<const f4*>(pb + boff);
+  }
+  // sa, sb = +1 or -1: the sign of the imaginary parts (-1 conjugates the operand)
+  __device__ __forceinline__ void stage(float* buf, float sa, float sb) const {
+    // A interleaved (re, sa im); B in the four-float form (re, sb im, -sb im, re)
+    *reinterpret_cast<f4*>(buf + (ak * ZL::LDA + ax) * 2) = f4{ra0[0], sa * ra0[1], ra0[2], sa * ra0[3]};
+    *reinterpret_cast<f4*>(buf + ((ak + 8) * ZL::LDA + ax) * 2) = f4{ra1[0], sa * ra1[1], ra1[2], sa * ra1[3]};
+    float* bb = buf + ZL::AS + (bk * ZL::LDB + bx) * 4;
+    const float i0 = sb * rb[1], i1 = sb * rb[3];
+    *reinterpret_cast<f4*>(bb) = f4{rb[0], i0, -i0, rb[0]};
+    *reinterpret_cast<f4*>(bb + 4) = f4{rb[2], i1, -i1, rb[2]};
+  }
+};
+
+// K loop of one interior tile whose first K tile is already in `zf`: K tiles
+// t < tp accumulate into accp, the rest into accq (pass the same array twice for
+// a single accumulator).  During the last K tile it prefetches the first K tile
+// of the next interior tile (if any), so that tile's load latency hides behind
+// this tile's MFMAs and epilogue.
+__device__ __forceinline__ void zl_loop_full(float* smem, ZFetch& zf, int tp, int nt, float sa, float sb,
+                                             const c32* A, long lda, const c32* B, long ldb, int m0, int n0,
+                                             bool has_next, int nm0, int nn0, f4 (&accp)[ZL::FM][ZL::FN],
+                                             f4 (&accq)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
+  float* buf0 = smem;
+  float* buf1 = smem + ZL::AS + ZL::BS;
+  auto prefetch = [&](int t) {
+    if (t < nt) zf.fetch(A, lda, B, ldb, m0, n0, t);
+    else if (has_next) zf.fetch(A, lda, B, ldb, nm0, nn0, 0);
+  };
+  auto mma = [&](int t, const float* buf) {
+    if (t < tp) zl_mma(buf, buf + ZL::AS, accp, wm0, wn0, lane);
+    else zl_mma(buf, buf + ZL::AS, accq, wm0, wn0, lane);
+  };
+  zf.stage(buf0, sa, sb);
+  __syncthreads();
+  for (int t = 0; t < nt; t += 2) {
+    prefetch(t + 1);
+    mma(t, buf0);
+    if (t + 1 < nt) zf.stage(buf1, sa, sb);
+    __syncthreads();
+    if (t + 1 >= nt) break;
+    prefetch(t + 2);
+    mma(t + 1, buf1);
+    if (t + 2 < nt) zf.stage(buf0, sa, sb);
+    __syncthreads();
+  }
+}
+
+// CUs of the current device (cached per device)
+inline int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+}  // namespace isdf

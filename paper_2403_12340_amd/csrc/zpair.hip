@@ -13,6 +13,7 @@
 //   computed (mirrored), and the occupied index is split across workgroups with
 //   a deterministic fixed-order reduction.
 #include "internal.h"
+#include "kmajor.h"
 #include "tile.h"
 
 #include <algorithm>
@@ -92,60 +93,10 @@ __global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int
 }
 
 // ----------------------------------------------------------------------------
-// Single-precision pair kernel: 128 points x 64 grid columns per workgroup,
-// 8 waves of 32 x 32.  A (the orbitals at the points, conjugated) is staged as
-// interleaved complex rows padded to 2 LDA = 32 (mod 64) floats; B (the grid
-// orbitals) in the expanded four-float form, rows padded to 4 LDB = 32 (mod 64)
-// floats, so lanes 0-31 and 32-63 of each LDS read fall on disjoint banks.
-// The K loop runs the occupied tiles into P and then the empty ones into Q as
-// one double-buffered pipeline, and the LDS fragments of the next MFMA step are
-// read while the current one runs.
+// Single-precision pair kernel: 128 points x 64 grid columns per workgroup on
+// the k-major engine of kmajor.h; the occupied K tiles accumulate into P and the
+// empty ones into Q in one pipeline.
 // ----------------------------------------------------------------------------
-struct ZL {
-  static constexpr int BM = 128, BN = 64, BK = 16, WGM = 4, WGN = 2, NT = 512;
-  static constexpr int WTM = BM / WGM, WTN = BN / WGN, FM = WTM / 16, FN = WTN / 8;
-  static constexpr int LDA = BM + 16;     // complex per A row
-  static constexpr int LDB = BN + 8;      // four-float groups per B row
-  static constexpr int AS = BK * LDA * 2;  // floats per A stage
-  static constexpr int BS = BK * LDB * 4;  // floats per B stage
-};
-
-__device__ __forceinline__ void zl_mma(const float* __restrict__ Af, const float* __restrict__ Bf,
-                                       f4 (&acc)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
-  constexpr int KK = ZL::BK / 2;
-  const int i = lane & 15, q = lane >> 4;
-  const float* ap = Af + ((q >> 1) * ZL::LDA + wm0 + i) * 2 + (q & 1);
-  const float* bp = Bf + ((q >> 1) * ZL::LDB + wn0 + (i >> 1)) * 4 + 2 * (q & 1) + (i & 1);
-  float a[2][ZL::FM], b[2][ZL::FN];
-#pragma unroll
-  for (int fm = 0; fm < ZL::FM; ++fm) a[0][fm] = ap[fm * 32];
-#pragma unroll
-  for (int fn = 0; fn < ZL::FN; ++fn) b[0][fn] = bp[fn * 32];
-#pragma unroll
-  for (int kk = 0; kk < KK; ++kk) {
-    const int c = kk & 1;
-    if (kk + 1 < KK) {
-#pragma unroll
-      for (int fm = 0; fm < ZL::FM; ++fm) a[c ^ 1][fm] = ap[(kk + 1) * 4 * ZL::LDA + fm * 32];
-#pragma unroll
-      for (int fn = 0; fn < ZL::FN; ++fn) b[c ^ 1][fn] = bp[(kk + 1) * 8 * ZL::LDB + fn * 32];
-    }
-#pragma unroll
-    for (int fm = 0; fm < ZL::FM; ++fm)
-#pragma unroll
-      for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = Mfma<float>::op(a[c][fm], b[c][fn], acc[fm][fn]);
-    // issue order: the next step's LDS reads between this step's MFMAs
-    if (kk + 1 < KK) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      }
-      __builtin_amdgcn_sched_group_barrier(0x008, ZL::FM * ZL::FN - 3, 0);
-    }
-  }
-}
-
 // Generic K loop (any tile edge): clamped loads, masked LDS stores.
 __device__ __forceinline__ void zl_loop_generic(float* smem, int M, int N, int nv, int ns, const c32* pm,
                                                 long ldp, const c32* b, long ldb, int m0, int n0,
@@ -184,72 +135,6 @@ __device__ __forceinline__ void zl_loop_generic(float* smem, int M, int N, int n
       sa.store(reinterpret_cast<c32*>(sn), ZL::LDA, -1.f, tid);
       store_b4(sb, sn + ZL::AS, ZL::LDB, 1.f, tid);
     }
-    __syncthreads();
-  }
-}
-
-// Interior tiles: every K tile full, so no bounds logic at all.  Each thread
-// moves two complex values per 16-byte load at offsets fixed for the whole
-// kernel (only the uniform tile base advances), and the two LDS stages are
-// addressed statically (the K loop is unrolled by two).
-struct ZFetch {
-  uint32_t aoff0, aoff1, boff;  // byte offsets of this thread's loads from the tile base
-  int ax, ak, bx, bk;           // its positions in the A (16 x 128) and B (16 x 64) tiles
-  f4 ra0, ra1, rb;              // staged data of one K tile
-  __device__ __forceinline__ void init(int tid, long ldp, long ldb) {
-    ax = 2 * (tid & 63); ak = tid >> 6; bx = 2 * (tid & 31); bk = tid >> 5;
-    aoff0 = (uint32_t)((ak * ldp + ax) * 8);
-    aoff1 = (uint32_t)(((ak + 8) * ldp + ax) * 8);
-    boff = (uint32_t)((bk * ldb + bx) * 8);
-  }
-  // K tile t of the tile at (m0, n0): orbital rows [16 t, 16 t + 16) (occupied rows first)
-  __device__ __forceinline__ void fetch(const c32* pm, long ldp, const c32* b, long ldb, int m0, int n0, int t) {
-    const long kr = (long)t * ZL::BK;
-    const char* pa = reinterpret_cast<const char*>(pm + kr * ldp + m0);
-    const char* pb = reinterpret_cast<const char*>(b + kr * ldb + n0);
-    ra0 = *reinterpret_cast<const f4*>(pa + aoff0);
-    ra1 = *reinterpret_cast<const f4*>(pa + aoff1);
-    rb = *reinterpret_cast<const f4*>(pb + boff);
-  }
-  __device__ __forceinline__ void stage(float* buf) const {
-    // A conjugated: interleaved (re, -im); B in the four-float form
-    *reinterpret_cast<f4*>(buf + (ak * ZL::LDA + ax) * 2) = f4{ra0[0], -ra0[1], ra0[2], -ra0[3]};
-    *reinterpret_cast<f4*>(buf + ((ak + 8) * ZL::LDA + ax) * 2) = f4{ra1[0], -ra1[1], ra1[2], -ra1[3]};
-    float* bb = buf + ZL::AS + (bk * ZL::LDB + bx) * 4;
-    *reinterpret_cast<f4*>(bb) = f4{rb[0], rb[1], -rb[1], rb[0]};
-    *reinterpret_cast<f4*>(bb + 4) = f4{rb[2], rb[3], -rb[3], rb[2]};
-  }
-};
-
-// K loop of one interior tile whose first K tile is already in `zf`.  During the
-// last K tile it prefetches the first K tile of the next interior tile (if any),
-// so that tile's load latency hides behind this tile's MFMAs and epilogue.
-__device__ __forceinline__ void zl_loop_full(float* smem, ZFetch& zf, int nv, int ns, const c32* pm, long ldp,
-                                             const c32* b, long ldb, int m0, int n0, bool has_next,
-                                             int nm0, int nn0, f4 (&accp)[ZL::FM][ZL::FN],
-                                             f4 (&accq)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
-  const int tp = nv / ZL::BK, nt = ns / ZL::BK;
-  float* buf0 = smem;
-  float* buf1 = smem + ZL::AS + ZL::BS;
-  auto prefetch = [&](int t) {
-    if (t < nt) zf.fetch(pm, ldp, b, ldb, m0, n0, t);
-    else if (has_next) zf.fetch(pm, ldp, b, ldb, nm0, nn0, 0);
-  };
-  auto mma = [&](int t, const float* buf) {
-    if (t < tp) zl_mma(buf, buf + ZL::AS, accp, wm0, wn0, lane);
-    else zl_mma(buf, buf + ZL::AS, accq, wm0, wn0, lane);
-  };
-  zf.stage(buf0);
-  __syncthreads();
-  for (int t = 0; t < nt; t += 2) {
-    prefetch(t + 1);
-    mma(t, buf0);
-    if (t + 1 < nt) zf.stage(buf1);
-    __syncthreads();
-    if (t + 1 >= nt) break;
-    prefetch(t + 2);
-    mma(t + 1, buf1);
-    if (t + 2 < nt) zf.stage(buf0);
     __syncthreads();
   }
 }
@@ -299,8 +184,8 @@ void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const c32* b, long 
     for (int fm = 0; fm < ZL::FM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < ZL::FN; ++fn) accp[fm][fn] = accq[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
-    zl_loop_full(smem, zf, nv, ns, pm, ldp, b, ldb, m0, n0, has_next, (nid % nti) * ZL::BM,
-                 (nid / nti) * ZL::BN, accp, accq, wm0, wn0, lane);
+    zl_loop_full(smem, zf, nv / ZL::BK, ns / ZL::BK, -1.f, 1.f, pm, ldp, b, ldb, m0, n0, has_next,
+                 (nid % nti) * ZL::BM, (nid / nti) * ZL::BN, accp, accq, wm0, wn0, lane);
     zl_epilogue(out, ldo, (m0 + ZL::BM), (n0 + ZL::BN), m0, n0, accp, accq, wm0, wn0, lane);
   }
 }
@@ -334,18 +219,6 @@ __global__ __launch_bounds__(ZL::NT) void zpair32_edge_kernel(int M, int N, int 
     for (int fn = 0; fn < ZL::FN; ++fn) accp[fm][fn] = accq[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
   zl_loop_generic(smem, M, N, nv, ns, pm, ldp, b, ldb, m0, n0, accp, accq, tid, wm0, wn0, lane);
   zl_epilogue(out, ldo, M, N, m0, n0, accp, accq, wm0, wn0, lane);
-}
-
-static int cu_count() {
-  static int cached[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cached[dev] == 0) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cached[dev] = n;
-  }
-  return cached[dev];
 }
 
 static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,

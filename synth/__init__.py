@@ -55,6 +55,8 @@ CONFIGS = {
     "tiny": dict(n=8, nv=3, nc=5, nmu=12, ng=40, complex=True, seed=7),
     # 16-aligned state counts with ragged points and grid: interior tiles plus both edge strips.
     "tiles": dict(n=22, nv=16, nc=48, nmu=200, ng=600, complex=True, seed=10),
+    # Full tiles everywhere (points and plane waves multiples of 128): the interior fast paths.
+    "kmaj": dict(n=20, nv=16, nc=48, nmu=256, ng=512, complex=True, seed=11),
     # Full rank: N_mu = Nv * Nc, where ISDF is exact.
     "fullrank": dict(n=12, nv=4, nc=6, nmu=24, ng=200, complex=True, seed=8),
     "fullrank_real": dict(n=12, nv=4, nc=6, nmu=24, ng=200, complex=False, seed=9),

@@ -17,7 +17,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank", "tiles"]
+SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank", "tiles", "kmaj"]
 TOL_EPS = {"fp64": 1e-10, "fp32": 1e-6}
 TOL_STAGE = {"fp64": 1e-10, "fp32": 1e-4}
 
