@@ -59,7 +59,7 @@ def flops_model(inp):
     }
 
 
-ZPAIR_SOURCES = ["zpair.hip", "tile.h", "common.h"]
+ZPAIR_SOURCES = ["zpair.hip", "kmajor.h", "tile.h", "common.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zpair_fp32_48cubed_nmu640_traffic.txt")
 
 
@@ -129,7 +129,7 @@ def summarize(args):
         for key, db, ctr in (("fetch", args.pmc_fetch, "FETCH_SIZE"), ("write", args.pmc_write, "WRITE_SIZE")):
             rows = _pmc_per_dispatch(db, ctr)
             copy = [v for n, g, v in rows if "convert_kernel<double, float>" in n]
-            zp = [v for n, g, v in rows if "zpair_kernel<float" in n and g > 1 << 20]
+            zp = [v for n, g, v in rows if n.startswith("isdf::zpair32_kernel(")]
             res[key] = (max(copy) if copy else None, sum(zp) / len(zp) if zp else None, len(zp))
         nbytes = inp.nv + inp.nc
         exp_fetch = nbytes * inp.nr * 16.0   # copy reads complex128
@@ -139,7 +139,7 @@ def summarize(args):
         zf = res["fetch"][1] * 1024.0 * f_fetch
         zw = res["write"][1] * 1024.0 * f_write
         lines.append("")
-        lines.append(f"HBM traffic of zpair_kernel<float> (pair-Gram, {args.config}), from FETCH_SIZE / WRITE_SIZE (KiB per dispatch)")
+        lines.append(f"HBM traffic of zpair32_kernel (pair-Gram, {args.config}), from FETCH_SIZE / WRITE_SIZE (KiB per dispatch)")
         lines.append(f"  calibration copy (orbitals complex128 -> complex64): expected fetch {exp_fetch:.4e} B, "
                      f"write {exp_write:.4e} B; counter factors fetch {f_fetch:.4f}, write {f_write:.4f}")
         lines.append(f"  zpair dispatches: {res['fetch'][2]} / {res['write'][2]}; calibrated fetch {zf:.4e} B, write {zw:.4e} B, "
@@ -225,7 +225,7 @@ def main():
     z_ms = m["stage_ms"][1]
     achieved = fl["zpair"] / (z_ms * 1e-3) / 1e12
     traffic = recorded_traffic()
-    roofline = {"kernel": "zpair_kernel<float> (Z = conj(Pv) * Qc over N_mu x Nr x (Nv + Nc))", "bound": "mfma",
+    roofline = {"kernel": "zpair32_kernel (Z = conj(Pv) * Qc over N_mu x Nr x (Nv + Nc))", "bound": "mfma",
                 "achieved": round(achieved, 2), "peak": PEAK["fp32"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["fp32"], 4), "traffic": traffic,
                 "flops_per_launch": fl["zpair"], "avg_ms": round(z_ms, 4)}
@@ -275,7 +275,7 @@ def main():
                                "fp64": round(total_flops / (results["fp64"]["ms_per_step"] * 1e-3) / 1e12, 2)},
         "stage_ms": {"mixed": [round(x, 4) for x in m["stage_ms"]],
                      "fp64": [round(x, 4) for x in results["fp64"]["stage_ms"]],
-                     "names": ["gather + operand conversion", "Z (pair-Gram kernel)", "DFT to X", "X^H X",
+                     "names": ["gather, first core M, operand conversion", "Z (pair-Gram kernel)", "DFT to X", "X^H X",
                                "core solve (waits for K = S M^-1 S)", "W = X H^-1", "output", "-"],
                      "note": "intervals on the caller's stream; S, M, M^-1 and K run on a second stream"},
         "roofline": roofline,

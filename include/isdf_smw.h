@@ -85,7 +85,7 @@ typedef struct {
 
 typedef struct {
   double stage_ms[8];        /* filled when want_timing != 0: HIP-event intervals on the caller's stream.
-                                isdf_eps_inv: [0] point gather and operand conversion, [1] the pair
+                                isdf_eps_inv: [0] point gather, first core M, operand conversion, [1] the pair
                                 product Z (exactly one kernel launch), [2] DFT to X = V^{1/2} F Z,
                                 [3] X^H X, [4] core solve (waits for K = S M^{-1} S from the
                                 library's second stream, H = X^H X - K, H^{-1}, refinement),

@@ -41,7 +41,7 @@ struct isdf_handle_s {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t ev[10] = {};         // stage timing (main stream)
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, core0 = nullptr;
   hipEvent_t m_ready[2] = {}, m_used[2] = {};
   std::string err;
 };
@@ -695,12 +695,15 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   const int ng = R.P.ng;
   TRY(prepare_psi(R, psi));
   TRY(stage_points(R));
-  // Fork: the side stream forms S = C C^H and, per frequency, M, M^{-1} and
+  // Fork: the side stream forms S = C C^H and, per frequency, M^{-1} and
   // K = S M^{-1} S (double-buffered), while this stream runs Z, the DFT to
   // X = V^{1/2} F Z and X^H X.  Then eps~^{-1} = I - X (X^H X - K)^{-1} X^H, which
   // equals eq. epsilon_with_SMW with U = X S^{-1}; S^{-1} is never formed.
-  // Work is enqueued frequency by frequency so that every stream wait is
-  // enqueued after the event record it waits for.
+  // The first core M (a compute-bound kernel that would otherwise hold the CUs
+  // the pair kernel starts on) runs on this stream ahead of Z; the later ones,
+  // and every latency-bound sweep step, run on the side stream.  Work is enqueued
+  // frequency by frequency so that every stream wait is enqueued after the event
+  // record it waits for.
   hipStream_t side = h->side;
   HIPCHK(hipEventRecord(h->fork, R.st));
   HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
@@ -708,7 +711,13 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   void* mbuf[2] = {at<char>(R.ws, R.L.l), at<char>(R.ws, R.L.l2)};
   auto side_core = [&](int k) -> isdf_status {
     if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
-    TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
+    if (k == 0) {
+      TRY(stage_core(R, n_omega ? omega[0] : 0.0, nullptr, mbuf[0], R.st));
+      HIPCHK(hipEventRecord(h->core0, R.st));
+      HIPCHK(hipStreamWaitEvent(side, h->core0, 0));
+    } else {
+      TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
+    }
     HIPCHK(sweep_inverse(R.P.nmu, mbuf[k & 1], at<char>(R.ws, R.L.lin2), &R.sb->status, side));  // M^{-1}
     TRY(stage_smis(R, mbuf[k & 1], at<char>(R.ws, R.L.q), side));                                 // S M^{-1} S
     HIPCHK(hipEventRecord(h->m_ready[k & 1], side));
@@ -760,7 +769,7 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
   if (hipSetDevice(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
-  for (hipEvent_t* e : {&h->fork, &h->join, &h->m_ready[0], &h->m_ready[1], &h->m_used[0], &h->m_used[1]})
+  for (hipEvent_t* e : {&h->fork, &h->join, &h->core0, &h->m_ready[0], &h->m_ready[1], &h->m_used[0], &h->m_used[1]})
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   // default priority, non-blocking with respect to the legacy default stream
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
@@ -781,7 +790,7 @@ isdf_status isdf_destroy(isdf_handle h) {
     (void)hipStreamDestroy(h->side);
   }
   for (auto& e : h->ev) if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {h->fork, h->join, h->m_ready[0], h->m_ready[1], h->m_used[0], h->m_used[1]})
+  for (hipEvent_t e : {h->fork, h->join, h->core0, h->m_ready[0], h->m_ready[1], h->m_used[0], h->m_used[1]})
     if (e) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
