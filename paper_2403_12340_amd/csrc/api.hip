@@ -116,6 +116,8 @@ struct Layout {
          miller = 0, recip = 0, sqrtv = 0, idx = 0, total = 0;
   size_t twx = 0, twy = 0, twz = 0;  // inside tabs
   size_t w1 = 0;                     // aliases the zt region
+  // frequency batch (n_omega >= 2): weights, core partials, M / M^{-1} / K, sweep scratch, S M^{-1}, H / T
+  size_t wb = 0, partb = 0, mb = 0, lb = 0, qb = 0, hb = 0;
   size_t zt_bytes = 0;               // size of the zt region
   size_t part = 0, l2 = 0, lin2 = 0, q = 0;  // core partials; second -M buffer, sweep scratch, S M^-1 S scratch
   size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (mixed precision only)
@@ -165,6 +167,15 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.x = take(nmu2 * z);
   L.rres = take(nmu2 * z);
   L.t = take(nmu2 * z);
+  if (P.nomega >= 2) {
+    const size_t nb = (size_t)P.nomega;
+    L.wb = take(nb * P.nv * P.nc * 8);
+    L.partb = take(nb * nmu2 * el);
+    L.mb = take(nb * nmu2 * z);
+    L.lb = take(nb * nmu2 * z);
+    L.qb = take(nb * nmu2 * z);
+    L.hb = take(nb * nmu2 * z);
+  }
   // big region: Zt (N_mu x Nr); once the DFT has consumed it, reused for the
   // split-K partial sums of U^H U and for U T
   const size_t zt_bytes = (size_t)P.nmu * P.nr * el;
@@ -502,29 +513,23 @@ isdf_status stage_core(Run& R, double omega, void* m_out, void* negm, hipStream_
 //   B = U (= X S^{-1}):  G = U^H U, K = M^{-1}
 //   B = X (= V^{1/2} F Z): G = X^H X, K = S M^{-1} S   (S^{-1} never formed)
 // `used` (optional) is recorded once K has been read.
-isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
+// FP64 Newton refinement T <- T + T (I - H T) of an inverse, from Hc (a copy of H)
+// and T0 = tneg * (first inverse), with residuals ||I - H T_k||_F^2 in the status
+// block; sets R.tmat / R.talpha.
+isdf_status refine_inverse(Run& R, const void* Hc, const void* Tfirst, double tneg) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Layout& L = R.L;
   const int n = P.nmu;
   const long n2 = (long)n * n;
-  void* H = at<char>(R.ws, L.a);
-  HIPCHK(axpby(at<char>(R.ws, L.g), 1.0, Mi, -1.0, H, n2, R.st));                   // H = G - K
-  if (used) HIPCHK(hipEventRecord(used, R.st));
-  HIPCHK(diag_min(H, n, &R.sb->min_pivot, R.st));
-  if (P.refine > 0) HIPCHK(convert_z(H, false, at<char>(R.ws, L.acopy), false, n2, R.st));
-  HIPCHK(sweep_inverse(n, H, at<char>(R.ws, L.lin), &R.sb->status, R.st));          // -T
-  R.tmat = H;
-  R.talpha = -1.0;
-  if (P.refine == 0) return ISDF_OK;
   void* T = at<char>(R.ws, L.t);
   void* T2 = at<char>(R.ws, L.x);
   void* Rr = at<char>(R.ws, L.rres);
-  HIPCHK(scale_z(H, T, n2, -1.0, R.st));
+  HIPCHK(scale_z(Tfirst, T, n2, tneg, R.st));
   for (int k = 0; k <= P.refine; ++k) {
     GemmDesc r;  // Rr = I - H T
     r.M = r.N = r.K = n;
-    r.A = at<char>(R.ws, L.acopy); r.sam = n; r.sak = 1;
+    r.A = Hc; r.sam = n; r.sak = 1;
     r.B = T; r.sbk = n; r.sbn = 1;
     r.C = Rr; r.ldc = n; r.alpha = -1.0; r.diag_add = 1.0;
     HIPCHK(gemm(P64, r, R.st));
@@ -542,6 +547,24 @@ isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   R.tmat = T;
   R.talpha = 1.0;
   return ISDF_OK;
+}
+
+isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const int n = P.nmu;
+  const long n2 = (long)n * n;
+  void* H = at<char>(R.ws, L.a);
+  HIPCHK(axpby(at<char>(R.ws, L.g), 1.0, Mi, -1.0, H, n2, R.st));                   // H = G - K
+  if (used) HIPCHK(hipEventRecord(used, R.st));
+  HIPCHK(diag_min(H, n, &R.sb->min_pivot, R.st));
+  if (P.refine > 0) HIPCHK(convert_z(H, false, at<char>(R.ws, L.acopy), false, n2, R.st));
+  HIPCHK(sweep_inverse(n, H, at<char>(R.ws, L.lin), &R.sb->status, R.st));          // -T
+  R.tmat = H;
+  R.talpha = -1.0;
+  if (P.refine == 0) return ISDF_OK;
+  return refine_inverse(R, at<char>(R.ws, L.acopy), H, -1.0);
 }
 
 isdf_status stage_out(Run& R, const Basis& b, void* out, Timer& tm) {
@@ -689,12 +712,93 @@ isdf_status clear_status(Run& R) {
 // Enqueue the whole path on the handle's stream (and its second stream, joined
 // back before returning).  No host synchronisation; the status block collects
 // error bits.
+// Frequency batch (n_omega >= 2).  X, X^H X and S are frequency independent and
+// formed once; every frequency-dependent step runs as one batched launch over
+// all frequencies: the weights and cores M(omega) (this stream, ahead of Z), the
+// sweeps to M(omega)^{-1} and K(omega) = S M^{-1} S (second stream, overlapping
+// Z and the DFT), H(omega) = X^H X - K(omega) and its sweep (this stream).  Only
+// the two output products run per frequency.
+isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* eps_inv, Timer& tm) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  const int n = P.nmu, ng = P.ng;
+  const long n2 = (long)n * n;
+  hipStream_t side = h->side;
+  HIPCHK(hipEventRecord(h->fork, R.st));
+  HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
+  TRY(stage_s(R, side, L.lin2, false));
+  double* wb = at<double>(R.ws, L.wb);
+  for (int k = 0; k < nw; ++k)
+    HIPCHK(pair_weights(R.e, P.nv, P.nc, omega[k], wb + (long)k * P.nv * P.nc, R.st));
+  void* mb = at<char>(R.ws, L.mb);
+  HIPCHK(core_partial(cp, n, P.nv, P.nc, at<char>(R.ws, L.pm), n, wb, at<char>(R.ws, L.partb), 1, R.st, nw));
+  HIPCHK(core_reduce(cp, n, at<char>(R.ws, L.partb), 1, P.f, nullptr, mb, R.st, nw));      // -M(omega)
+  HIPCHK(hipEventRecord(h->core0, R.st));
+  HIPCHK(hipStreamWaitEvent(side, h->core0, 0));
+  HIPCHK(sweep_inverse(n, mb, at<char>(R.ws, L.lb), &R.sb->status, side, nw));            // M(omega)^{-1}
+  {
+    const void* sk = at<char>(R.ws, L.s);   // S^T = conj(S)
+    void* qb = at<char>(R.ws, L.qb);
+    GemmDesc a;  // q = M^{-1} S
+    a.M = a.N = a.K = n;
+    a.A = mb; a.sam = n; a.sak = 1;
+    a.B = sk; a.sbk = n; a.sbn = 1; a.conjB = true;
+    a.C = qb; a.ldc = n;
+    a.batch = nw; a.bsa = n2; a.bsb = 0; a.bsc = n2;
+    HIPCHK(gemm(P64, a, side));
+    GemmDesc b;  // K = S q, over M^{-1}
+    b.M = b.N = b.K = n;
+    b.A = sk; b.sam = n; b.sak = 1; b.conjA = true;
+    b.B = qb; b.sbk = n; b.sbn = 1;
+    b.C = mb; b.ldc = n;
+    b.batch = nw; b.bsa = 0; b.bsb = n2; b.bsc = n2;
+    HIPCHK(gemm(P64, b, side));
+  }
+  HIPCHK(hipEventRecord(h->m_ready[0], side));
+  TRY(stage_z_operands(R));
+  tm.mark();
+  TRY(stage_z(R));
+  tm.mark();
+  TRY(stage_dft(R, true));
+  tm.mark();
+  const Basis xb{at<char>(R.ws, L.zg), 1, (long)ng};
+  TRY(stage_gram(R, xb));
+  tm.mark();
+  HIPCHK(hipStreamWaitEvent(R.st, h->m_ready[0], 0));
+  void* hb = at<char>(R.ws, L.hb);
+  HIPCHK(sub_bcast(at<char>(R.ws, L.g), mb, hb, n2, nw, R.st));                          // H(omega)
+  HIPCHK(diag_min(hb, n, &R.sb->min_pivot, R.st, nw));
+  HIPCHK(sweep_inverse(n, hb, at<char>(R.ws, L.lb), &R.sb->status, R.st, nw));            // -T(omega)
+  for (int k = 0; k < nw; ++k) {
+    Timer dummy{h, false};
+    Timer& t = (k == nw - 1) ? tm : dummy;
+    char* tk = at<char>(R.ws, L.hb) + (size_t)k * n2 * 16;
+    R.tmat = tk;
+    R.talpha = -1.0;
+    if (P.refine > 0) {
+      void* hc = at<char>(R.ws, L.acopy);
+      HIPCHK(sub_bcast(at<char>(R.ws, L.g), at<char>(R.ws, L.mb) + (size_t)k * n2 * 16, hc, n2, 1, R.st));
+      TRY(refine_inverse(R, hc, tk, -1.0));
+    }
+    t.mark();
+    void* out = reinterpret_cast<char*>(eps_inv) + (size_t)k * ng * ng * 16;
+    TRY(stage_out(R, xb, out, t));
+    t.mark();
+  }
+  HIPCHK(hipEventRecord(h->join, side));
+  HIPCHK(hipStreamWaitEvent(R.st, h->join, 0));
+  return ISDF_OK;
+}
+
 isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_omega, void* eps_inv,
                             Timer& tm) {
   isdf_handle h = R.h;
   const int ng = R.P.ng;
   TRY(prepare_psi(R, psi));
   TRY(stage_points(R));
+  if (n_omega >= 2 && R.P.nomega >= 2) return enqueue_eps_inv_batched(R, omega, n_omega, eps_inv, tm);
   // Fork: the side stream forms S = C C^H and, per frequency, M^{-1} and
   // K = S M^{-1} S (double-buffered), while this stream runs Z, the DFT to
   // X = V^{1/2} F Z and X^H X.  Then eps~^{-1} = I - X (X^H X - K)^{-1} X^H, which

@@ -21,6 +21,7 @@ struct GemmP {
   int ntm, ntn, total;
   int kchunk;   // split-K: split s covers k in [s * kchunk, (s + 1) * kchunk)
   void* part;   // split-K partial sums [split][M][N] complex (compute type), or null
+  long bsa, bsb, bsc;  // batch strides (complex elements); batch item = blockIdx.z
 };
 
 template <typename T, typename SA, typename SB, typename SC, class TL, bool AMC, bool BNC>
@@ -49,8 +50,8 @@ __global__ __launch_bounds__(TL::NT) void gemm_kernel(GemmP p) {
 
   Stager<T, SA, TL::BM, TL::BK, TL::NT, AMC> sa;
   Stager<T, SB, TL::BN, TL::BK, TL::NT, BNC> sb;
-  const cx<SA>* A = reinterpret_cast<const cx<SA>*>(p.A);
-  const cx<SB>* B = reinterpret_cast<const cx<SB>*>(p.B);
+  const cx<SA>* A = reinterpret_cast<const cx<SA>*>(p.A) + (long)blockIdx.z * p.bsa;
+  const cx<SB>* B = reinterpret_cast<const cx<SB>*>(p.B) + (long)blockIdx.z * p.bsb;
 
   typename TL::acc_t acc[TL::FM][TL::FN];
   zero_acc<TL>(acc);
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(TL::NT) void gemm_kernel(GemmP p) {
     __syncthreads();
   }
 
-  SC* Cr = reinterpret_cast<SC*>(p.C);
+  SC* Cr = reinterpret_cast<SC*>(p.C) + (long)blockIdx.z * p.bsc * 2;
   T* Pr = reinterpret_cast<T*>(p.part) + (long)blockIdx.y * p.M * p.N * 2;
   const int rc = lane & 15, part = rc & 1;
 #pragma unroll
@@ -144,13 +145,14 @@ static hipError_t launch(const GemmDesc& d, hipStream_t st) {
   p.C = d.C; p.ldc = d.ldc;
   p.alpha = d.alpha; p.beta = d.beta; p.diag_add = d.diag_add; p.rs = d.row_scale;
   p.herm = d.herm ? 1 : 0;
+  p.bsa = d.bsa; p.bsb = d.bsb; p.bsc = d.bsc;
   p.ntm = (int)cdiv(d.M, TL::BM);
   p.ntn = (int)cdiv(d.N, TL::BN);
   if (d.herm) p.total = p.ntm * (p.ntm + 1) / 2;
   else p.total = p.ntm * p.ntn;
   if (p.total == 0) return hipSuccess;
   int nsplit = 1;
-  if (d.split_ws) {
+  if (d.split_ws && d.batch == 1) {
     // enough workgroups to fill the chip, each split at least 4 K tiles deep
     nsplit = (512 + p.total - 1) / p.total;
     nsplit = std::min(nsplit, std::max(1, d.K / (4 * TL::BK)));
@@ -163,7 +165,8 @@ static hipError_t launch(const GemmDesc& d, hipStream_t st) {
   nsplit = nsplit > 1 ? (int)cdiv(d.K, p.kchunk) : 1;
   p.part = nsplit > 1 ? d.split_ws : nullptr;
   const unsigned grid = 8u * (unsigned)((p.total + 7) / 8);
-  hipLaunchKernelGGL((gemm_kernel<T, SA, SB, SC, TL, AMC, BNC>), dim3(grid, nsplit), dim3(TL::NT), 0, st, p);
+  hipLaunchKernelGGL((gemm_kernel<T, SA, SB, SC, TL, AMC, BNC>), dim3(grid, nsplit, std::max(d.batch, 1)),
+                     dim3(TL::NT), 0, st, p);
   if (nsplit > 1) {
     const long mn2 = (long)d.M * d.N * 2;
     hipLaunchKernelGGL((splitk_reduce_kernel<T, SC>), dim3(cdiv(mn2, 256)), dim3(256), 0, st, p, nsplit);

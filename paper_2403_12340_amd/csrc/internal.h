@@ -23,6 +23,8 @@ struct GemmDesc {
   // optional split-K scratch (device): when set, K is split across workgroups and the
   // partial sums are reduced in a fixed order by a second kernel
   void* split_ws = nullptr; size_t split_ws_bytes = 0;
+  // batch of independent products (no split-K): operand / result strides in complex elements
+  int batch = 1; long bsa = 0, bsb = 0, bsc = 0;
 };
 // Compute precision: P64 -> f64 MFMA; P32 -> f32 MFMA.
 hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st);
@@ -48,15 +50,16 @@ hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, lon
 //   M(mu, nu) = sum_{i, j} conj(a_i(mu)) b_j(mu) w_ij a_i(nu) conj(b_j(nu))
 // pm: [ns][ldp] complex128; w: [nv][nc] double; part: nsplit x nmu x nmu complex (f64 or f32 per compute)
 int core_splits(int nmu, int nv);
+// batch > 1: w holds batch weight sets [b][nv * nc], part [b][nsplit][nmu * nmu]
 hipError_t core_partial(Prec compute, int nmu, int nv, int nc, const void* pm, long ldp,
-                        const double* w, void* part, int nsplit, hipStream_t st);
+                        const double* w, void* part, int nsplit, hipStream_t st, int batch = 1);
 // M_out = scale * sum_s part[s]; writes complex128 (and optionally -M into negm)
 hipError_t core_reduce(Prec compute, int nmu, const void* part, int nsplit, double scale, void* m_out,
-                       void* negm_out, hipStream_t st);
+                       void* negm_out, hipStream_t st, int batch = 1);
 
 // ----- small FP64 dense algebra, row-major n x n complex128, ld = n
 // In-place Hermitian positive definite sweep: A <- -A^{-1}.  scratch: linalg_scratch_bytes(n).
-hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st);
+hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch = 1);
 size_t linalg_scratch_bytes(int n);
 
 // ----- grid / plane-wave helpers
@@ -95,6 +98,8 @@ hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);  // kernel clear, b
 hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStream_t st);  // z64
 // out[0] += ||a||_F^2 over count complex128, deterministic (single pass of block partials)
 hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st);
-hipError_t diag_min(const void* a, int n, double* out, hipStream_t st);
+hipError_t diag_min(const void* a, int n, double* out, hipStream_t st, int batch = 1);
+// H[b] = G - K[b] for b < batch (complex128, n2 elements each)
+hipError_t sub_bcast(const void* G, const void* K, void* H, long n2, int batch, hipStream_t st);
 
 }  // namespace isdf

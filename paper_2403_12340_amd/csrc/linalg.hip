@@ -40,6 +40,8 @@ typedef Tile<double, NB, 64, NB, 2, 2> TP;   // P (NB x NB, k-major in W) times 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_panel_kernel(int n, const z64* __restrict__ ain,
                                                           z64* __restrict__ aout, int k0, int kn,
                                                           int* status) {
+  ain += (long)blockIdx.y * n * n;   // batch item
+  aout += (long)blockIdx.y * n * n;
   __shared__ z64 W[NB][NB + 1];      // W[u][t] = P[t][u]: the k-major A operand of P (.)
   __shared__ z64 rowb[2][NB];        // pivot row broadcast, double-buffered
   __shared__ z64 Bs[NB * (64 + 1)];  // pivot rows at this block's columns, then R
@@ -145,6 +147,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
   __shared__ z64 Bs[TU::BS];  // [t][j] = R[t][n0 + j] (the pivot rows of A')
   const int id = xcd_remap(blockIdx.x, total);
   if (id >= total) return;
+  ain += (long)blockIdx.y * n * n;   // batch item
+  aout += (long)blockIdx.y * n * n;
   const int bm = id % ntm, bn = id / ntm;
   const int m0 = bm * TU::BM, n0 = bn * TU::BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
 
 size_t linalg_scratch_bytes(int n) { return (size_t)n * n * sizeof(z64); }
 
-hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st) {
+hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch) {
   z64* bufs[2] = {(z64*)a, (z64*)scratch};
   const int npb = (n + 63) / 64;                  // panel workgroups
   const int ntm = (n + TU::BM - 1) / TU::BM, ntn = (n + TU::BN - 1) / TU::BN;
@@ -207,17 +211,17 @@ hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t
   int cur = 0;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kn = min(NB, n - k0);
-    hipLaunchKernelGGL(sweep_panel_kernel, dim3(npb), dim3(256), 0, st, n, (const z64*)bufs[cur],
+    hipLaunchKernelGGL(sweep_panel_kernel, dim3(npb, batch), dim3(256), 0, st, n, (const z64*)bufs[cur],
                        bufs[cur ^ 1], k0, kn, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sweep_update_kernel, dim3(grid), dim3(256), 0, st, n, (const z64*)bufs[cur],
+    hipLaunchKernelGGL(sweep_update_kernel, dim3(grid, batch), dim3(256), 0, st, n, (const z64*)bufs[cur],
                        bufs[cur ^ 1], k0, kn, ntm, total);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;
   }
-  if (cur == 1) return convert_z(scratch, false, a, false, (long)n * n, st);
+  if (cur == 1) return convert_z(scratch, false, a, false, (long)n * n * batch, st);
   return hipSuccess;
 }
 
@@ -335,10 +339,15 @@ hipError_t frob2(const void* a, long count, double* partial, double* out, hipStr
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void diag_min_kernel(const z64* a, int n, double* out) {
+// smallest real diagonal entry over `batch` n x n matrices stored back to back
+__global__ __launch_bounds__(256) void diag_min_kernel(const z64* a, int n, int batch, double* out) {
   __shared__ double red[256];
   double m = 1e300;
-  for (int i = threadIdx.x; i < n; i += 256) m = fmin(m, a[(long)i * n + i].re);
+  const long nd = (long)n * batch;
+  for (long i = threadIdx.x; i < nd; i += 256) {
+    const long b = i / n, r = i % n;
+    m = fmin(m, a[b * n * n + r * n + r].re);
+  }
   red[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -348,8 +357,22 @@ __global__ __launch_bounds__(256) void diag_min_kernel(const z64* a, int n, doub
   if (threadIdx.x == 0) *out = red[0];
 }
 
-hipError_t diag_min(const void* a, int n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(diag_min_kernel, dim3(1), dim3(256), 0, st, (const z64*)a, n, out);
+hipError_t diag_min(const void* a, int n, double* out, hipStream_t st, int batch) {
+  hipLaunchKernelGGL(diag_min_kernel, dim3(1), dim3(256), 0, st, (const z64*)a, n, batch, out);
+  return hipGetLastError();
+}
+
+// H[b] = G - K[b] (complex128 as 2 n2 doubles per item)
+__global__ void sub_bcast_kernel(const double* G, const double* K, double* H, long n2x2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2x2) return;
+  const long o = (long)blockIdx.y * n2x2 + i;
+  H[o] = G[i] - K[o];
+}
+
+hipError_t sub_bcast(const void* G, const void* K, void* H, long n2, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(sub_bcast_kernel, dim3(cdiv(2 * n2, 256), batch), dim3(256), 0, st, (const double*)G,
+                     (const double*)K, (double*)H, 2 * n2);
   return hipGetLastError();
 }
 

@@ -290,6 +290,8 @@ __global__ __launch_bounds__(TL::NT) void core_kernel(int nmu, int nv, int nc, c
   const int bm = r, bn = id - r * (r + 1) / 2;
   const int m0 = bm * TL::BM, n0 = bn * TL::BN;
   const int split = blockIdx.y;
+  w += (long)blockIdx.z * nv * nc;                        // weight set of this batch item
+  part += (long)blockIdx.z * nsplit * nmu * nmu;
   const int i0 = (int)((long)split * nv / nsplit), i1 = (int)((long)(split + 1) * nv / nsplit);
   const int ni = i1 - i0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -398,15 +400,15 @@ int core_splits(int nmu, int nv) {
 }
 
 hipError_t core_partial(Prec compute, int nmu, int nv, int nc, const void* pm, long ldp,
-                        const double* w, void* part, int nsplit, hipStream_t st) {
+                        const double* w, void* part, int nsplit, hipStream_t st, int batch) {
   const int nt = (nmu + 63) / 64;
   const int total = nt * (nt + 1) / 2;
   const unsigned gx = 8u * (unsigned)((total + 7) / 8);
   if (compute == P64) {
-    hipLaunchKernelGGL((core_kernel<double, TC64>), dim3(gx, nsplit), dim3(TC64::NT), 0, st, nmu, nv,
+    hipLaunchKernelGGL((core_kernel<double, TC64>), dim3(gx, nsplit, batch), dim3(TC64::NT), 0, st, nmu, nv,
                        nc, (const z64*)pm, ldp, w, (z64*)part, nsplit, total);
   } else {
-    hipLaunchKernelGGL((core_kernel<float, TC32>), dim3(gx, nsplit), dim3(TC32::NT), 0, st, nmu, nv,
+    hipLaunchKernelGGL((core_kernel<float, TC32>), dim3(gx, nsplit, batch), dim3(TC32::NT), 0, st, nmu, nv,
                        nc, (const z64*)pm, ldp, w, (c32*)part, nsplit, total);
   }
   return hipGetLastError();
@@ -417,6 +419,10 @@ __global__ void core_reduce_kernel(long n2, const T* part, int nsplit, double sc
                                    double* negm) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;  // real index over 2 n2
   if (idx >= 2 * n2) return;
+  const long b = blockIdx.y;                                       // batch item
+  part += b * nsplit * 2 * n2;
+  if (m_out) m_out += b * 2 * n2;
+  if (negm) negm += b * 2 * n2;
   double s = 0.0;
   for (int k = 0; k < nsplit; ++k) s += (double)part[(long)k * 2 * n2 + idx];
   s *= scale;
@@ -425,14 +431,14 @@ __global__ void core_reduce_kernel(long n2, const T* part, int nsplit, double sc
 }
 
 hipError_t core_reduce(Prec compute, int nmu, const void* part, int nsplit, double scale, void* m_out,
-                       void* negm_out, hipStream_t st) {
+                       void* negm_out, hipStream_t st, int batch) {
   const long n2 = (long)nmu * nmu;
-  const unsigned grid = cdiv(2 * n2, 256);
+  const dim3 grid(cdiv(2 * n2, 256), batch);
   if (compute == P64)
     hipLaunchKernelGGL((core_reduce_kernel<double>), dim3(grid), dim3(256), 0, st, n2,
                        (const double*)part, nsplit, scale, (double*)m_out, (double*)negm_out);
   else
-    hipLaunchKernelGGL((core_reduce_kernel<float>), dim3(grid), dim3(256), 0, st, n2,
+    hipLaunchKernelGGL((core_reduce_kernel<float>), grid, dim3(256), 0, st, n2,
                        (const float*)part, nsplit, scale, (double*)m_out, (double*)negm_out);
   return hipGetLastError();
 }

@@ -124,11 +124,13 @@ def test_fullrank_equals_exact_definition():
     assert relf(got, ref) <= 1e-10
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_frequencies(prec):
+@pytest.mark.parametrize("prec,refine", [("fp64", 0), ("fp32", 0), ("fp32", 1)])
+def test_frequencies(prec, refine):
+    """Several imaginary frequencies in one call (the batched-frequency pipeline)."""
     inp = synth.make_inputs("mid", n_omega=4)
-    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, isdf.problem_for(inp, prec),
-                       omegas=inp.omegas)
+    print(f"[freq] prec={prec} refine={refine}", flush=True)
+    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller,
+                       isdf.problem_for(inp, prec, refine_steps=refine), omegas=inp.omegas)
     got = res.eps_inv.cpu().numpy()
     st = get_stages("mid")
     for k, om in enumerate(inp.omegas):
@@ -136,6 +138,7 @@ def test_frequencies(prec):
         stw["m"] = oracle.core_matrix(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, omega=om)
         ref = oracle.eps_inv_isdf(inp, stages=stw)
         assert relf(got[k], ref) <= TOL_EPS[prec], (k, om)
+        assert np.array_equal(got[k], got[k].conj().T)
 
 
 def test_refinement_reports_residual():
@@ -273,3 +276,16 @@ def test_full_size_48cubed(prec):
     print(f"  rel-F {err:.3e}  max-abs {np.abs(got - ref).max():.3e}", flush=True)
     assert err <= TOL_EPS[prec], err
     assert np.array_equal(got, got.conj().T)
+
+
+def test_frequencies_full_tiles():
+    """Frequency batch on the full-tile case (k-major output products per frequency)."""
+    inp = synth.make_inputs("kmaj", n_omega=3)
+    st = get_stages("kmaj")
+    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, isdf.problem_for(inp, "fp32"),
+                       omegas=inp.omegas)
+    got = res.eps_inv.cpu().numpy()
+    for k, om in enumerate(inp.omegas):
+        stw = dict(st)
+        stw["m"] = oracle.core_matrix(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, omega=om)
+        assert relf(got[k], oracle.eps_inv_isdf(inp, stages=stw)) <= TOL_EPS["fp32"], (k, om)
