@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--omegas", type=int, default=32,
+                    help="also time one mixed-path call with this many imaginary frequencies (0: skip)")
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
@@ -213,6 +215,30 @@ def main():
         results[prec] = dict(ms_per_step=dt * 1e3, builds_per_s=1.0 / dt, stage_ms=stages.tolist())
         print(f"[bench] {prec}: {dt * 1e3:.3f} ms/build  stages(ms) {np.round(stages, 3).tolist()}",
               file=sys.stderr, flush=True)
+
+    freq = None
+    if args.omegas > 1 and args.only is None:
+        # frequency batch: one plan call builds eps~^{-1}(i omega) for every frequency
+        inpw = synth.make_inputs(args.config, n_omega=args.omegas)
+        prob = isdf.problem_for(inpw, prec="fp32")
+        plan = isdf.Plan(prob, inpw.mu_idx, inpw.miller, n_omega=args.omegas)
+        ws = plan.new_workspace()
+        out = plan.new_output()
+        plan.eps_inv_async(psi, e_dev, out, ws, omegas=inpw.omegas)
+        plan.sync()
+        torch.cuda.synchronize()
+        reps = 3
+        t = time.perf_counter()
+        for _ in range(reps):
+            plan.eps_inv_async(psi, e_dev, out, ws, omegas=inpw.omegas)
+        plan.sync()
+        torch.cuda.synchronize()
+        dtw = (time.perf_counter() - t) / reps
+        freq = {"n_omega": args.omegas, "omega_range_eV": [0.01, 100.0], "ms_per_call": round(dtw * 1e3, 3),
+                "ms_per_frequency": round(dtw * 1e3 / args.omegas, 4),
+                "frequency_builds_per_s": round(args.omegas / dtw, 2), "path": "mixed"}
+        print(f"[bench] {args.omegas} frequencies: {dtw * 1e3:.2f} ms per call", file=sys.stderr, flush=True)
+        del plan, ws, out
 
     if args.only is not None:
         print(json.dumps({"only": args.only, **results[args.only]}))
@@ -278,6 +304,7 @@ def main():
                      "names": ["gather, first core M, operand conversion", "Z (pair-Gram kernel)", "DFT to X", "X^H X",
                                "core solve (waits for K = S M^-1 S)", "W = X H^-1", "output", "-"],
                      "note": "intervals on the caller's stream; S, M, M^-1 and K run on a second stream"},
+        "frequency_batch": freq,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

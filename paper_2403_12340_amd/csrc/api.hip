@@ -703,7 +703,7 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
 
 isdf_status clear_status(Run& R) {
   isdf_handle h = R.h;
-  HIPCHK(hipMemsetAsync(R.sb, 0, offsetof(StatusBlock, partial), R.st));
+  HIPCHK(zero_fill(R.sb, offsetof(StatusBlock, partial), R.st));
   return ISDF_OK;
 }
 

@@ -278,8 +278,14 @@ bool dft_supported(int n0, int n1, int kx, int ky, Prec compute) {
 template <typename T, int PF>
 static void xy_launch(const DftPlan& p, const void* zt, void* t2, int zb, dim3 grid, hipStream_t st) {
   const size_t lds = xy_lds_bytes<T>();
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_xy_kernel<T, PF>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  static bool attr_set[64] = {};  // once per device, outside any later stream capture
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64 || !attr_set[dev]) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_xy_kernel<T, PF>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (dev >= 0 && dev < 64) attr_set[dev] = true;
+  }
   hipLaunchKernelGGL((dft_xy_kernel<T, PF>), grid, dim3(XY_NT), lds, st, p, (const cx<T>*)zt, (cx<T>*)t2, zb);
 }
 

@@ -289,3 +289,28 @@ def test_frequencies_full_tiles():
         stw = dict(st)
         stw["m"] = oracle.core_matrix(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, omega=om)
         assert relf(got[k], oracle.eps_inv_isdf(inp, stages=stw)) <= TOL_EPS["fp32"], (k, om)
+
+
+def test_plan_graph_capture():
+    """A plan call captured into a HIP graph (both library streams) replays to the
+    eager result; eager calls and synchronisations run between the replays."""
+    inp, prob, plan = _plan_case("kmaj", "fp32")
+    print("[graph] case=kmaj prec=fp32", flush=True)
+    psi, e = dev(inp.psi_t), dev(inp.energies)
+    ws, out = plan.new_workspace(), plan.new_output()
+    plan.eps_inv_async(psi, e, out, ws)
+    plan.sync()
+    ref = out.clone()
+    graph_out = plan.new_output()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.eps_inv_async(psi, e, graph_out, ws)
+    for _ in range(3):
+        graph_out.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(graph_out, ref)
+        plan.eps_inv_async(psi, e, out, ws)
+        plan.sync()
+        assert torch.equal(out, ref)
+    assert relf(ref[0].cpu().numpy(), oracle.eps_inv_isdf(inp, stages=get_stages("kmaj"))) <= TOL_EPS["fp32"]
