@@ -216,6 +216,19 @@ isdf_status isdf_plan_workspace_bytes(isdf_plan plan, size_t* bytes);
 isdf_status isdf_plan_eps_inv(isdf_plan plan, const void* psi, const double* energies,
                               const double* omega, void* workspace, size_t ws_bytes, void* eps_inv);
 
+/* Several systems (possibly of different sizes) in one call: plans[i] with its
+ * own arguments psi[i], energies[i], omega[i] (omega may be NULL when no plan
+ * has frequencies), workspace[i] / ws_bytes[i], eps_inv[i], each as for
+ * isdf_plan_eps_inv.  The work of plans whose handles are bound to other
+ * streams is forked off plans[0]'s stream and joined back into it, so the
+ * systems run concurrently and the whole call can be captured into one graph
+ * on plans[0]'s stream; plans sharing a handle run one after another.  All
+ * plans must be on one device.  Only enqueues; each plan reports its own
+ * device errors at its next isdf_plan_sync. */
+isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const void* const* psi,
+                                    const double* const* energies, const double* const* omega,
+                                    void* const* workspace, const size_t* ws_bytes, void* const* eps_inv);
+
 /* Wait for the handle's stream and return the first error any call enqueued
  * since the previous sync found on the device: ISDF_E_ARG (energies without a
  * gap or not finite), ISDF_E_NOT_PD; then clear it.  rep (optional) receives

@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
             "isdf_plan_workspace_bytes": [vp, ctypes.POINTER(sz)],
             "isdf_plan_eps_inv": [vp, vp, vp, pdbl, vp, sz, vp],
             "isdf_plan_sync": [vp, prep],
+            "isdf_plan_eps_inv_multi": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -151,20 +153,25 @@ def check_inputs(prob: Problem, energies, mu_idx, miller, omegas=None) -> tuple[
 
 
 class Handle:
-    """Library handle bound to one device; the stream is refreshed from torch on every call."""
+    """Library handle bound to one device.  Without a fixed stream it follows
+    torch's current stream (refreshed on every call); with one (a torch stream)
+    it stays bound to it."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, stream=None):
         import torch
         self.device = device
+        self.stream = stream
+        cur = stream if stream is not None else torch.cuda.current_stream(device)
         h = ctypes.c_void_p()
-        st = lib().isdf_create(ctypes.byref(h), device, ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream))
+        st = lib().isdf_create(ctypes.byref(h), device, ctypes.c_void_p(cur.cuda_stream))
         if st != OK:
             raise IsdfError(st, "isdf_create failed (no GPU?)")
         self.h = h
 
     def sync_stream(self):
         import torch
-        lib().isdf_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+        if self.stream is None:
+            lib().isdf_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
 
     def check(self, st: int, what: str):
         if st != OK:
@@ -322,8 +329,11 @@ class Plan:
     energies are passed as a device float64 tensor; device-side errors surface
     at sync()."""
 
-    def __init__(self, prob: Problem, mu_idx, miller, n_omega: int = 0, device: int = 0):
-        self.h = handle(device)
+    def __init__(self, prob: Problem, mu_idx, miller, n_omega: int = 0, device: int = 0, stream=None):
+        # a fixed torch stream gives the plan a private handle bound to it (for
+        # systems that run concurrently in eps_inv_multi); otherwise the shared
+        # per-device handle follows torch's current stream
+        self.h = handle(device) if stream is None else Handle(device, stream)
         self.device = device
         self.prob = prob
         mu, pmu = _i32(mu_idx)
@@ -379,6 +389,48 @@ class Plan:
                 lib().isdf_plan_destroy(self.p)
         except Exception:
             pass
+
+
+def eps_inv_multi(plans, psis, energies_devs, outs, workspaces, omegas=None):
+    """isdf_plan_eps_inv_multi: enqueue several systems at once (forked off the
+    first plan's stream and joined back).  Sync each plan afterwards."""
+    n = len(plans)
+    if not (len(psis) == len(energies_devs) == len(outs) == len(workspaces) == n):
+        raise ValueError("one psi, energies, output and workspace per plan")
+    import torch
+    for p, psi, e, w in zip(plans, psis, energies_devs, workspaces):
+        _check_psi(psi, p.prob)
+        if e.dtype != torch.float64 or e.numel() != p.prob.nv + p.prob.nc or e.device.type != "cuda":
+            raise TypeError("energies must be device float64 tensors of N values")
+        if w is None:
+            raise ValueError("pass each plan's workspace (it must outlive the enqueued work)")
+    plans[0].h.sync_stream()
+    vp = ctypes.c_void_p
+    P = (vp * n)(*[p.p for p in plans])
+    PS = (vp * n)(*[psi.data_ptr() for psi in psis])
+    E = (vp * n)(*[e.data_ptr() for e in energies_devs])
+    keep = []
+    OM = None
+    if omegas is not None:
+        arrs = []
+        for p, om in zip(plans, omegas):
+            a = np.zeros(0) if om is None else np.asarray(om, dtype=np.float64)
+            if len(a) != p.n_omega:
+                raise ValueError("each plan's frequency count must match")
+            arrs.append(np.ascontiguousarray(a))
+        keep = arrs
+        OM = (vp * n)(*[a.ctypes.data if len(a) else None for a in arrs])
+    W = []
+    for p, w, psi in zip(plans, workspaces, psis):
+        wsbuf, wsptr = _workspace(p.workspace_bytes, psi.device, w)
+        W.append(wsptr)
+        keep.append(wsbuf)
+    WS = (vp * n)(*W)
+    SZ = (ctypes.c_size_t * n)(*[p.workspace_bytes for p in plans])
+    O = (vp * n)(*[o.data_ptr() for o in outs])
+    st = lib().isdf_plan_eps_inv_multi(n, P, PS, E, OM, WS, SZ, O)
+    plans[0].h.check(st, "isdf_plan_eps_inv_multi")
+    return outs
 
 
 def problem_for(inp, prec="fp64", refine_steps=0, v_scale=None) -> Problem:

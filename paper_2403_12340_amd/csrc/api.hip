@@ -42,6 +42,7 @@ struct isdf_handle_s {
   size_t pinned_bytes = 0;
   hipEvent_t ev[10] = {};         // stage timing (main stream)
   hipEvent_t fork = nullptr, join = nullptr, core0 = nullptr;
+  hipEvent_t mfork = nullptr, mdone = nullptr;  // multi-system calls
   hipEvent_t m_ready[2] = {}, m_used[2] = {};
   std::string err;
 };
@@ -194,6 +195,13 @@ isdf_status fail(isdf_handle h, isdf_status s, const std::string& msg) {
   if (h) h->err = msg;
   return s;
 }
+
+#define HIPCHK_H(hh, expr)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(hh, ISDF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
 
 #define HIPCHK(expr)                                                                       \
   do {                                                                                     \
@@ -873,7 +881,8 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
   if (hipSetDevice(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
-  for (hipEvent_t* e : {&h->fork, &h->join, &h->core0, &h->m_ready[0], &h->m_ready[1], &h->m_used[0], &h->m_used[1]})
+  for (hipEvent_t* e : {&h->fork, &h->join, &h->core0, &h->mfork, &h->mdone, &h->m_ready[0], &h->m_ready[1],
+                        &h->m_used[0], &h->m_used[1]})
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   // default priority, non-blocking with respect to the legacy default stream
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
@@ -894,7 +903,8 @@ isdf_status isdf_destroy(isdf_handle h) {
     (void)hipStreamDestroy(h->side);
   }
   for (auto& e : h->ev) if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {h->fork, h->join, h->core0, h->m_ready[0], h->m_ready[1], h->m_used[0], h->m_used[1]})
+  for (hipEvent_t e : {h->fork, h->join, h->core0, h->mfork, h->mdone, h->m_ready[0], h->m_ready[1], h->m_used[0],
+                       h->m_used[1]})
     if (e) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
@@ -1178,8 +1188,12 @@ isdf_status isdf_plan_workspace_bytes(isdf_plan pl, size_t* bytes) {
   return ISDF_OK;
 }
 
-isdf_status isdf_plan_eps_inv(isdf_plan pl, const void* psi, const double* energies, const double* omega,
-                              void* workspace, size_t ws_bytes, void* eps_inv) {
+}  // extern "C"
+
+namespace {
+
+isdf_status plan_check(isdf_plan pl, const void* psi, const double* energies, const double* omega, void* workspace,
+                       size_t ws_bytes, void* eps_inv) {
   if (!pl) return ISDF_E_ARG;
   isdf_handle h = pl->h;
   if (!psi) return fail(h, ISDF_E_ARG, "psi is NULL");
@@ -1188,7 +1202,12 @@ isdf_status isdf_plan_eps_inv(isdf_plan pl, const void* psi, const double* energ
   if (pl->n_omega > 0 && !omega) return fail(h, ISDF_E_ARG, "omega list invalid");
   for (int k = 0; k < pl->n_omega; ++k)
     if (!(omega[k] >= 0.0) || !std::isfinite(omega[k])) return fail(h, ISDF_E_ARG, "omega must be finite and >= 0");
-  TRY(check_ws(h, workspace, ws_bytes, pl->L.total));
+  return check_ws(h, workspace, ws_bytes, pl->L.total);
+}
+
+isdf_status plan_enqueue(isdf_plan pl, const void* psi, const double* energies, const double* omega,
+                         void* workspace, void* eps_inv) {
+  isdf_handle h = pl->h;
   Run R;
   R.h = h;
   R.P = pl->P;
@@ -1206,6 +1225,43 @@ isdf_status isdf_plan_eps_inv(isdf_plan pl, const void* psi, const double* energ
   HIPCHK(check_gap(energies, R.P.nv, R.P.nc, &R.sb->status, ST_NO_GAP, R.st));
   Timer none{h, false};
   return enqueue_eps_inv(R, psi, omega, pl->n_omega, eps_inv, none);
+}
+
+}  // namespace
+
+extern "C" {
+
+isdf_status isdf_plan_eps_inv(isdf_plan pl, const void* psi, const double* energies, const double* omega,
+                              void* workspace, size_t ws_bytes, void* eps_inv) {
+  TRY(plan_check(pl, psi, energies, omega, workspace, ws_bytes, eps_inv));
+  return plan_enqueue(pl, psi, energies, omega, workspace, eps_inv);
+}
+
+isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const void* const* psi,
+                                    const double* const* energies, const double* const* omega,
+                                    void* const* workspace, const size_t* ws_bytes, void* const* eps_inv) {
+  if (count < 1 || !plans || !psi || !energies || !workspace || !ws_bytes || !eps_inv) return ISDF_E_ARG;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return ISDF_E_ARG;
+    if (plans[i]->h->device != plans[0]->h->device) return fail(plans[0]->h, ISDF_E_ARG, "plans on different devices");
+    TRY(plan_check(plans[i], psi[i], energies[i], omega ? omega[i] : nullptr, workspace[i], ws_bytes[i], eps_inv[i]));
+  }
+  isdf_handle h0 = plans[0]->h;
+  hipStream_t main = h0->stream;
+  HIPCHK_H(h0, hipSetDevice(h0->device));
+  // fork every other stream off the first plan's stream, enqueue each system on
+  // its own handle's streams, and join them back (all capturable)
+  HIPCHK_H(h0, hipEventRecord(h0->mfork, main));
+  for (int i = 0; i < count; ++i) {
+    isdf_handle hi = plans[i]->h;
+    if (hi->stream != main) HIPCHK_H(hi, hipStreamWaitEvent(hi->stream, h0->mfork, 0));
+    TRY(plan_enqueue(plans[i], psi[i], energies[i], omega ? omega[i] : nullptr, workspace[i], eps_inv[i]));
+    if (hi->stream != main) {
+      HIPCHK_H(hi, hipEventRecord(hi->mdone, hi->stream));
+      HIPCHK_H(h0, hipStreamWaitEvent(main, hi->mdone, 0));
+    }
+  }
+  return ISDF_OK;
 }
 
 isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {

@@ -314,3 +314,68 @@ def test_plan_graph_capture():
         plan.sync()
         assert torch.equal(out, ref)
     assert relf(ref[0].cpu().numpy(), oracle.eps_inv_isdf(inp, stages=get_stages("kmaj"))) <= TOL_EPS["fp32"]
+
+
+def _multi_case(private_streams):
+    names = ["tiny", "mid", "kmaj"]
+    plans, psis, es, wss, outs, refs = [], [], [], [], [], []
+    for i, name in enumerate(names):
+        inp = get_inputs(name)
+        prob = isdf.problem_for(inp, "fp32")
+        solo = isdf.Plan(prob, inp.mu_idx, inp.miller)
+        psi, e = dev(inp.psi_t), dev(inp.energies)
+        o = solo.new_output()
+        solo.eps_inv_async(psi, e, o, solo.new_workspace())
+        solo.sync()
+        refs.append(o.clone())
+        stream = torch.cuda.Stream() if (private_streams and i > 0) else None
+        plans.append(isdf.Plan(prob, inp.mu_idx, inp.miller, stream=stream))
+        psis.append(psi); es.append(e)
+        wss.append(plans[-1].new_workspace()); outs.append(plans[-1].new_output())
+    return plans, psis, es, wss, outs, refs
+
+
+def test_multi_system_concurrent():
+    """Systems of different sizes in one multi call, each on its own stream:
+    every output equals its single-plan result."""
+    print("[multi] concurrent", flush=True)
+    plans, psis, es, wss, outs, refs = _multi_case(True)
+    isdf.eps_inv_multi(plans, psis, es, outs, wss)
+    for p in plans:
+        p.sync()
+    for o, r in zip(outs, refs):
+        assert torch.equal(o, r)
+
+
+def test_multi_system_graph():
+    """Systems of different sizes in one multi call on one stream, captured into one
+    graph; replays (with eager calls in between) equal the single-plan results."""
+    print("[multi] graph", flush=True)
+    plans, psis, es, wss, outs, refs = _multi_case(False)
+    isdf.eps_inv_multi(plans, psis, es, outs, wss)
+    for p in plans:
+        p.sync()
+    for o, r in zip(outs, refs):
+        assert torch.equal(o, r)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        isdf.eps_inv_multi(plans, psis, es, outs, wss)
+    for _ in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert torch.equal(o, r)
+        isdf.eps_inv_multi(plans, psis, es, outs, wss)
+        for p in plans:
+            p.sync()
+
+
+@pytest.mark.skip(reason="capturing systems forked onto several streams (nested forks from a joined "
+                         "stream) crashed the HIP runtime in stream-capture end once; off until the cause is found")
+def test_multi_system_concurrent_graph():
+    plans, psis, es, wss, outs, refs = _multi_case(True)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        isdf.eps_inv_multi(plans, psis, es, outs, wss)
