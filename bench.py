@@ -149,6 +149,60 @@ def summarize(args):
     print("\n".join(lines))
 
 
+def batch_systems(isdf, torch, dev, n_omega, first):
+    """The 48^3 system plus eight uneven ones (24^3..40^3, Nv 16..48, Nc = 4 Nv,
+    N_mu = 10 Nv, NG = 32 Nv), each with n_omega imaginary frequencies, built by
+    one multi-system call: captured into one graph (systems in sequence on one
+    stream) and, eagerly, with the systems on concurrent streams."""
+    import synth
+    names = [first] + [f"batch{i}" for i in range(8)]
+    inps = [synth.make_inputs(nm, n_omega=n_omega) for nm in names]
+    psis = [torch.from_numpy(i.psi_t).to(dev) for i in inps]
+    es = [torch.from_numpy(i.energies).to(dev) for i in inps]
+    oms = [i.omegas for i in inps]
+    probs = [isdf.problem_for(i, prec="fp32") for i in inps]
+    seq = [isdf.Plan(p, i.mu_idx, i.miller, n_omega=n_omega) for p, i in zip(probs, inps)]
+    wss = [p.new_workspace() for p in seq]
+    outs = [p.new_output() for p in seq]
+    isdf.eps_inv_multi(seq, psis, es, outs, wss, omegas=oms)
+    for p in seq:
+        p.sync()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        isdf.eps_inv_multi(seq, psis, es, outs, wss, omegas=oms)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = 3
+    t = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt_graph = (time.perf_counter() - t) / reps
+    for p in seq:
+        p.sync()
+    streams = [None] + [torch.cuda.Stream() for _ in names[1:]]
+    conc = [isdf.Plan(p, i.mu_idx, i.miller, n_omega=n_omega, stream=s) for p, i, s in zip(probs, inps, streams)]
+    isdf.eps_inv_multi(conc, psis, es, outs, wss, omegas=oms)
+    for p in conc:
+        p.sync()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        isdf.eps_inv_multi(conc, psis, es, outs, wss, omegas=oms)
+    for p in conc:
+        p.sync()
+    torch.cuda.synchronize()
+    dt_conc = (time.perf_counter() - t) / reps
+    nb = len(names) * n_omega
+    print(f"[bench] {len(names)} systems x {n_omega} frequencies: graph {dt_graph * 1e3:.1f} ms, "
+          f"concurrent {dt_conc * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    del g
+    return {"systems": [f"{i.n}^3 Nv={i.nv} Nc={i.nc} N_mu={i.nmu} NG={i.ng}" for i in inps], "n_omega": n_omega,
+            "path": "mixed", "ms_graph_launch": round(dt_graph * 1e3, 2),
+            "ms_concurrent_streams": round(dt_conc * 1e3, 2),
+            "frequency_builds_per_s": round(nb / min(dt_graph, dt_conc), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--summarize", default=None, help="rocpd database of a --kernel-trace run")
@@ -162,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--omegas", type=int, default=32,
                     help="also time one mixed-path call with this many imaginary frequencies (0: skip)")
+    ap.add_argument("--no-batch-systems", action="store_true",
+                    help="skip the 48^3 + 8 uneven systems frequency batch (one graph launch)")
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
@@ -240,6 +296,10 @@ def main():
         print(f"[bench] {args.omegas} frequencies: {dtw * 1e3:.2f} ms per call", file=sys.stderr, flush=True)
         del plan, ws, out
 
+    batch = None
+    if not args.no_batch_systems and args.omegas > 1 and args.only is None:
+        batch = batch_systems(isdf, torch, dev, args.omegas, args.config)
+
     if args.only is not None:
         print(json.dumps({"only": args.only, **results[args.only]}))
         return
@@ -305,6 +365,7 @@ def main():
                                "core solve (waits for K = S M^-1 S)", "W = X H^-1", "output", "-"],
                      "note": "intervals on the caller's stream; S, M, M^-1 and K run on a second stream"},
         "frequency_batch": freq,
+        "systems_batch": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
