@@ -229,6 +229,35 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
                                     const double* const* energies, const double* const* omega,
                                     void* const* workspace, const size_t* ws_bytes, void* const* eps_inv);
 
+/* Launch-shape knobs of a plan (a project-written autotuner chooses them):
+ *   dft_zb          z-planes per workgroup of the DFT's x/y stage, 1..64 (default 8)
+ *   core_split_pct  split of the core M over the occupied index, percent of the
+ *                   built-in choice, 25..200 (default 100)
+ *   gram_split      cap on the split-K factor of X^H X, 1..16 (default 16)
+ *   wg_per_cu       workgroups per CU of the persistent single-precision kernels, 1..4
+ *                   (default 1)
+ *   best_ms         output of isdf_plan_autotune: time of one call with the chosen knobs */
+typedef struct {
+  int32_t dft_zb;
+  int32_t core_split_pct;
+  int32_t gram_split;
+  int32_t wg_per_cu;
+  double best_ms;
+} isdf_tune;
+
+/* Set or read a plan's knobs (best_ms is ignored / returned as 0).  Knobs change
+ * launch shapes and split orders only; results change at most by rounding. */
+isdf_status isdf_plan_set_tune(isdf_plan plan, const isdf_tune* tune);
+isdf_status isdf_plan_get_tune(isdf_plan plan, isdf_tune* tune);
+
+/* Autotune a plan on real arguments (as for isdf_plan_eps_inv): times `reps`
+ * enqueued calls per candidate with HIP events on the handle's stream, going
+ * over the knobs one at a time (coordinate descent, each knob over a fixed
+ * candidate list) and keeping the fastest; leaves the plan set to the choice
+ * and returns it in `out` (optional).  Synchronises the stream. */
+isdf_status isdf_plan_autotune(isdf_plan plan, const void* psi, const double* energies, const double* omega,
+                               void* workspace, size_t ws_bytes, void* eps_inv, int32_t reps, isdf_tune* out);
+
 /* Wait for the handle's stream and return the first error any call enqueued
  * since the previous sync found on the device: ISDF_E_ARG (energies without a
  * gap or not finite), ISDF_E_NOT_PD; then clear it.  rep (optional) receives

@@ -35,6 +35,14 @@ class Problem(ctypes.Structure):
                 ("v_scale", ctypes.c_double), ("prec", ctypes.c_int32), ("refine_steps", ctypes.c_int32)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("dft_zb", ctypes.c_int32), ("core_split_pct", ctypes.c_int32), ("gram_split", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("best_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Report(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double * 8), ("refine_residual", ctypes.c_double * 9),
                 ("min_pivot", ctypes.c_double), ("want_timing", ctypes.c_int32),
@@ -72,6 +80,9 @@ def lib() -> ctypes.CDLL:
             "isdf_plan_workspace_bytes": [vp, ctypes.POINTER(sz)],
             "isdf_plan_eps_inv": [vp, vp, vp, pdbl, vp, sz, vp],
             "isdf_plan_sync": [vp, prep],
+            "isdf_plan_set_tune": [vp, ctypes.POINTER(Tune)],
+            "isdf_plan_get_tune": [vp, ctypes.POINTER(Tune)],
+            "isdf_plan_autotune": [vp, vp, vp, pdbl, vp, sz, vp, i32, ctypes.POINTER(Tune)],
             "isdf_plan_eps_inv_multi": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                         ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp)],
         }
@@ -376,6 +387,35 @@ class Plan:
                                      ctypes.c_void_p(wsptr), self.workspace_bytes, ctypes.c_void_p(out.data_ptr()))
         self.h.check(st, "isdf_plan_eps_inv")
         return out
+
+    def autotune(self, psi_t, energies_dev, out, workspace, omegas=None, reps=3) -> dict:
+        """isdf_plan_autotune on these arguments; leaves the plan tuned."""
+        _check_psi(psi_t, self.prob)
+        om = np.zeros(0) if omegas is None else np.asarray(omegas, dtype=np.float64)
+        if len(om) != self.n_omega:
+            raise ValueError(f"the plan was made for {self.n_omega} frequencies")
+        om, pom = _f64(om)
+        self.h.sync_stream()
+        wsbuf, wsptr = _workspace(self.workspace_bytes, psi_t.device, workspace)
+        t = Tune()
+        self.h.check(lib().isdf_plan_autotune(self.p, ctypes.c_void_p(psi_t.data_ptr()),
+                                              ctypes.c_void_p(energies_dev.data_ptr()), pom if len(om) else None,
+                                              ctypes.c_void_p(wsptr), self.workspace_bytes,
+                                              ctypes.c_void_p(out.data_ptr()), int(reps), ctypes.byref(t)),
+                     "isdf_plan_autotune")
+        return t.as_dict()
+
+    def get_tune(self) -> dict:
+        t = Tune()
+        self.h.check(lib().isdf_plan_get_tune(self.p, ctypes.byref(t)), "isdf_plan_get_tune")
+        return t.as_dict()
+
+    def set_tune(self, **knobs):
+        t = Tune()
+        lib().isdf_plan_get_tune(self.p, ctypes.byref(t))
+        for k, v in knobs.items():
+            setattr(t, k, int(v))
+        self.h.check(lib().isdf_plan_set_tune(self.p, ctypes.byref(t)), "isdf_plan_set_tune")
 
     def sync(self) -> Report:
         rep = Report()

@@ -132,7 +132,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += up(std::max<size_t>(bytes, 1)); return o; };
   L.kx = kx; L.ky = ky; L.kz = kz; L.nd = nd;
-  L.nsplit = core_splits(P.nmu, P.nv);
+  L.nsplit = std::min(P.nv, 2 * core_splits(P.nmu, P.nv));  // room for the tuned maximum (2x default)
   L.status = take(sizeof(StatusBlock));
   L.psi_c = P.cplx ? 0 : take((size_t)P.ns * P.nr * z);
   L.pm = take((size_t)P.ns * P.nmu * z);
@@ -331,8 +331,17 @@ struct Timer {
 };
 
 // ---- shared pieces of the pipeline --------------------------------------------------------
+// Launch-shape knobs (isdf_tune); defaults are what the library uses untuned.
+struct Tune {
+  int dft_zb = 8;          // z-planes per DFT workgroup
+  int core_split_pct = 100;  // core split count, percent of the default
+  int gram_split = 16;     // split-K cap of X^H X
+  int wg_per_cu = 1;       // workgroups per CU of the persistent k-major kernels
+};
+
 struct Run {
   isdf_handle h;
+  Tune tune;
   Problem P;
   Layout L;
   void* ws;
@@ -420,7 +429,7 @@ isdf_status stage_z(Run& R) {
     return ISDF_OK;
   }
   HIPCHK(zpair(P32, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm32), P.nmu, at<char>(R.ws, R.L.psi32),
-               P.nr, true, at<char>(R.ws, R.L.zt), P.nr, true, R.st));
+               P.nr, true, at<char>(R.ws, R.L.zt), P.nr, true, R.st, R.tune.wg_per_cu));
   return ISDF_OK;
 }
 
@@ -430,6 +439,7 @@ DftPlan make_plan(Run& R) {
   DftPlan p;
   p.n0 = P.n0; p.n1 = P.n1; p.n2 = P.n2; p.nmu = P.nmu; p.ng = P.ng;
   p.kx = L.kx; p.ky = L.ky; p.nd = L.nd; p.kz = L.kz;
+  p.zb = R.tune.dft_zb;
   p.twx = at<char>(R.ws, L.twx);
   p.twy = at<char>(R.ws, L.twy);
   p.twz = at<char>(R.ws, L.twz);
@@ -497,6 +507,7 @@ isdf_status stage_gram(Run& R, const Basis& b) {
   d.C = at<char>(R.ws, R.L.g); d.ldc = P.nmu;
   d.herm = true;
   d.split_ws = at<char>(R.ws, R.L.zt);    // Z^T region, free once the DFT has run
+  d.max_split = R.tune.gram_split;
   d.split_ws_bytes = R.L.zt_bytes;
   HIPCHK(gemm(cp, d, R.st));
   return ISDF_OK;
@@ -510,8 +521,9 @@ isdf_status stage_core(Run& R, double omega, void* m_out, void* negm, hipStream_
   double* w = at<double>(R.ws, R.L.w);
   HIPCHK(pair_weights(R.e, P.nv, P.nc, omega, w, st));
   void* part = at<char>(R.ws, R.L.part);
-  HIPCHK(core_partial(cp, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), P.nmu, w, part, R.L.nsplit, st));
-  HIPCHK(core_reduce(cp, P.nmu, part, R.L.nsplit, P.f, m_out, negm, st));
+  const int ns = std::max(1, std::min(R.L.nsplit, core_splits(P.nmu, P.nv) * R.tune.core_split_pct / 100));
+  HIPCHK(core_partial(cp, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), P.nmu, w, part, ns, st));
+  HIPCHK(core_reduce(cp, P.nmu, part, ns, P.f, m_out, negm, st));
   return ISDF_OK;
 }
 
@@ -589,9 +601,10 @@ isdf_status stage_out(Run& R, const Basis& b, void* out, Timer& tm) {
     void* wt = at<char>(R.ws, L.w1);
     HIPCHK(convert_z(R.tmat, false, t32, true, (long)P.nmu * P.nmu, R.st));
     HIPCHK(gemm32_kmajor(P.nmu, P.ng, P.nmu, t32, P.nmu, false, b.base, P.ng, false, wt, P.ng, false,
-                         R.talpha, R.st));
+                         R.talpha, R.st, R.tune.wg_per_cu));
     tm.mark();
-    HIPCHK(gemm32_kmajor(P.ng, P.ng, P.nmu, wt, P.ng, false, b.base, P.ng, true, out, P.ng, true, -1.0, R.st));
+    HIPCHK(gemm32_kmajor(P.ng, P.ng, P.nmu, wt, P.ng, false, b.base, P.ng, true, out, P.ng, true, -1.0, R.st,
+                         R.tune.wg_per_cu));
     return ISDF_OK;
   }
   GemmDesc d;  // W1 = B T
@@ -1124,6 +1137,7 @@ struct isdf_plan_s {
   isdf_handle h = nullptr;
   Problem P;
   Layout L;
+  Tune tune;
   int n_omega = 0;
   void* dev = nullptr;  // status block, point indices, Miller list, reciprocal basis, DFT tables
   size_t off_mu = 0, off_miller = 0, off_recip = 0, off_idx = 0;
@@ -1221,6 +1235,7 @@ isdf_status plan_enqueue(isdf_plan pl, const void* psi, const double* energies, 
   R.miller = reinterpret_cast<const int*>(d + pl->off_miller);
   R.recip = reinterpret_cast<const double*>(d + pl->off_recip);
   R.idx = reinterpret_cast<const int*>(d + pl->off_idx);
+  R.tune = pl->tune;
   HIPCHK(hipSetDevice(h->device));
   HIPCHK(check_gap(energies, R.P.nv, R.P.nc, &R.sb->status, ST_NO_GAP, R.st));
   Timer none{h, false};
@@ -1273,6 +1288,78 @@ isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(zero_fill(pl->dev, offsetof(StatusBlock, partial), h->stream));
   return report_status(h, hs, pl->P, rep);
+}
+
+static bool tune_valid(const isdf_tune* t) {
+  return t && t->dft_zb >= 1 && t->dft_zb <= 64 && t->core_split_pct >= 25 && t->core_split_pct <= 200 &&
+         t->gram_split >= 1 && t->gram_split <= 16 && t->wg_per_cu >= 1 && t->wg_per_cu <= 4;
+}
+
+isdf_status isdf_plan_set_tune(isdf_plan pl, const isdf_tune* t) {
+  if (!pl) return ISDF_E_ARG;
+  if (!tune_valid(t)) return fail(pl->h, ISDF_E_ARG, "tuning knob out of range");
+  pl->tune.dft_zb = t->dft_zb;
+  pl->tune.core_split_pct = t->core_split_pct;
+  pl->tune.gram_split = t->gram_split;
+  pl->tune.wg_per_cu = t->wg_per_cu;
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_get_tune(isdf_plan pl, isdf_tune* t) {
+  if (!pl || !t) return ISDF_E_ARG;
+  t->dft_zb = pl->tune.dft_zb;
+  t->core_split_pct = pl->tune.core_split_pct;
+  t->gram_split = pl->tune.gram_split;
+  t->wg_per_cu = pl->tune.wg_per_cu;
+  t->best_ms = 0.0;
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* energies, const double* omega,
+                               void* workspace, size_t ws_bytes, void* eps_inv, int32_t reps, isdf_tune* out) {
+  TRY(plan_check(pl, psi, energies, omega, workspace, ws_bytes, eps_inv));
+  if (reps < 1 || reps > 100) return fail(pl->h, ISDF_E_ARG, "reps must be in [1, 100]");
+  isdf_handle h = pl->h;
+  HIPCHK(hipSetDevice(h->device));
+  auto time_call = [&](float& ms) -> isdf_status {
+    TRY(plan_enqueue(pl, psi, energies, omega, workspace, eps_inv));  // warm-up
+    HIPCHK(hipEventRecord(h->ev[0], h->stream));
+    for (int r = 0; r < reps; ++r) TRY(plan_enqueue(pl, psi, energies, omega, workspace, eps_inv));
+    HIPCHK(hipEventRecord(h->ev[1], h->stream));
+    HIPCHK(hipEventSynchronize(h->ev[1]));
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+    ms /= (float)reps;
+    return ISDF_OK;
+  };
+  // coordinate descent over the knobs, each over its candidate list, keeping the best so far
+  float best = 0.f;
+  TRY(time_call(best));
+  const int zbs[] = {2, 4, 8, 16};
+  const int splits[] = {50, 100, 200};
+  const int grams[] = {4, 8, 16};
+  const int wpcs[] = {1, 2};
+  auto sweep = [&](int Tune::*knob, const int* cands, int nc) -> isdf_status {
+    const int keep = pl->tune.*knob;
+    int arg = keep;
+    for (int i = 0; i < nc; ++i) {
+      if (cands[i] == keep) continue;
+      pl->tune.*knob = cands[i];
+      float ms = 0.f;
+      TRY(time_call(ms));
+      if (ms < best) { best = ms; arg = cands[i]; }
+    }
+    pl->tune.*knob = arg;
+    return ISDF_OK;
+  };
+  TRY(sweep(&Tune::dft_zb, zbs, 4));
+  TRY(sweep(&Tune::core_split_pct, splits, 3));
+  TRY(sweep(&Tune::gram_split, grams, 3));
+  TRY(sweep(&Tune::wg_per_cu, wpcs, 2));
+  if (out) {
+    TRY(isdf_plan_get_tune(pl, out));
+    out->best_ms = best;
+  }
+  return ISDF_OK;
 }
 
 }  // extern "C"

@@ -299,7 +299,7 @@ static void xy_dispatch(const DftPlan& p, const void* zt, void* t2, int zb, dim3
 
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st) {
   if (p.n0 > 64 || p.n1 > 64) return hipErrorInvalidValue;
-  const int zb = std::min(p.n2, 8);
+  const int zb = std::max(1, std::min(p.n2, p.zb));
   const int nzb = (p.n2 + zb - 1) / zb;
   const dim3 grid((unsigned)(p.nmu * nzb));
   if (compute == P64) xy_dispatch<double>(p, zt, t2, zb, grid, st);

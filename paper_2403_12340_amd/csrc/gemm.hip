@@ -156,7 +156,7 @@ static hipError_t launch(const GemmDesc& d, hipStream_t st) {
     // enough workgroups to fill the chip, each split at least 4 K tiles deep
     nsplit = (512 + p.total - 1) / p.total;
     nsplit = std::min(nsplit, std::max(1, d.K / (4 * TL::BK)));
-    nsplit = std::min(nsplit, 16);
+    nsplit = std::min(nsplit, std::max(1, d.max_split));
     const size_t need = (size_t)nsplit * d.M * d.N * 2 * sizeof(T);
     while (nsplit > 1 && (size_t)nsplit * d.M * d.N * 2 * sizeof(T) > d.split_ws_bytes) --nsplit;
     (void)need;

@@ -94,12 +94,14 @@ bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, lo
 }
 
 hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conjA, const void* B, long ldb,
-                         bool conjB, void* C, long ldc, bool herm_identity, double alpha, hipStream_t st) {
+                         bool conjB, void* C, long ldc, bool herm_identity, double alpha, hipStream_t st,
+                         int wg_per_cu) {
   if (!gemm32_fits(M, N, K, A, lda, B, ldb) || (herm_identity && M != N)) return hipErrorNotSupported;
   const int nti = M / ZL::BM, ntj = N / ZL::BN;
   const int total = herm_identity ? nti * (nti + 1) : nti * ntj;
   if (total == 0) return hipSuccess;
-  const int g = std::max(8, std::min(8 * ((cu_count() + 7) / 8), 8 * (int)cdiv(total, 8)));
+  const int wpc = std::max(1, std::min(wg_per_cu, 4));
+  const int g = std::max(8, std::min(8 * ((wpc * cu_count() + 7) / 8), 8 * (int)cdiv(total, 8)));
   const float sa = conjA ? -1.f : 1.f, sb = conjB ? -1.f : 1.f;
   if (herm_identity)
     hipLaunchKernelGGL(gemm32_kernel<true>, dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A, lda, sa,

@@ -25,6 +25,7 @@ struct GemmDesc {
   void* split_ws = nullptr; size_t split_ws_bytes = 0;
   // batch of independent products (no split-K): operand / result strides in complex elements
   int batch = 1; long bsa = 0, bsb = 0, bsc = 0;
+  int max_split = 16;  // cap on the split-K factor (a tuning knob)
 };
 // Compute precision: P64 -> f64 MFMA; P32 -> f32 MFMA.
 hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st);
@@ -36,7 +37,8 @@ hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st);
 //   herm_identity = true (M = N): C = I + alpha A B, complex128, lower triangle
 //     computed and mirrored (the product must be Hermitian), diagonal real
 hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conjA, const void* B, long ldb,
-                         bool conjB, void* C, long ldc, bool herm_identity, double alpha, hipStream_t st);
+                         bool conjB, void* C, long ldc, bool herm_identity, double alpha, hipStream_t st,
+                         int wg_per_cu = 1);
 bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, long ldb);
 
 // ----- orbital pair Gram (step 1):  out[mu][c] = conj(Pv(mu, c)) * Qc(mu, c)
@@ -44,7 +46,7 @@ bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, lo
 //   pm: [ns][ldp] (orbitals at the points), b: [ns][ldb], both complex64 if in32 else complex128;
 //   out [M][ldo] complex64 if out32 else complex128
 hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
-                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st);
+                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st, int wg_per_cu = 1);
 
 // ----- core (step 2): partial sums over occupied ranges of
 //   M(mu, nu) = sum_{i, j} conj(a_i(mu)) b_j(mu) w_ij a_i(nu) conj(b_j(nu))
@@ -84,6 +86,7 @@ struct DftPlan {
   const int* g_d;          // ng: pair index of plane wave g
   const int* g_cz;         // ng: index into twz list of plane wave g
   const int* dmap;         // kx x ky: pair index d of (x-frequency a, y-frequency b), or -1
+  int zb = 8;              // z-planes per workgroup of the x/y stage (a tuning knob)
 };
 // zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][nd][n2] -> zg: [nmu][ng] (times scale[g] if given)
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);

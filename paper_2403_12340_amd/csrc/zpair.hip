@@ -222,7 +222,7 @@ __global__ __launch_bounds__(ZL::NT) void zpair32_edge_kernel(int M, int N, int 
 }
 
 static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
-                                 long ldb, void* out, long ldo, hipStream_t st) {
+                                 long ldb, void* out, long ldo, hipStream_t st, int wg_per_cu) {
   const int ntm = (int)cdiv(M, ZL::BM), ntn = (int)cdiv(N, ZL::BN);
   if (ntm == 0 || ntn == 0) return hipSuccess;
   // the 16-byte interior path needs K tiles that never straddle the occupied /
@@ -232,8 +232,9 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, l
   const int nti = aligned ? M / ZL::BM : 0, ntj = aligned ? N / ZL::BN : 0;
   const int interior = nti * ntj;
   if (interior > 0) {
-    // one workgroup per CU (a multiple of 8: one share per XCD), never more than the tiles
-    const int g = std::max(8, std::min(8 * ((cu_count() + 7) / 8), 8 * (int)cdiv(interior, 8)));
+    // wg_per_cu workgroups per CU (a multiple of 8: one share per XCD), never more than the tiles
+    const int wpc = std::max(1, std::min(wg_per_cu, 4));
+    const int g = std::max(8, std::min(8 * ((wpc * cu_count() + 7) / 8), 8 * (int)cdiv(interior, 8)));
     hipLaunchKernelGGL(zpair32_kernel, dim3(g), dim3(ZL::NT), 0, st, nv, ns, (const c32*)pm, ldp,
                        (const c32*)b, ldb, (float*)out, ldo, nti, interior);
     hipError_t e = hipGetLastError();
@@ -262,14 +263,14 @@ static hipError_t zpair_launch(int M, int N, int nv, int ns, const void* pm, lon
 }
 
 hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
-                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st) {
+                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st, int wg_per_cu) {
   if (compute == P64) {
     if (out32 || in32) return hipErrorInvalidValue;
     return zpair_launch<double, double, double, TZ64>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
   }
   // single precision: complex64 operands and output (the orbitals are converted once)
   if (!in32 || !out32) return hipErrorInvalidValue;
-  return zpair32_launch(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+  return zpair32_launch(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st, wg_per_cu);
 }
 
 // ----------------------------------------------------------------------------

@@ -379,3 +379,27 @@ def test_multi_system_concurrent_graph():
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         isdf.eps_inv_multi(plans, psis, es, outs, wss)
+
+
+def test_plan_autotune():
+    """The autotuner picks knobs from its candidate lists; the tuned plan still
+    meets the parity bar, and out-of-range knobs are rejected."""
+    inp, prob, plan = _plan_case("kmaj", "fp32")
+    print("[autotune] case=kmaj", flush=True)
+    psi, e = dev(inp.psi_t), dev(inp.energies)
+    ws, out = plan.new_workspace(), plan.new_output()
+    t = plan.autotune(psi, e, out, ws, reps=2)
+    assert t["dft_zb"] in (2, 4, 8, 16) and t["core_split_pct"] in (50, 100, 200)
+    assert t["gram_split"] in (4, 8, 16) and t["wg_per_cu"] in (1, 2) and t["best_ms"] > 0
+    assert plan.get_tune()["dft_zb"] == t["dft_zb"]
+    plan.eps_inv_async(psi, e, out, ws)
+    plan.sync()
+    assert relf(out[0].cpu().numpy(), oracle.eps_inv_isdf(inp, stages=get_stages("kmaj"))) <= TOL_EPS["fp32"]
+    for knobs in ({"dft_zb": 2, "core_split_pct": 200, "gram_split": 4, "wg_per_cu": 2},
+                  {"dft_zb": 16, "core_split_pct": 50, "gram_split": 1, "wg_per_cu": 1}):
+        plan.set_tune(**knobs)
+        plan.eps_inv_async(psi, e, out, ws)
+        plan.sync()
+        assert relf(out[0].cpu().numpy(), oracle.eps_inv_isdf(inp, stages=get_stages("kmaj"))) <= TOL_EPS["fp32"]
+    with pytest.raises(isdf.IsdfError):
+        plan.set_tune(dft_zb=0)
