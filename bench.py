@@ -216,6 +216,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--omegas", type=int, default=32,
                     help="also time one mixed-path call with this many imaginary frequencies (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true", help="time the plans with their default launch knobs")
     ap.add_argument("--no-batch-systems", action="store_true",
                     help="skip the 48^3 + 8 uneven systems frequency batch (one graph launch)")
     args = ap.parse_args()
@@ -246,6 +247,8 @@ def main():
         plan = isdf.Plan(prob, inp.mu_idx, inp.miller)
         ws = plan.new_workspace()
         out = plan.new_output()
+        tune = plan.autotune(psi, e_dev, out, ws, reps=2) if not args.no_autotune else plan.get_tune()
+        print(f"[bench] {prec} tune {tune}", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             plan.eps_inv_async(psi, e_dev, out, ws)
         plan.sync()
@@ -268,7 +271,7 @@ def main():
             stages += np.array(list(r.report.stage_ms))
         stages /= nrep
         del plan, ws, ws2, out2
-        results[prec] = dict(ms_per_step=dt * 1e3, builds_per_s=1.0 / dt, stage_ms=stages.tolist())
+        results[prec] = dict(ms_per_step=dt * 1e3, builds_per_s=1.0 / dt, stage_ms=stages.tolist(), tune=tune)
         print(f"[bench] {prec}: {dt * 1e3:.3f} ms/build  stages(ms) {np.round(stages, 3).tolist()}",
               file=sys.stderr, flush=True)
 
@@ -356,6 +359,7 @@ def main():
                       "ms_per_step": round(results["fp64"]["ms_per_step"], 4),
                       "zpair_tflops": round(fp64_z, 2), "zpair_frac_fp64_peak": round(fp64_z / PEAK["fp64"], 4)},
         "speedup_mixed_vs_fp64": round(results["fp64"]["ms_per_step"] / m["ms_per_step"], 3),
+        "tune": {"mixed": m["tune"], "fp64": results["fp64"]["tune"]},
         "errors_vs_oracle": errors,
         "algorithmic_tflops": {"mixed": round(total_flops / (m["ms_per_step"] * 1e-3) / 1e12, 2),
                                "fp64": round(total_flops / (results["fp64"]["ms_per_step"] * 1e-3) / 1e12, 2)},
