@@ -232,6 +232,74 @@ def eps_inv_smw(u: np.ndarray, m: np.ndarray) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# Full-grid Coulomb Gram (the paper's P^H V P over the whole real-space grid)
+# ----------------------------------------------------------------------------
+def grid_miller(n: int) -> np.ndarray:
+    """Every Miller vector of the n^3 grid, components in [-n/2, n/2)."""
+    r = np.arange(-(n // 2), n - n // 2)
+    mz, my, mx = np.meshgrid(r, r, r, indexing="ij")
+    return np.stack([mx.ravel(), my.ravel(), mz.ravel()], axis=1).astype(np.int32)
+
+
+def full_grid_list(miller: np.ndarray, n: int) -> np.ndarray:
+    """The plane-wave list followed by every other grid vector."""
+    allm = grid_miller(n)
+    key = lambda m: (m[:, 0] % n) + n * ((m[:, 1] % n) + n * (m[:, 2] % n))
+    rest = allm[~np.isin(key(allm), key(np.asarray(miller)))]
+    return np.concatenate([np.asarray(miller, dtype=np.int32), rest])
+
+
+def eps_inv_exact_full(inp, f=PAIR_FACTOR, omega=0.0, v_scale=None):
+    """NG block of the inverse of eps~ over the whole grid, chi0 from every pair.
+
+    Dense over all Nr plane waves: small grids only.
+    """
+    vs = inp.v_scale if v_scale is None else v_scale
+    full = full_grid_list(inp.miller, inp.n)
+    v = coulomb_diag(full, inp.cell, vs)
+    chi = chi0_exact_pw(inp.psi_t, inp.energies, inp.nv, inp.n, full, f, omega)
+    return invert_lu(eps_tilde(chi, v))[:inp.ng, :inp.ng]
+
+
+def u_full(inp, stages, v_scale=None) -> np.ndarray:
+    """U = V^{1/2} F Theta on the whole grid, rows in full_grid_list order (Nr, N_mu)."""
+    vs = inp.v_scale if v_scale is None else v_scale
+    full = full_grid_list(inp.miller, inp.n)
+    return np.sqrt(coulomb_diag(full, inp.cell, vs))[:, None] * theta_pw(stages["theta"], inp.n, full)
+
+
+def eps_inv_smw_full(inp, f=PAIR_FACTOR, omega=0.0, v_scale=None, stages=None):
+    """NG block of the SMW form with the Gram U^H U summed over the whole grid.
+
+    I + U_NG (M^{-1} - U^H U)^{-1} U_NG^H (eq. epsilon_with_SMW, symmetrised),
+    U over every grid vector, explicit inverses as the formula reads.
+    """
+    st = stages if stages is not None else isdf_stages(inp, f, omega, v_scale)
+    u = u_full(inp, st, v_scale)
+    k = np.linalg.inv(np.linalg.inv(st["m"]) - np.conj(u.T) @ u)
+    un = u[:inp.ng]
+    return np.eye(inp.ng) + un @ k @ np.conj(un.T)
+
+
+def eps_inv_isdf_full(inp, f=PAIR_FACTOR, omega=0.0, v_scale=None, stages=None, tol=1e-12):
+    """NG block of the inverse of eps~ = I - U M U^H over the whole grid (ISDF pairs).
+
+    U = V^{1/2} F Theta on every grid vector.  Plane waves where every column of U
+    is below tol (relative) lie outside the pair products' Fourier support; there
+    eps~ is the identity to that tolerance, so the dense LU runs on the support
+    plus the output list.
+    """
+    st = stages if stages is not None else isdf_stages(inp, f, omega, v_scale)
+    u = u_full(inp, st, v_scale)
+    norms = np.linalg.norm(u, axis=1)
+    keep = norms > tol * norms.max()
+    keep[:inp.ng] = True
+    uk = u[keep]
+    eps = np.eye(uk.shape[0]) - uk @ st["m"] @ np.conj(uk.T)
+    return invert_lu(eps)[:inp.ng, :inp.ng]
+
+
+# ----------------------------------------------------------------------------
 # Sampled evaluations for full-size checks
 # ----------------------------------------------------------------------------
 def isdf_gram(psi_t, nv, mu_idx) -> np.ndarray:

@@ -60,6 +60,8 @@ CONFIGS = {
     # Uneven systems batched with the 48^3 one (Nc = 4 Nv, N_mu = 10 Nv, NG = 32 Nv).
     **{f"batch{i}": dict(n=n, nv=nv, nc=4 * nv, nmu=10 * nv, ng=32 * nv, complex=True, seed=30 + i)
        for i, (n, nv) in enumerate(zip((24, 25, 27, 28, 30, 32, 36, 40), (16, 20, 24, 28, 32, 40, 44, 48)))},
+    # Odd 33^3 grid above 32 points per axis (every grid vector in the Gram: two DFT x/y chunks).
+    "wide": dict(n=33, nv=6, nc=18, nmu=60, ng=300, complex=True, seed=12),
     # Full rank: N_mu = Nv * Nc, where ISDF is exact.
     "fullrank": dict(n=12, nv=4, nc=6, nmu=24, ng=200, complex=True, seed=8),
     "fullrank_real": dict(n=12, nv=4, nc=6, nmu=24, ng=200, complex=False, seed=9),

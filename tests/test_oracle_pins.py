@@ -327,3 +327,58 @@ def test_pair_weights_two_pole_sum():
         two = 1.0 / (1j * om + d) + 1.0 / (-1j * om + d)
         np.testing.assert_allclose(2 * w, two.real, rtol=1e-14)
         assert np.abs(two.imag).max() < 1e-14
+
+
+# ---- full-grid Coulomb Gram (the paper's P^H V P over the whole grid) ----------------
+def test_full_grid_list_is_a_permutation_of_the_grid():
+    inp = synth.make_inputs("tiny")
+    full = oracle.full_grid_list(inp.miller, inp.n)
+    assert full.shape == (inp.nr, 3)
+    assert np.array_equal(full[:inp.ng], inp.miller)
+    key = (full[:, 0] % inp.n) + inp.n * ((full[:, 1] % inp.n) + inp.n * (full[:, 2] % inp.n))
+    assert np.array_equal(np.sort(key), np.arange(inp.nr))
+
+
+def test_full_grid_isdf_equals_exact_at_full_rank():
+    """N_mu = Nv Nc: the ISDF route over the support (dense LU) equals chi0 from every
+    pair over the whole grid (dense LU over all Nr plane waves)."""
+    inp = synth.make_inputs("fullrank")
+    a = oracle.eps_inv_isdf_full(inp)
+    b = oracle.eps_inv_exact_full(inp)
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-10
+
+
+def test_full_grid_support_cut_is_exact():
+    """Dropping the plane waves outside the pair products' Fourier support changes
+    nothing at the level of the tolerance: compare with the uncut whole grid."""
+    inp = synth.make_inputs("tiny")
+    st = oracle.isdf_stages(inp)
+    a = oracle.eps_inv_isdf_full(inp, stages=st)
+    b = oracle.eps_inv_isdf_full(inp, stages=st, tol=0.0)
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-12
+
+
+def test_full_grid_differs_from_truncated():
+    """The full-grid Gram is a different (larger) operator than the NG-truncated one:
+    the NG blocks differ when NG does not cover the support, and agree when it does."""
+    inp = synth.make_inputs("cfg0")
+    st = oracle.isdf_stages(inp)
+    full = oracle.eps_inv_isdf_full(inp, stages=st)
+    trunc = oracle.eps_inv_isdf(inp, stages=st)
+    assert np.linalg.norm(full - trunc) / np.linalg.norm(trunc) > 1e-8
+    big = synth.make_inputs("tiny", ng=synth.make_inputs("tiny").nr)   # NG = every grid vector
+    stb = oracle.isdf_stages(big)
+    a = oracle.eps_inv_isdf_full(big, stages=stb)
+    b = oracle.eps_inv_isdf(big, stages=stb)
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["tiny", "cfg0"])
+def test_full_grid_smw_equals_dense_inverse(name):
+    """SMW with the Gram summed over every grid vector equals the dense LU inverse of
+    I - U M U^H over the whole grid (support-cut): two routes to the same NG block."""
+    inp = synth.make_inputs(name)
+    st = oracle.isdf_stages(inp)
+    a = oracle.eps_inv_smw_full(inp, stages=st)
+    b = oracle.eps_inv_isdf_full(inp, stages=st, tol=0.0)
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-10
