@@ -81,6 +81,14 @@ typedef struct {
   double v_scale;        /* Coulomb prefactor; Nr / cell volume for unit-norm grid orbitals */
   int32_t prec;          /* isdf_precision */
   int32_t refine_steps;  /* FP64 Newton refinement steps T <- T + T (I - H T) on the core inverse, 0..8 */
+  int32_t coulomb_sum;   /* plane waves the Coulomb Gram Z^H V Z sums over (eqs. 11-13):
+                            0: the ng-vector list (the truncated basis, default);
+                            1: every grid vector, the paper's P^H V P over the whole FFT grid.
+                            The output is the ng x ng block over the list in both cases; with 1
+                            the workspace grows with Nr (isdf_workspace_bytes accounts for it).
+                            Read by the calls that take a plane-wave list (isdf_eps_inv,
+                            isdf_coulomb_u, isdf_plan_create); isdf_smw_apply sums over the
+                            rows of the U it is given. */
 } isdf_problem;
 
 typedef struct {
@@ -99,6 +107,9 @@ typedef struct {
   double min_pivot;          /* smallest diagonal entry of H (last frequency) */
   int32_t want_timing;       /* input: 1 to record per-stage HIP events (adds host syncs) */
   int32_t n_refine_reported; /* number of valid refine_residual entries */
+  double cond_est;           /* ||H||_F ||H^{-1}||_F of the last frequency, an upper bound on the
+                                2-norm condition number of the core H (isdf_eps_inv, isdf_smw_apply,
+                                plans); the core inverse loses about log10(cond_est) digits */
 } isdf_report;
 
 /* Create a handle bound to HIP device `device` and stream `hip_stream`

@@ -32,7 +32,8 @@ class IsdfError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("cell", ctypes.c_double * 9), ("nv", ctypes.c_int32),
                 ("nc", ctypes.c_int32), ("is_complex", ctypes.c_int32), ("pair_factor", ctypes.c_double),
-                ("v_scale", ctypes.c_double), ("prec", ctypes.c_int32), ("refine_steps", ctypes.c_int32)]
+                ("v_scale", ctypes.c_double), ("prec", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("coulomb_sum", ctypes.c_int32)]
 
 
 class Tune(ctypes.Structure):
@@ -46,7 +47,7 @@ class Tune(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double * 8), ("refine_residual", ctypes.c_double * 9),
                 ("min_pivot", ctypes.c_double), ("want_timing", ctypes.c_int32),
-                ("n_refine_reported", ctypes.c_int32)]
+                ("n_refine_reported", ctypes.c_int32), ("cond_est", ctypes.c_double)]
 
 
 _lib = None
@@ -106,7 +107,7 @@ def header_functions() -> list[str]:
 
 
 def make_problem(n, cell, nv, nc, *, is_complex=True, pair_factor=2.0, v_scale=None,
-                 prec="fp64", refine_steps=0) -> Problem:
+                 prec="fp64", refine_steps=0, coulomb_sum=0) -> Problem:
     p = Problem()
     n = (n, n, n) if np.isscalar(n) else tuple(n)
     for d in range(3):
@@ -122,6 +123,7 @@ def make_problem(n, cell, nv, nc, *, is_complex=True, pair_factor=2.0, v_scale=N
     p.v_scale = float(v_scale)
     p.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
     p.refine_steps = int(refine_steps)
+    p.coulomb_sum = int(coulomb_sum)
     return p
 
 
@@ -473,8 +475,8 @@ def eps_inv_multi(plans, psis, energies_devs, outs, workspaces, omegas=None):
     return outs
 
 
-def problem_for(inp, prec="fp64", refine_steps=0, v_scale=None) -> Problem:
+def problem_for(inp, prec="fp64", refine_steps=0, v_scale=None, coulomb_sum=0) -> Problem:
     """Problem description for a synthetic input set (synth.Inputs)."""
     return make_problem(inp.n, inp.cell, inp.nv, inp.nc, is_complex=inp.is_complex,
                         v_scale=inp.v_scale if v_scale is None else v_scale, prec=prec,
-                        refine_steps=refine_steps)
+                        refine_steps=refine_steps, coulomb_sum=coulomb_sum)

@@ -25,6 +25,7 @@
 #include <map>
 #include <set>
 #include <string>
+#include <deque>
 #include <vector>
 
 #include "../../include/isdf_smw.h"
@@ -57,12 +58,14 @@ struct StatusBlock {
   int pad;
   double min_pivot;
   double res[10];
-  double lh2;
+  double h2, t2;  // ||H||_F^2 and ||H^{-1}||_F^2 of the last frequency (condition estimate)
   double partial[1024];
 };
 
 struct Problem {
   int n0, n1, n2, nv, nc, ns, nmu, ng, nomega;
+  int ngg;         // plane waves the Coulomb Gram runs over: ng, or every grid vector (coulomb_sum = 1)
+  bool full_gram;
   long nr;
   bool cplx;
   Prec prec;
@@ -110,6 +113,28 @@ DftIndex dft_index(const int32_t* miller, int ng) {
   return ix;
 }
 
+// The plane-wave list followed by every other grid vector (components in
+// [-n_d/2, n_d/2)): the rows of the whole-grid Coulomb Gram, output list first.
+std::vector<int32_t> full_grid_list(const int32_t* miller, int ng, int n0, int n1, int n2) {
+  const long nr = (long)n0 * n1 * n2;
+  std::vector<char> in(nr, 0);
+  auto key = [&](int x, int y, int z) {
+    return (long)((x % n0 + n0) % n0) + n0 * ((long)((y % n1 + n1) % n1) + (long)n1 * ((z % n2 + n2) % n2));
+  };
+  std::vector<int32_t> out(miller, miller + 3 * (size_t)ng);
+  out.reserve(3 * (size_t)nr);
+  for (int g = 0; g < ng; ++g) in[key(miller[3 * g], miller[3 * g + 1], miller[3 * g + 2])] = 1;
+  for (int z = -(n2 / 2); z < n2 - n2 / 2; ++z)
+    for (int y = -(n1 / 2); y < n1 - n1 / 2; ++y)
+      for (int x = -(n0 / 2); x < n0 - n0 / 2; ++x)
+        if (!in[key(x, y, z)]) {
+          out.push_back(x);
+          out.push_back(y);
+          out.push_back(z);
+        }
+  return out;
+}
+
 // Workspace layout.  Offsets in bytes from the workspace base.
 struct Layout {
   size_t psi_c = 0, pm = 0, mu = 0, e = 0, w = 0, s = 0, lin = 0, zt = 0, tabs = 0, t2 = 0, zg = 0,
@@ -143,11 +168,11 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   // host-supplied arrays, adjacent so that one copy uploads them all
   L.mu = take((size_t)P.nmu * 4);
   L.e = take((size_t)P.ns * 8);
-  L.miller = take((size_t)P.ng * 3 * 4);
+  L.miller = take((size_t)P.ngg * 3 * 4);
   L.recip = take(9 * 8);
-  L.idx = take((size_t)(kx + ky + kz + 2 * nd + 2 * P.ng + kx * ky) * 4);
+  L.idx = take((size_t)(kx + ky + kz + 2 * nd + 2 * P.ngg + kx * ky) * 4);
   L.w = take((size_t)P.nv * P.nc * 8);
-  L.sqrtv = take((size_t)P.ng * 8);
+  L.sqrtv = take((size_t)P.ngg * 8);
   L.twx = take((size_t)kx * P.n0 * el);
   L.twy = take((size_t)ky * P.n1 * el);
   L.twz = take((size_t)kz * P.n2 * el);
@@ -155,7 +180,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.s = take(nmu2 * z);
   L.lin = take(linalg_scratch_bytes(P.nmu));
   L.t2 = take((size_t)P.nmu * P.n2 * nd * el);
-  L.zg = take((size_t)P.nmu * P.ng * el);
+  L.zg = take((size_t)P.nmu * P.ngg * el);
   L.u = take((size_t)P.ng * P.nmu * el);
   L.l = take(nmu2 * z);
   L.l2 = take(nmu2 * z);
@@ -220,6 +245,7 @@ isdf_status check_problem(isdf_handle h, const isdf_problem* pr, Problem& P) {
   if (pr->refine_steps < 0 || pr->refine_steps > 8) return fail(h, ISDF_E_ARG, "refine_steps must be in [0, 8]");
   if (pr->prec != ISDF_FP64 && pr->prec != ISDF_FP32 && pr->prec != ISDF_BF16X3) return fail(h, ISDF_E_ARG, "unknown precision");
   if (pr->is_complex != 0 && pr->is_complex != 1) return fail(h, ISDF_E_ARG, "is_complex must be 0 or 1");
+  if (pr->coulomb_sum != 0 && pr->coulomb_sum != 1) return fail(h, ISDF_E_ARG, "coulomb_sum must be 0 or 1");
   const double* c = pr->cell;
   const double det = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) + c[2] * (c[3] * c[7] - c[4] * c[6]);
   if (!(std::fabs(det) > 1e-12) || !std::isfinite(det)) return fail(h, ISDF_E_ARG, "cell is singular");
@@ -232,6 +258,7 @@ isdf_status check_problem(isdf_handle h, const isdf_problem* pr, Problem& P) {
   P.f = pr->pair_factor;
   P.v_scale = pr->v_scale;
   P.refine = pr->refine_steps;
+  P.full_gram = pr->coulomb_sum == 1;
   // reciprocal basis rows b_i = 2 pi (cell^{-1})^T rows
   const double inv[9] = {(c[4] * c[8] - c[5] * c[7]) / det, -(c[1] * c[8] - c[2] * c[7]) / det, (c[1] * c[5] - c[2] * c[4]) / det,
                          -(c[3] * c[8] - c[5] * c[6]) / det, (c[0] * c[8] - c[2] * c[6]) / det, -(c[0] * c[5] - c[2] * c[3]) / det,
@@ -301,7 +328,9 @@ struct Uploader {
   void* ws = nullptr;
   struct Item { size_t off; const void* src; size_t bytes; };
   std::vector<Item> items;
+  std::deque<std::vector<int32_t>> keep;   // host arrays built for this call, alive until run()
   void add(size_t off, const void* s, size_t bytes) { if (bytes) items.push_back({off, s, bytes}); }
+  const int32_t* hold(std::vector<int32_t>&& v) { keep.push_back(std::move(v)); return keep.back().data(); }
   isdf_status run() {
     if (items.empty()) return ISDF_OK;
     size_t lo = items[0].off, hi = 0;
@@ -437,7 +466,7 @@ DftPlan make_plan(Run& R) {
   const Problem& P = R.P;
   const Layout& L = R.L;
   DftPlan p;
-  p.n0 = P.n0; p.n1 = P.n1; p.n2 = P.n2; p.nmu = P.nmu; p.ng = P.ng;
+  p.n0 = P.n0; p.n1 = P.n1; p.n2 = P.n2; p.nmu = P.nmu; p.ng = P.ngg;
   p.kx = L.kx; p.ky = L.ky; p.nd = L.nd; p.kz = L.kz;
   p.zb = R.tune.dft_zb;
   p.twx = at<char>(R.ws, L.twx);
@@ -448,8 +477,8 @@ DftPlan make_plan(Run& R) {
   p.d_ax = ib + L.kx + L.ky + L.kz;
   p.d_by = p.d_ax + L.nd;
   p.g_d = p.d_by + L.nd;
-  p.g_cz = p.g_d + P.ng;
-  p.dmap = p.g_cz + P.ng;
+  p.g_cz = p.g_d + P.ngg;
+  p.dmap = p.g_cz + P.ngg;
   return p;
 }
 
@@ -462,7 +491,7 @@ isdf_status stage_dft(Run& R, bool scaled) {
   const Prec cp = P.prec == P64 ? P64 : P32;
   DftPlan p = make_plan(R);
   const int* ib = R.idx;
-  HIPCHK(coulomb_sqrt(R.miller, P.ng, R.recip, P.v_scale,
+  HIPCHK(coulomb_sqrt(R.miller, P.ngg, R.recip, P.v_scale,
                       at<double>(R.ws, L.sqrtv), R.st));
   HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), R.st));
   HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), R.st));
@@ -480,7 +509,7 @@ isdf_status stage_u(Run& R) {
   const Prec cp = P.prec == P64 ? P64 : P32;
   GemmDesc d;
   d.M = P.ng; d.N = P.nmu; d.K = P.nmu;
-  d.A = at<char>(R.ws, L.zg); d.sam = 1; d.sak = P.ng; d.a32 = P.m32;
+  d.A = at<char>(R.ws, L.zg); d.sam = 1; d.sak = P.ngg; d.a32 = P.m32;
   d.B = at<char>(R.ws, L.s); d.sbk = 1; d.sbn = P.nmu;
   d.C = at<char>(R.ws, L.u); d.ldc = P.nmu; d.c32 = P.m32;
   d.alpha = -1.0;
@@ -501,7 +530,7 @@ isdf_status stage_gram(Run& R, const Basis& b) {
   const Problem& P = R.P;
   const Prec cp = P.prec == P64 ? P64 : P32;
   GemmDesc d;
-  d.M = d.N = P.nmu; d.K = P.ng;
+  d.M = d.N = P.nmu; d.K = P.ngg;   // over the Gram's plane waves (the list, or the whole grid)
   d.A = b.base; d.sam = b.smu; d.sak = b.sg; d.conjA = true; d.a32 = P.m32;
   d.B = b.base; d.sbk = b.sg; d.sbn = b.smu; d.b32 = P.m32;
   d.C = at<char>(R.ws, R.L.g); d.ldc = P.nmu;
@@ -579,8 +608,10 @@ isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   HIPCHK(axpby(at<char>(R.ws, L.g), 1.0, Mi, -1.0, H, n2, R.st));                   // H = G - K
   if (used) HIPCHK(hipEventRecord(used, R.st));
   HIPCHK(diag_min(H, n, &R.sb->min_pivot, R.st));
+  HIPCHK(frob2(H, n2, R.sb->partial, &R.sb->h2, R.st));
   if (P.refine > 0) HIPCHK(convert_z(H, false, at<char>(R.ws, L.acopy), false, n2, R.st));
   HIPCHK(sweep_inverse(n, H, at<char>(R.ws, L.lin), &R.sb->status, R.st));          // -T
+  HIPCHK(frob2(H, n2, R.sb->partial, &R.sb->t2, R.st));
   R.tmat = H;
   R.talpha = -1.0;
   if (P.refine == 0) return ISDF_OK;
@@ -592,18 +623,18 @@ isdf_status stage_out(Run& R, const Basis& b, void* out, Timer& tm) {
   const Problem& P = R.P;
   const Layout& L = R.L;
   const Prec cp = P.prec == P64 ? P64 : P32;
-  if (P.m32 && b.sg == 1 && b.smu == P.ng && gemm32_fits(P.nmu, P.ng, P.nmu, b.base, P.ng, b.base, P.ng) &&
-      gemm32_fits(P.ng, P.ng, P.nmu, at<char>(R.ws, L.w1), P.ng, b.base, P.ng)) {
+  if (P.m32 && b.sg == 1 && b.smu >= P.ng && gemm32_fits(P.nmu, P.ng, P.nmu, b.base, b.smu, b.base, b.smu) &&
+      gemm32_fits(P.ng, P.ng, P.nmu, at<char>(R.ws, L.w1), P.ng, b.base, b.smu)) {
     // Mixed path with the basis stored [point][plane wave] (X^T): both products
     // have k-major operands.  W^T = talpha T^T X^T, then eps~^{-1} = I - W X^H.
     // T goes to complex64 in the refinement-residual buffer (free by now).
     void* t32 = at<char>(R.ws, L.rres);
     void* wt = at<char>(R.ws, L.w1);
     HIPCHK(convert_z(R.tmat, false, t32, true, (long)P.nmu * P.nmu, R.st));
-    HIPCHK(gemm32_kmajor(P.nmu, P.ng, P.nmu, t32, P.nmu, false, b.base, P.ng, false, wt, P.ng, false,
+    HIPCHK(gemm32_kmajor(P.nmu, P.ng, P.nmu, t32, P.nmu, false, b.base, b.smu, false, wt, P.ng, false,
                          R.talpha, R.st, R.tune.wg_per_cu));
     tm.mark();
-    HIPCHK(gemm32_kmajor(P.ng, P.ng, P.nmu, wt, P.ng, false, b.base, P.ng, true, out, P.ng, true, -1.0, R.st,
+    HIPCHK(gemm32_kmajor(P.ng, P.ng, P.nmu, wt, P.ng, false, b.base, b.smu, true, out, P.ng, true, -1.0, R.st,
                          R.tune.wg_per_cu));
     return ISDF_OK;
   }
@@ -630,6 +661,7 @@ isdf_status begin(isdf_handle h, const isdf_problem* prob, Problem& P, int nmu, 
   if (s != ISDF_OK) return s;
   P.nmu = nmu;
   P.ng = ng;
+  P.ngg = P.full_gram ? (int)P.nr : ng;
   P.nomega = nomega;
   if (P.prec == PBF3) return fail(h, ISDF_E_UNSUPPORTED, "BF16x3 precision is not available in this build");
   return ISDF_OK;
@@ -642,6 +674,7 @@ enum { ST_NOT_PD = 1, ST_NO_GAP = 2 };
 isdf_status report_status(isdf_handle h, const StatusBlock& hs, const Problem& P, isdf_report* rep) {
   if (rep) {
     rep->min_pivot = hs.min_pivot;
+    rep->cond_est = std::sqrt(hs.h2 * hs.t2);
     rep->n_refine_reported = P.refine > 0 ? P.refine + 1 : 0;
     for (int k = 0; k < 9; ++k)
       rep->refine_residual[k] = k < rep->n_refine_reported ? std::sqrt(hs.res[k] / (double)P.nmu) : 0.0;
@@ -683,10 +716,13 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
   if (miller) {
     s = check_miller(h, R.P, miller, ng);
     if (s != ISDF_OK) return s;
-    ix = dft_index(miller, ng);
+    // the Gram's plane waves: the list itself, or the list followed by the rest of the grid
+    if (R.P.full_gram) miller = up_.hold(full_grid_list(miller, ng, R.P.n0, R.P.n1, R.P.n2));
+    ix = dft_index(miller, R.P.ngg);
     if (!dft_supported(R.P.n0, R.P.n1, (int)ix.xl.size(), (int)ix.yl.size(), R.P.prec == P64 ? P64 : P32))
       return fail(h, ISDF_E_UNSUPPORTED, "grid plane too large for the LDS-resident DFT slab");
   } else {
+    R.P.ngg = ng;   // no Gram in this call
     ix.xl = ix.yl = ix.zl = {0};
     ix.d_ax = ix.d_by = {0};
     ix.dmap = {-1};
@@ -712,7 +748,7 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
   up_.add(R.L.mu, mu_idx, (size_t)n_mu * 4);
   if (energies) up_.add(R.L.e, energies, (size_t)R.P.ns * 8);
   if (miller) {
-    up_.add(R.L.miller, miller, (size_t)ng * 12);
+    up_.add(R.L.miller, miller, (size_t)R.P.ngg * 12);
     idxbuf.clear();
     for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz, &ix.dmap})
       idxbuf.insert(idxbuf.end(), v->begin(), v->end());
@@ -784,14 +820,17 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
   tm.mark();
   TRY(stage_dft(R, true));
   tm.mark();
-  const Basis xb{at<char>(R.ws, L.zg), 1, (long)ng};
+  const Basis xb{at<char>(R.ws, L.zg), 1, (long)P.ngg};
   TRY(stage_gram(R, xb));
   tm.mark();
   HIPCHK(hipStreamWaitEvent(R.st, h->m_ready[0], 0));
   void* hb = at<char>(R.ws, L.hb);
   HIPCHK(sub_bcast(at<char>(R.ws, L.g), mb, hb, n2, nw, R.st));                          // H(omega)
   HIPCHK(diag_min(hb, n, &R.sb->min_pivot, R.st, nw));
+  char* hlast = at<char>(R.ws, L.hb) + (size_t)(nw - 1) * n2 * 16;
+  HIPCHK(frob2(hlast, n2, R.sb->partial, &R.sb->h2, R.st));
   HIPCHK(sweep_inverse(n, hb, at<char>(R.ws, L.lb), &R.sb->status, R.st, nw));            // -T(omega)
+  HIPCHK(frob2(hlast, n2, R.sb->partial, &R.sb->t2, R.st));
   for (int k = 0; k < nw; ++k) {
     Timer dummy{h, false};
     Timer& t = (k == nw - 1) ? tm : dummy;
@@ -857,7 +896,7 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   tm.mark();
   TRY(stage_dft(R, true));
   tm.mark();
-  const Basis xb{at<char>(R.ws, R.L.zg), 1, (long)ng};
+  const Basis xb{at<char>(R.ws, R.L.zg), 1, (long)R.P.ngg};
   TRY(stage_gram(R, xb));
   tm.mark();
   for (int k = 0; k < nw; ++k) {
@@ -942,9 +981,10 @@ isdf_status isdf_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t
   P.nmu = n_mu;
   P.ng = ng;
   P.nomega = n_omega;
-  // worst-case DFT bookkeeping for ng vectors: every list at most min(ng, n_d), pairs at most ng
-  const int kx = std::min(ng, P.n0), ky = std::min(ng, P.n1), kz = std::min(ng, P.n2);
-  const int nd = (int)std::min<long>(ng, (long)P.n0 * P.n1);
+  P.ngg = P.full_gram ? (int)P.nr : ng;
+  // worst-case DFT bookkeeping for ngg vectors: every list at most min(ngg, n_d), pairs at most ngg
+  const int kx = std::min(P.ngg, P.n0), ky = std::min(P.ngg, P.n1), kz = std::min(P.ngg, P.n2);
+  const int nd = (int)std::min<long>(P.ngg, (long)P.n0 * P.n1);
   *bytes = make_layout(P, kx, ky, kz, nd).total;
   return ISDF_OK;
 }
@@ -1152,7 +1192,12 @@ isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int3
   TRY(begin(h, prob, P, n_mu, ng, n_omega));
   TRY(check_points(h, P, mu_idx, n_mu));
   TRY(check_miller(h, P, miller, ng));
-  DftIndex ix = dft_index(miller, ng);
+  std::vector<int32_t> full;
+  if (P.full_gram) {
+    full = full_grid_list(miller, ng, P.n0, P.n1, P.n2);
+    miller = full.data();
+  }
+  DftIndex ix = dft_index(miller, P.ngg);
   if (!dft_supported(P.n0, P.n1, (int)ix.xl.size(), (int)ix.yl.size(), P.prec == P64 ? P64 : P32))
     return fail(h, ISDF_E_UNSUPPORTED, "grid plane too large for the LDS-resident DFT slab");
   std::vector<int> idxbuf;
@@ -1165,12 +1210,12 @@ isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int3
   pl->L = make_layout(P, (int)ix.xl.size(), (int)ix.yl.size(), (int)ix.zl.size(), (int)ix.d_ax.size());
   size_t off = up(sizeof(StatusBlock));
   pl->off_mu = off; off += up((size_t)n_mu * 4);
-  pl->off_miller = off; off += up((size_t)ng * 12);
+  pl->off_miller = off; off += up((size_t)P.ngg * 12);
   pl->off_recip = off; off += up(9 * 8);
   pl->off_idx = off; off += up(idxbuf.size() * 4);
   std::vector<char> host(off, 0);
   std::memcpy(host.data() + pl->off_mu, mu_idx, (size_t)n_mu * 4);
-  std::memcpy(host.data() + pl->off_miller, miller, (size_t)ng * 12);
+  std::memcpy(host.data() + pl->off_miller, miller, (size_t)P.ngg * 12);
   std::memcpy(host.data() + pl->off_recip, P.recip, 9 * 8);
   std::memcpy(host.data() + pl->off_idx, idxbuf.data(), idxbuf.size() * 4);
   auto bail = [&](hipError_t e) {

@@ -44,6 +44,19 @@ def test_workspace_bytes_monotone_and_validated():
     assert isdf.lib().isdf_workspace_bytes(ctypes.byref(prob), 0, 4096, 0, ctypes.byref(out)) == isdf.binding.E_ARG
 
 
+def test_workspace_bytes_whole_grid_gram():
+    """coulomb_sum = 1 sizes the Gram operands for every grid vector; other values are rejected."""
+    prob = isdf.make_problem(48, np.eye(3) * 20.0, 64, 256, prec="fp32")
+    full = isdf.make_problem(48, np.eye(3) * 20.0, 64, 256, prec="fp32", coulomb_sum=1)
+    a = isdf.workspace_bytes(prob, 640, 4096)
+    b = isdf.workspace_bytes(full, 640, 4096)
+    # at least the N_mu x Nr complex64 X^T the whole-grid Gram reads
+    assert b - a >= 640 * (48 ** 3 - 4096) * 8
+    out = ctypes.c_size_t(0)
+    bad = isdf.make_problem(48, np.eye(3) * 20.0, 64, 256, coulomb_sum=2)
+    assert isdf.lib().isdf_workspace_bytes(ctypes.byref(bad), 640, 4096, 0, ctypes.byref(out)) == isdf.binding.E_ARG
+
+
 @pytest.fixture(scope="module")
 def cfg0():
     return synth.make_inputs("cfg0")

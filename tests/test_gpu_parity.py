@@ -124,6 +124,44 @@ def test_fullrank_equals_exact_definition():
     assert relf(got, ref) <= 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["tiny", "cfg0", "fullrank", "wide"])
+def test_eps_inv_whole_grid_gram(name, prec):
+    """coulomb_sum = 1: the Gram X^H X runs over every grid vector (33^3 in 'wide',
+    two DFT chunks per axis); the NG block equals the oracle's SMW with the
+    whole-grid Gram."""
+    inp = get_inputs(name)
+    print(f"[whole-grid] case={name} prec={prec}", flush=True)
+    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller,
+                       isdf.problem_for(inp, prec, coulomb_sum=1))
+    got = res.eps_inv[0].cpu().numpy()
+    ref = oracle.eps_inv_smw_full(inp, stages=get_stages(name))
+    err = relf(got, ref)
+    print(f"  rel-F {err:.3e}", flush=True)
+    assert err <= TOL_EPS[prec], err
+    assert np.array_equal(got, got.conj().T)
+    if name == "fullrank" and prec == "fp64":   # ISDF exact: chi0 from every pair, whole grid, dense LU
+        assert relf(got, oracle.eps_inv_exact_full(inp)) <= 1e-10
+
+
+def test_plan_whole_grid_frequencies():
+    """Plan path with coulomb_sum = 1 and a frequency batch: equals the direct call."""
+    inp = synth.make_inputs("wide", n_omega=3)
+    prob = isdf.problem_for(inp, "fp32", coulomb_sum=1)
+    psi = dev(inp.psi_t)
+    direct = isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob, omegas=inp.omegas).eps_inv.cpu()
+    plan = isdf.Plan(prob, inp.mu_idx, inp.miller, n_omega=3)
+    out = plan.new_output()
+    plan.eps_inv_async(psi, dev(inp.energies), out, plan.new_workspace(), omegas=inp.omegas)
+    plan.sync()
+    assert torch.equal(out.cpu(), direct)
+    st = get_stages("wide")
+    for k, om in enumerate(inp.omegas):
+        stw = dict(st)
+        stw["m"] = oracle.core_matrix(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, omega=om)
+        assert relf(direct[k].numpy(), oracle.eps_inv_smw_full(inp, stages=stw)) <= TOL_EPS["fp32"], k
+
+
 @pytest.mark.parametrize("prec,refine", [("fp64", 0), ("fp32", 0), ("fp32", 1)])
 def test_frequencies(prec, refine):
     """Several imaginary frequencies in one call (the batched-frequency pipeline)."""
@@ -403,3 +441,17 @@ def test_plan_autotune():
         assert relf(out[0].cpu().numpy(), oracle.eps_inv_isdf(inp, stages=get_stages("kmaj"))) <= TOL_EPS["fp32"]
     with pytest.raises(isdf.IsdfError):
         plan.set_tune(dft_zb=0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_condition_estimate(prec):
+    """cond_est = ||H||_F ||H^-1||_F brackets the 2-norm condition number of the
+    core H = U^H U - M^-1 (here formed by the oracle) from above, within a factor n."""
+    inp = get_inputs("mid")
+    st = get_stages("mid")
+    res = isdf.smw_apply(dev(st["u"]), dev(st["m"]), isdf.problem_for(inp, prec))
+    h = st["u"].conj().T @ st["u"] - np.linalg.inv(st["m"])
+    k2 = np.linalg.cond(h)
+    ce = res.report.cond_est
+    print(f"  cond2 {k2:.4e}  cond_est {ce:.4e}", flush=True)
+    assert np.isfinite(ce) and k2 * (1 - 1e-6) <= ce <= inp.nmu * k2
