@@ -96,6 +96,30 @@ def _kernel_stats(db):
                      "group by name order by sum(end - start) desc").fetchall()
 
 
+def _phase_dispatches(db, steps, warmup):
+    """Durations (ns) of the mixed path's pair-Gram launches on the benchmark workload,
+    split by the benchmark's fixed order: autotune, W warm-up calls, the K timed calls,
+    then the stage-timing pass (nrep calls), all before the FP64 path's first Z launch
+    (the FP64 pair-Gram kernel over the whole grid; its small launches form S on the points)."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, start, end, grid_x * grid_y * grid_z from kernels where "
+                     "name like 'isdf::zpair32_kernel(%' or name like '%zpair_kernel<double%' "
+                     "order by start").fetchall()
+    big = max((g for n, _, _, g in rows if "zpair_kernel<double" in n), default=0)
+    z32 = []
+    for name, t0, t1, g in rows:
+        if "zpair_kernel<double" in name:
+            if g == big:
+                break
+            continue
+        z32.append(t1 - t0)
+    nrep = max(3, min(steps, 10))
+    if len(z32) < nrep + steps + warmup:
+        return None
+    return {"timed": z32[-(nrep + steps):-nrep], "stage_pass": z32[-nrep:]}
+
+
 def _pmc_per_dispatch(db, counter):
     """[(kernel name, grid size, counter value)] per dispatch from a rocprofv3 --pmc database."""
     import sqlite3
@@ -122,6 +146,14 @@ def summarize(args):
     lines.append(f"{'kernel':<100} {'calls':>6} {'avg_us':>10} {'total_ms':>10} {'share':>6}")
     for name, cnt, avg, ssum in stats[:30]:
         lines.append(f"{name[:100]:<100} {cnt:>6} {avg / 1e3:>10.1f} {ssum / 1e6:>10.3f} {100 * ssum / tot:>5.1f}%")
+    ph = _phase_dispatches(args.summarize, args.steps, args.warmup)
+    if ph:
+        lines.append("")
+        lines.append(f"zpair32_kernel on the benchmark workload (mixed path; the kernel's other launches above belong "
+                     f"to the frequency and multi-system batches)")
+        for key, d in ph.items():
+            lines.append(f"  {key:<10} launches {len(d):>3}  avg_us {np.mean(d) / 1e3:8.1f}  "
+                         f"min_us {np.min(d) / 1e3:8.1f}  max_us {np.max(d) / 1e3:8.1f}")
     if args.pmc_fetch and args.pmc_write:
         import synth
         inp = synth.make_inputs(args.config) if args.config else None
