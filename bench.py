@@ -240,7 +240,7 @@ def main():
     ap.add_argument("--summarize", default=None, help="rocpd database of a --kernel-trace run")
     ap.add_argument("--pmc-fetch", default=None)
     ap.add_argument("--pmc-write", default=None)
-    ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--only", choices=["fp32", "fp64", "bf16x3"], default=None)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)

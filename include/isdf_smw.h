@@ -69,7 +69,9 @@ typedef enum {
 typedef enum {
   ISDF_FP64 = 0,    /* every contraction in FP64 on MFMA */
   ISDF_FP32 = 1,    /* large contractions in FP32 on MFMA, FP32 accumulation; N_mu x N_mu core in FP64 */
-  ISDF_BF16X3 = 2   /* large contractions as three BF16 products (hi*hi + hi*lo + lo*hi), FP32 accumulation; core in FP64 */
+  ISDF_BF16X3 = 2   /* the pair-Gram contraction of step 1 as three BF16 products (hi*hi + hi*lo + lo*hi,
+                       x = hi + lo split by round to nearest) on bf16 MFMA with FP32 accumulation; the
+                       other large contractions as ISDF_FP32; N_mu x N_mu core in FP64 */
 } isdf_precision;
 
 typedef struct {

@@ -146,7 +146,8 @@ struct Layout {
   size_t wb = 0, partb = 0, mb = 0, lb = 0, qb = 0, hb = 0;
   size_t zt_bytes = 0;               // size of the zt region
   size_t part = 0, l2 = 0, lin2 = 0, q = 0;  // core partials; second -M buffer, sweep scratch, S M^-1 S scratch
-  size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (mixed precision only)
+  size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (FP32 mode only)
+  size_t bf_rows = 0, bf_pts = 0;    // bf16 hi / lo planes of the orbitals (BF16x3 mode only)
   int kx = 0, ky = 0, kz = 0, nd = 0, nsplit = 1;
 };
 
@@ -161,9 +162,12 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.status = take(sizeof(StatusBlock));
   L.psi_c = P.cplx ? 0 : take((size_t)P.ns * P.nr * z);
   L.pm = take((size_t)P.ns * P.nmu * z);
-  if (P.m32) {
+  if (P.prec == P32) {
     L.psi32 = take((size_t)P.ns * P.nr * 8);
     L.pm32 = take((size_t)P.ns * P.nmu * 8);
+  } else if (P.prec == PBF3) {
+    L.bf_rows = take(bf3_rows_bytes(P.nr, P.nv, P.nc));
+    L.bf_pts = take(bf3_points_bytes(P.nmu, P.nv, P.nc));
   }
   // host-supplied arrays, adjacent so that one copy uploads them all
   L.mu = take((size_t)P.nmu * 4);
@@ -443,6 +447,11 @@ isdf_status stage_z_operands(Run& R) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   if (P.prec == P64) return ISDF_OK;
+  if (P.prec == PBF3) {
+    HIPCHK(bf3_split_rows(R.psi, P.nr, P.nr, P.nv, P.nc, at<char>(R.ws, R.L.bf_rows), R.st));
+    HIPCHK(bf3_split_points(at<char>(R.ws, R.L.pm), P.nmu, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.bf_pts), R.st));
+    return ISDF_OK;
+  }
   HIPCHK(convert_z(R.psi, false, at<char>(R.ws, R.L.psi32), true, (long)P.ns * P.nr, R.st));
   HIPCHK(convert_z(at<char>(R.ws, R.L.pm), false, at<char>(R.ws, R.L.pm32), true, (long)P.ns * P.nmu, R.st));
   return ISDF_OK;
@@ -455,6 +464,11 @@ isdf_status stage_z(Run& R) {
   if (P.prec == P64) {
     HIPCHK(zpair(P64, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm), P.nmu, R.psi, P.nr, false,
                  at<char>(R.ws, R.L.zt), P.nr, false, R.st));
+    return ISDF_OK;
+  }
+  if (P.prec == PBF3) {
+    HIPCHK(zpair_bf3(P.nr, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.bf_rows), at<char>(R.ws, R.L.bf_pts),
+                     at<char>(R.ws, R.L.zt), P.nr, R.st));
     return ISDF_OK;
   }
   HIPCHK(zpair(P32, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm32), P.nmu, at<char>(R.ws, R.L.psi32),
@@ -663,7 +677,6 @@ isdf_status begin(isdf_handle h, const isdf_problem* prob, Problem& P, int nmu, 
   P.ng = ng;
   P.ngg = P.full_gram ? (int)P.nr : ng;
   P.nomega = nomega;
-  if (P.prec == PBF3) return fail(h, ISDF_E_UNSUPPORTED, "BF16x3 precision is not available in this build");
   return ISDF_OK;
 }
 

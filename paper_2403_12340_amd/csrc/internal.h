@@ -96,6 +96,20 @@ bool dft_supported(int n0, int n1, int kx, int ky, Prec compute);  // LDS fits
 
 hipError_t conj_transpose(int n, const void* a, void* at, hipStream_t st);   // at = a^H (z64)
 hipError_t convert_z(const void* src, bool src32, void* dst, bool dst32, long count, hipStream_t st);
+
+// ----- BF16x3 split precision (bf3.hip): operands split into bf16 hi / lo planes
+inline int bf3_pad(int n) { return (n + 15) / 16 * 16; }           // states per phase, whole k tiles
+inline long bf3_rpad(long nr) { return (nr + 127) / 128 * 128; }   // grid rows, whole row blocks
+inline int bf3_npad(int nmu) { return (nmu + 63) / 64 * 64; }       // points, whole point blocks
+size_t bf3_rows_bytes(long nr, int nv, int nc);
+size_t bf3_points_bytes(int nmu, int nv, int nc);
+// psi: complex128 [state][row], row stride ld; planes: bf3_rows_bytes
+hipError_t bf3_split_rows(const void* psi, long ld, long nr, int nv, int nc, void* planes, hipStream_t st);
+// pm: complex128 [state][point], row stride ld; planes: bf3_points_bytes
+hipError_t bf3_split_points(const void* pm, long ld, int nmu, int nv, int nc, void* planes, hipStream_t st);
+// out[mu][r] = conj(Pv) Qc (complex64, row stride ldo) from the split planes
+hipError_t zpair_bf3(long nr, int nmu, int nv, int nc, const void* rows, const void* points, void* out, long ldo,
+                     hipStream_t st);
 hipError_t axpby(const void* A, double a, const void* B, double b, void* C, long count, hipStream_t st);  // z64
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);  // kernel clear, bytes % 4 == 0
 hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStream_t st);  // z64
