@@ -354,8 +354,31 @@ __global__ __launch_bounds__(TL::NT) void core_kernel(int nmu, int nv, int nc, c
     }
   };
 
+  // Single precision: the MFMA accumulators hold at most FLUSH k tiles
+  // (FLUSH * BK terms) before they are added into FP64 registers, so the FP32
+  // accumulation error stays that of a short sum however long K = Nv Nc is.
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int FLUSH = 16;
   typename TL::acc_t acc[TL::FM][TL::FN];
+  double acc64[TL::FM][TL::FN][4];
   zero_acc<TL>(acc);
+#pragma unroll
+  for (int fm = 0; fm < TL::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < TL::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[fm][fn][v] = 0.0;
+  auto flush = [&]() {
+#pragma unroll
+    for (int fm = 0; fm < TL::FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < TL::FN; ++fn)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          acc64[fm][fn][v] += (double)acc[fm][fn][v];
+          acc[fm][fn][v] = (T)0;
+        }
+  };
   if (S > 0) {
     fetch(0);
     store(smem);
@@ -365,10 +388,12 @@ __global__ __launch_bounds__(TL::NT) void core_kernel(int nmu, int nv, int nc, c
       if (s + 1 < S) fetch(s + 1);
       cx<T>* sc = smem + cur * (TL::AS + TL::BS);
       tile_mma<T, TL>(sc, sc + TL::AS, acc, wm0, wn0, lane);
+      if (F32 && (s + 1) % FLUSH == 0) flush();
       if (s + 1 < S) store(smem + (cur ^ 1) * (TL::AS + TL::BS));
       __syncthreads();
     }
   }
+  if (F32) flush();
 
   T* out = reinterpret_cast<T*>(part + (long)split * nmu * nmu);
   const int rc = lane & 15, pp = rc & 1;
@@ -381,7 +406,8 @@ __global__ __launch_bounds__(TL::NT) void core_kernel(int nmu, int nv, int nc, c
         const int row = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, v);
         const int col = n0 + wn0 + fn * 8 + (rc >> 1);
         if (row >= nmu || col >= nmu) continue;
-        const T val = (row == col && pp == 1) ? (T)0 : acc[fm][fn][v];  // Hermitian: real diagonal
+        const double a = F32 ? acc64[fm][fn][v] : (double)acc[fm][fn][v];
+        const T val = (row == col && pp == 1) ? (T)0 : (T)a;  // Hermitian: real diagonal
         if (bm == bn && row < col) continue;
         out[((long)row * nmu + col) * 2 + pp] = val;
         if (row > col) out[((long)col * nmu + row) * 2 + pp] = pp ? -val : val;
