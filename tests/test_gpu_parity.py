@@ -318,6 +318,54 @@ def test_full_size_48cubed(prec):
     assert np.array_equal(got, got.conj().T)
 
 
+_big = {}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_full_size_64cubed(prec):
+    """The 64^3 solid-like workload (256 / 1024 states, 2048 points, 8192 plane
+    waves) at full size in the plan launch configuration.  The oracle's dense
+    route does not finish in seconds here, so the checks are:
+      - 64 sampled core entries M(mu, nu) against the oracle's sum over all
+        Nv Nc pairs (the contraction whose length grows fastest with size);
+      - eps~^{-1} eps~ = I, eps~ = I - U M U^H from this path's FP64 stage
+        outputs (the SMW step at full size);
+      - exact Hermiticity and the G = 0 row e0."""
+    inp = get_inputs("cfg2")
+    print(f"[full64] prec={prec}", flush=True)
+    if not _big:
+        psi = dev(inp.psi_t)
+        p64 = isdf.problem_for(inp, "fp64")
+        _big["psi"] = psi
+        _big["u"] = isdf.coulomb_u(psi, inp.mu_idx, inp.miller, p64)
+        _big["m"] = isdf.core_m(psi, inp.energies, inp.mu_idx, p64)
+        rng = np.random.default_rng(64)
+        pairs = rng.integers(0, inp.nmu, size=(64, 2))
+        pairs[:8, 1] = pairs[:8, 0]
+        _big["pairs"] = pairs
+        _big["m_ref"] = oracle.core_entries(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, pairs)
+    psi, pairs, m_ref = _big["psi"], _big["pairs"], _big["m_ref"]
+    prob = isdf.problem_for(inp, prec)
+    m = isdf.core_m(psi, inp.energies, inp.mu_idx, prob).cpu().numpy()[pairs[:, 0], pairs[:, 1]]
+    err_m = np.abs(m - m_ref).max() / np.abs(m_ref).max()
+    plan = isdf.Plan(prob, inp.mu_idx, inp.miller)
+    out = plan.new_output()
+    plan.eps_inv_async(psi, dev(inp.energies), out, plan.new_workspace())
+    plan.sync()
+    got = out[0]
+    u, mm = _big["u"], _big["m"]
+    eps = -(u @ mm) @ u.conj().T
+    eps.diagonal().add_(1.0)
+    r = got @ eps
+    r.diagonal().sub_(1.0)
+    err_id = (r.norm() / np.sqrt(inp.ng)).item()
+    print(f"  core sampled max rel {err_m:.3e}  ||eps^-1 eps - I||_F / sqrt(NG) {err_id:.3e}", flush=True)
+    assert err_m <= TOL_STAGE[prec] * 1e-2, err_m
+    assert err_id <= TOL_EPS[prec], err_id
+    assert torch.equal(got, got.conj().T)
+    assert bool((got[0, 1:] == 0).all()) and got[0, 0].item() == 1.0
+
+
 def test_frequencies_full_tiles():
     """Frequency batch on the full-tile case (k-major output products per frequency)."""
     inp = synth.make_inputs("kmaj", n_omega=3)
