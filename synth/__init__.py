@@ -214,3 +214,14 @@ def make_inputs(name: str = "cfg0", *, nmu: int | None = None, n_omega: int = 0,
                   is_complex=bool(c["complex"]), L=box_length(nv), psi_t=psi_t,
                   energies=energies, mu_idx=mu, miller=miller, omegas=omegas,
                   seed=int(c["seed"]))
+
+
+def loss_weight(ng: int, seed: int = 4) -> np.ndarray:
+    """Seeded Hermitian weight W (NG x NG) of the scalar loss Re tr(W eps~^{-1}):
+    W = (X + X^H) / 2 with X ~ CN(0, 1) / sqrt(NG), values exactly representable
+    in complex64, returned as complex128."""
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal((ng, ng)) + 1j * rng.standard_normal((ng, ng))) / np.sqrt(2.0 * ng)
+    w = ((x + x.conj().T) / 2).astype(np.complex64)
+    w = (w + w.conj().T) / 2   # exact Hermitian after the rounding (halving is exact)
+    return w.astype(np.complex128)

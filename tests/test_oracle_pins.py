@@ -382,3 +382,47 @@ def test_full_grid_smw_equals_dense_inverse(name):
     a = oracle.eps_inv_smw_full(inp, stages=st)
     b = oracle.eps_inv_isdf_full(inp, stages=st, tol=0.0)
     assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-10
+
+
+# ---- oracle gradient of L = Re tr(W eps~^{-1}) (autograd through the dense definition) ----
+@pytest.mark.parametrize("name", ["tiny", "cfg0"])
+def test_torch_definition_matches_numpy_oracle(name):
+    """The torch transcription computes the same eps~^{-1} as the pinned NumPy route."""
+    import torch
+    from oracle import adjoint as oadj
+    inp = synth.make_inputs(name)
+    got = oadj.eps_inv_isdf_torch(torch.as_tensor(inp.psi_t.astype(np.complex128)),
+                                  torch.as_tensor(inp.energies), inp).numpy()
+    ref = oracle.eps_inv_isdf(inp)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.05])
+def test_oracle_gradient_matches_central_differences(omega):
+    """dL/d eps_n and dL/dRe psi + i dL/dIm psi (at interpolation points and at one
+    other grid point) against central differences, h = 1e-5: fixes the autograd
+    route and the gradient convention independently of each other."""
+    from oracle import adjoint as oadj
+    inp = synth.make_inputs("tiny")
+    w = synth.loss_weight(inp.ng)
+    lval, ge, gpsi = oadj.loss_and_grad(inp, w, omega=omega)
+    h = 1e-5
+    psi0 = inp.psi_t.astype(np.complex128)
+    for n in range(inp.nv + inp.nc):
+        e1, e2 = inp.energies.copy(), inp.energies.copy()
+        e1[n] += h
+        e2[n] -= h
+        fd = (oadj.loss_value(inp, psi0, e1, w, omega=omega) - oadj.loss_value(inp, psi0, e2, w, omega=omega)) / (2 * h)
+        assert abs(fd - ge[n]) <= 1e-6 * max(1.0, abs(fd)), (n, fd, ge[n])
+    other = int(np.setdiff1d(np.arange(inp.nr), inp.mu_idx)[3])
+    cases = [(0, inp.mu_idx[0]), (inp.nv, inp.mu_idx[5]), (inp.nv + inp.nc - 1, inp.mu_idx[-1]), (1, other)]
+    for n, k in cases:
+        for step, part in ((h, "re"), (1j * h, "im")):
+            p1, p2 = psi0.copy(), psi0.copy()
+            p1[n, k] += step
+            p2[n, k] -= step
+            fd = (oadj.loss_value(inp, p1, inp.energies, w, omega=omega)
+                  - oadj.loss_value(inp, p2, inp.energies, w, omega=omega)) / (2 * h)
+            g = gpsi[n, k].real if part == "re" else gpsi[n, k].imag
+            assert abs(fd - g) <= 1e-6 * max(1.0, abs(fd)), (n, k, part, fd, g)
+    assert np.isfinite(lval)
