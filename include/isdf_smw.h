@@ -286,6 +286,36 @@ isdf_status isdf_check_inputs(const isdf_problem* prob, const double* energies,
                               int32_t ng, const double* omega, int32_t n_omega, char* msg,
                               size_t msg_len);
 
+/* ---- Adjoint of one build (FP64) -------------------------------------------
+ * Gradients of the scalar loss L = Re tr(W eps~^{-1}) for a Hermitian weight W,
+ * eps~^{-1} the NG x NG result of isdf_eps_inv at one imaginary frequency omega
+ * (0 = static).  The derivative is taken of the whole chain: the ISDF fit
+ * (eq. MatrixExpressionISDF), the core M = f C Omega^{-1} C^H (eq. COmegaCstar),
+ * the Coulomb Gram through the DFT and the SMW update (eq. epsilon_with_SMW).
+ * The Nr x N_mu pair products are recomputed from psi, not stored: nothing of
+ * an earlier forward call is needed.
+ *   prob        prec must be ISDF_FP64 (else ISDF_E_UNSUPPORTED); coulomb_sum 0 or 1
+ *   psi, energies, mu_idx, n_mu, miller, ng   as for isdf_eps_inv
+ *   omega       host, one frequency >= 0 (Hartree)
+ *   w           device, ng x ng complex128 row-major, Hermitian (read only)
+ *   workspace   device, >= isdf_grad_workspace_bytes, 256-byte aligned
+ *   grad_energies  device out, N doubles: dL/d eps_n
+ *   grad_psi_mu    device out, N x n_mu complex128 row-major: [n][mu] =
+ *                  dL/dRe psi_n(r_mu) + i dL/dIm psi_n(r_mu), the total derivative
+ *                  with respect to the orbital value at each interpolation point
+ *                  (through C, S, M and the grid rows of the pair products)
+ *   loss        host out, optional: L
+ * Synchronises the handle's stream.  Errors: ISDF_E_ARG, ISDF_E_WORKSPACE,
+ * ISDF_E_UNSUPPORTED, ISDF_E_NOT_PD (S, -M or U^H U - M^{-1} not positive
+ * definite), ISDF_E_DEVICE; outputs unspecified on error. */
+isdf_status isdf_grad_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t ng,
+                                      size_t* bytes);
+isdf_status isdf_eps_inv_grad(isdf_handle h, const isdf_problem* prob, const void* psi,
+                              const double* energies, const int32_t* mu_idx, int32_t n_mu,
+                              const int32_t* miller, int32_t ng, double omega, const void* w,
+                              void* workspace, size_t ws_bytes, double* grad_energies,
+                              void* grad_psi_mu, double* loss);
+
 /* Last error message of this handle ("" if none).  Valid until the next call. */
 const char* isdf_last_error(isdf_handle h);
 

@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
             "isdf_core_m": [vp, pprob, vp, pdbl, pi32, i32, dbl, vp, sz, vp],
             "isdf_coulomb_u": [vp, pprob, vp, pi32, i32, pi32, i32, vp, sz, vp],
             "isdf_smw_apply": [vp, pprob, vp, vp, i32, i32, vp, sz, vp, prep],
+            "isdf_grad_workspace_bytes": [pprob, i32, i32, ctypes.POINTER(sz)],
+            "isdf_eps_inv_grad": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, dbl, vp, vp, sz, vp, vp, pdbl],
             "isdf_plan_create": [vp, pprob, pi32, i32, pi32, i32, i32, ctypes.POINTER(vp)],
             "isdf_plan_destroy": [vp],
             "isdf_plan_workspace_bytes": [vp, ctypes.POINTER(sz)],
@@ -334,6 +336,72 @@ def smw_apply(u, m, prob: Problem, workspace=None, timing=False) -> Result:
                               ctypes.byref(rep))
     h.check(st, "isdf_smw_apply")
     return Result(out, rep)
+
+
+def grad_workspace_bytes(prob: Problem, n_mu: int, ng: int) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().isdf_grad_workspace_bytes(ctypes.byref(prob), n_mu, ng, ctypes.byref(out))
+    if st != OK:
+        raise IsdfError(st, "isdf_grad_workspace_bytes rejected the problem")
+    return int(out.value)
+
+
+def eps_inv_grad(psi_t, energies, mu_idx, miller, prob: Problem, w, omega=0.0, workspace=None):
+    """isdf_eps_inv_grad: (L, dL/d energies (N,), dL/d psi at the points (N, N_mu) complex128)
+    for L = Re tr(W eps~^{-1}); W is a device (NG, NG) complex128 Hermitian tensor."""
+    import torch
+    _check_psi(psi_t, prob)
+    dev = psi_t.device
+    h = handle(dev.index or 0)
+    e, pe = _f64(energies)
+    mu, pmu = _i32(mu_idx)
+    mi, pmi = _i32(miller)
+    ng, nmu = len(mi), len(mu)
+    if w.dtype != torch.complex128 or tuple(w.shape) != (ng, ng) or w.device != dev:
+        raise ValueError("w must be a (NG, NG) complex128 tensor on the orbitals' device")
+    w = w.contiguous()
+    nbytes = grad_workspace_bytes(prob, nmu, ng)
+    wsbuf, wsptr = _workspace(nbytes, dev, workspace)
+    ge = torch.empty(prob.nv + prob.nc, dtype=torch.float64, device=dev)
+    gp = torch.empty((prob.nv + prob.nc, nmu), dtype=torch.complex128, device=dev)
+    loss = ctypes.c_double(0.0)
+    st = lib().isdf_eps_inv_grad(h.h, ctypes.byref(prob), ctypes.c_void_p(psi_t.data_ptr()), pe, pmu, nmu, pmi, ng,
+                                 float(omega), ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(wsptr), nbytes,
+                                 ctypes.c_void_p(ge.data_ptr()), ctypes.c_void_p(gp.data_ptr()), ctypes.byref(loss))
+    h.check(st, "isdf_eps_inv_grad")
+    return float(loss.value), ge, gp
+
+
+def _eps_inv_loss_function():
+    import torch
+
+    class EpsInvLoss(torch.autograd.Function):
+        """L = Re tr(W eps~^{-1}) as a function of the orbital energies and of the
+        orbital samples at the interpolation points (N, N_mu); the other grid
+        values of psi_t are held fixed.  Forward and backward are one call of the
+        hand-written adjoint (isdf_eps_inv_grad); gradients follow torch's
+        convention for real losses (dL/dRe + i dL/dIm)."""
+
+        @staticmethod
+        def forward(ctx, energies, psi_mu, psi_t, w, mu_idx, miller, prob, omega):
+            mu = torch.as_tensor(np.asarray(mu_idx, dtype=np.int64), device=psi_t.device)
+            psi = psi_t.detach().clone()
+            psi[:, mu] = psi_mu.detach().to(psi.dtype)
+            lval, ge, gp = eps_inv_grad(psi, energies.detach().cpu().numpy(), mu_idx, miller, prob, w, omega)
+            ctx.save_for_backward(ge.to(energies.device), gp if psi_mu.is_complex() else gp.real.contiguous())
+            return torch.tensor(lval, dtype=torch.float64, device=energies.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            ge, gp = ctx.saved_tensors
+            return g * ge, (g.to(gp.device) * gp), None, None, None, None, None, None
+
+    return EpsInvLoss
+
+
+def eps_inv_loss(energies, psi_mu, psi_t, w, mu_idx, miller, prob: Problem, omega=0.0):
+    """Differentiable L = Re tr(W eps~^{-1}) in (energies, psi_mu) through EpsInvLoss."""
+    return _eps_inv_loss_function().apply(energies, psi_mu, psi_t, w, mu_idx, miller, prob, omega)
 
 
 class Plan:

@@ -1421,3 +1421,239 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint of L = Re tr(W eps~^{-1}) (FP64).  Nothing of a forward call is kept:
+// the pair products, X = V^{1/2} F Z, S, M and their inverses are recomputed,
+// then the forward's steps are run backwards.  With K = (M^{-1} - U^H U)^{-1}
+// and Y = U K (so that eps~^{-1} = I + U K U^H and eps~^{-1} U = U K M^{-1}):
+//   T = W Y,  G_U = 2 (T + Y U^H T),  R = M^{-1} Y^H T M^{-1}    (dL/dU, dL/dM)
+//   U = X S^{-1}:  Gbar = G_U S^{-1},  G_S = -U^H Gbar,  G_Z = F^H V^{1/2} Gbar
+//   Z = conj(Pa) Pb:  G_Pa = conj(G_Z) Pb,  G_Pb = G_Z Pa
+//   S = conj(Ga) Pb-Gram:  G_Ga = conj(G_S) Gb,  G_Gb = G_S Ga
+//   M = f C diag(w) C^H:  per occupied i, U_i = R (conj(a_i) b) gives dL/da_i,
+//   dL/db and dL/dw_ij = f c_ij^H R c_ij, and dL/d eps through w_ij(eps).
+// Gradients follow dL/dRe + i dL/dIm; the orbital gradient is the total
+// derivative with respect to each sample psi_n(r_mu).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GradLayout {
+  size_t pa = 0, pb = 0, t1b = 0, u = 0, y = 0, t = 0, gu = 0, gbar = 0;
+  size_t ga = 0, gb = 0, s = 0, sinv = 0, m = 0, minv = 0, km = 0, p = 0, yht = 0, r = 0, tmp = 0, gs = 0;
+  size_t ha = 0, hb = 0, qa = 0, q = 0, csr = 0, loss = 0, total = 0;
+  int nb = 1;   // occupied states per core-backward batch (its operands reuse the pa / pb regions)
+};
+
+GradLayout grad_layout(const Problem& P, const Layout& L, int kx, int nd) {
+  GradLayout G;
+  size_t off = L.total;
+  auto take = [&](size_t bytes) { size_t o = off; off += up(std::max<size_t>(bytes, 1)); return o; };
+  const size_t z = 16, n2 = (size_t)P.nmu * P.nmu * z, tall = (size_t)P.nmu * P.nr * z,
+               list = (size_t)P.ngg * P.nmu * z;
+  G.pa = take(tall);
+  G.pb = take(tall);
+  G.t1b = take((size_t)P.nmu * P.n2 * P.n1 * kx * z);
+  G.u = take(list); G.y = take(list); G.t = take(list); G.gu = take(list); G.gbar = take(list);
+  for (size_t* f : {&G.ga, &G.gb, &G.s, &G.sinv, &G.m, &G.minv, &G.km, &G.p, &G.yht, &G.r, &G.tmp, &G.gs,
+                    &G.ha, &G.hb, &G.qa})
+    *f = take(n2);
+  G.q = take((size_t)P.nv * P.nc * z);
+  G.csr = take((size_t)(nd + 1 + P.ngg + kx + 1 + nd) * 4);
+  G.loss = take(8);
+  G.total = off;
+  G.nb = (int)std::max<long>(1, std::min<long>(std::min<long>(P.nv, 64), P.nr / P.nc));
+  return G;
+}
+
+// plane waves grouped by (x, y) pair, then pairs grouped by x frequency (stable order)
+std::vector<int32_t> grad_csr(const DftIndex& ix, int ngg) {
+  const int nd = (int)ix.d_ax.size(), kx = (int)ix.xl.size();
+  std::vector<int32_t> out((size_t)nd + 1 + ngg + kx + 1 + nd, 0);
+  int32_t* gd_off = out.data();
+  int32_t* gd_list = gd_off + nd + 1;
+  int32_t* da_off = gd_list + ngg;
+  int32_t* da_list = da_off + kx + 1;
+  for (int g = 0; g < ngg; ++g) ++gd_off[ix.g_d[g] + 1];
+  for (int d = 0; d < nd; ++d) gd_off[d + 1] += gd_off[d];
+  std::vector<int32_t> fill(gd_off, gd_off + nd);
+  for (int g = 0; g < ngg; ++g) gd_list[fill[ix.g_d[g]]++] = g;
+  for (int d = 0; d < nd; ++d) ++da_off[ix.d_ax[d] + 1];
+  for (int a = 0; a < kx; ++a) da_off[a + 1] += da_off[a];
+  std::vector<int32_t> fa(da_off, da_off + kx);
+  for (int d = 0; d < nd; ++d) da_list[fa[ix.d_ax[d]]++] = d;
+  return out;
+}
+
+GemmDesc gd(int M, int N, int K, const void* A, long sam, long sak, bool ca, const void* B, long sbk, long sbn,
+            bool cb, void* C, long ldc, double alpha = 1.0, double beta = 0.0) {
+  GemmDesc d;
+  d.M = M; d.N = N; d.K = K;
+  d.A = A; d.sam = sam; d.sak = sak; d.conjA = ca;
+  d.B = B; d.sbk = sbk; d.sbn = sbn; d.conjB = cb;
+  d.C = C; d.ldc = ldc; d.alpha = alpha; d.beta = beta;
+  return d;
+}
+
+isdf_status enqueue_grad(Run& R, const GradLayout& G, const void* psi, double omega, const void* w, double* ge,
+                         void* gpsi) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  hipStream_t st = R.st;
+  auto B = [&](size_t off) { return at<char>(R.ws, off); };
+  const int nmu = P.nmu, nv = P.nv, nc = P.nc, ngg = P.ngg, ng = P.ng;
+  const long nr = P.nr, n2 = (long)nmu * nmu;
+  TRY(prepare_psi(R, psi));
+  TRY(stage_points(R));
+  char* pm = B(L.pm);
+  const char* ps = reinterpret_cast<const char*>(R.psi);
+  char* ga_out = reinterpret_cast<char*>(gpsi);
+  char* gb_out = ga_out + (size_t)nv * nmu * 16;
+  void* lin = B(L.lin);
+  int* status = &R.sb->status;
+  // split-K scratch: the Z^T region once the DFT has read it
+  auto split = [&](GemmDesc d, int cap = 16) {
+    d.split_ws = B(L.zt); d.split_ws_bytes = L.zt_bytes; d.max_split = cap;
+    return d;
+  };
+  // forward, recomputed: Pa^T, Pb^T, Z^T = conj(Pa^T) Pb^T, X^T = (V^{1/2} F Z)^T
+  HIPCHK(gemm(P64, gd(nmu, (int)nr, nv, pm, 1, nmu, true, ps, nr, 1, false, B(G.pa), nr), st));
+  HIPCHK(gemm(P64, gd(nmu, (int)nr, nc, pm + (size_t)nv * nmu * 16, 1, nmu, true, ps + (size_t)nv * nr * 16, nr, 1,
+                      false, B(G.pb), nr), st));
+  HIPCHK(adj_conj_mul(B(G.pa), B(G.pb), B(L.zt), (long)nmu * nr, st));
+  TRY(stage_dft(R, true));
+  // S = conj(Ga) Gb, S^{-1}; M (with its pair weights) and M^{-1}
+  HIPCHK(gemm(P64, gd(nmu, nmu, nv, pm, 1, nmu, false, pm, nmu, 1, true, B(G.ga), nmu), st));
+  HIPCHK(gemm(P64, gd(nmu, nmu, nc, pm + (size_t)nv * nmu * 16, 1, nmu, false, pm + (size_t)nv * nmu * 16, nmu, 1,
+                      true, B(G.gb), nmu), st));
+  HIPCHK(adj_conj_mul(B(G.ga), B(G.gb), B(G.s), n2, st));
+  HIPCHK(scale_z(B(G.s), B(G.sinv), n2, 1.0, st));
+  HIPCHK(sweep_inverse(nmu, B(G.sinv), lin, status, st));   // -S^{-1}
+  HIPCHK(scale_z(B(G.sinv), B(G.sinv), n2, -1.0, st));
+  TRY(stage_core(R, omega, B(G.m), B(G.minv), st));          // M, -M
+  HIPCHK(sweep_inverse(nmu, B(G.minv), lin, status, st));   // -(-M)^{-1} = M^{-1}
+  // U = X S^{-1};  K = -(U^H U - M^{-1})^{-1}
+  HIPCHK(gemm(P64, gd(ngg, nmu, nmu, B(L.zg), 1, ngg, false, B(G.sinv), nmu, 1, false, B(G.u), nmu), st));
+  {
+    GemmDesc d = split(gd(nmu, nmu, ngg, B(G.u), 1, nmu, true, B(G.u), nmu, 1, false, B(G.km), nmu));
+    d.herm = true;
+    HIPCHK(gemm(P64, d, st));
+  }
+  HIPCHK(axpby(B(G.km), 1.0, B(G.minv), -1.0, B(G.km), n2, st));
+  HIPCHK(sweep_inverse(nmu, B(G.km), lin, status, st));      // K
+  // Y = U K;  T = W Y (rows of the output list; zero below);  P = U^H T;  G_U = 2 (T + Y P)
+  HIPCHK(gemm(P64, gd(ngg, nmu, nmu, B(G.u), nmu, 1, false, B(G.km), nmu, 1, false, B(G.y), nmu), st));
+  if (ngg > ng) HIPCHK(zero_fill(B(G.t) + (size_t)ng * nmu * 16, (size_t)(ngg - ng) * nmu * 16, st));
+  HIPCHK(gemm(P64, gd(ng, nmu, ng, w, ng, 1, false, B(G.y), nmu, 1, false, B(G.t), nmu), st));
+  HIPCHK(gemm(P64, split(gd(nmu, nmu, ng, B(G.u), 1, nmu, true, B(G.t), nmu, 1, false, B(G.p), nmu)), st));
+  HIPCHK(adj_loss(w, ng, ng, B(G.p), nmu, at<double>(R.ws, G.loss), st));
+  HIPCHK(gemm(P64, gd(ngg, nmu, nmu, B(G.y), nmu, 1, false, B(G.p), nmu, 1, false, B(G.gu), nmu), st));
+  HIPCHK(axpby(B(G.t), 2.0, B(G.gu), 2.0, B(G.gu), (long)ngg * nmu, st));
+  // R = M^{-1} (Y^H T) M^{-1}
+  HIPCHK(gemm(P64, split(gd(nmu, nmu, ng, B(G.y), 1, nmu, true, B(G.t), nmu, 1, false, B(G.yht), nmu)), st));
+  HIPCHK(gemm(P64, gd(nmu, nmu, nmu, B(G.minv), nmu, 1, false, B(G.yht), nmu, 1, false, B(G.tmp), nmu), st));
+  HIPCHK(gemm(P64, gd(nmu, nmu, nmu, B(G.tmp), nmu, 1, false, B(G.minv), nmu, 1, false, B(G.r), nmu), st));
+  // Gbar = G_U S^{-1};  G_S = -U^H Gbar
+  HIPCHK(gemm(P64, gd(ngg, nmu, nmu, B(G.gu), nmu, 1, false, B(G.sinv), nmu, 1, false, B(G.gbar), nmu), st));
+  HIPCHK(gemm(P64, split(gd(nmu, nmu, ngg, B(G.u), 1, nmu, true, B(G.gbar), nmu, 1, false, B(G.gs), nmu, -1.0)), st));
+  // G_Z^T = (F^H V^{1/2} Gbar)^T into the Z^T region
+  {
+    const int* ib = R.idx;
+    const int32_t* c = reinterpret_cast<const int32_t*>(B(G.csr));
+    AdjDft a;
+    a.n0 = P.n0; a.n1 = P.n1; a.n2 = P.n2; a.nmu = nmu; a.kx = L.kx; a.nd = L.nd;
+    a.twx = B(L.twx); a.twy = B(L.twy); a.twz = B(L.twz);
+    a.sqrtv = at<double>(R.ws, L.sqrtv);
+    a.gd_off = c; a.gd_list = c + L.nd + 1; a.da_off = a.gd_list + ngg; a.da_list = a.da_off + L.kx + 1;
+    // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ngg] g_cz[ngg] dmap
+    a.d_by = ib + L.kx + L.ky + L.kz + L.nd;
+    a.g_cz = ib + L.kx + L.ky + L.kz + 2 * L.nd + ngg;
+    HIPCHK(adj_dft(a, B(G.gbar), B(L.t2), B(G.t1b), B(L.zt), st));
+  }
+  // G_Pa^T, G_Pb^T in place of Pa^T, Pb^T
+  HIPCHK(adj_pair_grad(B(L.zt), B(G.pa), B(G.pb), (long)nmu * nr, st));
+  // orbital gradients at the points: through the point side of the pair products (sum over the grid) ...
+  HIPCHK(gemm(P64, split(gd(nv, nmu, (int)nr, ps, nr, 1, false, B(G.pa), 1, nr, true, ga_out, nmu), 64), st));
+  HIPCHK(gemm(P64, split(gd(nc, nmu, (int)nr, ps + (size_t)nv * nr * 16, nr, 1, false, B(G.pb), 1, nr, true, gb_out,
+                            nmu), 64), st));
+  // ... the grid rows that are themselves points ...
+  HIPCHK(adj_gather_cols(B(G.pa), nr, R.mu, nmu, nmu, B(G.qa), st));
+  HIPCHK(gemm(P64, gd(nv, nmu, nmu, pm, nmu, 1, false, B(G.qa), nmu, 1, false, ga_out, nmu, 1.0, 1.0), st));
+  HIPCHK(adj_gather_cols(B(G.pb), nr, R.mu, nmu, nmu, B(G.qa), st));
+  HIPCHK(gemm(P64, gd(nc, nmu, nmu, pm + (size_t)nv * nmu * 16, nmu, 1, false, B(G.qa), nmu, 1, false, gb_out, nmu,
+                      1.0, 1.0), st));
+  // ... S = conj(Ga) Gb ...
+  HIPCHK(adj_pair_grad(B(G.gs), B(G.ga), B(G.gb), n2, st));
+  HIPCHK(adj_herm_plus(B(G.ga), B(G.ha), nmu, st));
+  HIPCHK(adj_herm_plus(B(G.gb), B(G.hb), nmu, st));
+  HIPCHK(gemm(P64, gd(nv, nmu, nmu, pm, nmu, 1, false, B(G.ha), 1, nmu, false, ga_out, nmu, 1.0, 1.0), st));
+  HIPCHK(gemm(P64, gd(nc, nmu, nmu, pm + (size_t)nv * nmu * 16, nmu, 1, false, B(G.hb), 1, nmu, false, gb_out, nmu,
+                      1.0, 1.0), st));
+  // ... and the core, a batch of occupied states at a time (pair operands in pa, products in pb)
+  for (int i0 = 0; i0 < nv; i0 += G.nb) {
+    const int nb = std::min(G.nb, nv - i0);
+    HIPCHK(adj_core_pairs(pm, nmu, nv, nc, i0, nb, B(G.pa), st));
+    GemmDesc d = gd(nmu, nc, nmu, B(G.r), nmu, 1, false, B(G.pa), nc, 1, false, B(G.pb), nc);
+    d.batch = nb; d.bsa = 0; d.bsb = (long)nmu * nc; d.bsc = (long)nmu * nc;
+    HIPCHK(gemm(P64, d, st));
+    HIPCHK(adj_core_grads(B(G.pb), pm, at<double>(R.ws, L.w), nmu, nv, nc, i0, nb, P.f, ga_out, B(G.q), gb_out, st));
+  }
+  HIPCHK(adj_energy_grad(B(G.q), R.e, nv, nc, omega, ge, st));
+  return ISDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+isdf_status isdf_grad_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t ng, size_t* bytes) {
+  if (!bytes) return ISDF_E_ARG;
+  Problem P;
+  isdf_status s = check_problem(nullptr, prob, P);
+  if (s != ISDF_OK) return s;
+  if (P.prec != P64) return ISDF_E_UNSUPPORTED;
+  if (n_mu < 1 || ng < 1) return ISDF_E_ARG;
+  P.nmu = n_mu;
+  P.ng = ng;
+  P.ngg = P.full_gram ? (int)P.nr : ng;
+  P.nomega = 0;
+  const int kx = std::min(P.ngg, P.n0), ky = std::min(P.ngg, P.n1), kz = std::min(P.ngg, P.n2);
+  const int nd = (int)std::min<long>(P.ngg, (long)P.n0 * P.n1);
+  *bytes = grad_layout(P, make_layout(P, kx, ky, kz, nd), kx, nd).total;
+  return ISDF_OK;
+}
+
+isdf_status isdf_eps_inv_grad(isdf_handle h, const isdf_problem* prob, const void* psi, const double* energies,
+                              const int32_t* mu_idx, int32_t n_mu, const int32_t* miller, int32_t ng, double omega,
+                              const void* w, void* workspace, size_t ws_bytes, double* grad_energies,
+                              void* grad_psi_mu, double* loss) {
+  if (!h) return ISDF_E_ARG;
+  if (!w || !grad_energies || !grad_psi_mu) return fail(h, ISDF_E_ARG, "w, grad_energies and grad_psi_mu must be non-NULL");
+  if (!energies) return fail(h, ISDF_E_ARG, "energies is NULL");
+  if (!miller) return fail(h, ISDF_E_ARG, "miller is NULL");
+  if (!(omega >= 0.0) || !std::isfinite(omega)) return fail(h, ISDF_E_ARG, "omega must be finite and >= 0");
+  Run R;
+  Uploader upl;
+  DftIndex ix;
+  std::vector<int> idxbuf;
+  TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, energies, 0, workspace, ws_bytes, upl, ix, idxbuf));
+  if (R.P.prec != P64) return fail(h, ISDF_E_UNSUPPORTED, "the adjoint runs in FP64 (prec = ISDF_FP64)");
+  const GradLayout G = grad_layout(R.P, R.L, R.L.kx, R.L.nd);
+  TRY(check_ws(h, workspace, ws_bytes, G.total));
+  std::vector<int32_t> csr = grad_csr(ix, R.P.ngg);
+  const size_t csr_bytes = csr.size() * 4;
+  upl.add(G.csr, upl.hold(std::move(csr)), csr_bytes);
+  HIPCHK(hipSetDevice(h->device));
+  TRY(upl.run());
+  TRY(clear_status(R));
+  TRY(enqueue_grad(R, G, psi, omega, w, grad_energies, grad_psi_mu));
+  double lval = 0.0;
+  HIPCHK(hipMemcpyAsync(&lval, at<double>(workspace, G.loss), 8, hipMemcpyDeviceToHost, R.st));
+  Timer none{h, false};
+  TRY(finish(R, nullptr, none));
+  if (loss) *loss = lval;
+  return ISDF_OK;
+}
+
+}  // extern "C"

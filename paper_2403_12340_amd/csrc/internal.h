@@ -111,6 +111,28 @@ hipError_t bf3_split_points(const void* pm, long ld, int nmu, int nv, int nc, vo
 hipError_t zpair_bf3(long nr, int nmu, int nv, int nc, const void* rows, const void* points, void* out, long ldo,
                      hipStream_t st);
 hipError_t axpby(const void* A, double a, const void* B, double b, void* C, long count, hipStream_t st);  // z64
+
+// ----- adjoint of L = Re tr(W eps~^{-1}) (adjoint.hip), complex128 throughout
+hipError_t adj_conj_mul(const void* x, const void* y, void* out, long n, hipStream_t st);   // out = conj(x) y
+hipError_t adj_pair_grad(const void* g, void* p, void* q, long n, hipStream_t st);        // p <- conj(g) q, q <- g p
+hipError_t adj_herm_plus(const void* g, void* h, int n, hipStream_t st);                   // h = g + g^H
+hipError_t adj_gather_cols(const void* src, long ld, const int* idx, int nv, int rows, void* out, hipStream_t st);
+// adjoint of the pruned DFT: gz[mu][r] = sum_g conj(F(g, r)) sqrtv[g] gbar[g][mu]
+struct AdjDft {
+  int n0 = 0, n1 = 0, n2 = 0, nmu = 0, kx = 0, nd = 0;
+  const void* twx = nullptr; const void* twy = nullptr; const void* twz = nullptr;   // forward tables
+  const double* sqrtv = nullptr;
+  const int* gd_off = nullptr; const int* gd_list = nullptr;   // plane waves grouped by (x, y) pair
+  const int* g_cz = nullptr;                                   // plane wave -> z-frequency index
+  const int* da_off = nullptr; const int* da_list = nullptr;   // pairs grouped by x frequency
+  const int* d_by = nullptr;                                   // pair -> y-frequency index
+};
+hipError_t adj_dft(const AdjDft& a, const void* gbar, void* t2b, void* t1b, void* gz, hipStream_t st);
+hipError_t adj_core_pairs(const void* pm, int nmu, int nv, int nc, int i0, int nb, void* cb, hipStream_t st);
+hipError_t adj_core_grads(const void* ub, const void* pm, const double* w, int nmu, int nv, int nc, int i0, int nb,
+                          double f, void* ga, void* q, void* gb, hipStream_t st);
+hipError_t adj_energy_grad(const void* q, const double* e, int nv, int nc, double omega, double* ge, hipStream_t st);
+hipError_t adj_loss(const void* w, int ng, long ldw, const void* p, int n, double* out, hipStream_t st);
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);  // kernel clear, bytes % 4 == 0
 hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStream_t st);  // z64
 // out[0] += ||a||_F^2 over count complex128, deterministic (single pass of block partials)
