@@ -235,6 +235,25 @@ def batch_systems(isdf, torch, dev, n_omega, first):
             "frequency_builds_per_s": round(nb / min(dt_graph, dt_conc), 1)}
 
 
+def adjoint_timing(isdf, torch, dev, inp, psi, reps, fwd_ms):
+    """Wall time of the FP64 adjoint of Re tr(W eps~^-1) (one isdf_eps_inv_grad call:
+    recomputed forward, backward, gradients; it ends with a stream sync)."""
+    import synth
+    prob = isdf.problem_for(inp, prec="fp64")
+    w = torch.from_numpy(synth.loss_weight(inp.ng)).to(dev)
+    nbytes = isdf.grad_workspace_bytes(prob, inp.nmu, inp.ng)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    isdf.eps_inv_grad(psi, inp.energies, inp.mu_idx, inp.miller, prob, w, 0.0, workspace=ws)
+    t = time.perf_counter()
+    for _ in range(reps):
+        isdf.eps_inv_grad(psi, inp.energies, inp.mu_idx, inp.miller, prob, w, 0.0, workspace=ws)
+    dt = (time.perf_counter() - t) / reps
+    print(f"[bench] adjoint {inp.n}^3: {dt * 1e3:.1f} ms per call", file=sys.stderr, flush=True)
+    del ws, w
+    return {"ms_per_call": round(dt * 1e3, 2), "ratio_to_fp64_forward": round(dt * 1e3 / fwd_ms, 2),
+            "loss": "Re tr(W eps~^-1), W seeded Hermitian", "gradients": "dL/d eps_n, dL/d psi_n(r_mu)"}
+
+
 def solid_like(isdf, torch, dev, steps):
     """The 64^3 solid-like system (Nv = 256, Nc = 1024, N_mu = 2048, NG = 8192),
     static, timed per precision path with plan calls as for the headline; the
@@ -266,6 +285,8 @@ def solid_like(isdf, torch, dev, steps):
     ref = outs["fp64"]
     for prec in ("bf16x3", "fp32"):
         res[prec]["rel_fro_vs_fp64_path"] = float(((outs[prec] - ref).norm() / ref.norm()).item())
+    del outs, ref
+    res["adjoint_fp64"] = adjoint_timing(isdf, torch, dev, inp, psi, 2, res["fp64"]["ms_per_build"])
     return {"workload": f"static eps~^-1, {inp.n}^3 grid, Nv={inp.nv}, Nc={inp.nc}, N_mu={inp.nmu}, NG={inp.ng}, "
                         "complex orbitals", "steps": steps, **res}
 
@@ -371,6 +392,10 @@ def main():
     if not args.no_batch_systems and args.omegas > 1 and args.only is None:
         batch = batch_systems(isdf, torch, dev, args.omegas, args.config)
 
+    adj = None
+    if args.only is None:
+        adj = adjoint_timing(isdf, torch, dev, inp, psi, 3, results["fp64"]["ms_per_step"])
+
     solid = None
     if not args.no_solid and args.only is None:
         solid = solid_like(isdf, torch, dev, 3)
@@ -454,6 +479,7 @@ def main():
         "frequency_batch": freq,
         "systems_batch": batch,
         "solid_like_64cubed": solid,
+        "adjoint_fp64": adj,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
