@@ -426,3 +426,59 @@ def test_oracle_gradient_matches_central_differences(omega):
             g = gpsi[n, k].real if part == "re" else gpsi[n, k].imag
             assert abs(fd - g) <= 1e-6 * max(1.0, abs(fd)), (n, k, part, fd, g)
     assert np.isfinite(lval)
+
+
+# ---- Cauchy-integral core (Algorithm 2) ----------------------------------------------
+def test_contour_quadrature_of_one_pole_pair():
+    """Closed form: the contour rule gives 1/(a - b) for a below the top occupied
+    energy and b in the empty band, within the cited quadrature bound."""
+    from oracle import cauchy as oc
+    rng = np.random.default_rng(3)
+    for q, big_q in ((0.2, 1.0), (0.3, 25.0), (0.05, 40.0)):
+        n = oc.nodes_for_tolerance(q, big_q, 1e-12)
+        z, w = oc.contour_nodes(q, big_q, n)
+        for _ in range(5):
+            a = -rng.uniform(0.0, 3.0 * big_q)
+            b = rng.uniform(q, big_q)
+            s = -np.sum(w / ((z - a) * (z - b)))                   # counterclockwise upper half
+            val = -(s - np.conj(s)) / (2j * np.pi)
+            assert abs(val - 1.0 / (a - b)) * abs(a - b) <= 1e-11, (q, big_q, a, b, val)
+
+
+def test_contour_half_plane_and_ends():
+    """The mapped nodes lie in the upper half plane, and the ends of the segment map to
+    real points below the gap and above the band (the contour separates them)."""
+    from oracle import cauchy as oc
+    q, big_q = 0.3, 25.0
+    z, _ = oc.contour_nodes(q, big_q, 64)
+    assert np.all(z.imag > 0)
+    assert z[0].real < q and z[-1].real > big_q
+
+
+@pytest.mark.parametrize("name", ["tiny", "cfg0", "mid"])
+def test_cauchy_core_equals_direct_sum(name):
+    """Algorithm 2 with the node count from eq. rel_err_Cauchy at 1e-13 equals the
+    direct pair sum of eq. COmegaCstar; the adaptive rule reaches its tolerance."""
+    from oracle import cauchy as oc
+    inp = synth.make_inputs(name)
+    ref = oracle.core_matrix(inp.psi_t, inp.energies, inp.nv, inp.mu_idx)
+    _, q, big_q = oc.gap_and_width(inp.energies, inp.nv)
+    m = oc.core_cauchy(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, oc.nodes_for_tolerance(q, big_q, 1e-13))
+    assert np.linalg.norm(m - ref) / np.linalg.norm(ref) < 1e-11
+    assert np.array_equal(m, m.conj().T)
+    ma, _ = oc.core_cauchy_adaptive(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, 1e-10)
+    assert np.linalg.norm(ma - ref) / np.linalg.norm(ref) < 1e-9
+
+
+def test_cauchy_error_falls_with_nodes():
+    """Geometric convergence in the node count, below the cited bound."""
+    from oracle import cauchy as oc
+    inp = synth.make_inputs("mid")
+    ref = oracle.core_matrix(inp.psi_t, inp.energies, inp.nv, inp.mu_idx)
+    _, q, big_q = oc.gap_and_width(inp.energies, inp.nv)
+    errs = []
+    for n in (4, 6, 8, 10):
+        m = oc.core_cauchy(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, n)
+        errs.append(np.linalg.norm(m - ref) / np.linalg.norm(ref))
+        assert errs[-1] <= np.exp(-np.pi ** 2 * n / (2 * np.log(big_q / q) + 6))
+    assert all(b < a for a, b in zip(errs, errs[1:]))
