@@ -91,6 +91,16 @@ typedef struct {
                             Read by the calls that take a plane-wave list (isdf_eps_inv,
                             isdf_coulomb_u, isdf_plan_create); isdf_smw_apply sums over the
                             rows of the U it is given. */
+  int32_t core_method;   /* how the core M = f C Omega^{-1} C^H is formed:
+                            0: the direct pair sum over every (i, j) (eq. COmegaCstar, default);
+                            1: the contour integral of Algorithm 2 (static only: isdf_eps_inv
+                               with n_omega = 0, isdf_core_m with omega = 0; plans and the
+                               adjoint return ISDF_E_UNSUPPORTED).  Cost N_lambda (Nv + Nc)
+                               N_mu^2 instead of Nv Nc N_mu^2 / 2 */
+  double core_tol;       /* core_method 1: quadrature tolerance; the node count N_lambda is the
+                            smallest with exp(-pi^2 N / (2 log(Q/q) + 6)) <= core_tol
+                            (eq. rel_err_Cauchy; q gap, Q span of the empty band; at most 256).
+                            0 selects 1e-13; must be < 1e-2 */
 } isdf_problem;
 
 typedef struct {
@@ -285,6 +295,16 @@ isdf_status isdf_check_inputs(const isdf_problem* prob, const double* energies,
                               const int32_t* mu_idx, int32_t n_mu, const int32_t* miller,
                               int32_t ng, const double* omega, int32_t n_omega, char* msg,
                               size_t msg_len);
+
+/* Host only: the contour rule of core_method 1 for these energies (Algorithm 2).
+ * The nodes lie on the upper half of the elliptic-map contour around the empty
+ * band, q = eps[nv] - eps[nv-1], Q = eps[nv+nc-1] - eps[nv-1] (the energies must
+ * be sorted at the band edges: eps[nv-1] the largest occupied, eps[nv] the
+ * smallest empty).  out (host, 4 * 256 doubles) receives n lambdas then n
+ * quadrature weights, each as (re, im), ordered from the low-energy end; n_out the
+ * node count.  Errors: ISDF_E_ARG. */
+isdf_status isdf_contour_nodes(const double* energies, int32_t nv, int32_t nc, double tol, double* out,
+                               int32_t* n_out);
 
 /* ---- Adjoint of one build (FP64) -------------------------------------------
  * Gradients of the scalar loss L = Re tr(W eps~^{-1}) for a Hermitian weight W,

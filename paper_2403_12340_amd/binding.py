@@ -33,7 +33,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("cell", ctypes.c_double * 9), ("nv", ctypes.c_int32),
                 ("nc", ctypes.c_int32), ("is_complex", ctypes.c_int32), ("pair_factor", ctypes.c_double),
                 ("v_scale", ctypes.c_double), ("prec", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("coulomb_sum", ctypes.c_int32)]
+                ("coulomb_sum", ctypes.c_int32), ("core_method", ctypes.c_int32), ("core_tol", ctypes.c_double)]
 
 
 class Tune(ctypes.Structure):
@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
             "isdf_coulomb_u": [vp, pprob, vp, pi32, i32, pi32, i32, vp, sz, vp],
             "isdf_smw_apply": [vp, pprob, vp, vp, i32, i32, vp, sz, vp, prep],
             "isdf_grad_workspace_bytes": [pprob, i32, i32, ctypes.POINTER(sz)],
+            "isdf_contour_nodes": [pdbl, i32, i32, dbl, pdbl, ctypes.POINTER(i32)],
             "isdf_eps_inv_grad": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, dbl, vp, vp, sz, vp, vp, pdbl],
             "isdf_plan_create": [vp, pprob, pi32, i32, pi32, i32, i32, ctypes.POINTER(vp)],
             "isdf_plan_destroy": [vp],
@@ -109,7 +110,7 @@ def header_functions() -> list[str]:
 
 
 def make_problem(n, cell, nv, nc, *, is_complex=True, pair_factor=2.0, v_scale=None,
-                 prec="fp64", refine_steps=0, coulomb_sum=0) -> Problem:
+                 prec="fp64", refine_steps=0, coulomb_sum=0, core_method=0, core_tol=0.0) -> Problem:
     p = Problem()
     n = (n, n, n) if np.isscalar(n) else tuple(n)
     for d in range(3):
@@ -126,6 +127,8 @@ def make_problem(n, cell, nv, nc, *, is_complex=True, pair_factor=2.0, v_scale=N
     p.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
     p.refine_steps = int(refine_steps)
     p.coulomb_sum = int(coulomb_sum)
+    p.core_method = int(core_method)
+    p.core_tol = float(core_tol)
     return p
 
 
@@ -338,6 +341,21 @@ def smw_apply(u, m, prob: Problem, workspace=None, timing=False) -> Result:
     return Result(out, rep)
 
 
+def contour_nodes(energies, nv: int, nc: int, tol: float = 1e-13):
+    """isdf_contour_nodes: (lambda (n,), weights (n,)) of the core's contour rule (host only)."""
+    e, pe = _f64(energies)
+    out = np.zeros(4 * 256)
+    n = ctypes.c_int32(0)
+    st = lib().isdf_contour_nodes(pe, nv, nc, float(tol), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(n))
+    if st != OK:
+        raise IsdfError(st, "isdf_contour_nodes rejected the energies")
+    k = n.value
+    z = out[:2 * k].view(np.complex128)
+    w = out[2 * k:4 * k].view(np.complex128)
+    return z.copy(), w.copy()
+
+
 def grad_workspace_bytes(prob: Problem, n_mu: int, ng: int) -> int:
     out = ctypes.c_size_t(0)
     st = lib().isdf_grad_workspace_bytes(ctypes.byref(prob), n_mu, ng, ctypes.byref(out))
@@ -543,8 +561,9 @@ def eps_inv_multi(plans, psis, energies_devs, outs, workspaces, omegas=None):
     return outs
 
 
-def problem_for(inp, prec="fp64", refine_steps=0, v_scale=None, coulomb_sum=0) -> Problem:
+def problem_for(inp, prec="fp64", refine_steps=0, v_scale=None, coulomb_sum=0, core_method=0, core_tol=0.0) -> Problem:
     """Problem description for a synthetic input set (synth.Inputs)."""
     return make_problem(inp.n, inp.cell, inp.nv, inp.nc, is_complex=inp.is_complex,
                         v_scale=inp.v_scale if v_scale is None else v_scale, prec=prec,
-                        refine_steps=refine_steps, coulomb_sum=coulomb_sum)
+                        refine_steps=refine_steps, coulomb_sum=coulomb_sum, core_method=core_method,
+                        core_tol=core_tol)

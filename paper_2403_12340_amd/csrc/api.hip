@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <set>
@@ -62,10 +63,15 @@ struct StatusBlock {
   double partial[1024];
 };
 
+constexpr int CAUCHY_MAX_NODES = 256;  // contour node table size
+constexpr int CAUCHY_CHUNK = 8;        // nodes per batched Gram pair
+
 struct Problem {
   int n0, n1, n2, nv, nc, ns, nmu, ng, nomega;
   int ngg;         // plane waves the Coulomb Gram runs over: ng, or every grid vector (coulomb_sum = 1)
   bool full_gram;
+  int core_method;  // 0: direct pair sum; 1: contour integral (Algorithm 2)
+  double core_tol;  // quadrature tolerance of the contour integral
   long nr;
   bool cplx;
   Prec prec;
@@ -113,6 +119,80 @@ DftIndex dft_index(const int32_t* miller, int ng) {
   return ix;
 }
 
+// Jacobi elliptic functions sn, cn, dn of a real argument u and parameter m in
+// [0, 1), and the complete integral K(m), by the arithmetic-geometric mean
+// (descending Landen) method of Abramowitz and Stegun 16.4 / 17.6.
+struct Jacobi {
+  double sn, cn, dn;
+};
+double ellip_k(double m) {
+  double a = 1.0, b = std::sqrt(1.0 - m);
+  for (int i = 0; i < 64 && std::fabs(a - b) > 1e-16 * a; ++i) {
+    const double an = 0.5 * (a + b);
+    b = std::sqrt(a * b);
+    a = an;
+  }
+  return M_PI / (2.0 * a);
+}
+Jacobi jacobi_real(double u, double m) {
+  if (m <= 0.0) return {std::sin(u), std::cos(u), 1.0};
+  double a[40], c[40];
+  a[0] = 1.0;
+  c[0] = std::sqrt(m);
+  double b = std::sqrt(1.0 - m);
+  int n = 0;
+  while (n < 38 && std::fabs(c[n]) > 1e-17) {
+    a[n + 1] = 0.5 * (a[n] + b);
+    c[n + 1] = 0.5 * (a[n] - b);
+    b = std::sqrt(a[n] * b);
+    ++n;
+  }
+  double phi = std::ldexp(a[n] * u, n), prev = phi;
+  for (int k = n; k > 0; --k) {
+    prev = phi;
+    phi = 0.5 * (phi + std::asin(c[k] * std::sin(phi) / a[k]));
+  }
+  const double sn = std::sin(phi), cn = std::cos(phi);
+  return {sn, cn, n > 0 ? cn / std::cos(prev - phi) : 1.0};
+}
+// sn, cn, dn at x + i y (real x, y): addition theorem with the imaginary
+// transformation (Abramowitz and Stegun 16.21)
+void jacobi_complex(double x, double y, double m, std::complex<double>& sn, std::complex<double>& cn,
+                    std::complex<double>& dn) {
+  const Jacobi r = jacobi_real(x, m), i = jacobi_real(y, 1.0 - m);
+  const double den = i.cn * i.cn + m * r.sn * r.sn * i.sn * i.sn;
+  sn = std::complex<double>(r.sn * i.dn, r.cn * r.dn * i.sn * i.cn) / den;
+  cn = std::complex<double>(r.cn * i.cn, -r.sn * r.dn * i.sn * i.dn) / den;
+  dn = std::complex<double>(r.dn * i.cn * i.dn, -m * r.sn * r.cn * i.sn) / den;
+}
+
+// Contour of the core's Cauchy integral (Algorithm 2): with q the gap and Q the
+// span of the empty band above the top occupied energy e_v, the segment
+// [-K + iK'/2, K + iK'/2] of the parameter t (modulus r = (sqrt(Q/q) - 1) /
+// (sqrt(Q/q) + 1)) maps to the upper half of a closed curve around the empty
+// band by z = e_v + sqrt(qQ) (1/r + sn t) / (1/r - sn t), walked clockwise.  The
+// midpoint rule takes n nodes, n from the quadrature bound
+// exp(-pi^2 n / (2 log(Q/q) + 6)) <= tol (eq. rel_err_Cauchy).  Output: n
+// lambdas then n weights (dz/dt times the step), interleaved re / im.
+std::vector<double> cauchy_nodes(const double* e, int nv, int nc, double tol) {
+  const double ev = e[nv - 1], q = e[nv] - ev, big_q = e[nv + nc - 1] - ev;
+  const double ratio = std::max(big_q / q, 1.0 + 1e-12);
+  int n = (int)std::ceil((2.0 * std::log(ratio) + 6.0) * std::log(1.0 / tol) / (M_PI * M_PI));
+  n = std::max(4, std::min(n, CAUCHY_MAX_NODES));
+  const double r = (std::sqrt(ratio) - 1.0) / (std::sqrt(ratio) + 1.0), m = r * r;
+  const double kk = ellip_k(m), half = 0.5 * ellip_k(1.0 - m), sq = std::sqrt(q * big_q);
+  std::vector<double> out(4 * (size_t)n);
+  for (int k = 0; k < n; ++k) {
+    std::complex<double> sn, cn, dn;
+    jacobi_complex(-kk + 2.0 * kk * (k + 0.5) / n, half, m, sn, cn, dn);
+    const std::complex<double> z = ev + sq * (1.0 / r + sn) / (1.0 / r - sn);
+    const std::complex<double> w = 2.0 * sq / r * cn * dn / ((1.0 / r - sn) * (1.0 / r - sn)) * (2.0 * kk / n);
+    out[2 * k] = z.real(); out[2 * k + 1] = z.imag();
+    out[2 * (n + k)] = w.real(); out[2 * (n + k) + 1] = w.imag();
+  }
+  return out;
+}
+
 // The plane-wave list followed by every other grid vector (components in
 // [-n_d/2, n_d/2)): the rows of the whole-grid Coulomb Gram, output list first.
 std::vector<int32_t> full_grid_list(const int32_t* miller, int ng, int n0, int n1, int n2) {
@@ -148,6 +228,8 @@ struct Layout {
   size_t part = 0, l2 = 0, lin2 = 0, q = 0;  // core partials; second -M buffer, sweep scratch, S M^-1 S scratch
   size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (FP32 mode only)
   size_t bf_rows = 0, bf_pts = 0;    // bf16 hi / lo planes of the orbitals (BF16x3 mode only)
+  // contour-integral core: node table (lambda, weight), scaled operands, Gram pairs, running sum
+  size_t cnodes = 0, cops = 0, cprod = 0, csum = 0;
   int kx = 0, ky = 0, kz = 0, nd = 0, nsplit = 1;
 };
 
@@ -168,6 +250,12 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   } else if (P.prec == PBF3) {
     L.bf_rows = take(bf3_rows_bytes(P.nr, P.nv, P.nc));
     L.bf_pts = take(bf3_points_bytes(P.nmu, P.nv, P.nc));
+  }
+  if (P.core_method == 1) {
+    L.cnodes = take((size_t)2 * CAUCHY_MAX_NODES * z);
+    L.cops = take((size_t)CAUCHY_CHUNK * P.ns * P.nmu * z);
+    L.cprod = take((size_t)2 * CAUCHY_CHUNK * nmu2 * z);
+    L.csum = take(nmu2 * z);
   }
   // host-supplied arrays, adjacent so that one copy uploads them all
   L.mu = take((size_t)P.nmu * 4);
@@ -250,6 +338,8 @@ isdf_status check_problem(isdf_handle h, const isdf_problem* pr, Problem& P) {
   if (pr->prec != ISDF_FP64 && pr->prec != ISDF_FP32 && pr->prec != ISDF_BF16X3) return fail(h, ISDF_E_ARG, "unknown precision");
   if (pr->is_complex != 0 && pr->is_complex != 1) return fail(h, ISDF_E_ARG, "is_complex must be 0 or 1");
   if (pr->coulomb_sum != 0 && pr->coulomb_sum != 1) return fail(h, ISDF_E_ARG, "coulomb_sum must be 0 or 1");
+  if (pr->core_method != 0 && pr->core_method != 1) return fail(h, ISDF_E_ARG, "core_method must be 0 or 1");
+  if (!(pr->core_tol >= 0.0 && pr->core_tol < 1e-2)) return fail(h, ISDF_E_ARG, "core_tol must be in [0, 1e-2)");
   const double* c = pr->cell;
   const double det = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) + c[2] * (c[3] * c[7] - c[4] * c[6]);
   if (!(std::fabs(det) > 1e-12) || !std::isfinite(det)) return fail(h, ISDF_E_ARG, "cell is singular");
@@ -263,6 +353,8 @@ isdf_status check_problem(isdf_handle h, const isdf_problem* pr, Problem& P) {
   P.v_scale = pr->v_scale;
   P.refine = pr->refine_steps;
   P.full_gram = pr->coulomb_sum == 1;
+  P.core_method = pr->core_method;
+  P.core_tol = pr->core_tol > 0.0 ? pr->core_tol : 1e-13;
   // reciprocal basis rows b_i = 2 pi (cell^{-1})^T rows
   const double inv[9] = {(c[4] * c[8] - c[5] * c[7]) / det, -(c[1] * c[8] - c[2] * c[7]) / det, (c[1] * c[5] - c[2] * c[4]) / det,
                          -(c[3] * c[8] - c[5] * c[6]) / det, (c[0] * c[8] - c[2] * c[6]) / det, -(c[0] * c[5] - c[2] * c[3]) / det,
@@ -335,6 +427,8 @@ struct Uploader {
   std::deque<std::vector<int32_t>> keep;   // host arrays built for this call, alive until run()
   void add(size_t off, const void* s, size_t bytes) { if (bytes) items.push_back({off, s, bytes}); }
   const int32_t* hold(std::vector<int32_t>&& v) { keep.push_back(std::move(v)); return keep.back().data(); }
+  std::deque<std::vector<double>> keepd;
+  const double* hold(std::vector<double>&& v) { keepd.push_back(std::move(v)); return keepd.back().data(); }
   isdf_status run() {
     if (items.empty()) return ISDF_OK;
     size_t lo = items[0].off, hi = 0;
@@ -387,6 +481,7 @@ struct Run {
   const double* recip = nullptr;
   const int* idx = nullptr;       // pruned-DFT index lists
   const void* tmat = nullptr;  // T (times talpha) after the core algebra
+  int cn = 0;                  // contour nodes in the table (core_method 1)
   double talpha = 1.0;
   hipStream_t st;
 };
@@ -557,10 +652,52 @@ isdf_status stage_gram(Run& R, const Basis& b) {
 }
 
 // core M at one frequency: written to m_out (if given) and/or -M to negm
+// Core by the contour integral (Algorithm 2), static: chunks of nodes, each a
+// scaling pass, two batched Gram products and a fixed-order Hadamard accumulation.
+isdf_status stage_core_cauchy(Run& R, void* m_out, void* negm, hipStream_t st) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  const int n = P.nmu, nv = P.nv, ns = P.ns;
+  const long n2 = (long)n * n;
+  char* pm = at<char>(R.ws, L.pm);
+  char* ops = at<char>(R.ws, L.cops);
+  char* av = at<char>(R.ws, L.cprod);
+  char* ac = av + (size_t)CAUCHY_CHUNK * n2 * 16;
+  const char* lam = at<char>(R.ws, L.cnodes);
+  const char* wts = lam + (size_t)R.cn * 16;
+  HIPCHK(zero_fill(at<char>(R.ws, L.csum), (size_t)n2 * 16, st));
+  for (int k0 = 0; k0 < R.cn; k0 += CAUCHY_CHUNK) {
+    const int kc = std::min(CAUCHY_CHUNK, R.cn - k0);
+    HIPCHK(cauchy_scale(pm, R.e, lam, n, nv, ns, k0, kc, ops, st));
+    GemmDesc a;   // Av_k(mu, nu) = sum_i conj(psi_i(mu)) ops_k[i][nu]
+    a.M = a.N = n; a.K = nv;
+    a.A = pm; a.sam = 1; a.sak = n; a.conjA = true;
+    a.B = ops; a.sbk = n; a.sbn = 1;
+    a.C = av; a.ldc = n;
+    a.batch = kc; a.bsa = 0; a.bsb = (long)ns * n; a.bsc = n2;
+    HIPCHK(gemm(cp, a, st));
+    GemmDesc c = a;   // Ac_k(mu, nu) = sum_j psi_j(mu) ops_k[j][nu] (ops holds conj(psi_j) / (lambda - eps_j))
+    c.K = P.nc;
+    c.A = pm + (size_t)nv * n * 16; c.conjA = false;
+    c.B = ops + (size_t)nv * n * 16;
+    c.C = ac;
+    HIPCHK(gemm(cp, c, st));
+    HIPCHK(cauchy_accum(av, ac, wts, k0, kc, n, at<char>(R.ws, L.csum), st));
+  }
+  HIPCHK(cauchy_finish(at<char>(R.ws, L.csum), n, P.f, m_out, negm, st));
+  return ISDF_OK;
+}
+
 isdf_status stage_core(Run& R, double omega, void* m_out, void* negm, hipStream_t st) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Prec cp = P.prec == P64 ? P64 : P32;
+  if (P.core_method == 1) {
+    if (omega != 0.0) return fail(h, ISDF_E_UNSUPPORTED, "the contour-integral core is static (omega = 0)");
+    return stage_core_cauchy(R, m_out, negm, st);
+  }
   double* w = at<double>(R.ws, R.L.w);
   HIPCHK(pair_weights(R.e, P.nv, P.nc, omega, w, st));
   void* part = at<char>(R.ws, R.L.part);
@@ -760,6 +897,12 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
   up_.ws = ws;
   up_.add(R.L.mu, mu_idx, (size_t)n_mu * 4);
   if (energies) up_.add(R.L.e, energies, (size_t)R.P.ns * 8);
+  if (energies && R.P.core_method == 1) {
+    std::vector<double> nodes = cauchy_nodes(energies, R.P.nv, R.P.nc, R.P.core_tol);
+    R.cn = (int)(nodes.size() / 4);
+    const size_t bytes = nodes.size() * 8;
+    up_.add(R.L.cnodes, up_.hold(std::move(nodes)), bytes);
+  }
   if (miller) {
     up_.add(R.L.miller, miller, (size_t)R.P.ngg * 12);
     idxbuf.clear();
@@ -1068,6 +1211,8 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
   DftIndex ix;
   std::vector<int> idxbuf;
   TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, energies, n_omega, workspace, ws_bytes, upl, ix, idxbuf));
+  if (R.P.core_method == 1 && n_omega > 0)
+    return fail(h, ISDF_E_UNSUPPORTED, "the contour-integral core is static (n_omega = 0)");
   HIPCHK(hipSetDevice(h->device));
   TRY(upl.run());
   TRY(clear_status(R));
@@ -1203,6 +1348,8 @@ isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int3
   if (n_omega < 0) return fail(h, ISDF_E_ARG, "n_omega must be >= 0");
   Problem P;
   TRY(begin(h, prob, P, n_mu, ng, n_omega));
+  if (P.core_method == 1)
+    return fail(h, ISDF_E_UNSUPPORTED, "plans take device energies; the contour-integral core needs them on the host");
   TRY(check_points(h, P, mu_idx, n_mu));
   TRY(check_miller(h, P, miller, ng));
   std::vector<int32_t> full;
@@ -1607,6 +1754,23 @@ isdf_status enqueue_grad(Run& R, const GradLayout& G, const void* psi, double om
 
 extern "C" {
 
+isdf_status isdf_contour_nodes(const double* energies, int32_t nv, int32_t nc, double tol, double* out,
+                               int32_t* n_out) {
+  if (!energies || !out || !n_out || nv < 1 || nc < 1) return ISDF_E_ARG;
+  if (!(tol > 0.0 && tol < 1e-2)) return ISDF_E_ARG;
+  double vmax = -INFINITY, cmin = INFINITY;
+  for (int i = 0; i < nv + nc; ++i) {
+    if (!std::isfinite(energies[i])) return ISDF_E_ARG;
+    if (i < nv) vmax = std::max(vmax, energies[i]);
+    else cmin = std::min(cmin, energies[i]);
+  }
+  if (!(vmax < cmin) || energies[nv - 1] != vmax || energies[nv] != cmin) return ISDF_E_ARG;
+  const std::vector<double> t = cauchy_nodes(energies, nv, nc, tol);
+  std::copy(t.begin(), t.end(), out);
+  *n_out = (int32_t)(t.size() / 4);
+  return ISDF_OK;
+}
+
 isdf_status isdf_grad_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t ng, size_t* bytes) {
   if (!bytes) return ISDF_E_ARG;
   Problem P;
@@ -1639,6 +1803,7 @@ isdf_status isdf_eps_inv_grad(isdf_handle h, const isdf_problem* prob, const voi
   std::vector<int> idxbuf;
   TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, energies, 0, workspace, ws_bytes, upl, ix, idxbuf));
   if (R.P.prec != P64) return fail(h, ISDF_E_UNSUPPORTED, "the adjoint runs in FP64 (prec = ISDF_FP64)");
+  if (R.P.core_method != 0) return fail(h, ISDF_E_UNSUPPORTED, "the adjoint differentiates the direct core (core_method = 0)");
   const GradLayout G = grad_layout(R.P, R.L, R.L.kx, R.L.nd);
   TRY(check_ws(h, workspace, ws_bytes, G.total));
   std::vector<int32_t> csr = grad_csr(ix, R.P.ngg);

@@ -109,3 +109,26 @@ def test_create_without_gpu_is_an_error():
     h = ctypes.c_void_p()
     assert isdf.lib().isdf_create(ctypes.byref(h), 0, None) != 0
     assert isdf.lib().isdf_eps_inv(None, None, None, None, None, 0, None, 0, None, 0, None, 0, None, None) == isdf.binding.E_ARG
+
+
+@pytest.mark.parametrize("name", ["tiny", "cfg0", "cfg1"])
+def test_contour_nodes_match_oracle(name):
+    """The library's host contour rule (its own arithmetic-geometric-mean Jacobi
+    functions) against the oracle's (scipy's), node by node."""
+    from oracle import cauchy as oc
+    inp = synth.make_inputs(name)
+    z, w = isdf.contour_nodes(inp.energies, inp.nv, inp.nc, 1e-13)
+    ev, q, big_q = oc.gap_and_width(inp.energies, inp.nv)
+    assert len(z) == oc.nodes_for_tolerance(q, big_q, 1e-13)
+    zo, wo = oc.contour_nodes(q, big_q, len(z))
+    assert np.abs(z - (zo + ev)).max() <= 1e-13 * np.abs(z).max()
+    assert np.abs(w - wo).max() <= 1e-13 * np.abs(w).max()
+
+
+def test_contour_nodes_validated():
+    bad = np.array([1.0, 0.5, 2.0])   # occupied above empty
+    with pytest.raises(isdf.IsdfError):
+        isdf.contour_nodes(bad, 2, 1)
+    prob = isdf.make_problem(12, np.eye(3) * 10.0, 8, 24, core_method=2)
+    out = ctypes.c_size_t(0)
+    assert isdf.lib().isdf_workspace_bytes(ctypes.byref(prob), 96, 256, 0, ctypes.byref(out)) == isdf.binding.E_ARG

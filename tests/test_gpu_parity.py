@@ -117,6 +117,40 @@ def test_eps_inv(name, prec):
     assert np.array_equal(got[0], e0) and np.array_equal(got[:, 0], e0), "G = 0 row/column is not e0"  # V(0) = 0
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["tiny", "cfg0", "mid", "kmaj"])
+def test_core_contour_integral(name, prec):
+    """core_method 1 (Algorithm 2, 1e-13 quadrature tolerance) against the oracle's
+    direct pair sum: the stage (FP64 <= 1e-11; single precision at the core's stage
+    bar) and the whole build (the eps~^{-1} bars)."""
+    inp = get_inputs(name)
+    print(f"[cauchy] case={name} prec={prec}", flush=True)
+    prob = isdf.problem_for(inp, prec, core_method=1)
+    m = isdf.core_m(dev(inp.psi_t), inp.energies, inp.mu_idx, prob).cpu().numpy()
+    ref = get_stages(name)["m"]
+    err_m = relf(m, ref)
+    got = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, prob).eps_inv[0].cpu().numpy()
+    err = relf(got, oracle.eps_inv_isdf(inp, stages=get_stages(name)))
+    print(f"  core rel-F {err_m:.3e}  eps^-1 rel-F {err:.3e}", flush=True)
+    assert err_m <= (1e-11 if prec == "fp64" else TOL_STAGE["fp32"] * 1e-2), err_m
+    assert np.array_equal(m, m.conj().T)
+    assert err <= TOL_EPS[prec], err
+
+
+def test_core_contour_integral_unsupported():
+    """The contour core is static and needs host energies: frequencies, plans and the
+    adjoint refuse it."""
+    inp = get_inputs("tiny")
+    prob = isdf.problem_for(inp, "fp64", core_method=1)
+    with pytest.raises(isdf.IsdfError) as e1:
+        isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, prob, omegas=[0.1])
+    with pytest.raises(isdf.IsdfError) as e2:
+        isdf.Plan(prob, inp.mu_idx, inp.miller)
+    with pytest.raises(isdf.IsdfError) as e3:
+        isdf.core_m(dev(inp.psi_t), inp.energies, inp.mu_idx, prob, omega=0.1)
+    assert e1.value.status == e2.value.status == e3.value.status == isdf.binding.E_UNSUPPORTED
+
+
 def test_fullrank_equals_exact_definition():
     """N_mu = Nv Nc: the GPU ISDF-SMW result equals chi0 from all pairs + dense LU."""
     inp = get_inputs("fullrank")
@@ -364,6 +398,23 @@ def test_full_size_64cubed(prec):
     assert err_id <= TOL_EPS[prec], err_id
     assert torch.equal(got, got.conj().T)
     assert bool((got[0, 1:] == 0).all()) and got[0, 0].item() == 1.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_core_contour_integral_64cubed(prec):
+    """Algorithm 2 at the 64^3 size (Nv Nc = 262144 pairs, 2048 points): 64 sampled
+    core entries against the oracle's direct pair sum."""
+    inp = get_inputs("cfg2")
+    print(f"[cauchy64] prec={prec}", flush=True)
+    rng = np.random.default_rng(65)
+    pairs = rng.integers(0, inp.nmu, size=(64, 2))
+    pairs[:8, 1] = pairs[:8, 0]
+    ref = oracle.core_entries(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, pairs)
+    m = isdf.core_m(dev(inp.psi_t), inp.energies, inp.mu_idx, isdf.problem_for(inp, prec, core_method=1))
+    got = m.cpu().numpy()[pairs[:, 0], pairs[:, 1]]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"  sampled max rel {err:.3e}", flush=True)
+    assert err <= (1e-11 if prec == "fp64" else TOL_STAGE["fp32"] * 1e-2), err
 
 
 def test_frequencies_full_tiles():
