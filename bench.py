@@ -282,8 +282,28 @@ def solid_like(isdf, torch, dev, steps):
         outs[prec] = out[0].clone()
         print(f"[bench] 64^3 {prec}: {dt * 1e3:.1f} ms/build", file=sys.stderr, flush=True)
         del plan, ws, out
+    # the same build with the contour-integral core (Algorithm 2), direct calls (the
+    # contour nodes come from the host energies; each call uploads and synchronises)
+    for prec in ("bf16x3", "fp64"):
+        prob = isdf.problem_for(inp, prec=prec, core_method=1)
+        nb = isdf.workspace_bytes(prob, inp.nmu, inp.ng, 0)
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        out = torch.empty((1, inp.ng, inp.ng), dtype=torch.complex128, device=dev)
+        isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        key = f"{prec}_contour_core"
+        res[key] = {"ms_per_build": round(dt * 1e3, 2), "builds_per_s": round(1.0 / dt, 3),
+                    "contour_nodes": int(len(isdf.contour_nodes(inp.energies, inp.nv, inp.nc)[0]))}
+        outs[key] = out[0].clone()
+        print(f"[bench] 64^3 {prec} contour core: {dt * 1e3:.1f} ms/build", file=sys.stderr, flush=True)
+        del ws, out
     ref = outs["fp64"]
-    for prec in ("bf16x3", "fp32"):
+    for prec in ("bf16x3", "fp32", "bf16x3_contour_core", "fp64_contour_core"):
         res[prec]["rel_fro_vs_fp64_path"] = float(((outs[prec] - ref).norm() / ref.norm()).item())
     del outs, ref
     res["adjoint_fp64"] = adjoint_timing(isdf, torch, dev, inp, psi, 2, res["fp64"]["ms_per_build"])
