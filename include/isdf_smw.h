@@ -75,7 +75,8 @@ typedef enum {
 } isdf_precision;
 
 typedef struct {
-  int32_t n[3];          /* FFT grid; Nr = n[0] n[1] n[2]; each in [2, 1024] */
+  int32_t n[3];          /* FFT grid; Nr = n[0] n[1] n[2]; each in [2, 1024]; the calls that
+                            take a plane-wave list need each <= 64 (else ISDF_E_UNSUPPORTED) */
   double cell[9];        /* lattice vectors as rows, Bohr */
   int32_t nv, nc;        /* occupied / empty state counts, both >= 1 */
   int32_t is_complex;    /* 0: psi is real float64; 1: psi is complex128 */
@@ -259,12 +260,16 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
  *   gram_split      cap on the split-K factor of X^H X, 1..16 (default 16)
  *   wg_per_cu       workgroups per CU of the persistent single-precision kernels, 1..4
  *                   (default 1)
+ *   core_stream     where the first frequency's core M runs: 0 on the caller's stream
+ *                   before the pair kernel (default), 1 on the library's second stream
+ *                   after it, beside the DFT and X^H X
  *   best_ms         output of isdf_plan_autotune: time of one call with the chosen knobs */
 typedef struct {
   int32_t dft_zb;
   int32_t core_split_pct;
   int32_t gram_split;
   int32_t wg_per_cu;
+  int32_t core_stream;
   double best_ms;
 } isdf_tune;
 

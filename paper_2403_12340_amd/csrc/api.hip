@@ -43,7 +43,7 @@ struct isdf_handle_s {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t ev[10] = {};         // stage timing (main stream)
-  hipEvent_t fork = nullptr, join = nullptr, core0 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, core0 = nullptr, zdone = nullptr, zops = nullptr;
   hipEvent_t mfork = nullptr, mdone = nullptr;  // multi-system calls
   hipEvent_t m_ready[2] = {}, m_used[2] = {};
   std::string err;
@@ -84,6 +84,7 @@ struct Problem {
 // pruned-DFT index lists derived from the Miller list (host bookkeeping)
 struct DftIndex {
   std::vector<int> xl, yl, zl, d_ax, d_by, g_d, g_cz, dmap;
+  std::vector<int> gd_off, gd_list;   // plane waves grouped by (x, y) pair (CSR, ascending g)
 };
 
 DftIndex dft_index(const int32_t* miller, int ng) {
@@ -116,6 +117,13 @@ DftIndex dft_index(const int32_t* miller, int ng) {
     ix.g_d[g] = (int)(std::lower_bound(ds.begin(), ds.end(), pairkey(xs[g], ys[g])) - ds.begin());
     ix.g_cz[g] = pos(ix.zl, zs[g]);
   }
+  const size_t nd = ix.d_ax.size();
+  ix.gd_off.assign(nd + 1, 0);
+  for (int g = 0; g < ng; ++g) ++ix.gd_off[ix.g_d[g] + 1];
+  for (size_t d = 0; d < nd; ++d) ix.gd_off[d + 1] += ix.gd_off[d];
+  ix.gd_list.resize(ng);
+  std::vector<int> fill(ix.gd_off.begin(), ix.gd_off.end() - 1);
+  for (int g = 0; g < ng; ++g) ix.gd_list[fill[ix.g_d[g]]++] = g;
   return ix;
 }
 
@@ -262,7 +270,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.e = take((size_t)P.ns * 8);
   L.miller = take((size_t)P.ngg * 3 * 4);
   L.recip = take(9 * 8);
-  L.idx = take((size_t)(kx + ky + kz + 2 * nd + 2 * P.ngg + kx * ky) * 4);
+  L.idx = take((size_t)(kx + ky + kz + 2 * nd + 2 * P.ngg + kx * ky + nd + 1 + P.ngg) * 4);
   L.w = take((size_t)P.nv * P.nc * 8);
   L.sqrtv = take((size_t)P.ngg * 8);
   L.twx = take((size_t)kx * P.n0 * el);
@@ -464,6 +472,7 @@ struct Tune {
   int core_split_pct = 100;  // core split count, percent of the default
   int gram_split = 16;     // split-K cap of X^H X
   int wg_per_cu = 1;       // workgroups per CU of the persistent k-major kernels
+  int core_stream = 0;     // first core: 0 main stream before Z, 1 side stream after Z
 };
 
 struct Run {
@@ -538,19 +547,20 @@ isdf_status stage_smis(Run& R, void* mi, void* q, hipStream_t st) {
 
 // Operands of the pair product.  Mixed precision: one streaming pass to complex64
 // halves the bytes the contraction reads.
-isdf_status stage_z_operands(Run& R) {
+isdf_status stage_z_operands(Run& R, hipStream_t st) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   if (P.prec == P64) return ISDF_OK;
   if (P.prec == PBF3) {
-    HIPCHK(bf3_split_rows(R.psi, P.nr, P.nr, P.nv, P.nc, at<char>(R.ws, R.L.bf_rows), R.st));
-    HIPCHK(bf3_split_points(at<char>(R.ws, R.L.pm), P.nmu, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.bf_pts), R.st));
+    HIPCHK(bf3_split_rows(R.psi, P.nr, P.nr, P.nv, P.nc, at<char>(R.ws, R.L.bf_rows), st));
+    HIPCHK(bf3_split_points(at<char>(R.ws, R.L.pm), P.nmu, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.bf_pts), st));
     return ISDF_OK;
   }
-  HIPCHK(convert_z(R.psi, false, at<char>(R.ws, R.L.psi32), true, (long)P.ns * P.nr, R.st));
-  HIPCHK(convert_z(at<char>(R.ws, R.L.pm), false, at<char>(R.ws, R.L.pm32), true, (long)P.ns * P.nmu, R.st));
+  HIPCHK(convert_z(R.psi, false, at<char>(R.ws, R.L.psi32), true, (long)P.ns * P.nr, st));
+  HIPCHK(convert_z(at<char>(R.ws, R.L.pm), false, at<char>(R.ws, R.L.pm32), true, (long)P.ns * P.nmu, st));
   return ISDF_OK;
 }
+isdf_status stage_z_operands(Run& R) { return stage_z_operands(R, R.st); }
 
 // Z^T [mu][r] by the pair-Gram kernel (one launch).
 isdf_status stage_z(Run& R) {
@@ -582,12 +592,14 @@ DftPlan make_plan(Run& R) {
   p.twy = at<char>(R.ws, L.twy);
   p.twz = at<char>(R.ws, L.twz);
   const int* ib = R.idx;
-  // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ng] g_cz[ng] dmap[kx][ky]
+  // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ng] g_cz[ng] dmap[kx][ky] gd_off[nd + 1] gd_list[ng]
   p.d_ax = ib + L.kx + L.ky + L.kz;
   p.d_by = p.d_ax + L.nd;
   p.g_d = p.d_by + L.nd;
   p.g_cz = p.g_d + P.ngg;
   p.dmap = p.g_cz + P.ngg;
+  p.gd_off = p.dmap + L.kx * L.ky;
+  p.gd_list = p.gd_off + L.nd + 1;
   return p;
 }
 
@@ -869,8 +881,8 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
     // the Gram's plane waves: the list itself, or the list followed by the rest of the grid
     if (R.P.full_gram) miller = up_.hold(full_grid_list(miller, ng, R.P.n0, R.P.n1, R.P.n2));
     ix = dft_index(miller, R.P.ngg);
-    if (!dft_supported(R.P.n0, R.P.n1, (int)ix.xl.size(), (int)ix.yl.size(), R.P.prec == P64 ? P64 : P32))
-      return fail(h, ISDF_E_UNSUPPORTED, "grid plane too large for the LDS-resident DFT slab");
+    if (!dft_supported(R.P.n0, R.P.n1, R.P.n2, (int)ix.xl.size(), (int)ix.yl.size(), R.P.prec == P64 ? P64 : P32))
+      return fail(h, ISDF_E_UNSUPPORTED, "grid axis above 64 points: the DFT keeps an x-y slab in LDS and a z-line per wave");
   } else {
     R.P.ngg = ng;   // no Gram in this call
     ix.xl = ix.yl = ix.zl = {0};
@@ -906,7 +918,7 @@ isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const 
   if (miller) {
     up_.add(R.L.miller, miller, (size_t)R.P.ngg * 12);
     idxbuf.clear();
-    for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz, &ix.dmap})
+    for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz, &ix.dmap, &ix.gd_off, &ix.gd_list})
       idxbuf.insert(idxbuf.end(), v->begin(), v->end());
     up_.add(R.L.idx, idxbuf.data(), idxbuf.size() * 4);
     up_.add(R.L.recip, R.P.recip, 9 * 8);
@@ -942,6 +954,9 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
   HIPCHK(hipEventRecord(h->fork, R.st));
   HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
   TRY(stage_s(R, side, L.lin2, false));
+  // the pair kernel's operand pass (streaming, memory-bound) beside the first core
+  TRY(stage_z_operands(R, side));
+  HIPCHK(hipEventRecord(h->zops, side));
   double* wb = at<double>(R.ws, L.wb);
   for (int k = 0; k < nw; ++k)
     HIPCHK(pair_weights(R.e, P.nv, P.nc, omega[k], wb + (long)k * P.nv * P.nc, R.st));
@@ -970,7 +985,7 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
     HIPCHK(gemm(P64, b, side));
   }
   HIPCHK(hipEventRecord(h->m_ready[0], side));
-  TRY(stage_z_operands(R));
+  HIPCHK(hipStreamWaitEvent(R.st, h->zops, 0));
   tm.mark();
   TRY(stage_z(R));
   tm.mark();
@@ -1029,12 +1044,17 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
   const int nw = std::max(n_omega, 1);
   void* mbuf[2] = {at<char>(R.ws, R.L.l), at<char>(R.ws, R.L.l2)};
+  // core_stream 1: the first core waits for Z on the side stream instead, beside the DFT
+  const bool core_side = R.tune.core_stream == 1;
   auto side_core = [&](int k) -> isdf_status {
     if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
-    if (k == 0) {
+    if (k == 0 && !core_side) {
       TRY(stage_core(R, n_omega ? omega[0] : 0.0, nullptr, mbuf[0], R.st));
       HIPCHK(hipEventRecord(h->core0, R.st));
       HIPCHK(hipStreamWaitEvent(side, h->core0, 0));
+    } else if (k == 0) {
+      HIPCHK(hipStreamWaitEvent(side, h->zdone, 0));
+      TRY(stage_core(R, n_omega ? omega[0] : 0.0, nullptr, mbuf[0], side));
     } else {
       TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
     }
@@ -1044,11 +1064,21 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
     return ISDF_OK;
   };
   TRY(stage_s(R, side, R.L.lin2, false));
-  TRY(side_core(0));
-  if (nw > 1) TRY(side_core(1));
-  TRY(stage_z_operands(R));
+  // the pair kernel's operand pass (streaming, memory-bound) beside the first core
+  TRY(stage_z_operands(R, side));
+  HIPCHK(hipEventRecord(h->zops, side));
+  if (!core_side) {
+    TRY(side_core(0));
+    if (nw > 1) TRY(side_core(1));
+  }
+  HIPCHK(hipStreamWaitEvent(R.st, h->zops, 0));
   tm.mark();
   TRY(stage_z(R));
+  if (core_side) {
+    HIPCHK(hipEventRecord(h->zdone, R.st));
+    TRY(side_core(0));
+    if (nw > 1) TRY(side_core(1));
+  }
   tm.mark();
   TRY(stage_dft(R, true));
   tm.mark();
@@ -1089,7 +1119,7 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
   if (hipSetDevice(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
-  for (hipEvent_t* e : {&h->fork, &h->join, &h->core0, &h->mfork, &h->mdone, &h->m_ready[0], &h->m_ready[1],
+  for (hipEvent_t* e : {&h->fork, &h->join, &h->core0, &h->zdone, &h->zops, &h->mfork, &h->mdone, &h->m_ready[0], &h->m_ready[1],
                         &h->m_used[0], &h->m_used[1]})
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   // default priority, non-blocking with respect to the legacy default stream
@@ -1111,7 +1141,7 @@ isdf_status isdf_destroy(isdf_handle h) {
     (void)hipStreamDestroy(h->side);
   }
   for (auto& e : h->ev) if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {h->fork, h->join, h->core0, h->mfork, h->mdone, h->m_ready[0], h->m_ready[1], h->m_used[0],
+  for (hipEvent_t e : {h->fork, h->join, h->core0, h->zdone, h->zops, h->mfork, h->mdone, h->m_ready[0], h->m_ready[1], h->m_used[0],
                        h->m_used[1]})
     if (e) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
@@ -1358,10 +1388,10 @@ isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int3
     miller = full.data();
   }
   DftIndex ix = dft_index(miller, P.ngg);
-  if (!dft_supported(P.n0, P.n1, (int)ix.xl.size(), (int)ix.yl.size(), P.prec == P64 ? P64 : P32))
-    return fail(h, ISDF_E_UNSUPPORTED, "grid plane too large for the LDS-resident DFT slab");
+  if (!dft_supported(P.n0, P.n1, P.n2, (int)ix.xl.size(), (int)ix.yl.size(), P.prec == P64 ? P64 : P32))
+    return fail(h, ISDF_E_UNSUPPORTED, "grid axis above 64 points: the DFT keeps an x-y slab in LDS and a z-line per wave");
   std::vector<int> idxbuf;
-  for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz, &ix.dmap})
+  for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz, &ix.dmap, &ix.gd_off, &ix.gd_list})
     idxbuf.insert(idxbuf.end(), v->begin(), v->end());
   isdf_plan pl = new isdf_plan_s;
   pl->h = h;
@@ -1497,7 +1527,8 @@ isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {
 
 static bool tune_valid(const isdf_tune* t) {
   return t && t->dft_zb >= 1 && t->dft_zb <= 64 && t->core_split_pct >= 25 && t->core_split_pct <= 200 &&
-         t->gram_split >= 1 && t->gram_split <= 16 && t->wg_per_cu >= 1 && t->wg_per_cu <= 4;
+         t->gram_split >= 1 && t->gram_split <= 16 && t->wg_per_cu >= 1 && t->wg_per_cu <= 4 &&
+         (t->core_stream == 0 || t->core_stream == 1);
 }
 
 isdf_status isdf_plan_set_tune(isdf_plan pl, const isdf_tune* t) {
@@ -1507,6 +1538,7 @@ isdf_status isdf_plan_set_tune(isdf_plan pl, const isdf_tune* t) {
   pl->tune.core_split_pct = t->core_split_pct;
   pl->tune.gram_split = t->gram_split;
   pl->tune.wg_per_cu = t->wg_per_cu;
+  pl->tune.core_stream = t->core_stream;
   return ISDF_OK;
 }
 
@@ -1516,6 +1548,7 @@ isdf_status isdf_plan_get_tune(isdf_plan pl, isdf_tune* t) {
   t->core_split_pct = pl->tune.core_split_pct;
   t->gram_split = pl->tune.gram_split;
   t->wg_per_cu = pl->tune.wg_per_cu;
+  t->core_stream = pl->tune.core_stream;
   t->best_ms = 0.0;
   return ISDF_OK;
 }
@@ -1543,6 +1576,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
   const int splits[] = {50, 100, 200};
   const int grams[] = {4, 8, 16};
   const int wpcs[] = {1, 2};
+  const int cstreams[] = {0, 1};
   auto sweep = [&](int Tune::*knob, const int* cands, int nc) -> isdf_status {
     const int keep = pl->tune.*knob;
     int arg = keep;
@@ -1560,6 +1594,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
   TRY(sweep(&Tune::core_split_pct, splits, 3));
   TRY(sweep(&Tune::gram_split, grams, 3));
   TRY(sweep(&Tune::wg_per_cu, wpcs, 2));
+  TRY(sweep(&Tune::core_stream, cstreams, 2));
   if (out) {
     TRY(isdf_plan_get_tune(pl, out));
     out->best_ms = best;

@@ -268,9 +268,10 @@ __global__ __launch_bounds__(XY_NT) void dft_xy_kernel(DftPlan p, const cx<T>* _
   }
 }
 
-bool dft_supported(int n0, int n1, int kx, int ky, Prec compute) {
+bool dft_supported(int n0, int n1, int n2, int kx, int ky, Prec compute) {
   (void)kx; (void)ky;  // any list length: the x and y stages run in chunks of 32 frequencies
   if (n1 > 64 || n0 > 64) return false;  // one 64 x 64 slab per MFMA tile
+  if (n2 > 64) return false;             // one z-line per wave in the z stage
   const size_t bytes = compute == P64 ? xy_lds_bytes<double>() : xy_lds_bytes<float>();
   return bytes <= 160 * 1024;
 }
@@ -308,12 +309,16 @@ hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipS
 }
 
 // z stage: zg[mu][g] = scale[g] sum_z t2[mu][d_g][z] twz[c_g][z], one thread per
-// (g, point), reading the z-contiguous line of its pair with independent loads.
+// (plane wave, point).  Threads take the plane waves in (x, y)-pair order, so the
+// ~NG/nd neighbours that share a pair read the same z-line (few distinct cache
+// lines per load); each thread runs four independent partial sums.
 template <typename T>
-__global__ void dft_z_kernel(DftPlan p, const cx<T>* t2, cx<T>* zg, const double* scale) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void dft_z_kernel(DftPlan p, const cx<T>* __restrict__ t2, cx<T>* __restrict__ zg,
+                                                    const double* __restrict__ scale) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int mu = blockIdx.y;
-  if (g >= p.ng) return;
+  if (e >= p.ng) return;
+  const int g = p.gd_list[e];
   const int d = p.g_d[g], c = p.g_cz[g];
   const cx<T>* twz = reinterpret_cast<const cx<T>*>(p.twz) + (long)c * p.n2;
   const cx<T>* line = t2 + ((long)mu * p.nd + d) * p.n2;

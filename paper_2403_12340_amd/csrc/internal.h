@@ -86,13 +86,15 @@ struct DftPlan {
   const int* g_d;          // ng: pair index of plane wave g
   const int* g_cz;         // ng: index into twz list of plane wave g
   const int* dmap;         // kx x ky: pair index d of (x-frequency a, y-frequency b), or -1
+  const int* gd_off;       // nd + 1: plane waves of pair d are gd_list[gd_off[d] .. gd_off[d + 1])
+  const int* gd_list;      // ng
   int zb = 8;              // z-planes per workgroup of the x/y stage (a tuning knob)
 };
 // zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][nd][n2] -> zg: [nmu][ng] (times scale[g] if given)
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);
 hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, const double* scale,
                  hipStream_t st);
-bool dft_supported(int n0, int n1, int kx, int ky, Prec compute);  // LDS fits
+bool dft_supported(int n0, int n1, int n2, int kx, int ky, Prec compute);  // LDS fits
 
 hipError_t conj_transpose(int n, const void* a, void* at, hipStream_t st);   // at = a^H (z64)
 hipError_t convert_z(const void* src, bool src32, void* dst, bool dst32, long count, hipStream_t st);

@@ -530,6 +530,7 @@ def test_plan_autotune():
     t = plan.autotune(psi, e, out, ws, reps=2)
     assert t["dft_zb"] in (2, 4, 8, 16) and t["core_split_pct"] in (50, 100, 200)
     assert t["gram_split"] in (4, 8, 16) and t["wg_per_cu"] in (1, 2) and t["best_ms"] > 0
+    assert t["core_stream"] in (0, 1)
     assert plan.get_tune()["dft_zb"] == t["dft_zb"]
     plan.eps_inv_async(psi, e, out, ws)
     plan.sync()
@@ -542,6 +543,25 @@ def test_plan_autotune():
         assert relf(out[0].cpu().numpy(), oracle.eps_inv_isdf(inp, stages=get_stages("kmaj"))) <= TOL_EPS["fp32"]
     with pytest.raises(isdf.IsdfError):
         plan.set_tune(dft_zb=0)
+    with pytest.raises(isdf.IsdfError):
+        plan.set_tune(core_stream=2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_core_stream_placement_is_bit_identical(prec):
+    """The first core on the second stream after Z (core_stream 1) runs the same
+    kernels on the same data: the result equals the default placement bit for bit."""
+    inp, prob, plan = _plan_case("mid", prec)
+    psi, e = dev(inp.psi_t), dev(inp.energies)
+    ws = plan.new_workspace()
+    a, b = plan.new_output(), plan.new_output()
+    plan.set_tune(core_stream=0)
+    plan.eps_inv_async(psi, e, a, ws)
+    plan.sync()
+    plan.set_tune(core_stream=1)
+    plan.eps_inv_async(psi, e, b, ws)
+    plan.sync()
+    assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
