@@ -437,12 +437,22 @@ struct Uploader {
   const int32_t* hold(std::vector<int32_t>&& v) { keep.push_back(std::move(v)); return keep.back().data(); }
   std::deque<std::vector<double>> keepd;
   const double* hold(std::vector<double>&& v) { keepd.push_back(std::move(v)); return keepd.back().data(); }
+  // Items are staged in pinned memory and copied in groups: items whose workspace
+  // ranges are separated by no more than alignment padding share one copy; any
+  // larger gap holds other buffers and starts a new copy (so the copies never
+  // write outside the items and their padding).
   isdf_status run() {
     if (items.empty()) return ISDF_OK;
-    size_t lo = items[0].off, hi = 0;
-    for (auto& it : items) { lo = std::min(lo, it.off); hi = std::max(hi, it.off + it.bytes); }
-    const size_t total = hi - lo;
-    // the previous call's copy out of the pinned buffer must be complete
+    std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.off < b.off; });
+    struct Group { size_t lo, hi, at; };
+    std::vector<Group> groups;
+    for (auto& it : items) {
+      if (groups.empty() || it.off > groups.back().hi + ALIGN) groups.push_back({it.off, it.off + it.bytes, 0});
+      else groups.back().hi = std::max(groups.back().hi, it.off + it.bytes);
+    }
+    size_t total = 0;
+    for (auto& g : groups) { g.at = total; total += g.hi - g.lo; }
+    // the previous call's copies out of the pinned buffer must be complete
     HIPCHK(hipStreamSynchronize(h->stream));
     if (total > h->pinned_bytes) {
       if (h->pinned) HIPCHK(hipHostFree(h->pinned));
@@ -452,8 +462,14 @@ struct Uploader {
       h->pinned_bytes = total;
     }
     char* base = reinterpret_cast<char*>(h->pinned);
-    for (auto& it : items) std::memcpy(base + (it.off - lo), it.src, it.bytes);
-    HIPCHK(hipMemcpyAsync(reinterpret_cast<char*>(ws) + lo, base, total, hipMemcpyHostToDevice, h->stream));
+    size_t gi = 0;
+    for (auto& it : items) {
+      while (it.off >= groups[gi].hi) ++gi;
+      std::memcpy(base + groups[gi].at + (it.off - groups[gi].lo), it.src, it.bytes);
+    }
+    for (auto& g : groups)
+      HIPCHK(hipMemcpyAsync(reinterpret_cast<char*>(ws) + g.lo, base + g.at, g.hi - g.lo, hipMemcpyHostToDevice,
+                            h->stream));
     return ISDF_OK;
   }
 };
