@@ -63,27 +63,50 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
 #pragma unroll
       for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
     zl_loop_full(smem, zf, nt, nt, sa, sb, A, lda, B, ldb, m0, n0, has_next, nm0, nn0, acc, acc, wm0, wn0, lane);
+    if (!HERM) {
+#pragma unroll
+      for (int fm = 0; fm < ZL::FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < ZL::FN; ++fn)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = m0 + wm0 + fm * 16 + Mfma<float>::row(lane, v);
+            const int c = n0 + wn0 + fn * 8 + (rc >> 1);
+            reinterpret_cast<float*>(C)[((long)r * ldc + c) * 2 + part] = alpha * acc[fm][fn][v];
+          }
+      continue;
+    }
+    // Hermitian output through LDS (free after the K loop's last barrier): the tile
+    // [128 rows][64 complex, stride 65] is written once row by row (lower part) and
+    // once column by column as the conjugate mirror, both as contiguous rows of the
+    // complex128 output.
+    float* ts = smem;
 #pragma unroll
     for (int fm = 0; fm < ZL::FM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < ZL::FN; ++fn)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = m0 + wm0 + fm * 16 + Mfma<float>::row(lane, v);
-          const int c = n0 + wn0 + fn * 8 + (rc >> 1);
-          const float val = alpha * acc[fm][fn][v];
-          if (!HERM) {
-            reinterpret_cast<float*>(C)[((long)r * ldc + c) * 2 + part] = val;
-          } else {
-            double* o = reinterpret_cast<double*>(C);
-            if (r > c) {
-              o[((long)r * ldc + c) * 2 + part] = (double)val;
-              o[((long)c * ldc + r) * 2 + part] = part ? -(double)val : (double)val;
-            } else if (r == c) {
-              o[((long)r * ldc + c) * 2 + part] = part ? 0.0 : 1.0 + (double)val;
-            }
-          }
+          const int r = wm0 + fm * 16 + Mfma<float>::row(lane, v);
+          const int c = wn0 + fn * 8 + (rc >> 1);
+          ts[(r * 65 + c) * 2 + part] = alpha * acc[fm][fn][v];
         }
+    __syncthreads();
+    double* o = reinterpret_cast<double*>(C);
+    for (int e = tid; e < ZL::BM * ZL::BN; e += ZL::NT) {   // lower part, row-major
+      const int r = e / ZL::BN, c = e % ZL::BN, gr = m0 + r, gc = n0 + c;
+      if (gr < gc) continue;
+      const float re = ts[(r * 65 + c) * 2], im = ts[(r * 65 + c) * 2 + 1];
+      *reinterpret_cast<double2*>(o + ((long)gr * ldc + gc) * 2) =
+          gr == gc ? double2{1.0 + (double)re, 0.0} : double2{(double)re, (double)im};
+    }
+    for (int e = tid; e < ZL::BM * ZL::BN; e += ZL::NT) {   // mirror: output row gc, contiguous along gr
+      const int c = e / ZL::BM, r = e % ZL::BM, gr = m0 + r, gc = n0 + c;
+      if (gr <= gc) continue;
+      const float re = ts[(r * 65 + c) * 2], im = ts[(r * 65 + c) * 2 + 1];
+      *reinterpret_cast<double2*>(o + ((long)gc * ldc + gr) * 2) = double2{(double)re, -(double)im};
+    }
+    __syncthreads();   // the next tile stages into the same LDS
   }
 }
 
