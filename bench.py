@@ -5,8 +5,7 @@ Gram via the pruned DFT, SMW solve and output) for one static system, with the
 orbitals, energies, workspace and output already resident in HBM.  The timed
 steps are enqueue-only isdf_plan_eps_inv calls (the plan is made once, before
 the timed region), closed by one isdf_plan_sync that also checks the device
-status; per-stage times come from a separate pass of isdf_eps_inv with HIP
-events.
+status and returns the mean per-stage HIP-event intervals of the timed calls.
 
 Workload: 48^3 grid, Nv = 64, Nc = 256, N_mu = 640, NG = 4096, complex
 orbitals (seeded synthetic inputs, see synth/).  The headline value is the
@@ -98,26 +97,24 @@ def _kernel_stats(db):
 
 def _phase_dispatches(db, steps, warmup):
     """Durations (ns) of the mixed path's pair-Gram launches on the benchmark workload,
-    split by the benchmark's fixed order: autotune, W warm-up calls, the K timed calls,
-    then the stage-timing pass (nrep calls), all before the FP64 path's first Z launch
-    (the FP64 pair-Gram kernel over the whole grid; its small launches form S on the points)."""
+    split by the benchmark's fixed order: autotune, W warm-up calls, then the K timed
+    calls, all before the FP64 path's first Z launch (the FP64 pair-Gram kernel over a
+    whole grid, >= 1e6 threads; its launches that form S on the points are far smaller)."""
     import sqlite3
     c = sqlite3.connect(db)
     rows = c.execute("select name, start, end, grid_x * grid_y * grid_z from kernels where "
                      "name like 'isdf::zpair32_kernel(%' or name like '%zpair_kernel<double%' "
                      "order by start").fetchall()
-    big = max((g for n, _, _, g in rows if "zpair_kernel<double" in n), default=0)
     z32 = []
     for name, t0, t1, g in rows:
         if "zpair_kernel<double" in name:
-            if g == big:
+            if g >= 1_000_000:   # Z over a whole grid (S on the points launches far fewer threads)
                 break
             continue
         z32.append(t1 - t0)
-    nrep = max(3, min(steps, 10))
-    if len(z32) < nrep + steps + warmup:
+    if len(z32) < steps + warmup:
         return None
-    return {"timed": z32[-(nrep + steps):-nrep], "stage_pass": z32[-nrep:]}
+    return {"timed": z32[-steps:], "warmup": z32[-(steps + warmup):-steps]}
 
 
 def _pmc_per_dispatch(db, counter):
@@ -361,25 +358,19 @@ def main():
         for _ in range(args.warmup):
             plan.eps_inv_async(psi, e_dev, out, ws)
         plan.sync()
+        # the timed calls record HIP events at their stage boundaries on the library's
+        # stream (the stream the kernels run on); sync() returns each stage's mean
+        plan.time_stages(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.steps):
             plan.eps_inv_async(psi, e_dev, out, ws)
-        plan.sync()
+        rep = plan.sync()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
+        stages = np.array(list(rep.stage_ms))
         outs[prec] = out[0].cpu().numpy()
-        # per-stage HIP events on the library's stream (separate pass, direct entry point)
-        nbytes = isdf.workspace_bytes(prob, inp.nmu, inp.ng, 0)
-        ws2 = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-        out2 = torch.empty((1, inp.ng, inp.ng), dtype=torch.complex128, device=dev)
-        stages = np.zeros(8)
-        nrep = max(3, min(args.steps, 10))
-        for _ in range(nrep):
-            r = isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob, out=out2, workspace=ws2, timing=True)
-            stages += np.array(list(r.report.stage_ms))
-        stages /= nrep
-        del plan, ws, ws2, out2
+        del plan, ws
         results[prec] = dict(ms_per_step=dt * 1e3, builds_per_s=1.0 / dt, stage_ms=stages.tolist(), tune=tune)
         print(f"[bench] {prec}: {dt * 1e3:.3f} ms/build  stages(ms) {np.round(stages, 3).tolist()}",
               file=sys.stderr, flush=True)
@@ -426,8 +417,9 @@ def main():
     fl = flops_model(inp)
     total_flops = sum(fl.values())
     m = results["fp32"]
-    # dominant kernel: the pair-Gram kernel; stage 1 brackets exactly its one launch
-    # (HIP events on the library's stream, the stream the kernel runs on)
+    # dominant kernel: the pair-Gram kernel; stage 1 brackets exactly its one launch per
+    # call (HIP events on the library's stream, the stream the kernel runs on), averaged
+    # over the K timed calls
     z_ms = m["stage_ms"][1]
     achieved = fl["zpair"] / (z_ms * 1e-3) / 1e12
     traffic = recorded_traffic()

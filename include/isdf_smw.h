@@ -289,8 +289,16 @@ isdf_status isdf_plan_autotune(isdf_plan plan, const void* psi, const double* en
 /* Wait for the handle's stream and return the first error any call enqueued
  * since the previous sync found on the device: ISDF_E_ARG (energies without a
  * gap or not finite), ISDF_E_NOT_PD; then clear it.  rep (optional) receives
- * the last call's min_pivot and refinement residuals (no stage times). */
+ * the last call's min_pivot and refinement residuals, and, with stage timing
+ * on, stage_ms = the mean of each stage's HIP-event interval over the calls
+ * since the previous sync (zeros otherwise). */
 isdf_status isdf_plan_sync(isdf_plan plan, isdf_report* rep);
+
+/* Stage timing of a plan's calls: on = 1 makes each call record HIP events at
+ * its stage boundaries on the handle's stream (the stages of isdf_report;
+ * at most 256 calls between two syncs are timed), on = 0 stops it.  For
+ * measurement; not for calls inside a stream capture.  Errors: ISDF_E_ARG. */
+isdf_status isdf_plan_time_stages(isdf_plan plan, int32_t on);
 
 /* Host-only check of every host-side argument of isdf_eps_inv (problem, energies,
  * points, plane waves, frequencies); no GPU or handle needed.  Returns the

@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "isdf_plan_workspace_bytes": [vp, ctypes.POINTER(sz)],
             "isdf_plan_eps_inv": [vp, vp, vp, pdbl, vp, sz, vp],
             "isdf_plan_sync": [vp, prep],
+            "isdf_plan_time_stages": [vp, i32],
             "isdf_plan_set_tune": [vp, ctypes.POINTER(Tune)],
             "isdf_plan_get_tune": [vp, ctypes.POINTER(Tune)],
             "isdf_plan_autotune": [vp, vp, vp, pdbl, vp, sz, vp, i32, ctypes.POINTER(Tune)],
@@ -504,6 +505,10 @@ class Plan:
         for k, v in knobs.items():
             setattr(t, k, int(v))
         self.h.check(lib().isdf_plan_set_tune(self.p, ctypes.byref(t)), "isdf_plan_set_tune")
+
+    def time_stages(self, on: bool = True):
+        """Record per-stage HIP events in every call; sync() then reports their means."""
+        self.h.check(lib().isdf_plan_time_stages(self.p, 1 if on else 0), "isdf_plan_time_stages")
 
     def sync(self) -> Report:
         rep = Report()

@@ -64,6 +64,7 @@ struct StatusBlock {
 };
 
 constexpr int CAUCHY_MAX_NODES = 256;  // contour node table size
+constexpr int PLAN_TIMED_CALLS = 256;  // calls a plan times between two syncs
 constexpr int CAUCHY_CHUNK = 8;        // nodes per batched Gram pair
 
 struct Problem {
@@ -478,7 +479,10 @@ struct Timer {
   isdf_handle h;
   bool on;
   int k = 0;
-  void mark() { if (on && k < 10) (void)hipEventRecord(h->ev[k++], h->stream); }
+  hipEvent_t* evs = nullptr;   // events to record into (10 of them); the handle's own when null
+  void mark() {
+    if (on && k < 10) (void)hipEventRecord(evs ? evs[k++] : h->ev[k++], h->stream);
+  }
 };
 
 // ---- shared pieces of the pipeline --------------------------------------------------------
@@ -1385,6 +1389,10 @@ struct isdf_plan_s {
   int n_omega = 0;
   void* dev = nullptr;  // status block, point indices, Miller list, reciprocal basis, DFT tables
   size_t off_mu = 0, off_miller = 0, off_recip = 0, off_idx = 0;
+  // per-call stage timing (isdf_plan_time_stages): 10 events per call since the last sync
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  int tn = 0, tmarks = 0;
 };
 
 isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int32_t* mu_idx, int32_t n_mu,
@@ -1443,7 +1451,15 @@ isdf_status isdf_plan_destroy(isdf_plan pl) {
   (void)hipSetDevice(pl->h->device);
   (void)hipStreamSynchronize(pl->h->stream);
   if (pl->dev) (void)hipFree(pl->dev);
+  for (hipEvent_t e : pl->tev) (void)hipEventDestroy(e);
   delete pl;
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_time_stages(isdf_plan pl, int32_t on) {
+  if (!pl || (on != 0 && on != 1)) return ISDF_E_ARG;
+  pl->timing = on == 1;
+  pl->tn = 0;
   return ISDF_OK;
 }
 
@@ -1488,6 +1504,20 @@ isdf_status plan_enqueue(isdf_plan pl, const void* psi, const double* energies, 
   R.idx = reinterpret_cast<const int*>(d + pl->off_idx);
   R.tune = pl->tune;
   HIPCHK(hipSetDevice(h->device));
+  if (pl->timing && pl->tn < PLAN_TIMED_CALLS) {
+    while ((int)pl->tev.size() < 10 * (pl->tn + 1)) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pl->tev.push_back(e);
+    }
+    Timer t{h, true, 0, pl->tev.data() + 10 * pl->tn};
+    t.mark();
+    HIPCHK(check_gap(energies, R.P.nv, R.P.nc, &R.sb->status, ST_NO_GAP, R.st));
+    TRY(enqueue_eps_inv(R, psi, omega, pl->n_omega, eps_inv, t));
+    pl->tmarks = t.k;
+    ++pl->tn;
+    return ISDF_OK;
+  }
   HIPCHK(check_gap(energies, R.P.nv, R.P.nc, &R.sb->status, ST_NO_GAP, R.st));
   Timer none{h, false};
   return enqueue_eps_inv(R, psi, omega, pl->n_omega, eps_inv, none);
@@ -1538,6 +1568,19 @@ isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {
   HIPCHK(hipMemcpyAsync(&hs, pl->dev, offsetof(StatusBlock, partial), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(zero_fill(pl->dev, offsetof(StatusBlock, partial), h->stream));
+  if (rep) for (int k = 0; k < 8; ++k) rep->stage_ms[k] = 0.0;
+  if (rep && pl->tn > 0) {   // mean of each stage interval over the timed calls since the last sync
+    for (int k = 0; k + 1 < pl->tmarks && k < 8; ++k) {
+      double sum = 0.0;
+      for (int c = 0; c < pl->tn; ++c) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pl->tev[10 * c + k], pl->tev[10 * c + k + 1]));
+        sum += ms;
+      }
+      rep->stage_ms[k] = sum / pl->tn;
+    }
+  }
+  pl->tn = 0;
   return report_status(h, hs, pl->P, rep);
 }
 

@@ -295,6 +295,26 @@ def test_plan_matches_direct(prec):
         assert torch.equal(o.cpu(), direct)
 
 
+def test_plan_stage_timing():
+    """Stage timing on a plan: the timed calls give the same result, and sync returns
+    positive mean stage intervals (then zeros once timing is off)."""
+    inp, prob, plan = _plan_case("mid", "fp32")
+    psi, e = dev(inp.psi_t), dev(inp.energies)
+    ws, a, b = plan.new_workspace(), plan.new_output(), plan.new_output()
+    plan.eps_inv_async(psi, e, a, ws)
+    plan.sync()
+    plan.time_stages(True)
+    for _ in range(3):
+        plan.eps_inv_async(psi, e, b, ws)
+    rep = plan.sync()
+    assert torch.equal(a, b)
+    st = list(rep.stage_ms)
+    assert all(x > 0 for x in st[:7]), st
+    plan.time_stages(False)
+    plan.eps_inv_async(psi, e, b, ws)
+    assert all(x == 0 for x in plan.sync().stage_ms)
+
+
 def test_plan_frequencies():
     inp, prob, plan = _plan_case("mid", "fp32", n_omega=4)
     psi = dev(inp.psi_t)
