@@ -238,7 +238,7 @@ struct Layout {
   size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (FP32 mode only)
   size_t bf_rows = 0, bf_pts = 0;    // bf16 hi / lo planes of the orbitals (BF16x3 mode only)
   // contour-integral core: node table (lambda, weight), scaled operands, Gram pairs, running sum
-  size_t cnodes = 0, cops = 0, cprod = 0, csum = 0;
+  size_t cnodes = 0, cops = 0, cprod = 0, csum = 0, cpm32 = 0;
   int kx = 0, ky = 0, kz = 0, nd = 0, nsplit = 1;
 };
 
@@ -265,6 +265,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
     L.cops = take((size_t)CAUCHY_CHUNK * P.ns * P.nmu * z);
     L.cprod = take((size_t)2 * CAUCHY_CHUNK * nmu2 * z);
     L.csum = take(nmu2 * z);
+    L.cpm32 = take((size_t)P.ns * P.nmu * 8);
   }
   // host-supplied arrays, adjacent so that one copy uploads them all
   L.mu = take((size_t)P.nmu * 4);
@@ -700,9 +701,34 @@ isdf_status stage_core_cauchy(Run& R, void* m_out, void* negm, hipStream_t st) {
   const char* lam = at<char>(R.ws, L.cnodes);
   const char* wts = lam + (size_t)R.cn * 16;
   HIPCHK(zero_fill(at<char>(R.ws, L.csum), (size_t)n2 * 16, st));
+  // single precision on full tiles: the Gram pairs on the k-major engine, complex64 operands and products
+  char* pm32 = at<char>(R.ws, L.cpm32);
+  const size_t opsz = (size_t)ns * n * 8;   // one node's complex64 operands
+  const bool km = cp == P32 && opsz % 16 == 0 && ((size_t)n2 * 8) % 16 == 0 &&
+                  gemm32_fits(n, n, nv, pm32, n, ops, n) &&
+                  gemm32_fits(n, n, P.nc, pm32 + (size_t)nv * n * 8, n, ops + (size_t)nv * n * 8, n);
+  if (km) {
+    HIPCHK(convert_z(pm, false, pm32, true, (long)ns * n, st));
+    char* av32 = av;
+    char* ac32 = av + (size_t)CAUCHY_CHUNK * n2 * 8;
+    for (int k0 = 0; k0 < R.cn; k0 += CAUCHY_CHUNK) {
+      const int kc = std::min(CAUCHY_CHUNK, R.cn - k0);
+      HIPCHK(cauchy_scale(pm, R.e, lam, n, nv, ns, k0, kc, ops, true, st));
+      for (int kk = 0; kk < kc; ++kk) {
+        char* o = ops + kk * opsz;
+        HIPCHK(gemm32_kmajor(n, n, nv, pm32, n, true, o, n, false, av32 + (size_t)kk * n2 * 8, n, false, 1.0, st,
+                             R.tune.wg_per_cu));
+        HIPCHK(gemm32_kmajor(n, n, P.nc, pm32 + (size_t)nv * n * 8, n, false, o + (size_t)nv * n * 8, n, false,
+                             ac32 + (size_t)kk * n2 * 8, n, false, 1.0, st, R.tune.wg_per_cu));
+      }
+      HIPCHK(cauchy_accum(av32, ac32, true, wts, k0, kc, n, at<char>(R.ws, L.csum), st));
+    }
+    HIPCHK(cauchy_finish(at<char>(R.ws, L.csum), n, P.f, m_out, negm, st));
+    return ISDF_OK;
+  }
   for (int k0 = 0; k0 < R.cn; k0 += CAUCHY_CHUNK) {
     const int kc = std::min(CAUCHY_CHUNK, R.cn - k0);
-    HIPCHK(cauchy_scale(pm, R.e, lam, n, nv, ns, k0, kc, ops, st));
+    HIPCHK(cauchy_scale(pm, R.e, lam, n, nv, ns, k0, kc, ops, false, st));
     GemmDesc a;   // Av_k(mu, nu) = sum_i conj(psi_i(mu)) ops_k[i][nu]
     a.M = a.N = n; a.K = nv;
     a.A = pm; a.sam = 1; a.sak = n; a.conjA = true;
@@ -716,7 +742,7 @@ isdf_status stage_core_cauchy(Run& R, void* m_out, void* negm, hipStream_t st) {
     c.B = ops + (size_t)nv * n * 16;
     c.C = ac;
     HIPCHK(gemm(cp, c, st));
-    HIPCHK(cauchy_accum(av, ac, wts, k0, kc, n, at<char>(R.ws, L.csum), st));
+    HIPCHK(cauchy_accum(av, ac, false, wts, k0, kc, n, at<char>(R.ws, L.csum), st));
   }
   HIPCHK(cauchy_finish(at<char>(R.ws, L.csum), n, P.f, m_out, negm, st));
   return ISDF_OK;

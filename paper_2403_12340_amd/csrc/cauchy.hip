@@ -19,9 +19,11 @@ namespace {
 
 // ops[kk][i][nu] = psi_i(r_nu) / (lambda_k - eps_i) (occupied rows) and
 //                  conj(psi_j(r_nu)) / (lambda_k - eps_j) (empty rows), k = k0 + kk
+// (T = double: complex128 out; T = float: complex64 out, for the single-precision engine)
+template <typename T>
 __global__ void cauchy_scale_kernel(const z64* __restrict__ pm, const double* __restrict__ e,
                                     const z64* __restrict__ lam, int nmu, int nv, int ns, int k0,
-                                    z64* __restrict__ ops) {
+                                    cx<T>* __restrict__ ops) {
   const int nu = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = blockIdx.y, kk = blockIdx.z;
   if (nu >= nmu) return;
@@ -31,17 +33,18 @@ __global__ void cauchy_scale_kernel(const z64* __restrict__ pm, const double* __
   const z64 inv = {dr * s, -di * s};               // 1 / (lambda - eps_n)
   z64 p = pm[(long)n * nmu + nu];
   if (n >= nv) p.im = -p.im;
-  ops[((long)kk * ns + n) * nmu + nu] = z64{p.re * inv.re - p.im * inv.im, p.re * inv.im + p.im * inv.re};
+  ops[((long)kk * ns + n) * nmu + nu] = cx<T>{(T)(p.re * inv.re - p.im * inv.im), (T)(p.re * inv.im + p.im * inv.re)};
 }
 
-// s[mu][nu] += sum_kk w_k av[kk][mu][nu] ac[kk][mu][nu], in node order
-__global__ void cauchy_accum_kernel(const z64* __restrict__ av, const z64* __restrict__ ac,
+// s[mu][nu] += sum_kk w_k av[kk][mu][nu] ac[kk][mu][nu], in node order (products stored as cx<T>)
+template <typename T>
+__global__ void cauchy_accum_kernel(const cx<T>* __restrict__ av, const cx<T>* __restrict__ ac,
                                     const z64* __restrict__ w, int k0, int kc, long n2, z64* __restrict__ s) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n2) return;
   z64 acc = s[idx];
   for (int kk = 0; kk < kc; ++kk) {
-    const z64 a = av[kk * n2 + idx], b = ac[kk * n2 + idx], wk = w[k0 + kk];
+    const z64 a = cvt<double>(av[kk * n2 + idx]), b = cvt<double>(ac[kk * n2 + idx]), wk = w[k0 + kk];
     const z64 j = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
     acc.re += wk.re * j.re - wk.im * j.im;
     acc.im += wk.re * j.im + wk.im * j.re;
@@ -66,17 +69,25 @@ __global__ void cauchy_finish_kernel(const z64* __restrict__ s, int n, double f,
 }  // namespace
 
 hipError_t cauchy_scale(const void* pm, const double* e, const void* lam, int nmu, int nv, int ns, int k0, int kc,
-                        void* ops, hipStream_t st) {
-  hipLaunchKernelGGL(cauchy_scale_kernel, dim3(cdiv(nmu, 256), ns, kc), dim3(256), 0, st, (const z64*)pm, e,
-                     (const z64*)lam, nmu, nv, ns, k0, (z64*)ops);
+                        void* ops, bool ops32, hipStream_t st) {
+  if (ops32)
+    hipLaunchKernelGGL(cauchy_scale_kernel<float>, dim3(cdiv(nmu, 256), ns, kc), dim3(256), 0, st, (const z64*)pm,
+                       e, (const z64*)lam, nmu, nv, ns, k0, (c32*)ops);
+  else
+    hipLaunchKernelGGL(cauchy_scale_kernel<double>, dim3(cdiv(nmu, 256), ns, kc), dim3(256), 0, st, (const z64*)pm,
+                       e, (const z64*)lam, nmu, nv, ns, k0, (z64*)ops);
   return hipGetLastError();
 }
 
-hipError_t cauchy_accum(const void* av, const void* ac, const void* w, int k0, int kc, int nmu, void* s,
+hipError_t cauchy_accum(const void* av, const void* ac, bool prod32, const void* w, int k0, int kc, int nmu, void* s,
                         hipStream_t st) {
   const long n2 = (long)nmu * nmu;
-  hipLaunchKernelGGL(cauchy_accum_kernel, dim3(cdiv(n2, 256)), dim3(256), 0, st, (const z64*)av, (const z64*)ac,
-                     (const z64*)w, k0, kc, n2, (z64*)s);
+  if (prod32)
+    hipLaunchKernelGGL(cauchy_accum_kernel<float>, dim3(cdiv(n2, 256)), dim3(256), 0, st, (const c32*)av,
+                       (const c32*)ac, (const z64*)w, k0, kc, n2, (z64*)s);
+  else
+    hipLaunchKernelGGL(cauchy_accum_kernel<double>, dim3(cdiv(n2, 256)), dim3(256), 0, st, (const z64*)av,
+                       (const z64*)ac, (const z64*)w, k0, kc, n2, (z64*)s);
   return hipGetLastError();
 }
 

@@ -115,11 +115,11 @@ hipError_t zpair_bf3(long nr, int nmu, int nv, int nc, const void* rows, const v
 hipError_t axpby(const void* A, double a, const void* B, double b, void* C, long count, hipStream_t st);  // z64
 
 // ----- contour-integral core (cauchy.hip), complex128 storage
-// ops[kk][n][nu] = (n < nv ? pm[n][nu] : conj(pm[n][nu])) / (lam[k0 + kk] - e[n])
+// ops[kk][n][nu] = (n < nv ? pm[n][nu] : conj(pm[n][nu])) / (lam[k0 + kk] - e[n]), complex64 if ops32
 hipError_t cauchy_scale(const void* pm, const double* e, const void* lam, int nmu, int nv, int ns, int k0, int kc,
-                        void* ops, hipStream_t st);
-// s += sum_kk w[k0 + kk] av[kk] (.) ac[kk]  (nmu x nmu, fixed node order)
-hipError_t cauchy_accum(const void* av, const void* ac, const void* w, int k0, int kc, int nmu, void* s,
+                        void* ops, bool ops32, hipStream_t st);
+// s += sum_kk w[k0 + kk] av[kk] (.) ac[kk]  (nmu x nmu, fixed node order; products complex64 if prod32)
+hipError_t cauchy_accum(const void* av, const void* ac, bool prod32, const void* w, int k0, int kc, int nmu, void* s,
                         hipStream_t st);
 // m = f / (2 pi i) (s - s^H), negm = -m (either may be null)
 hipError_t cauchy_finish(const void* s, int nmu, double f, void* m, void* negm, hipStream_t st);
