@@ -254,7 +254,8 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
                                     void* const* workspace, const size_t* ws_bytes, void* const* eps_inv);
 
 /* Launch-shape knobs of a plan (a project-written autotuner chooses them):
- *   dft_zb          z-planes per workgroup of the DFT's x/y stage, 1..64 (default 8)
+ *   dft_zb          z-planes per workgroup of the DFT, 1..64 (default 8); the fused
+ *                   x/y/z pass raises it to at least ceil(n[2] / 8)
  *   core_split_pct  split of the core M over the occupied index, percent of the
  *                   built-in choice, 25..200 (default 100)
  *   gram_split      cap on the split-K factor of X^H X, 1..16 (default 16)

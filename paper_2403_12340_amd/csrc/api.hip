@@ -234,6 +234,7 @@ struct Layout {
   // frequency batch (n_omega >= 2): weights, core partials, M / M^{-1} / K, sweep scratch, S M^{-1}, H / T
   size_t wb = 0, partb = 0, mb = 0, lb = 0, qb = 0, hb = 0;
   size_t zt_bytes = 0;               // size of the zt region
+  size_t t2_bytes = 0;               // size of the t2 region
   size_t part = 0, l2 = 0, lin2 = 0, q = 0;  // core partials; second -M buffer, sweep scratch, S M^-1 S scratch
   size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (FP32 mode only)
   size_t bf_rows = 0, bf_pts = 0;    // bf16 hi / lo planes of the orbitals (BF16x3 mode only)
@@ -281,7 +282,9 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.tabs = L.twx;
   L.s = take(nmu2 * z);
   L.lin = take(linalg_scratch_bytes(P.nmu));
-  L.t2 = take((size_t)P.nmu * P.n2 * nd * el);
+  // T2 of the separate x/y and z stages, or the fused DFT's per-z-block partial sums
+  L.t2_bytes = std::max((size_t)P.nmu * P.n2 * nd, (size_t)std::min(DFT_MAX_ZBLOCKS, P.n2) * P.nmu * P.ngg) * el;
+  L.t2 = take(L.t2_bytes);
   L.zg = take((size_t)P.nmu * P.ngg * el);
   L.u = take((size_t)P.ng * P.nmu * el);
   L.l = take(nmu2 * z);
@@ -638,8 +641,14 @@ isdf_status stage_dft(Run& R, bool scaled) {
   HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), R.st));
   HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), R.st));
   HIPCHK(dft_twiddles(ib + L.kx + L.ky, L.kz, P.n2, P.m32, at<char>(R.ws, L.twz), R.st));
+  const double* scale = scaled ? at<double>(R.ws, L.sqrtv) : nullptr;
+  if (dft_fused_fits(cp, p)) {
+    HIPCHK(dft_fused(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), L.t2_bytes, at<char>(R.ws, L.zg), scale,
+                     R.st));
+    return ISDF_OK;
+  }
   HIPCHK(dft_xy(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), R.st));
-  HIPCHK(dft_z(cp, p, at<char>(R.ws, L.t2), at<char>(R.ws, L.zg), scaled ? at<double>(R.ws, L.sqrtv) : nullptr, R.st));
+  HIPCHK(dft_z(cp, p, at<char>(R.ws, L.t2), at<char>(R.ws, L.zg), scale, R.st));
   return ISDF_OK;
 }
 
@@ -1010,6 +1019,10 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
   HIPCHK(core_partial(cp, n, P.nv, P.nc, at<char>(R.ws, L.pm), n, wb, at<char>(R.ws, L.partb), 1, R.st, nw));
   HIPCHK(core_reduce(cp, n, at<char>(R.ws, L.partb), 1, P.f, nullptr, mb, R.st, nw));      // -M(omega)
   HIPCHK(hipEventRecord(h->core0, R.st));
+  // the pair kernel goes into the main stream ahead of the side stream's sweep launches
+  HIPCHK(hipStreamWaitEvent(R.st, h->zops, 0));
+  tm.mark();
+  TRY(stage_z(R));
   HIPCHK(hipStreamWaitEvent(side, h->core0, 0));
   HIPCHK(sweep_inverse(n, mb, at<char>(R.ws, L.lb), &R.sb->status, side, nw));            // M(omega)^{-1}
   {
@@ -1031,9 +1044,6 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
     HIPCHK(gemm(P64, b, side));
   }
   HIPCHK(hipEventRecord(h->m_ready[0], side));
-  HIPCHK(hipStreamWaitEvent(R.st, h->zops, 0));
-  tm.mark();
-  TRY(stage_z(R));
   tm.mark();
   TRY(stage_dft(R, true));
   tm.mark();
@@ -1092,39 +1102,41 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   void* mbuf[2] = {at<char>(R.ws, R.L.l), at<char>(R.ws, R.L.l2)};
   // core_stream 1: the first core waits for Z on the side stream instead, beside the DFT
   const bool core_side = R.tune.core_stream == 1;
-  auto side_core = [&](int k) -> isdf_status {
-    if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
-    if (k == 0 && !core_side) {
-      TRY(stage_core(R, n_omega ? omega[0] : 0.0, nullptr, mbuf[0], R.st));
-      HIPCHK(hipEventRecord(h->core0, R.st));
-      HIPCHK(hipStreamWaitEvent(side, h->core0, 0));
-    } else if (k == 0) {
-      HIPCHK(hipStreamWaitEvent(side, h->zdone, 0));
-      TRY(stage_core(R, n_omega ? omega[0] : 0.0, nullptr, mbuf[0], side));
-    } else {
-      TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
-    }
+  // side_tail: M^{-1} and K = S M^{-1} S of frequency k on the side stream, once
+  // its core M is in mbuf
+  auto side_tail = [&](int k) -> isdf_status {
     HIPCHK(sweep_inverse(R.P.nmu, mbuf[k & 1], at<char>(R.ws, R.L.lin2), &R.sb->status, side));  // M^{-1}
     TRY(stage_smis(R, mbuf[k & 1], at<char>(R.ws, R.L.q), side));                                 // S M^{-1} S
     HIPCHK(hipEventRecord(h->m_ready[k & 1], side));
     return ISDF_OK;
+  };
+  auto side_core = [&](int k) -> isdf_status {
+    if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
+    if (k == 0) HIPCHK(hipStreamWaitEvent(side, h->zdone, 0));
+    TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
+    return side_tail(k);
   };
   TRY(stage_s(R, side, R.L.lin2, false));
   // the pair kernel's operand pass (streaming, memory-bound) beside the first core
   TRY(stage_z_operands(R, side));
   HIPCHK(hipEventRecord(h->zops, side));
   if (!core_side) {
-    TRY(side_core(0));
-    if (nw > 1) TRY(side_core(1));
+    TRY(stage_core(R, n_omega ? omega[0] : 0.0, nullptr, mbuf[0], R.st));
+    HIPCHK(hipEventRecord(h->core0, R.st));
   }
+  // The pair kernel is enqueued before the side stream's many small sweep
+  // launches, so that host-side launch latency never holds it back.
   HIPCHK(hipStreamWaitEvent(R.st, h->zops, 0));
   tm.mark();
   TRY(stage_z(R));
-  if (core_side) {
-    HIPCHK(hipEventRecord(h->zdone, R.st));
+  if (core_side) HIPCHK(hipEventRecord(h->zdone, R.st));
+  if (!core_side) {
+    HIPCHK(hipStreamWaitEvent(side, h->core0, 0));
+    TRY(side_tail(0));
+  } else {
     TRY(side_core(0));
-    if (nw > 1) TRY(side_core(1));
   }
+  if (nw > 1) TRY(side_core(1));
   tm.mark();
   TRY(stage_dft(R, true));
   tm.mark();
@@ -1657,7 +1669,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
   // coordinate descent over the knobs, each over its candidate list, keeping the best so far
   float best = 0.f;
   TRY(time_call(best));
-  const int zbs[] = {2, 4, 8, 16};
+  const int zbs[] = {4, 6, 8, 12, 16, 24};
   const int splits[] = {50, 100, 200};
   const int grams[] = {4, 8, 16};
   const int wpcs[] = {1, 2};
@@ -1675,7 +1687,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
     pl->tune.*knob = arg;
     return ISDF_OK;
   };
-  TRY(sweep(&Tune::dft_zb, zbs, 4));
+  TRY(sweep(&Tune::dft_zb, zbs, 6));
   TRY(sweep(&Tune::core_split_pct, splits, 3));
   TRY(sweep(&Tune::gram_split, grams, 3));
   TRY(sweep(&Tune::wg_per_cu, wpcs, 2));

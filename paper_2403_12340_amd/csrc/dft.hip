@@ -308,6 +308,321 @@ hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipS
   return hipGetLastError();
 }
 
+// Fused x, y and z stages for lists with at most 32 x- and y-frequencies (the
+// plane-wave spheres of the Coulomb Gram).  A workgroup of ceil(kx / 8) waves
+// walks zb consecutive z-planes of one point; wave w owns the x-frequencies
+// [8 w, 8 w + 8).  Per slab (n1 x n0, y rows, x contiguous):
+//   x stage  T1 (y x a_w)  = slab (y x x) . TWX^T (x x a_w)     rows y in 16s
+//   y stage  T2 (b x a_w)  = TWY (b x y) . T1 (y x a_w)         rows b in 16s
+// T1 goes through a region of LDS private to the wave (no workgroup barrier
+// between the stages), and T2 overwrites it in place.  After one barrier every
+// thread adds T2[b_g][a_g] twz[c_g][z] into the running sums of its plane waves
+// (ng / blockDim of them, in registers), so T2 never reaches HBM.  The sums of
+// the z-range go to `part` [zblock][mu][g]; with a single z-block they are the
+// result, scaled, in zg.  Padding rows and columns of the slab are zero (set
+// once); twiddle padding is zero, so padded terms contribute exactly zero.
+// Register budgets (slab elements and plane waves per thread) of the two
+// instantiations: up to 48^3-like shapes, and up to 64^3-like ones (FP32 only).
+constexpr int FUSED_PF_S = 12, FUSED_GPT_S = 24, FUSED_PF_L = 16, FUSED_GPT_L = 32;
+
+struct FusedShape {
+  int nw, nt, fmx, fmb, pf, gpt, zb, nzb, x2, y2, ls, la, wsz;
+  size_t lds;
+};
+
+template <typename T>
+static bool fused_shape(const DftPlan& p, FusedShape& f) {
+  if (p.kx < 1 || p.kx > 32 || p.ky < 1 || p.ky > 32 || p.kz < 1 || p.kz > 64) return false;
+  if (p.n0 > 64 || p.n1 > 64 || p.n2 > 64) return false;
+  f.nw = (p.kx + 7) / 8;
+  f.nt = 64 * f.nw;
+  f.fmx = (p.n1 + 15) / 16;
+  f.fmb = (p.ky + 15) / 16;
+  f.pf = (p.n0 * p.n1 + f.nt - 1) / f.nt;
+  f.gpt = (p.ng + f.nt - 1) / f.nt;
+  const bool large_ok = sizeof(T) == 4;
+  if (f.pf > (large_ok ? FUSED_PF_L : FUSED_PF_S) || f.gpt > (large_ok ? FUSED_GPT_L : FUSED_GPT_S)) return false;
+  f.zb = std::max(std::max(1, std::min(p.n2, p.zb)), (p.n2 + DFT_MAX_ZBLOCKS - 1) / DFT_MAX_ZBLOCKS);
+  f.nzb = (p.n2 + f.zb - 1) / f.zb;
+  f.x2 = (p.n0 + 3) & ~3;   // K extents in whole pairs of MFMA steps (zero padding)
+  f.y2 = (p.n1 + 3) & ~3;
+  f.ls = f.x2 + 1;
+  f.la = 8 * f.nw + 1;
+  f.wsz = std::max(16 * f.fmx, 32) * 9;
+  const size_t el = (size_t)16 * f.fmx * f.ls + (size_t)f.x2 * f.la + (size_t)f.y2 * 33 + (size_t)f.nw * f.wsz +
+                    (size_t)f.zb * p.kz;
+  f.lds = el * sizeof(cx<T>);
+  return f.lds <= 160 * 1024;
+}
+
+// issue order of one MFMA step: the next step's LDS reads (N + 1 of them) between
+// this step's N MFMAs
+template <int N>
+__device__ __forceinline__ void fused_interleave() {
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+  }
+  __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+}
+
+template <typename T, int PF, int GPT, int FMX>
+__global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f, const cx<T>* __restrict__ zt,
+                                                        cx<T>* __restrict__ out, const double* __restrict__ scale) {
+  static_assert(GPT % 8 == 0, "plane waves are summed in groups of 8");
+  constexpr int FMB = 2;   // b rows in two blocks of 16 (ky <= 32; zero twiddle columns beyond ky)
+  extern __shared__ unsigned char lds_raw[];
+  const int rows = 16 * FMX;
+  cx<T>* Ss = reinterpret_cast<cx<T>*>(lds_raw);   // slab [y][x], rows x ls
+  cx<T>* Xs = Ss + rows * f.ls;                     // TWX^T [x][a], x2 x la
+  cx<T>* Ys = Xs + f.x2 * f.la;                     // TWY^T [y][b], y2 x 33
+  cx<T>* Tw = Ys + f.y2 * 33;                       // per wave: T1 [y][a_w], then T2 [b][a_w]; stride 9
+  cx<T>* Zs = Tw + f.nw * f.wsz;                    // twz of this z-range [z - z0][c]
+  const int nt = f.nt, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mu = blockIdx.x / f.nzb, zi = blockIdx.x % f.nzb;
+  const int z0 = zi * f.zb, z1 = min(p.n2, z0 + f.zb);
+  const int nslab = p.n0 * p.n1;
+  const cx<T>* twx = reinterpret_cast<const cx<T>*>(p.twx);
+  const cx<T>* twy = reinterpret_cast<const cx<T>*>(p.twy);
+  const cx<T>* twz = reinterpret_cast<const cx<T>*>(p.twz);
+  const cx<T> zero{(T)0, (T)0};
+  for (int i = tid; i < rows * f.ls; i += nt) Ss[i] = zero;
+  for (int i = tid; i < f.x2 * f.la; i += nt) {
+    const int k = i / f.la, c = i % f.la;
+    Xs[i] = (k < p.n0 && c < p.kx) ? twx[c * p.n0 + k] : zero;
+  }
+  for (int i = tid; i < f.y2 * 33; i += nt) {
+    const int k = i / 33, c = i % 33;
+    Ys[i] = (k < p.n1 && c < p.ky) ? twy[c * p.n1 + k] : zero;
+  }
+  for (int i = tid; i < (z1 - z0) * p.kz; i += nt) {
+    const int zl = i / p.kz, c = i % p.kz;
+    Zs[i] = twz[c * p.n2 + z0 + zl];
+  }
+  // this thread's plane waves g = tid + nt j: T2 offset in Tw | z-frequency << 16;
+  // slots past the list hold code 0 (summed like the rest, never stored)
+  uint32_t gcode[GPT];
+  cx<T> zacc[GPT];
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) {
+    const int g = tid + nt * j;
+    zacc[j] = zero;
+    gcode[j] = 0;
+    if (g < p.ng) {
+      const int d = p.g_d[g], a = p.d_ax[d];
+      gcode[j] = (uint32_t)((a >> 3) * f.wsz + p.d_by[d] * 9 + (a & 7)) | ((uint32_t)p.g_cz[g] << 16);
+    }
+  }
+  // slab element e of this thread: i = tid + nt e at Ss[(i / n0) ls + i % n0], stepped incrementally
+  const int r0 = tid / p.n0, c0 = tid % p.n0, dr = nt / p.n0, dc = nt % p.n0;
+  T pfr[PF], pfi[PF];
+  auto fetch = [&](int z) {
+    const char* src = reinterpret_cast<const char*>(zt + ((long)mu * p.n2 + z) * nslab);
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int i = tid + nt * e;
+      const cx<T> v = *reinterpret_cast<const cx<T>*>(src + (uint32_t)(i < nslab ? i : 0) * (uint32_t)sizeof(cx<T>));
+      pfr[e] = v.re; pfi[e] = v.im;
+    }
+  };
+  if (z0 < z1) fetch(z0);
+  __syncthreads();  // Ss zeroed before any slab element lands
+  const int i16 = lane & 15, q = lane >> 4, rc = lane & 15, part = rc & 1;
+  const int bpart = ((q & 1) == (i16 & 1)) ? 0 : 1;
+  const T bsign = ((q & 1) == 1 && (i16 & 1) == 0) ? (T)-1 : (T)1;
+  const T* SsR = reinterpret_cast<const T*>(Ss);
+  const T* XsR = reinterpret_cast<const T*>(Xs);
+  const T* YsR = reinterpret_cast<const T*>(Ys);
+  T* TwR = reinterpret_cast<T*>(Tw + wave * f.wsz);
+  for (int z = z0; z < z1; ++z) {
+    {
+      int r = r0, c = c0;
+#pragma unroll
+      for (int e = 0; e < PF; ++e) {
+        if (tid + nt * e < nslab) Ss[r * f.ls + c] = cx<T>{pfr[e], pfi[e]};
+        r += dr; c += dc;
+        if (c >= p.n0) { c -= p.n0; ++r; }
+      }
+    }
+    if (z + 1 < z1) fetch(z + 1);  // next slab in flight under this slab's MFMAs
+    __syncthreads();
+    // x stage: rows y (fmx blocks of 16), columns a in [8 wave, 8 wave + 8), k = x
+    typename Mfma<T>::acc_t acc1[FMX];
+#pragma unroll
+    for (int fm = 0; fm < FMX; ++fm)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc1[fm][v] = 0;
+    {
+      // fragments of step kk + 1 are read while the MFMAs of step kk issue; the
+      // step index is clamped, so the read past the end is an in-bounds repeat
+      const int nk = f.x2 / 2, sa = 4, sb = 4 * f.la;
+      const T* ap = SsR + (i16 * f.ls + (q >> 1)) * 2 + (q & 1);
+      const T* bp = XsR + ((q >> 1) * f.la + 8 * wave + (i16 >> 1)) * 2 + bpart;
+      T a0[FMX], a1[FMX], b0, b1;
+      auto rd = [&](int kk, T (&a)[FMX], T& b) {
+        kk = min(kk, nk - 1);
+#pragma unroll
+        for (int fm = 0; fm < FMX; ++fm) a[fm] = ap[fm * 32 * f.ls + kk * sa];
+        b = bsign * bp[kk * sb];
+      };
+      rd(0, a0, b0);
+      for (int kk = 0; kk < nk; kk += 2) {   // nk is even
+        rd(kk + 1, a1, b1);
+#pragma unroll
+        for (int fm = 0; fm < FMX; ++fm) acc1[fm] = Mfma<T>::op(a0[fm], b0, acc1[fm]);
+        fused_interleave<FMX>();
+        rd(kk + 2, a0, b0);
+#pragma unroll
+        for (int fm = 0; fm < FMX; ++fm) acc1[fm] = Mfma<T>::op(a1[fm], b1, acc1[fm]);
+        fused_interleave<FMX>();
+      }
+    }
+#pragma unroll
+    for (int fm = 0; fm < FMX; ++fm)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) TwR[((16 * fm + Mfma<T>::row(lane, v)) * 9 + (rc >> 1)) * 2 + part] = acc1[fm][v];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // y stage: rows b (fmb blocks of 16), columns a of this wave, k = y
+    typename Mfma<T>::acc_t acc2[FMB];
+#pragma unroll
+    for (int fb = 0; fb < FMB; ++fb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc2[fb][v] = 0;
+    {
+      const int nk = f.y2 / 2;
+      const T* ap = YsR + ((q >> 1) * 33 + i16) * 2 + (q & 1);
+      const T* bp = TwR + ((q >> 1) * 9 + (i16 >> 1)) * 2 + bpart;
+      T a0[FMB], a1[FMB], b0, b1;
+      auto rd = [&](int kk, T (&a)[FMB], T& b) {
+        kk = min(kk, nk - 1);
+#pragma unroll
+        for (int fb = 0; fb < FMB; ++fb) a[fb] = ap[fb * 32 + kk * 4 * 33];
+        b = bsign * bp[kk * 4 * 9];
+      };
+      rd(0, a0, b0);
+      for (int kk = 0; kk < nk; kk += 2) {   // nk is even
+        rd(kk + 1, a1, b1);
+#pragma unroll
+        for (int fb = 0; fb < FMB; ++fb) acc2[fb] = Mfma<T>::op(a0[fb], b0, acc2[fb]);
+        fused_interleave<FMB>();
+        rd(kk + 2, a0, b0);
+#pragma unroll
+        for (int fb = 0; fb < FMB; ++fb) acc2[fb] = Mfma<T>::op(a1[fb], b1, acc2[fb]);
+        fused_interleave<FMB>();
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();   // every lane has read T1 before T2 overwrites it
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int fb = 0; fb < FMB; ++fb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) TwR[((16 * fb + Mfma<T>::row(lane, v)) * 9 + (rc >> 1)) * 2 + part] = acc2[fb][v];
+    __syncthreads();
+    // z stage: running sums of this thread's plane waves
+    const cx<T>* zrow = Zs + (z - z0) * p.kz;
+#pragma unroll
+    for (int j0 = 0; j0 < GPT; j0 += 8) {
+      __builtin_amdgcn_sched_barrier(0);   // bounds the LDS reads in flight (register pressure)
+#pragma unroll
+      for (int j = j0; j < j0 + 8; ++j) {
+        // opaque to the optimiser: decoded per use, not hoisted out of the slab loop as
+        // two more registers per plane wave
+        uint32_t code = gcode[j];
+        asm volatile("" : "+v"(code));
+        const cx<T> v = Tw[code & 0xffffu], w = zrow[code >> 16];
+        zacc[j].re += v.re * w.re - v.im * w.im;
+        zacc[j].im += v.re * w.im + v.im * w.re;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) {
+    if (tid + nt * j >= p.ng) continue;
+    const int g = tid + nt * j;
+    if (f.nzb == 1) {
+      const T sc = scale ? (T)scale[g] : (T)1;
+      out[(long)mu * p.ng + g] = cx<T>{zacc[j].re * sc, zacc[j].im * sc};
+    } else {
+      out[((long)zi * p.nmu + mu) * p.ng + g] = zacc[j];
+    }
+  }
+}
+
+// zg[mu][g] = scale[g] sum_zi part[zi][mu][g], z-blocks in increasing order
+template <typename T>
+__global__ void dft_zsum_kernel(const cx<T>* __restrict__ part, int nzb, int nmu, int ng,
+                                const double* __restrict__ scale, cx<T>* __restrict__ zg) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x, mu = blockIdx.y;
+  if (g >= ng) return;
+  T re = 0, im = 0;
+  for (int zi = 0; zi < nzb; ++zi) {
+    const cx<T> v = part[((long)zi * nmu + mu) * ng + g];
+    re += v.re;
+    im += v.im;
+  }
+  const T sc = scale ? (T)scale[g] : (T)1;
+  zg[(long)mu * ng + g] = cx<T>{re * sc, im * sc};
+}
+
+template <typename T, int PF, int GPT, int FMX>
+static void fused_kernel_launch(const DftPlan& p, const FusedShape& f, const void* zt, void* out,
+                                const double* scale, hipStream_t st) {
+  static bool attr_set[64] = {};  // once per device, outside any later stream capture
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64 || !attr_set[dev]) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_fused_kernel<T, PF, GPT, FMX>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (dev >= 0 && dev < 64) attr_set[dev] = true;
+  }
+  hipLaunchKernelGGL((dft_fused_kernel<T, PF, GPT, FMX>), dim3((unsigned)(p.nmu * f.nzb)), dim3(f.nt), f.lds, st,
+                     p, f, (const cx<T>*)zt, (cx<T>*)out, scale);
+}
+
+template <typename T, int PF, int GPT>
+static void fused_dispatch(const DftPlan& p, const FusedShape& f, const void* zt, void* out, const double* scale,
+                           hipStream_t st) {
+  switch (f.fmx) {
+    case 1: fused_kernel_launch<T, PF, GPT, 1>(p, f, zt, out, scale, st); break;
+    case 2: fused_kernel_launch<T, PF, GPT, 2>(p, f, zt, out, scale, st); break;
+    case 3: fused_kernel_launch<T, PF, GPT, 3>(p, f, zt, out, scale, st); break;
+    default: fused_kernel_launch<T, PF, GPT, 4>(p, f, zt, out, scale, st); break;
+  }
+}
+
+template <typename T>
+static hipError_t fused_launch(const DftPlan& p, const void* zt, void* part, size_t part_bytes, void* zg,
+                               const double* scale, hipStream_t st) {
+  FusedShape f;
+  if (!fused_shape<T>(p, f)) return hipErrorNotSupported;
+  if (f.nzb > 1 && (size_t)f.nzb * p.nmu * p.ng * sizeof(cx<T>) > part_bytes) return hipErrorNotSupported;
+  void* out = f.nzb == 1 ? zg : part;
+  const double* sc = f.nzb == 1 ? scale : nullptr;
+  if (f.pf <= FUSED_PF_S && f.gpt <= FUSED_GPT_S) fused_dispatch<T, FUSED_PF_S, FUSED_GPT_S>(p, f, zt, out, sc, st);
+  else fused_dispatch<float, FUSED_PF_L, FUSED_GPT_L>(p, f, zt, out, sc, st);   // FP32 only (fused_shape)
+  if (f.nzb == 1) return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dft_zsum_kernel<T>, dim3(cdiv(p.ng, 256), p.nmu), dim3(256), 0, st, (const cx<T>*)part, f.nzb,
+                     p.nmu, p.ng, scale, (cx<T>*)zg);
+  return hipGetLastError();
+}
+
+bool dft_fused_fits(Prec compute, const DftPlan& p) {
+  FusedShape f;
+  return compute == P64 ? fused_shape<double>(p, f) : fused_shape<float>(p, f);
+}
+
+hipError_t dft_fused(Prec compute, const DftPlan& p, const void* zt, void* part, size_t part_bytes, void* zg,
+                     const double* scale, hipStream_t st) {
+  if (compute == P64) return fused_launch<double>(p, zt, part, part_bytes, zg, scale, st);
+  return fused_launch<float>(p, zt, part, part_bytes, zg, scale, st);
+}
+
 // z stage: zg[mu][g] = scale[g] sum_z t2[mu][d_g][z] twz[c_g][z], one thread per
 // (plane wave, point).  Threads take the plane waves in (x, y)-pair order, so the
 // ~NG/nd neighbours that share a pair read the same z-line (few distinct cache

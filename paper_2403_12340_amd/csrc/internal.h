@@ -92,6 +92,14 @@ struct DftPlan {
 };
 // zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][nd][n2] -> zg: [nmu][ng] (times scale[g] if given)
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);
+// All three stages in one pass (kx, ky <= 32 and few plane waves per thread):
+// zt -> zg (times scale[g] if given) with per-z-block partial sums in `part`
+// (at most DFT_MAX_ZBLOCKS x nmu x ng elements).  hipErrorNotSupported when the
+// shape or `part_bytes` does not fit (the caller then runs dft_xy + dft_z).
+constexpr int DFT_MAX_ZBLOCKS = 8;
+bool dft_fused_fits(Prec compute, const DftPlan& p);
+hipError_t dft_fused(Prec compute, const DftPlan& p, const void* zt, void* part, size_t part_bytes, void* zg,
+                     const double* scale, hipStream_t st);
 hipError_t dft_z(Prec compute, const DftPlan& p, const void* t2, void* zg, const double* scale,
                  hipStream_t st);
 bool dft_supported(int n0, int n1, int n2, int kx, int ky, Prec compute);  // LDS fits

@@ -548,7 +548,7 @@ def test_plan_autotune():
     psi, e = dev(inp.psi_t), dev(inp.energies)
     ws, out = plan.new_workspace(), plan.new_output()
     t = plan.autotune(psi, e, out, ws, reps=2)
-    assert t["dft_zb"] in (2, 4, 8, 16) and t["core_split_pct"] in (50, 100, 200)
+    assert t["dft_zb"] in (4, 6, 8, 12, 16, 24) and t["core_split_pct"] in (50, 100, 200)
     assert t["gram_split"] in (4, 8, 16) and t["wg_per_cu"] in (1, 2) and t["best_ms"] > 0
     assert t["core_stream"] in (0, 1)
     assert plan.get_tune()["dft_zb"] == t["dft_zb"]
