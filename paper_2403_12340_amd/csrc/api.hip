@@ -303,7 +303,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
     L.wb = take(nb * P.nv * P.nc * 8);
     L.partb = take(nb * nmu2 * el);
     L.mb = take(nb * nmu2 * z);
-    L.lb = take(nb * nmu2 * z);
+    L.lb = take(nb * linalg_scratch_bytes(P.nmu));
     L.qb = take(nb * nmu2 * z);
     L.hb = take(nb * nmu2 * z);
   }
@@ -768,6 +768,12 @@ isdf_status stage_core(Run& R, double omega, void* m_out, void* negm, hipStream_
   double* w = at<double>(R.ws, R.L.w);
   HIPCHK(pair_weights(R.e, P.nv, P.nc, omega, w, st));
   void* part = at<char>(R.ws, R.L.part);
+  if (cp == P32 && core32_fits(P.nmu, P.nc)) {
+    const int ns = core32_splits(P.nmu, P.nv, R.L.nsplit);
+    HIPCHK(core32_partial(P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), w, part, ns, st));
+    HIPCHK(core_reduce(cp, P.nmu, part, ns, P.f, m_out, negm, st));
+    return ISDF_OK;
+  }
   const int ns = std::max(1, std::min(R.L.nsplit, core_splits(P.nmu, P.nv) * R.tune.core_split_pct / 100));
   HIPCHK(core_partial(cp, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), P.nmu, w, part, ns, st));
   HIPCHK(core_reduce(cp, P.nmu, part, ns, P.f, m_out, negm, st));
@@ -1016,7 +1022,10 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
   for (int k = 0; k < nw; ++k)
     HIPCHK(pair_weights(R.e, P.nv, P.nc, omega[k], wb + (long)k * P.nv * P.nc, R.st));
   void* mb = at<char>(R.ws, L.mb);
-  HIPCHK(core_partial(cp, n, P.nv, P.nc, at<char>(R.ws, L.pm), n, wb, at<char>(R.ws, L.partb), 1, R.st, nw));
+  if (cp == P32 && core32_fits(n, P.nc))
+    HIPCHK(core32_partial(n, P.nv, P.nc, at<char>(R.ws, L.pm), wb, at<char>(R.ws, L.partb), 1, R.st, nw));
+  else
+    HIPCHK(core_partial(cp, n, P.nv, P.nc, at<char>(R.ws, L.pm), n, wb, at<char>(R.ws, L.partb), 1, R.st, nw));
   HIPCHK(core_reduce(cp, n, at<char>(R.ws, L.partb), 1, P.f, nullptr, mb, R.st, nw));      // -M(omega)
   HIPCHK(hipEventRecord(h->core0, R.st));
   // the pair kernel goes into the main stream ahead of the side stream's sweep launches

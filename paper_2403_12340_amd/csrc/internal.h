@@ -52,6 +52,12 @@ hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, lon
 //   M(mu, nu) = sum_{i, j} conj(a_i(mu)) b_j(mu) w_ij a_i(nu) conj(b_j(nu))
 // pm: [ns][ldp] complex128; w: [nv][nc] double; part: nsplit x nmu x nmu complex (f64 or f32 per compute)
 int core_splits(int nmu, int nv);
+// Single-precision core on the k-major engine (core32.hip): FP64 point samples in,
+// complex64 partial sums out (as core_partial); needs nmu % 128 == 0, nc % 32 == 0.
+bool core32_fits(int nmu, int nc);
+int core32_splits(int nmu, int nv, int max_split);
+hipError_t core32_partial(int nmu, int nv, int nc, const void* pm, const double* w, void* part, int nsplit,
+                          hipStream_t st, int batch = 1);
 // batch > 1: w holds batch weight sets [b][nv * nc], part [b][nsplit][nmu * nmu]
 hipError_t core_partial(Prec compute, int nmu, int nv, int nc, const void* pm, long ldp,
                         const double* w, void* part, int nsplit, hipStream_t st, int batch = 1);

@@ -37,37 +37,11 @@ __device__ __forceinline__ double drcp(double x) {
 // broadcast and one barrier per pivot.
 typedef Tile<double, NB, 64, NB, 2, 2> TP;   // P (NB x NB, k-major in W) times a NB x 64 panel
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_panel_kernel(int n, const z64* __restrict__ ain,
-                                                          z64* __restrict__ aout, int k0, int kn,
-                                                          int* status) {
-  ain += (long)blockIdx.y * n * n;   // batch item
-  aout += (long)blockIdx.y * n * n;
-  __shared__ z64 W[NB][NB + 1];      // W[u][t] = P[t][u]: the k-major A operand of P (.)
-  __shared__ z64 rowb[2][NB];        // pivot row broadcast, double-buffered
-  __shared__ z64 Bs[NB * (64 + 1)];  // pivot rows at this block's columns, then R
-  const int c0 = blockIdx.x * 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // pivot block first: Gauss-Jordan waits only for these loads.
-  // Thread owns column gj of rows gr + 8 e (identity padding beyond kn).
-  constexpr int EW = NB * NB / 256;
-  const int gj = tid % NB, gr = tid / NB;
-  z64 w[EW];
-#pragma unroll
-  for (int e = 0; e < EW; ++e) {
-    const int r = gr + 8 * e;
-    const bool ok = r < kn && gj < kn;
-    const z64 v = ain[ok ? (long)(k0 + r) * n + k0 + gj : 0];
-    w[e] = ok ? v : z64{r == gj ? 1.0 : 0.0, 0.0};
-  }
-  // raw pivot rows at this block's columns, kept in registers until the inversion is done
-  constexpr int EB = NB * 64 / 256;
-  z64 braw[EB];
-#pragma unroll
-  for (int e = 0; e < EB; ++e) {
-    const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
-    const bool ok = t < kn && c0 + c < n;
-    braw[e] = ain[ok ? (long)(k0 + t) * n + c0 + c : 0];
-  }
+// Gauss-Jordan inversion of the NB x NB pivot block held as w[e] = B[gr + 8 e][gj]
+// by 256 threads (identity padding beyond the block); returns whether a pivot was
+// not positive and finite.  One row broadcast through rowb and one barrier per pivot.
+constexpr int EW = NB * NB / 256;
+__device__ __forceinline__ bool pivot_gj(z64 (&w)[EW], z64 (*rowb)[NB], int gj, int gr) {
   bool bad_any = false;
 #pragma unroll
   for (int p = 0; p < NB; ++p) {
@@ -91,6 +65,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
       const bool own = (r == p);
       w[e] = z64{own ? rj.re : br - x.re, own ? rj.im : bi - x.im};
     }
+  }
+  return bad_any;
+}
+
+// pin: P of this step (W layout, P[t][u] at pin[u NB + t]) when the previous
+// update launch computed it, else null (the panel inverts the block itself)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_panel_kernel(int n, const z64* __restrict__ ain,
+                                                          z64* __restrict__ aout, int k0, int kn,
+                                                          const z64* __restrict__ pin, int* status) {
+  ain += (long)blockIdx.y * n * n;   // batch item
+  aout += (long)blockIdx.y * n * n;
+  __shared__ z64 W[NB][NB + 1];      // W[u][t] = P[t][u]: the k-major A operand of P (.)
+  __shared__ z64 rowb[2][NB];        // pivot row broadcast, double-buffered
+  __shared__ z64 Bs[NB * (64 + 1)];  // pivot rows at this block's columns, then R
+  const int c0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // pivot block first: Gauss-Jordan waits only for these loads.
+  // Thread owns column gj of rows gr + 8 e (identity padding beyond kn).
+  const int gj = tid % NB, gr = tid / NB;
+  if (pin) pin += (long)blockIdx.y * NB * NB;
+  z64 w[EW];
+  if (!pin) {
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+      const int r = gr + 8 * e;
+      const bool ok = r < kn && gj < kn;
+      const z64 v = ain[ok ? (long)(k0 + r) * n + k0 + gj : 0];
+      w[e] = ok ? v : z64{r == gj ? 1.0 : 0.0, 0.0};
+    }
+  }
+  // raw pivot rows at this block's columns, kept in registers until the inversion is done
+  constexpr int EB = NB * 64 / 256;
+  z64 braw[EB];
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
+    const bool ok = t < kn && c0 + c < n;
+    braw[e] = ain[ok ? (long)(k0 + t) * n + c0 + c : 0];
+  }
+  bool bad_any = false;
+  if (pin) {
+    // P precomputed by the previous step's update launch
+#pragma unroll
+    for (int e = 0; e < EW; ++e) w[e] = pin[gj * NB + gr + 8 * e];
+  } else {
+    bad_any = pivot_gj(w, rowb, gj, gr);
   }
   if (bad_any && tid == 0 && blockIdx.x == 0) atomicOr(status, 1);
 #pragma unroll
@@ -140,15 +160,80 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
 // Rank-kn update of every element outside the pivot rows and columns.
 typedef Tile<double, 64, 32, 16, 2, 2> TU;
 
+// With pout set, one more workgroup (the last) looks ahead: it forms the next
+// pivot block k1 of A' (kn1 wide) from the same formula, inverts it by
+// Gauss-Jordan while the others update, and stores P for the next panel launch,
+// so that the serial inversion is off the critical path of every step but the first.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_update_kernel(int n, const z64* __restrict__ ain,
                                                            z64* __restrict__ aout, int k0, int kn,
-                                                           int ntm, int total) {
+                                                           int ntm, int total, z64* __restrict__ pout,
+                                                           int k1, int kn1, int* status) {
   __shared__ z64 As[TU::AS];  // [t][i] = conj(A[k0 + t][m0 + i])
   __shared__ z64 Bs[TU::BS];  // [t][j] = R[t][n0 + j] (the pivot rows of A')
-  const int id = xcd_remap(blockIdx.x, total);
-  if (id >= total) return;
   ain += (long)blockIdx.y * n * n;   // batch item
   aout += (long)blockIdx.y * n * n;
+  if (pout && blockIdx.x == gridDim.x - 1) {
+    pout += (long)blockIdx.y * NB * NB;
+    const int tid = threadIdx.x, gj = tid % NB, gr = tid / NB;
+    const bool colok = gj < kn1;
+    // sum_t conj(A[k0 + t][k1 + r]) R[t][k1 + gj], t in halves of 16 staged in LDS:
+    // As[t][r] = A[k0 + t][k1 + r], Bs[t][u] = R[t][k1 + u] (stride 33; zero beyond the blocks)
+    static_assert(TU::AS >= 16 * 33 && TU::BS >= 16 * 33, "look-ahead staging fits the tile buffers");
+    z64 vold[EW];
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+      const int r = gr + 8 * e;
+      vold[e] = ain[r < kn1 && colok ? (long)(k1 + r) * n + k1 + gj : 0];
+    }
+    z64 acc[EW];
+#pragma unroll
+    for (int e = 0; e < EW; ++e) acc[e] = z64{0.0, 0.0};
+    for (int t0 = 0; t0 < kn; t0 += 16) {
+      z64 sa[2], sb[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {   // element (t, c) = (idx / 32, idx % 32), idx = tid + 256 h
+        const int idx = tid + 256 * h, t = idx >> 5, c = idx & 31;
+        const bool tok = t0 + t < kn && c < kn1;
+        sa[h] = ain[tok ? (long)(k0 + t0 + t) * n + k1 + c : 0];
+        sb[h] = aout[tok ? (long)(k0 + t0 + t) * n + k1 + c : 0];
+        if (!tok) sa[h] = sb[h] = z64{0.0, 0.0};
+      }
+      __syncthreads();   // the previous half has been read
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int idx = tid + 256 * h, t = idx >> 5, c = idx & 31;
+        As[t * 33 + c] = sa[h];
+        Bs[t * 33 + c] = sb[h];
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int t = 0; t < 16; ++t) {
+        const z64 rv = Bs[t * 33 + gj];
+#pragma unroll
+        for (int e = 0; e < EW; ++e) {
+          const z64 x = cmulc(As[t * 33 + gr + 8 * e], rv);
+          acc[e].re += x.re;
+          acc[e].im += x.im;
+        }
+      }
+    }
+    __syncthreads();   // As is reused as the pivot-row broadcast
+    z64 w[EW];
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+      const int r = gr + 8 * e;
+      const bool ok = r < kn1 && colok;
+      w[e] = ok ? z64{vold[e].re - acc[e].re, vold[e].im - acc[e].im} : z64{r == gj ? 1.0 : 0.0, 0.0};
+    }
+    z64 (*rowb)[NB] = reinterpret_cast<z64 (*)[NB]>(As);
+    const bool bad = pivot_gj(w, rowb, gj, gr);
+    if (bad && tid == 0) atomicOr(status, 1);
+#pragma unroll
+    for (int e = 0; e < EW; ++e) pout[gj * NB + gr + 8 * e] = w[e];
+    return;
+  }
+  const int id = xcd_remap(blockIdx.x, total);
+  if (id >= total) return;
   const int bm = id % ntm, bn = id / ntm;
   const int m0 = bm * TU::BM, n0 = bn * TU::BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -200,7 +285,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
       }
 }
 
-size_t linalg_scratch_bytes(int n) { return (size_t)n * n * sizeof(z64); }
+// ping-pong copy of the matrix, then the look-ahead pivot inverse
+size_t linalg_scratch_bytes(int n) { return ((size_t)n * n + NB * NB) * sizeof(z64); }
 
 hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch) {
   z64* bufs[2] = {(z64*)a, (z64*)scratch};
@@ -208,15 +294,19 @@ hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t
   const int ntm = (n + TU::BM - 1) / TU::BM, ntn = (n + TU::BN - 1) / TU::BN;
   const int total = ntm * ntn;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
+  z64* pbuf = (z64*)scratch + (long)batch * n * n;   // look-ahead P, one block per batch item
   int cur = 0;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kn = min(NB, n - k0);
     hipLaunchKernelGGL(sweep_panel_kernel, dim3(npb, batch), dim3(256), 0, st, n, (const z64*)bufs[cur],
-                       bufs[cur ^ 1], k0, kn, status);
+                       bufs[cur ^ 1], k0, kn, k0 > 0 ? (const z64*)pbuf : nullptr, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sweep_update_kernel, dim3(grid, batch), dim3(256), 0, st, n, (const z64*)bufs[cur],
-                       bufs[cur ^ 1], k0, kn, ntm, total);
+    const int k1 = k0 + NB, kn1 = min(NB, n - k1);
+    const bool ahead = k1 < n;
+    hipLaunchKernelGGL(sweep_update_kernel, dim3(grid + (ahead ? 1 : 0), batch), dim3(256), 0, st, n,
+                       (const z64*)bufs[cur], bufs[cur ^ 1], k0, kn, ntm, total, ahead ? pbuf : nullptr, k1, kn1,
+                       status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;

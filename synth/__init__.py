@@ -57,6 +57,9 @@ CONFIGS = {
     "tiles": dict(n=22, nv=16, nc=48, nmu=200, ng=600, complex=True, seed=10),
     # Full tiles everywhere (points and plane waves multiples of 128): the interior fast paths.
     "kmaj": dict(n=20, nv=16, nc=48, nmu=256, ng=512, complex=True, seed=11),
+    # Points a multiple of 128 and Nc a multiple of 32: the single-precision core on the
+    # k-major engine (one occupied state per split).
+    "core32": dict(n=20, nv=12, nc=64, nmu=256, ng=400, complex=True, seed=13),
     # Uneven systems batched with the 48^3 one (Nc = 4 Nv, N_mu = 10 Nv, NG = 32 Nv).
     **{f"batch{i}": dict(n=n, nv=nv, nc=4 * nv, nmu=10 * nv, ng=32 * nv, complex=True, seed=30 + i)
        for i, (n, nv) in enumerate(zip((24, 25, 27, 28, 30, 32, 36, 40), (16, 20, 24, 28, 32, 40, 44, 48)))},
