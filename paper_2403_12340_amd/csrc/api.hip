@@ -855,11 +855,13 @@ isdf_status stage_out(Run& R, const Basis& b, void* out, Timer& tm) {
     void* t32 = at<char>(R.ws, L.rres);
     void* wt = at<char>(R.ws, L.w1);
     HIPCHK(convert_z(R.tmat, false, t32, true, (long)P.nmu * P.nmu, R.st));
+    // the t2 region (DFT scratch, consumed by now) holds the K slices of the split tails
+    void* tail = at<char>(R.ws, L.t2);
     HIPCHK(gemm32_kmajor(P.nmu, P.ng, P.nmu, t32, P.nmu, false, b.base, b.smu, false, wt, P.ng, false,
-                         R.talpha, R.st, R.tune.wg_per_cu));
+                         R.talpha, R.st, R.tune.wg_per_cu, tail, L.t2_bytes));
     tm.mark();
     HIPCHK(gemm32_kmajor(P.ng, P.ng, P.nmu, wt, P.ng, false, b.base, b.smu, true, out, P.ng, true, -1.0, R.st,
-                         R.tune.wg_per_cu));
+                         R.tune.wg_per_cu, tail, L.t2_bytes));
     return ISDF_OK;
   }
   GemmDesc d;  // W1 = B T

@@ -8,6 +8,11 @@
 // prefetches the next tile's first K tile under the current epilogue.  Only
 // full tiles are handled here (M % 128 = N % 64 = K % 16 = 0); the caller keeps
 // the general GEMM for anything else.
+//
+// Tail split: when a share does not fill whole rounds, its leftover tiles are
+// cut along K so that every workgroup of the XCD takes one slice (given scratch
+// for the slices); gemm32_tail_kernel then adds the slices in a fixed order and
+// applies the epilogue, so the last round is as full as the others.
 #include "internal.h"
 #include "kmajor.h"
 
@@ -26,37 +31,62 @@ __device__ __forceinline__ void herm_tile(int id, int& bm, int& bn) {
   bn = id - r * (r + 1);
 }
 
+// Full rounds and split tail of one XCD's share of `total` tiles (nper workgroups
+// per XCD, nt K tiles): tiles [lo, lo + nfull) run whole, the ntail after them are
+// cut into `split` K slices each (split = 1: no tail).
+struct TailPlan {
+  int lo, nfull, ntail, split;
+};
+__host__ __device__ inline TailPlan tail_plan(int xcd, int total, int nper, int nt, bool allow) {
+  const int per = (total + 7) / 8;
+  const int lo = xcd * per, hi = total < lo + per ? total : lo + per;
+  const int cnt = hi > lo ? hi - lo : 0;
+  TailPlan t{lo, cnt, 0, 1};
+  if (!allow || nper < 2) return t;
+  const int rounds = cnt / nper, rest = cnt - rounds * nper;
+  if (rest == 0) return t;
+  int sp = nper / rest;
+  if (sp > nt) sp = nt;
+  if (sp < 2) return t;
+  t.nfull = rounds * nper;
+  t.ntail = rest;
+  t.split = sp;
+  return t;
+}
+
+template <bool HERM>
+__device__ __forceinline__ void tile_origin(int id, int ntj, int& m0, int& n0) {
+  int bm, bn;
+  if (HERM) herm_tile(id, bm, bn);
+  else { bm = id / ntj; bn = id % ntj; }
+  m0 = bm * ZL::BM;
+  n0 = bn * ZL::BN;
+}
+
 template <bool HERM>
 __global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(3)))
 void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, const c32* B, long ldb,
-                   float sb, void* C, long ldc, float alpha) {
+                   float sb, void* C, long ldc, float alpha, float* tail_ws) {
   __shared__ float smem[2 * (ZL::AS + ZL::BS)];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave % ZL::WGM) * ZL::WTM, wn0 = (wave / ZL::WGM) * ZL::WTN;
   const int xcd = blockIdx.x % 8, nper = gridDim.x / 8, j = blockIdx.x / 8;
-  const int per = (total + 7) / 8;
-  const int lo = xcd * per, hi = min(total, lo + per);
   const int nt = K / ZL::BK;
-  auto origin = [&](int id, int& m0, int& n0) {
-    int bm, bn;
-    if (HERM) herm_tile(id, bm, bn);
-    else { bm = id / ntj; bn = id % ntj; }
-    m0 = bm * ZL::BM;
-    n0 = bn * ZL::BN;
-  };
+  const TailPlan tp = tail_plan(xcd, total, nper, nt, tail_ws != nullptr);
+  const int lo = tp.lo, hi = tp.lo + tp.nfull;
   ZFetch zf;
   zf.init(tid, lda, ldb);
   if (lo + j < hi) {
     int m0, n0;
-    origin(lo + j, m0, n0);
+    tile_origin<HERM>(lo + j, ntj, m0, n0);
     zf.fetch(A, lda, B, ldb, m0, n0, 0);
   }
   const int rc = lane & 15, part = rc & 1;
   for (int id = lo + j; id < hi; id += nper) {
     int m0, n0, nm0 = 0, nn0 = 0;
-    origin(id, m0, n0);
+    tile_origin<HERM>(id, ntj, m0, n0);
     const bool has_next = id + nper < hi;
-    if (has_next) origin(id + nper, nm0, nn0);
+    if (has_next) tile_origin<HERM>(id + nper, ntj, nm0, nn0);
     f4 acc[ZL::FM][ZL::FN];
 #pragma unroll
     for (int fm = 0; fm < ZL::FM; ++fm)
@@ -108,6 +138,74 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
     }
     __syncthreads();   // the next tile stages into the same LDS
   }
+  // one K slice of a leftover tile: raw partial sum to the scratch, [row][column] complex64
+  if (tp.ntail > 0 && j < tp.ntail * tp.split) {
+    const int tt = j / tp.split, ks = j % tp.split;
+    int m0, n0;
+    tile_origin<HERM>(hi + tt, ntj, m0, n0);
+    const int t0 = ks * nt / tp.split, t1 = (ks + 1) * nt / tp.split;
+    const c32* As = A + (long)t0 * ZL::BK * lda;
+    const c32* Bs = B + (long)t0 * ZL::BK * ldb;
+    f4 acc[ZL::FM][ZL::FN];
+#pragma unroll
+    for (int fm = 0; fm < ZL::FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
+    zf.fetch(As, lda, Bs, ldb, m0, n0, 0);
+    zl_loop_full(smem, zf, t1 - t0, t1 - t0, sa, sb, As, lda, Bs, ldb, m0, n0, false, 0, 0, acc, acc, wm0, wn0,
+                 lane);
+    float* ws = tail_ws + (size_t)(xcd * nper + j) * ZL::BM * ZL::BN * 2;
+#pragma unroll
+    for (int fm = 0; fm < ZL::FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < ZL::FN; ++fn)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = wm0 + fm * 16 + Mfma<float>::row(lane, v);
+          const int c = wn0 + fn * 8 + (rc >> 1);
+          ws[(r * ZL::BN + c) * 2 + part] = acc[fm][fn][v];
+        }
+  }
+}
+
+// Leftover tiles of the split tail: workgroup (xcd, t) adds the K slices of that
+// XCD's tail tile t in slice order, scales by alpha and writes the tile as the
+// main kernel's epilogue would.
+template <bool HERM>
+__global__ __launch_bounds__(256) void gemm32_tail_kernel(int ntj, int total, int nper, int nt, const float* tail_ws,
+                                                          void* C, long ldc, float alpha) {
+  const int xcd = blockIdx.x, t = blockIdx.y;
+  const TailPlan tp = tail_plan(xcd, total, nper, nt, true);
+  if (t >= tp.ntail) return;
+  int m0, n0;
+  tile_origin<HERM>(tp.lo + tp.nfull + t, ntj, m0, n0);
+  const size_t unit = (size_t)ZL::BM * ZL::BN * 2;
+  const float* ws = tail_ws + (size_t)(xcd * nper + t * tp.split) * unit;
+  for (int e = threadIdx.x; e < ZL::BM * ZL::BN; e += blockDim.x) {
+    float re = 0.f, im = 0.f;
+    for (int ks = 0; ks < tp.split; ++ks) {
+      re += ws[ks * unit + 2 * e];
+      im += ws[ks * unit + 2 * e + 1];
+    }
+    re *= alpha;
+    im *= alpha;
+    const int r = e / ZL::BN, c = e % ZL::BN, gr = m0 + r, gc = n0 + c;
+    if (!HERM) {
+      reinterpret_cast<float2*>(C)[(long)gr * ldc + gc] = float2{re, im};
+      continue;
+    }
+    double* o = reinterpret_cast<double*>(C);
+    if (gr < gc) continue;
+    *reinterpret_cast<double2*>(o + ((long)gr * ldc + gc) * 2) =
+        gr == gc ? double2{1.0 + (double)re, 0.0} : double2{(double)re, (double)im};
+    if (gr > gc) *reinterpret_cast<double2*>(o + ((long)gc * ldc + gr) * 2) = double2{(double)re, -(double)im};
+  }
+}
+
+size_t gemm32_tail_bytes(int wg_per_cu) {
+  const int wpc = std::max(1, std::min(wg_per_cu, 4));
+  const int g = 8 * ((wpc * cu_count() + 7) / 8);
+  return (size_t)g * ZL::BM * ZL::BN * 2 * sizeof(float);
 }
 
 bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, long ldb) {
@@ -118,7 +216,7 @@ bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, lo
 
 hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conjA, const void* B, long ldb,
                          bool conjB, void* C, long ldc, bool herm_identity, double alpha, hipStream_t st,
-                         int wg_per_cu) {
+                         int wg_per_cu, void* tail_ws, size_t tail_bytes) {
   if (!gemm32_fits(M, N, K, A, lda, B, ldb) || (herm_identity && M != N)) return hipErrorNotSupported;
   const int nti = M / ZL::BM, ntj = N / ZL::BN;
   const int total = herm_identity ? nti * (nti + 1) : nti * ntj;
@@ -126,12 +224,27 @@ hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conj
   const int wpc = std::max(1, std::min(wg_per_cu, 4));
   const int g = std::max(8, std::min(8 * ((wpc * cu_count() + 7) / 8), 8 * (int)cdiv(total, 8)));
   const float sa = conjA ? -1.f : 1.f, sb = conjB ? -1.f : 1.f;
+  const int nper = g / 8, nt = K / ZL::BK;
+  // the split tail only with scratch for every workgroup's slice
+  const size_t need = (size_t)g * ZL::BM * ZL::BN * 2 * sizeof(float);
+  float* ws = (tail_ws && tail_bytes >= need) ? (float*)tail_ws : nullptr;
+  bool any_tail = false;
+  for (int x = 0; ws && x < 8; ++x) any_tail |= tail_plan(x, total, nper, nt, true).ntail > 0;
+  if (!any_tail) ws = nullptr;
   if (herm_identity)
     hipLaunchKernelGGL(gemm32_kernel<true>, dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A, lda, sa,
-                       (const c32*)B, ldb, sb, C, ldc, (float)alpha);
+                       (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
   else
     hipLaunchKernelGGL(gemm32_kernel<false>, dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A, lda, sa,
-                       (const c32*)B, ldb, sb, C, ldc, (float)alpha);
+                       (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !ws) return e;
+  if (herm_identity)
+    hipLaunchKernelGGL(gemm32_tail_kernel<true>, dim3(8, nper), dim3(256), 0, st, ntj, total, nper, nt, ws, C, ldc,
+                       (float)alpha);
+  else
+    hipLaunchKernelGGL(gemm32_tail_kernel<false>, dim3(8, nper), dim3(256), 0, st, ntj, total, nper, nt, ws, C,
+                       ldc, (float)alpha);
   return hipGetLastError();
 }
 

@@ -60,6 +60,9 @@ CONFIGS = {
     # Points a multiple of 128 and Nc a multiple of 32: the single-precision core on the
     # k-major engine (one occupied state per split).
     "core32": dict(n=20, nv=12, nc=64, nmu=256, ng=400, complex=True, seed=13),
+    # 2048 plane waves on full tiles: 272 Hermitian output tiles, so the output
+    # product's last round is cut along K (split tail).
+    "tail": dict(n=20, nv=16, nc=48, nmu=256, ng=2048, complex=True, seed=14),
     # Uneven systems batched with the 48^3 one (Nc = 4 Nv, N_mu = 10 Nv, NG = 32 Nv).
     **{f"batch{i}": dict(n=n, nv=nv, nc=4 * nv, nmu=10 * nv, ng=32 * nv, complex=True, seed=30 + i)
        for i, (n, nv) in enumerate(zip((24, 25, 27, 28, 30, 32, 36, 40), (16, 20, 24, 28, 32, 40, 44, 48)))},
