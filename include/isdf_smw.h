@@ -263,7 +263,8 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
  *                   (default 1)
  *   core_stream     where the first frequency's core M runs: 0 on the caller's stream
  *                   before the pair kernel (default), 1 on the library's second stream
- *                   after it, beside the DFT and X^H X
+ *                   after it, beside the DFT and X^H X, 2 on the second stream right
+ *                   after the pair kernel's operand pass, beside the pair kernel
  *   best_ms         output of isdf_plan_autotune: time of one call with the chosen knobs */
 typedef struct {
   int32_t dft_zb;

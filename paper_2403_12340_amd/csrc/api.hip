@@ -496,7 +496,7 @@ struct Tune {
   int core_split_pct = 100;  // core split count, percent of the default
   int gram_split = 16;     // split-K cap of X^H X
   int wg_per_cu = 1;       // workgroups per CU of the persistent k-major kernels
-  int core_stream = 0;     // first core: 0 main stream before Z, 1 side stream after Z
+  int core_stream = 0;     // first core: 0 main stream before Z, 1 side stream after Z, 2 side stream beside Z
 };
 
 struct Run {
@@ -1111,8 +1111,10 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
   const int nw = std::max(n_omega, 1);
   void* mbuf[2] = {at<char>(R.ws, R.L.l), at<char>(R.ws, R.L.l2)};
-  // core_stream 1: the first core waits for Z on the side stream instead, beside the DFT
-  const bool core_side = R.tune.core_stream == 1;
+  // core_stream 1: the first core waits for Z on the side stream instead, beside the DFT;
+  // 2: on the side stream right after the operand pass, beside Z
+  const bool core_side = R.tune.core_stream != 0;
+  const bool core_beside_z = R.tune.core_stream == 2;
   // side_tail: M^{-1} and K = S M^{-1} S of frequency k on the side stream, once
   // its core M is in mbuf
   auto side_tail = [&](int k) -> isdf_status {
@@ -1123,7 +1125,7 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   };
   auto side_core = [&](int k) -> isdf_status {
     if (k >= 2) HIPCHK(hipStreamWaitEvent(side, h->m_used[k & 1], 0));
-    if (k == 0) HIPCHK(hipStreamWaitEvent(side, h->zdone, 0));
+    if (k == 0 && !core_beside_z) HIPCHK(hipStreamWaitEvent(side, h->zdone, 0));
     TRY(stage_core(R, n_omega ? omega[k] : 0.0, nullptr, mbuf[k & 1], side));
     return side_tail(k);
   };
@@ -1636,7 +1638,7 @@ isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {
 static bool tune_valid(const isdf_tune* t) {
   return t && t->dft_zb >= 1 && t->dft_zb <= 64 && t->core_split_pct >= 25 && t->core_split_pct <= 200 &&
          t->gram_split >= 1 && t->gram_split <= 16 && t->wg_per_cu >= 1 && t->wg_per_cu <= 4 &&
-         (t->core_stream == 0 || t->core_stream == 1);
+         t->core_stream >= 0 && t->core_stream <= 2;
 }
 
 isdf_status isdf_plan_set_tune(isdf_plan pl, const isdf_tune* t) {
@@ -1684,7 +1686,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
   const int splits[] = {50, 100, 200};
   const int grams[] = {4, 8, 16};
   const int wpcs[] = {1, 2};
-  const int cstreams[] = {0, 1};
+  const int cstreams[] = {0, 1, 2};
   auto sweep = [&](int Tune::*knob, const int* cands, int nc) -> isdf_status {
     const int keep = pl->tune.*knob;
     int arg = keep;
@@ -1702,7 +1704,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
   TRY(sweep(&Tune::core_split_pct, splits, 3));
   TRY(sweep(&Tune::gram_split, grams, 3));
   TRY(sweep(&Tune::wg_per_cu, wpcs, 2));
-  TRY(sweep(&Tune::core_stream, cstreams, 2));
+  TRY(sweep(&Tune::core_stream, cstreams, 3));
   if (out) {
     TRY(isdf_plan_get_tune(pl, out));
     out->best_ms = best;

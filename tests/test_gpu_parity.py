@@ -550,7 +550,7 @@ def test_plan_autotune():
     t = plan.autotune(psi, e, out, ws, reps=2)
     assert t["dft_zb"] in (4, 6, 8, 12, 16, 24) and t["core_split_pct"] in (50, 100, 200)
     assert t["gram_split"] in (4, 8, 16) and t["wg_per_cu"] in (1, 2) and t["best_ms"] > 0
-    assert t["core_stream"] in (0, 1)
+    assert t["core_stream"] in (0, 1, 2)
     assert plan.get_tune()["dft_zb"] == t["dft_zb"]
     plan.eps_inv_async(psi, e, out, ws)
     plan.sync()
@@ -564,24 +564,24 @@ def test_plan_autotune():
     with pytest.raises(isdf.IsdfError):
         plan.set_tune(dft_zb=0)
     with pytest.raises(isdf.IsdfError):
-        plan.set_tune(core_stream=2)
+        plan.set_tune(core_stream=3)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_core_stream_placement_is_bit_identical(prec):
-    """The first core on the second stream after Z (core_stream 1) runs the same
-    kernels on the same data: the result equals the default placement bit for bit."""
+    """The first core on the second stream after Z (core_stream 1) or beside it (2)
+    runs the same kernels on the same data: the result equals the default placement
+    bit for bit."""
     inp, prob, plan = _plan_case("mid", prec)
     psi, e = dev(inp.psi_t), dev(inp.energies)
     ws = plan.new_workspace()
-    a, b = plan.new_output(), plan.new_output()
-    plan.set_tune(core_stream=0)
-    plan.eps_inv_async(psi, e, a, ws)
-    plan.sync()
-    plan.set_tune(core_stream=1)
-    plan.eps_inv_async(psi, e, b, ws)
-    plan.sync()
-    assert torch.equal(a, b)
+    outs = []
+    for cs in (0, 1, 2):
+        outs.append(plan.new_output())
+        plan.set_tune(core_stream=cs)
+        plan.eps_inv_async(psi, e, outs[-1], ws)
+        plan.sync()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
