@@ -168,9 +168,12 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
   }
 }
 
-// Leftover tiles of the split tail: workgroup (xcd, t) adds the K slices of that
-// XCD's tail tile t in slice order, scales by alpha and writes the tile as the
-// main kernel's epilogue would.
+// Leftover tiles of the split tail: workgroup (xcd, t, chunk) adds, for 512 complex
+// elements of that XCD's tail tile t (two per thread, one 16-byte load per slice),
+// the K slices in slice order, scales by alpha and writes them as the main
+// kernel's epilogue would.
+constexpr int TAIL_CHUNKS = ZL::BM * ZL::BN / 512;
+
 template <bool HERM>
 __global__ __launch_bounds__(256) void gemm32_tail_kernel(int ntj, int total, int nper, int nt, const float* tail_ws,
                                                           void* C, long ldc, float alpha) {
@@ -181,15 +184,16 @@ __global__ __launch_bounds__(256) void gemm32_tail_kernel(int ntj, int total, in
   tile_origin<HERM>(tp.lo + tp.nfull + t, ntj, m0, n0);
   const size_t unit = (size_t)ZL::BM * ZL::BN * 2;
   const float* ws = tail_ws + (size_t)(xcd * nper + t * tp.split) * unit;
-  for (int e = threadIdx.x; e < ZL::BM * ZL::BN; e += blockDim.x) {
-    float re = 0.f, im = 0.f;
-    for (int ks = 0; ks < tp.split; ++ks) {
-      re += ws[ks * unit + 2 * e];
-      im += ws[ks * unit + 2 * e + 1];
-    }
-    re *= alpha;
-    im *= alpha;
-    const int r = e / ZL::BN, c = e % ZL::BN, gr = m0 + r, gc = n0 + c;
+  const int e = 2 * (blockIdx.z * 256 + threadIdx.x);   // elements e, e + 1 (same row)
+  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int ks = 0; ks < tp.split; ++ks) acc += *reinterpret_cast<const f4*>(ws + ks * unit + 2 * e);
+  acc *= alpha;
+  const int r = e / ZL::BN, c = e % ZL::BN, gr = m0 + r;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int gc = n0 + c + h;
+    const float re = acc[2 * h], im = acc[2 * h + 1];
     if (!HERM) {
       reinterpret_cast<float2*>(C)[(long)gr * ldc + gc] = float2{re, im};
       continue;
@@ -239,12 +243,14 @@ hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conj
                        (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !ws) return e;
+  int max_tail = 0;
+  for (int x = 0; x < 8; ++x) max_tail = std::max(max_tail, tail_plan(x, total, nper, nt, true).ntail);
+  const dim3 tg(8, max_tail, TAIL_CHUNKS);
   if (herm_identity)
-    hipLaunchKernelGGL(gemm32_tail_kernel<true>, dim3(8, nper), dim3(256), 0, st, ntj, total, nper, nt, ws, C, ldc,
-                       (float)alpha);
+    hipLaunchKernelGGL(gemm32_tail_kernel<true>, tg, dim3(256), 0, st, ntj, total, nper, nt, ws, C, ldc, (float)alpha);
   else
-    hipLaunchKernelGGL(gemm32_tail_kernel<false>, dim3(8, nper), dim3(256), 0, st, ntj, total, nper, nt, ws, C,
-                       ldc, (float)alpha);
+    hipLaunchKernelGGL(gemm32_tail_kernel<false>, tg, dim3(256), 0, st, ntj, total, nper, nt, ws, C, ldc,
+                       (float)alpha);
   return hipGetLastError();
 }
 

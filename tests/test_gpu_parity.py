@@ -17,7 +17,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank", "tiles", "kmaj", "core32", "tail"]
+SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank", "tiles", "kmaj", "core32", "tail", "wide"]
 TOL_EPS = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6}
 # bf16x3 stages: effective unit roundoff ~3 * 2^-16 (hi + lo split, lo*lo dropped) times cond(S) <= 2e2 here
 TOL_STAGE = {"fp64": 1e-10, "fp32": 1e-4, "bf16x3": 2e-3}
@@ -437,17 +437,21 @@ def test_core_contour_integral_64cubed(prec):
     assert err <= (1e-11 if prec == "fp64" else TOL_STAGE["fp32"] * 1e-2), err
 
 
-def test_frequencies_full_tiles():
-    """Frequency batch on the full-tile case (k-major output products per frequency)."""
-    inp = synth.make_inputs("kmaj", n_omega=3)
-    st = get_stages("kmaj")
-    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, isdf.problem_for(inp, "fp32"),
+@pytest.mark.parametrize("name,prec", [("kmaj", "fp32"), ("core32", "fp32"), ("core32", "bf16x3")])
+def test_frequencies_full_tiles(name, prec):
+    """Frequency batch on full-tile cases: k-major output products per frequency
+    (kmaj), and the cores M(omega) of all frequencies in one launch of the k-major
+    single-precision core (core32)."""
+    inp = synth.make_inputs(name, n_omega=3)
+    st = get_stages(name)
+    print(f"[freq] case={name} prec={prec}", flush=True)
+    res = isdf.eps_inv(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller, isdf.problem_for(inp, prec),
                        omegas=inp.omegas)
     got = res.eps_inv.cpu().numpy()
     for k, om in enumerate(inp.omegas):
         stw = dict(st)
         stw["m"] = oracle.core_matrix(inp.psi_t, inp.energies, inp.nv, inp.mu_idx, omega=om)
-        assert relf(got[k], oracle.eps_inv_isdf(inp, stages=stw)) <= TOL_EPS["fp32"], (k, om)
+        assert relf(got[k], oracle.eps_inv_isdf(inp, stages=stw)) <= TOL_EPS[prec], (k, om)
 
 
 def test_plan_graph_capture():
