@@ -643,9 +643,10 @@ isdf_status stage_dft(Run& R, bool scaled) {
   HIPCHK(dft_twiddles(ib + L.kx + L.ky, L.kz, P.n2, P.m32, at<char>(R.ws, L.twz), R.st));
   const double* scale = scaled ? at<double>(R.ws, L.sqrtv) : nullptr;
   if (dft_fused_fits(cp, p)) {
-    HIPCHK(dft_fused(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), L.t2_bytes, at<char>(R.ws, L.zg), scale,
-                     R.st));
-    return ISDF_OK;
+    const hipError_t e = dft_fused(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), L.t2_bytes,
+                                   at<char>(R.ws, L.zg), scale, R.st);
+    if (e == hipSuccess) return ISDF_OK;
+    if (e != hipErrorNotSupported) HIPCHK(e);
   }
   HIPCHK(dft_xy(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), R.st));
   HIPCHK(dft_z(cp, p, at<char>(R.ws, L.t2), at<char>(R.ws, L.zg), scale, R.st));

@@ -13,6 +13,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include "kmajor.h"   // cu_count
 #include "tile.h"
 
 #include <cmath>
@@ -310,25 +311,35 @@ hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipS
 
 // Fused x, y and z stages for lists with at most 32 x- and y-frequencies (the
 // plane-wave spheres of the Coulomb Gram).  A workgroup of ceil(kx / 8) waves
-// walks zb consecutive z-planes of one point; wave w owns the x-frequencies
-// [8 w, 8 w + 8).  Per slab (n1 x n0, y rows, x contiguous):
+// walks an equal run of consecutive (point, z-plane) slabs; wave w owns the
+// x-frequencies [8 w, 8 w + 8).  Per slab (n1 x n0, y rows, x contiguous):
 //   x stage  T1 (y x a_w)  = slab (y x x) . TWX^T (x x a_w)     rows y in 16s
 //   y stage  T2 (b x a_w)  = TWY (b x y) . T1 (y x a_w)         rows b in 16s
 // T1 goes through a region of LDS private to the wave (no workgroup barrier
 // between the stages), and T2 overwrites it in place.  After one barrier every
 // thread adds T2[b_g][a_g] twz[c_g][z] into the running sums of its plane waves
 // (ng / blockDim of them, in registers), so T2 never reaches HBM.  The sums of
-// the z-range go to `part` [zblock][mu][g]; with a single z-block they are the
-// result, scaled, in zg.  Padding rows and columns of the slab are zero (set
+// each point's run go to `part` [mu][piece][g], and dft_zsum_kernel adds the
+// pieces and applies the scale.  Padding rows and columns of the slab are zero (set
 // once); twiddle padding is zero, so padded terms contribute exactly zero.
 // Register budgets (slab elements and plane waves per thread) of the two
 // instantiations: up to 48^3-like shapes, and up to 64^3-like ones (FP32 only).
 constexpr int FUSED_PF_S = 12, FUSED_GPT_S = 24, FUSED_PF_L = 16, FUSED_GPT_L = 32;
 
+// g workgroups; workgroup w transforms the slabs [w S / g, (w + 1) S / g) of the
+// S = nmu n2 slabs in (point, z) order, so the work is balanced whatever nmu and
+// the number of resident workgroups are.  The run of one point inside a
+// workgroup's range is one piece of that point's z sum (at most pmax pieces).
 struct FusedShape {
-  int nw, nt, fmx, fmb, pf, gpt, zb, nzb, x2, y2, ls, la, wsz;
+  int nw, nt, fmx, fmb, pf, gpt, x2, y2, ls, la, wsz, g, pmax;
   size_t lds;
 };
+
+// last workgroup whose range starts at or before slab x
+__host__ __device__ inline int fused_owner(long x, long S, int g) {
+  const long w = ((x + 1) * g - 1) / S;
+  return (int)(w < g - 1 ? w : g - 1);
+}
 
 template <typename T>
 static bool fused_shape(const DftPlan& p, FusedShape& f) {
@@ -342,15 +353,14 @@ static bool fused_shape(const DftPlan& p, FusedShape& f) {
   f.gpt = (p.ng + f.nt - 1) / f.nt;
   const bool large_ok = sizeof(T) == 4;
   if (f.pf > (large_ok ? FUSED_PF_L : FUSED_PF_S) || f.gpt > (large_ok ? FUSED_GPT_L : FUSED_GPT_S)) return false;
-  f.zb = std::max(std::max(1, std::min(p.n2, p.zb)), (p.n2 + DFT_MAX_ZBLOCKS - 1) / DFT_MAX_ZBLOCKS);
-  f.nzb = (p.n2 + f.zb - 1) / f.zb;
   f.x2 = (p.n0 + 3) & ~3;   // K extents in whole pairs of MFMA steps (zero padding)
   f.y2 = (p.n1 + 3) & ~3;
   f.ls = f.x2 + 1;
   f.la = 8 * f.nw + 1;
   f.wsz = std::max(16 * f.fmx, 32) * 9;
   const size_t el = (size_t)16 * f.fmx * f.ls + (size_t)f.x2 * f.la + (size_t)f.y2 * 33 + (size_t)f.nw * f.wsz +
-                    (size_t)f.zb * p.kz;
+                    (size_t)p.n2 * p.kz;
+  f.g = f.pmax = 0;   // set by the launcher
   f.lds = el * sizeof(cx<T>);
   return f.lds <= 160 * 1024;
 }
@@ -378,10 +388,10 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
   cx<T>* Xs = Ss + rows * f.ls;                     // TWX^T [x][a], x2 x la
   cx<T>* Ys = Xs + f.x2 * f.la;                     // TWY^T [y][b], y2 x 33
   cx<T>* Tw = Ys + f.y2 * 33;                       // per wave: T1 [y][a_w], then T2 [b][a_w]; stride 9
-  cx<T>* Zs = Tw + f.nw * f.wsz;                    // twz of this z-range [z - z0][c]
+  cx<T>* Zs = Tw + f.nw * f.wsz;                    // twz [z][c]
   const int nt = f.nt, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int mu = blockIdx.x / f.nzb, zi = blockIdx.x % f.nzb;
-  const int z0 = zi * f.zb, z1 = min(p.n2, z0 + f.zb);
+  const long S = (long)p.nmu * p.n2;
+  const long s0 = (long)blockIdx.x * S / f.g, s1 = (long)(blockIdx.x + 1) * S / f.g;
   const int nslab = p.n0 * p.n1;
   const cx<T>* twx = reinterpret_cast<const cx<T>*>(p.twx);
   const cx<T>* twy = reinterpret_cast<const cx<T>*>(p.twy);
@@ -396,9 +406,9 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
     const int k = i / 33, c = i % 33;
     Ys[i] = (k < p.n1 && c < p.ky) ? twy[c * p.n1 + k] : zero;
   }
-  for (int i = tid; i < (z1 - z0) * p.kz; i += nt) {
-    const int zl = i / p.kz, c = i % p.kz;
-    Zs[i] = twz[c * p.n2 + z0 + zl];
+  for (int i = tid; i < p.n2 * p.kz; i += nt) {
+    const int z = i / p.kz, c = i % p.kz;
+    Zs[i] = twz[c * p.n2 + z];
   }
   // this thread's plane waves g = tid + nt j: T2 offset in Tw | z-frequency << 16;
   // slots past the list hold code 0 (summed like the rest, never stored)
@@ -417,6 +427,7 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
   // slab element e of this thread: i = tid + nt e at Ss[(i / n0) ls + i % n0], stepped incrementally
   const int r0 = tid / p.n0, c0 = tid % p.n0, dr = nt / p.n0, dc = nt % p.n0;
   T pfr[PF], pfi[PF];
+  int mu = 0;   // point of the current run
   auto fetch = [&](int z) {
     const char* src = reinterpret_cast<const char*>(zt + ((long)mu * p.n2 + z) * nslab);
 #pragma unroll
@@ -426,7 +437,6 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
       pfr[e] = v.re; pfi[e] = v.im;
     }
   };
-  if (z0 < z1) fetch(z0);
   __syncthreads();  // Ss zeroed before any slab element lands
   const int i16 = lane & 15, q = lane >> 4, rc = lane & 15, part = rc & 1;
   const int bpart = ((q & 1) == (i16 & 1)) ? 0 : 1;
@@ -435,6 +445,12 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
   const T* XsR = reinterpret_cast<const T*>(Xs);
   const T* YsR = reinterpret_cast<const T*>(Ys);
   T* TwR = reinterpret_cast<T*>(Tw + wave * f.wsz);
+  for (long sb = s0; sb < s1;) {   // runs of one point
+  mu = (int)(sb / p.n2);
+  const int z0 = (int)(sb % p.n2), z1 = (int)min((long)p.n2, z0 + (s1 - sb));
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) zacc[j] = zero;
+  fetch(z0);
   for (int z = z0; z < z1; ++z) {
     {
       int r = r0, c = c0;
@@ -523,7 +539,7 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
       for (int v = 0; v < 4; ++v) TwR[((16 * fb + Mfma<T>::row(lane, v)) * 9 + (rc >> 1)) * 2 + part] = acc2[fb][v];
     __syncthreads();
     // z stage: running sums of this thread's plane waves
-    const cx<T>* zrow = Zs + (z - z0) * p.kz;
+    const cx<T>* zrow = Zs + z * p.kz;
 #pragma unroll
     for (int j0 = 0; j0 < GPT; j0 += 8) {
       __builtin_amdgcn_sched_barrier(0);   // bounds the LDS reads in flight (register pressure)
@@ -540,27 +556,26 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
     }
   }
 #pragma unroll
-  for (int j = 0; j < GPT; ++j) {
+  for (int j = 0; j < GPT; ++j) {   // this run is piece (workgroup - first owner) of the point's sum
     if (tid + nt * j >= p.ng) continue;
     const int g = tid + nt * j;
-    if (f.nzb == 1) {
-      const T sc = scale ? (T)scale[g] : (T)1;
-      out[(long)mu * p.ng + g] = cx<T>{zacc[j].re * sc, zacc[j].im * sc};
-    } else {
-      out[((long)zi * p.nmu + mu) * p.ng + g] = zacc[j];
-    }
+    const int piece = (int)blockIdx.x - fused_owner((long)mu * p.n2, S, f.g);
+    out[((long)mu * f.pmax + piece) * p.ng + g] = zacc[j];
+  }
+  sb += z1 - z0;
   }
 }
 
-// zg[mu][g] = scale[g] sum_zi part[zi][mu][g], z-blocks in increasing order
+// zg[mu][g] = scale[g] sum_j part[mu][j][g] over the point's pieces, in piece order
 template <typename T>
-__global__ void dft_zsum_kernel(const cx<T>* __restrict__ part, int nzb, int nmu, int ng,
+__global__ void dft_zsum_kernel(const cx<T>* __restrict__ part, int pmax, long S, int g_wg, int n2, int nmu, int ng,
                                 const double* __restrict__ scale, cx<T>* __restrict__ zg) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x, mu = blockIdx.y;
   if (g >= ng) return;
+  const int np = fused_owner((long)(mu + 1) * n2 - 1, S, g_wg) - fused_owner((long)mu * n2, S, g_wg) + 1;
   T re = 0, im = 0;
-  for (int zi = 0; zi < nzb; ++zi) {
-    const cx<T> v = part[((long)zi * nmu + mu) * ng + g];
+  for (int j = 0; j < np; ++j) {
+    const cx<T> v = part[((long)mu * pmax + j) * ng + g];
     re += v.re;
     im += v.im;
   }
@@ -569,28 +584,54 @@ __global__ void dft_zsum_kernel(const cx<T>* __restrict__ part, int nzb, int nmu
 }
 
 template <typename T, int PF, int GPT, int FMX>
-static void fused_kernel_launch(const DftPlan& p, const FusedShape& f, const void* zt, void* out,
-                                const double* scale, hipStream_t st) {
-  static bool attr_set[64] = {};  // once per device, outside any later stream capture
+static hipError_t fused_kernel_launch(const DftPlan& p, FusedShape& f, const void* zt, void* part,
+                                      size_t part_bytes, hipStream_t st) {
+  const void* fn = reinterpret_cast<const void*>(&dft_fused_kernel<T, PF, GPT, FMX>);
+  // per device: the LDS attribute once (outside any later stream capture), and the
+  // resident workgroups per CU for the last shape asked
+  static bool attr_set[64] = {};
+  static int occ_lds[64] = {}, occ_nt[64] = {}, occ[64] = {};
   int dev = 0;
   (void)hipGetDevice(&dev);
-  if (dev < 0 || dev >= 64 || !attr_set[dev]) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dft_fused_kernel<T, PF, GPT, FMX>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (dev >= 0 && dev < 64) attr_set[dev] = true;
+  const bool cache = dev >= 0 && dev < 64;
+  if (!cache || !attr_set[dev]) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (cache) attr_set[dev] = true;
   }
-  hipLaunchKernelGGL((dft_fused_kernel<T, PF, GPT, FMX>), dim3((unsigned)(p.nmu * f.nzb)), dim3(f.nt), f.lds, st,
-                     p, f, (const cx<T>*)zt, (cx<T>*)out, scale);
+  int per_cu = 0;
+  if (cache && occ_lds[dev] == (int)f.lds && occ_nt[dev] == f.nt) {
+    per_cu = occ[dev];
+  } else {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, f.nt, f.lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (cache) { occ_lds[dev] = (int)f.lds; occ_nt[dev] = f.nt; occ[dev] = per_cu; }
+  }
+  // one resident round of workgroups (at least 4 slabs each); fewer if the pieces
+  // per point would overflow the scratch
+  const long S = (long)p.nmu * p.n2;
+  long g = std::min<long>((long)per_cu * cu_count(), std::max<long>(1, S / 4));
+  for (;;) {
+    int pmax = 1;
+    for (int mu = 0; mu < p.nmu; ++mu)
+      pmax = std::max(pmax, fused_owner((long)(mu + 1) * p.n2 - 1, S, (int)g) - fused_owner((long)mu * p.n2, S, (int)g) + 1);
+    f.g = (int)g;
+    f.pmax = pmax;
+    if ((size_t)p.nmu * pmax * p.ng * sizeof(cx<T>) <= part_bytes) break;
+    if (g == 1) return hipErrorNotSupported;
+    g = std::max<long>(1, g * 3 / 4);
+  }
+  hipLaunchKernelGGL((dft_fused_kernel<T, PF, GPT, FMX>), dim3((unsigned)f.g), dim3(f.nt), f.lds, st, p, f,
+                     (const cx<T>*)zt, (cx<T>*)part, nullptr);
+  return hipGetLastError();
 }
 
 template <typename T, int PF, int GPT>
-static void fused_dispatch(const DftPlan& p, const FusedShape& f, const void* zt, void* out, const double* scale,
-                           hipStream_t st) {
+static hipError_t fused_dispatch(const DftPlan& p, FusedShape& f, const void* zt, void* part, size_t part_bytes,
+                                 hipStream_t st) {
   switch (f.fmx) {
-    case 1: fused_kernel_launch<T, PF, GPT, 1>(p, f, zt, out, scale, st); break;
-    case 2: fused_kernel_launch<T, PF, GPT, 2>(p, f, zt, out, scale, st); break;
-    case 3: fused_kernel_launch<T, PF, GPT, 3>(p, f, zt, out, scale, st); break;
-    default: fused_kernel_launch<T, PF, GPT, 4>(p, f, zt, out, scale, st); break;
+    case 1: return fused_kernel_launch<T, PF, GPT, 1>(p, f, zt, part, part_bytes, st);
+    case 2: return fused_kernel_launch<T, PF, GPT, 2>(p, f, zt, part, part_bytes, st);
+    case 3: return fused_kernel_launch<T, PF, GPT, 3>(p, f, zt, part, part_bytes, st);
+    default: return fused_kernel_launch<T, PF, GPT, 4>(p, f, zt, part, part_bytes, st);
   }
 }
 
@@ -599,16 +640,12 @@ static hipError_t fused_launch(const DftPlan& p, const void* zt, void* part, siz
                                const double* scale, hipStream_t st) {
   FusedShape f;
   if (!fused_shape<T>(p, f)) return hipErrorNotSupported;
-  if (f.nzb > 1 && (size_t)f.nzb * p.nmu * p.ng * sizeof(cx<T>) > part_bytes) return hipErrorNotSupported;
-  void* out = f.nzb == 1 ? zg : part;
-  const double* sc = f.nzb == 1 ? scale : nullptr;
-  if (f.pf <= FUSED_PF_S && f.gpt <= FUSED_GPT_S) fused_dispatch<T, FUSED_PF_S, FUSED_GPT_S>(p, f, zt, out, sc, st);
-  else fused_dispatch<float, FUSED_PF_L, FUSED_GPT_L>(p, f, zt, out, sc, st);   // FP32 only (fused_shape)
-  if (f.nzb == 1) return hipGetLastError();
-  hipError_t e = hipGetLastError();
+  const hipError_t e = (f.pf <= FUSED_PF_S && f.gpt <= FUSED_GPT_S)
+                           ? fused_dispatch<T, FUSED_PF_S, FUSED_GPT_S>(p, f, zt, part, part_bytes, st)
+                           : fused_dispatch<float, FUSED_PF_L, FUSED_GPT_L>(p, f, zt, part, part_bytes, st);  // FP32 only
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(dft_zsum_kernel<T>, dim3(cdiv(p.ng, 256), p.nmu), dim3(256), 0, st, (const cx<T>*)part, f.nzb,
-                     p.nmu, p.ng, scale, (cx<T>*)zg);
+  hipLaunchKernelGGL(dft_zsum_kernel<T>, dim3(cdiv(p.ng, 256), p.nmu), dim3(256), 0, st, (const cx<T>*)part, f.pmax,
+                     (long)p.nmu * p.n2, f.g, p.n2, p.nmu, p.ng, scale, (cx<T>*)zg);
   return hipGetLastError();
 }
 

@@ -97,14 +97,14 @@ struct DftPlan {
   const int* dmap;         // kx x ky: pair index d of (x-frequency a, y-frequency b), or -1
   const int* gd_off;       // nd + 1: plane waves of pair d are gd_list[gd_off[d] .. gd_off[d + 1])
   const int* gd_list;      // ng
-  int zb = 8;              // z-planes per workgroup of the x/y stage (a tuning knob)
+  int zb = 8;              // z-planes per workgroup of dft_xy (a tuning knob)
 };
 // zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][nd][n2] -> zg: [nmu][ng] (times scale[g] if given)
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);
 // All three stages in one pass (kx, ky <= 32 and few plane waves per thread):
-// zt -> zg (times scale[g] if given) with per-z-block partial sums in `part`
-// (at most DFT_MAX_ZBLOCKS x nmu x ng elements).  hipErrorNotSupported when the
-// shape or `part_bytes` does not fit (the caller then runs dft_xy + dft_z).
+// zt -> zg (times scale[g] if given), with per-point partial sums in `part` (at
+// most DFT_MAX_ZBLOCKS x nmu x ng elements).  hipErrorNotSupported when the shape
+// or `part_bytes` does not fit (the caller then runs dft_xy + dft_z).
 constexpr int DFT_MAX_ZBLOCKS = 8;
 bool dft_fused_fits(Prec compute, const DftPlan& p);
 hipError_t dft_fused(Prec compute, const DftPlan& p, const void* zt, void* part, size_t part_bytes, void* zg,
