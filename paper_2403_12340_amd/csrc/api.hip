@@ -560,11 +560,12 @@ isdf_status stage_smis(Run& R, void* mi, void* q, hipStream_t st) {
   a.B = sk; a.sbk = n; a.sbn = 1; a.conjB = true;
   a.C = q; a.ldc = n;
   HIPCHK(gemm(P64, a, st));
-  GemmDesc b;  // mi = S q
+  GemmDesc b;  // mi = S q (Hermitian: lower tiles, mirrored)
   b.M = b.N = b.K = n;
   b.A = sk; b.sam = n; b.sak = 1; b.conjA = true;
   b.B = q; b.sbk = n; b.sbn = 1;
   b.C = mi; b.ldc = n;
+  b.herm = true;
   HIPCHK(gemm(P64, b, st));
   return ISDF_OK;
 }
@@ -1047,11 +1048,12 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
     a.C = qb; a.ldc = n;
     a.batch = nw; a.bsa = n2; a.bsb = 0; a.bsc = n2;
     HIPCHK(gemm(P64, a, side));
-    GemmDesc b;  // K = S q, over M^{-1}
+    GemmDesc b;  // K = S q, over M^{-1} (Hermitian: lower tiles, mirrored)
     b.M = b.N = b.K = n;
     b.A = sk; b.sam = n; b.sak = 1; b.conjA = true;
     b.B = qb; b.sbk = n; b.sbn = 1;
     b.C = mb; b.ldc = n;
+    b.herm = true;
     b.batch = nw; b.bsa = 0; b.bsb = n2; b.bsc = n2;
     HIPCHK(gemm(P64, b, side));
   }
