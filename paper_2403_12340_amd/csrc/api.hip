@@ -236,7 +236,7 @@ struct Layout {
   size_t zt_bytes = 0;               // size of the zt region
   size_t t2_bytes = 0;               // size of the t2 region
   size_t part = 0, l2 = 0, lin2 = 0, q = 0;  // core partials; second -M buffer, sweep scratch, S M^-1 S scratch
-  size_t psi32 = 0, pm32 = 0;        // complex64 copies of the orbitals (FP32 mode only)
+  size_t pm32 = 0;                   // complex64 copy of the orbitals at the points (FP32 mode only)
   size_t bf_rows = 0, bf_pts = 0;    // bf16 hi / lo planes of the orbitals (BF16x3 mode only)
   // contour-integral core: node table (lambda, weight), scaled operands, Gram pairs, running sum
   size_t cnodes = 0, cops = 0, cprod = 0, csum = 0, cpm32 = 0;
@@ -255,7 +255,6 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.psi_c = P.cplx ? 0 : take((size_t)P.ns * P.nr * z);
   L.pm = take((size_t)P.ns * P.nmu * z);
   if (P.prec == P32) {
-    L.psi32 = take((size_t)P.ns * P.nr * 8);
     L.pm32 = take((size_t)P.ns * P.nmu * 8);
   } else if (P.prec == PBF3) {
     L.bf_rows = take(bf3_rows_bytes(P.nr, P.nv, P.nc));
@@ -570,8 +569,9 @@ isdf_status stage_smis(Run& R, void* mi, void* q, hipStream_t st) {
   return ISDF_OK;
 }
 
-// Operands of the pair product.  Mixed precision: one streaming pass to complex64
-// halves the bytes the contraction reads.
+// Operands of the pair product.  FP32 mode: the orbitals at the points go to
+// complex64 (the pair kernel reads the grid orbitals as they are and rounds them
+// while staging).  BF16x3: both go to bf16 hi / lo planes.
 isdf_status stage_z_operands(Run& R, hipStream_t st) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
@@ -581,7 +581,6 @@ isdf_status stage_z_operands(Run& R, hipStream_t st) {
     HIPCHK(bf3_split_points(at<char>(R.ws, R.L.pm), P.nmu, P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.bf_pts), st));
     return ISDF_OK;
   }
-  HIPCHK(convert_z(R.psi, false, at<char>(R.ws, R.L.psi32), true, (long)P.ns * P.nr, st));
   HIPCHK(convert_z(at<char>(R.ws, R.L.pm), false, at<char>(R.ws, R.L.pm32), true, (long)P.ns * P.nmu, st));
   return ISDF_OK;
 }
@@ -601,8 +600,8 @@ isdf_status stage_z(Run& R) {
                      at<char>(R.ws, R.L.zt), P.nr, R.st));
     return ISDF_OK;
   }
-  HIPCHK(zpair(P32, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm32), P.nmu, at<char>(R.ws, R.L.psi32),
-               P.nr, true, at<char>(R.ws, R.L.zt), P.nr, true, R.st, R.tune.wg_per_cu));
+  HIPCHK(zpair(P32, P.nmu, (int)P.nr, P.nv, P.ns, at<char>(R.ws, R.L.pm32), P.nmu, R.psi, P.nr, true,
+               at<char>(R.ws, R.L.zt), P.nr, true, R.st, R.tune.wg_per_cu));
   return ISDF_OK;
 }
 

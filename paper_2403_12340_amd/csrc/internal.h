@@ -46,8 +46,9 @@ bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, lo
 
 // ----- orbital pair Gram (step 1):  out[mu][c] = conj(Pv(mu, c)) * Qc(mu, c)
 //   Pv(mu, c) = sum_{i < nv} conj(pm[i][mu]) b[i][c],  Qc(mu, c) = sum_{nv <= j < ns} conj(pm[j][mu]) b[j][c]
-//   pm: [ns][ldp] (orbitals at the points), b: [ns][ldb], both complex64 if in32 else complex128;
-//   out [M][ldo] complex64 if out32 else complex128
+//   pm: [ns][ldp] (orbitals at the points), b: [ns][ldb] (orbitals on the grid, complex128).
+//   P64: pm complex128, in32 = out32 = false, out complex128.  P32: pm complex64 (in32 = true),
+//   b rounded to FP32 as it is staged, out complex64 (out32 = true).
 hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
                  long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st, int wg_per_cu = 1);
 

@@ -96,13 +96,15 @@ struct ZFetch {
   }
 };
 
-// K loop of one interior tile whose first K tile is already in `zf`: K tiles
+// K loop of one interior tile whose first K tile is already in `zf` (a ZFetch, or
+// a fetch of the same interface whose B operand has another storage type): K tiles
 // t < tp accumulate into accp, the rest into accq (pass the same array twice for
 // a single accumulator).  During the last K tile it prefetches the first K tile
 // of the next interior tile (if any), so that tile's load latency hides behind
 // this tile's MFMAs and epilogue.
-__device__ __forceinline__ void zl_loop_full(float* smem, ZFetch& zf, int tp, int nt, float sa, float sb,
-                                             const c32* A, long lda, const c32* B, long ldb, int m0, int n0,
+template <class F, typename SB>
+__device__ __forceinline__ void zl_loop_full(float* smem, F& zf, int tp, int nt, float sa, float sb,
+                                             const c32* A, long lda, const SB* B, long ldb, int m0, int n0,
                                              bool has_next, int nm0, int nn0, f4 (&accp)[ZL::FM][ZL::FN],
                                              f4 (&accq)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
   float* buf0 = smem;

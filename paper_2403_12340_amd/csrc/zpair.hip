@@ -99,19 +99,19 @@ __global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int
 // ----------------------------------------------------------------------------
 // Generic K loop (any tile edge): clamped loads, masked LDS stores.
 __device__ __forceinline__ void zl_loop_generic(float* smem, int M, int N, int nv, int ns, const c32* pm,
-                                                long ldp, const c32* b, long ldb, int m0, int n0,
+                                                long ldp, const z64* b, long ldb, int m0, int n0,
                                                 f4 (&accp)[ZL::FM][ZL::FN], f4 (&accq)[ZL::FM][ZL::FN],
                                                 int tid, int wm0, int wn0, int lane) {
   const int tp = (nv + ZL::BK - 1) / ZL::BK, tq = (ns - nv + ZL::BK - 1) / ZL::BK;
   const int nt = tp + tq;
-  auto kbase = [&](int t, const c32*& pa, const c32*& pb, int& k0, int& K) {
+  auto kbase = [&](int t, const c32*& pa, const z64*& pb, int& k0, int& K) {
     if (t < tp) { pa = pm; pb = b; k0 = t * ZL::BK; K = nv; }
     else { pa = pm + (long)nv * ldp; pb = b + (long)nv * ldb; k0 = (t - tp) * ZL::BK; K = ns - nv; }
   };
   Stager<float, float, ZL::BM, ZL::BK, ZL::NT, true> sa;
-  Stager<float, float, ZL::BN, ZL::BK, ZL::NT, true> sb;
+  Stager<float, double, ZL::BN, ZL::BK, ZL::NT, true> sb;   // orbitals rounded to FP32 at staging
   {
-    const c32* pa; const c32* pb; int k0, K;
+    const c32* pa; const z64* pb; int k0, K;
     kbase(0, pa, pb, k0, K);
     sa.fetch(pa, 1, ldp, m0, k0, M, K, tid);
     sb.fetch(pb, 1, ldb, n0, k0, N, K, tid);
@@ -122,7 +122,7 @@ __device__ __forceinline__ void zl_loop_generic(float* smem, int M, int N, int n
   for (int t = 0; t < nt; ++t) {
     const int cur = t & 1;
     if (t + 1 < nt) {
-      const c32* pa; const c32* pb; int k0, K;
+      const c32* pa; const z64* pb; int k0, K;
       kbase(t + 1, pa, pb, k0, K);
       sa.fetch(pa, 1, ldp, m0, k0, M, K, tid);
       sb.fetch(pb, 1, ldb, n0, k0, N, K, tid);
@@ -159,12 +159,45 @@ __device__ __forceinline__ void zl_epilogue(float* out, long ldo, int M, int N, 
       }
 }
 
+// Interior-tile fetch of the pair kernel: the points (A) as complex64 like
+// ZFetch, the orbitals (B) straight from their complex128 storage, two values
+// (32 bytes) per thread, rounded to FP32 as they are staged.  No converted copy
+// of the orbitals is made.
+struct ZFetchB64 {
+  uint32_t aoff0, aoff1, boff;
+  int ax, ak, bx, bk;
+  f4 ra0, ra1;
+  d4 rb;
+  __device__ __forceinline__ void init(int tid, long ldp, long ldb) {
+    ax = 2 * (tid & 63); ak = tid >> 6; bx = 2 * (tid & 31); bk = tid >> 5;
+    aoff0 = (uint32_t)((ak * ldp + ax) * 8);
+    aoff1 = (uint32_t)(((ak + 8) * ldp + ax) * 8);
+    boff = (uint32_t)((bk * ldb + bx) * 16);
+  }
+  __device__ __forceinline__ void fetch(const c32* pm, long ldp, const z64* b, long ldb, int m0, int n0, int t) {
+    const long kr = (long)t * ZL::BK;
+    const char* pa = reinterpret_cast<const char*>(pm + kr * ldp + m0);
+    const char* pb = reinterpret_cast<const char*>(b + kr * ldb + n0);
+    ra0 = *reinterpret_cast<const f4*>(pa + aoff0);
+    ra1 = *reinterpret_cast<const f4*>(pa + aoff1);
+    rb = *reinterpret_cast<const d4*>(pb + boff);
+  }
+  __device__ __forceinline__ void stage(float* buf, float sa, float sb) const {
+    *reinterpret_cast<f4*>(buf + (ak * ZL::LDA + ax) * 2) = f4{ra0[0], sa * ra0[1], ra0[2], sa * ra0[3]};
+    *reinterpret_cast<f4*>(buf + ((ak + 8) * ZL::LDA + ax) * 2) = f4{ra1[0], sa * ra1[1], ra1[2], sa * ra1[3]};
+    float* bb = buf + ZL::AS + (bk * ZL::LDB + bx) * 4;
+    const float r0 = (float)rb[0], i0 = sb * (float)rb[1], r1 = (float)rb[2], i1 = sb * (float)rb[3];
+    *reinterpret_cast<f4*>(bb) = f4{r0, i0, -i0, r0};
+    *reinterpret_cast<f4*>(bb + 4) = f4{r1, i1, -i1, r1};
+  }
+};
+
 // Interior tiles (nti x ntj of them, all full): one workgroup per CU walks its
 // share with no inter-workgroup synchronisation.  The tiles of each XCD form a
 // contiguous range of the point-fastest tile order, dealt to that XCD's
 // workgroups in turn, so they share the grid-orbital panels in its L2.
 __global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(3)))
-void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const c32* b, long ldb, float* out, long ldo,
+void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long ldb, float* out, long ldo,
                     int nti, int total) {
   __shared__ float smem[2 * (ZL::AS + ZL::BS)];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -172,7 +205,7 @@ void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const c32* b, long 
   const int xcd = blockIdx.x % 8, nper = gridDim.x / 8, j = blockIdx.x / 8;
   const int per = (total + 7) / 8;
   const int lo = xcd * per, hi = min(total, lo + per);
-  ZFetch zf;
+  ZFetchB64 zf;
   zf.init(tid, ldp, ldb);
   if (lo + j < hi) zf.fetch(pm, ldp, b, ldb, ((lo + j) % nti) * ZL::BM, ((lo + j) / nti) * ZL::BN, 0);
   for (int id = lo + j; id < hi; id += nper) {
@@ -194,7 +227,7 @@ void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const c32* b, long 
 // workgroup per tile from a list given as (first tile, count) of a column-major
 // walk over the ntm x ntn tiles, or the edge strips.
 __global__ __launch_bounds__(ZL::NT) void zpair32_edge_kernel(int M, int N, int nv, int ns, const c32* pm,
-                                                              long ldp, const c32* b, long ldb, float* out,
+                                                              long ldp, const z64* b, long ldb, float* out,
                                                               long ldo, int ntm, int ntn, int nti, int ntj,
                                                               int all) {
   __shared__ float smem[2 * (ZL::AS + ZL::BS)];
@@ -225,10 +258,11 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, l
                                  long ldb, void* out, long ldo, hipStream_t st, int wg_per_cu) {
   const int ntm = (int)cdiv(M, ZL::BM), ntn = (int)cdiv(N, ZL::BN);
   if (ntm == 0 || ntn == 0) return hipSuccess;
-  // the 16-byte interior path needs K tiles that never straddle the occupied /
-  // empty boundary, even leading dimensions and 16-byte aligned bases
+  // the vector-load interior path needs K tiles that never straddle the occupied /
+  // empty boundary, even leading dimensions, a 16-byte aligned point base and a
+  // 32-byte aligned orbital base
   const bool aligned = nv % ZL::BK == 0 && (ns - nv) % ZL::BK == 0 && (ldp & 1) == 0 && (ldb & 1) == 0 &&
-                       ((reinterpret_cast<uintptr_t>(pm) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+                       (reinterpret_cast<uintptr_t>(pm) & 15) == 0 && (reinterpret_cast<uintptr_t>(b) & 31) == 0;
   const int nti = aligned ? M / ZL::BM : 0, ntj = aligned ? N / ZL::BN : 0;
   const int interior = nti * ntj;
   if (interior > 0) {
@@ -236,7 +270,7 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, l
     const int wpc = std::max(1, std::min(wg_per_cu, 4));
     const int g = std::max(8, std::min(8 * ((wpc * cu_count() + 7) / 8), 8 * (int)cdiv(interior, 8)));
     hipLaunchKernelGGL(zpair32_kernel, dim3(g), dim3(ZL::NT), 0, st, nv, ns, (const c32*)pm, ldp,
-                       (const c32*)b, ldb, (float*)out, ldo, nti, interior);
+                       (const z64*)b, ldb, (float*)out, ldo, nti, interior);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -244,7 +278,7 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, l
   const int nedge = all ? ntm * ntn : (ntj < ntn ? ntm : 0) + (nti < ntm ? ntj : 0);
   if (nedge == 0) return hipSuccess;
   hipLaunchKernelGGL(zpair32_edge_kernel, dim3(nedge), dim3(ZL::NT), 0, st, M, N, nv, ns, (const c32*)pm,
-                     ldp, (const c32*)b, ldb, (float*)out, ldo, ntm, ntn, nti, ntj, all);
+                     ldp, (const z64*)b, ldb, (float*)out, ldo, ntm, ntn, nti, ntj, all);
   return hipGetLastError();
 }
 
@@ -268,7 +302,7 @@ hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, lon
     if (out32 || in32) return hipErrorInvalidValue;
     return zpair_launch<double, double, double, TZ64>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
   }
-  // single precision: complex64 operands and output (the orbitals are converted once)
+  // single precision: complex64 points, complex128 orbitals (rounded as staged), complex64 output
   if (!in32 || !out32) return hipErrorInvalidValue;
   return zpair32_launch(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st, wg_per_cu);
 }
