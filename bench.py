@@ -335,7 +335,7 @@ def main():
         summarize(args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding across GPUs is a design note, not implemented", file=sys.stderr)
         sys.exit(2)
 

@@ -63,7 +63,7 @@ typedef enum {
   ISDF_E_NOT_PD = -2,      /* a Hermitian matrix that must be positive definite was not */
   ISDF_E_DEVICE = -3,      /* HIP runtime error */
   ISDF_E_WORKSPACE = -4,   /* workspace NULL, too small or misaligned (256 B) */
-  ISDF_E_UNSUPPORTED = -5  /* valid request this build does not implement */
+  ISDF_E_UNSUPPORTED = -5  /* valid request the library does not implement */
 } isdf_status;
 
 typedef enum {
