@@ -3,6 +3,7 @@
 // with an optional Hermitian mode (lower tiles only, upper written as the
 // conjugate mirror).
 #include "internal.h"
+#include "kmajor.h"   // cu_count
 #include "tile.h"
 
 #include <algorithm>
@@ -134,6 +135,7 @@ __global__ void splitk_reduce_kernel(GemmP p, int nsplit) {
 }
 
 typedef Tile<double, 64, 64, 16, 2, 2> Tile64;
+typedef Tile<double, 32, 32, 16, 2, 2> Tile64s;   // FP64 products too small to fill the CUs with 64x64 tiles
 typedef Tile<float, 64, 64, 32, 2, 2> Tile32;
 
 template <typename T, typename SA, typename SB, typename SC, class TL, bool AMC, bool BNC>
@@ -194,6 +196,12 @@ hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st) {
   if (!(d.sam == 1 || d.sak == 1) || !(d.sbk == 1 || d.sbn == 1)) return hipErrorInvalidValue;
   if (compute == P64) {
     if (d.a32 || d.b32 || d.c32) return hipErrorInvalidValue;
+    // a single product with fewer 64 x 64 tiles than CUs (the N_mu x N_mu algebra) runs on
+    // 32 x 32 tiles: four times the workgroups, each a quarter of the MFMA work per K step
+    const long tm = cdiv(d.M, 64), tn = cdiv(d.N, 64);
+    const long t64 = d.herm ? tm * (tm + 1) / 2 : tm * tn;
+    if (d.batch <= 1 && !d.split_ws && t64 < cu_count())
+      return by_layout<double, double, double, double, Tile64s>(d, st);
     return by_layout<double, double, double, double, Tile64>(d, st);
   }
   if (d.a32) {
