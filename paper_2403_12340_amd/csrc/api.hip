@@ -250,7 +250,8 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += up(std::max<size_t>(bytes, 1)); return o; };
   L.kx = kx; L.ky = ky; L.kz = kz; L.nd = nd;
-  L.nsplit = std::min(P.nv, 2 * core_splits(P.nmu, P.nv));  // room for the tuned maximum (2x default)
+  // room for the tuned maximum of the generic core (2x default) and for the k-major core's split
+  L.nsplit = std::min(P.nv, std::max(2 * core_splits(P.nmu, P.nv), 32));
   L.status = take(sizeof(StatusBlock));
   L.psi_c = P.cplx ? 0 : take((size_t)P.ns * P.nr * z);
   L.pm = take((size_t)P.ns * P.nmu * z);

@@ -168,19 +168,18 @@ __global__ __launch_bounds__(ZL::NT) void core32_kernel(int nmu, int nv, int nc,
 
 bool core32_fits(int nmu, int nc) { return nmu >= ZL::BM && nmu % ZL::BM == 0 && nc >= 32 && nc % 32 == 0; }
 
-// Split of the occupied index: the smallest count whose workgroups fill whole
-// rounds of one per CU to at least 90% (else the best fill), at most max_split.
+// Split of the occupied index: the count s (at most max_split) that minimises the
+// makespan rounds(s) * ceil(nv / s), with rounds(s) the rounds of one workgroup per
+// CU that tiles * s workgroups take; the smallest such s (fewest partial sums).
 int core32_splits(int nmu, int nv, int max_split) {
   const int nti = nmu / ZL::BM, tiles = nti * (nti + 1);
-  const int slots = cu_count();
+  const long slots = cu_count();
   int best = 1;
-  double best_fill = 0.0;
+  long best_cost = -1;
   for (int s = 1; s <= std::max(1, std::min(nv, max_split)); ++s) {
-    const long wg = (long)tiles * s;
-    const long rounds = (wg + slots - 1) / slots;
-    const double fill = (double)wg / (double)(rounds * slots);
-    if (wg >= slots && fill >= 0.9) return s;
-    if (fill > best_fill + 1e-9) { best_fill = fill; best = s; }
+    const long rounds = ((long)tiles * s + slots - 1) / slots;
+    const long cost = rounds * ((nv + s - 1) / s);
+    if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = s; }
   }
   return best;
 }
