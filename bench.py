@@ -361,7 +361,7 @@ def main():
         plan = isdf.Plan(prob, inp.mu_idx, inp.miller)
         ws = plan.new_workspace()
         out = plan.new_output()
-        tune = plan.autotune(psi, e_dev, out, ws, reps=2) if not args.no_autotune else plan.get_tune()
+        tune = plan.autotune(psi, e_dev, out, ws, reps=6) if not args.no_autotune else plan.get_tune()
         print(f"[bench] {prec} tune {tune}", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             plan.eps_inv_async(psi, e_dev, out, ws)

@@ -92,7 +92,7 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
     for (int fm = 0; fm < ZL::FM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
-    zl_loop_full(smem, zf, nt, nt, sa, sb, A, lda, B, ldb, m0, n0, has_next, nm0, nn0, acc, acc, wm0, wn0, lane);
+    zl_range(smem, zf, 0, nt, sa, sb, A, lda, B, ldb, m0, n0, has_next, nm0, nn0, 0, acc, wm0, wn0, lane);
     if (!HERM) {
 #pragma unroll
       for (int fm = 0; fm < ZL::FM; ++fm)
@@ -152,8 +152,7 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
 #pragma unroll
       for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
     zf.fetch(As, lda, Bs, ldb, m0, n0, 0);
-    zl_loop_full(smem, zf, t1 - t0, t1 - t0, sa, sb, As, lda, Bs, ldb, m0, n0, false, 0, 0, acc, acc, wm0, wn0,
-                 lane);
+    zl_range(smem, zf, 0, t1 - t0, sa, sb, As, lda, Bs, ldb, m0, n0, false, 0, 0, 0, acc, wm0, wn0, lane);
     float* ws = tail_ws + (size_t)(xcd * nper + j) * ZL::BM * ZL::BN * 2;
 #pragma unroll
     for (int fm = 0; fm < ZL::FM; ++fm)

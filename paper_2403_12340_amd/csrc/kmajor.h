@@ -96,38 +96,37 @@ struct ZFetch {
   }
 };
 
-// K loop of one interior tile whose first K tile is already in `zf` (a ZFetch, or
-// a fetch of the same interface whose B operand has another storage type): K tiles
-// t < tp accumulate into accp, the rest into accq (pass the same array twice for
-// a single accumulator).  During the last K tile it prefetches the first K tile
-// of the next interior tile (if any), so that tile's load latency hides behind
-// this tile's MFMAs and epilogue.
+// K tiles [t0, t1) of one interior tile into the accumulator `acc`.  `z` (a
+// ZFetch, or a fetch of the same interface whose B operand has another storage
+// type) holds K tile t0, fetched and not yet staged, and both LDS stages are free
+// on entry.  During the last K tile it is refilled with K tile nk of the tile at
+// (nm0, nn0) if `refill` (the next range's first K tile), so that load's latency
+// hides behind this range's MFMAs.  Each kernel has a single instance of this
+// loop (a kernel with two accumulators runs its ranges through one call site), so
+// the loop-invariant LDS and global addresses are held once.
 template <class F, typename SB>
-__device__ __forceinline__ void zl_loop_full(float* smem, F& zf, int tp, int nt, float sa, float sb,
-                                             const c32* A, long lda, const SB* B, long ldb, int m0, int n0,
-                                             bool has_next, int nm0, int nn0, f4 (&accp)[ZL::FM][ZL::FN],
-                                             f4 (&accq)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
-  float* buf0 = smem;
-  float* buf1 = smem + ZL::AS + ZL::BS;
+__device__ __forceinline__ void zl_range(float* smem, F& z, int t0, int t1, float sa, float sb, const c32* A,
+                                         long lda, const SB* B, long ldb, int m0, int n0, bool refill, int nm0,
+                                         int nn0, int nk, f4 (&acc)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
+  if (t0 >= t1) return;
+  float* s0 = smem;
+  float* s1 = smem + ZL::AS + ZL::BS;
   auto prefetch = [&](int t) {
-    if (t < nt) zf.fetch(A, lda, B, ldb, m0, n0, t);
-    else if (has_next) zf.fetch(A, lda, B, ldb, nm0, nn0, 0);
+    if (t < t1) z.fetch(A, lda, B, ldb, m0, n0, t);
+    else if (refill) z.fetch(A, lda, B, ldb, nm0, nn0, nk);
   };
-  auto mma = [&](int t, const float* buf) {
-    if (t < tp) zl_mma(buf, buf + ZL::AS, accp, wm0, wn0, lane);
-    else zl_mma(buf, buf + ZL::AS, accq, wm0, wn0, lane);
-  };
-  zf.stage(buf0, sa, sb);
+  z.stage(s0, sa, sb);
   __syncthreads();
-  for (int t = 0; t < nt; t += 2) {
+  // two K tiles per pass, so both LDS stages are addressed statically
+  for (int t = t0; t < t1; t += 2) {
     prefetch(t + 1);
-    mma(t, buf0);
-    if (t + 1 < nt) zf.stage(buf1, sa, sb);
+    zl_mma(s0, s0 + ZL::AS, acc, wm0, wn0, lane);
+    if (t + 1 < t1) z.stage(s1, sa, sb);
     __syncthreads();
-    if (t + 1 >= nt) break;
+    if (t + 1 >= t1) break;
     prefetch(t + 2);
-    mma(t + 1, buf1);
-    if (t + 2 < nt) zf.stage(buf0, sa, sb);
+    zl_mma(s1, s1 + ZL::AS, acc, wm0, wn0, lane);
+    if (t + 2 < t1) z.stage(s0, sa, sb);
     __syncthreads();
   }
 }

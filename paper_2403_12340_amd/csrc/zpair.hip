@@ -195,7 +195,9 @@ struct ZFetchB64 {
 // Interior tiles (nti x ntj of them, all full): one workgroup per CU walks its
 // share with no inter-workgroup synchronisation.  The tiles of each XCD form a
 // contiguous range of the point-fastest tile order, dealt to that XCD's
-// workgroups in turn, so they share the grid-orbital panels in its L2.
+// workgroups in turn, so they share the grid-orbital panels in its L2.  The
+// occupied and the empty K ranges run through one K loop with one running
+// accumulator, whose occupied sum moves to accp at the boundary.
 __global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(3)))
 void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long ldb, float* out, long ldo,
                     int nti, int total) {
@@ -205,20 +207,34 @@ void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long 
   const int xcd = blockIdx.x % 8, nper = gridDim.x / 8, j = blockIdx.x / 8;
   const int per = (total + 7) / 8;
   const int lo = xcd * per, hi = min(total, lo + per);
+  const int tp = nv / ZL::BK, nt = ns / ZL::BK;
   ZFetchB64 zf;
   zf.init(tid, ldp, ldb);
   if (lo + j < hi) zf.fetch(pm, ldp, b, ldb, ((lo + j) % nti) * ZL::BM, ((lo + j) / nti) * ZL::BN, 0);
   for (int id = lo + j; id < hi; id += nper) {
     const int m0 = (id % nti) * ZL::BM, n0 = (id / nti) * ZL::BN;
     const int nid = id + nper;
-    const bool has_next = nid < hi;
     f4 accp[ZL::FM][ZL::FN], accq[ZL::FM][ZL::FN];
 #pragma unroll
     for (int fm = 0; fm < ZL::FM; ++fm)
 #pragma unroll
-      for (int fn = 0; fn < ZL::FN; ++fn) accp[fm][fn] = accq[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
-    zl_loop_full(smem, zf, nv / ZL::BK, ns / ZL::BK, -1.f, 1.f, pm, ldp, b, ldb, m0, n0, has_next,
-                 (nid % nti) * ZL::BM, (nid / nti) * ZL::BN, accp, accq, wm0, wn0, lane);
+      for (int fn = 0; fn < ZL::FN; ++fn) accq[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int ph = 0; ph < 2; ++ph) {
+      const bool last = ph == 1;
+      zl_range(smem, zf, last ? tp : 0, last ? nt : tp, -1.f, 1.f, pm, ldp, b, ldb, m0, n0,
+               last ? nid < hi : true, last ? (nid % nti) * ZL::BM : m0, last ? (nid / nti) * ZL::BN : n0,
+               last ? 0 : tp, accq, wm0, wn0, lane);
+      if (!last) {
+#pragma unroll
+        for (int fm = 0; fm < ZL::FM; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < ZL::FN; ++fn) {
+            accp[fm][fn] = accq[fm][fn];
+            accq[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+    }
     zl_epilogue(out, ldo, (m0 + ZL::BM), (n0 + ZL::BN), m0, n0, accp, accq, wm0, wn0, lane);
   }
 }
