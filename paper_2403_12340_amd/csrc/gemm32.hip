@@ -64,7 +64,7 @@ __device__ __forceinline__ void tile_origin(int id, int ntj, int& m0, int& n0) {
 }
 
 template <bool HERM>
-__global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(2)))
 void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, const c32* B, long ldb,
                    float sb, void* C, long ldc, float alpha, float* tail_ws) {
   __shared__ float smem[2 * (ZL::AS + ZL::BS)];

@@ -96,6 +96,35 @@ struct ZFetch {
   }
 };
 
+// Operands of one MFMA step of a K tile staged at `buf`: A at buf, B at buf + AS.
+struct ZFrag {
+  float a[ZL::FM], b[ZL::FN];
+};
+__device__ __forceinline__ void zl_frag(const float* buf, int kk, ZFrag& f, int wm0, int wn0, int lane) {
+  const int i = lane & 15, q = lane >> 4;
+  const float* ap = buf + ((q >> 1) * ZL::LDA + wm0 + i) * 2 + (q & 1);
+  const float* bp = buf + ZL::AS + ((q >> 1) * ZL::LDB + wn0 + (i >> 1)) * 4 + 2 * (q & 1) + (i & 1);
+#pragma unroll
+  for (int fm = 0; fm < ZL::FM; ++fm) f.a[fm] = ap[kk * 4 * ZL::LDA + fm * 32];
+#pragma unroll
+  for (int fn = 0; fn < ZL::FN; ++fn) f.b[fn] = bp[kk * 8 * ZL::LDB + fn * 32];
+}
+__device__ __forceinline__ void zl_step(const ZFrag& f, f4 (&acc)[ZL::FM][ZL::FN]) {
+#pragma unroll
+  for (int fm = 0; fm < ZL::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = Mfma<float>::op(f.a[fm], f.b[fn], acc[fm][fn]);
+}
+// issue order: the LDS reads just written in source order between the first MFMAs
+__device__ __forceinline__ void zl_interleave() {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, ZL::FM * ZL::FN - 3, 0);
+}
+
 // K tiles [t0, t1) of one interior tile into the accumulator `acc`.  `z` (a
 // ZFetch, or a fetch of the same interface whose B operand has another storage
 // type) holds K tile t0, fetched and not yet staged, and both LDS stages are free
@@ -104,10 +133,18 @@ struct ZFetch {
 // hides behind this range's MFMAs.  Each kernel has a single instance of this
 // loop (a kernel with two accumulators runs its ranges through one call site), so
 // the loop-invariant LDS and global addresses are held once.
+//
+// Per K tile: steps 0 .. BK/2 - 2 (each reading the next step's operands), then the
+// next K tile is staged and the barrier passed while the last step's operands are
+// already in registers, so the next tile's first LDS reads overlap the last step's
+// MFMAs.  Every read of a stage is issued before the barrier that precedes its
+// next overwrite (the barrier waits for outstanding LDS operations), and the last
+// K tile also ends with a barrier, so the LDS is free on return.
 template <class F, typename SB>
 __device__ __forceinline__ void zl_range(float* smem, F& z, int t0, int t1, float sa, float sb, const c32* A,
                                          long lda, const SB* B, long ldb, int m0, int n0, bool refill, int nm0,
                                          int nn0, int nk, f4 (&acc)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
+  constexpr int KK = ZL::BK / 2;
   if (t0 >= t1) return;
   float* s0 = smem;
   float* s1 = smem + ZL::AS + ZL::BS;
@@ -115,19 +152,31 @@ __device__ __forceinline__ void zl_range(float* smem, F& z, int t0, int t1, floa
     if (t < t1) z.fetch(A, lda, B, ldb, m0, n0, t);
     else if (refill) z.fetch(A, lda, B, ldb, nm0, nn0, nk);
   };
+  ZFrag f[2];
+  // one K tile staged at cur, its step-0 operands in f[0]; the next one (if any) goes to nxt
+  auto tile = [&](int t, const float* cur, float* nxt) {
+    prefetch(t + 1);
+#pragma unroll
+    for (int kk = 0; kk + 1 < KK; ++kk) {
+      const int c = kk & 1;
+      zl_frag(cur, kk + 1, f[c ^ 1], wm0, wn0, lane);
+      zl_step(f[c], acc);
+      zl_interleave();
+    }
+    if (t + 1 < t1) z.stage(nxt, sa, sb);
+    __syncthreads();
+    if (t + 1 < t1) zl_frag(nxt, 0, f[0], wm0, wn0, lane);
+    zl_step(f[(KK - 1) & 1], acc);
+    zl_interleave();
+  };
   z.stage(s0, sa, sb);
   __syncthreads();
+  zl_frag(s0, 0, f[0], wm0, wn0, lane);
   // two K tiles per pass, so both LDS stages are addressed statically
   for (int t = t0; t < t1; t += 2) {
-    prefetch(t + 1);
-    zl_mma(s0, s0 + ZL::AS, acc, wm0, wn0, lane);
-    if (t + 1 < t1) z.stage(s1, sa, sb);
-    __syncthreads();
+    tile(t, s0, s1);
     if (t + 1 >= t1) break;
-    prefetch(t + 2);
-    zl_mma(s1, s1 + ZL::AS, acc, wm0, wn0, lane);
-    if (t + 2 < t1) z.stage(s0, sa, sb);
-    __syncthreads();
+    tile(t + 1, s1, s0);
   }
 }
 

@@ -74,6 +74,9 @@ __device__ __forceinline__ bool pivot_gj(z64 (&w)[EW], z64 (*rowb)[NB], int gj, 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_panel_kernel(int n, const z64* __restrict__ ain,
                                                           z64* __restrict__ aout, int k0, int kn,
                                                           const z64* __restrict__ pin, int* status) {
+  // The sweep steps are latency-bound and run beside the pair kernel's waves: their
+  // waves take issue priority on the SIMDs they share.
+  __builtin_amdgcn_s_setprio(3);
   ain += (long)blockIdx.y * n * n;   // batch item
   aout += (long)blockIdx.y * n * n;
   __shared__ z64 W[NB][NB + 1];      // W[u][t] = P[t][u]: the k-major A operand of P (.)
@@ -170,6 +173,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
                                                            int k1, int kn1, int* status) {
   __shared__ z64 As[TU::AS];  // [t][i] = conj(A[k0 + t][m0 + i])
   __shared__ z64 Bs[TU::BS];  // [t][j] = R[t][n0 + j] (the pivot rows of A')
+  __builtin_amdgcn_s_setprio(3);   // issue priority beside the pair kernel, as in the panel
   ain += (long)blockIdx.y * n * n;   // batch item
   aout += (long)blockIdx.y * n * n;
   if (pout && blockIdx.x == gridDim.x - 1) {
