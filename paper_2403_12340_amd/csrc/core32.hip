@@ -129,23 +129,41 @@ __global__ __launch_bounds__(ZL::NT) void core32_kernel(int nmu, int nv, int nc,
   CFetch cf;
   cf.init(tid, nmu);
   auto fetch_step = [&](int s) { cf.fetch(pc, nmu, w + (long)(i0 + s / nt) * nc, m0, n0, s % nt); };
+  // One K tile (step s of the flattened (state, K tile) walk) staged at cur, its first MFMA
+  // step's operands in f[0]: MFMA steps 0 .. BK/2 - 2, then the next K tile is staged and
+  // the barrier passed before the last step (its operands already in registers), so the
+  // next tile's first LDS reads overlap it.  After a state's last K tile its G_i goes
+  // into the FP64 sums.
+  ZFrag f[2];
+  auto tile = [&](int s, const float* cur, float* nxt) {
+    constexpr int KK = ZL::BK / 2;
+    const bool end = s % nt == nt - 1;
+    if (s + 1 < S) fetch_step(s + 1);
+    if (end) load_a(i0 + s / nt);
+#pragma unroll
+    for (int kk = 0; kk + 1 < KK; ++kk) {
+      const int c = kk & 1;
+      zl_frag(cur, kk + 1, f[c ^ 1], wm0, wn0, lane);
+      zl_step(f[c], acc);
+      zl_interleave();
+    }
+    if (s + 1 < S) cf.stage(nxt);
+    __syncthreads();
+    if (s + 1 < S) zl_frag(nxt, 0, f[0], wm0, wn0, lane);
+    zl_step(f[(KK - 1) & 1], acc);
+    zl_interleave();
+    if (end) flush();
+  };
   if (S > 0) {
     fetch_step(0);
     cf.stage(buf0);
   }
   __syncthreads();
+  if (S > 0) zl_frag(buf0, 0, f[0], wm0, wn0, lane);
   // two steps per pass (S is even), so both LDS stages are addressed statically
   for (int s = 0; s < S; s += 2) {
-    if (s + 1 < S) fetch_step(s + 1);
-    zl_mma(buf0, buf0 + ZL::AS, acc, wm0, wn0, lane);
-    if (s + 1 < S) cf.stage(buf1);
-    __syncthreads();
-    if (s + 2 < S) fetch_step(s + 2);
-    if ((s + 1) % nt == nt - 1) load_a(i0 + (s + 1) / nt);
-    zl_mma(buf1, buf1 + ZL::AS, acc, wm0, wn0, lane);
-    if ((s + 1) % nt == nt - 1) flush();
-    if (s + 2 < S) cf.stage(buf0);
-    __syncthreads();
+    tile(s, buf0, buf1);
+    tile(s + 1, buf1, buf0);
   }
 
   float* out = reinterpret_cast<float*>(part + (long)split * nmu * nmu);
