@@ -75,6 +75,7 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
   const TailPlan tp = tail_plan(xcd, total, nper, nt, tail_ws != nullptr);
   const int lo = tp.lo, hi = tp.lo + tp.nfull;
   ZFetch zf;
+  ZFrag frag[2];
   zf.init(tid, lda, ldb);
   if (lo + j < hi) {
     int m0, n0;
@@ -92,7 +93,8 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
     for (int fm = 0; fm < ZL::FM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
-    zl_range(smem, zf, 0, nt, sa, sb, A, lda, B, ldb, m0, n0, has_next, nm0, nn0, 0, acc, wm0, wn0, lane);
+    zl_range(smem, zf, frag, 0, nt, false, sa, sb, A, lda, B, ldb, m0, n0, has_next, nm0, nn0, 0, acc, wm0,
+             wn0, lane);
     if (!HERM) {
 #pragma unroll
       for (int fm = 0; fm < ZL::FM; ++fm)
@@ -152,7 +154,8 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
 #pragma unroll
       for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
     zf.fetch(As, lda, Bs, ldb, m0, n0, 0);
-    zl_range(smem, zf, 0, t1 - t0, sa, sb, As, lda, Bs, ldb, m0, n0, false, 0, 0, 0, acc, wm0, wn0, lane);
+    zl_range(smem, zf, frag, 0, t1 - t0, false, sa, sb, As, lda, Bs, ldb, m0, n0, false, 0, 0, 0, acc, wm0,
+             wn0, lane);
     float* ws = tail_ws + (size_t)(xcd * nper + j) * ZL::BM * ZL::BN * 2;
 #pragma unroll
     for (int fm = 0; fm < ZL::FM; ++fm)

@@ -128,34 +128,40 @@ __device__ __forceinline__ void zl_interleave() {
 // K tiles [t0, t1) of one interior tile into the accumulator `acc`.  `z` (a
 // ZFetch, or a fetch of the same interface whose B operand has another storage
 // type) holds K tile t0, fetched and not yet staged, and both LDS stages are free
-// on entry.  During the last K tile it is refilled with K tile nk of the tile at
-// (nm0, nn0) if `refill` (the next range's first K tile), so that load's latency
-// hides behind this range's MFMAs.  Each kernel has a single instance of this
-// loop (a kernel with two accumulators runs its ranges through one call site), so
-// the loop-invariant LDS and global addresses are held once.
+// on entry; or, with `staged`, K tile t0 is already in stage 0 and its first MFMA
+// step's operands in f[0].  During the last K tile the loop fetches K tile nk of
+// the tile at (nm0, nn0) if `refill` (the next range's first K tile), else that
+// last K tile again; either way it stages what it fetched into the other stage and
+// loads its first operands into f[0].  With t1 - t0 even that stage is stage 0, so
+// a refilled K tile is ready for a call with `staged`.  Each kernel has a single
+// instance of this loop (a kernel with two accumulators runs its ranges through
+// one call site), so the loop-invariant LDS and global addresses are held once.
 //
 // Per K tile: steps 0 .. BK/2 - 2 (each reading the next step's operands), then the
 // next K tile is staged and the barrier passed while the last step's operands are
 // already in registers, so the next tile's first LDS reads overlap the last step's
-// MFMAs.  Every read of a stage is issued before the barrier that precedes its
-// next overwrite (the barrier waits for outstanding LDS operations), and the last
-// K tile also ends with a barrier, so the LDS is free on return.
+// MFMAs.  Fetch, staging and barrier happen for every K tile, with no condition,
+// so no path leaves loads in flight (the compiler would otherwise wait for them,
+// and with them for every store issued since, before the next fetch).  Every read
+// of a stage is issued before the barrier that precedes its next overwrite (the
+// barrier waits for outstanding LDS operations), and the last K tile also ends
+// with a barrier, so on return stage 1 is free, and stage 0 too unless the caller
+// uses the staged refill.
 template <class F, typename SB>
-__device__ __forceinline__ void zl_range(float* smem, F& z, int t0, int t1, float sa, float sb, const c32* A,
-                                         long lda, const SB* B, long ldb, int m0, int n0, bool refill, int nm0,
-                                         int nn0, int nk, f4 (&acc)[ZL::FM][ZL::FN], int wm0, int wn0, int lane) {
+__device__ __forceinline__ void zl_range(float* smem, F& z, ZFrag (&f)[2], int t0, int t1, bool staged, float sa,
+                                         float sb, const c32* A, long lda, const SB* B, long ldb, int m0, int n0,
+                                         bool refill, int nm0, int nn0, int nk, f4 (&acc)[ZL::FM][ZL::FN], int wm0,
+                                         int wn0, int lane) {
   constexpr int KK = ZL::BK / 2;
   if (t0 >= t1) return;
   float* s0 = smem;
   float* s1 = smem + ZL::AS + ZL::BS;
-  auto prefetch = [&](int t) {
-    if (t < t1) z.fetch(A, lda, B, ldb, m0, n0, t);
-    else if (refill) z.fetch(A, lda, B, ldb, nm0, nn0, nk);
-  };
-  ZFrag f[2];
-  // one K tile staged at cur, its step-0 operands in f[0]; the next one (if any) goes to nxt
+  // one K tile staged at cur, its step-0 operands in f[0]; the next one goes to nxt
   auto tile = [&](int t, const float* cur, float* nxt) {
-    prefetch(t + 1);
+    const bool inrange = t + 1 < t1;
+    const bool other = !inrange && refill;
+    z.fetch(A, lda, B, ldb, other ? nm0 : m0, other ? nn0 : n0, inrange ? t + 1 : (refill ? nk : t));
+    __builtin_amdgcn_sched_barrier(0);   // the loads stay ahead of this tile's MFMAs
 #pragma unroll
     for (int kk = 0; kk + 1 < KK; ++kk) {
       const int c = kk & 1;
@@ -163,15 +169,18 @@ __device__ __forceinline__ void zl_range(float* smem, F& z, int t0, int t1, floa
       zl_step(f[c], acc);
       zl_interleave();
     }
-    if (t + 1 < t1) z.stage(nxt, sa, sb);
+    __builtin_amdgcn_sched_barrier(0);   // and the staging (which waits for them) behind them
+    z.stage(nxt, sa, sb);
     __syncthreads();
-    if (t + 1 < t1) zl_frag(nxt, 0, f[0], wm0, wn0, lane);
+    zl_frag(nxt, 0, f[0], wm0, wn0, lane);
     zl_step(f[(KK - 1) & 1], acc);
     zl_interleave();
   };
-  z.stage(s0, sa, sb);
-  __syncthreads();
-  zl_frag(s0, 0, f[0], wm0, wn0, lane);
+  if (!staged) {
+    z.stage(s0, sa, sb);
+    __syncthreads();
+    zl_frag(s0, 0, f[0], wm0, wn0, lane);
+  }
   // two K tiles per pass, so both LDS stages are addressed statically
   for (int t = t0; t < t1; t += 2) {
     tile(t, s0, s1);

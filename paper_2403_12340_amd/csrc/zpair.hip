@@ -197,7 +197,13 @@ struct ZFetchB64 {
 // contiguous range of the point-fastest tile order, dealt to that XCD's
 // workgroups in turn, so they share the grid-orbital panels in its L2.  The
 // occupied and the empty K ranges run through one K loop with one running
-// accumulator, whose occupied sum moves to accp at the boundary.
+// accumulator, whose occupied sum moves to accp at the boundary.  EVEN (both
+// ranges an even number of K tiles): the first K tile is staged before the tile
+// loop and each range's last K tile stages the next range's first one, so no
+// range starts with a wait on global loads; the refill loads would otherwise be
+// waited for behind the previous tile's Z stores, which the memory counter
+// retires in issue order.
+template <bool EVEN>
 __global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(3)))
 void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long ldb, float* out, long ldo,
                     int nti, int total) {
@@ -209,8 +215,16 @@ void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long 
   const int lo = xcd * per, hi = min(total, lo + per);
   const int tp = nv / ZL::BK, nt = ns / ZL::BK;
   ZFetchB64 zf;
+  ZFrag frag[2];
   zf.init(tid, ldp, ldb);
-  if (lo + j < hi) zf.fetch(pm, ldp, b, ldb, ((lo + j) % nti) * ZL::BM, ((lo + j) / nti) * ZL::BN, 0);
+  if (lo + j < hi) {
+    zf.fetch(pm, ldp, b, ldb, ((lo + j) % nti) * ZL::BM, ((lo + j) / nti) * ZL::BN, 0);
+    if (EVEN) {   // every range then starts staged
+      zf.stage(smem, -1.f, 1.f);
+      __syncthreads();
+      zl_frag(smem, 0, frag[0], wm0, wn0, lane);
+    }
+  }
   for (int id = lo + j; id < hi; id += nper) {
     const int m0 = (id % nti) * ZL::BM, n0 = (id / nti) * ZL::BN;
     const int nid = id + nper;
@@ -222,9 +236,9 @@ void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long 
 #pragma unroll 1
     for (int ph = 0; ph < 2; ++ph) {
       const bool last = ph == 1;
-      zl_range(smem, zf, last ? tp : 0, last ? nt : tp, -1.f, 1.f, pm, ldp, b, ldb, m0, n0,
-               last ? nid < hi : true, last ? (nid % nti) * ZL::BM : m0, last ? (nid / nti) * ZL::BN : n0,
-               last ? 0 : tp, accq, wm0, wn0, lane);
+      zl_range(smem, zf, frag, last ? tp : 0, last ? nt : tp, EVEN, -1.f, 1.f, pm,
+               ldp, b, ldb, m0, n0, last ? nid < hi : true, last ? (nid % nti) * ZL::BM : m0,
+               last ? (nid / nti) * ZL::BN : n0, last ? 0 : tp, accq, wm0, wn0, lane);
       if (!last) {
 #pragma unroll
         for (int fm = 0; fm < ZL::FM; ++fm)
@@ -285,8 +299,13 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, l
     // wg_per_cu workgroups per CU (a multiple of 8: one share per XCD), never more than the tiles
     const int wpc = std::max(1, std::min(wg_per_cu, 4));
     const int g = std::max(8, std::min(8 * ((wpc * cu_count() + 7) / 8), 8 * (int)cdiv(interior, 8)));
-    hipLaunchKernelGGL(zpair32_kernel, dim3(g), dim3(ZL::NT), 0, st, nv, ns, (const c32*)pm, ldp,
-                       (const z64*)b, ldb, (float*)out, ldo, nti, interior);
+    const int tp = nv / ZL::BK, tq = (ns - nv) / ZL::BK;
+    if (tp >= 2 && tp % 2 == 0 && tq >= 2 && tq % 2 == 0)
+      hipLaunchKernelGGL(zpair32_kernel<true>, dim3(g), dim3(ZL::NT), 0, st, nv, ns, (const c32*)pm, ldp,
+                         (const z64*)b, ldb, (float*)out, ldo, nti, interior);
+    else
+      hipLaunchKernelGGL(zpair32_kernel<false>, dim3(g), dim3(ZL::NT), 0, st, nv, ns, (const c32*)pm, ldp,
+                         (const z64*)b, ldb, (float*)out, ldo, nti, interior);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -57,6 +57,10 @@ CONFIGS = {
     "tiles": dict(n=22, nv=16, nc=48, nmu=200, ng=600, complex=True, seed=10),
     # Full tiles everywhere (points and plane waves multiples of 128): the interior fast paths.
     "kmaj": dict(n=20, nv=16, nc=48, nmu=256, ng=512, complex=True, seed=11),
+    # Both state counts multiples of 32 (even numbers of K tiles in both pair ranges) on a
+    # 28^3 grid: the pair kernel's path that stages each range's first K tile ahead, with
+    # 686 interior tiles, so most workgroups walk several and refill across tiles.
+    "kmaj_even": dict(n=28, nv=32, nc=64, nmu=256, ng=512, complex=True, seed=15),
     # Points a multiple of 128 and Nc a multiple of 32: the single-precision core on the
     # k-major engine (one occupied state per split).
     "core32": dict(n=20, nv=12, nc=64, nmu=256, ng=400, complex=True, seed=13),

@@ -17,7 +17,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank", "tiles", "kmaj", "core32", "tail", "wide"]
+SMALL = ["tiny", "cfg0", "mid", "mid_real", "fullrank", "tiles", "kmaj", "kmaj_even", "core32", "tail", "wide"]
 TOL_EPS = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6}
 # bf16x3 stages: effective unit roundoff ~3 * 2^-16 (hi + lo split, lo*lo dropped) times cond(S) <= 2e2 here
 TOL_STAGE = {"fp64": 1e-10, "fp32": 1e-4, "bf16x3": 2e-3}
