@@ -104,7 +104,7 @@ def _phase_dispatches(db, steps, warmup):
     import sqlite3
     c = sqlite3.connect(db)
     rows = c.execute("select name, start, end, grid_x * grid_y * grid_z from kernels where "
-                     "name like 'isdf::zpair32_kernel(%' or name like '%zpair_kernel<double%' "
+                     "name like '%zpair32_kernel%' or name like '%zpair_kernel<double%' "
                      "order by start").fetchall()
     z32 = []
     for name, t0, t1, g in rows:
@@ -159,7 +159,7 @@ def summarize(args):
         for key, db, ctr in (("fetch", args.pmc_fetch, "FETCH_SIZE"), ("write", args.pmc_write, "WRITE_SIZE")):
             rows = _pmc_per_dispatch(db, ctr)
             copy = [v for n, g, v in rows if "split_rows_kernel" in n]
-            zp = [v for n, g, v in rows if n.startswith("isdf::zpair32_kernel(")]
+            zp = [v for n, g, v in rows if "zpair32_kernel" in n]   # either instantiation, not the edge kernel
             res[key] = (max(copy) if copy else None, sum(zp) / len(zp) if zp else None, len(zp))
         pad16 = lambda n: (n + 15) // 16 * 16
         kt = (pad16(inp.nv) + pad16(inp.nc)) // 16
