@@ -258,7 +258,7 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
  *                   x/y/z pass raises it to at least ceil(n[2] / 8)
  *   core_split_pct  split of the core M over the occupied index, percent of the
  *                   built-in choice, 25..200 (default 100)
- *   gram_split      cap on the split-K factor of X^H X, 1..16 (default 16)
+ *   gram_split      cap on the split-K factor of X^H X, 1..16 (default 8)
  *   wg_per_cu       workgroups per CU of the persistent single-precision kernels, 1..4
  *                   (default 1)
  *   core_stream     where the first frequency's core M runs: 0 on the caller's stream
@@ -283,8 +283,10 @@ isdf_status isdf_plan_get_tune(isdf_plan plan, isdf_tune* tune);
 /* Autotune a plan on real arguments (as for isdf_plan_eps_inv): times `reps`
  * enqueued calls per candidate with HIP events on the handle's stream, going
  * over the knobs one at a time (coordinate descent, each knob over a fixed
- * candidate list) and keeping the fastest; leaves the plan set to the choice
- * and returns it in `out` (optional).  Synchronises the stream. */
+ * candidate list) and keeping the fastest; a candidate replaces the current
+ * choice only when it is at least 0.5% faster, so timing noise does not move
+ * the knobs.  Leaves the plan set to the choice and returns it in `out`
+ * (optional).  Synchronises the stream. */
 isdf_status isdf_plan_autotune(isdf_plan plan, const void* psi, const double* energies, const double* omega,
                                void* workspace, size_t ws_bytes, void* eps_inv, int32_t reps, isdf_tune* out);
 

@@ -494,7 +494,7 @@ struct Timer {
 struct Tune {
   int dft_zb = 8;          // z-planes per DFT workgroup
   int core_split_pct = 100;  // core split count, percent of the default
-  int gram_split = 16;     // split-K cap of X^H X
+  int gram_split = 8;      // split-K cap of X^H X
   int wg_per_cu = 1;       // workgroups per CU of the persistent k-major kernels
   int core_stream = 0;     // first core: 0 main stream before Z, 1 side stream after Z, 2 side stream beside Z
 };
@@ -1683,6 +1683,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
     return ISDF_OK;
   };
   // coordinate descent over the knobs, each over its candidate list, keeping the best so far
+  // (a candidate must beat it by 0.5%)
   float best = 0.f;
   TRY(time_call(best));
   const int zbs[] = {4, 6, 8, 12, 16, 24};
@@ -1698,7 +1699,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
       pl->tune.*knob = cands[i];
       float ms = 0.f;
       TRY(time_call(ms));
-      if (ms < best) { best = ms; arg = cands[i]; }
+      if (ms < 0.995f * best) { best = ms; arg = cands[i]; }   // 0.5% margin against timing noise
     }
     pl->tune.*knob = arg;
     return ISDF_OK;
