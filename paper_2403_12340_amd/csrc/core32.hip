@@ -135,11 +135,16 @@ __global__ __launch_bounds__(ZL::NT) void core32_kernel(int nmu, int nv, int nc,
   // next tile's first LDS reads overlap it.  After a state's last K tile its G_i goes
   // into the FP64 sums.
   ZFrag f[2];
+  // The fetch, staging and barrier happen for every K tile (the last one fetches itself
+  // again into the free stage), so no path leaves loads in flight for the compiler to
+  // wait on before the next fetch; scheduling barriers keep the loads at the top of the
+  // tile and the staging behind the MFMA steps.
   auto tile = [&](int s, const float* cur, float* nxt) {
     constexpr int KK = ZL::BK / 2;
     const bool end = s % nt == nt - 1;
-    if (s + 1 < S) fetch_step(s + 1);
+    fetch_step(s + 1 < S ? s + 1 : s);
     if (end) load_a(i0 + s / nt);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kk = 0; kk + 1 < KK; ++kk) {
       const int c = kk & 1;
@@ -147,9 +152,10 @@ __global__ __launch_bounds__(ZL::NT) void core32_kernel(int nmu, int nv, int nc,
       zl_step(f[c], acc);
       zl_interleave();
     }
-    if (s + 1 < S) cf.stage(nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    cf.stage(nxt);
     __syncthreads();
-    if (s + 1 < S) zl_frag(nxt, 0, f[0], wm0, wn0, lane);
+    zl_frag(nxt, 0, f[0], wm0, wn0, lane);
     zl_step(f[(KK - 1) & 1], acc);
     zl_interleave();
     if (end) flush();
