@@ -63,7 +63,12 @@ __device__ __forceinline__ void tile_origin(int id, int ntj, int& m0, int& n0) {
   n0 = bn * ZL::BN;
 }
 
-template <bool HERM>
+// EVEN (plain output, an even number of K tiles): the first K tile is staged before
+// the tile loop and each tile's last K tile stages the next tile's first one, so no
+// tile starts with a wait on global loads (which the memory counter would retire
+// only after the previous tile's output stores).  The Hermitian output goes through
+// the LDS, so it stages at the start of every tile.
+template <bool HERM, bool EVEN>
 __global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(2)))
 void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, const c32* B, long ldb,
                    float sb, void* C, long ldc, float alpha, float* tail_ws) {
@@ -77,10 +82,16 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
   ZFetch zf;
   ZFrag frag[2];
   zf.init(tid, lda, ldb);
+  static_assert(!(HERM && EVEN), "the Hermitian epilogue uses the LDS stages");
   if (lo + j < hi) {
     int m0, n0;
     tile_origin<HERM>(lo + j, ntj, m0, n0);
     zf.fetch(A, lda, B, ldb, m0, n0, 0);
+    if (EVEN) {
+      zf.stage(smem, sa, sb);
+      __syncthreads();
+      zl_frag(smem, 0, frag[0], wm0, wn0, lane);
+    }
   }
   const int rc = lane & 15, part = rc & 1;
   for (int id = lo + j; id < hi; id += nper) {
@@ -93,7 +104,7 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
     for (int fm = 0; fm < ZL::FM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < ZL::FN; ++fn) acc[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
-    zl_range(smem, zf, frag, 0, nt, false, sa, sb, A, lda, B, ldb, m0, n0, has_next, nm0, nn0, 0, acc, wm0,
+    zl_range(smem, zf, frag, 0, nt, EVEN, sa, sb, A, lda, B, ldb, m0, n0, has_next, nm0, nn0, 0, acc, wm0,
              wn0, lane);
     if (!HERM) {
 #pragma unroll
@@ -238,11 +249,14 @@ hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conj
   for (int x = 0; ws && x < 8; ++x) any_tail |= tail_plan(x, total, nper, nt, true).ntail > 0;
   if (!any_tail) ws = nullptr;
   if (herm_identity)
-    hipLaunchKernelGGL(gemm32_kernel<true>, dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A, lda, sa,
-                       (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
+    hipLaunchKernelGGL((gemm32_kernel<true, false>), dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A,
+                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
+  else if (nt % 2 == 0)
+    hipLaunchKernelGGL((gemm32_kernel<false, true>), dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A,
+                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
   else
-    hipLaunchKernelGGL(gemm32_kernel<false>, dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A, lda, sa,
-                       (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
+    hipLaunchKernelGGL((gemm32_kernel<false, false>), dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A,
+                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !ws) return e;
   int max_tail = 0;
