@@ -56,6 +56,7 @@ extern "C" {
 
 typedef struct isdf_handle_s* isdf_handle;
 typedef struct isdf_plan_s* isdf_plan;
+typedef struct isdf_graph_s* isdf_graph;
 
 typedef enum {
   ISDF_OK = 0,
@@ -84,7 +85,8 @@ typedef struct {
   double v_scale;        /* Coulomb prefactor; Nr / cell volume for unit-norm grid orbitals */
   int32_t prec;          /* isdf_precision */
   int32_t refine_steps;  /* FP64 Newton refinement steps T <- T + T (I - H T) on the core inverse, 0..8 */
-  int32_t coulomb_sum;   /* plane waves the Coulomb Gram Z^H V Z sums over (eqs. 11-13):
+  int32_t coulomb_sum;   /* plane waves the Coulomb Gram sums over (the P^H V P of Algorithm 3,
+                            step 2, inside eq. epsilon_with_SMW):
                             0: the ng-vector list (the truncated basis, default);
                             1: every grid vector, the paper's P^H V P over the whole FFT grid.
                             The output is the ng x ng block over the list in both cases; with 1
@@ -203,8 +205,8 @@ isdf_status isdf_smw_apply(isdf_handle h, const isdf_problem* prob, const void* 
  * the validated problem, the interpolation points, the plane-wave list, the
  * pruned-DFT index tables and the workspace layout.  isdf_plan_create checks
  * these inputs on the host (same rules as isdf_eps_inv), builds the tables and
- * copies them to a small device buffer owned by the plan (the only device
- * allocation the library makes; freed by isdf_plan_destroy).
+ * copies them into a small device buffer the caller provides (its size from
+ * isdf_plan_table_bytes); the plan also keeps its device status block there.
  *
  * isdf_plan_eps_inv then only enqueues work on the handle's stream: no host
  * synchronisation, no host-to-device copy, so a loop of calls keeps the GPU
@@ -215,14 +217,28 @@ isdf_status isdf_smw_apply(isdf_handle h, const isdf_problem* prob, const void* 
  * and each call's workspace must not be in use by another call still in flight
  * (calls on one stream are ordered, so one workspace can serve a whole loop). */
 
+/* Device bytes of a plan's tables for these arguments (host only, no handle or
+ * GPU needed; arguments as for isdf_plan_create).  Errors as isdf_plan_create's
+ * host checks: ISDF_E_ARG, ISDF_E_UNSUPPORTED. */
+isdf_status isdf_plan_table_bytes(const isdf_problem* prob, const int32_t* mu_idx, int32_t n_mu,
+                                  const int32_t* miller, int32_t ng, int32_t n_omega, size_t* bytes);
+
 /* Create a plan for `prob` with n_mu points mu_idx, ng plane waves miller and
  * n_omega frequencies per call (0 = static); arguments as for isdf_eps_inv
- * (host arrays, copied).  Errors: ISDF_E_ARG, ISDF_E_UNSUPPORTED, ISDF_E_DEVICE. */
+ * (host arrays, copied).
+ *   tables       device, caller-owned, >= isdf_plan_table_bytes(...), 256-byte aligned;
+ *                written here (a copy on the handle's stream, then a stream
+ *                synchronisation) and used by every call of the plan, so it must
+ *                stay allocated and untouched until isdf_plan_destroy
+ *   table_bytes  its size
+ * Errors: ISDF_E_ARG, ISDF_E_UNSUPPORTED, ISDF_E_WORKSPACE (tables NULL, too
+ * small or misaligned), ISDF_E_DEVICE. */
 isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int32_t* mu_idx,
                              int32_t n_mu, const int32_t* miller, int32_t ng, int32_t n_omega,
-                             isdf_plan* plan);
+                             void* tables, size_t table_bytes, isdf_plan* plan);
 
-/* Destroy a plan (waits for the handle's stream).  NULL is accepted. */
+/* Destroy a plan (waits for the streams of its calls).  NULL is accepted.  The
+ * table buffer stays the caller's. */
 isdf_status isdf_plan_destroy(isdf_plan plan);
 
 /* Device workspace bytes one isdf_plan_eps_inv call needs. */
@@ -245,13 +261,38 @@ isdf_status isdf_plan_eps_inv(isdf_plan plan, const void* psi, const double* ene
  * has frequencies), workspace[i] / ws_bytes[i], eps_inv[i], each as for
  * isdf_plan_eps_inv.  The work of plans whose handles are bound to other
  * streams is forked off plans[0]'s stream and joined back into it, so the
- * systems run concurrently and the whole call can be captured into one graph
- * on plans[0]'s stream; plans sharing a handle run one after another.  All
+ * systems run concurrently; plans sharing a handle run one after another.  All
  * plans must be on one device.  Only enqueues; each plan reports its own
- * device errors at its next isdf_plan_sync. */
+ * device errors at its next isdf_plan_sync.
+ * Stream capture: when plans[0]'s stream is capturing, every plan must be bound
+ * to that same stream (the systems then run one after another in the graph);
+ * otherwise ISDF_E_UNSUPPORTED and nothing is enqueued.  For concurrent systems
+ * in one graph use isdf_multi_graph_create. */
 isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const void* const* psi,
                                     const double* const* energies, const double* const* omega,
                                     void* const* workspace, const size_t* ws_bytes, void* const* eps_inv);
+
+/* Several systems as one instantiated HIP graph whose systems run concurrently.
+ * Arguments as for isdf_plan_eps_inv_multi; they are baked into the graph, so
+ * every buffer must stay allocated while the graph exists, and each system
+ * needs its own workspace and output (ISDF_E_ARG otherwise).  Each plan's call
+ * is captured on its own handle's stream (which must be a created stream, not
+ * the null stream) and becomes a child graph of one parent graph, with no
+ * dependencies between the children.  Capturing enqueues nothing; stage timing
+ * is not recorded inside the graph.  Errors: ISDF_E_ARG, ISDF_E_WORKSPACE,
+ * ISDF_E_DEVICE (a capture or instantiation error). */
+isdf_status isdf_multi_graph_create(int32_t count, const isdf_plan* plans, const void* const* psi,
+                                    const double* const* energies, const double* const* omega,
+                                    void* const* workspace, const size_t* ws_bytes,
+                                    void* const* eps_inv, isdf_graph* graph);
+
+/* Launch the graph on `hip_stream` (a hipStream_t, NULL = null stream).  The
+ * plans' next isdf_plan_sync waits for that stream and returns the device errors
+ * of the launch.  Launches of one graph must not overlap. */
+isdf_status isdf_graph_launch(isdf_graph graph, void* hip_stream);
+
+/* Destroy the graph (NULL is accepted); the plans and buffers stay the caller's. */
+isdf_status isdf_graph_destroy(isdf_graph graph);
 
 /* Launch-shape knobs of a plan (a project-written autotuner chooses them):
  *   dft_zb          z-planes per workgroup of the DFT, 1..64 (default 8); the fused
@@ -290,8 +331,8 @@ isdf_status isdf_plan_get_tune(isdf_plan plan, isdf_tune* tune);
 isdf_status isdf_plan_autotune(isdf_plan plan, const void* psi, const double* energies, const double* omega,
                                void* workspace, size_t ws_bytes, void* eps_inv, int32_t reps, isdf_tune* out);
 
-/* Wait for the handle's stream and return the first error any call enqueued
- * since the previous sync found on the device: ISDF_E_ARG (energies without a
+/* Wait for the stream of the plan's last call (or graph launch) and return the
+ * first error any call enqueued since the previous sync found on the device: ISDF_E_ARG (energies without a
  * gap or not finite), ISDF_E_NOT_PD; then clear it.  rep (optional) receives
  * the last call's min_pivot and refinement residuals, and, with stage timing
  * on, stage_ms = the mean of each stage's HIP-event interval over the calls

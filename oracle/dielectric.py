@@ -329,3 +329,60 @@ def core_entries(psi_t, energies, nv, mu_idx, pairs, f=PAIR_FACTOR, omega=0.0) -
         cb = np.conj(psi_t[:nv, rb])[:, None] * psi_t[nv:, rb][None, :]
         out[t] = f * np.sum(ca * w * np.conj(cb))
     return out
+
+
+# ----------------------------------------------------------------------------
+# The same definitions evaluated with bounded memory (full-size references)
+# ----------------------------------------------------------------------------
+def state_coefficients(psi_t, nv, mu_idx, i) -> np.ndarray:
+    """The block of C for one occupied state i: C_i(mu, j) = conj(psi_i(r_mu)) psi_j(r_mu), (N_mu, Nc)."""
+    pts = psi_t[:, mu_idx]
+    return (np.conj(pts[i])[:, None] * pts[nv:].T).astype(np.complex128)
+
+
+def isdf_gram_by_state(psi_t, nv, mu_idx) -> np.ndarray:
+    """S = C C^H summed over the occupied index: S = sum_i C_i C_i^H (C never held whole)."""
+    nmu = len(mu_idx)
+    s = np.zeros((nmu, nmu), dtype=np.complex128)
+    for i in range(nv):
+        ci = state_coefficients(psi_t, nv, mu_idx, i)
+        s += ci @ np.conj(ci.T)
+    return s
+
+
+def core_matrix_by_state(psi_t, energies, nv, mu_idx, f=PAIR_FACTOR, omega=0.0) -> np.ndarray:
+    """f C diag(w) C^H summed over the occupied index: f sum_i C_i diag(w_i) C_i^H (eq. COmegaCstar)."""
+    nmu = len(mu_idx)
+    w = pair_weights(energies, nv, omega)
+    m = np.zeros((nmu, nmu), dtype=np.complex128)
+    for i in range(nv):
+        ci = state_coefficients(psi_t, nv, mu_idx, i)
+        m += f * (ci * w[i][None, :]) @ np.conj(ci.T)
+    return m
+
+
+def isdf_stages_chunked(inp, f=PAIR_FACTOR, omega=0.0, v_scale=None, chunk=16384, mu_chunk=128) -> dict:
+    """isdf_stages with bounded memory: S and M summed over the occupied index,
+    Theta = Z S^{-1} (eq. MatrixExpressionISDF, least squares) formed by blocks of
+    grid rows, and Theta_G = F Theta by blocks of columns.  Theta itself (Nr x N_mu)
+    is the only full-size array held."""
+    psi_t, nv, mu = inp.psi_t, inp.nv, inp.mu_idx
+    nr, nmu = psi_t.shape[1], len(mu)
+    s = isdf_gram_by_state(psi_t, nv, mu)
+    lu = scipy.linalg.lu_factor(s)
+    pv, pc = psi_t[:nv], psi_t[nv:]
+    av, ac = np.conj(pv[:, mu]), np.conj(pc[:, mu])
+    theta = np.empty((nr, nmu), dtype=np.complex128)
+    for r0 in range(0, nr, chunk):
+        r1 = min(nr, r0 + chunk)
+        z = np.conj(pv[:, r0:r1].T @ av) * (pc[:, r0:r1].T @ ac)     # Z rows (isdf_rhs)
+        # Theta S = Z  <=>  S Theta^H = Z^H
+        theta[r0:r1] = np.conj(scipy.linalg.lu_solve(lu, np.conj(z.T)).T)
+    tg = np.empty((len(inp.miller), nmu), dtype=np.complex128)
+    for c0 in range(0, nmu, mu_chunk):
+        c1 = min(nmu, c0 + mu_chunk)
+        tg[:, c0:c1] = theta_pw(theta[:, c0:c1], inp.n, inp.miller)
+    v = coulomb_factor(inp, v_scale)
+    u = np.sqrt(v)[:, None] * tg
+    m = core_matrix_by_state(psi_t, inp.energies, nv, mu, f, omega)
+    return dict(theta=theta, theta_g=tg, v=v, u=u, m=m, s=s)

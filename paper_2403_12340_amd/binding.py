@@ -79,7 +79,8 @@ def lib() -> ctypes.CDLL:
             "isdf_grad_workspace_bytes": [pprob, i32, i32, ctypes.POINTER(sz)],
             "isdf_contour_nodes": [pdbl, i32, i32, dbl, pdbl, ctypes.POINTER(i32)],
             "isdf_eps_inv_grad": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, dbl, vp, vp, sz, vp, vp, pdbl],
-            "isdf_plan_create": [vp, pprob, pi32, i32, pi32, i32, i32, ctypes.POINTER(vp)],
+            "isdf_plan_table_bytes": [pprob, pi32, i32, pi32, i32, i32, ctypes.POINTER(sz)],
+            "isdf_plan_create": [vp, pprob, pi32, i32, pi32, i32, i32, vp, sz, ctypes.POINTER(vp)],
             "isdf_plan_destroy": [vp],
             "isdf_plan_workspace_bytes": [vp, ctypes.POINTER(sz)],
             "isdf_plan_eps_inv": [vp, vp, vp, pdbl, vp, sz, vp],
@@ -90,6 +91,11 @@ def lib() -> ctypes.CDLL:
             "isdf_plan_autotune": [vp, vp, vp, pdbl, vp, sz, vp, i32, ctypes.POINTER(Tune)],
             "isdf_plan_eps_inv_multi": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                         ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp)],
+            "isdf_multi_graph_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp)],
+            "isdf_graph_launch": [vp, vp],
+            "isdf_graph_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -439,9 +445,18 @@ class Plan:
         mu, pmu = _i32(mu_idx)
         mi, pmi = _i32(miller)
         self.nmu, self.ng, self.n_omega = len(mu), len(mi), int(n_omega)
+        import torch
+        tb = ctypes.c_size_t(0)
+        st = lib().isdf_plan_table_bytes(ctypes.byref(prob), pmu, len(mu), pmi, len(mi), self.n_omega,
+                                         ctypes.byref(tb))
+        if st != OK:
+            raise IsdfError(st, "isdf_plan_table_bytes rejected the plan's arguments")
+        # the plan's device tables live in this caller-owned buffer for the plan's lifetime
+        self._tables, tptr = _workspace(int(tb.value), f"cuda:{device}")
         p = ctypes.c_void_p()
         self.h.check(lib().isdf_plan_create(self.h.h, ctypes.byref(prob), pmu, len(mu), pmi, len(mi),
-                                            self.n_omega, ctypes.byref(p)), "isdf_plan_create")
+                                            self.n_omega, ctypes.c_void_p(tptr), int(tb.value), ctypes.byref(p)),
+                     "isdf_plan_create")
         self.p = p
         out = ctypes.c_size_t(0)
         self.h.check(lib().isdf_plan_workspace_bytes(self.p, ctypes.byref(out)), "isdf_plan_workspace_bytes")
@@ -511,8 +526,8 @@ class Plan:
         self.h.check(lib().isdf_plan_time_stages(self.p, 1 if on else 0), "isdf_plan_time_stages")
 
     def sync(self) -> Report:
+        """isdf_plan_sync: waits for the stream of the plan's last call or graph launch."""
         rep = Report()
-        self.h.sync_stream()
         self.h.check(lib().isdf_plan_sync(self.p, ctypes.byref(rep)), "isdf_plan_sync")
         return rep
 
@@ -564,6 +579,63 @@ def eps_inv_multi(plans, psis, energies_devs, outs, workspaces, omegas=None):
     st = lib().isdf_plan_eps_inv_multi(n, P, PS, E, OM, WS, SZ, O)
     plans[0].h.check(st, "isdf_plan_eps_inv_multi")
     return outs
+
+
+class MultiGraph:
+    """isdf_multi_graph_create: several plans' calls as one HIP graph whose systems run
+    concurrently (each captured on its own plan's stream, joined as child graphs).
+    The buffers are baked into the graph and kept alive by this object."""
+
+    def __init__(self, plans, psis, energies_devs, outs, workspaces, omegas=None):
+        n = len(plans)
+        if not (len(psis) == len(energies_devs) == len(outs) == len(workspaces) == n):
+            raise ValueError("one psi, energies, output and workspace per plan")
+        for p, psi, e, w in zip(plans, psis, energies_devs, workspaces):
+            _check_psi(psi, p.prob)
+            if w is None:
+                raise ValueError("pass each plan's workspace")
+        vp = ctypes.c_void_p
+        self._keep = [plans, psis, energies_devs, outs]
+        P = (vp * n)(*[p.p for p in plans])
+        PS = (vp * n)(*[psi.data_ptr() for psi in psis])
+        E = (vp * n)(*[e.data_ptr() for e in energies_devs])
+        OM = None
+        if omegas is not None:
+            arrs = [np.ascontiguousarray(np.zeros(0) if om is None else np.asarray(om, dtype=np.float64))
+                    for om in omegas]
+            for p, a in zip(plans, arrs):
+                if len(a) != p.n_omega:
+                    raise ValueError("each plan's frequency count must match")
+            self._keep.append(arrs)
+            OM = (vp * n)(*[a.ctypes.data if len(a) else None for a in arrs])
+        W = []
+        for p, w, psi in zip(plans, workspaces, psis):
+            wsbuf, wsptr = _workspace(p.workspace_bytes, psi.device, w)
+            W.append(wsptr)
+            self._keep.append(wsbuf)
+        WS = (vp * n)(*W)
+        SZ = (ctypes.c_size_t * n)(*[p.workspace_bytes for p in plans])
+        O = (vp * n)(*[o.data_ptr() for o in outs])
+        g = ctypes.c_void_p()
+        st = lib().isdf_multi_graph_create(n, P, PS, E, OM, WS, SZ, O, ctypes.byref(g))
+        plans[0].h.check(st, "isdf_multi_graph_create")
+        self.g = g
+        self.plans = plans
+
+    def launch(self, stream=None):
+        """isdf_graph_launch on `stream` (a torch stream; default: torch's current one)."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.plans[0].device)
+        st = lib().isdf_graph_launch(self.g, ctypes.c_void_p(s.cuda_stream))
+        if st != OK:
+            raise IsdfError(st, "isdf_graph_launch failed")
+
+    def __del__(self):
+        try:
+            if getattr(self, "g", None):
+                lib().isdf_graph_destroy(self.g)
+        except Exception:
+            pass
 
 
 def problem_for(inp, prec="fp64", refine_steps=0, v_scale=None, coulomb_sum=0, core_method=0, core_tol=0.0) -> Problem:

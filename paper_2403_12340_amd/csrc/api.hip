@@ -1200,7 +1200,7 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   h->pinned_bytes = 1 << 20;
   if (hipHostMalloc(&h->pinned, h->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
-    delete h;
+    (void)isdf_destroy(h);
     return ISDF_E_DEVICE;
   }
   *out = h;
@@ -1441,20 +1441,30 @@ struct isdf_plan_s {
   Layout L;
   Tune tune;
   int n_omega = 0;
-  void* dev = nullptr;  // status block, point indices, Miller list, reciprocal basis, DFT tables
+  void* dev = nullptr;  // caller's table buffer: status block, point indices, Miller list, reciprocal basis, DFT tables
   size_t off_mu = 0, off_miller = 0, off_recip = 0, off_idx = 0;
   // per-call stage timing (isdf_plan_time_stages): 10 events per call since the last sync
   bool timing = false;
   std::vector<hipEvent_t> tev;
   int tn = 0, tmarks = 0;
+  hipStream_t last = nullptr;   // stream of the last enqueued call (isdf_plan_sync waits for it)
+  bool last_set = false;
 };
 
-isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int32_t* mu_idx, int32_t n_mu,
-                             const int32_t* miller, int32_t ng, int32_t n_omega, isdf_plan* out) {
-  if (!h || !out) return ISDF_E_ARG;
-  *out = nullptr;
-  if (n_omega < 0) return fail(h, ISDF_E_ARG, "n_omega must be >= 0");
+namespace {
+
+// Host image of a plan's device tables (validated problem, points, plane waves).
+struct PlanTables {
   Problem P;
+  Layout L;
+  size_t off_mu = 0, off_miller = 0, off_recip = 0, off_idx = 0, total = 0;
+  std::vector<char> host;
+};
+
+isdf_status plan_tables(isdf_handle h, const isdf_problem* prob, const int32_t* mu_idx, int32_t n_mu,
+                        const int32_t* miller, int32_t ng, int32_t n_omega, PlanTables& T) {
+  if (n_omega < 0) return fail(h, ISDF_E_ARG, "n_omega must be >= 0");
+  Problem& P = T.P;
   TRY(begin(h, prob, P, n_mu, ng, n_omega));
   if (P.core_method == 1)
     return fail(h, ISDF_E_UNSUPPORTED, "plans take device energies; the contour-integral core needs them on the host");
@@ -1471,30 +1481,57 @@ isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int3
   std::vector<int> idxbuf;
   for (auto* v : {&ix.xl, &ix.yl, &ix.zl, &ix.d_ax, &ix.d_by, &ix.g_d, &ix.g_cz, &ix.dmap, &ix.gd_off, &ix.gd_list})
     idxbuf.insert(idxbuf.end(), v->begin(), v->end());
+  T.L = make_layout(P, (int)ix.xl.size(), (int)ix.yl.size(), (int)ix.zl.size(), (int)ix.d_ax.size());
+  size_t off = up(sizeof(StatusBlock));
+  T.off_mu = off; off += up((size_t)n_mu * 4);
+  T.off_miller = off; off += up((size_t)P.ngg * 12);
+  T.off_recip = off; off += up(9 * 8);
+  T.off_idx = off; off += up(idxbuf.size() * 4);
+  T.total = off;
+  T.host.assign(off, 0);
+  std::memcpy(T.host.data() + T.off_mu, mu_idx, (size_t)n_mu * 4);
+  std::memcpy(T.host.data() + T.off_miller, miller, (size_t)P.ngg * 12);
+  std::memcpy(T.host.data() + T.off_recip, P.recip, 9 * 8);
+  std::memcpy(T.host.data() + T.off_idx, idxbuf.data(), idxbuf.size() * 4);
+  return ISDF_OK;
+}
+
+}  // namespace
+
+isdf_status isdf_plan_table_bytes(const isdf_problem* prob, const int32_t* mu_idx, int32_t n_mu,
+                                  const int32_t* miller, int32_t ng, int32_t n_omega, size_t* bytes) {
+  if (!bytes) return ISDF_E_ARG;
+  isdf_handle_s tmp;
+  PlanTables T;
+  TRY(plan_tables(&tmp, prob, mu_idx, n_mu, miller, ng, n_omega, T));
+  *bytes = T.total;
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_create(isdf_handle h, const isdf_problem* prob, const int32_t* mu_idx, int32_t n_mu,
+                             const int32_t* miller, int32_t ng, int32_t n_omega, void* tables,
+                             size_t table_bytes, isdf_plan* out) {
+  if (!h || !out) return ISDF_E_ARG;
+  *out = nullptr;
+  PlanTables T;
+  TRY(plan_tables(h, prob, mu_idx, n_mu, miller, ng, n_omega, T));
+  if (!tables) return fail(h, ISDF_E_WORKSPACE, "plan table buffer is NULL");
+  if (reinterpret_cast<uintptr_t>(tables) % ALIGN) return fail(h, ISDF_E_WORKSPACE, "plan table buffer not 256-byte aligned");
+  if (table_bytes < T.total)
+    return fail(h, ISDF_E_WORKSPACE, "plan table buffer too small: need " + std::to_string(T.total) + " bytes");
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipMemcpyAsync(tables, T.host.data(), T.total, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
   isdf_plan pl = new isdf_plan_s;
   pl->h = h;
-  pl->P = P;
+  pl->P = T.P;
+  pl->L = T.L;
   pl->n_omega = n_omega;
-  pl->L = make_layout(P, (int)ix.xl.size(), (int)ix.yl.size(), (int)ix.zl.size(), (int)ix.d_ax.size());
-  size_t off = up(sizeof(StatusBlock));
-  pl->off_mu = off; off += up((size_t)n_mu * 4);
-  pl->off_miller = off; off += up((size_t)P.ngg * 12);
-  pl->off_recip = off; off += up(9 * 8);
-  pl->off_idx = off; off += up(idxbuf.size() * 4);
-  std::vector<char> host(off, 0);
-  std::memcpy(host.data() + pl->off_mu, mu_idx, (size_t)n_mu * 4);
-  std::memcpy(host.data() + pl->off_miller, miller, (size_t)P.ngg * 12);
-  std::memcpy(host.data() + pl->off_recip, P.recip, 9 * 8);
-  std::memcpy(host.data() + pl->off_idx, idxbuf.data(), idxbuf.size() * 4);
-  auto bail = [&](hipError_t e) {
-    if (pl->dev) (void)hipFree(pl->dev);
-    delete pl;
-    return fail(h, ISDF_E_DEVICE, std::string("plan setup: ") + hipGetErrorString(e));
-  };
-  hipError_t e = hipSetDevice(h->device);
-  if (e == hipSuccess) e = hipMalloc(&pl->dev, off);
-  if (e == hipSuccess) e = hipMemcpy(pl->dev, host.data(), off, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return bail(e);
+  pl->dev = tables;
+  pl->off_mu = T.off_mu;
+  pl->off_miller = T.off_miller;
+  pl->off_recip = T.off_recip;
+  pl->off_idx = T.off_idx;
   *out = pl;
   h->err.clear();
   return ISDF_OK;
@@ -1504,7 +1541,7 @@ isdf_status isdf_plan_destroy(isdf_plan pl) {
   if (!pl) return ISDF_OK;
   (void)hipSetDevice(pl->h->device);
   (void)hipStreamSynchronize(pl->h->stream);
-  if (pl->dev) (void)hipFree(pl->dev);
+  if (pl->last_set && pl->last != pl->h->stream) (void)hipStreamSynchronize(pl->last);
   for (hipEvent_t e : pl->tev) (void)hipEventDestroy(e);
   delete pl;
   return ISDF_OK;
@@ -1541,7 +1578,7 @@ isdf_status plan_check(isdf_plan pl, const void* psi, const double* energies, co
 }
 
 isdf_status plan_enqueue(isdf_plan pl, const void* psi, const double* energies, const double* omega,
-                         void* workspace, void* eps_inv) {
+                         void* workspace, void* eps_inv, bool allow_timing = true) {
   isdf_handle h = pl->h;
   Run R;
   R.h = h;
@@ -1558,7 +1595,9 @@ isdf_status plan_enqueue(isdf_plan pl, const void* psi, const double* energies, 
   R.idx = reinterpret_cast<const int*>(d + pl->off_idx);
   R.tune = pl->tune;
   HIPCHK(hipSetDevice(h->device));
-  if (pl->timing && pl->tn < PLAN_TIMED_CALLS) {
+  pl->last = R.st;
+  pl->last_set = true;
+  if (allow_timing && pl->timing && pl->tn < PLAN_TIMED_CALLS) {
     while ((int)pl->tev.size() < 10 * (pl->tn + 1)) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e));
@@ -1599,8 +1638,23 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
   isdf_handle h0 = plans[0]->h;
   hipStream_t main = h0->stream;
   HIPCHK_H(h0, hipSetDevice(h0->device));
-  // fork every other stream off the first plan's stream, enqueue each system on
-  // its own handle's streams, and join them back (all capturable)
+  // Eagerly, every other stream is forked off the first plan's stream, each system
+  // is enqueued on its own handle's streams, and they are joined back.  Under a
+  // stream capture such a fork would make the handles' second streams join the
+  // capture through streams that themselves joined it (a nested fork); that form
+  // is refused here.  Systems that should run concurrently inside one graph go
+  // through isdf_multi_graph_create instead, which captures each system on its
+  // own and joins the captures as child graphs.
+  bool forks = false;
+  for (int i = 0; i < count; ++i) forks = forks || plans[i]->h->stream != main;
+  if (forks) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK_H(h0, hipStreamIsCapturing(main, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(h0, ISDF_E_UNSUPPORTED,
+                  "isdf_plan_eps_inv_multi under stream capture needs every plan on the capturing stream "
+                  "(use isdf_multi_graph_create for systems that run concurrently in one graph)");
+  }
   HIPCHK_H(h0, hipEventRecord(h0->mfork, main));
   for (int i = 0; i < count; ++i) {
     isdf_handle hi = plans[i]->h;
@@ -1614,14 +1668,99 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
   return ISDF_OK;
 }
 
+// ---- several systems as one graph of concurrent child graphs -----------------------------
+struct isdf_graph_s {
+  int device = 0;
+  std::vector<isdf_plan> plans;
+  std::vector<hipGraph_t> children;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+isdf_status isdf_graph_destroy(isdf_graph g) {
+  if (!g) return ISDF_OK;
+  (void)hipSetDevice(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (hipGraph_t c : g->children) (void)hipGraphDestroy(c);
+  delete g;
+  return ISDF_OK;
+}
+
+isdf_status isdf_multi_graph_create(int32_t count, const isdf_plan* plans, const void* const* psi,
+                                    const double* const* energies, const double* const* omega,
+                                    void* const* workspace, const size_t* ws_bytes, void* const* eps_inv,
+                                    isdf_graph* out) {
+  if (!out) return ISDF_E_ARG;
+  *out = nullptr;
+  if (count < 1 || !plans || !psi || !energies || !workspace || !ws_bytes || !eps_inv) return ISDF_E_ARG;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return ISDF_E_ARG;
+    if (plans[i]->h->device != plans[0]->h->device) return fail(plans[0]->h, ISDF_E_ARG, "plans on different devices");
+    if (!plans[i]->h->stream)
+      return fail(plans[i]->h, ISDF_E_ARG, "each plan's handle needs a created stream (the null stream cannot be captured)");
+    TRY(plan_check(plans[i], psi[i], energies[i], omega ? omega[i] : nullptr, workspace[i], ws_bytes[i], eps_inv[i]));
+    for (int j = 0; j < i; ++j)
+      if (workspace[j] == workspace[i] || eps_inv[j] == eps_inv[i])
+        return fail(plans[i]->h, ISDF_E_ARG, "the systems of one graph run concurrently: each needs its own workspace and output");
+  }
+  isdf_handle h0 = plans[0]->h;
+  HIPCHK_H(h0, hipSetDevice(h0->device));
+  isdf_graph g = new isdf_graph_s;
+  g->device = h0->device;
+  auto bail = [&](isdf_status s) { (void)isdf_graph_destroy(g); return s; };
+  if (hipGraphCreate(&g->graph, 0) != hipSuccess) return bail(fail(h0, ISDF_E_DEVICE, "hipGraphCreate failed"));
+  for (int i = 0; i < count; ++i) {
+    // Each system is captured on its own handle's stream (its second stream joins that
+    // capture directly), then added to the parent graph as a child with no
+    // dependencies, so the systems run concurrently when the graph is launched.
+    isdf_handle hi = plans[i]->h;
+    hipStream_t s = hi->stream;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return bail(fail(hi, ISDF_E_DEVICE, "hipStreamBeginCapture failed"));
+    const isdf_status st = plan_enqueue(plans[i], psi[i], energies[i], omega ? omega[i] : nullptr, workspace[i],
+                                        eps_inv[i], false);
+    hipGraph_t child = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &child);
+    if (child) g->children.push_back(child);
+    if (st != ISDF_OK) return bail(st);
+    if (e != hipSuccess || !child)
+      return bail(fail(hi, ISDF_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e)));
+    hipGraphNode_t node;
+    if (hipGraphAddChildGraphNode(&node, g->graph, nullptr, 0, child) != hipSuccess)
+      return bail(fail(hi, ISDF_E_DEVICE, "hipGraphAddChildGraphNode failed"));
+    g->plans.push_back(plans[i]);
+  }
+  const hipError_t e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(fail(h0, ISDF_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)));
+  *out = g;
+  return ISDF_OK;
+}
+
+isdf_status isdf_graph_launch(isdf_graph g, void* hip_stream) {
+  if (!g) return ISDF_E_ARG;
+  if (hipSetDevice(g->device) != hipSuccess) return ISDF_E_DEVICE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (hipGraphLaunch(g->exec, s) != hipSuccess) return ISDF_E_DEVICE;
+  for (isdf_plan p : g->plans) {   // isdf_plan_sync waits for this stream
+    p->last = s;
+    p->last_set = true;
+  }
+  return ISDF_OK;
+}
+
 isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {
   if (!pl) return ISDF_E_ARG;
   isdf_handle h = pl->h;
   StatusBlock hs;
   HIPCHK(hipSetDevice(h->device));
-  HIPCHK(hipMemcpyAsync(&hs, pl->dev, offsetof(StatusBlock, partial), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  HIPCHK(zero_fill(pl->dev, offsetof(StatusBlock, partial), h->stream));
+  // the stream the plan's last call was enqueued on (calls of one plan never overlap),
+  // which need not be the handle's current one
+  hipStream_t st = pl->last_set ? pl->last : h->stream;
+  HIPCHK(hipMemcpyAsync(&hs, pl->dev, offsetof(StatusBlock, partial), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(zero_fill(pl->dev, offsetof(StatusBlock, partial), st));
+  HIPCHK(hipStreamSynchronize(st));
   if (rep) for (int k = 0; k < 8; ++k) rep->stage_ms[k] = 0.0;
   if (rep && pl->tn > 0) {   // mean of each stage interval over the timed calls since the last sync
     for (int k = 0; k + 1 < pl->tmarks && k < 8; ++k) {

@@ -132,3 +132,30 @@ def test_contour_nodes_validated():
     prob = isdf.make_problem(12, np.eye(3) * 10.0, 8, 24, core_method=2)
     out = ctypes.c_size_t(0)
     assert isdf.lib().isdf_workspace_bytes(ctypes.byref(prob), 96, 256, 0, ctypes.byref(out)) == isdf.binding.E_ARG
+
+
+def test_plan_table_bytes(cfg0):
+    """The plan's device tables (status block, points, plane waves, DFT index lists)
+    are sized on the host; invalid plan arguments are refused before any GPU call."""
+    x = cfg0
+    prob = isdf.problem_for(x)
+    lib = isdf.lib()
+    out = ctypes.c_size_t(0)
+    mu = np.ascontiguousarray(x.mu_idx, dtype=np.int32)
+    mi = np.ascontiguousarray(x.miller, dtype=np.int32)
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    st = lib.isdf_plan_table_bytes(ctypes.byref(prob), mu.ctypes.data_as(pi32), len(mu), mi.ctypes.data_as(pi32),
+                                   len(mi), 0, ctypes.byref(out))
+    assert st == 0
+    # at least the point indices, the Miller list and one index per plane wave
+    assert out.value >= 4 * len(mu) + 12 * len(mi) + 4 * len(mi)
+    assert out.value % 256 == 0
+    bad = mu.copy(); bad[1] = bad[0]
+    st = lib.isdf_plan_table_bytes(ctypes.byref(prob), bad.ctypes.data_as(pi32), len(bad), mi.ctypes.data_as(pi32),
+                                   len(mi), 0, ctypes.byref(out))
+    assert st == isdf.binding.E_ARG
+    full = isdf.problem_for(x, coulomb_sum=1)
+    big = ctypes.c_size_t(0)
+    assert lib.isdf_plan_table_bytes(ctypes.byref(full), mu.ctypes.data_as(pi32), len(mu), mi.ctypes.data_as(pi32),
+                                     len(mi), 0, ctypes.byref(big)) == 0
+    assert big.value > out.value   # every grid vector in the Gram's list

@@ -536,12 +536,71 @@ def test_multi_system_graph():
 
 
 @pytest.mark.skip(reason="capturing systems forked onto several streams (nested forks from a joined "
-                         "stream) crashed the HIP runtime in stream-capture end once; off until the cause is found")
+                         "stream) crashed the HIP runtime in stream-capture end once; the library now refuses "
+                         "that form (ISDF_E_UNSUPPORTED) and concurrent systems in one graph go through "
+                         "isdf_multi_graph_create")
 def test_multi_system_concurrent_graph():
     plans, psis, es, wss, outs, refs = _multi_case(True)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         isdf.eps_inv_multi(plans, psis, es, outs, wss)
+
+
+def test_multi_graph_runs_systems_concurrently():
+    """isdf_multi_graph_create: each system captured on its own plan's stream, the
+    captures joined as child graphs of one graph with no dependencies between them.
+    Every replay (with eager calls and synchronisations in between) equals the
+    single-plan results bit for bit."""
+    print("[multi] child-graph launch", flush=True)
+    plans, psis, es, wss, outs, refs = [], [], [], [], [], []
+    for name in ["tiny", "mid", "kmaj"]:
+        inp = get_inputs(name)
+        prob = isdf.problem_for(inp, "fp32")
+        solo = isdf.Plan(prob, inp.mu_idx, inp.miller)
+        psi, e = dev(inp.psi_t), dev(inp.energies)
+        o = solo.new_output()
+        solo.eps_inv_async(psi, e, o, solo.new_workspace())
+        solo.sync()
+        refs.append(o.clone())
+        plans.append(isdf.Plan(prob, inp.mu_idx, inp.miller, stream=torch.cuda.Stream()))
+        psis.append(psi); es.append(e)
+        wss.append(plans[-1].new_workspace()); outs.append(plans[-1].new_output())
+    g = isdf.MultiGraph(plans, psis, es, outs, wss)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.launch()
+        for p in plans:
+            p.sync()
+        for o, r in zip(outs, refs):
+            assert torch.equal(o, r)
+        isdf.eps_inv_multi(plans, psis, es, outs, wss)   # eager, concurrent streams
+        for p in plans:
+            p.sync()
+    with pytest.raises(isdf.IsdfError) as err:          # one workspace for two concurrent systems
+        isdf.MultiGraph(plans[:2], psis[:2], es[:2], outs[:2], [wss[1], wss[1]])
+    assert err.value.status == isdf.binding.E_ARG
+
+
+def test_multi_under_capture_with_forks_is_refused():
+    """isdf_plan_eps_inv_multi with plans on several streams inside a stream capture
+    returns ISDF_E_UNSUPPORTED before enqueueing anything."""
+    plans, psis, es, wss, outs, refs = _multi_case(True)
+    x = torch.zeros(4, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(isdf.IsdfError) as err:
+        with torch.cuda.graph(g):
+            x.add_(1.0)
+            isdf.eps_inv_multi(plans, psis, es, outs, wss)
+    assert err.value.status == isdf.binding.E_UNSUPPORTED
+    torch.cuda.synchronize()
+    isdf.eps_inv_multi(plans, psis, es, outs, wss)       # eagerly the same call runs
+    for p in plans:
+        p.sync()
+    for o, r in zip(outs, refs):
+        assert torch.equal(o, r)
 
 
 def test_plan_autotune():

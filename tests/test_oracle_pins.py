@@ -200,6 +200,21 @@ def test_core_matrix_by_loops(tiny):
     np.testing.assert_allclose(ent, [ref[a, b] for a, b in pairs], atol=1e-15)
 
 
+@pytest.mark.parametrize("name", ["tiny", "cfg0", "mid"])
+def test_bounded_memory_forms_equal_plain_definitions(name):
+    """The bounded-memory forms used for the full-size references (S and M summed over
+    the occupied index, Theta by blocks of grid rows, Theta_G by blocks of columns)
+    equal the plain definitions; small blocks force several of each.  The plain
+    definitions are themselves pinned by the brute-force tests in this file."""
+    inp = synth.make_inputs(name)
+    ref = oracle.isdf_stages(inp)
+    got = oracle.isdf_stages_chunked(inp, chunk=97, mu_chunk=7)
+    for k in ("theta", "theta_g", "u", "m"):
+        assert np.abs(got[k] - ref[k]).max() <= 1e-12 * np.abs(ref[k]).max(), k
+    s = oracle.isdf_gram(inp.psi_t, inp.nv, inp.mu_idx)
+    assert np.abs(got["s"] - s).max() <= 1e-13 * np.abs(s).max()
+
+
 # ---------------------------------------------------------------------------
 # Exact-rank special cases reduce to the dense LU inverse
 # ---------------------------------------------------------------------------
