@@ -174,31 +174,66 @@ def _energies(rng, nv, nc):
 
 
 def select_points(rng, psi_t, nv, nmu, is_complex):
-    """Interpolation points by column-pivoted QR of a random sketch of the pair products.
+    """Interpolation points of the valence-conduction pair set (occupied x empty states)."""
+    nstates = psi_t.shape[0]
+    return select_pair_points(rng, psi_t, np.arange(nv), np.arange(nv, nstates), nmu, is_complex)
 
-    The sketch column t is conj(sum_i psi_i g_it) * (sum_j psi_j h_jt), i.e. the pair
+
+def select_pair_points(rng, psi_t, a_rows, b_rows, nmu, is_complex):
+    """Interpolation points by column-pivoted QR of a random sketch of the pair products
+    conj(psi_a) psi_b, a in a_rows, b in b_rows.
+
+    The sketch column t is conj(sum_a psi_a g_at) * (sum_b psi_b h_bt), i.e. the pair
     products contracted with Gaussian weights; it is evaluated on a random candidate
     subset of the grid when the grid is large.  Returns sorted distinct int32 indices.
     """
-    nstates, nr = psi_t.shape
-    nc = nstates - nv
+    nr = psi_t.shape[1]
+    na, nb = len(a_rows), len(b_rows)
     p = nmu + min(nmu, 64)
     if nr <= 20000:
         cand = np.arange(nr)
     else:
         cand = np.sort(rng.choice(nr, size=min(nr, 4 * nmu), replace=False))
-    pv = psi_t[:nv, cand].T
-    pc = psi_t[nv:, cand].T
+    pa = psi_t[a_rows][:, cand].T
+    pb = psi_t[b_rows][:, cand].T
     if is_complex:
-        g = rng.standard_normal((nv, p)) + 1j * rng.standard_normal((nv, p))
-        h = rng.standard_normal((nc, p)) + 1j * rng.standard_normal((nc, p))
+        g = rng.standard_normal((na, p)) + 1j * rng.standard_normal((na, p))
+        h = rng.standard_normal((nb, p)) + 1j * rng.standard_normal((nb, p))
     else:
-        g = rng.standard_normal((nv, p))
-        h = rng.standard_normal((nc, p))
-    sk = np.conj(pv @ g) * (pc @ h)
+        g = rng.standard_normal((na, p))
+        h = rng.standard_normal((nb, p))
+    sk = np.conj(pa @ g) * (pb @ h)
     _, _, piv = scipy.linalg.qr(sk.T, mode="economic", pivoting=True)
     mu = np.sort(cand[piv[:nmu]]).astype(np.int32)
     return mu
+
+
+def sigma_point_counts(inp) -> tuple[int, int]:
+    """Point counts of the two self-energy pair sets at the valence-conduction set's ratio
+    k_mu = N_mu / sqrt(Nv Nc): N_mu^vn = k_mu sqrt(Nv N) and N_mu^nn = k_mu N (N = Nv + Nc),
+    each at most Nr and below the pair set's rank (N (N + 1) / 2 distinct products for
+    real orbitals)."""
+    ns = inp.nv + inp.nc
+    k = inp.nmu / math.sqrt(inp.nv * inp.nc)
+    nvn = int(round(k * math.sqrt(inp.nv * ns)))
+    nnn = int(round(k * ns))
+    nnn_rank = ns * (ns + 1) // 2 if not inp.is_complex else ns * ns
+    return min(nvn, inp.nr, inp.nv * ns), min(nnn, inp.nr, nnn_rank)
+
+
+def sigma_points(inp, nmu_vn: int | None = None, nmu_nn: int | None = None):
+    """Interpolation points of the occupied x all (vn) and all x all (nn) pair sets that
+    the self-energy fits use (Algorithm 3's P_vn and P_nn), from their own seeded
+    stream (seed + 1000), so the dielectric inputs stay as drawn."""
+    dvn, dnn = sigma_point_counts(inp)
+    nvn = dvn if nmu_vn is None else nmu_vn
+    nnn = dnn if nmu_nn is None else nmu_nn
+    rng = np.random.default_rng(inp.seed + 1000)
+    ns = inp.nv + inp.nc
+    allr = np.arange(ns)
+    mu_vn = select_pair_points(rng, inp.psi_t, np.arange(inp.nv), allr, nvn, inp.is_complex)
+    mu_nn = select_pair_points(rng, inp.psi_t, allr, allr, nnn, inp.is_complex)
+    return mu_vn, mu_nn
 
 
 def make_inputs(name: str = "cfg0", *, nmu: int | None = None, n_omega: int = 0,
