@@ -171,6 +171,25 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
                          int32_t n_omega, void* workspace, size_t ws_bytes, void* eps_inv,
                          isdf_report* rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): isdf_eps_inv with no
+ * workspace argument.  The workspace is a library-owned device array of
+ * ISDF_SCRATCH_MAX_BYTES per GPU, set up by isdf_create and held until the
+ * process ends; this call allocates nothing (device or pinned host memory).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a GPU
+ * (on different streams or handles) race and give undefined results.  The
+ * array keeps the last call's contents; the call clears what must start at zero.
+ * Arguments as for isdf_eps_inv.  Errors: those of isdf_eps_inv, and
+ * ISDF_E_WORKSPACE (with a message) when the problem needs more than
+ * ISDF_SCRATCH_MAX_BYTES (isdf_workspace_bytes tells beforehand) or its host
+ * arrays do not fit the handle's pinned staging buffer (1 MiB); nothing is
+ * enqueued then. */
+#define ISDF_SCRATCH_MAX_BYTES ((size_t)64 << 20)
+isdf_status isdf_eps_inv_noalloc(isdf_handle h, const isdf_problem* prob, const void* psi,
+                                 const double* energies, const int32_t* mu_idx, int32_t n_mu,
+                                 const int32_t* miller, int32_t ng, const double* omega,
+                                 int32_t n_omega, void* eps_inv, isdf_report* rep);
+
 /* Step 1 alone: Theta in real space (eq. ISDF, least-squares fit).
  *   theta  device out, N_mu x Nr complex128 C order: theta[mu][k] = Theta(r_k, mu).
  * Other arguments as for isdf_eps_inv. */

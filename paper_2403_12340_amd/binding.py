@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
             "isdf_gvectors": [pprob, i32, pi32],
             "isdf_check_inputs": [pprob, pdbl, pi32, i32, pi32, i32, pdbl, i32, ctypes.c_char_p, sz],
             "isdf_eps_inv": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, pdbl, i32, vp, sz, vp, prep],
+            "isdf_eps_inv_noalloc": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, pdbl, i32, vp, prep],
             "isdf_fit_theta": [vp, pprob, vp, pi32, i32, vp, sz, vp],
             "isdf_core_m": [vp, pprob, vp, pdbl, pi32, i32, dbl, vp, sz, vp],
             "isdf_coulomb_u": [vp, pprob, vp, pi32, i32, pi32, i32, vp, sz, vp],
@@ -273,6 +274,34 @@ def eps_inv(psi_t, energies, mu_idx, miller, prob: Problem, omegas=None, *, out=
                             pom if len(om) else None, len(om), ctypes.c_void_p(wsptr), nbytes,
                             ctypes.c_void_p(out.data_ptr()), ctypes.byref(rep))
     h.check(st, "isdf_eps_inv")
+    return Result(out, rep)
+
+
+SCRATCH_MAX_BYTES = 64 << 20   # ISDF_SCRATCH_MAX_BYTES
+
+
+def eps_inv_noalloc(psi_t, energies, mu_idx, miller, prob: Problem, omegas=None, *, out) -> Result:
+    """isdf_eps_inv_noalloc: eps~^{-1} with the library's per-GPU scratch array as the
+    workspace (problems up to SCRATCH_MAX_BYTES of workspace).  `out` is caller-owned
+    (max(n_omega, 1), ng, ng) complex128; nothing is allocated on the device."""
+    import torch
+    _check_psi(psi_t, prob)
+    dev = psi_t.device
+    h = handle(dev.index or 0)
+    e, pe = _f64(energies)
+    mu, pmu = _i32(mu_idx)
+    mi, pmi = _i32(miller)
+    om = np.zeros(0) if omegas is None else np.asarray(omegas, dtype=np.float64)
+    om, pom = _f64(om)
+    ng = len(mi)
+    if (out.dtype != torch.complex128 or tuple(out.shape) != (max(len(om), 1), ng, ng) or not out.is_contiguous()
+            or out.device != dev):
+        raise ValueError("out must be contiguous complex128 (max(n_omega, 1), ng, ng) on psi's device")
+    rep = Report()
+    st = lib().isdf_eps_inv_noalloc(h.h, ctypes.byref(prob), ctypes.c_void_p(psi_t.data_ptr()), pe, pmu, len(mu),
+                                    pmi, ng, pom if len(om) else None, len(om), ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.byref(rep))
+    h.check(st, "isdf_eps_inv_noalloc")
     return Result(out, rep)
 
 

@@ -24,6 +24,7 @@
 #include <complex>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <deque>
@@ -435,6 +436,7 @@ isdf_status check_ws(isdf_handle h, void* ws, size_t have, size_t need) {
 struct Uploader {
   isdf_handle h;
   void* ws = nullptr;
+  bool no_alloc = false;   // refuse to grow the pinned staging buffer
   struct Item { size_t off; const void* src; size_t bytes; };
   std::vector<Item> items;
   std::deque<std::vector<int32_t>> keep;   // host arrays built for this call, alive until run()
@@ -459,6 +461,10 @@ struct Uploader {
     for (auto& g : groups) { g.at = total; total += g.hi - g.lo; }
     // the previous call's copies out of the pinned buffer must be complete
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (total > h->pinned_bytes && no_alloc)
+      return fail(h, ISDF_E_WORKSPACE, "the host arrays (" + std::to_string(total) +
+                  " bytes) do not fit the handle's pinned staging buffer (" + std::to_string(h->pinned_bytes) +
+                  " bytes) and this call allocates nothing");
     if (total > h->pinned_bytes) {
       if (h->pinned) HIPCHK(hipHostFree(h->pinned));
       h->pinned = nullptr;
@@ -1178,6 +1184,38 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
 }  // namespace
 
 
+// ---- the workspace of the allocation-free entry point ----------------------------
+// One array per GPU, a file-scope device variable: the runtime places a copy on each
+// device the library runs on and keeps it until the process ends.  In host code its
+// name is only a stand-in; the device address is taken once per device, with that
+// device current, by scratch_setup (from isdf_create), and only that address is used.
+static __device__ __align__(256) unsigned char scratch[ISDF_SCRATCH_MAX_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+// the calling thread's current device must be `device`
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_addr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & (ALIGN - 1)) != 0) return hipErrorInvalidSymbol;
+  scratch_addr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return scratch_addr[device];
+}
+}  // namespace
+
 extern "C" {
 
 const char* isdf_version(void) { return "isdf-smw-gfx950 0.1"; }
@@ -1191,6 +1229,7 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
   h->device = device;
   h->stream = (hipStream_t)stream;
   if (hipSetDevice(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
+  if (scratch_setup(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   for (hipEvent_t* e : {&h->fork, &h->join, &h->core0, &h->zdone, &h->zops, &h->mfork, &h->mdone, &h->m_ready[0], &h->m_ready[1],
@@ -1315,6 +1354,41 @@ isdf_status isdf_eps_inv(isdf_handle h, const isdf_problem* prob, const void* ps
   DftIndex ix;
   std::vector<int> idxbuf;
   TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, energies, n_omega, workspace, ws_bytes, upl, ix, idxbuf));
+  if (R.P.core_method == 1 && n_omega > 0)
+    return fail(h, ISDF_E_UNSUPPORTED, "the contour-integral core is static (n_omega = 0)");
+  HIPCHK(hipSetDevice(h->device));
+  TRY(upl.run());
+  TRY(clear_status(R));
+  Timer tm{h, rep && rep->want_timing != 0};
+  tm.mark();
+  TRY(enqueue_eps_inv(R, psi, omega, n_omega, eps_inv, tm));
+  return finish(R, rep, tm);
+}
+
+isdf_status isdf_eps_inv_noalloc(isdf_handle h, const isdf_problem* prob, const void* psi, const double* energies,
+                                 const int32_t* mu_idx, int32_t n_mu, const int32_t* miller, int32_t ng,
+                                 const double* omega, int32_t n_omega, void* eps_inv, isdf_report* rep) {
+  if (!h) return ISDF_E_ARG;
+  if (n_omega < 0 || (n_omega > 0 && !omega)) return fail(h, ISDF_E_ARG, "omega list invalid");
+  for (int k = 0; k < n_omega; ++k)
+    if (!(omega[k] >= 0.0) || !std::isfinite(omega[k])) return fail(h, ISDF_E_ARG, "omega must be finite and >= 0");
+  if (!eps_inv) return fail(h, ISDF_E_ARG, "eps_inv is NULL");
+  if (!energies) return fail(h, ISDF_E_ARG, "energies is NULL");
+  if (!miller) return fail(h, ISDF_E_ARG, "miller is NULL");
+  void* ws = scratch_of(h->device);
+  if (!ws) return fail(h, ISDF_E_DEVICE, "the device's scratch array was not set up by isdf_create");
+  Run R;
+  Uploader upl;
+  upl.no_alloc = true;
+  DftIndex ix;
+  std::vector<int> idxbuf;
+  const isdf_status s0 = setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, energies, n_omega, ws,
+                                      ISDF_SCRATCH_MAX_BYTES, upl, ix, idxbuf);
+  if (s0 == ISDF_E_WORKSPACE)
+    return fail(h, ISDF_E_WORKSPACE, "the problem needs " + std::to_string(R.L.total) +
+                " bytes of workspace; the allocation-free entry point holds at most " +
+                std::to_string((size_t)ISDF_SCRATCH_MAX_BYTES) + " (use isdf_eps_inv with a caller workspace)");
+  TRY(s0);
   if (R.P.core_method == 1 && n_omega > 0)
     return fail(h, ISDF_E_UNSUPPORTED, "the contour-integral core is static (n_omega = 0)");
   HIPCHK(hipSetDevice(h->device));
