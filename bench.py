@@ -183,9 +183,11 @@ def summarize(args):
 
 def batch_systems(isdf, torch, dev, n_omega, first):
     """The 48^3 system plus eight uneven ones (24^3..40^3, Nv 16..48, Nc = 4 Nv,
-    N_mu = 10 Nv, NG = 32 Nv), each with n_omega imaginary frequencies, built by
-    one multi-system call: captured into one graph (systems in sequence on one
-    stream) and, eagerly, with the systems on concurrent streams."""
+    N_mu = 10 Nv, NG = 32 Nv), each with n_omega imaginary frequencies: one graph
+    launch whose systems run concurrently (isdf_multi_graph_create: each system
+    captured on its own plan's stream, joined as child graphs), beside the same
+    systems as one eager multi-system call on concurrent streams and as one
+    captured multi-system call with the systems in sequence on one stream."""
     import synth
     names = [first] + [f"batch{i}" for i in range(8)]
     inps = [synth.make_inputs(nm, n_omega=n_omega) for nm in names]
@@ -193,46 +195,53 @@ def batch_systems(isdf, torch, dev, n_omega, first):
     es = [torch.from_numpy(i.energies).to(dev) for i in inps]
     oms = [i.omegas for i in inps]
     probs = [isdf.problem_for(i, prec="fp32") for i in inps]
+    reps = 3
+
+    def timed(run, plans):
+        run()
+        for p in plans:
+            p.sync()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            run()
+        for p in plans:
+            p.sync()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    # every plan on its own stream: autotuned once (launch shapes and splits only)
+    streams = [torch.cuda.Stream() for _ in names]
+    conc = [isdf.Plan(p, i.mu_idx, i.miller, n_omega=n_omega, stream=s) for p, i, s in zip(probs, inps, streams)]
+    wss = [p.new_workspace() for p in conc]
+    outs = [p.new_output() for p in conc]
+    for p, psi, e, i, ws, o in zip(conc, psis, es, inps, wss, outs):
+        p.autotune(psi, e, o, ws, omegas=i.omegas, reps=2)
+    tune = [p.get_tune() for p in conc]
+    mg = isdf.MultiGraph(conc, psis, es, outs, wss, omegas=oms)
+    dt_mgraph = timed(mg.launch, conc)
+    dt_conc = timed(lambda: isdf.eps_inv_multi(conc, psis, es, outs, wss, omegas=oms), conc)
+    del mg
     seq = [isdf.Plan(p, i.mu_idx, i.miller, n_omega=n_omega) for p, i in zip(probs, inps)]
-    wss = [p.new_workspace() for p in seq]
-    outs = [p.new_output() for p in seq]
+    for p, t in zip(seq, tune):
+        p.set_tune(**t)
     isdf.eps_inv_multi(seq, psis, es, outs, wss, omegas=oms)
     for p in seq:
         p.sync()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         isdf.eps_inv_multi(seq, psis, es, outs, wss, omegas=oms)
-    g.replay()
-    torch.cuda.synchronize()
-    reps = 3
-    t = time.perf_counter()
-    for _ in range(reps):
-        g.replay()
-    torch.cuda.synchronize()
-    dt_graph = (time.perf_counter() - t) / reps
-    for p in seq:
-        p.sync()
-    streams = [None] + [torch.cuda.Stream() for _ in names[1:]]
-    conc = [isdf.Plan(p, i.mu_idx, i.miller, n_omega=n_omega, stream=s) for p, i, s in zip(probs, inps, streams)]
-    isdf.eps_inv_multi(conc, psis, es, outs, wss, omegas=oms)
-    for p in conc:
-        p.sync()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(reps):
-        isdf.eps_inv_multi(conc, psis, es, outs, wss, omegas=oms)
-    for p in conc:
-        p.sync()
-    torch.cuda.synchronize()
-    dt_conc = (time.perf_counter() - t) / reps
-    nb = len(names) * n_omega
-    print(f"[bench] {len(names)} systems x {n_omega} frequencies: graph {dt_graph * 1e3:.1f} ms, "
-          f"concurrent {dt_conc * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    dt_seq = timed(g.replay, seq)
     del g
+    nb = len(names) * n_omega
+    print(f"[bench] {len(names)} systems x {n_omega} frequencies: concurrent graph {dt_mgraph * 1e3:.1f} ms, "
+          f"eager concurrent {dt_conc * 1e3:.1f} ms, sequential graph {dt_seq * 1e3:.1f} ms",
+          file=sys.stderr, flush=True)
     return {"systems": [f"{i.n}^3 Nv={i.nv} Nc={i.nc} N_mu={i.nmu} NG={i.ng}" for i in inps], "n_omega": n_omega,
-            "path": "mixed", "ms_graph_launch": round(dt_graph * 1e3, 2),
+            "path": "mixed", "autotuned": True, "ms_graph_launch": round(dt_mgraph * 1e3, 2),
             "ms_concurrent_streams": round(dt_conc * 1e3, 2),
-            "frequency_builds_per_s": round(nb / min(dt_graph, dt_conc), 1)}
+            "ms_graph_sequential": round(dt_seq * 1e3, 2),
+            "frequency_builds_per_s": round(nb / dt_mgraph, 1)}
 
 
 def adjoint_timing(isdf, torch, dev, inp, psi, reps, fwd_ms):
