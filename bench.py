@@ -136,6 +136,78 @@ def _pmc_per_dispatch(db, counter):
     return out
 
 
+def _trace_by_shape(db):
+    """{(kernel name, grid threads): (dispatches, mean duration ns)} from a kernel-trace database."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, grid_x * grid_y * grid_z, count(*), avg(end - start) from kernels "
+                     "group by name, grid_x * grid_y * grid_z").fetchall()
+    return {(n, int(g)): (int(k), float(a)) for n, g, k, a in rows}
+
+
+def _pmc_by_shape(db, counters):
+    """{(kernel name, grid threads): {counter: mean value per dispatch}} from a --pmc database."""
+    out = {}
+    for ctr in counters:
+        acc = {}
+        for name, grid, v in _pmc_per_dispatch(db, ctr):
+            acc.setdefault((name, grid), []).append(v)
+        for key, vals in acc.items():
+            out.setdefault(key, {})[ctr] = float(np.mean(vals))
+    return out
+
+
+MOPS = {"SQ_INSTS_VALU_MFMA_MOPS_F32": "fp32", "SQ_INSTS_VALU_MFMA_MOPS_F64": "fp64",
+        "SQ_INSTS_VALU_MFMA_MOPS_BF16": "bf16"}
+
+
+def summarize_counters(args, lines):
+    """Issued MFMA work and HBM bytes per kernel shape: MOPS counters (512 flops each) over the
+    kernel trace's mean duration, against the peak of the instruction type; FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch, times the calibration factors of the traffic record) over it."""
+    trace = _trace_by_shape(args.summarize)
+    lines.append("")
+    if args.pmc_mfma:
+        mops = _pmc_by_shape(args.pmc_mfma, list(MOPS))
+        lines.append("Issued MFMA work per kernel shape (SQ_INSTS_VALU_MFMA_MOPS_* x 512 flops per dispatch, over the "
+                     "mean duration of the same shape in the kernel trace)")
+        lines.append(f"{'kernel':<72} {'grid':>9} {'calls':>6} {'avg_us':>9} {'TFLOP':>8} {'TFLOP/s':>8} "
+                     f"{'type':>5} {'frac':>6}")
+        rows = []
+        for key, ctrs in mops.items():
+            if key not in trace:
+                continue
+            typ, val = max(((MOPS[c], v) for c, v in ctrs.items()), key=lambda t: t[1])
+            if val <= 0:
+                continue
+            calls, dur = trace[key]
+            fl = val * 512.0
+            rate = fl / (dur * 1e-9) / 1e12
+            rows.append((fl * calls, key, calls, dur, fl, rate, typ))
+        for _, (name, grid), calls, dur, fl, rate, typ in sorted(rows, reverse=True)[:24]:
+            lines.append(f"{name[:72]:<72} {grid:>9} {calls:>6} {dur / 1e3:>9.1f} {fl / 1e12:>8.4f} {rate:>8.1f} "
+                         f"{typ:>5} {rate / PEAK[typ]:>6.3f}")
+    if args.pmc_fetch and args.pmc_write and args.factors:
+        ff, fw = (float(x) for x in args.factors.split(","))
+        fetch = _pmc_by_shape(args.pmc_fetch, ["FETCH_SIZE"])
+        write = _pmc_by_shape(args.pmc_write, ["WRITE_SIZE"])
+        lines.append("")
+        lines.append(f"HBM bytes per kernel shape (FETCH_SIZE x {ff:.4f} + WRITE_SIZE x {fw:.4f}, KiB -> B, over the "
+                     "mean duration in the kernel trace; peak 8 TB/s)")
+        lines.append(f"{'kernel':<72} {'grid':>9} {'avg_us':>9} {'GB':>8} {'GB/s':>8} {'frac':>6}")
+        rows = []
+        for key in fetch:
+            if key not in write or key not in trace:
+                continue
+            b = fetch[key]["FETCH_SIZE"] * 1024.0 * ff + write[key]["WRITE_SIZE"] * 1024.0 * fw
+            calls, dur = trace[key]
+            rows.append((b * calls, key, dur, b))
+        for _, (name, grid), dur, b in sorted(rows, reverse=True)[:24]:
+            gbs = b / (dur * 1e-9) / 1e9
+            lines.append(f"{name[:72]:<72} {grid:>9} {dur / 1e3:>9.1f} {b / 1e9:>8.3f} {gbs:>8.1f} "
+                         f"{gbs / HBM_PEAK:>6.3f}")
+
+
 def summarize(args):
     lines = []
     stats = _kernel_stats(args.summarize)
@@ -178,6 +250,8 @@ def summarize(args):
                      f"total {zf + zw:.4e} B per dispatch")
         lines.append(f"TRAFFIC_BYTES_PER_LAUNCH {zf + zw:.6e}")
         lines.append(f"SOURCE_SHA256 {zpair_source_hash()}")
+    if args.pmc_mfma or args.factors:
+        summarize_counters(args, lines)
     print("\n".join(lines))
 
 
@@ -275,7 +349,9 @@ def solid_like(isdf, torch, dev, steps):
     e_dev = torch.from_numpy(inp.energies).to(dev)
     res, outs = {}, {}
     for prec in ("bf16x3", "fp32", "fp64"):
-        plan = isdf.Plan(isdf.problem_for(inp, prec=prec), inp.mu_idx, inp.miller)
+        # the solid-like configuration runs BF16x3 with two FP64 refinement steps of the core inverse
+        refine = 2 if prec == "bf16x3" else 0
+        plan = isdf.Plan(isdf.problem_for(inp, prec=prec, refine_steps=refine), inp.mu_idx, inp.miller)
         ws = plan.new_workspace()
         out = plan.new_output()
         plan.eps_inv_async(psi, e_dev, out, ws)
@@ -287,7 +363,7 @@ def solid_like(isdf, torch, dev, steps):
         plan.sync()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
-        res[prec] = {"ms_per_build": round(dt * 1e3, 2), "builds_per_s": round(1.0 / dt, 3)}
+        res[prec] = {"ms_per_build": round(dt * 1e3, 2), "builds_per_s": round(1.0 / dt, 3), "refine_steps": refine}
         outs[prec] = out[0].clone()
         print(f"[bench] 64^3 {prec}: {dt * 1e3:.1f} ms/build", file=sys.stderr, flush=True)
         del plan, ws, out
@@ -314,10 +390,75 @@ def solid_like(isdf, torch, dev, steps):
     ref = outs["fp64"]
     for prec in ("bf16x3", "fp32", "bf16x3_contour_core", "fp64_contour_core"):
         res[prec]["rel_fro_vs_fp64_path"] = float(((outs[prec] - ref).norm() / ref.norm()).item())
+    # against the FP64 oracle: its eps~^{-1} rows stored by tests/golden/make_full_size.py
+    # (an oracle-only script), compared entry by entry on those rows
+    gold = os.path.join(ROOT, "tests", "golden", "cfg2_oracle.npz")
+    if os.path.exists(gold):
+        g = np.load(gold)
+        if np.array_equal(g["mu_idx"], inp.mu_idx):
+            rows = g["rows"]
+            eye_rows = np.eye(inp.ng)[rows]
+            for key in outs:
+                got = outs[key][torch.from_numpy(rows).to(dev)].cpu().numpy()
+                d = got - g["eps_rows"]
+                res[key]["errors_vs_oracle_sampled_rows"] = {
+                    "rows": int(len(rows)),
+                    "max_abs": float(np.abs(d).max()),
+                    "max_abs_over_max_screening": float(np.abs(d).max() / float(g["max_screen"])),
+                    "rel_fro_rows": float(np.linalg.norm(d) / np.linalg.norm(g["eps_rows"])),
+                    "rel_fro_screening_rows": float(np.linalg.norm(d) / np.linalg.norm(g["eps_rows"] - eye_rows))}
     del outs, ref
     res["adjoint_fp64"] = adjoint_timing(isdf, torch, dev, inp, psi, 2, res["fp64"]["ms_per_build"])
     return {"workload": f"static eps~^-1, {inp.n}^3 grid, Nv={inp.nv}, Nc={inp.nc}, N_mu={inp.nmu}, NG={inp.ng}, "
                         "complex orbitals", "steps": steps, **res}
+
+
+def blas_info():
+    """The BLAS library NumPy/SciPy call, its version and thread count (threadpoolctl)."""
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        return [{"library": d.get("internal_api"), "version": d.get("version"), "threads": d.get("num_threads"),
+                 "file": os.path.basename(d.get("filepath", ""))} for d in libs]
+    except Exception as e:  # report, do not fail the benchmark
+        return f"unknown ({type(e).__name__})"
+
+
+def stress_variant(isdf, torch, dev, inp, psi, st, oracle):
+    """The workload with v_scale raised until lambda_max(eps~) = 10: the mixed paths'
+    conditioning check.  lambda_max(eps~) - 1 = lambda_max(L^H U^H U L) with -M = L L^H
+    grows linearly with v_scale, so one eigenvalue problem on the N_mu x N_mu core gives
+    the factor.  Each path runs once (direct call, refinement 0 and 2) against the
+    oracle at the raised scale; cond(S), cond(M) from the oracle's matrices and the
+    library's cond_est(H) are reported beside the errors."""
+    u, m = st["u"], st["m"]
+    lc = np.linalg.cholesky(-m)
+    g = np.conj(u.T) @ u
+    lam0 = float(np.linalg.eigvalsh(np.conj(lc.T) @ g @ lc).max())
+    factor = 9.0 / lam0
+    vs = inp.v_scale * factor
+    t = time.perf_counter()
+    ref = oracle.eps_inv_isdf(inp, v_scale=vs)
+    tor = time.perf_counter() - t
+    lam_max = 1.0 / float(np.linalg.eigvalsh(ref).min())
+    eye = np.eye(inp.ng)
+    s_mat = oracle.isdf_gram(inp.psi_t, inp.nv, inp.mu_idx)
+    out = {"v_scale_factor": round(factor, 3), "lambda_max_eps": round(lam_max, 3),
+           "lambda_max_eps_base": round(1.0 + lam0, 4), "cond_S": float(np.linalg.cond(s_mat)),
+           "cond_M": float(np.linalg.cond(m)), "oracle_s": round(tor, 1), "paths": {}}
+    for prec, refine in (("fp32", 0), ("fp32", 2), ("bf16x3", 0), ("bf16x3", 2), ("fp64", 0)):
+        prob = isdf.problem_for(inp, prec=prec, refine_steps=refine, v_scale=vs)
+        res = isdf.eps_inv(psi, inp.energies, inp.mu_idx, inp.miller, prob)
+        got = res.eps_inv[0].cpu().numpy()
+        d = got - ref
+        out["paths"][f"{prec}_refine{refine}"] = {
+            "max_abs": float(np.abs(d).max()), "rel_fro": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "rel_fro_screening": float(np.linalg.norm(d) / np.linalg.norm(ref - eye)),
+            "cond_est_H": float(res.report.cond_est),
+            "refine_residuals": [float(x) for x in list(res.report.refine_residual)[:res.report.n_refine_reported]]}
+    print(f"[bench] stress lambda_max(eps~) = {lam_max:.2f}: " +
+          ", ".join(f"{k} {v['rel_fro_screening']:.2e}" for k, v in out["paths"].items()), file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -325,6 +466,9 @@ def main():
     ap.add_argument("--summarize", default=None, help="rocpd database of a --kernel-trace run")
     ap.add_argument("--pmc-fetch", default=None)
     ap.add_argument("--pmc-write", default=None)
+    ap.add_argument("--pmc-mfma", default=None, help="rocpd database of a --pmc run of the SQ_INSTS_VALU_MFMA_MOPS_* counters")
+    ap.add_argument("--factors", default=None,
+                    help="FETCH_SIZE,WRITE_SIZE calibration factors: per-kernel HBM table from --pmc-fetch/--pmc-write")
     ap.add_argument("--only", choices=["fp32", "fp64", "bf16x3"], default=None)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -457,22 +601,32 @@ def main():
 
     errors = {}
     cpu = None
+    stress = None
     if not args.no_cpu_baseline:
         import oracle
         nthreads = len(os.sched_getaffinity(0))
+        blas = blas_info()
         t = time.perf_counter()
         st = oracle.isdf_stages(inp)
         ref = oracle.eps_inv_isdf(inp, stages=st)
         tcpu = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.eps_inv_exact(inp)
+        texact = time.perf_counter() - t
         cpu = {"value": round(1.0 / tcpu, 5), "unit": "builds/s", "cores": nthreads, "kind": "oracle",
                "sample": f"one full {args.config} build (ISDF fit, core, DFT, dense eps~ and LU inverse), "
-                         f"{tcpu:.1f} s, NumPy/SciPy FP64 on {nthreads} host threads"}
+                         f"{tcpu:.1f} s, NumPy/SciPy FP64 on {nthreads} host threads",
+               "blas": blas,
+               "exact_mode": {"seconds": round(texact, 2), "builds_per_s": round(1.0 / texact, 5),
+                              "what": "chi0 from every valence-conduction pair (FFT per occupied state), "
+                                      "dense eps~, LU inverse"}}
         eye = np.eye(inp.ng)
         for prec, got in outs.items():
             errors[prec] = {"rel_fro": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
                             "max_abs": float(np.abs(got - ref).max()),
                             "rel_fro_screening": float(np.linalg.norm(got - ref) / np.linalg.norm(ref - eye))}
-        print(f"[bench] oracle {tcpu:.1f}s errors {errors}", file=sys.stderr, flush=True)
+        print(f"[bench] oracle {tcpu:.1f}s (exact mode {texact:.1f}s) errors {errors}", file=sys.stderr, flush=True)
+        stress = stress_variant(isdf, torch, dev, inp, psi, st, oracle)
 
     line = {
         "metric": "eps^-1 builds/s/GPU, mixed path (FP32 MFMA contractions + FP64 core) at stated error vs FP64 oracle",
@@ -509,6 +663,7 @@ def main():
         "systems_batch": batch,
         "solid_like_64cubed": solid,
         "adjoint_fp64": adj,
+        "stress_lambda_max_10": stress,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -70,9 +70,10 @@ typedef enum {
 typedef enum {
   ISDF_FP64 = 0,    /* every contraction in FP64 on MFMA */
   ISDF_FP32 = 1,    /* large contractions in FP32 on MFMA, FP32 accumulation; N_mu x N_mu core in FP64 */
-  ISDF_BF16X3 = 2   /* the pair-Gram contraction of step 1 as three BF16 products (hi*hi + hi*lo + lo*hi,
-                       x = hi + lo split by round to nearest) on bf16 MFMA with FP32 accumulation; the
-                       other large contractions as ISDF_FP32; N_mu x N_mu core in FP64 */
+  ISDF_BF16X3 = 2   /* the pair-Gram contraction of step 1 and the core M of step 2 as three BF16 products
+                       (hi*hi + hi*lo + lo*hi, x = hi + lo split by round to nearest) on bf16 MFMA with
+                       FP32 accumulation (the core's per-state sums added in FP64); the other large
+                       contractions as ISDF_FP32; N_mu x N_mu algebra in FP64 */
 } isdf_precision;
 
 typedef struct {
@@ -383,15 +384,21 @@ isdf_status isdf_check_inputs(const isdf_problem* prob, const double* energies,
 isdf_status isdf_contour_nodes(const double* energies, int32_t nv, int32_t nc, double tol, double* out,
                                int32_t* n_out);
 
-/* ---- Adjoint of one build (FP64) -------------------------------------------
+/* ---- Adjoint of one build ---------------------------------------------------
  * Gradients of the scalar loss L = Re tr(W eps~^{-1}) for a Hermitian weight W,
  * eps~^{-1} the NG x NG result of isdf_eps_inv at one imaginary frequency omega
  * (0 = static).  The derivative is taken of the whole chain: the ISDF fit
  * (eq. MatrixExpressionISDF), the core M = f C Omega^{-1} C^H (eq. COmegaCstar),
  * the Coulomb Gram through the DFT and the SMW update (eq. epsilon_with_SMW).
  * The Nr x N_mu pair products are recomputed from psi, not stored: nothing of
- * an earlier forward call is needed.
- *   prob        prec must be ISDF_FP64 (else ISDF_E_UNSUPPORTED); coulomb_sum 0 or 1
+ * an earlier forward call is needed.  They exist for one chunk of interpolation
+ * points at a time (at most 512 MiB each), so the workspace grows with N_mu Nr only
+ * through that chunk.
+ *   prob        prec ISDF_FP64 (every step in FP64) or ISDF_FP32 (the contractions
+ *               over the grid, those that form the pair products and those that
+ *               contract their cotangents with psi, in FP32 on MFMA with FP64
+ *               storage; everything else in FP64); ISDF_BF16X3 is
+ *               ISDF_E_UNSUPPORTED; coulomb_sum 0 or 1
  *   psi, energies, mu_idx, n_mu, miller, ng   as for isdf_eps_inv
  *   omega       host, one frequency >= 0 (Hartree)
  *   w           device, ng x ng complex128 row-major, Hermitian (read only)
@@ -412,6 +419,40 @@ isdf_status isdf_eps_inv_grad(isdf_handle h, const isdf_problem* prob, const voi
                               const int32_t* miller, int32_t ng, double omega, const void* w,
                               void* workspace, size_t ws_bytes, double* grad_energies,
                               void* grad_psi_mu, double* loss);
+
+/* Static COHSEX self-energy diagonals (paper: Algorithm 3, steps 2 and 4-7; the
+ * self-energy terms of eq. selfenergySum in the matrix form of eq. classical56,
+ * reduced by eq. Hadamard).  For every band n (N = nv + nc):
+ *   Sigma_SEX_X(n) = - sum_{i in v}   m_in^H (W - V) m_in,
+ *   Sigma_X(n)     = - sum_{i in v}   m_in^H  V      m_in,
+ *   Sigma_COH(n)   = 1/2 sum_{i in all} m_in^H (W - V) m_in,
+ * with the pair functions m_in = conj(psi_i) psi_n replaced by their ISDF fits on two
+ * more point sets: mu_vn for the occupied x all pairs (P_vn) and mu_nn for the all x
+ * all pairs (P_nn), each fitted by least squares like the valence-conduction set.
+ * W - V = V^{1/2} (eps~^{-1} - I) V^{1/2} on the plane-wave list, with eps~^{-1} the
+ * static result of isdf_eps_inv for mu_idx (written to eps_inv on the way); V is the
+ * same list's Coulomb operator, for the bare exchange too.  The screened part enters
+ * in Algorithm 3's low-rank form (P_s^H V P_vc) K (P_s^H V P_vc)^H; no NG x NG matrix
+ * is read.  Arguments as for isdf_eps_inv (static: no frequencies), and
+ *   mu_vn, mu_nn  host, distinct grid indices; 1 <= n_mu_vn <= nv N and
+ *                 1 <= n_mu_nn <= N^2 (and <= Nr)
+ *   workspace     device, >= isdf_sigma_workspace_bytes(...), 256-byte aligned
+ *   eps_inv       device out, ng x ng complex128 (as isdf_eps_inv)
+ *   sigma         device out, 3 x N doubles (Hartree): [0] Sigma_SEX_X, [1] Sigma_X,
+ *                 [2] Sigma_COH (each diagonal is real: Hermitian forms)
+ * ISDF_FP64 runs every step in FP64; ISDF_FP32 and ISDF_BF16X3 run the self-energy
+ * sets' contractions over the grid and the plane waves in FP32 (complex64 storage)
+ * and their N_mu-sized algebra in FP64.  Synchronises the handle's stream.
+ * Errors: those of isdf_eps_inv; ISDF_E_UNSUPPORTED for coulomb_sum = 1; ISDF_E_NOT_PD
+ * also for S_vn or S_nn (points that make a set's C rank deficient). */
+isdf_status isdf_sigma_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t ng,
+                                       int32_t n_mu_vn, int32_t n_mu_nn, size_t* bytes);
+isdf_status isdf_sigma_cohsex(isdf_handle h, const isdf_problem* prob, const void* psi,
+                              const double* energies, const int32_t* mu_idx, int32_t n_mu,
+                              const int32_t* mu_vn, int32_t n_mu_vn, const int32_t* mu_nn,
+                              int32_t n_mu_nn, const int32_t* miller, int32_t ng,
+                              void* workspace, size_t ws_bytes, void* eps_inv, double* sigma,
+                              isdf_report* rep);
 
 /* Last error message of this handle ("" if none).  Valid until the next call. */
 const char* isdf_last_error(isdf_handle h);

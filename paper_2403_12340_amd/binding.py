@@ -73,6 +73,9 @@ def lib() -> ctypes.CDLL:
             "isdf_check_inputs": [pprob, pdbl, pi32, i32, pi32, i32, pdbl, i32, ctypes.c_char_p, sz],
             "isdf_eps_inv": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, pdbl, i32, vp, sz, vp, prep],
             "isdf_eps_inv_noalloc": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, pdbl, i32, vp, prep],
+            "isdf_sigma_workspace_bytes": [pprob, i32, i32, i32, i32, ctypes.POINTER(sz)],
+            "isdf_sigma_cohsex": [vp, pprob, vp, pdbl, pi32, i32, pi32, i32, pi32, i32, pi32, i32, vp, sz, vp, vp,
+                                  prep],
             "isdf_fit_theta": [vp, pprob, vp, pi32, i32, vp, sz, vp],
             "isdf_core_m": [vp, pprob, vp, pdbl, pi32, i32, dbl, vp, sz, vp],
             "isdf_coulomb_u": [vp, pprob, vp, pi32, i32, pi32, i32, vp, sz, vp],
@@ -303,6 +306,45 @@ def eps_inv_noalloc(psi_t, energies, mu_idx, miller, prob: Problem, omegas=None,
                                     ctypes.byref(rep))
     h.check(st, "isdf_eps_inv_noalloc")
     return Result(out, rep)
+
+
+def sigma_workspace_bytes(prob: Problem, n_mu: int, ng: int, n_mu_vn: int, n_mu_nn: int) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().isdf_sigma_workspace_bytes(ctypes.byref(prob), n_mu, ng, n_mu_vn, n_mu_nn, ctypes.byref(out))
+    if st != OK:
+        raise IsdfError(st, "isdf_sigma_workspace_bytes rejected the arguments")
+    return int(out.value)
+
+
+@dataclass
+class SigmaResult:
+    sigma: "object"        # torch float64 (3, N): Sigma_SEX_X, Sigma_X, Sigma_COH
+    eps_inv: "object"      # torch complex128 (1, ng, ng), the static eps~^{-1} built on the way
+    report: Report
+
+
+def sigma_cohsex(psi_t, energies, mu_idx, mu_vn, mu_nn, miller, prob: Problem, workspace=None) -> SigmaResult:
+    """isdf_sigma_cohsex: the static COHSEX self-energy diagonals of every band."""
+    import torch
+    _check_psi(psi_t, prob)
+    dev = psi_t.device
+    h = handle(dev.index or 0)
+    e, pe = _f64(energies)
+    mu, pmu = _i32(mu_idx)
+    mvn, pvn = _i32(mu_vn)
+    mnn, pnn = _i32(mu_nn)
+    mi, pmi = _i32(miller)
+    ng = len(mi)
+    nbytes = sigma_workspace_bytes(prob, len(mu), ng, len(mvn), len(mnn))
+    wsbuf, wsptr = _workspace(nbytes, dev, workspace)
+    out = torch.empty((1, ng, ng), dtype=torch.complex128, device=dev)
+    sig = torch.empty((3, prob.nv + prob.nc), dtype=torch.float64, device=dev)
+    rep = Report()
+    st = lib().isdf_sigma_cohsex(h.h, ctypes.byref(prob), ctypes.c_void_p(psi_t.data_ptr()), pe, pmu, len(mu),
+                                 pvn, len(mvn), pnn, len(mnn), pmi, ng, ctypes.c_void_p(wsptr), nbytes,
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(sig.data_ptr()), ctypes.byref(rep))
+    h.check(st, "isdf_sigma_cohsex")
+    return SigmaResult(sig, out, rep)
 
 
 def fit_theta(psi_t, mu_idx, prob: Problem, workspace=None):

@@ -46,8 +46,8 @@ __global__ void gather_cols_kernel(const z64* __restrict__ src, long ld, const i
   if (v < nv) out[(long)m * nv + v] = src[(long)m * ld + idx[v]];
 }
 
-// z stage: t2b[mu][d][z] = sum_{g in d} conj(twz[c_g][z]) sqrtv[g] gb[g][mu]
-__global__ void adj_z_kernel(int nmu, int nd, int n2, const int* __restrict__ off, const int* __restrict__ list,
+// z stage: t2b[mu][d][z] = sum_{g in d} conj(twz[c_g][z]) sqrtv[g] gb[g][mu] (gb row stride ldg)
+__global__ void adj_z_kernel(long ldg, int nd, int n2, const int* __restrict__ off, const int* __restrict__ list,
                              const int* __restrict__ g_cz, const z64* __restrict__ twz,
                              const double* __restrict__ sqrtv, const z64* __restrict__ gb, z64* __restrict__ t2b) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -57,7 +57,7 @@ __global__ void adj_z_kernel(int nmu, int nd, int n2, const int* __restrict__ of
   z64 acc = {0.0, 0.0};
   for (int e = off[d]; e < off[d + 1]; ++e) {
     const int g = list[e];
-    const z64 v = gb[(long)g * nmu + mu];
+    const z64 v = gb[(long)g * ldg + mu];
     const z64 tw = twz[(long)g_cz[g] * n2 + z];
     const z64 p = zcmul(tw, v);
     acc.re += sqrtv[g] * p.re;
@@ -228,7 +228,7 @@ hipError_t adj_gather_cols(const void* src, long ld, const int* idx, int nv, int
 }
 
 hipError_t adj_dft(const AdjDft& a, const void* gbar, void* t2b, void* t1b, void* gz, hipStream_t st) {
-  hipLaunchKernelGGL(adj_z_kernel, dim3(cdiv((long)a.nd * a.n2, 256), a.nmu), dim3(256), 0, st, a.nmu, a.nd, a.n2,
+  hipLaunchKernelGGL(adj_z_kernel, dim3(cdiv((long)a.nd * a.n2, 256), a.nmu), dim3(256), 0, st, a.ldg, a.nd, a.n2,
                      a.gd_off, a.gd_list, a.g_cz, (const z64*)a.twz, a.sqrtv, (const z64*)gbar, (z64*)t2b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

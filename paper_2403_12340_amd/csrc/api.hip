@@ -81,7 +81,18 @@ struct Problem {
   double f, v_scale;
   int refine;
   double recip[9];
+  int zrows = 0;   // rows of the Z^T region and the DFT scratch (0: N_mu; the adjoint works in chunks of points)
 };
+
+// Points per chunk of the adjoint: the N_mu x Nr intermediates (the pair Gram blocks
+// P_a, P_b and Z, and the cotangent of Z) are formed for one chunk of points at a
+// time, each at most 512 MiB, in chunks of equal size.
+int grad_chunk(const Problem& P) {
+  const double per = (double)P.nr * 16.0;                  // bytes of one point's row
+  const long cap = std::max<long>(1, (long)((double)(1L << 29) / per));
+  const long chunks = (P.nmu + cap - 1) / cap;
+  return (int)((P.nmu + chunks - 1) / chunks);
+}
 
 // pruned-DFT index lists derived from the Miller list (host bookkeeping)
 struct DftIndex {
@@ -239,6 +250,7 @@ struct Layout {
   size_t part = 0, l2 = 0, lin2 = 0, q = 0;  // core partials; second -M buffer, sweep scratch, S M^-1 S scratch
   size_t pm32 = 0;                   // complex64 copy of the orbitals at the points (FP32 mode only)
   size_t bf_rows = 0, bf_pts = 0;    // bf16 hi / lo planes of the orbitals (BF16x3 mode only)
+  size_t core_a = 0;                 // bf16 hi / lo planes of the empty states at the points (BF16x3 core)
   // contour-integral core: node table (lambda, weight), scaled operands, Gram pairs, running sum
   size_t cnodes = 0, cops = 0, cprod = 0, csum = 0, cpm32 = 0;
   int kx = 0, ky = 0, kz = 0, nd = 0, nsplit = 1;
@@ -261,6 +273,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   } else if (P.prec == PBF3) {
     L.bf_rows = take(bf3_rows_bytes(P.nr, P.nv, P.nc));
     L.bf_pts = take(bf3_points_bytes(P.nmu, P.nv, P.nc));
+    if (core_bf3_fits(P.nmu, P.nc)) L.core_a = take(core_bf3_plane_bytes(P.nmu, P.nc));
   }
   if (P.core_method == 1) {
     L.cnodes = take((size_t)2 * CAUCHY_MAX_NODES * z);
@@ -284,7 +297,8 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   L.s = take(nmu2 * z);
   L.lin = take(linalg_scratch_bytes(P.nmu));
   // T2 of the separate x/y and z stages, or the fused DFT's per-z-block partial sums
-  L.t2_bytes = std::max((size_t)P.nmu * P.n2 * nd, (size_t)std::min(DFT_MAX_ZBLOCKS, P.n2) * P.nmu * P.ngg) * el;
+  const size_t zr = (size_t)(P.zrows > 0 ? P.zrows : P.nmu);
+  L.t2_bytes = std::max(zr * P.n2 * nd, (size_t)std::min(DFT_MAX_ZBLOCKS, P.n2) * zr * P.ngg) * el;
   L.t2 = take(L.t2_bytes);
   L.zg = take((size_t)P.nmu * P.ngg * el);
   L.u = take((size_t)P.ng * P.nmu * el);
@@ -310,7 +324,7 @@ Layout make_layout(const Problem& P, int kx, int ky, int kz, int nd) {
   }
   // big region: Zt (N_mu x Nr); once the DFT has consumed it, reused for the
   // split-K partial sums of U^H U and for U T
-  const size_t zt_bytes = (size_t)P.nmu * P.nr * el;
+  const size_t zt_bytes = zr * P.nr * el;
   const size_t w1_bytes = (size_t)P.ng * P.nmu * el;
   L.zt_bytes = std::max(zt_bytes, w1_bytes);
   L.zt = take(L.zt_bytes);
@@ -340,6 +354,8 @@ isdf_status fail(isdf_handle h, isdf_status s, const std::string& msg) {
     if (e_ != hipSuccess)                                                                  \
       return fail(h, ISDF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
   } while (0)
+
+#define TRY(x) do { isdf_status s_ = (x); if (s_ != ISDF_OK) return s_; } while (0)
 
 isdf_status check_problem(isdf_handle h, const isdf_problem* pr, Problem& P) {
   if (!pr) return fail(h, ISDF_E_ARG, "problem is NULL");
@@ -522,6 +538,7 @@ struct Run {
   const void* tmat = nullptr;  // T (times talpha) after the core algebra
   int cn = 0;                  // contour nodes in the table (core_method 1)
   double talpha = 1.0;
+  Prec grad_big = P64;         // adjoint: compute precision of the contractions over the grid
   hipStream_t st;
 };
 
@@ -634,30 +651,43 @@ DftPlan make_plan(Run& R) {
   return p;
 }
 
-// Unitary DFT of the N_mu rows of Z^T on the plane-wave list.  With scaled = true the
-// result is X^T = (V^{1/2} F Z)^T, [mu][g] in the zg buffer.
-isdf_status stage_dft(Run& R, bool scaled) {
+// The pruned DFT of p.nmu rows zt[mu][r] onto the plane-wave list (times scale[g] if
+// given): the fused pass when the shape fits, else the x/y and z kernels.  t2 is the
+// scratch of either (t2_bytes).
+isdf_status dft_apply(Run& R, const DftPlan& p, const void* zt, void* t2, size_t t2_bytes, void* zg,
+                      const double* scale) {
   isdf_handle h = R.h;
-  const Problem& P = R.P;
-  const Layout& L = R.L;
-  const Prec cp = P.prec == P64 ? P64 : P32;
-  DftPlan p = make_plan(R);
-  const int* ib = R.idx;
-  HIPCHK(coulomb_sqrt(R.miller, P.ngg, R.recip, P.v_scale,
-                      at<double>(R.ws, L.sqrtv), R.st));
-  HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), R.st));
-  HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), R.st));
-  HIPCHK(dft_twiddles(ib + L.kx + L.ky, L.kz, P.n2, P.m32, at<char>(R.ws, L.twz), R.st));
-  const double* scale = scaled ? at<double>(R.ws, L.sqrtv) : nullptr;
+  const Prec cp = R.P.prec == P64 ? P64 : P32;
   if (dft_fused_fits(cp, p)) {
-    const hipError_t e = dft_fused(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), L.t2_bytes,
-                                   at<char>(R.ws, L.zg), scale, R.st);
+    const hipError_t e = dft_fused(cp, p, zt, t2, t2_bytes, zg, scale, R.st);
     if (e == hipSuccess) return ISDF_OK;
     if (e != hipErrorNotSupported) HIPCHK(e);
   }
-  HIPCHK(dft_xy(cp, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), R.st));
-  HIPCHK(dft_z(cp, p, at<char>(R.ws, L.t2), at<char>(R.ws, L.zg), scale, R.st));
+  HIPCHK(dft_xy(cp, p, zt, t2, R.st));
+  HIPCHK(dft_z(cp, p, t2, zg, scale, R.st));
   return ISDF_OK;
+}
+
+// Unitary DFT of the N_mu rows of Z^T on the plane-wave list.  With scaled = true the
+// result is X^T = (V^{1/2} F Z)^T, [mu][g] in the zg buffer.
+isdf_status dft_tables(Run& R) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const int* ib = R.idx;
+  HIPCHK(coulomb_sqrt(R.miller, P.ngg, R.recip, P.v_scale, at<double>(R.ws, L.sqrtv), R.st));
+  HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), R.st));
+  HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), R.st));
+  HIPCHK(dft_twiddles(ib + L.kx + L.ky, L.kz, P.n2, P.m32, at<char>(R.ws, L.twz), R.st));
+  return ISDF_OK;
+}
+
+isdf_status stage_dft(Run& R, bool scaled) {
+  const Layout& L = R.L;
+  TRY(dft_tables(R));
+  DftPlan p = make_plan(R);
+  const double* scale = scaled ? at<double>(R.ws, L.sqrtv) : nullptr;
+  return dft_apply(R, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), L.t2_bytes, at<char>(R.ws, L.zg), scale);
 }
 
 // U = X S^{-1} (stage entry only): U(g, nu) = sum_mu Xt[mu][g] S^{-1}(mu, nu), S^{-1}(mu, nu) = -Sw[nu][mu]
@@ -776,6 +806,14 @@ isdf_status stage_core(Run& R, double omega, void* m_out, void* negm, hipStream_
   double* w = at<double>(R.ws, R.L.w);
   HIPCHK(pair_weights(R.e, P.nv, P.nc, omega, w, st));
   void* part = at<char>(R.ws, R.L.part);
+  if (P.prec == PBF3 && R.L.core_a) {
+    void* planes = at<char>(R.ws, R.L.core_a);
+    const int ns = core32_splits(P.nmu, P.nv, R.L.nsplit);
+    HIPCHK(core_bf3_split(P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), planes, st));
+    HIPCHK(core_bf3_partial(P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), planes, w, part, ns, st));
+    HIPCHK(core_reduce(cp, P.nmu, part, ns, P.f, m_out, negm, st));
+    return ISDF_OK;
+  }
   if (cp == P32 && core32_fits(P.nmu, P.nc)) {
     const int ns = core32_splits(P.nmu, P.nv, R.L.nsplit);
     HIPCHK(core32_partial(P.nmu, P.nv, P.nc, at<char>(R.ws, R.L.pm), w, part, ns, st));
@@ -939,10 +977,11 @@ isdf_status finish(Run& R, isdf_report* rep, Timer& tm) {
 isdf_status setup_common(Run& R, isdf_handle h, const isdf_problem* prob, const void* psi,
                          const int32_t* mu_idx, int n_mu, const int32_t* miller, int ng,
                          const double* energies, int nomega, void* ws, size_t ws_bytes, Uploader& up_,
-                         DftIndex& ix, std::vector<int>& idxbuf) {
+                         DftIndex& ix, std::vector<int>& idxbuf, bool grad = false) {
   if (!h) return ISDF_E_ARG;
   isdf_status s = begin(h, prob, R.P, n_mu, ng, nomega);
   if (s != ISDF_OK) return s;
+  if (grad) R.P.zrows = grad_chunk(R.P);
   if (!psi) return fail(h, ISDF_E_ARG, "psi is NULL");
   s = check_points(h, R.P, mu_idx, n_mu);
   if (s != ISDF_OK) return s;
@@ -1003,7 +1042,6 @@ isdf_status clear_status(Run& R) {
   return ISDF_OK;
 }
 
-#define TRY(x) do { isdf_status s_ = (x); if (s_ != ISDF_OK) return s_; } while (0)
 
 // Enqueue the whole path on the handle's stream (and its second stream, joined
 // back before returning).  No host synchronisation; the status block collects
@@ -1032,7 +1070,11 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
   for (int k = 0; k < nw; ++k)
     HIPCHK(pair_weights(R.e, P.nv, P.nc, omega[k], wb + (long)k * P.nv * P.nc, R.st));
   void* mb = at<char>(R.ws, L.mb);
-  if (cp == P32 && core32_fits(n, P.nc))
+  if (P.prec == PBF3 && L.core_a) {
+    HIPCHK(core_bf3_split(n, P.nv, P.nc, at<char>(R.ws, L.pm), at<char>(R.ws, L.core_a), R.st));
+    HIPCHK(core_bf3_partial(n, P.nv, P.nc, at<char>(R.ws, L.pm), at<char>(R.ws, L.core_a), wb,
+                            at<char>(R.ws, L.partb), 1, R.st, nw));
+  } else if (cp == P32 && core32_fits(n, P.nc))
     HIPCHK(core32_partial(n, P.nv, P.nc, at<char>(R.ws, L.pm), wb, at<char>(R.ws, L.partb), 1, R.st, nw));
   else
     HIPCHK(core_partial(cp, n, P.nv, P.nc, at<char>(R.ws, L.pm), n, wb, at<char>(R.ws, L.partb), 1, R.st, nw));
@@ -1178,6 +1220,180 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   }
   HIPCHK(hipEventRecord(h->join, side));
   HIPCHK(hipStreamWaitEvent(R.st, h->join, 0));
+  return ISDF_OK;
+}
+
+// ---- COHSEX self-energy diagonals (Algorithm 3, steps 2 and 4-7) ------------------
+// Two more pair sets, each with its own points: vn (occupied x all states) and nn
+// (all x all).  For a set s with points r_mu^s:
+//   S_s = C_s C_s^H and Z_s = M_s C_s^H (the least-squares fit, as for the vc set),
+//   X_s = V^{1/2} F Z_s on the plane-wave list, A_s = X_s^H X (X of the vc set),
+//   W_s = -S_s^{-1} A_s H^{-1} A_s^H S_s^{-1}, which is Algorithm 3's
+//         (P_s^H V P_vc) K (P_s^H V P_vc)^H with P = Theta = Z S^{-1} and
+//         K = (M^{-1} - U^H U)^{-1} = -S H^{-1} S, H = X^H X - S M^{-1} S;
+//   V_vn = S_vn^{-1} X_vn^H X_vn S_vn^{-1} (the bare exchange on the vn points);
+//   then eq. Hadamard: Sigma(n) = coef diag(Psi_s^H (W_s (.) G_set) Psi_s)(n).
+// All N_mu-sized algebra runs in FP64; the contractions over the grid and the
+// plane waves in the mode's precision (BF16x3: FP32).
+struct SigmaLayout {
+  size_t mu_vn = 0, mu_nn = 0, pm = 0, pm32 = 0, s = 0, lin = 0, a = 0, q = 0, b = 0, q2 = 0, w = 0, g = 0,
+         e = 0, xt = 0, t2 = 0, zt = 0, total = 0;
+  size_t t2_bytes = 0;
+};
+
+// the sigma region starts at `base` (the end of the eps~^{-1} layout)
+SigmaLayout make_sigma_layout(const Problem& P, int nd, int nvn, int nnn, size_t base) {
+  SigmaLayout S;
+  size_t off = base;
+  auto take = [&](size_t bytes) { size_t o = off; off += up(std::max<size_t>(bytes, 1)); return o; };
+  const size_t z = 16, el = P.m32 ? 8 : 16;
+  const size_t nm = (size_t)std::max(nvn, nnn);
+  S.mu_vn = take((size_t)nvn * 4);
+  S.mu_nn = take((size_t)nnn * 4);
+  S.pm = take((size_t)P.ns * nm * z);
+  if (P.m32) S.pm32 = take((size_t)P.ns * nm * 8);
+  S.s = take(nm * nm * z);
+  S.lin = take(linalg_scratch_bytes((int)nm));
+  S.a = take(nm * P.nmu * z);
+  S.q = take(nm * P.nmu * z);
+  S.b = take(nm * nm * z);
+  S.q2 = take(nm * nm * z);
+  S.w = take(nm * nm * z);
+  S.g = take(nm * nm * z);
+  S.e = take(nm * P.ns * z);
+  S.xt = take(nm * P.ng * el);
+  S.t2_bytes = std::max(nm * P.n2 * nd, (size_t)std::min(DFT_MAX_ZBLOCKS, P.n2) * nm * P.ng) * el;
+  S.t2 = take(S.t2_bytes);
+  S.zt = take(nm * P.nr * el);
+  S.total = off - base;
+  return S;
+}
+
+isdf_status check_set_points(isdf_handle h, const Problem& P, const int32_t* mu, int nmu, long pairs, const char* what) {
+  if (!mu) return fail(h, ISDF_E_ARG, std::string(what) + " is NULL");
+  if (nmu < 1) return fail(h, ISDF_E_ARG, std::string(what) + ": need at least one point");
+  if ((long)nmu > pairs || (long)nmu > P.nr)
+    return fail(h, ISDF_E_ARG, std::string(what) + ": more points than pair functions or grid points (S would be singular)");
+  std::vector<int32_t> v(mu, mu + nmu);
+  std::sort(v.begin(), v.end());
+  if (v.front() < 0 || v.back() >= P.nr) return fail(h, ISDF_E_ARG, std::string(what) + " out of range");
+  for (int i = 1; i < nmu; ++i)
+    if (v[i] == v[i - 1]) return fail(h, ISDF_E_ARG, std::string(what) + " has duplicate points");
+  return ISDF_OK;
+}
+
+// One pair set: na states in the first range (occupied: nv, or all: ns), all states in
+// the second; sigma terms written to out_terms[k] for each (coef, use_w) requested.
+isdf_status enqueue_sigma_set(Run& R, const SigmaLayout& S, const int* mu, int nmu, int na, bool with_exchange,
+                              double* out_sx, double* out_x, double* out_coh) {
+  isdf_handle h = R.h;
+  const Problem& P = R.P;
+  const Layout& L = R.L;
+  const Prec cp = P.prec == P64 ? P64 : P32;
+  const int ns = P.ns, n = P.nmu, ng = P.ng;
+  const long m2 = (long)nmu * nmu;
+  void* pm = at<char>(R.ws, S.pm);
+  void* sw = at<char>(R.ws, S.s);
+  HIPCHK(gather_points(R.psi, P.nr, ns, mu, nmu, pm, R.st));
+  // S_s^T = conj(S_s) on the points, then Sw = -(S_s^T)^{-1} = -conj(S_s^{-1})
+  HIPCHK(zpair(P64, nmu, nmu, na, na + ns, pm, nmu, pm, nmu, false, sw, nmu, false, R.st, 1, 0));
+  HIPCHK(sweep_inverse(nmu, sw, at<char>(R.ws, S.lin), &R.sb->status, R.st));
+  // Z_s^T [mu][r] over the grid, then X_s^T = (V^{1/2} F Z_s)^T [mu][g]
+  void* zt = at<char>(R.ws, S.zt);
+  if (cp == P64) {
+    HIPCHK(zpair(P64, nmu, (int)P.nr, na, na + ns, pm, nmu, R.psi, P.nr, false, zt, P.nr, false, R.st, 1, 0));
+  } else {
+    void* pm32 = at<char>(R.ws, S.pm32);
+    HIPCHK(convert_z(pm, false, pm32, true, (long)ns * nmu, R.st));
+    HIPCHK(zpair(P32, nmu, (int)P.nr, na, na + ns, pm32, nmu, R.psi, P.nr, true, zt, P.nr, true, R.st,
+                 R.tune.wg_per_cu, 0));
+  }
+  DftPlan dp = make_plan(R);
+  dp.nmu = nmu;
+  void* xt = at<char>(R.ws, S.xt);
+  TRY(dft_apply(R, dp, zt, at<char>(R.ws, S.t2), S.t2_bytes, xt, at<double>(R.ws, L.sqrtv)));
+  // A_s = X_s^H X (N_mu^s x N_mu), over the plane waves
+  void* a = at<char>(R.ws, S.a);
+  {
+    GemmDesc d;
+    d.M = nmu; d.N = n; d.K = ng;
+    d.A = xt; d.sam = ng; d.sak = 1; d.conjA = true; d.a32 = P.m32;
+    d.B = at<char>(R.ws, L.zg); d.sbk = 1; d.sbn = P.ngg; d.b32 = P.m32;
+    d.C = a; d.ldc = n;
+    HIPCHK(gemm(cp, d, R.st));
+  }
+  // B_s = A_s H^{-1} A_s^H with H^{-1} = talpha * tmat (FP64)
+  void* q = at<char>(R.ws, S.q);
+  void* b = at<char>(R.ws, S.b);
+  {
+    GemmDesc d;
+    d.M = nmu; d.N = n; d.K = n;
+    d.A = a; d.sam = n; d.sak = 1;
+    d.B = R.tmat; d.sbk = n; d.sbn = 1;
+    d.C = q; d.ldc = n; d.alpha = R.talpha;
+    HIPCHK(gemm(P64, d, R.st));
+    GemmDesc e;
+    e.M = e.N = nmu; e.K = n;
+    e.A = q; e.sam = n; e.sak = 1;
+    e.B = a; e.sbk = 1; e.sbn = n; e.conjB = true;
+    e.C = b; e.ldc = nmu; e.herm = true;
+    HIPCHK(gemm(P64, e, R.st));
+  }
+  // sandwich: out = alpha S_s^{-1} in S_s^{-1} = alpha conj(Sw) in conj(Sw)
+  void* q2 = at<char>(R.ws, S.q2);
+  void* w = at<char>(R.ws, S.w);
+  auto sandwich = [&](const void* in, double alpha, void* out) -> isdf_status {
+    GemmDesc d;
+    d.M = d.N = d.K = nmu;
+    d.A = in; d.sam = nmu; d.sak = 1;
+    d.B = sw; d.sbk = nmu; d.sbn = 1; d.conjB = true;
+    d.C = q2; d.ldc = nmu;
+    HIPCHK(gemm(P64, d, R.st));
+    GemmDesc e;
+    e.M = e.N = e.K = nmu;
+    e.A = sw; e.sam = nmu; e.sak = 1; e.conjA = true;
+    e.B = q2; e.sbk = nmu; e.sbn = 1;
+    e.C = out; e.ldc = nmu; e.alpha = alpha; e.herm = true;
+    HIPCHK(gemm(P64, e, R.st));
+    return ISDF_OK;
+  };
+  // G_set(mu, nu) = sum_{i < na} psi_i(r_mu) conj(psi_i(r_nu))
+  void* g = at<char>(R.ws, S.g);
+  {
+    GemmDesc d;
+    d.M = d.N = nmu; d.K = na;
+    d.A = pm; d.sam = 1; d.sak = nmu;
+    d.B = pm; d.sbk = nmu; d.sbn = 1; d.conjB = true;
+    d.C = g; d.ldc = nmu; d.herm = true;
+    HIPCHK(gemm(P64, d, R.st));
+  }
+  // Sigma(n) = coef Re diag(Psi^H (Y (.) G) Psi), Y = W_s or V_vn
+  void* ebuf = at<char>(R.ws, S.e);
+  auto diag_term = [&](const void* y, double coef, double* out) -> isdf_status {
+    HIPCHK(mul_z(y, g, q2, m2, R.st));
+    GemmDesc d;   // E = (Y (.) G) Psi, Psi(nu, n) = pm[n][nu]
+    d.M = nmu; d.N = ns; d.K = nmu;
+    d.A = q2; d.sam = nmu; d.sak = 1;
+    d.B = pm; d.sbk = 1; d.sbn = nmu;
+    d.C = ebuf; d.ldc = ns;
+    HIPCHK(gemm(P64, d, R.st));
+    HIPCHK(sigma_diag(pm, ebuf, nmu, ns, coef, out, R.st));
+    return ISDF_OK;
+  };
+  TRY(sandwich(b, -1.0, w));                       // W_s
+  if (with_exchange) {
+    TRY(diag_term(w, -1.0, out_sx));               // Sigma_SEX_X = -diag(Psi^H (W_vn (.) G_v) Psi)
+    GemmDesc d;                                    // X_vn^H X_vn (Hermitian, over the plane waves)
+    d.M = d.N = nmu; d.K = ng;
+    d.A = xt; d.sam = ng; d.sak = 1; d.conjA = true; d.a32 = P.m32;
+    d.B = xt; d.sbk = 1; d.sbn = ng; d.b32 = P.m32;
+    d.C = b; d.ldc = nmu; d.herm = true;
+    HIPCHK(gemm(cp, d, R.st));
+    TRY(sandwich(b, 1.0, w));                      // V_vn
+    TRY(diag_term(w, -1.0, out_x));                // Sigma_X
+  } else {
+    TRY(diag_term(w, 0.5, out_coh));               // Sigma_COH = 1/2 diag(Psi^H (W_nn (.) G_all) Psi)
+  }
   return ISDF_OK;
 }
 
@@ -1397,6 +1613,56 @@ isdf_status isdf_eps_inv_noalloc(isdf_handle h, const isdf_problem* prob, const 
   Timer tm{h, rep && rep->want_timing != 0};
   tm.mark();
   TRY(enqueue_eps_inv(R, psi, omega, n_omega, eps_inv, tm));
+  return finish(R, rep, tm);
+}
+
+isdf_status isdf_sigma_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t ng, int32_t n_mu_vn,
+                                       int32_t n_mu_nn, size_t* bytes) {
+  if (!bytes || n_mu_vn < 1 || n_mu_nn < 1) return ISDF_E_ARG;
+  size_t main = 0;
+  TRY(isdf_workspace_bytes(prob, n_mu, ng, 0, &main));
+  Problem P;
+  TRY(check_problem(nullptr, prob, P));
+  P.nmu = n_mu;
+  P.ng = P.ngg = ng;
+  const int nd = (int)std::min<long>(ng, (long)P.n0 * P.n1);
+  *bytes = main + make_sigma_layout(P, nd, n_mu_vn, n_mu_nn, main).total;
+  return ISDF_OK;
+}
+
+isdf_status isdf_sigma_cohsex(isdf_handle h, const isdf_problem* prob, const void* psi, const double* energies,
+                              const int32_t* mu_idx, int32_t n_mu, const int32_t* mu_vn, int32_t n_mu_vn,
+                              const int32_t* mu_nn, int32_t n_mu_nn, const int32_t* miller, int32_t ng,
+                              void* workspace, size_t ws_bytes, void* eps_inv, double* sigma, isdf_report* rep) {
+  if (!h) return ISDF_E_ARG;
+  if (!eps_inv) return fail(h, ISDF_E_ARG, "eps_inv is NULL");
+  if (!sigma) return fail(h, ISDF_E_ARG, "sigma is NULL");
+  if (!energies) return fail(h, ISDF_E_ARG, "energies is NULL");
+  if (!miller) return fail(h, ISDF_E_ARG, "miller is NULL");
+  if (prob && prob->coulomb_sum != 0)
+    return fail(h, ISDF_E_UNSUPPORTED, "the self-energies use the plane-wave list's Coulomb operator (coulomb_sum = 0)");
+  Run R;
+  Uploader upl;
+  DftIndex ix;
+  std::vector<int> idxbuf;
+  // the eps~^{-1} layout first, checked against the whole workspace below
+  TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, energies, 0, workspace, ws_bytes, upl, ix, idxbuf));
+  const Problem& P = R.P;
+  TRY(check_set_points(h, P, mu_vn, n_mu_vn, (long)P.nv * P.ns, "mu_vn"));
+  TRY(check_set_points(h, P, mu_nn, n_mu_nn, (long)P.ns * P.ns, "mu_nn"));
+  const SigmaLayout S = make_sigma_layout(P, R.L.nd, n_mu_vn, n_mu_nn, R.L.total);
+  TRY(check_ws(h, workspace, ws_bytes, R.L.total + S.total));
+  upl.add(S.mu_vn, mu_vn, (size_t)n_mu_vn * 4);
+  upl.add(S.mu_nn, mu_nn, (size_t)n_mu_nn * 4);
+  HIPCHK(hipSetDevice(h->device));
+  TRY(upl.run());
+  TRY(clear_status(R));
+  Timer tm{h, rep && rep->want_timing != 0};
+  tm.mark();
+  TRY(enqueue_eps_inv(R, psi, nullptr, 0, eps_inv, tm));
+  const int ns = P.ns;
+  TRY(enqueue_sigma_set(R, S, at<int>(workspace, S.mu_vn), n_mu_vn, P.nv, true, sigma, sigma + ns, nullptr));
+  TRY(enqueue_sigma_set(R, S, at<int>(workspace, S.mu_nn), n_mu_nn, ns, false, nullptr, nullptr, sigma + 2 * ns));
   return finish(R, rep, tm);
 }
 
@@ -1958,11 +2224,15 @@ GradLayout grad_layout(const Problem& P, const Layout& L, int kx, int nd) {
   GradLayout G;
   size_t off = L.total;
   auto take = [&](size_t bytes) { size_t o = off; off += up(std::max<size_t>(bytes, 1)); return o; };
-  const size_t z = 16, n2 = (size_t)P.nmu * P.nmu * z, tall = (size_t)P.nmu * P.nr * z,
+  const size_t cz = (size_t)(P.zrows > 0 ? P.zrows : P.nmu);   // points per chunk
+  // the core backward's batches of occupied states reuse the pa / pb regions
+  G.nb = (int)std::max<long>(1, std::min<long>(std::min<long>(P.nv, 64), (long)(cz * P.nr / ((size_t)P.nmu * P.nc))));
+  const size_t z = 16, n2 = (size_t)P.nmu * P.nmu * z,
+               tall = std::max(cz * P.nr, (size_t)G.nb * P.nmu * P.nc) * z,
                list = (size_t)P.ngg * P.nmu * z;
   G.pa = take(tall);
   G.pb = take(tall);
-  G.t1b = take((size_t)P.nmu * P.n2 * P.n1 * kx * z);
+  G.t1b = take(cz * P.n2 * P.n1 * kx * z);
   G.u = take(list); G.y = take(list); G.t = take(list); G.gu = take(list); G.gbar = take(list);
   for (size_t* f : {&G.ga, &G.gb, &G.s, &G.sinv, &G.m, &G.minv, &G.km, &G.p, &G.yht, &G.r, &G.tmp, &G.gs,
                     &G.ha, &G.hb, &G.qa})
@@ -1971,7 +2241,6 @@ GradLayout grad_layout(const Problem& P, const Layout& L, int kx, int nd) {
   G.csr = take((size_t)(nd + 1 + P.ngg + kx + 1 + nd) * 4);
   G.loss = take(8);
   G.total = off;
-  G.nb = (int)std::max<long>(1, std::min<long>(std::min<long>(P.nv, 64), P.nr / P.nc));
   return G;
 }
 
@@ -2026,12 +2295,26 @@ isdf_status enqueue_grad(Run& R, const GradLayout& G, const void* psi, double om
     d.split_ws = B(L.zt); d.split_ws_bytes = L.zt_bytes; d.max_split = cap;
     return d;
   };
-  // forward, recomputed: Pa^T, Pb^T, Z^T = conj(Pa^T) Pb^T, X^T = (V^{1/2} F Z)^T
-  HIPCHK(gemm(P64, gd(nmu, (int)nr, nv, pm, 1, nmu, true, ps, nr, 1, false, B(G.pa), nr), st));
-  HIPCHK(gemm(P64, gd(nmu, (int)nr, nc, pm + (size_t)nv * nmu * 16, 1, nmu, true, ps + (size_t)nv * nr * 16, nr, 1,
-                      false, B(G.pb), nr), st));
-  HIPCHK(adj_conj_mul(B(G.pa), B(G.pb), B(L.zt), (long)nmu * nr, st));
-  TRY(stage_dft(R, true));
+  // The N_mu x Nr intermediates exist for one chunk of points [c0, c0 + cn) at a time.
+  const int chunk = P.zrows > 0 ? P.zrows : nmu;
+  // Pa^T, Pb^T of a chunk: Pa^T[mu][r] = sum_{i < nv} conj(psi_i(r_mu)) psi_i(r), Pb^T over the empty states
+  auto pair_blocks = [&](int c0, int cn) -> isdf_status {
+    HIPCHK(gemm(R.grad_big, gd(cn, (int)nr, nv, pm + (size_t)c0 * 16, 1, nmu, true, ps, nr, 1, false, B(G.pa), nr),
+                st));
+    HIPCHK(gemm(R.grad_big, gd(cn, (int)nr, nc, pm + ((size_t)nv * nmu + c0) * 16, 1, nmu, true,
+                               ps + (size_t)nv * nr * 16, nr, 1, false, B(G.pb), nr), st));
+    return ISDF_OK;
+  };
+  // forward, recomputed chunk by chunk: Z^T = conj(Pa^T) Pb^T, X^T = (V^{1/2} F Z)^T (rows c0..)
+  TRY(dft_tables(R));
+  for (int c0 = 0; c0 < nmu; c0 += chunk) {
+    const int cn = std::min(chunk, nmu - c0);
+    TRY(pair_blocks(c0, cn));
+    HIPCHK(adj_conj_mul(B(G.pa), B(G.pb), B(L.zt), (long)cn * nr, st));
+    DftPlan dp = make_plan(R);
+    dp.nmu = cn;
+    TRY(dft_apply(R, dp, B(L.zt), B(L.t2), L.t2_bytes, B(L.zg) + (size_t)c0 * ngg * 16, at<double>(R.ws, L.sqrtv)));
+  }
   // S = conj(Ga) Gb, S^{-1}; M (with its pair weights) and M^{-1}
   HIPCHK(gemm(P64, gd(nmu, nmu, nv, pm, 1, nmu, false, pm, nmu, 1, true, B(G.ga), nmu), st));
   HIPCHK(gemm(P64, gd(nmu, nmu, nc, pm + (size_t)nv * nmu * 16, 1, nmu, false, pm + (size_t)nv * nmu * 16, nmu, 1,
@@ -2066,32 +2349,40 @@ isdf_status enqueue_grad(Run& R, const GradLayout& G, const void* psi, double om
   // Gbar = G_U S^{-1};  G_S = -U^H Gbar
   HIPCHK(gemm(P64, gd(ngg, nmu, nmu, B(G.gu), nmu, 1, false, B(G.sinv), nmu, 1, false, B(G.gbar), nmu), st));
   HIPCHK(gemm(P64, split(gd(nmu, nmu, ngg, B(G.u), 1, nmu, true, B(G.gbar), nmu, 1, false, B(G.gs), nmu, -1.0)), st));
-  // G_Z^T = (F^H V^{1/2} Gbar)^T into the Z^T region
-  {
-    const int* ib = R.idx;
-    const int32_t* c = reinterpret_cast<const int32_t*>(B(G.csr));
-    AdjDft a;
-    a.n0 = P.n0; a.n1 = P.n1; a.n2 = P.n2; a.nmu = nmu; a.kx = L.kx; a.nd = L.nd;
-    a.twx = B(L.twx); a.twy = B(L.twy); a.twz = B(L.twz);
-    a.sqrtv = at<double>(R.ws, L.sqrtv);
-    a.gd_off = c; a.gd_list = c + L.nd + 1; a.da_off = a.gd_list + ngg; a.da_list = a.da_off + L.kx + 1;
-    // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ngg] g_cz[ngg] dmap
-    a.d_by = ib + L.kx + L.ky + L.kz + L.nd;
-    a.g_cz = ib + L.kx + L.ky + L.kz + 2 * L.nd + ngg;
-    HIPCHK(adj_dft(a, B(G.gbar), B(L.t2), B(G.t1b), B(L.zt), st));
+  // Per chunk of points: G_Z^T = (F^H V^{1/2} Gbar)^T into the Z^T region, the pair blocks
+  // recomputed, their cotangents in place, and the orbital gradients at the points
+  // through the point side of the pair products (sum over the grid: columns c0.. of the
+  // outputs) and through the grid rows that are themselves points (all columns,
+  // accumulated over the chunks).
+  const int* ib = R.idx;
+  const int32_t* csr = reinterpret_cast<const int32_t*>(B(G.csr));
+  HIPCHK(zero_fill(gpsi, (size_t)P.ns * nmu * 16, st));   // every term below accumulates
+  for (int c0 = 0; c0 < nmu; c0 += chunk) {
+    const int cn = std::min(chunk, nmu - c0);
+    {
+      AdjDft a;
+      a.n0 = P.n0; a.n1 = P.n1; a.n2 = P.n2; a.nmu = cn; a.ldg = nmu; a.kx = L.kx; a.nd = L.nd;
+      a.twx = B(L.twx); a.twy = B(L.twy); a.twz = B(L.twz);
+      a.sqrtv = at<double>(R.ws, L.sqrtv);
+      a.gd_off = csr; a.gd_list = csr + L.nd + 1; a.da_off = a.gd_list + ngg; a.da_list = a.da_off + L.kx + 1;
+      // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ngg] g_cz[ngg] dmap
+      a.d_by = ib + L.kx + L.ky + L.kz + L.nd;
+      a.g_cz = ib + L.kx + L.ky + L.kz + 2 * L.nd + ngg;
+      HIPCHK(adj_dft(a, B(G.gbar) + (size_t)c0 * 16, B(L.t2), B(G.t1b), B(L.zt), st));
+    }
+    TRY(pair_blocks(c0, cn));
+    HIPCHK(adj_pair_grad(B(L.zt), B(G.pa), B(G.pb), (long)cn * nr, st));   // G_Pa^T, G_Pb^T
+    HIPCHK(gemm(R.grad_big, split(gd(nv, cn, (int)nr, ps, nr, 1, false, B(G.pa), 1, nr, true,
+                                     ga_out + (size_t)c0 * 16, nmu, 1.0, 1.0), 64), st));
+    HIPCHK(gemm(R.grad_big, split(gd(nc, cn, (int)nr, ps + (size_t)nv * nr * 16, nr, 1, false, B(G.pb), 1, nr, true,
+                                     gb_out + (size_t)c0 * 16, nmu, 1.0, 1.0), 64), st));
+    HIPCHK(adj_gather_cols(B(G.pa), nr, R.mu, nmu, cn, B(G.qa), st));
+    HIPCHK(gemm(P64, gd(nv, nmu, cn, pm + (size_t)c0 * 16, nmu, 1, false, B(G.qa), nmu, 1, false, ga_out, nmu, 1.0,
+                        1.0), st));
+    HIPCHK(adj_gather_cols(B(G.pb), nr, R.mu, nmu, cn, B(G.qa), st));
+    HIPCHK(gemm(P64, gd(nc, nmu, cn, pm + ((size_t)nv * nmu + c0) * 16, nmu, 1, false, B(G.qa), nmu, 1, false, gb_out,
+                        nmu, 1.0, 1.0), st));
   }
-  // G_Pa^T, G_Pb^T in place of Pa^T, Pb^T
-  HIPCHK(adj_pair_grad(B(L.zt), B(G.pa), B(G.pb), (long)nmu * nr, st));
-  // orbital gradients at the points: through the point side of the pair products (sum over the grid) ...
-  HIPCHK(gemm(P64, split(gd(nv, nmu, (int)nr, ps, nr, 1, false, B(G.pa), 1, nr, true, ga_out, nmu), 64), st));
-  HIPCHK(gemm(P64, split(gd(nc, nmu, (int)nr, ps + (size_t)nv * nr * 16, nr, 1, false, B(G.pb), 1, nr, true, gb_out,
-                            nmu), 64), st));
-  // ... the grid rows that are themselves points ...
-  HIPCHK(adj_gather_cols(B(G.pa), nr, R.mu, nmu, nmu, B(G.qa), st));
-  HIPCHK(gemm(P64, gd(nv, nmu, nmu, pm, nmu, 1, false, B(G.qa), nmu, 1, false, ga_out, nmu, 1.0, 1.0), st));
-  HIPCHK(adj_gather_cols(B(G.pb), nr, R.mu, nmu, nmu, B(G.qa), st));
-  HIPCHK(gemm(P64, gd(nc, nmu, nmu, pm + (size_t)nv * nmu * 16, nmu, 1, false, B(G.qa), nmu, 1, false, gb_out, nmu,
-                      1.0, 1.0), st));
   // ... S = conj(Ga) Gb ...
   HIPCHK(adj_pair_grad(B(G.gs), B(G.ga), B(G.gb), n2, st));
   HIPCHK(adj_herm_plus(B(G.ga), B(G.ha), nmu, st));
@@ -2134,16 +2425,19 @@ isdf_status isdf_contour_nodes(const double* energies, int32_t nv, int32_t nc, d
 }
 
 isdf_status isdf_grad_workspace_bytes(const isdf_problem* prob, int32_t n_mu, int32_t ng, size_t* bytes) {
-  if (!bytes) return ISDF_E_ARG;
+  if (!bytes || !prob) return ISDF_E_ARG;
+  if (prob->prec == ISDF_BF16X3) return ISDF_E_UNSUPPORTED;
+  isdf_problem p64 = *prob;
+  p64.prec = ISDF_FP64;   // FP64 storage in both adjoint modes
   Problem P;
-  isdf_status s = check_problem(nullptr, prob, P);
+  isdf_status s = check_problem(nullptr, &p64, P);
   if (s != ISDF_OK) return s;
-  if (P.prec != P64) return ISDF_E_UNSUPPORTED;
   if (n_mu < 1 || ng < 1) return ISDF_E_ARG;
   P.nmu = n_mu;
   P.ng = ng;
   P.ngg = P.full_gram ? (int)P.nr : ng;
   P.nomega = 0;
+  P.zrows = grad_chunk(P);
   const int kx = std::min(P.ngg, P.n0), ky = std::min(P.ngg, P.n1), kz = std::min(P.ngg, P.n2);
   const int nd = (int)std::min<long>(P.ngg, (long)P.n0 * P.n1);
   *bytes = grad_layout(P, make_layout(P, kx, ky, kz, nd), kx, nd).total;
@@ -2163,8 +2457,17 @@ isdf_status isdf_eps_inv_grad(isdf_handle h, const isdf_problem* prob, const voi
   Uploader upl;
   DftIndex ix;
   std::vector<int> idxbuf;
-  TRY(setup_common(R, h, prob, psi, mu_idx, n_mu, miller, ng, energies, 0, workspace, ws_bytes, upl, ix, idxbuf));
-  if (R.P.prec != P64) return fail(h, ISDF_E_UNSUPPORTED, "the adjoint runs in FP64 (prec = ISDF_FP64)");
+  if (!prob) return fail(h, ISDF_E_ARG, "problem is NULL");
+  if (prob->prec == ISDF_BF16X3)
+    return fail(h, ISDF_E_UNSUPPORTED, "the adjoint runs in FP64 or with FP32 grid contractions (ISDF_FP64, ISDF_FP32)");
+  // the workspace holds FP64 data in both modes; ISDF_FP32 only changes the compute
+  // precision of the contractions over the grid
+  isdf_problem p64 = *prob;
+  const bool mixed = prob->prec == ISDF_FP32;
+  p64.prec = ISDF_FP64;
+  TRY(setup_common(R, h, &p64, psi, mu_idx, n_mu, miller, ng, energies, 0, workspace, ws_bytes, upl, ix, idxbuf,
+                   true));
+  R.grad_big = mixed ? P32 : P64;
   if (R.P.core_method != 0) return fail(h, ISDF_E_UNSUPPORTED, "the adjoint differentiates the direct core (core_method = 0)");
   const GradLayout G = grad_layout(R.P, R.L, R.L.kx, R.L.nd);
   TRY(check_ws(h, workspace, ws_bytes, G.total));

@@ -45,12 +45,15 @@ size_t gemm32_tail_bytes(int wg_per_cu);
 bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, long ldb);
 
 // ----- orbital pair Gram (step 1):  out[mu][c] = conj(Pv(mu, c)) * Qc(mu, c)
-//   Pv(mu, c) = sum_{i < nv} conj(pm[i][mu]) b[i][c],  Qc(mu, c) = sum_{nv <= j < ns} conj(pm[j][mu]) b[j][c]
-//   pm: [ns][ldp] (orbitals at the points), b: [ns][ldb] (orbitals on the grid, complex128).
+//   Pv(mu, c) = sum_{i < nv} conj(pm[i][mu]) b[i][c],  Qc(mu, c) = sum_{b0 <= j < b0 + ns - nv} conj(pm[j][mu]) b[j][c]
+//   pm: [states][ldp] (orbitals at the points), b: [states][ldb] (orbitals on the grid, complex128).
+//   The second state range starts at b0 (default nv: the empty states after the occupied
+//   ones); the ranges may overlap (the self-energy pair sets: occupied x all, all x all).
 //   P64: pm complex128, in32 = out32 = false, out complex128.  P32: pm complex64 (in32 = true),
 //   b rounded to FP32 as it is staged, out complex64 (out32 = true).
 hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
-                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st, int wg_per_cu = 1);
+                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st, int wg_per_cu = 1,
+                 int b0 = -1);
 
 // ----- core (step 2): partial sums over occupied ranges of
 //   M(mu, nu) = sum_{i, j} conj(a_i(mu)) b_j(mu) w_ij a_i(nu) conj(b_j(nu))
@@ -130,6 +133,14 @@ hipError_t bf3_split_points(const void* pm, long ld, int nmu, int nv, int nc, vo
 // out[mu][r] = conj(Pv) Qc (complex64, row stride ldo) from the split planes
 hipError_t zpair_bf3(long nr, int nmu, int nv, int nc, const void* rows, const void* points, void* out, long ldo,
                      hipStream_t st);
+// BF16x3 core (core_bf3.hip): A planes of the empty states at the points (split once per
+// build into planes of core_bf3_plane_bytes), then partial sums as core_partial.  Needs
+// nmu % 128 == 0 and nc % 16 == 0.
+bool core_bf3_fits(int nmu, int nc);
+size_t core_bf3_plane_bytes(int nmu, int nc);
+hipError_t core_bf3_split(int nmu, int nv, int nc, const void* pm, void* planes, hipStream_t st);
+hipError_t core_bf3_partial(int nmu, int nv, int nc, const void* pm, const void* planes, const double* w,
+                            void* part, int nsplit, hipStream_t st, int batch = 1);
 hipError_t axpby(const void* A, double a, const void* B, double b, void* C, long count, hipStream_t st);  // z64
 
 // ----- contour-integral core (cauchy.hip), complex128 storage
@@ -149,7 +160,8 @@ hipError_t adj_herm_plus(const void* g, void* h, int n, hipStream_t st);        
 hipError_t adj_gather_cols(const void* src, long ld, const int* idx, int nv, int rows, void* out, hipStream_t st);
 // adjoint of the pruned DFT: gz[mu][r] = sum_g conj(F(g, r)) sqrtv[g] gbar[g][mu]
 struct AdjDft {
-  int n0 = 0, n1 = 0, n2 = 0, nmu = 0, kx = 0, nd = 0;
+  int n0 = 0, n1 = 0, n2 = 0, nmu = 0, kx = 0, nd = 0;   // nmu: columns of gbar transformed
+  long ldg = 0;                                          // gbar: [g][ldg] complex128
   const void* twx = nullptr; const void* twy = nullptr; const void* twz = nullptr;   // forward tables
   const double* sqrtv = nullptr;
   const int* gd_off = nullptr; const int* gd_list = nullptr;   // plane waves grouped by (x, y) pair
@@ -164,6 +176,10 @@ hipError_t adj_core_grads(const void* ub, const void* pm, const double* w, int n
 hipError_t adj_energy_grad(const void* q, const double* e, int nv, int nc, double omega, double* ge, hipStream_t st);
 hipError_t adj_loss(const void* w, int ng, long ldw, const void* p, int n, double* out, hipStream_t st);
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);  // kernel clear, bytes % 4 == 0
+// ----- self-energy reductions (sigma.hip), complex128
+hipError_t mul_z(const void* a, const void* b, void* c, long count, hipStream_t st);   // c = a (.) b
+// out[n] = coef Re sum_mu conj(pm[n][mu]) e[mu][n], n < ns (pm: [ns][nmu], e: [nmu][ns])
+hipError_t sigma_diag(const void* pm, const void* e, int nmu, int ns, double coef, double* out, hipStream_t st);
 hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStream_t st);  // z64
 // out[0] += ||a||_F^2 over count complex128, deterministic (single pass of block partials)
 hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st);

@@ -57,7 +57,7 @@ __device__ __forceinline__ void kloop_xx(cx<T>* smem, const cx<S>* A, long lda, 
 }
 
 template <typename T, typename S, typename SO, class TL>
-__global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int ns, const cx<S>* pm,
+__global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int ns, int b0, const cx<S>* pm,
                                                        long ldp, const cx<S>* b, long ldb, SO* out,
                                                        long ldo, int ntm, int total) {
   __shared__ cx<T> smem[2 * (TL::AS + TL::BS)];
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int
   zero_acc<TL>(accp);
   zero_acc<TL>(accq);
   kloop_xx<T, S, TL>(smem, pm, ldp, b, ldb, m0, n0, M, N, nv, (T)-1, (T)1, accp, tid, wm0, wn0, lane);
-  kloop_xx<T, S, TL>(smem, pm + (long)nv * ldp, ldp, b + (long)nv * ldb, ldb, m0, n0, M, N, ns - nv,
+  kloop_xx<T, S, TL>(smem, pm + (long)b0 * ldp, ldp, b + (long)b0 * ldb, ldb, m0, n0, M, N, ns - nv,
                      (T)-1, (T)1, accq, tid, wm0, wn0, lane);
 
   const int rc = lane & 15, part = rc & 1;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int
 // empty ones into Q in one pipeline.
 // ----------------------------------------------------------------------------
 // Generic K loop (any tile edge): clamped loads, masked LDS stores.
-__device__ __forceinline__ void zl_loop_generic(float* smem, int M, int N, int nv, int ns, const c32* pm,
+__device__ __forceinline__ void zl_loop_generic(float* smem, int M, int N, int nv, int ns, int b0, const c32* pm,
                                                 long ldp, const z64* b, long ldb, int m0, int n0,
                                                 f4 (&accp)[ZL::FM][ZL::FN], f4 (&accq)[ZL::FM][ZL::FN],
                                                 int tid, int wm0, int wn0, int lane) {
@@ -106,7 +106,7 @@ __device__ __forceinline__ void zl_loop_generic(float* smem, int M, int N, int n
   const int nt = tp + tq;
   auto kbase = [&](int t, const c32*& pa, const z64*& pb, int& k0, int& K) {
     if (t < tp) { pa = pm; pb = b; k0 = t * ZL::BK; K = nv; }
-    else { pa = pm + (long)nv * ldp; pb = b + (long)nv * ldb; k0 = (t - tp) * ZL::BK; K = ns - nv; }
+    else { pa = pm + (long)b0 * ldp; pb = b + (long)b0 * ldb; k0 = (t - tp) * ZL::BK; K = ns - nv; }
   };
   Stager<float, float, ZL::BM, ZL::BK, ZL::NT, true> sa;
   Stager<float, double, ZL::BN, ZL::BK, ZL::NT, true> sb;   // orbitals rounded to FP32 at staging
@@ -166,6 +166,8 @@ __device__ __forceinline__ void zl_epilogue(float* out, long ldo, int M, int N, 
 struct ZFetchB64 {
   uint32_t aoff0, aoff1, boff;
   int ax, ak, bx, bk;
+  int tsplit;    // first K tile of the second state range
+  long shift;    // rows from K tile tsplit's position to the second range's first state
   f4 ra0, ra1;
   d4 rb;
   __device__ __forceinline__ void init(int tid, long ldp, long ldb) {
@@ -175,7 +177,7 @@ struct ZFetchB64 {
     boff = (uint32_t)((bk * ldb + bx) * 16);
   }
   __device__ __forceinline__ void fetch(const c32* pm, long ldp, const z64* b, long ldb, int m0, int n0, int t) {
-    const long kr = (long)t * ZL::BK;
+    const long kr = (long)t * ZL::BK + (t >= tsplit ? shift : 0);
     const char* pa = reinterpret_cast<const char*>(pm + kr * ldp + m0);
     const char* pb = reinterpret_cast<const char*>(b + kr * ldb + n0);
     ra0 = *reinterpret_cast<const f4*>(pa + aoff0);
@@ -205,7 +207,7 @@ struct ZFetchB64 {
 // retires in issue order.
 template <bool EVEN>
 __global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(3)))
-void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long ldb, float* out, long ldo,
+void zpair32_kernel(int nv, int ns, int b0, const c32* pm, long ldp, const z64* b, long ldb, float* out, long ldo,
                     int nti, int total) {
   __shared__ float smem[2 * (ZL::AS + ZL::BS)];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -217,6 +219,8 @@ void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long 
   ZFetchB64 zf;
   ZFrag frag[2];
   zf.init(tid, ldp, ldb);
+  zf.tsplit = tp;
+  zf.shift = (long)b0 - nv;
   if (lo + j < hi) {
     zf.fetch(pm, ldp, b, ldb, ((lo + j) % nti) * ZL::BM, ((lo + j) / nti) * ZL::BN, 0);
     if (EVEN) {   // every range then starts staged
@@ -256,7 +260,7 @@ void zpair32_kernel(int nv, int ns, const c32* pm, long ldp, const z64* b, long 
 // Any tiles (edges, or operands that do not allow the 16-byte path): one
 // workgroup per tile from a list given as (first tile, count) of a column-major
 // walk over the ntm x ntn tiles, or the edge strips.
-__global__ __launch_bounds__(ZL::NT) void zpair32_edge_kernel(int M, int N, int nv, int ns, const c32* pm,
+__global__ __launch_bounds__(ZL::NT) void zpair32_edge_kernel(int M, int N, int nv, int ns, int b0, const c32* pm,
                                                               long ldp, const z64* b, long ldb, float* out,
                                                               long ldo, int ntm, int ntn, int nti, int ntj,
                                                               int all) {
@@ -280,11 +284,11 @@ __global__ __launch_bounds__(ZL::NT) void zpair32_edge_kernel(int M, int N, int 
   for (int fm = 0; fm < ZL::FM; ++fm)
 #pragma unroll
     for (int fn = 0; fn < ZL::FN; ++fn) accp[fm][fn] = accq[fm][fn] = f4{0.f, 0.f, 0.f, 0.f};
-  zl_loop_generic(smem, M, N, nv, ns, pm, ldp, b, ldb, m0, n0, accp, accq, tid, wm0, wn0, lane);
+  zl_loop_generic(smem, M, N, nv, ns, b0, pm, ldp, b, ldb, m0, n0, accp, accq, tid, wm0, wn0, lane);
   zl_epilogue(out, ldo, M, N, m0, n0, accp, accq, wm0, wn0, lane);
 }
 
-static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
+static hipError_t zpair32_launch(int M, int N, int nv, int ns, int b0, const void* pm, long ldp, const void* b,
                                  long ldb, void* out, long ldo, hipStream_t st, int wg_per_cu) {
   const int ntm = (int)cdiv(M, ZL::BM), ntn = (int)cdiv(N, ZL::BN);
   if (ntm == 0 || ntn == 0) return hipSuccess;
@@ -301,10 +305,10 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, l
     const int g = std::max(8, std::min(8 * ((wpc * cu_count() + 7) / 8), 8 * (int)cdiv(interior, 8)));
     const int tp = nv / ZL::BK, tq = (ns - nv) / ZL::BK;
     if (tp >= 2 && tp % 2 == 0 && tq >= 2 && tq % 2 == 0)
-      hipLaunchKernelGGL(zpair32_kernel<true>, dim3(g), dim3(ZL::NT), 0, st, nv, ns, (const c32*)pm, ldp,
+      hipLaunchKernelGGL(zpair32_kernel<true>, dim3(g), dim3(ZL::NT), 0, st, nv, ns, b0, (const c32*)pm, ldp,
                          (const z64*)b, ldb, (float*)out, ldo, nti, interior);
     else
-      hipLaunchKernelGGL(zpair32_kernel<false>, dim3(g), dim3(ZL::NT), 0, st, nv, ns, (const c32*)pm, ldp,
+      hipLaunchKernelGGL(zpair32_kernel<false>, dim3(g), dim3(ZL::NT), 0, st, nv, ns, b0, (const c32*)pm, ldp,
                          (const z64*)b, ldb, (float*)out, ldo, nti, interior);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -312,7 +316,7 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, l
   const int all = interior == 0 ? 1 : 0;
   const int nedge = all ? ntm * ntn : (ntj < ntn ? ntm : 0) + (nti < ntm ? ntj : 0);
   if (nedge == 0) return hipSuccess;
-  hipLaunchKernelGGL(zpair32_edge_kernel, dim3(nedge), dim3(ZL::NT), 0, st, M, N, nv, ns, (const c32*)pm,
+  hipLaunchKernelGGL(zpair32_edge_kernel, dim3(nedge), dim3(ZL::NT), 0, st, M, N, nv, ns, b0, (const c32*)pm,
                      ldp, (const z64*)b, ldb, (float*)out, ldo, ntm, ntn, nti, ntj, all);
   return hipGetLastError();
 }
@@ -320,26 +324,27 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, const void* pm, l
 typedef Tile<double, 64, 64, 16, 2, 2> TZ64;
 
 template <typename T, typename S, typename SO, class TL>
-static hipError_t zpair_launch(int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
+static hipError_t zpair_launch(int M, int N, int nv, int ns, int b0, const void* pm, long ldp, const void* b,
                                long ldb, void* out, long ldo, hipStream_t st) {
   const int ntm = (int)cdiv(M, TL::BM), ntn = (int)cdiv(N, TL::BN);
   const int total = ntm * ntn;
   if (total == 0) return hipSuccess;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
-  hipLaunchKernelGGL((zpair_kernel<T, S, SO, TL>), dim3(grid), dim3(TL::NT), 0, st, M, N, nv, ns,
+  hipLaunchKernelGGL((zpair_kernel<T, S, SO, TL>), dim3(grid), dim3(TL::NT), 0, st, M, N, nv, ns, b0,
                      (const cx<S>*)pm, ldp, (const cx<S>*)b, ldb, (SO*)out, ldo, ntm, total);
   return hipGetLastError();
 }
 
 hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, long ldp, const void* b,
-                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st, int wg_per_cu) {
+                 long ldb, bool in32, void* out, long ldo, bool out32, hipStream_t st, int wg_per_cu, int b0) {
+  if (b0 < 0) b0 = nv;   // the second state range follows the first
   if (compute == P64) {
     if (out32 || in32) return hipErrorInvalidValue;
-    return zpair_launch<double, double, double, TZ64>(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st);
+    return zpair_launch<double, double, double, TZ64>(M, N, nv, ns, b0, pm, ldp, b, ldb, out, ldo, st);
   }
   // single precision: complex64 points, complex128 orbitals (rounded as staged), complex64 output
   if (!in32 || !out32) return hipErrorInvalidValue;
-  return zpair32_launch(M, N, nv, ns, pm, ldp, b, ldb, out, ldo, st, wg_per_cu);
+  return zpair32_launch(M, N, nv, ns, b0, pm, ldp, b, ldb, out, ldo, st, wg_per_cu);
 }
 
 // ----------------------------------------------------------------------------

@@ -70,6 +70,9 @@ CONFIGS = {
     # Uneven systems batched with the 48^3 one (Nc = 4 Nv, N_mu = 10 Nv, NG = 32 Nv).
     **{f"batch{i}": dict(n=n, nv=nv, nc=4 * nv, nmu=10 * nv, ng=32 * nv, complex=True, seed=30 + i)
        for i, (n, nv) in enumerate(zip((24, 25, 27, 28, 30, 32, 36, 40), (16, 20, 24, 28, 32, 40, 44, 48)))},
+    # 32-aligned state counts on a 14^3 grid: the self-energy pair sets (occupied x all,
+    # all x all) run the single-precision pair kernel's interior path with even K ranges.
+    "sig_even": dict(n=14, nv=32, nc=32, nmu=192, ng=400, complex=True, seed=16),
     # Odd 33^3 grid above 32 points per axis (every grid vector in the Gram: two DFT x/y chunks).
     "wide": dict(n=33, nv=6, nc=18, nmu=60, ng=300, complex=True, seed=12),
     # Full rank: N_mu = Nv * Nc, where ISDF is exact.

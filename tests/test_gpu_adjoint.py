@@ -1,4 +1,4 @@
-"""GPU checks of the hand-written adjoint (isdf_eps_inv_grad, FP64) of
+"""GPU checks of the hand-written adjoint (isdf_eps_inv_grad, FP64 and mixed) of
 L = Re tr(W eps~^{-1}).
 
 Parity: loss and gradients against the oracle gradient (torch CPU autograd
@@ -47,6 +47,27 @@ def test_grad_matches_oracle(name, omega):
     assert e_l <= 1e-10, e_l
     assert e_e <= 1e-8, e_e
     assert e_p <= 1e-8, e_p
+
+
+@pytest.mark.parametrize("name,omega", [("tiny", 0.0), ("cfg0", 0.0), ("mid", 0.02)])
+def test_grad_mixed_matches_oracle(name, omega):
+    """The mixed backward (ISDF_FP32: the contractions over the grid in FP32 on MFMA,
+    everything else FP64) against the FP64 oracle gradient.  Bar 1e-5 relative
+    Frobenius: those contractions sum up to Nr terms of products rounded to FP32
+    (u = 6e-8, error growing like sqrt(Nr) u ~ 5e-6 at 20^3), and the result passes
+    through S^{-1} and the SMW core (cond <= 2e2) only in FP64."""
+    inp = synth.make_inputs(name)
+    w = synth.loss_weight(inp.ng)
+    print(f"[grad-mixed] case={name} omega={omega}", flush=True)
+    lref, ge_ref, gp_ref = oadj.loss_and_grad(inp, w, omega=omega)
+    lval, ge, gp = isdf.eps_inv_grad(dev(inp.psi_t), inp.energies, inp.mu_idx, inp.miller,
+                                     isdf.problem_for(inp, "fp32"), dev(w), omega)
+    ge, gp = ge.cpu().numpy(), gp.cpu().numpy()
+    gp_ref = gp_ref[:, inp.mu_idx]
+    e_l = abs(lval - lref) / max(1.0, abs(lref))
+    e_e, e_p = relf(ge, ge_ref), relf(gp, gp_ref)
+    print(f"  loss {lval:.6f} rel {e_l:.2e}  d/d eps rel-F {e_e:.2e}  d/d psi(r_mu) rel-F {e_p:.2e}", flush=True)
+    assert e_l <= 1e-5 and e_e <= 1e-5 and e_p <= 1e-5, (e_l, e_e, e_p)
 
 
 def _loss_gpu(inp, prob, psi_t, energies, w_dev, omega, ws):
@@ -126,3 +147,22 @@ def test_grad_full_size_64cubed():
     prob = isdf.problem_for(inp, "fp64")
     print("[grad-fd] case=cfg2", flush=True)
     _fd_check(inp, prob, 0.0, [(0, 0), (inp.nv + 5, 100)], [0, inp.nv], 1e-5)
+
+
+def test_grad_48cubed_chunks_and_mixed():
+    """At 48^3 (640 points, Nr = 110592) the adjoint forms its N_mu x Nr intermediates in
+    three chunks of points: central differences of the FP64 forward on sampled
+    entries, and the mixed backward within 1e-4 (relative Frobenius) of the FP64 one
+    (FP32 sums over 1e5 grid terms: sqrt(Nr) u ~ 2e-5)."""
+    inp = synth.make_inputs("cfg1")
+    prob = isdf.problem_for(inp, "fp64")
+    print("[grad-fd] case=cfg1", flush=True)
+    _fd_check(inp, prob, 0.0, [(0, 0), (inp.nv + 7, 300), (inp.nv + inp.nc - 1, inp.nmu - 1)], [0, inp.nv], 1e-6)
+    w = dev(synth.loss_weight(inp.ng))
+    psi = dev(inp.psi_t)
+    _, ge64, gp64 = isdf.eps_inv_grad(psi, inp.energies, inp.mu_idx, inp.miller, prob, w, 0.0)
+    _, ge32, gp32 = isdf.eps_inv_grad(psi, inp.energies, inp.mu_idx, inp.miller, isdf.problem_for(inp, "fp32"), w, 0.0)
+    e_e = relf(ge32.cpu().numpy(), ge64.cpu().numpy())
+    e_p = relf(gp32.cpu().numpy(), gp64.cpu().numpy())
+    print(f"  mixed vs FP64 adjoint: d/d eps rel-F {e_e:.2e}  d/d psi(r_mu) rel-F {e_p:.2e}", flush=True)
+    assert e_e <= 1e-4 and e_p <= 1e-4, (e_e, e_p)
