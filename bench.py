@@ -250,6 +250,8 @@ def summarize(args):
                      f"total {zf + zw:.4e} B per dispatch")
         lines.append(f"TRAFFIC_BYTES_PER_LAUNCH {zf + zw:.6e}")
         lines.append(f"SOURCE_SHA256 {zpair_source_hash()}")
+        if not args.factors:
+            args.factors = f"{f_fetch},{f_write}"
     if args.pmc_mfma or args.factors:
         summarize_counters(args, lines)
     print("\n".join(lines))
@@ -335,6 +337,33 @@ def adjoint_timing(isdf, torch, dev, inp, psi, reps, fwd_ms):
     del ws, w
     return {"ms_per_call": round(dt * 1e3, 2), "ratio_to_fp64_forward": round(dt * 1e3 / fwd_ms, 2),
             "loss": "Re tr(W eps~^-1), W seeded Hermitian", "gradients": "dL/d eps_n, dL/d psi_n(r_mu)"}
+
+
+def sigma_timing(isdf, torch, dev, inp, psi, reps=3):
+    """Wall time of the static COHSEX self-energy diagonals (isdf_sigma_cohsex: the eps~^-1
+    build plus the vn and nn pair sets, each call ending with a stream sync), FP32 and
+    FP64, and the FP32 diagonals' largest distance from the FP64 ones."""
+    import synth
+    mu_vn, mu_nn = synth.sigma_points(inp)
+    out = {"n_mu_vn": int(len(mu_vn)), "n_mu_nn": int(len(mu_nn))}
+    sig = {}
+    for prec in ("fp32", "fp64"):
+        prob = isdf.problem_for(inp, prec=prec)
+        nb = isdf.sigma_workspace_bytes(prob, inp.nmu, inp.ng, len(mu_vn), len(mu_nn))
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        res = isdf.sigma_cohsex(psi, inp.energies, inp.mu_idx, mu_vn, mu_nn, inp.miller, prob, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            res = isdf.sigma_cohsex(psi, inp.energies, inp.mu_idx, mu_vn, mu_nn, inp.miller, prob, workspace=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        sig[prec] = res.sigma.cpu().numpy()
+        out[prec] = {"ms_per_call": round(dt * 1e3, 2), "workspace_GiB": round(nb / 2 ** 30, 2)}
+        print(f"[bench] COHSEX sigma {inp.n}^3 {prec}: {dt * 1e3:.1f} ms per call", file=sys.stderr, flush=True)
+        del ws, res
+    out["fp32_max_abs_vs_fp64_over_max"] = float(np.abs(sig["fp32"] - sig["fp64"]).max() / np.abs(sig["fp64"]).max())
+    return out
 
 
 def solid_like(isdf, torch, dev, steps):
@@ -565,8 +594,11 @@ def main():
         batch = batch_systems(isdf, torch, dev, args.omegas, args.config)
 
     adj = None
+    cohsex = None
     if args.only is None:
         adj = adjoint_timing(isdf, torch, dev, inp, psi, 3, results["fp64"]["ms_per_step"])
+        if not args.no_solid:
+            cohsex = sigma_timing(isdf, torch, dev, inp, psi)
 
     solid = None
     if not args.no_solid and args.only is None:
@@ -663,6 +695,7 @@ def main():
         "systems_batch": batch,
         "solid_like_64cubed": solid,
         "adjoint_fp64": adj,
+        "cohsex_sigma": cohsex,
         "stress_lambda_max_10": stress,
         "roofline": roofline,
         "cpu_baseline": cpu,

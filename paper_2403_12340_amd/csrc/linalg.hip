@@ -1,7 +1,7 @@
 // FP64 dense algebra on the N_mu x N_mu core (row-major complex128, ld = n).
 //
 //   sweep_inverse  blocked Gauss-Jordan sweep of a Hermitian positive definite
-//                  matrix, A <- -A^{-1}, two kernels per 32-wide pivot block.
+//                  matrix, A <- -A^{-1}, one kernel per 32-wide pivot block.
 // A non-positive or non-finite pivot sets bit 0 of *status (ISDF_E_NOT_PD);
 // the pivots of a Hermitian positive definite matrix stay positive throughout.
 #include "internal.h"
@@ -21,216 +21,179 @@ __device__ __forceinline__ double drcp(double x) {
   return r;
 }
 
-// One 32-pivot step of the sweep is two kernels.  With pivot rows
-// k = [k0, k0 + kn), P = A_kk^{-1} and R = P A_k: (kn x n),
-//   A'_kj = R_j (j outside k),  A'_kk = -P,
-//   A'_ik = A_ik P = (P A_ki)^H = R_i^H (i outside k; A stays Hermitian),
-//   A'_ij = A_ij - A_ik P A_kj = A_ij - sum_t conj(A[k0 + t][i]) R[t][j].
-// sweep_panel_kernel writes the pivot rows and columns of A' (one workgroup per
-// 64-column block), sweep_update_kernel the rest.  Input and output are
-// different buffers, so no workgroup reads what another one writes.
+// One 32-pivot step of the sweep is one kernel.  With pivot rows k = [k0, k0 + kn)
+// and P = A_kk^{-1}:
+//   A'_kk = -P,  A'_kj = (P A_k)_j = R_j (j outside k),
+//   A'_ik = A_ik P (i outside k),  A'_ij = A_ij - A_ik R_j,
+// with A_ik = conj(A_ki) (A stays Hermitian).  The workgroup of a 64 x 32 tile forms
+// the R block of its own columns in LDS (P times the 32 x 32 pivot-row block), so no
+// separate panel launch is needed; the tile on the pivot columns multiplies by P
+// instead.  Input and output are different buffers, so no workgroup reads what
+// another one writes.  P comes from the previous step's last workgroup, which forms
+// the next pivot block of A' by the same formula and inverts it while the others
+// update (look-ahead); the first step's P comes from sweep_first_kernel.
 //
-// The pivot block is inverted by in-register Gauss-Jordan.  After pivots
-// 0..p-1 the working block B satisfies B[r][j] = s conj(B[j][r]) with s = -1
-// exactly when one of r, j is already a pivot, so row p alone carries what
-// every thread needs: the column value is B[r][p] = s conj(B[p][r]).  One row
-// broadcast and one barrier per pivot.
-typedef Tile<double, NB, 64, NB, 2, 2> TP;   // P (NB x NB, k-major in W) times a NB x 64 panel
-
-// Gauss-Jordan inversion of the NB x NB pivot block held as w[e] = B[gr + 8 e][gj]
-// by 256 threads (identity padding beyond the block); returns whether a pivot was
-// not positive and finite.  One row broadcast through rowb and one barrier per pivot.
+// The pivot block is inverted by in-register Gauss-Jordan, two pivots per barrier.
+// After the pivots before p0 the working block B satisfies B[r][j] = s conj(B[j][r])
+// with s = -1 exactly when one of r, j is already a pivot, so the two pivot rows
+// alone carry what every thread needs: the 2 x 2 pivot block D (inverted in closed
+// form), the pivot-row values at the thread's column, and the pivot-column values
+// at its rows B[r][p0 + a] = s conj(B[p0 + a][r]).
 constexpr int EW = NB * NB / 256;
-__device__ __forceinline__ bool pivot_gj(z64 (&w)[EW], z64 (*rowb)[NB], int gj, int gr) {
+
+// Gauss-Jordan inversion of the NB x NB block held as w[e] = B[gr + 8 e][gj] by 256
+// threads (identity padding beyond the block); rowb: LDS for two pivot rows, double
+// buffered.  Returns whether a pivot block was not positive definite.
+__device__ __forceinline__ bool pivot_gj2(z64 (&w)[EW], z64 (*rowb)[2][NB], int gj, int gr) {
   bool bad_any = false;
-#pragma unroll
-  for (int p = 0; p < NB; ++p) {
-    const int b = p & 1;
-    if (gr == (p & 7)) rowb[b][gj] = w[p >> 3];
-    __syncthreads();
-    const double piv = rowb[b][p].re;
-    const bool bad = !(piv > 0.0) || !isfinite(piv);
-    bad_any |= bad;
-    const double d = bad ? 1.0 : drcp(piv);
-    const z64 rv = rowb[b][gj];
-    const z64 rj = (gj == p) ? z64{d, 0.0} : z64{rv.re * d, rv.im * d};  // scaled pivot row here
+#pragma unroll 1
+  for (int q = 0; q < NB / 2; ++q) {
+    const int p0 = 2 * q, b = q & 1;
+    // the owners of rows p0 and p0 + 1 (thread rows gr + 8 e) broadcast them; every
+    // register index stays a constant (a run-time one would go through scratch)
 #pragma unroll
     for (int e = 0; e < EW; ++e) {
       const int r = gr + 8 * e;
-      const z64 pr = rowb[b][r];                 // B[p][r]
-      const double sg = (r < p) ? -1.0 : 1.0;    // B[r][p] = sg conj(B[p][r])
-      const z64 cv{sg * pr.re, -sg * pr.im};
-      const z64 x = cmul(cv, rj);
-      const double br = (gj == p) ? 0.0 : w[e].re, bi = (gj == p) ? 0.0 : w[e].im;
-      const bool own = (r == p);
-      w[e] = z64{own ? rj.re : br - x.re, own ? rj.im : bi - x.im};
+      if (r == p0) rowb[b][0][gj] = w[e];
+      if (r == p0 + 1) rowb[b][1][gj] = w[e];
+    }
+    __syncthreads();
+    const double a = rowb[b][0][p0].re, d = rowb[b][1][p0 + 1].re;
+    const z64 c = rowb[b][0][p0 + 1];
+    const double det = a * d - (c.re * c.re + c.im * c.im);
+    const bool bad = !(a > 0.0) || !(det > 0.0) || !isfinite(det);
+    bad_any |= bad;
+    const double idet = bad ? 0.0 : drcp(det);
+    // D^{-1} = [d, -c; -conj(c), a] / det
+    const z64 i00{d * idet, 0.0}, i11{a * idet, 0.0};
+    const z64 i01{-c.re * idet, -c.im * idet}, i10{-c.re * idet, c.im * idet};
+    const z64 v0 = rowb[b][0][gj], v1 = rowb[b][1][gj];
+    const z64 u0 = z64{i00.re * v0.re + (i01.re * v1.re - i01.im * v1.im), i00.re * v0.im + (i01.re * v1.im + i01.im * v1.re)};
+    const z64 u1 = z64{(i10.re * v0.re - i10.im * v0.im) + i11.re * v1.re, (i10.re * v0.im + i10.im * v0.re) + i11.re * v1.im};
+    const bool pc = gj == p0 || gj == p0 + 1;
+    const z64 dj0 = gj == p0 ? i00 : i01, dj1 = gj == p0 ? i10 : i11;   // D^{-1}[.][gj - p0]
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+      const int r = gr + 8 * e;
+      if (r == p0 || r == p0 + 1) {
+        w[e] = pc ? (r == p0 ? dj0 : dj1) : (r == p0 ? u0 : u1);
+        continue;
+      }
+      const double sg = r < p0 ? -1.0 : 1.0;
+      const z64 x0 = rowb[b][0][r], x1 = rowb[b][1][r];
+      const z64 ca0{sg * x0.re, -sg * x0.im}, ca1{sg * x1.re, -sg * x1.im};   // B[r][p0], B[r][p0 + 1]
+      const z64 y0 = pc ? dj0 : u0, y1 = pc ? dj1 : u1;
+      const z64 t = z64{ca0.re * y0.re - ca0.im * y0.im + ca1.re * y1.re - ca1.im * y1.im,
+                        ca0.re * y0.im + ca0.im * y0.re + ca1.re * y1.im + ca1.im * y1.re};
+      w[e] = pc ? z64{-t.re, -t.im} : z64{w[e].re - t.re, w[e].im - t.im};
     }
   }
   return bad_any;
 }
 
-// pin: P of this step (W layout, P[t][u] at pin[u NB + t]) when the previous
-// update launch computed it, else null (the panel inverts the block itself)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_panel_kernel(int n, const z64* __restrict__ ain,
-                                                          z64* __restrict__ aout, int k0, int kn,
-                                                          const z64* __restrict__ pin, int* status) {
+typedef Tile<double, 32, 32, 32, 2, 2> TR;   // R = P A_kj: 32 x 32 x 32
+typedef Tile<double, 64, 32, 32, 2, 2> TU;   // the tile update: 64 x 32, K = the 32 pivots
+constexpr int LP = NB + 1;                   // row stride of the 32 x 32 LDS blocks
+
+// P of the first pivot block, per batch item (pout[u NB + t] = P[t][u])
+__global__ __launch_bounds__(256) void sweep_first_kernel(int n, const z64* __restrict__ ain, z64* __restrict__ pout,
+                                                          int kn, int* status) {
+  __shared__ z64 rowb[2][2][NB];
+  ain += (long)blockIdx.y * n * n;
+  pout += (long)blockIdx.y * NB * NB;
+  const int tid = threadIdx.x, gj = tid % NB, gr = tid / NB;
+  z64 w[EW];
+#pragma unroll
+  for (int e = 0; e < EW; ++e) {
+    const int r = gr + 8 * e;
+    const bool ok = r < kn && gj < kn;
+    const z64 v = ain[ok ? (long)r * n + gj : 0];
+    w[e] = ok ? v : z64{r == gj ? 1.0 : 0.0, 0.0};
+  }
+  const bool bad = pivot_gj2(w, rowb, gj, gr);
+  if (bad && tid == 0) atomicOr(status, 1);
+#pragma unroll
+  for (int e = 0; e < EW; ++e) pout[gj * NB + gr + 8 * e] = w[e];
+}
+
+// R = P K in LDS: Ps[s][t] = P[t][s] (k-major A operand), Ks[s][j] = A[k0 + s][c0 + j];
+// R[t][j] to Rs (stride LP)
+__device__ __forceinline__ void form_r(const z64* Ps, const z64* Ks, z64* Rs, int lane, int wave) {
+  const int wm0 = (wave % TR::WGM) * TR::WTM, wn0 = (wave / TR::WGM) * TR::WTN;
+  const int rc = lane & 15, part = rc & 1;
+  TR::acc_t acc[TR::FM][TR::FN];
+  zero_acc<TR>(acc);
+  tile_mma<double, TR>(Ps, Ks, acc, wm0, wn0, lane);
+  double* Rr = reinterpret_cast<double*>(Rs);
+#pragma unroll
+  for (int fm = 0; fm < TR::FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < TR::FN; ++fn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int t = wm0 + fm * 16 + Mfma<double>::row(lane, v);
+        const int j = wn0 + fn * 8 + (rc >> 1);
+        Rr[(t * LP + j) * 2 + part] = acc[fm][fn][v];
+      }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_step_kernel(
+    int n, const z64* __restrict__ ain, z64* __restrict__ aout, int k0, int kn, const z64* __restrict__ pin,
+    z64* __restrict__ pout, int k1, int kn1, int ntm, int total, int* status) {
   // The sweep steps are latency-bound and run beside the pair kernel's waves: their
   // waves take issue priority on the SIMDs they share.
   __builtin_amdgcn_s_setprio(3);
+  __shared__ z64 L0[2 * NB * LP];   // Ps + Ks, later the update's A operand [t][i] (32 x 65)
+  __shared__ z64 Rs[NB * LP];       // R [t][j], or P [t][u] on the pivot columns
+  static_assert(TU::AS <= 2 * NB * LP && TU::BS <= NB * LP, "update operands fit the LDS blocks");
+  z64* Ps = L0;
+  z64* Ks = L0 + NB * LP;
   ain += (long)blockIdx.y * n * n;   // batch item
   aout += (long)blockIdx.y * n * n;
-  __shared__ z64 W[NB][NB + 1];      // W[u][t] = P[t][u]: the k-major A operand of P (.)
-  __shared__ z64 rowb[2][NB];        // pivot row broadcast, double-buffered
-  __shared__ z64 Bs[NB * (64 + 1)];  // pivot rows at this block's columns, then R
-  const int c0 = blockIdx.x * 64;
+  pin += (long)blockIdx.y * NB * NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // pivot block first: Gauss-Jordan waits only for these loads.
-  // Thread owns column gj of rows gr + 8 e (identity padding beyond kn).
-  const int gj = tid % NB, gr = tid / NB;
-  if (pin) pin += (long)blockIdx.y * NB * NB;
-  z64 w[EW];
-  if (!pin) {
-#pragma unroll
-    for (int e = 0; e < EW; ++e) {
-      const int r = gr + 8 * e;
-      const bool ok = r < kn && gj < kn;
-      const z64 v = ain[ok ? (long)(k0 + r) * n + k0 + gj : 0];
-      w[e] = ok ? v : z64{r == gj ? 1.0 : 0.0, 0.0};
-    }
-  }
-  // raw pivot rows at this block's columns, kept in registers until the inversion is done
-  constexpr int EB = NB * 64 / 256;
-  z64 braw[EB];
-#pragma unroll
-  for (int e = 0; e < EB; ++e) {
-    const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
-    const bool ok = t < kn && c0 + c < n;
-    braw[e] = ain[ok ? (long)(k0 + t) * n + c0 + c : 0];
-  }
-  bool bad_any = false;
-  if (pin) {
-    // P precomputed by the previous step's update launch
-#pragma unroll
-    for (int e = 0; e < EW; ++e) w[e] = pin[gj * NB + gr + 8 * e];
-  } else {
-    bad_any = pivot_gj(w, rowb, gj, gr);
-  }
-  if (bad_any && tid == 0 && blockIdx.x == 0) atomicOr(status, 1);
-#pragma unroll
-  for (int e = 0; e < EW; ++e) W[gj][gr + 8 * e] = w[e];
-#pragma unroll
-  for (int e = 0; e < EB; ++e) {
-    const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
-    const bool ok = t < kn && c0 + c < n;
-    Bs[t * (64 + 1) + c] = ok ? braw[e] : z64{0.0, 0.0};
-  }
-  __syncthreads();
-  // R = P A_k(:, block columns) with MFMA
-  const int pm0 = (wave % TP::WGM) * TP::WTM, pn0 = (wave / TP::WGM) * TP::WTN;
   const int rc = lane & 15, part = rc & 1;
-  TP::acc_t racc[TP::FM][TP::FN];
-  zero_acc<TP>(racc);
-  tile_mma<double, TP>(&W[0][0], Bs, racc, pm0, pn0, lane);
-  __syncthreads();  // every wave is done reading the raw panel
-  double* Bsr = reinterpret_cast<double*>(Bs);
-#pragma unroll
-  for (int fn = 0; fn < TP::FN; ++fn)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int t = pm0 + Mfma<double>::row(lane, v);
-      const int c = pn0 + fn * 8 + (rc >> 1);
-      const int gc = c0 + c;
-      const bool piv_col = gc >= k0 && gc < k0 + kn;
-      const z64 pv = W[(gc - k0) & (NB - 1)][t];  // P[t][gc - k0]
-      Bsr[(t * (64 + 1) + c) * 2 + part] = piv_col ? -(part ? pv.im : pv.re) : racc[0][fn][v];
-    }
-  __syncthreads();
-  // pivot rows: A'[k0 + t][c0 + c] (coalesced along c)
-#pragma unroll
-  for (int e = 0; e < EB; ++e) {
-    const int idx = tid + 256 * e, t = idx >> 6, c = idx & 63;
-    if (t < kn && c0 + c < n) aout[(long)(k0 + t) * n + c0 + c] = Bs[t * (64 + 1) + c];
-  }
-  // pivot columns: A'[i][k0 + t] = conj(R[t][i]) for rows i of this block outside k (coalesced along t)
-#pragma unroll
-  for (int e = 0; e < EB; ++e) {
-    const int idx = tid + 256 * e, t = idx & (NB - 1), c = idx / NB;
-    const int i = c0 + c;
-    if (t < kn && i < n && !(i >= k0 && i < k0 + kn)) aout[(long)i * n + k0 + t] = cconj(Bs[t * (64 + 1) + c]);
-  }
-}
-
-// Rank-kn update of every element outside the pivot rows and columns.
-typedef Tile<double, 64, 32, 16, 2, 2> TU;
-
-// With pout set, one more workgroup (the last) looks ahead: it forms the next
-// pivot block k1 of A' (kn1 wide) from the same formula, inverts it by
-// Gauss-Jordan while the others update, and stores P for the next panel launch,
-// so that the serial inversion is off the critical path of every step but the first.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_update_kernel(int n, const z64* __restrict__ ain,
-                                                           z64* __restrict__ aout, int k0, int kn,
-                                                           int ntm, int total, z64* __restrict__ pout,
-                                                           int k1, int kn1, int* status) {
-  __shared__ z64 As[TU::AS];  // [t][i] = conj(A[k0 + t][m0 + i])
-  __shared__ z64 Bs[TU::BS];  // [t][j] = R[t][n0 + j] (the pivot rows of A')
-  __builtin_amdgcn_s_setprio(3);   // issue priority beside the pair kernel, as in the panel
-  ain += (long)blockIdx.y * n * n;   // batch item
-  aout += (long)blockIdx.y * n * n;
   if (pout && blockIdx.x == gridDim.x - 1) {
+    // look-ahead: A'_{k1 k1} = A_{k1 k1} - conj(A_{k k1})^T R1, R1 = P A_{k k1}; then its inverse
     pout += (long)blockIdx.y * NB * NB;
-    const int tid = threadIdx.x, gj = tid % NB, gr = tid / NB;
-    const bool colok = gj < kn1;
-    // sum_t conj(A[k0 + t][k1 + r]) R[t][k1 + gj], t in halves of 16 staged in LDS:
-    // As[t][r] = A[k0 + t][k1 + r], Bs[t][u] = R[t][k1 + u] (stride 33; zero beyond the blocks)
-    static_assert(TU::AS >= 16 * 33 && TU::BS >= 16 * 33, "look-ahead staging fits the tile buffers");
-    z64 vold[EW];
+    const int gj = tid % NB, gr = tid / NB;
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+      const int idx = tid + 256 * e, s2 = idx / NB, t = idx % NB;
+      Ps[s2 * LP + t] = pin[idx];                                             // P[t][s2]
+      const bool ok = s2 < kn && t < kn1;
+      const z64 v = ain[ok ? (long)(k0 + s2) * n + k1 + t : 0];
+      Ks[s2 * LP + t] = ok ? v : z64{0.0, 0.0};                               // A[k0 + s2][k1 + t]
+    }
+    z64 old[EW];
 #pragma unroll
     for (int e = 0; e < EW; ++e) {
       const int r = gr + 8 * e;
-      vold[e] = ain[r < kn1 && colok ? (long)(k1 + r) * n + k1 + gj : 0];
+      old[e] = ain[r < kn1 && gj < kn1 ? (long)(k1 + r) * n + k1 + gj : 0];
     }
-    z64 acc[EW];
+    __syncthreads();
+    form_r(Ps, Ks, Rs, lane, wave);
+    __syncthreads();
+    // conj(A_{k k1})^T as the k-major A operand, in Ps's place
 #pragma unroll
-    for (int e = 0; e < EW; ++e) acc[e] = z64{0.0, 0.0};
-    for (int t0 = 0; t0 < kn; t0 += 16) {
-      z64 sa[2], sb[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {   // element (t, c) = (idx / 32, idx % 32), idx = tid + 256 h
-        const int idx = tid + 256 * h, t = idx >> 5, c = idx & 31;
-        const bool tok = t0 + t < kn && c < kn1;
-        sa[h] = ain[tok ? (long)(k0 + t0 + t) * n + k1 + c : 0];
-        sb[h] = aout[tok ? (long)(k0 + t0 + t) * n + k1 + c : 0];
-        if (!tok) sa[h] = sb[h] = z64{0.0, 0.0};
-      }
-      __syncthreads();   // the previous half has been read
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int idx = tid + 256 * h, t = idx >> 5, c = idx & 31;
-        As[t * 33 + c] = sa[h];
-        Bs[t * 33 + c] = sb[h];
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int t = 0; t < 16; ++t) {
-        const z64 rv = Bs[t * 33 + gj];
-#pragma unroll
-        for (int e = 0; e < EW; ++e) {
-          const z64 x = cmulc(As[t * 33 + gr + 8 * e], rv);
-          acc[e].re += x.re;
-          acc[e].im += x.im;
-        }
-      }
+    for (int e = 0; e < EW; ++e) {
+      const int idx = tid + 256 * e, s2 = idx / NB, t = idx % NB;
+      Ps[s2 * LP + t] = cconj(Ks[s2 * LP + t]);
     }
-    __syncthreads();   // As is reused as the pivot-row broadcast
+    __syncthreads();
+    // C = conj(A_{k k1})^T R1 into Ks's place (its raw values are no longer needed)
+    form_r(Ps, Rs, Ks, lane, wave);
+    __syncthreads();
     z64 w[EW];
 #pragma unroll
     for (int e = 0; e < EW; ++e) {
       const int r = gr + 8 * e;
-      const bool ok = r < kn1 && colok;
-      w[e] = ok ? z64{vold[e].re - acc[e].re, vold[e].im - acc[e].im} : z64{r == gj ? 1.0 : 0.0, 0.0};
+      const bool ok = r < kn1 && gj < kn1;
+      const z64 cv = Ks[r * LP + gj];
+      w[e] = ok ? z64{old[e].re - cv.re, old[e].im - cv.im} : z64{r == gj ? 1.0 : 0.0, 0.0};
     }
-    z64 (*rowb)[NB] = reinterpret_cast<z64 (*)[NB]>(As);
-    const bool bad = pivot_gj(w, rowb, gj, gr);
+    __syncthreads();   // Ks read before rowb reuses Rs
+    const bool bad = pivot_gj2(w, reinterpret_cast<z64 (*)[2][NB]>(Rs), gj, gr);
     if (bad && tid == 0) atomicOr(status, 1);
 #pragma unroll
     for (int e = 0; e < EW; ++e) pout[gj * NB + gr + 8 * e] = w[e];
@@ -240,13 +203,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
   if (id >= total) return;
   const int bm = id % ntm, bn = id / ntm;
   const int m0 = bm * TU::BM, n0 = bn * TU::BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool pcol = n0 == k0;   // the tile on the pivot columns (k0 is a multiple of 32)
   const int wm0 = (wave % TU::WGM) * TU::WTM, wn0 = (wave / TU::WGM) * TU::WTN;
-  const int rc = lane & 15, part = rc & 1;
+  // the update's A operand conj(A[k0 + t][m0 + i]), in flight while R is formed
   Stager<double, double, TU::BM, TU::BK, TU::NT, true> sa;
-  Stager<double, double, TU::BN, TU::BK, TU::NT, true> sb;
   sa.fetch(ain + (long)k0 * n, 1, n, m0, 0, n, kn, tid);
-  sb.fetch(aout + (long)k0 * n, 1, n, n0, 0, n, kn, tid);
+  if (pcol) {
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+      const int idx = tid + 256 * e, u = idx / NB, t = idx % NB;
+      Rs[t * LP + u] = pin[idx];                                              // P[t][u]
+    }
+  } else {
+    Stager<double, double, NB, NB, 256, true> sk;
+    sk.fetch(ain + (long)k0 * n, 1, n, n0, 0, n, kn, tid);
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+      const int idx = tid + 256 * e, s2 = idx / NB, t = idx % NB;
+      Ps[s2 * LP + t] = pin[idx];                                             // P[t][s2]
+    }
+    sk.store(Ks, LP, 1.0, tid);
+    __syncthreads();
+    form_r(Ps, Ks, Rs, lane, wave);
+  }
   const double* ainr = reinterpret_cast<const double*>(ain);
   double cold[TU::FM][TU::FN][4];
 #pragma unroll
@@ -261,19 +240,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
         const unsigned off = (row < n && col < n) ? ((unsigned)(row * n + col) * 2u + part) * 8u : 0u;
         cold[fm][fn][v] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(ainr) + off);
       }
+  __syncthreads();   // Ps / Ks read by form_r before the A operand overwrites them
+  sa.store(L0, TU::LDA, -1.0, tid);
+  __syncthreads();
   TU::acc_t acc[TU::FM][TU::FN];
   zero_acc<TU>(acc);
-  for (int kc = 0; kc < kn; kc += TU::BK) {
-    sa.store(As, TU::LDA, -1.0, tid);
-    sb.store(Bs, TU::LDB, 1.0, tid);
-    __syncthreads();
-    if (kc + TU::BK < kn) {
-      sa.fetch(ain + (long)k0 * n, 1, n, m0, kc + TU::BK, n, kn, tid);
-      sb.fetch(aout + (long)k0 * n, 1, n, n0, kc + TU::BK, n, kn, tid);
-    }
-    tile_mma<double, TU>(As, Bs, acc, wm0, wn0, lane);
-    __syncthreads();
-  }
+  tile_mma<double, TU>(L0, Rs, acc, wm0, wn0, lane);
+  const double* Rr = reinterpret_cast<const double*>(Rs);
   double* aoutr = reinterpret_cast<double*>(aout);
 #pragma unroll
   for (int fm = 0; fm < TU::FM; ++fm)
@@ -284,36 +257,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
         const int row = m0 + wm0 + fm * 16 + Mfma<double>::row(lane, v);
         const int col = n0 + wn0 + fn * 8 + (rc >> 1);
         if (row >= n || col >= n) continue;
-        if ((row >= k0 && row < k0 + kn) || (col >= k0 && col < k0 + kn)) continue;
-        aoutr[((long)row * n + col) * 2 + part] = cold[fm][fn][v] - acc[fm][fn][v];
+        const bool prow = row >= k0 && row < k0 + kn;
+        double val;
+        if (pcol) val = prow ? -Rr[((row - k0) * LP + (col - k0)) * 2 + part] : acc[fm][fn][v];   // -P, A_ik P
+        else val = prow ? Rr[((row - k0) * LP + (col - n0)) * 2 + part] : cold[fm][fn][v] - acc[fm][fn][v];
+        aoutr[((long)row * n + col) * 2 + part] = val;
       }
 }
 
-// ping-pong copy of the matrix, then the look-ahead pivot inverse
-size_t linalg_scratch_bytes(int n) { return ((size_t)n * n + NB * NB) * sizeof(z64); }
+// ping-pong copy of the matrix, then the two look-ahead pivot inverses (by step parity)
+size_t linalg_scratch_bytes(int n) { return ((size_t)n * n + 2 * NB * NB) * sizeof(z64); }
 
 hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch) {
   z64* bufs[2] = {(z64*)a, (z64*)scratch};
-  const int npb = (n + 63) / 64;                  // panel workgroups
+  z64* pbuf[2] = {(z64*)scratch + (long)batch * n * n, (z64*)scratch + (long)batch * n * n + (long)batch * NB * NB};
   const int ntm = (n + TU::BM - 1) / TU::BM, ntn = (n + TU::BN - 1) / TU::BN;
   const int total = ntm * ntn;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
-  z64* pbuf = (z64*)scratch + (long)batch * n * n;   // look-ahead P, one block per batch item
-  int cur = 0;
+  hipLaunchKernelGGL(sweep_first_kernel, dim3(1, batch), dim3(256), 0, st, n, (const z64*)a, pbuf[0], min(NB, n),
+                     status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int cur = 0, par = 0;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kn = min(NB, n - k0);
-    hipLaunchKernelGGL(sweep_panel_kernel, dim3(npb, batch), dim3(256), 0, st, n, (const z64*)bufs[cur],
-                       bufs[cur ^ 1], k0, kn, k0 > 0 ? (const z64*)pbuf : nullptr, status);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const int k1 = k0 + NB, kn1 = min(NB, n - k1);
     const bool ahead = k1 < n;
-    hipLaunchKernelGGL(sweep_update_kernel, dim3(grid + (ahead ? 1 : 0), batch), dim3(256), 0, st, n,
-                       (const z64*)bufs[cur], bufs[cur ^ 1], k0, kn, ntm, total, ahead ? pbuf : nullptr, k1, kn1,
-                       status);
+    hipLaunchKernelGGL(sweep_step_kernel, dim3(grid + (ahead ? 1 : 0), batch), dim3(256), 0, st, n,
+                       (const z64*)bufs[cur], bufs[cur ^ 1], k0, kn, (const z64*)pbuf[par],
+                       ahead ? pbuf[par ^ 1] : nullptr, k1, kn1, ntm, total, status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;
+    par ^= 1;
   }
   if (cur == 1) return convert_z(scratch, false, a, false, (long)n * n * batch, st);
   return hipSuccess;

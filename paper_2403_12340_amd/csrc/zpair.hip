@@ -323,6 +323,96 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, int b0, const voi
 
 typedef Tile<double, 64, 64, 16, 2, 2> TZ64;
 
+// FP64 pair kernel on the grid, persistent: one workgroup per slot walks its XCD's
+// contiguous share of the 64 x 64 tiles in point-fastest order (consecutive tiles
+// share the grid-orbital panel in that XCD's L2).  The occupied and the empty K
+// ranges run through one K loop with one running accumulator, whose occupied sum
+// moves to accp at the range boundary; the loop fetches the next K tile (or the
+// next tile's first one) into registers while the MFMAs of the current one run,
+// so no tile starts with an exposed load.  Needs no tile edges: M % 64 == 0,
+// N % 64 == 0 (the caller keeps zpair_kernel for anything else).
+typedef Tile<double, 64, 64, 16, 4, 2> TZ64P;   // 8 waves of 16 x 32 (the generic 4-wave tile needs 315 registers)
+
+__global__ __launch_bounds__(TZ64P::NT, 1) void zpair64_kernel(int nv, int ns, int b0, const z64* __restrict__ pm,
+                                                               long ldp, const z64* __restrict__ b, long ldb,
+                                                               z64* __restrict__ out, long ldo, int nti, int total) {
+  typedef TZ64P TL;
+  __shared__ z64 smem[2 * (TL::AS + TL::BS)];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave % TL::WGM) * TL::WTM, wn0 = (wave / TL::WGM) * TL::WTN;
+  const int xcd = blockIdx.x % 8, nper = gridDim.x / 8, j = blockIdx.x / 8;
+  const int per = (total + 7) / 8;
+  const int lo = xcd * per, hi = min(total, lo + per);
+  const int tp = (nv + TL::BK - 1) / TL::BK, tq = (ns - nv + TL::BK - 1) / TL::BK, nt = tp + tq;
+  const int K1 = ns - nv;
+  Stager<double, double, TL::BM, TL::BK, TL::NT, true> sa;
+  Stager<double, double, TL::BN, TL::BK, TL::NT, true> sb;
+  // K tile t of the tile at (m0, n0): the occupied range, then the second range from row b0
+  auto fetch = [&](int t, int m0, int n0) {
+    if (t < tp) {
+      sa.fetch(pm, 1, ldp, m0, t * TL::BK, 1 << 30, nv, tid);
+      sb.fetch(b, 1, ldb, n0, t * TL::BK, 1 << 30, nv, tid);
+    } else {
+      sa.fetch(pm + (long)b0 * ldp, 1, ldp, m0, (t - tp) * TL::BK, 1 << 30, K1, tid);
+      sb.fetch(b + (long)b0 * ldb, 1, ldb, n0, (t - tp) * TL::BK, 1 << 30, K1, tid);
+    }
+  };
+  auto stage = [&](int s) {
+    z64* buf = smem + s * (TL::AS + TL::BS);
+    sa.store(buf, TL::LDA, -1.0, tid);
+    sb.store(buf + TL::AS, TL::LDB, 1.0, tid);
+  };
+  int id = lo + j;
+  if (id < hi) {
+    fetch(0, (id % nti) * TL::BM, (id / nti) * TL::BN);
+    stage(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  const int rc = lane & 15, part = rc & 1;
+  for (; id < hi; id += nper) {
+    const int m0 = (id % nti) * TL::BM, n0 = (id / nti) * TL::BN;
+    const int nid = id + nper;
+    TL::acc_t acc[TL::FM][TL::FN], accp[TL::FM][TL::FN];
+    zero_acc<TL>(acc);
+    for (int t = 0; t < nt; ++t) {
+      const bool last = t + 1 == nt;
+      if (!last) fetch(t + 1, m0, n0);
+      else if (nid < hi) fetch(0, (nid % nti) * TL::BM, (nid / nti) * TL::BN);
+      const z64* buf = smem + cur * (TL::AS + TL::BS);
+      tile_mma<double, TL>(buf, buf + TL::AS, acc, wm0, wn0, lane);
+      if (t + 1 == tp) {
+#pragma unroll
+        for (int fm = 0; fm < TL::FM; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < TL::FN; ++fn) {
+            accp[fm][fn] = acc[fm][fn];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[fm][fn][v] = 0.0;
+          }
+      }
+      if (!last || nid < hi) stage(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
+    double* o = reinterpret_cast<double*>(out);
+#pragma unroll
+    for (int fm = 0; fm < TL::FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < TL::FN; ++fn)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double po = accp[fm][fn][v], qo = acc[fm][fn][v];
+          const double px = xor1(po), qx = xor1(qo);
+          // conj(P) Q: re = Pr Qr + Pi Qi, im = Pr Qi - Pi Qr
+          const double val = part == 0 ? (po * qo + px * qx) : (px * qo - po * qx);
+          const int row = m0 + wm0 + fm * 16 + Mfma<double>::row(lane, v);
+          const int col = n0 + wn0 + fn * 8 + (rc >> 1);
+          o[((long)row * ldo + col) * 2 + part] = val;
+        }
+  }
+}
+
 template <typename T, typename S, typename SO, class TL>
 static hipError_t zpair_launch(int M, int N, int nv, int ns, int b0, const void* pm, long ldp, const void* b,
                                long ldb, void* out, long ldo, hipStream_t st) {
@@ -340,6 +430,16 @@ hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, lon
   if (b0 < 0) b0 = nv;   // the second state range follows the first
   if (compute == P64) {
     if (out32 || in32) return hipErrorInvalidValue;
+    const int nti = M / TZ64P::BM, ntj = N / TZ64P::BN;
+    const long total = (long)nti * ntj;
+    if (M % TZ64P::BM == 0 && N % TZ64P::BN == 0 && nv >= 1 && ns > nv && total >= 8 * cu_count()) {
+      // persistent: one 8-wave workgroup per CU (207 registers: two waves per SIMD), a
+      // multiple of 8 (one share per XCD)
+      const int g = (int)std::min<long>(8L * ((cu_count() + 7) / 8), 8L * ((total + 7) / 8));
+      hipLaunchKernelGGL(zpair64_kernel, dim3(g), dim3(TZ64P::NT), 0, st, nv, ns, b0, (const z64*)pm, ldp,
+                         (const z64*)b, ldb, (z64*)out, ldo, nti, (int)total);
+      return hipGetLastError();
+    }
     return zpair_launch<double, double, double, TZ64>(M, N, nv, ns, b0, pm, ldp, b, ldb, out, ldo, st);
   }
   // single precision: complex64 points, complex128 orbitals (rounded as staged), complex64 output
