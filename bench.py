@@ -99,15 +99,18 @@ def _kernel_stats(db):
 def _phase_dispatches(db, steps, warmup):
     """Durations (ns) of the mixed path's pair-Gram launches on the benchmark workload,
     split by the benchmark's fixed order: autotune, W warm-up calls, then the K timed
-    calls, all before the FP64 path's first Z launch (the FP64 pair-Gram kernel over a
-    whole grid, >= 1e6 threads; its launches that form S on the points are far smaller)."""
+    calls, all before the FP64 path's first Z launch (the persistent FP64 pair-Gram
+    kernel, or the generic one over a whole grid, >= 1e6 threads; the generic kernel's
+    launches that form S on the points are far smaller)."""
     import sqlite3
     c = sqlite3.connect(db)
     rows = c.execute("select name, start, end, grid_x * grid_y * grid_z from kernels where "
-                     "name like '%zpair32_kernel%' or name like '%zpair_kernel<double%' "
+                     "name like '%zpair32_kernel%' or name like '%zpair_kernel<double%' or name like '%zpair64_kernel%' "
                      "order by start").fetchall()
     z32 = []
     for name, t0, t1, g in rows:
+        if "zpair64_kernel" in name:
+            break
         if "zpair_kernel<double" in name:
             if g >= 1_000_000:   # Z over a whole grid (S on the points launches far fewer threads)
                 break

@@ -326,6 +326,9 @@ isdf_status isdf_graph_destroy(isdf_graph graph);
  *                   before the pair kernel (default), 1 on the library's second stream
  *                   after it, beside the DFT and X^H X, 2 on the second stream right
  *                   after the pair kernel's operand pass, beside the pair kernel
+ *   side_prio       1 (default): the Gauss-Jordan sweep steps on the library's second
+ *                   stream raise their waves' issue priority over the kernels they share
+ *                   the CUs with; 0: they run at normal priority
  *   best_ms         output of isdf_plan_autotune: time of one call with the chosen knobs */
 typedef struct {
   int32_t dft_zb;
@@ -333,6 +336,7 @@ typedef struct {
   int32_t gram_split;
   int32_t wg_per_cu;
   int32_t core_stream;
+  int32_t side_prio;
   double best_ms;
 } isdf_tune;
 

@@ -519,6 +519,7 @@ struct Tune {
   int gram_split = 8;      // split-K cap of X^H X
   int wg_per_cu = 1;       // workgroups per CU of the persistent k-major kernels
   int core_stream = 0;     // first core: 0 main stream before Z, 1 side stream after Z, 2 side stream beside Z
+  int side_prio = 1;       // 1: the second stream's sweep steps raise their waves' issue priority
 };
 
 struct Run {
@@ -1085,7 +1086,7 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
   tm.mark();
   TRY(stage_z(R));
   HIPCHK(hipStreamWaitEvent(side, h->core0, 0));
-  HIPCHK(sweep_inverse(n, mb, at<char>(R.ws, L.lb), &R.sb->status, side, nw));            // M(omega)^{-1}
+  HIPCHK(sweep_inverse(n, mb, at<char>(R.ws, L.lb), &R.sb->status, side, nw, R.tune.side_prio != 0));  // M(omega)^{-1}
   {
     const void* sk = at<char>(R.ws, L.s);   // S^T = conj(S)
     void* qb = at<char>(R.ws, L.qb);
@@ -1169,7 +1170,8 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   // side_tail: M^{-1} and K = S M^{-1} S of frequency k on the side stream, once
   // its core M is in mbuf
   auto side_tail = [&](int k) -> isdf_status {
-    HIPCHK(sweep_inverse(R.P.nmu, mbuf[k & 1], at<char>(R.ws, R.L.lin2), &R.sb->status, side));  // M^{-1}
+    HIPCHK(sweep_inverse(R.P.nmu, mbuf[k & 1], at<char>(R.ws, R.L.lin2), &R.sb->status, side, 1,
+                         R.tune.side_prio != 0));                                                // M^{-1}
     TRY(stage_smis(R, mbuf[k & 1], at<char>(R.ws, R.L.q), side));                                 // S M^{-1} S
     HIPCHK(hipEventRecord(h->m_ready[k & 1], side));
     return ISDF_OK;
@@ -2120,7 +2122,7 @@ isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {
 static bool tune_valid(const isdf_tune* t) {
   return t && t->dft_zb >= 1 && t->dft_zb <= 64 && t->core_split_pct >= 25 && t->core_split_pct <= 200 &&
          t->gram_split >= 1 && t->gram_split <= 16 && t->wg_per_cu >= 1 && t->wg_per_cu <= 4 &&
-         t->core_stream >= 0 && t->core_stream <= 2;
+         t->core_stream >= 0 && t->core_stream <= 2 && t->side_prio >= 0 && t->side_prio <= 1;
 }
 
 isdf_status isdf_plan_set_tune(isdf_plan pl, const isdf_tune* t) {
@@ -2131,6 +2133,7 @@ isdf_status isdf_plan_set_tune(isdf_plan pl, const isdf_tune* t) {
   pl->tune.gram_split = t->gram_split;
   pl->tune.wg_per_cu = t->wg_per_cu;
   pl->tune.core_stream = t->core_stream;
+  pl->tune.side_prio = t->side_prio;
   return ISDF_OK;
 }
 
@@ -2141,6 +2144,7 @@ isdf_status isdf_plan_get_tune(isdf_plan pl, isdf_tune* t) {
   t->gram_split = pl->tune.gram_split;
   t->wg_per_cu = pl->tune.wg_per_cu;
   t->core_stream = pl->tune.core_stream;
+  t->side_prio = pl->tune.side_prio;
   t->best_ms = 0.0;
   return ISDF_OK;
 }
@@ -2170,6 +2174,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
   const int grams[] = {4, 8, 16};
   const int wpcs[] = {1, 2};
   const int cstreams[] = {0, 1, 2};
+  const int prios[] = {0, 1};
   auto sweep = [&](int Tune::*knob, const int* cands, int nc) -> isdf_status {
     const int keep = pl->tune.*knob;
     int arg = keep;
@@ -2188,6 +2193,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
   TRY(sweep(&Tune::gram_split, grams, 3));
   TRY(sweep(&Tune::wg_per_cu, wpcs, 2));
   TRY(sweep(&Tune::core_stream, cstreams, 3));
+  TRY(sweep(&Tune::side_prio, prios, 2));
   if (out) {
     TRY(isdf_plan_get_tune(pl, out));
     out->best_ms = best;

@@ -74,7 +74,8 @@ hipError_t core_reduce(Prec compute, int nmu, const void* part, int nsplit, doub
 
 // ----- small FP64 dense algebra, row-major n x n complex128, ld = n
 // In-place Hermitian positive definite sweep: A <- -A^{-1}.  scratch: linalg_scratch_bytes(n).
-hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch = 1);
+hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch = 1,
+                         bool prio = true);
 size_t linalg_scratch_bytes(int n);
 
 // ----- grid / plane-wave helpers

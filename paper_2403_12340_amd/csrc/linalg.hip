@@ -139,10 +139,10 @@ __device__ __forceinline__ void form_r(const z64* Ps, const z64* Ks, z64* Rs, in
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sweep_step_kernel(
     int n, const z64* __restrict__ ain, z64* __restrict__ aout, int k0, int kn, const z64* __restrict__ pin,
-    z64* __restrict__ pout, int k1, int kn1, int ntm, int total, int* status) {
-  // The sweep steps are latency-bound and run beside the pair kernel's waves: their
-  // waves take issue priority on the SIMDs they share.
-  __builtin_amdgcn_s_setprio(3);
+    z64* __restrict__ pout, int k1, int kn1, int ntm, int total, int* status, int prio) {
+  // The sweep steps are latency-bound and run beside the pair kernel's waves: with
+  // prio set, their waves take issue priority on the SIMDs they share.
+  if (prio) __builtin_amdgcn_s_setprio(3);
   __shared__ z64 L0[2 * NB * LP];   // Ps + Ks, later the update's A operand [t][i] (32 x 65)
   __shared__ z64 Rs[NB * LP];       // R [t][j], or P [t][u] on the pivot columns
   static_assert(TU::AS <= 2 * NB * LP && TU::BS <= NB * LP, "update operands fit the LDS blocks");
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
 // ping-pong copy of the matrix, then the two look-ahead pivot inverses (by step parity)
 size_t linalg_scratch_bytes(int n) { return ((size_t)n * n + 2 * NB * NB) * sizeof(z64); }
 
-hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch) {
+hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch, bool prio) {
   z64* bufs[2] = {(z64*)a, (z64*)scratch};
   z64* pbuf[2] = {(z64*)scratch + (long)batch * n * n, (z64*)scratch + (long)batch * n * n + (long)batch * NB * NB};
   const int ntm = (n + TU::BM - 1) / TU::BM, ntn = (n + TU::BN - 1) / TU::BN;
@@ -285,7 +285,7 @@ hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t
     const bool ahead = k1 < n;
     hipLaunchKernelGGL(sweep_step_kernel, dim3(grid + (ahead ? 1 : 0), batch), dim3(256), 0, st, n,
                        (const z64*)bufs[cur], bufs[cur ^ 1], k0, kn, (const z64*)pbuf[par],
-                       ahead ? pbuf[par ^ 1] : nullptr, k1, kn1, ntm, total, status);
+                       ahead ? pbuf[par ^ 1] : nullptr, k1, kn1, ntm, total, status, prio ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;

@@ -2,12 +2,15 @@
 function, and its host-side logic (plane-wave list, workspace sizing, argument
 validation) behaves as documented."""
 import ctypes
+import pathlib
 
 import numpy as np
 import pytest
 
 import paper_2403_12340_amd as isdf
 import synth
+
+ROOT = pathlib.Path(__file__).resolve().parent.parent
 
 
 def test_library_exports_every_declared_symbol():
@@ -159,3 +162,39 @@ def test_plan_table_bytes(cfg0):
     assert lib.isdf_plan_table_bytes(ctypes.byref(full), mu.ctypes.data_as(pi32), len(mu), mi.ctypes.data_as(pi32),
                                      len(mi), 0, ctypes.byref(big)) == 0
     assert big.value > out.value   # every grid vector in the Gram's list
+
+
+def _header_structs():
+    """Field (name, ctype, count) lists of every `typedef struct { ... } name;` in the header."""
+    import re
+    text = (ROOT / "include" / "isdf_smw.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    types = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
+    out = {}
+    for body, name in re.findall(r"typedef struct \{(.*?)\}\s*(\w+);", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            ty, names = decl.split(None, 1)
+            for nm in names.split(","):
+                m = re.fullmatch(r"\s*(\w+)(?:\[(\d+)\])?\s*", nm)
+                fields.append((m.group(1), types[ty], int(m.group(2) or 1)))
+        out[name] = fields
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("isdf_problem", "Problem"), ("isdf_report", "Report"),
+                                          ("isdf_tune", "Tune")])
+def test_binding_structs_match_header(cname, pyname):
+    """The ctypes structures of the binding have the header's fields, in order, with its types."""
+    from paper_2403_12340_amd import binding
+    want = _header_structs()[cname]
+    got = []
+    for nm, ty in getattr(binding, pyname)._fields_:
+        if hasattr(ty, "_length_"):
+            got.append((nm, ty._type_, ty._length_))
+        else:
+            got.append((nm, ty, 1))
+    assert got == want

@@ -682,7 +682,7 @@ def test_plan_autotune():
     t = plan.autotune(psi, e, out, ws, reps=2)
     assert t["dft_zb"] in (4, 6, 8, 12, 16, 24) and t["core_split_pct"] in (50, 100, 200)
     assert t["gram_split"] in (4, 8, 16) and t["wg_per_cu"] in (1, 2) and t["best_ms"] > 0
-    assert t["core_stream"] in (0, 1, 2)
+    assert t["core_stream"] in (0, 1, 2) and t["side_prio"] in (0, 1)
     assert plan.get_tune()["dft_zb"] == t["dft_zb"]
     plan.eps_inv_async(psi, e, out, ws)
     plan.sync()
@@ -697,23 +697,25 @@ def test_plan_autotune():
         plan.set_tune(dft_zb=0)
     with pytest.raises(isdf.IsdfError):
         plan.set_tune(core_stream=3)
+    with pytest.raises(isdf.IsdfError):
+        plan.set_tune(side_prio=2)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_core_stream_placement_is_bit_identical(prec):
-    """The first core on the second stream after Z (core_stream 1) or beside it (2)
-    runs the same kernels on the same data: the result equals the default placement
-    bit for bit."""
+    """The first core on the second stream after Z (core_stream 1) or beside it (2),
+    and the second stream's sweep at normal wave priority (side_prio 0), run the same
+    kernels on the same data: the result equals the default placement bit for bit."""
     inp, prob, plan = _plan_case("mid", prec)
     psi, e = dev(inp.psi_t), dev(inp.energies)
     ws = plan.new_workspace()
     outs = []
-    for cs in (0, 1, 2):
+    for cs, sp in ((0, 1), (1, 1), (2, 1), (0, 0), (2, 0)):
         outs.append(plan.new_output())
-        plan.set_tune(core_stream=cs)
+        plan.set_tune(core_stream=cs, side_prio=sp)
         plan.eps_inv_async(psi, e, outs[-1], ws)
         plan.sync()
-    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
