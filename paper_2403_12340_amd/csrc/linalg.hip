@@ -33,62 +33,87 @@ __device__ __forceinline__ double drcp(double x) {
 // the next pivot block of A' by the same formula and inverts it while the others
 // update (look-ahead); the first step's P comes from sweep_first_kernel.
 //
-// The pivot block is inverted by in-register Gauss-Jordan, two pivots per barrier.
-// After the pivots before p0 the working block B satisfies B[r][j] = s conj(B[j][r])
-// with s = -1 exactly when one of r, j is already a pivot, so the two pivot rows
-// alone carry what every thread needs: the 2 x 2 pivot block D (inverted in closed
-// form), the pivot-row values at the thread's column, and the pivot-column values
-// at its rows B[r][p0 + a] = s conj(B[p0 + a][r]).
-constexpr int EW = NB * NB / 256;
+// The pivot block is inverted by Gauss-Jordan, two pivots per barrier.  After the
+// pivots before p0 the working block B satisfies B[r][j] = s conj(B[j][r]) with
+// s = -1 exactly when one of r, j is already a pivot, so the two pivot rows alone
+// carry what every thread needs: the 2 x 2 pivot block D (inverted in closed form),
+// the pivot-row values at the thread's columns, and the pivot-column values at its
+// rows B[r][p0 + a] = s conj(B[p0 + a][r]).  One round is the rank-2 update
+//   B' = B~ - C Y,   C[r][a] = B[r][p0 + a] (pivot rows: C = -I),
+//   Y[a][j] = (D^{-1} (B[p0][j], B[p0 + 1][j]))_a (pivot columns: D^{-1}[a][j - p0]),
+// where B~ is B with its two pivot rows and columns cleared.  In the real block form
+// of the complex product this is exactly one 16x16x4 FP64 MFMA per 16-row tile: the
+// four k of the MFMA are (re, im) of the two pivots.
+//
+// Layout: 4 waves; wave w holds the real columns [16 w, 16 w + 16) of both 16-row
+// tiles as MFMA accumulators, acc[t][v] = real entry (16 t + 4 v + l / 16, 16 w + l % 16)
+// of lane l (complex column (16 w + l % 16) / 2, re or im by the column's parity).
+constexpr int GJ_THREADS = 256;
+constexpr int EW = NB * NB / GJ_THREADS;   // complex entries of a 32 x 32 block per thread
 
-// Gauss-Jordan inversion of the NB x NB block held as w[e] = B[gr + 8 e][gj] by 256
-// threads (identity padding beyond the block); rowb: LDS for two pivot rows, double
-// buffered.  Returns whether a pivot block was not positive definite.
-__device__ __forceinline__ bool pivot_gj2(z64 (&w)[EW], z64 (*rowb)[2][NB], int gj, int gr) {
+// Gauss-Jordan inversion of the NB x NB block in acc (identity padding beyond the
+// block); rowd: LDS for the two pivot rows as reals, double buffered.  Returns whether
+// a 2 x 2 pivot block was not positive definite (every thread returns the same).
+__device__ __forceinline__ bool pivot_gj(d4 (&acc)[2], double (*rowd)[2][2 * NB], int lane, int wave) {
+  const int kq = lane >> 4, i16 = lane & 15;
+  const int jr = 16 * wave + i16, j = jr >> 1, part = jr & 1;   // this lane's real / complex column
+  const int ka = kq >> 1, kp = kq & 1;                           // MFMA k = 2 a + p: pivot a, re / im
   bool bad_any = false;
-#pragma unroll 1
+#pragma unroll
   for (int q = 0; q < NB / 2; ++q) {
     const int p0 = 2 * q, b = q & 1;
-    // the owners of rows p0 and p0 + 1 (thread rows gr + 8 e) broadcast them; every
-    // register index stays a constant (a run-time one would go through scratch)
-#pragma unroll
-    for (int e = 0; e < EW; ++e) {
-      const int r = gr + 8 * e;
-      if (r == p0) rowb[b][0][gj] = w[e];
-      if (r == p0 + 1) rowb[b][1][gj] = w[e];
-    }
+    // rows p0, p0 + 1 to LDS: tile p / 16, register (p % 16) / 4, lanes with l / 16 = p % 4
+    if (kq == (p0 & 3)) rowd[b][0][jr] = acc[p0 >> 4][(p0 & 15) >> 2];
+    if (kq == ((p0 + 1) & 3)) rowd[b][1][jr] = acc[(p0 + 1) >> 4][((p0 + 1) & 15) >> 2];
     __syncthreads();
-    const double a = rowb[b][0][p0].re, d = rowb[b][1][p0 + 1].re;
-    const z64 c = rowb[b][0][p0 + 1];
-    const double det = a * d - (c.re * c.re + c.im * c.im);
+    const double a = rowd[b][0][2 * p0], d = rowd[b][1][2 * p0 + 2];
+    const double cre = rowd[b][0][2 * p0 + 2], cim = rowd[b][0][2 * p0 + 3];
+    const double v0r = rowd[b][0][2 * j], v0i = rowd[b][0][2 * j + 1];
+    const double v1r = rowd[b][1][2 * j], v1i = rowd[b][1][2 * j + 1];
+    double xa[2];   // component kp of B[p0 + ka][r], r = 16 t + l % 16
+#pragma unroll
+    for (int t = 0; t < 2; ++t) xa[t] = rowd[b][ka][2 * (16 * t + i16) + kp];
+    __builtin_amdgcn_sched_barrier(0);   // every read of the round in flight at once
+    const double det = a * d - (cre * cre + cim * cim);
     const bool bad = !(a > 0.0) || !(det > 0.0) || !isfinite(det);
     bad_any |= bad;
     const double idet = bad ? 0.0 : drcp(det);
-    // D^{-1} = [d, -c; -conj(c), a] / det
-    const z64 i00{d * idet, 0.0}, i11{a * idet, 0.0};
-    const z64 i01{-c.re * idet, -c.im * idet}, i10{-c.re * idet, c.im * idet};
-    const z64 v0 = rowb[b][0][gj], v1 = rowb[b][1][gj];
-    const z64 u0 = z64{i00.re * v0.re + (i01.re * v1.re - i01.im * v1.im), i00.re * v0.im + (i01.re * v1.im + i01.im * v1.re)};
-    const z64 u1 = z64{(i10.re * v0.re - i10.im * v0.im) + i11.re * v1.re, (i10.re * v0.im + i10.im * v0.re) + i11.re * v1.im};
-    const bool pc = gj == p0 || gj == p0 + 1;
-    const z64 dj0 = gj == p0 ? i00 : i01, dj1 = gj == p0 ? i10 : i11;   // D^{-1}[.][gj - p0]
+    // row ka of D^{-1} = [d, -c; -conj(c), a] / det
+    const double e0r = ka == 0 ? d * idet : -cre * idet, e0i = ka == 0 ? 0.0 : cim * idet;
+    const double e1r = ka == 0 ? -cre * idet : a * idet, e1i = ka == 0 ? -cim * idet : 0.0;
+    double yr = e0r * v0r - e0i * v0i + e1r * v1r - e1i * v1i;
+    double yi = e0r * v0i + e0i * v0r + e1r * v1i + e1i * v1r;
+    if (j == p0) { yr = e0r; yi = e0i; }
+    if (j == p0 + 1) { yr = e1r; yi = e1i; }
+    // B operand: entry (k = 2 ka + kp, real column jr) of the real block form of -Y
+    const double bop = part == 0 ? (kp == 0 ? -yr : yi) : (kp == 0 ? -yi : -yr);
+    const bool jpiv = j == p0 || j == p0 + 1;
 #pragma unroll
-    for (int e = 0; e < EW; ++e) {
-      const int r = gr + 8 * e;
-      if (r == p0 || r == p0 + 1) {
-        w[e] = pc ? (r == p0 ? dj0 : dj1) : (r == p0 ? u0 : u1);
-        continue;
-      }
+    for (int t = 0; t < 2; ++t) {
+      const int r = 16 * t + i16;
       const double sg = r < p0 ? -1.0 : 1.0;
-      const z64 x0 = rowb[b][0][r], x1 = rowb[b][1][r];
-      const z64 ca0{sg * x0.re, -sg * x0.im}, ca1{sg * x1.re, -sg * x1.im};   // B[r][p0], B[r][p0 + 1]
-      const z64 y0 = pc ? dj0 : u0, y1 = pc ? dj1 : u1;
-      const z64 t = z64{ca0.re * y0.re - ca0.im * y0.im + ca1.re * y1.re - ca1.im * y1.im,
-                        ca0.re * y0.im + ca0.im * y0.re + ca1.re * y1.im + ca1.im * y1.re};
-      w[e] = pc ? z64{-t.re, -t.im} : z64{w[e].re - t.re, w[e].im - t.im};
+      // A operand: component kp of C[r][ka] = sg conj(B[p0 + ka][r]); -I on the pivot rows
+      double aop = kp == 0 ? sg * xa[t] : -sg * xa[t];
+      if (r == p0 || r == p0 + 1) aop = (r - p0 == ka && kp == 0) ? -1.0 : 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + 4 * v + kq;
+        if (jpiv || row == p0 || row == p0 + 1) acc[t][v] = 0.0;
+      }
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, acc[t], 0, 0, 0);
     }
   }
   return bad_any;
+}
+
+// P = the inverted block from acc into pout (pout[u NB + t] = P[t][u])
+__device__ __forceinline__ void store_p(const d4 (&acc)[2], z64* pout, int lane, int wave) {
+  const int kq = lane >> 4, jr = 16 * wave + (lane & 15);
+  double* pd = reinterpret_cast<double*>(pout);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pd[((jr >> 1) * NB + 16 * t + 4 * v + kq) * 2 + (jr & 1)] = acc[t][v];
 }
 
 typedef Tile<double, 32, 32, 32, 2, 2> TR;   // R = P A_kj: 32 x 32 x 32
@@ -96,24 +121,27 @@ typedef Tile<double, 64, 32, 32, 2, 2> TU;   // the tile update: 64 x 32, K = th
 constexpr int LP = NB + 1;                   // row stride of the 32 x 32 LDS blocks
 
 // P of the first pivot block, per batch item (pout[u NB + t] = P[t][u])
-__global__ __launch_bounds__(256) void sweep_first_kernel(int n, const z64* __restrict__ ain, z64* __restrict__ pout,
-                                                          int kn, int* status) {
-  __shared__ z64 rowb[2][2][NB];
+__global__ __launch_bounds__(GJ_THREADS) void sweep_first_kernel(int n, const z64* __restrict__ ain,
+                                                                 z64* __restrict__ pout, int kn, int* status) {
+  __shared__ double rowd[2][2][2 * NB];
   ain += (long)blockIdx.y * n * n;
   pout += (long)blockIdx.y * NB * NB;
-  const int tid = threadIdx.x, gj = tid % NB, gr = tid / NB;
-  z64 w[EW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kq = lane >> 4, jr = 16 * wave + (lane & 15), j = jr >> 1, part = jr & 1;
+  const double* ad = reinterpret_cast<const double*>(ain);
+  d4 acc[2];
 #pragma unroll
-  for (int e = 0; e < EW; ++e) {
-    const int r = gr + 8 * e;
-    const bool ok = r < kn && gj < kn;
-    const z64 v = ain[ok ? (long)r * n + gj : 0];
-    w[e] = ok ? v : z64{r == gj ? 1.0 : 0.0, 0.0};
-  }
-  const bool bad = pivot_gj2(w, rowb, gj, gr);
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * t + 4 * v + kq;
+      const bool ok = r < kn && j < kn;
+      const double x = ad[ok ? ((long)r * n + j) * 2 + part : 0];
+      acc[t][v] = ok ? x : (r == j && part == 0 ? 1.0 : 0.0);
+    }
+  const bool bad = pivot_gj(acc, rowd, lane, wave);
   if (bad && tid == 0) atomicOr(status, 1);
-#pragma unroll
-  for (int e = 0; e < EW; ++e) pout[gj * NB + gr + 8 * e] = w[e];
+  store_p(acc, pout, lane, wave);
 }
 
 // R = P K in LDS: Ps[s][t] = P[t][s] (k-major A operand), Ks[s][j] = A[k0 + s][c0 + j];
@@ -156,7 +184,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
   if (pout && blockIdx.x == gridDim.x - 1) {
     // look-ahead: A'_{k1 k1} = A_{k1 k1} - conj(A_{k k1})^T R1, R1 = P A_{k k1}; then its inverse
     pout += (long)blockIdx.y * NB * NB;
-    const int gj = tid % NB, gr = tid / NB;
 #pragma unroll
     for (int e = 0; e < EW; ++e) {
       const int idx = tid + 256 * e, s2 = idx / NB, t = idx % NB;
@@ -165,12 +192,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
       const z64 v = ain[ok ? (long)(k0 + s2) * n + k1 + t : 0];
       Ks[s2 * LP + t] = ok ? v : z64{0.0, 0.0};                               // A[k0 + s2][k1 + t]
     }
-    z64 old[EW];
+    // A_{k1 k1} in the elimination's layout (real entry (16 t + 4 v + l / 16, 16 w + l % 16))
+    const int kq = lane >> 4, jr = 16 * wave + (lane & 15), j = jr >> 1, part = jr & 1;
+    const double* ad = reinterpret_cast<const double*>(ain);
+    d4 acc[2];
 #pragma unroll
-    for (int e = 0; e < EW; ++e) {
-      const int r = gr + 8 * e;
-      old[e] = ain[r < kn1 && gj < kn1 ? (long)(k1 + r) * n + k1 + gj : 0];
-    }
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * t + 4 * v + kq;
+        acc[t][v] = ad[r < kn1 && j < kn1 ? ((long)(k1 + r) * n + k1 + j) * 2 + part : 0];
+      }
     __syncthreads();
     form_r(Ps, Ks, Rs, lane, wave);
     __syncthreads();
@@ -184,19 +216,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     // C = conj(A_{k k1})^T R1 into Ks's place (its raw values are no longer needed)
     form_r(Ps, Rs, Ks, lane, wave);
     __syncthreads();
-    z64 w[EW];
+    {
+      const double* Kd = reinterpret_cast<const double*>(Ks);
 #pragma unroll
-    for (int e = 0; e < EW; ++e) {
-      const int r = gr + 8 * e;
-      const bool ok = r < kn1 && gj < kn1;
-      const z64 cv = Ks[r * LP + gj];
-      w[e] = ok ? z64{old[e].re - cv.re, old[e].im - cv.im} : z64{r == gj ? 1.0 : 0.0, 0.0};
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * t + 4 * v + kq;
+          const bool ok = r < kn1 && j < kn1;
+          acc[t][v] = ok ? acc[t][v] - Kd[(r * LP + j) * 2 + part] : (r == j && part == 0 ? 1.0 : 0.0);
+        }
     }
-    __syncthreads();   // Ks read before rowb reuses Rs
-    const bool bad = pivot_gj2(w, reinterpret_cast<z64 (*)[2][NB]>(Rs), gj, gr);
+    __syncthreads();   // Ks read before the pivot rows reuse Rs
+    const bool bad = pivot_gj(acc, reinterpret_cast<double (*)[2][2 * NB]>(Rs), lane, wave);
     if (bad && tid == 0) atomicOr(status, 1);
-#pragma unroll
-    for (int e = 0; e < EW; ++e) pout[gj * NB + gr + 8 * e] = w[e];
+    store_p(acc, pout, lane, wave);
     return;
   }
   const int id = xcd_remap(blockIdx.x, total);
