@@ -329,6 +329,9 @@ isdf_status isdf_graph_destroy(isdf_graph graph);
  *   side_prio       1 (default): the Gauss-Jordan sweep steps on the library's second
  *                   stream raise their waves' issue priority over the kernels they share
  *                   the CUs with; 0: they run at normal priority
+ *   dft_pipe        single precision: 1 (default) runs the DFT to X as a warp-specialised
+ *                   pass (matrix-core waves transform a slab while other waves sum the
+ *                   previous one) where the grid shape allows, 0 the single-role pass
  *   best_ms         output of isdf_plan_autotune: time of one call with the chosen knobs */
 typedef struct {
   int32_t dft_zb;
@@ -337,6 +340,7 @@ typedef struct {
   int32_t wg_per_cu;
   int32_t core_stream;
   int32_t side_prio;
+  int32_t dft_pipe;
   double best_ms;
 } isdf_tune;
 

@@ -39,7 +39,7 @@ class Problem(ctypes.Structure):
 class Tune(ctypes.Structure):
     _fields_ = [("dft_zb", ctypes.c_int32), ("core_split_pct", ctypes.c_int32), ("gram_split", ctypes.c_int32),
                 ("wg_per_cu", ctypes.c_int32), ("core_stream", ctypes.c_int32), ("side_prio", ctypes.c_int32),
-                ("best_ms", ctypes.c_double)]
+                ("dft_pipe", ctypes.c_int32), ("best_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

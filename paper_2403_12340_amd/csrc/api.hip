@@ -520,6 +520,7 @@ struct Tune {
   int wg_per_cu = 1;       // workgroups per CU of the persistent k-major kernels
   int core_stream = 0;     // first core: 0 main stream before Z, 1 side stream after Z, 2 side stream beside Z
   int side_prio = 1;       // 1: the second stream's sweep steps raise their waves' issue priority
+  int dft_pipe = 1;        // 1: the warp-specialised fused DFT (single precision) where it fits
 };
 
 struct Run {
@@ -637,6 +638,7 @@ DftPlan make_plan(Run& R) {
   p.n0 = P.n0; p.n1 = P.n1; p.n2 = P.n2; p.nmu = P.nmu; p.ng = P.ngg;
   p.kx = L.kx; p.ky = L.ky; p.nd = L.nd; p.kz = L.kz;
   p.zb = R.tune.dft_zb;
+  p.pipe = R.tune.dft_pipe;
   p.twx = at<char>(R.ws, L.twx);
   p.twy = at<char>(R.ws, L.twy);
   p.twz = at<char>(R.ws, L.twz);
@@ -2122,7 +2124,8 @@ isdf_status isdf_plan_sync(isdf_plan pl, isdf_report* rep) {
 static bool tune_valid(const isdf_tune* t) {
   return t && t->dft_zb >= 1 && t->dft_zb <= 64 && t->core_split_pct >= 25 && t->core_split_pct <= 200 &&
          t->gram_split >= 1 && t->gram_split <= 16 && t->wg_per_cu >= 1 && t->wg_per_cu <= 4 &&
-         t->core_stream >= 0 && t->core_stream <= 2 && t->side_prio >= 0 && t->side_prio <= 1;
+         t->core_stream >= 0 && t->core_stream <= 2 && t->side_prio >= 0 && t->side_prio <= 1 &&
+         t->dft_pipe >= 0 && t->dft_pipe <= 1;
 }
 
 isdf_status isdf_plan_set_tune(isdf_plan pl, const isdf_tune* t) {
@@ -2134,6 +2137,7 @@ isdf_status isdf_plan_set_tune(isdf_plan pl, const isdf_tune* t) {
   pl->tune.wg_per_cu = t->wg_per_cu;
   pl->tune.core_stream = t->core_stream;
   pl->tune.side_prio = t->side_prio;
+  pl->tune.dft_pipe = t->dft_pipe;
   return ISDF_OK;
 }
 
@@ -2145,6 +2149,7 @@ isdf_status isdf_plan_get_tune(isdf_plan pl, isdf_tune* t) {
   t->wg_per_cu = pl->tune.wg_per_cu;
   t->core_stream = pl->tune.core_stream;
   t->side_prio = pl->tune.side_prio;
+  t->dft_pipe = pl->tune.dft_pipe;
   t->best_ms = 0.0;
   return ISDF_OK;
 }
@@ -2194,6 +2199,7 @@ isdf_status isdf_plan_autotune(isdf_plan pl, const void* psi, const double* ener
   TRY(sweep(&Tune::wg_per_cu, wpcs, 2));
   TRY(sweep(&Tune::core_stream, cstreams, 3));
   TRY(sweep(&Tune::side_prio, prios, 2));
+  TRY(sweep(&Tune::dft_pipe, prios, 2));
   if (out) {
     TRY(isdf_plan_get_tune(pl, out));
     out->best_ms = best;

@@ -566,6 +566,203 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
   }
 }
 
+// Warp-specialised fused pass (FP32, grids with n0 and n1 rounding to the same 2 NK):
+// the workgroup has nw MFMA waves and nw z-waves.  At step s the MFMA waves run the x
+// and y stages of slab s (their twiddle fragments held in registers) while the
+// z-waves add slab s - 1's T2 into the running plane-wave sums, then load slab s + 1
+// and store it into LDS once the x stage has read the current one.
+// Two barriers per slab:
+//   B1: slab s staged, T2 of slab s - 1 complete;   B2: slab s read by the x stage.
+// T2 is double buffered ([s & 1]); T1 stays in a region private to each MFMA wave.
+// The sums, the pieces and the twiddle padding follow dft_fused_kernel.
+struct PipeShape {
+  int nw, nt, ls, wsz, t2sz, g, pmax;
+  size_t lds;
+};
+
+template <int FMX, int NK, int GPT, int PF>
+__global__ __launch_bounds__(512) void dft_pipe_kernel(DftPlan p, PipeShape f, const c32* __restrict__ zt,
+                                                       c32* __restrict__ out) {
+  constexpr int FMB = 2;   // b rows in two blocks of 16 (ky <= 32)
+  extern __shared__ unsigned char lds_raw[];
+  const int rows = 16 * FMX;
+  c32* Ss = reinterpret_cast<c32*>(lds_raw);   // slab [y][x], rows x ls
+  c32* Tw = Ss + rows * f.ls;                   // per MFMA wave: T1 [y][a_w], stride 9
+  c32* T2 = Tw + f.nw * f.wsz;                  // [2][nw][32][9]: T2 [b][a_w] per MFMA wave
+  c32* Zs = T2 + 2 * f.t2sz;                    // twz [z][c]
+  uint32_t* Gc = reinterpret_cast<uint32_t*>(Zs + p.n2 * p.kz);   // plane-wave codes [j][z-thread]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool zw = wave >= f.nw;
+  const int S = p.nmu * p.n2;   // slabs (the launcher keeps this in int range)
+  const int s0 = (int)((long)blockIdx.x * S / f.g), s1 = (int)((long)(blockIdx.x + 1) * S / f.g);
+  const int nslab = p.n0 * p.n1;
+  const c32* twx = reinterpret_cast<const c32*>(p.twx);
+  const c32* twy = reinterpret_cast<const c32*>(p.twy);
+  const c32* twz = reinterpret_cast<const c32*>(p.twz);
+  const c32 zero{0.f, 0.f};
+  for (int i = tid; i < rows * f.ls; i += f.nt) Ss[i] = zero;
+  for (int i = tid; i < p.n2 * p.kz; i += f.nt) {
+    const int z = i / p.kz, c = i % p.kz;
+    Zs[i] = twz[c * p.n2 + z];
+  }
+  if (s0 >= s1) return;   // the whole workgroup
+  __syncthreads();        // the zeroed slab and the z twiddles before any use
+  const int i16 = lane & 15, q = lane >> 4, rc = lane & 15, part = rc & 1;
+  if (!zw) {
+    // ---- MFMA waves: x and y stages of slab s at step s
+    const int bpart = ((q & 1) == (i16 & 1)) ? 0 : 1;
+    const float bsign = ((q & 1) == 1 && (i16 & 1) == 0) ? -1.f : 1.f;
+    float xb[NK], ya[NK][FMB];   // x-stage B and y-stage A fragments (zero padded)
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int k = (q >> 1) + 2 * kk, c = 8 * wave + (i16 >> 1);
+      const c32 v = (k < p.n0 && c < p.kx) ? twx[c * p.n0 + k] : zero;
+      xb[kk] = bsign * (bpart ? v.im : v.re);
+#pragma unroll
+      for (int fb = 0; fb < FMB; ++fb) {
+        const int cy = i16 + 16 * fb;
+        const c32 u = (k < p.n1 && cy < p.ky) ? twy[cy * p.n1 + k] : zero;
+        ya[kk][fb] = (q & 1) ? u.im : u.re;
+      }
+    }
+    const float* SsR = reinterpret_cast<const float*>(Ss);
+    float* TwR = reinterpret_cast<float*>(Tw + wave * f.wsz);
+    for (int s = s0; s <= s1; ++s) {
+      __syncthreads();   // B1
+      Mfma<float>::acc_t acc1[FMX];
+      if (s < s1) {
+#pragma unroll
+        for (int fm = 0; fm < FMX; ++fm) acc1[fm] = f4{0.f, 0.f, 0.f, 0.f};
+        const float* ap = SsR + (i16 * f.ls + (q >> 1)) * 2 + (q & 1);
+        float a0[FMX], a1[FMX];
+#pragma unroll
+        for (int fm = 0; fm < FMX; ++fm) a0[fm] = ap[fm * 32 * f.ls];
+#pragma unroll
+        for (int kk = 0; kk < NK; kk += 2) {
+#pragma unroll
+          for (int fm = 0; fm < FMX; ++fm) a1[fm] = ap[fm * 32 * f.ls + (kk + 1) * 4];
+#pragma unroll
+          for (int fm = 0; fm < FMX; ++fm) acc1[fm] = Mfma<float>::op(a0[fm], xb[kk], acc1[fm]);
+          fused_interleave<FMX>();
+          if (kk + 2 < NK) {
+#pragma unroll
+            for (int fm = 0; fm < FMX; ++fm) a0[fm] = ap[fm * 32 * f.ls + (kk + 2) * 4];
+          }
+#pragma unroll
+          for (int fm = 0; fm < FMX; ++fm) acc1[fm] = Mfma<float>::op(a1[fm], xb[kk + 1], acc1[fm]);
+          fused_interleave<FMX>();
+        }
+#pragma unroll
+        for (int fm = 0; fm < FMX; ++fm)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) TwR[((16 * fm + Mfma<float>::row(lane, v)) * 9 + (rc >> 1)) * 2 + part] = acc1[fm][v];
+      }
+      __syncthreads();   // B2 (also orders this wave's T1 writes before its reads)
+      if (s < s1) {
+        Mfma<float>::acc_t acc2[FMB];
+#pragma unroll
+        for (int fb = 0; fb < FMB; ++fb) acc2[fb] = f4{0.f, 0.f, 0.f, 0.f};
+        const int bpart2 = bpart;
+        const float* bp = TwR + ((q >> 1) * 9 + (i16 >> 1)) * 2 + bpart2;
+        float b0 = bsign * bp[0], b1;
+#pragma unroll
+        for (int kk = 0; kk < NK; kk += 2) {
+          b1 = bsign * bp[(kk + 1) * 4 * 9];
+#pragma unroll
+          for (int fb = 0; fb < FMB; ++fb) acc2[fb] = Mfma<float>::op(ya[kk][fb], b0, acc2[fb]);
+          if (kk + 2 < NK) b0 = bsign * bp[(kk + 2) * 4 * 9];
+#pragma unroll
+          for (int fb = 0; fb < FMB; ++fb) acc2[fb] = Mfma<float>::op(ya[kk + 1][fb], b1, acc2[fb]);
+        }
+        float* T2R = reinterpret_cast<float*>(T2 + (s & 1) * f.t2sz + wave * 288);
+#pragma unroll
+        for (int fb = 0; fb < FMB; ++fb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) T2R[((16 * fb + Mfma<float>::row(lane, v)) * 9 + (rc >> 1)) * 2 + part] = acc2[fb][v];
+      }
+    }
+  } else {
+    // ---- z-waves: the sums of slab s - 1 and the loads of slab s + 1 at step s
+    const int zt0 = tid - 64 * f.nw, nzt = 64 * f.nw;
+    // this thread's plane waves g = zt0 + nzt j: T2 offset | z-frequency << 16, kept in LDS
+    // (read by this thread only); slots past the list hold code 0 (summed, never stored)
+    c32 zacc[GPT];
+#pragma unroll
+    for (int j = 0; j < GPT; ++j) zacc[j] = zero;
+#pragma unroll 1
+    for (int j = 0; j < GPT; ++j) {
+      const int g = zt0 + nzt * j;
+      uint32_t code = 0;
+      if (g < p.ng) {
+        const int d = p.g_d[g], a = p.d_ax[d];
+        code = (uint32_t)((a >> 3) * 288 + p.d_by[d] * 9 + (a & 7)) | ((uint32_t)p.g_cz[g] << 16);
+      }
+      Gc[j * nzt + zt0] = code;
+    }
+    const int r0 = zt0 / p.n0, c0 = zt0 % p.n0, dr = nzt / p.n0, dc = nzt % p.n0;
+    float pfr[PF], pfi[PF];
+    auto fetch = [&](int sl) {
+      const char* src = reinterpret_cast<const char*>(zt + (long)sl * nslab);
+#pragma unroll
+      for (int e = 0; e < PF; ++e) {
+        const int i = zt0 + nzt * e;
+        const c32 v = *reinterpret_cast<const c32*>(src + (uint32_t)(i < nslab ? i : 0) * (uint32_t)sizeof(c32));
+        pfr[e] = v.re; pfi[e] = v.im;
+      }
+    };
+    auto store = [&]() {
+      int r = r0, c = c0;
+#pragma unroll
+      for (int e = 0; e < PF; ++e) {
+        if (zt0 + nzt * e < nslab) Ss[r * f.ls + c] = c32{pfr[e], pfi[e]};
+        r += dr; c += dc;
+        if (c >= p.n0) { c -= p.n0; ++r; }
+      }
+    };
+    fetch(s0);
+    store();
+    // step s0: nothing to sum yet
+    __syncthreads();   // B1
+    if (s0 + 1 < s1) fetch(s0 + 1);
+    __syncthreads();   // B2
+    if (s0 + 1 < s1) store();
+    // step sp + 1 sums slab sp; the runs of one point end with the store of its piece
+    for (int sp = s0; sp < s1;) {
+      const int mu = sp / p.n2;
+      const int rb = min(s1, (mu + 1) * p.n2);
+      for (; sp < rb; ++sp) {
+        __syncthreads();   // B1: T2 of slab sp complete
+        const c32* t2 = T2 + (sp & 1) * f.t2sz;
+        const c32* zrow = Zs + (sp % p.n2) * p.kz;
+#pragma unroll
+        for (int j0 = 0; j0 < GPT; j0 += 4) {
+          __builtin_amdgcn_sched_barrier(0);   // bounds the LDS reads in flight (register pressure)
+#pragma unroll
+          for (int j = j0; j < j0 + 4; ++j) {
+            const uint32_t code = Gc[j * nzt + zt0];
+            const c32 v = t2[code & 0xffffu], w = zrow[code >> 16];
+            zacc[j].re += v.re * w.re - v.im * w.im;
+            zacc[j].im += v.re * w.im + v.im * w.re;
+          }
+        }
+        // the next slab's loads: in flight while this wave waits for the x stage at B2
+        // (issued after the sums, so the sums and the loaded values are never live together)
+        if (sp + 2 < s1) fetch(sp + 2);
+        __syncthreads();   // B2: the x stage has read slab sp + 1
+        if (sp + 2 < s1) store();
+      }
+      const int piece = (int)blockIdx.x - fused_owner((long)mu * p.n2, S, f.g);
+      c32* ob = out + ((long)mu * f.pmax + piece) * p.ng;
+#pragma unroll
+      for (int j = 0; j < GPT; ++j) {
+        const int g = zt0 + nzt * j;
+        if (g < p.ng) ob[g] = zacc[j];
+        zacc[j] = zero;
+      }
+    }
+  }
+}
+
 // zg[mu][g] = scale[g] sum_j part[mu][j][g] over the point's pieces, in piece order
 template <typename T>
 __global__ void dft_zsum_kernel(const cx<T>* __restrict__ part, int pmax, long S, int g_wg, int n2, int nmu, int ng,
@@ -624,6 +821,81 @@ static hipError_t fused_kernel_launch(const DftPlan& p, FusedShape& f, const voi
   return hipGetLastError();
 }
 
+
+// even NK (K steps of both stages) and the register budgets of its instantiation
+static bool pipe_shape(const DftPlan& p, PipeShape& f, int& nk) {
+  const int x2 = (p.n0 + 3) & ~3, y2 = (p.n1 + 3) & ~3;
+  if (x2 != y2 || x2 > 48) return false;   // larger slabs need more registers than a wave has
+  if (p.kx < 1 || p.kx > 32 || p.ky < 1 || p.ky > 32 || p.kz < 1 || p.kz > 64 || p.n2 > 64) return false;
+  nk = x2 / 2;
+  f.nw = (p.kx + 7) / 8;
+  f.nt = 128 * f.nw;
+  const int fmx = (2 * nk + 15) / 16, nzt = 64 * f.nw;
+  const long gpt = cdiv(p.ng, nzt), pf = cdiv((long)p.n0 * p.n1, nzt);
+  if (nk <= 24 ? (gpt > 24 || pf > 12) : (gpt > 32 || pf > 16)) return false;
+  f.ls = x2 + 1;
+  f.wsz = 16 * fmx * 9;
+  f.t2sz = f.nw * 288;
+  f.g = f.pmax = 0;
+  f.lds = ((size_t)16 * fmx * f.ls + (size_t)f.nw * f.wsz + 2 * (size_t)f.t2sz + (size_t)p.n2 * p.kz) * sizeof(c32) +
+          (size_t)(nk <= 24 ? 24 : 32) * nzt * sizeof(uint32_t);
+  return f.lds <= 160 * 1024;
+}
+
+template <int NK>
+static hipError_t pipe_kernel_launch(const DftPlan& p, PipeShape& f, const void* zt, void* part, size_t part_bytes,
+                                     hipStream_t st) {
+  constexpr int FMX = (2 * NK + 15) / 16, GPT = NK <= 24 ? 24 : 32, PF = NK <= 24 ? 12 : 16;
+  const void* fn = reinterpret_cast<const void*>(&dft_pipe_kernel<FMX, NK, GPT, PF>);
+  static bool attr_set[64] = {};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const bool cache = dev >= 0 && dev < 64;
+  if (!cache || !attr_set[dev]) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (cache) attr_set[dev] = true;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, f.nt, f.lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  // one resident round of workgroups (at least 4 slabs each); fewer if the pieces
+  // per point would overflow the scratch
+  const long S = (long)p.nmu * p.n2;
+  long g = std::min<long>((long)per_cu * cu_count(), std::max<long>(1, S / 4));
+  for (;;) {
+    int pmax = 1;
+    for (int mu = 0; mu < p.nmu; ++mu)
+      pmax = std::max(pmax, fused_owner((long)(mu + 1) * p.n2 - 1, S, (int)g) - fused_owner((long)mu * p.n2, S, (int)g) + 1);
+    f.g = (int)g;
+    f.pmax = pmax;
+    if ((size_t)p.nmu * pmax * p.ng * sizeof(c32) <= part_bytes) break;
+    if (g == 1) return hipErrorNotSupported;
+    g = std::max<long>(1, g * 3 / 4);
+  }
+  hipLaunchKernelGGL((dft_pipe_kernel<FMX, NK, GPT, PF>), dim3((unsigned)f.g), dim3(f.nt), f.lds, st, p, f,
+                     (const c32*)zt, (c32*)part);
+  return hipGetLastError();
+}
+
+// hipErrorNotSupported when no instantiation covers the shape
+static hipError_t pipe_launch(const DftPlan& p, PipeShape& f, const void* zt, void* part, size_t part_bytes,
+                              hipStream_t st) {
+  int nk = 0;
+  if (!pipe_shape(p, f, nk)) return hipErrorNotSupported;
+  switch (nk) {
+    case 4: return pipe_kernel_launch<4>(p, f, zt, part, part_bytes, st);
+    case 6: return pipe_kernel_launch<6>(p, f, zt, part, part_bytes, st);
+    case 8: return pipe_kernel_launch<8>(p, f, zt, part, part_bytes, st);
+    case 10: return pipe_kernel_launch<10>(p, f, zt, part, part_bytes, st);
+    case 12: return pipe_kernel_launch<12>(p, f, zt, part, part_bytes, st);
+    case 14: return pipe_kernel_launch<14>(p, f, zt, part, part_bytes, st);
+    case 16: return pipe_kernel_launch<16>(p, f, zt, part, part_bytes, st);
+    case 18: return pipe_kernel_launch<18>(p, f, zt, part, part_bytes, st);
+    case 20: return pipe_kernel_launch<20>(p, f, zt, part, part_bytes, st);
+    case 24: return pipe_kernel_launch<24>(p, f, zt, part, part_bytes, st);
+    default: return hipErrorNotSupported;
+  }
+}
+
 template <typename T, int PF, int GPT>
 static hipError_t fused_dispatch(const DftPlan& p, FusedShape& f, const void* zt, void* part, size_t part_bytes,
                                  hipStream_t st) {
@@ -638,6 +910,14 @@ static hipError_t fused_dispatch(const DftPlan& p, FusedShape& f, const void* zt
 template <typename T>
 static hipError_t fused_launch(const DftPlan& p, const void* zt, void* part, size_t part_bytes, void* zg,
                                const double* scale, hipStream_t st) {
+  if (sizeof(T) == 4 && p.pipe) {
+    PipeShape ps;
+    const hipError_t e = pipe_launch(p, ps, zt, part, part_bytes, st);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(dft_zsum_kernel<T>, dim3(cdiv(p.ng, 256), p.nmu), dim3(256), 0, st, (const cx<T>*)part,
+                         ps.pmax, (long)p.nmu * p.n2, ps.g, p.n2, p.nmu, p.ng, scale, (cx<T>*)zg);
+    if (e != hipErrorNotSupported) return e == hipSuccess ? hipGetLastError() : e;
+  }
   FusedShape f;
   if (!fused_shape<T>(p, f)) return hipErrorNotSupported;
   const hipError_t e = (f.pf <= FUSED_PF_S && f.gpt <= FUSED_GPT_S)

@@ -103,6 +103,7 @@ struct DftPlan {
   const int* gd_off;       // nd + 1: plane waves of pair d are gd_list[gd_off[d] .. gd_off[d + 1])
   const int* gd_list;      // ng
   int zb = 8;              // z-planes per workgroup of dft_xy (a tuning knob)
+  int pipe = 1;            // single precision: the warp-specialised fused pass where its shape fits
 };
 // zt: [nmu][n2][n1][n0] (compute type) -> t2: [nmu][nd][n2] -> zg: [nmu][ng] (times scale[g] if given)
 hipError_t dft_xy(Prec compute, const DftPlan& p, const void* zt, void* t2, hipStream_t st);

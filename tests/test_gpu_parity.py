@@ -682,7 +682,7 @@ def test_plan_autotune():
     t = plan.autotune(psi, e, out, ws, reps=2)
     assert t["dft_zb"] in (4, 6, 8, 12, 16, 24) and t["core_split_pct"] in (50, 100, 200)
     assert t["gram_split"] in (4, 8, 16) and t["wg_per_cu"] in (1, 2) and t["best_ms"] > 0
-    assert t["core_stream"] in (0, 1, 2) and t["side_prio"] in (0, 1)
+    assert t["core_stream"] in (0, 1, 2) and t["side_prio"] in (0, 1) and t["dft_pipe"] in (0, 1)
     assert plan.get_tune()["dft_zb"] == t["dft_zb"]
     plan.eps_inv_async(psi, e, out, ws)
     plan.sync()
@@ -716,6 +716,27 @@ def test_core_stream_placement_is_bit_identical(prec):
         plan.eps_inv_async(psi, e, outs[-1], ws)
         plan.sync()
     assert all(torch.equal(outs[0], o) for o in outs[1:])
+
+
+@pytest.mark.parametrize("name", ["mid", "tiles", "kmaj_even", "wide", "sig_even"])
+def test_dft_pipe_and_single_role_pass_agree(name):
+    """The warp-specialised DFT (dft_pipe 1, the default) and the single-role pass
+    (dft_pipe 0) each meet the FP32 bars against the oracle, and agree with each
+    other to FP32 rounding (their z sums are split into pieces differently)."""
+    inp, prob, plan = _plan_case(name, "fp32")
+    print(f"[dft_pipe] case={name}", flush=True)
+    psi, e = dev(inp.psi_t), dev(inp.energies)
+    ws = plan.new_workspace()
+    ref = oracle.eps_inv_isdf(inp, stages=get_stages(name))
+    outs = []
+    for pipe in (1, 0):
+        outs.append(plan.new_output())
+        plan.set_tune(dft_pipe=pipe)
+        plan.eps_inv_async(psi, e, outs[-1], ws)
+        plan.sync()
+        check_eps(outs[-1][0].cpu().numpy(), ref, "fp32", tag=f"pipe={pipe} ")
+    a, b = outs[0][0].cpu().numpy(), outs[1][0].cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-6 * max(1.0, np.abs(b).max())
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
