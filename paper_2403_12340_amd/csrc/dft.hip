@@ -567,72 +567,76 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
 }
 
 // Warp-specialised fused pass (FP32, grids with n0 and n1 rounding to the same 2 NK):
-// the workgroup has nw MFMA waves and nw z-waves.  At step s the MFMA waves run the x
-// and y stages of slab s (their twiddle fragments held in registers) while the
-// z-waves add slab s - 1's T2 into the running plane-wave sums, then load slab s + 1
-// and store it into LDS once the x stage has read the current one.
-// Two barriers per slab:
-//   B1: slab s staged, T2 of slab s - 1 complete;   B2: slab s read by the x stage.
-// T2 is double buffered ([s & 1]); T1 stays in a region private to each MFMA wave.
-// The sums, the pieces and the twiddle padding follow dft_fused_kernel.
+// a workgroup has two groups of nw MFMA waves and PIPE_ZW z-waves.  At step t group k
+// runs the x and y stages of slab s0 + 2 t + k (its twiddle fragments held in
+// registers) from the slab buffers of parity t, while the z-waves store the pair of
+// step t + 1 (loaded during step t - 1) into the buffers of the other parity, issue the
+// loads of the pair of step t + 2, and add the T2 of both slabs of step t - 1 into the
+// running plane-wave sums (slab order; a point's run ends with the store of its piece).
+// One barrier per step: the pair of step t staged and T2 of step t - 1 complete.  Slabs
+// and T2 are double buffered by step parity; T1 stays in a region private to each MFMA
+// wave.  The sums, the pieces and the twiddle padding follow dft_fused_kernel.
+constexpr int PIPE_ZW = 5;   // z-waves per workgroup
 struct PipeShape {
-  int nw, nt, ls, wsz, t2sz, g, pmax;
+  int nw, nt, ls, ssz, wsz, t2sz, g, pmax;
   size_t lds;
 };
 
 template <int FMX, int NK, int GPT, int PF>
-__global__ __launch_bounds__(512) void dft_pipe_kernel(DftPlan p, PipeShape f, const c32* __restrict__ zt,
+__global__ __launch_bounds__(704) __attribute__((amdgpu_waves_per_eu(3))) void dft_pipe_kernel(DftPlan p, PipeShape f, const c32* __restrict__ zt,
                                                        c32* __restrict__ out) {
   constexpr int FMB = 2;   // b rows in two blocks of 16 (ky <= 32)
   extern __shared__ unsigned char lds_raw[];
-  const int rows = 16 * FMX;
-  c32* Ss = reinterpret_cast<c32*>(lds_raw);   // slab [y][x], rows x ls
-  c32* Tw = Ss + rows * f.ls;                   // per MFMA wave: T1 [y][a_w], stride 9
-  c32* T2 = Tw + f.nw * f.wsz;                  // [2][nw][32][9]: T2 [b][a_w] per MFMA wave
-  c32* Zs = T2 + 2 * f.t2sz;                    // twz [z][c]
+  c32* Ss = reinterpret_cast<c32*>(lds_raw);   // four slabs [parity][k][y][x], ssz each (rows x ls)
+  c32* Tw = Ss + 4 * f.ssz;                     // per MFMA wave: T1 [y][a_w], stride 9
+  c32* T2 = Tw + 2 * f.nw * f.wsz;              // [parity][k][nw][32][9]: T2 [b][a_w]
+  c32* Zs = T2 + 4 * f.t2sz;                    // twz [z][c]
   uint32_t* Gc = reinterpret_cast<uint32_t*>(Zs + p.n2 * p.kz);   // plane-wave codes [j][z-thread]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool zw = wave >= f.nw;
+  const bool zw = wave >= 2 * f.nw;
   const int S = p.nmu * p.n2;   // slabs (the launcher keeps this in int range)
   const int s0 = (int)((long)blockIdx.x * S / f.g), s1 = (int)((long)(blockIdx.x + 1) * S / f.g);
+  const int nsteps = (s1 - s0 + 1) / 2;
   const int nslab = p.n0 * p.n1;
   const c32* twx = reinterpret_cast<const c32*>(p.twx);
   const c32* twy = reinterpret_cast<const c32*>(p.twy);
   const c32* twz = reinterpret_cast<const c32*>(p.twz);
   const c32 zero{0.f, 0.f};
-  for (int i = tid; i < rows * f.ls; i += f.nt) Ss[i] = zero;
+  for (int i = tid; i < 4 * f.ssz; i += f.nt) Ss[i] = zero;
   for (int i = tid; i < p.n2 * p.kz; i += f.nt) {
     const int z = i / p.kz, c = i % p.kz;
     Zs[i] = twz[c * p.n2 + z];
   }
   if (s0 >= s1) return;   // the whole workgroup
-  __syncthreads();        // the zeroed slab and the z twiddles before any use
+  __syncthreads();        // the zeroed slabs and the z twiddles before any use
   const int i16 = lane & 15, q = lane >> 4, rc = lane & 15, part = rc & 1;
   if (!zw) {
-    // ---- MFMA waves: x and y stages of slab s at step s
+    // ---- MFMA waves: group k = wave / nw, x-frequency block w = wave % nw
+    const int k = wave / f.nw, w = wave % f.nw;
     const int bpart = ((q & 1) == (i16 & 1)) ? 0 : 1;
     const float bsign = ((q & 1) == 1 && (i16 & 1) == 0) ? -1.f : 1.f;
     float xb[NK], ya[NK][FMB];   // x-stage B and y-stage A fragments (zero padded)
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int k = (q >> 1) + 2 * kk, c = 8 * wave + (i16 >> 1);
-      const c32 v = (k < p.n0 && c < p.kx) ? twx[c * p.n0 + k] : zero;
+      const int kx = (q >> 1) + 2 * kk, c = 8 * w + (i16 >> 1);
+      const c32 v = (kx < p.n0 && c < p.kx) ? twx[c * p.n0 + kx] : zero;
       xb[kk] = bsign * (bpart ? v.im : v.re);
 #pragma unroll
       for (int fb = 0; fb < FMB; ++fb) {
         const int cy = i16 + 16 * fb;
-        const c32 u = (k < p.n1 && cy < p.ky) ? twy[cy * p.n1 + k] : zero;
+        const c32 u = (kx < p.n1 && cy < p.ky) ? twy[cy * p.n1 + kx] : zero;
         ya[kk][fb] = (q & 1) ? u.im : u.re;
       }
     }
-    const float* SsR = reinterpret_cast<const float*>(Ss);
     float* TwR = reinterpret_cast<float*>(Tw + wave * f.wsz);
-    for (int s = s0; s <= s1; ++s) {
-      __syncthreads();   // B1
+    for (int t = 0; t <= nsteps; ++t) {
+      const bool mine = t < nsteps && s0 + 2 * t + k < s1;
+      __syncthreads();   // the pair of step t staged; T2 of step t - 1 read by the z-waves
       Mfma<float>::acc_t acc1[FMX];
-      if (s < s1) {
+      if (mine) {
 #pragma unroll
         for (int fm = 0; fm < FMX; ++fm) acc1[fm] = f4{0.f, 0.f, 0.f, 0.f};
+        const float* SsR = reinterpret_cast<const float*>(Ss + ((t & 1) * 2 + k) * f.ssz);
         const float* ap = SsR + (i16 * f.ls + (q >> 1)) * 2 + (q & 1);
         float a0[FMX], a1[FMX];
 #pragma unroll
@@ -656,14 +660,14 @@ __global__ __launch_bounds__(512) void dft_pipe_kernel(DftPlan p, PipeShape f, c
         for (int fm = 0; fm < FMX; ++fm)
 #pragma unroll
           for (int v = 0; v < 4; ++v) TwR[((16 * fm + Mfma<float>::row(lane, v)) * 9 + (rc >> 1)) * 2 + part] = acc1[fm][v];
-      }
-      __syncthreads();   // B2 (also orders this wave's T1 writes before its reads)
-      if (s < s1) {
+        // T1 is private to this wave: its writes before its reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         Mfma<float>::acc_t acc2[FMB];
 #pragma unroll
         for (int fb = 0; fb < FMB; ++fb) acc2[fb] = f4{0.f, 0.f, 0.f, 0.f};
-        const int bpart2 = bpart;
-        const float* bp = TwR + ((q >> 1) * 9 + (i16 >> 1)) * 2 + bpart2;
+        const float* bp = TwR + ((q >> 1) * 9 + (i16 >> 1)) * 2 + bpart;
         float b0 = bsign * bp[0], b1;
 #pragma unroll
         for (int kk = 0; kk < NK; kk += 2) {
@@ -674,7 +678,7 @@ __global__ __launch_bounds__(512) void dft_pipe_kernel(DftPlan p, PipeShape f, c
 #pragma unroll
           for (int fb = 0; fb < FMB; ++fb) acc2[fb] = Mfma<float>::op(ya[kk + 1][fb], b1, acc2[fb]);
         }
-        float* T2R = reinterpret_cast<float*>(T2 + (s & 1) * f.t2sz + wave * 288);
+        float* T2R = reinterpret_cast<float*>(T2 + ((t & 1) * 2 + k) * f.t2sz + w * 288);
 #pragma unroll
         for (int fb = 0; fb < FMB; ++fb)
 #pragma unroll
@@ -682,8 +686,8 @@ __global__ __launch_bounds__(512) void dft_pipe_kernel(DftPlan p, PipeShape f, c
       }
     }
   } else {
-    // ---- z-waves: the sums of slab s - 1 and the loads of slab s + 1 at step s
-    const int zt0 = tid - 64 * f.nw, nzt = 64 * f.nw;
+    // ---- z-waves
+    const int zt0 = tid - 128 * f.nw, nzt = 64 * PIPE_ZW;
     // this thread's plane waves g = zt0 + nzt j: T2 offset | z-frequency << 16, kept in LDS
     // (read by this thread only); slots past the list hold code 0 (summed, never stored)
     c32 zacc[GPT];
@@ -700,64 +704,79 @@ __global__ __launch_bounds__(512) void dft_pipe_kernel(DftPlan p, PipeShape f, c
       Gc[j * nzt + zt0] = code;
     }
     const int r0 = zt0 / p.n0, c0 = zt0 % p.n0, dr = nzt / p.n0, dc = nzt % p.n0;
-    float pfr[PF], pfi[PF];
-    auto fetch = [&](int sl) {
-      const char* src = reinterpret_cast<const char*>(zt + (long)sl * nslab);
+    float pfr[2][PF], pfi[2][PF];
+    // the pair of step t into registers (slabs past the range are not read)
+    auto fetch = [&](int t) {
 #pragma unroll
-      for (int e = 0; e < PF; ++e) {
-        const int i = zt0 + nzt * e;
-        const c32 v = *reinterpret_cast<const c32*>(src + (uint32_t)(i < nslab ? i : 0) * (uint32_t)sizeof(c32));
-        pfr[e] = v.re; pfi[e] = v.im;
+      for (int k = 0; k < 2; ++k) {
+        const int sl = s0 + 2 * t + k;
+        if (sl >= s1) continue;
+        const char* src = reinterpret_cast<const char*>(zt + (long)sl * nslab);
+#pragma unroll
+        for (int e = 0; e < PF; ++e) {
+          const int i = zt0 + nzt * e;
+          const c32 v = *reinterpret_cast<const c32*>(src + (uint32_t)(i < nslab ? i : 0) * (uint32_t)sizeof(c32));
+          pfr[k][e] = v.re; pfi[k][e] = v.im;
+        }
       }
     };
-    auto store = [&]() {
-      int r = r0, c = c0;
+    auto store = [&](int t) {
 #pragma unroll
-      for (int e = 0; e < PF; ++e) {
-        if (zt0 + nzt * e < nslab) Ss[r * f.ls + c] = c32{pfr[e], pfi[e]};
-        r += dr; c += dc;
-        if (c >= p.n0) { c -= p.n0; ++r; }
+      for (int k = 0; k < 2; ++k) {
+        if (s0 + 2 * t + k >= s1) continue;
+        c32* dst = Ss + ((t & 1) * 2 + k) * f.ssz;
+        int r = r0, c = c0;
+#pragma unroll
+        for (int e = 0; e < PF; ++e) {
+          if (zt0 + nzt * e < nslab) dst[r * f.ls + c] = c32{pfr[k][e], pfi[k][e]};
+          r += dr; c += dc;
+          if (c >= p.n0) { c -= p.n0; ++r; }
+        }
       }
     };
-    fetch(s0);
-    store();
-    // step s0: nothing to sum yet
-    __syncthreads();   // B1
-    if (s0 + 1 < s1) fetch(s0 + 1);
-    __syncthreads();   // B2
-    if (s0 + 1 < s1) store();
-    // step sp + 1 sums slab sp; the runs of one point end with the store of its piece
-    for (int sp = s0; sp < s1;) {
-      const int mu = sp / p.n2;
-      const int rb = min(s1, (mu + 1) * p.n2);
-      for (; sp < rb; ++sp) {
-        __syncthreads();   // B1: T2 of slab sp complete
-        const c32* t2 = T2 + (sp & 1) * f.t2sz;
-        const c32* zrow = Zs + (sp % p.n2) * p.kz;
+    fetch(0);
+    store(0);
+    if (1 < nsteps) fetch(1);
+    for (int t = 0; t <= nsteps; ++t) {
+      __syncthreads();   // the pair of step t staged; T2 of step t - 1 complete
+      // the pair of step t + 1 (loaded during the previous step) into the other buffers,
+      // whose last reader was step t - 1; then the loads of the pair of step t + 2
+      if (t + 1 < nsteps) store(t + 1);
+      if (t + 2 < nsteps) fetch(t + 2);
+      if (t > 0) {
+#pragma unroll 1
+        for (int k = 0; k < 2; ++k) {
+          const int sp = s0 + 2 * (t - 1) + k;   // slab summed now
+          if (sp >= s1) break;
+          const c32* t2 = T2 + (((t - 1) & 1) * 2 + k) * f.t2sz;
+          const c32* zrow = Zs + (sp % p.n2) * p.kz;
 #pragma unroll
-        for (int j0 = 0; j0 < GPT; j0 += 4) {
-          __builtin_amdgcn_sched_barrier(0);   // bounds the LDS reads in flight (register pressure)
+          for (int j0 = 0; j0 < GPT; j0 += 2) {
+            __builtin_amdgcn_sched_barrier(0);   // bounds the LDS reads in flight (register pressure)
 #pragma unroll
-          for (int j = j0; j < j0 + 4; ++j) {
-            const uint32_t code = Gc[j * nzt + zt0];
-            const c32 v = t2[code & 0xffffu], w = zrow[code >> 16];
-            zacc[j].re += v.re * w.re - v.im * w.im;
-            zacc[j].im += v.re * w.im + v.im * w.re;
+            for (int j = j0; j < j0 + 2 && j < GPT; ++j) {
+              const uint32_t code = Gc[j * nzt + zt0];
+              const c32 v = t2[code & 0xffffu], wz = zrow[code >> 16];
+              zacc[j].re += v.re * wz.re - v.im * wz.im;
+              zacc[j].im += v.re * wz.im + v.im * wz.re;
+            }
+          }
+          if (sp + 1 == s1 || (sp + 1) % p.n2 == 0) {   // the run of this point ends: store its piece
+            const int mu = sp / p.n2;
+            const int piece = (int)blockIdx.x - fused_owner((long)mu * p.n2, S, f.g);
+            c32* ob = out + ((long)mu * f.pmax + piece) * p.ng;
+            // one running index, opaque to the optimiser: no per-plane-wave index is
+            // hoisted out of the slab loop into a register of its own
+            int g = zt0;
+            asm volatile("" : "+v"(g));
+#pragma unroll
+            for (int j = 0; j < GPT; ++j) {
+              if (g < p.ng) ob[g] = zacc[j];
+              zacc[j] = zero;
+              g += nzt;
+            }
           }
         }
-        // the next slab's loads: in flight while this wave waits for the x stage at B2
-        // (issued after the sums, so the sums and the loaded values are never live together)
-        if (sp + 2 < s1) fetch(sp + 2);
-        __syncthreads();   // B2: the x stage has read slab sp + 1
-        if (sp + 2 < s1) store();
-      }
-      const int piece = (int)blockIdx.x - fused_owner((long)mu * p.n2, S, f.g);
-      c32* ob = out + ((long)mu * f.pmax + piece) * p.ng;
-#pragma unroll
-      for (int j = 0; j < GPT; ++j) {
-        const int g = zt0 + nzt * j;
-        if (g < p.ng) ob[g] = zacc[j];
-        zacc[j] = zero;
       }
     }
   }
@@ -826,26 +845,28 @@ static hipError_t fused_kernel_launch(const DftPlan& p, FusedShape& f, const voi
 static bool pipe_shape(const DftPlan& p, PipeShape& f, int& nk) {
   const int x2 = (p.n0 + 3) & ~3, y2 = (p.n1 + 3) & ~3;
   if (x2 != y2 || x2 > 48) return false;   // larger slabs need more registers than a wave has
-  if (p.kx < 1 || p.kx > 32 || p.ky < 1 || p.ky > 32 || p.kz < 1 || p.kz > 64 || p.n2 > 64) return false;
+  if (p.kx < 1 || p.kx > 24 || p.ky < 1 || p.ky > 32 || p.kz < 1 || p.kz > 64 || p.n2 > 64) return false;
+  if ((long)p.nmu * p.n2 > 0x7fffffffL) return false;
   nk = x2 / 2;
   f.nw = (p.kx + 7) / 8;
-  f.nt = 128 * f.nw;
-  const int fmx = (2 * nk + 15) / 16, nzt = 64 * f.nw;
+  f.nt = 128 * f.nw + 64 * PIPE_ZW;
+  const int fmx = (2 * nk + 15) / 16, nzt = 64 * PIPE_ZW;
   const long gpt = cdiv(p.ng, nzt), pf = cdiv((long)p.n0 * p.n1, nzt);
-  if (nk <= 24 ? (gpt > 24 || pf > 12) : (gpt > 32 || pf > 16)) return false;
+  if (gpt > 14 || pf > 8) return false;
   f.ls = x2 + 1;
+  f.ssz = 16 * fmx * f.ls;
   f.wsz = 16 * fmx * 9;
   f.t2sz = f.nw * 288;
   f.g = f.pmax = 0;
-  f.lds = ((size_t)16 * fmx * f.ls + (size_t)f.nw * f.wsz + 2 * (size_t)f.t2sz + (size_t)p.n2 * p.kz) * sizeof(c32) +
-          (size_t)(nk <= 24 ? 24 : 32) * nzt * sizeof(uint32_t);
+  f.lds = ((size_t)4 * f.ssz + (size_t)2 * f.nw * f.wsz + 4 * (size_t)f.t2sz + (size_t)p.n2 * p.kz) * sizeof(c32) +
+          (size_t)14 * nzt * sizeof(uint32_t);
   return f.lds <= 160 * 1024;
 }
 
 template <int NK>
 static hipError_t pipe_kernel_launch(const DftPlan& p, PipeShape& f, const void* zt, void* part, size_t part_bytes,
                                      hipStream_t st) {
-  constexpr int FMX = (2 * NK + 15) / 16, GPT = NK <= 24 ? 24 : 32, PF = NK <= 24 ? 12 : 16;
+  constexpr int FMX = (2 * NK + 15) / 16, GPT = 14, PF = 8;
   const void* fn = reinterpret_cast<const void*>(&dft_pipe_kernel<FMX, NK, GPT, PF>);
   static bool attr_set[64] = {};
   int dev = 0;
