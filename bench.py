@@ -388,16 +388,19 @@ def solid_like(isdf, torch, dev, steps):
         out = plan.new_output()
         plan.eps_inv_async(psi, e_dev, out, ws)
         plan.sync()
+        plan.time_stages(True)   # stage boundaries as for the headline (HIP events on the library's stream)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
             plan.eps_inv_async(psi, e_dev, out, ws)
-        plan.sync()
+        rep = plan.sync()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
-        res[prec] = {"ms_per_build": round(dt * 1e3, 2), "builds_per_s": round(1.0 / dt, 3), "refine_steps": refine}
+        stages = [round(x, 3) for x in rep.stage_ms]
+        res[prec] = {"ms_per_build": round(dt * 1e3, 2), "builds_per_s": round(1.0 / dt, 3), "refine_steps": refine,
+                     "stage_ms": stages}
         outs[prec] = out[0].clone()
-        print(f"[bench] 64^3 {prec}: {dt * 1e3:.1f} ms/build", file=sys.stderr, flush=True)
+        print(f"[bench] 64^3 {prec}: {dt * 1e3:.1f} ms/build  stages(ms) {stages}", file=sys.stderr, flush=True)
         del plan, ws, out
     # the same build with the contour-integral core (Algorithm 2), direct calls (the
     # contour nodes come from the host energies; each call uploads and synchronises)
