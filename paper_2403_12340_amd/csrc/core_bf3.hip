@@ -33,11 +33,12 @@ __device__ __forceinline__ void split2(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);   // exact difference in FP32
 }
 
-// A planes: one thread per (row m, k tile); the source is complex64 or complex128
+// A planes: one thread per (row m, k tile); the source is complex64 or complex128.
+// With `copy`, the values also go to copy[k ld + m] as complex64.
 template <typename S>
 __global__ __launch_bounds__(256) void split_arows_kernel(const cx<S>* __restrict__ s, long ld, int M, int K,
                                                           float sgn, long mpad, bf8g* __restrict__ hi,
-                                                          bf8g* __restrict__ lo) {
+                                                          bf8g* __restrict__ lo, c32* __restrict__ copy) {
   const long m = (long)blockIdx.x * 256 + threadIdx.x;
   const int kt = blockIdx.y;
   if (m >= mpad) return;
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(256) void split_arows_kernel(const cx<S>* __restric
       const cx<S> v = s[(long)k * ld + m];
       vr = (float)v.re;
       vi = (float)v.im;
+      if (copy) copy[(long)k * ld + m] = c32{vr, vi};
     }
     __bf16 a, b, c, d;
     split2(vr, a, b);
@@ -85,7 +87,8 @@ __device__ __forceinline__ void herm_tile_bf3(int id, int& bm, int& bn) {
 // The structure of the single-precision core (core32.hip): for each occupied i,
 // G_i = B diag(w_i) B^H over the empty states j, with A(mu, j) = b_j(mu) (the same
 // for every i: split once into A planes) and B(j, nu) = w_ij conj(b_j(nu)) (split
-// while staged, from the FP64 samples and the weights); G_i accumulates in FP32 over
+// while staged, from a complex64 copy of the samples made with the A planes, and the
+// FP64 weights); G_i accumulates in FP32 over
 // the Nc terms and the rank-one factor conj(a_i(mu)) a_i(nu) is applied in FP64
 // registers after each i.  8 waves (4 x 2), each 32 rows x 64 real columns of a
 // 128 x 64 lower-triangle tile; the occupied index is split across workgroups and
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(CNT) void core_bf3_kernel(int nmu, int nv, int nc, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 3, wn = wave >> 2;
   const int li = lane & 15, g = lane >> 4, pp = li & 1;
-  const z64* pc = pm + (long)nv * nmu;                    // empty states at the points, [j][mu]
+  const c32* pc = reinterpret_cast<const c32*>(A + 2 * aplane);   // empty states at the points (complex64), [j][mu]
   const int nt = nc / KT;
   const int S = (i1 - i0) * nt;
   // A (pre-split planes): this thread's 16-byte chunk of the hi and of the lo plane
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(CNT) void core_bf3_kernel(int nmu, int nv, int nc, 
   const int bc = tid & 63, bp = tid >> 6;
   const int sb0 = swz(2 * bc, bp >> 1) + (bp & 1) * 8, sb1 = swz(2 * bc + 1, bp >> 1) + (bp & 1) * 8;
   u4g ra[2];
-  z64 rb[2];
+  c32 rb[2];
   double rw[2];
   auto gload = [&](int s) {
     const int i = i0 + s / nt, t = s % nt;
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(CNT) void core_bf3_kernel(int nmu, int nv, int nc, 
     __bf16 h0[4], l0[4], h1[4], l1[4];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const float br = (float)(rw[q] * rb[q].re), bi = (float)(-rw[q] * rb[q].im);
+      const float br = (float)(rw[q] * (double)rb[q].re), bi = (float)(-rw[q] * (double)rb[q].im);
       __bf16 rh, rl, ih, il, nh, nl;
       split2(br, rh, rl);
       split2(bi, ih, il);
@@ -249,15 +252,18 @@ __global__ __launch_bounds__(CNT) void core_bf3_kernel(int nmu, int nv, int nc, 
 
 bool core_bf3_fits(int nmu, int nc) { return nmu >= GBM && nmu % GBM == 0 && nc >= KT && nc % KT == 0; }
 
-size_t core_bf3_plane_bytes(int nmu, int nc) { return (size_t)2 * (nc / KT) * nmu * 64; }
+// the hi and lo planes, then a complex64 copy of the empty states at the points (the B
+// operand's source: half the bytes per k tile of the complex128 samples)
+size_t core_bf3_plane_bytes(int nmu, int nc) { return (size_t)2 * (nc / KT) * nmu * 64 + (size_t)nc * nmu * 8; }
 
 hipError_t core_bf3_split(int nmu, int nv, int nc, const void* pm, void* planes, hipStream_t st) {
   if (!core_bf3_fits(nmu, nc)) return hipErrorInvalidValue;
   const int kt = nc / KT;
   bf8g* hi = reinterpret_cast<bf8g*>(planes);
   bf8g* lo = hi + (long)kt * nmu * 4;
+  c32* copy = reinterpret_cast<c32*>(lo + (long)kt * nmu * 4);
   hipLaunchKernelGGL(split_arows_kernel<double>, dim3(cdiv(nmu, 256), kt), dim3(256), 0, st,
-                     (const z64*)pm + (long)nv * nmu, (long)nmu, nmu, nc, 1.f, (long)nmu, hi, lo);
+                     (const z64*)pm + (long)nv * nmu, (long)nmu, nmu, nc, 1.f, (long)nmu, hi, lo, copy);
   return hipGetLastError();
 }
 
