@@ -323,11 +323,12 @@ def batch_systems(isdf, torch, dev, n_omega, first):
             "frequency_builds_per_s": round(nb / dt_mgraph, 1)}
 
 
-def adjoint_timing(isdf, torch, dev, inp, psi, reps, fwd_ms):
-    """Wall time of the FP64 adjoint of Re tr(W eps~^-1) (one isdf_eps_inv_grad call:
-    recomputed forward, backward, gradients; it ends with a stream sync)."""
+def adjoint_timing(isdf, torch, dev, inp, psi, reps, fwd_ms, prec="fp64"):
+    """Wall time of the adjoint of Re tr(W eps~^-1) (one isdf_eps_inv_grad call:
+    recomputed forward, backward, gradients; it ends with a stream sync), in FP64 or
+    mixed (prec "fp32": the contractions over the grid and the points in FP32)."""
     import synth
-    prob = isdf.problem_for(inp, prec="fp64")
+    prob = isdf.problem_for(inp, prec=prec)
     w = torch.from_numpy(synth.loss_weight(inp.ng)).to(dev)
     nbytes = isdf.grad_workspace_bytes(prob, inp.nmu, inp.ng)
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
@@ -336,7 +337,7 @@ def adjoint_timing(isdf, torch, dev, inp, psi, reps, fwd_ms):
     for _ in range(reps):
         isdf.eps_inv_grad(psi, inp.energies, inp.mu_idx, inp.miller, prob, w, 0.0, workspace=ws)
     dt = (time.perf_counter() - t) / reps
-    print(f"[bench] adjoint {inp.n}^3: {dt * 1e3:.1f} ms per call", file=sys.stderr, flush=True)
+    print(f"[bench] adjoint {prec} {inp.n}^3: {dt * 1e3:.1f} ms per call", file=sys.stderr, flush=True)
     del ws, w
     return {"ms_per_call": round(dt * 1e3, 2), "ratio_to_fp64_forward": round(dt * 1e3 / fwd_ms, 2),
             "loss": "Re tr(W eps~^-1), W seeded Hermitian", "gradients": "dL/d eps_n, dL/d psi_n(r_mu)"}
@@ -444,6 +445,7 @@ def solid_like(isdf, torch, dev, steps):
                     "rel_fro_screening_rows": float(np.linalg.norm(d) / np.linalg.norm(g["eps_rows"] - eye_rows))}
     del outs, ref
     res["adjoint_fp64"] = adjoint_timing(isdf, torch, dev, inp, psi, 2, res["fp64"]["ms_per_build"])
+    res["adjoint_mixed"] = adjoint_timing(isdf, torch, dev, inp, psi, 2, res["fp64"]["ms_per_build"], "fp32")
     return {"workload": f"static eps~^-1, {inp.n}^3 grid, Nv={inp.nv}, Nc={inp.nc}, N_mu={inp.nmu}, NG={inp.ng}, "
                         "complex orbitals", "steps": steps, **res}
 
@@ -599,10 +601,11 @@ def main():
     if not args.no_batch_systems and args.omegas > 1 and args.only is None:
         batch = batch_systems(isdf, torch, dev, args.omegas, args.config)
 
-    adj = None
+    adj = adj_mixed = None
     cohsex = None
     if args.only is None:
         adj = adjoint_timing(isdf, torch, dev, inp, psi, 3, results["fp64"]["ms_per_step"])
+        adj_mixed = adjoint_timing(isdf, torch, dev, inp, psi, 3, results["fp64"]["ms_per_step"], "fp32")
         if not args.no_solid:
             cohsex = sigma_timing(isdf, torch, dev, inp, psi)
 
@@ -701,6 +704,7 @@ def main():
         "systems_batch": batch,
         "solid_like_64cubed": solid,
         "adjoint_fp64": adj,
+        "adjoint_mixed": adj_mixed,
         "cohsex_sigma": cohsex,
         "stress_lambda_max_10": stress,
         "roofline": roofline,

@@ -8,6 +8,7 @@
 // are bit-reproducible.
 #include "internal.h"
 #include "common.h"
+#include "kmajor.h"
 
 namespace isdf {
 
@@ -101,6 +102,166 @@ __global__ void adj_x_kernel(int n0, int n1, int n2, int kx, const z64* __restri
     acc.im += p.im;
   }
   gz[(long)mu * nr + r] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// The y and x stages of the adjoint DFT on FP64 MFMA, for lists with at most 32 x- and
+// y-frequencies and slabs of at most 64 x 64.  A workgroup of four waves walks an equal
+// run of (point, z-plane) slabs.  Per slab:
+//   y stage  T1 (y x a)   = CY (y x b) . T2F (b x a)
+//   x stage  slab (y x x) = T1 (y x a) . CX (a x x)
+// CY[y][b] = conj(twy[b][y]) and CX[a][x] = conj(twx[a][x]) stay in LDS for the whole
+// run; T2F is the slab's t2b values of the listed (a, b) pairs placed in a dense block
+// whose other entries are zero (set once: the pair set is the same on every slab).
+// Padding rows and columns of CY, CX are zero, so padded terms add exactly zero.  The
+// slab goes straight from the accumulators to gz.  Two barriers per slab: after the
+// T2F scatter (every wave is past the previous slab's x stage, so T1 is free), and
+// after T1 is written (every wave is past this slab's y stage, so T2F is free).
+// ---------------------------------------------------------------------------
+constexpr int AXY_NT = 256;
+constexpr int AXY_LD = 65;    // row stride (complex) of the y- and x-indexed arrays
+constexpr int AXY_LDA = 33;   // row stride of T2F (a-indexed)
+constexpr int AXY_KMAX = 32;  // x- and y-frequencies held
+constexpr int AXY_PF = 4;     // pairs per thread (nd <= kx ky <= 1024)
+
+size_t axy_lds_bytes(int kxp, int kyp) {
+  return sizeof(z64) * ((size_t)kyp * AXY_LD + (size_t)kyp * AXY_LDA + 2 * (size_t)kxp * AXY_LD);
+}
+
+// One 16-deep k block of the wave's FM x FN MFMAs: C += A B with A read k-major
+// (As[k][m], stride lda) and B k-major (Bs[k][n], stride ldb), complex128 on the
+// real block form (see tile.h).  Fragments with no live row or column are skipped
+// (wave-uniform).
+template <int FM, int FN>
+__device__ __forceinline__ void axy_step(const z64* __restrict__ As, int lda, const z64* __restrict__ Bs, int ldb,
+                                         d4 (&acc)[FM][FN], int wm0, int wn0, int mlim, int nlim, int lane) {
+  const double* Ar = reinterpret_cast<const double*>(As);
+  const double* Br = reinterpret_cast<const double*>(Bs);
+  const int i = lane & 15, q = lane >> 4;
+  const int bpart = ((q & 1) == (i & 1)) ? 0 : 1;
+  const double bsign = ((q & 1) == 1 && (i & 1) == 0) ? -1.0 : 1.0;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    const int k = 2 * kk + (q >> 1);
+    double a[FM], b[FN];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) a[fm] = Ar[(k * lda + wm0 + fm * 16 + i) * 2 + (q & 1)];
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) b[fn] = bsign * Br[(k * ldb + wn0 + fn * 8 + (i >> 1)) * 2 + bpart];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+        if (wm0 + fm * 16 < mlim && wn0 + fn * 8 < nlim)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(AXY_NT) void adj_xy_kernel(AdjDft p, int kxp, int kyp, long nslab_total, int g,
+                                                        const z64* __restrict__ t2b, z64* __restrict__ gz) {
+  extern __shared__ unsigned char lds_raw[];
+  z64* cy = reinterpret_cast<z64*>(lds_raw);   // [b][y]
+  z64* t2f = cy + kyp * AXY_LD;                // [b][a]
+  z64* t1 = t2f + kyp * AXY_LDA;               // [a][y]
+  z64* cxs = t1 + kxp * AXY_LD;                // [a][x]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const z64* twx = reinterpret_cast<const z64*>(p.twx);
+  const z64* twy = reinterpret_cast<const z64*>(p.twy);
+  for (int i = tid; i < kyp * AXY_LD; i += AXY_NT) {
+    const int b = i / AXY_LD, y = i % AXY_LD;
+    const bool ok = b < p.ky && y < p.n1;
+    const z64 v = twy[ok ? (long)b * p.n1 + y : 0];
+    cy[i] = z64{ok ? v.re : 0.0, ok ? -v.im : 0.0};
+  }
+  for (int i = tid; i < kxp * AXY_LD; i += AXY_NT) {
+    const int a = i / AXY_LD, x = i % AXY_LD;
+    const bool ok = a < p.kx && x < p.n0;
+    const z64 v = twx[ok ? (long)a * p.n0 + x : 0];
+    cxs[i] = z64{ok ? v.re : 0.0, ok ? -v.im : 0.0};
+    t1[i] = z64{0.0, 0.0};
+  }
+  for (int i = tid; i < kyp * AXY_LDA; i += AXY_NT) t2f[i] = z64{0.0, 0.0};
+  // this thread's pairs: LDS offset in T2F, or -1
+  int off[AXY_PF];
+#pragma unroll
+  for (int e = 0; e < AXY_PF; ++e) {
+    const int d = tid + e * AXY_NT;
+    off[e] = d < p.nd ? p.d_by[d] * AXY_LDA + p.d_ax[d] : -1;
+  }
+  const long s0 = nslab_total * blockIdx.x / g, s1 = nslab_total * (blockIdx.x + 1) / g;
+  const int nd = p.nd, n2 = p.n2;
+  // t2b offsets of this thread's pairs on slab s: (mu nd + d) n2 + z
+  long src[AXY_PF];
+#pragma unroll
+  for (int e = 0; e < AXY_PF; ++e) src[e] = tid + e * AXY_NT < nd ? (long)(tid + e * AXY_NT) * n2 : -1;
+  double pvr[AXY_PF], pvi[AXY_PF];   // split re / im keeps the prefetch in registers
+  if (s0 < s1) {
+    const long base = (s0 / n2) * nd * n2 + s0 % n2;
+#pragma unroll
+    for (int e = 0; e < AXY_PF; ++e) {
+      const z64 v = t2b[src[e] >= 0 ? base + src[e] : 0];
+      pvr[e] = v.re; pvi[e] = v.im;
+    }
+  }
+  const int rc = lane & 15, part = rc & 1;
+  const int wm0 = (wave & 1) * 32;
+  const int yn0 = (wave >> 1) * 16, xn0 = (wave >> 1) * 32;
+  const int n1p = (p.n1 + 15) & ~15;
+  const long nslab = (long)p.n0 * p.n1;
+  double* t1r = reinterpret_cast<double*>(t1);
+  double* gzr = reinterpret_cast<double*>(gz);
+  for (long s = s0; s < s1; ++s) {
+    if (s == s0) __syncthreads();   // the tables and zeros are in place
+#pragma unroll
+    for (int e = 0; e < AXY_PF; ++e)
+      if (off[e] >= 0) t2f[off[e]] = z64{pvr[e], pvi[e]};
+    if (s + 1 < s1) {   // the next slab's pairs, under this slab's MFMAs
+      const long base = ((s + 1) / n2) * nd * n2 + (s + 1) % n2;
+#pragma unroll
+      for (int e = 0; e < AXY_PF; ++e) {
+        const z64 v = t2b[src[e] >= 0 ? base + src[e] : 0];
+        pvr[e] = v.re; pvi[e] = v.im;
+      }
+    }
+    __syncthreads();
+    d4 acc1[2][2];
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 2; ++fn) acc1[fm][fn] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < kyp; kc += 16)
+      axy_step<2, 2>(cy + kc * AXY_LD, AXY_LD, t2f + kc * AXY_LDA, AXY_LDA, acc1, wm0, yn0, n1p, kxp, lane);
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int y = wm0 + fm * 16 + Mfma<double>::row(lane, v);
+          const int a = yn0 + fn * 8 + (rc >> 1);
+          if (a < kxp) t1r[(a * AXY_LD + y) * 2 + part] = acc1[fm][fn][v];
+        }
+    __syncthreads();
+    d4 acc2[2][4];
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn) acc2[fm][fn] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < kxp; kc += 16)
+      axy_step<2, 4>(t1 + kc * AXY_LD, AXY_LD, cxs + kc * AXY_LD, AXY_LD, acc2, wm0, xn0, n1p, p.n0, lane);
+    const int mu = (int)(s / p.n2), z = (int)(s % p.n2);
+    double* dst = gzr + ((long)mu * p.n2 + z) * nslab * 2;
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int y = wm0 + fm * 16 + Mfma<double>::row(lane, v);
+          const int x = xn0 + fn * 8 + (rc >> 1);
+          if (y < p.n1 && x < p.n0) dst[((long)y * p.n0 + x) * 2 + part] = acc2[fm][fn][v];
+        }
+  }
 }
 
 // cb[ii][v][j] = conj(a[i0 + ii][v]) b[j][v]   (a = pm rows 0..nv-1, b = rows nv..)
@@ -232,6 +393,23 @@ hipError_t adj_dft(const AdjDft& a, const void* gbar, void* t2b, void* t1b, void
                      a.gd_off, a.gd_list, a.g_cz, (const z64*)a.twz, a.sqrtv, (const z64*)gbar, (z64*)t2b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (a.kx <= AXY_KMAX && a.ky <= AXY_KMAX && a.n0 <= 64 && a.n1 <= 64 && a.nd <= AXY_PF * AXY_NT) {
+    const int kxp = (a.kx + 15) & ~15, kyp = (a.ky + 15) & ~15;
+    const size_t lds = axy_lds_bytes(kxp, kyp);
+    static bool attr_set[64] = {};  // once per device, for the largest tables
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64 || !attr_set[dev]) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_xy_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)axy_lds_bytes(AXY_KMAX, AXY_KMAX));
+      if (dev >= 0 && dev < 64) attr_set[dev] = true;
+    }
+    const long S = (long)a.nmu * a.n2;
+    const int g = (int)std::min<long>(S, cu_count());
+    hipLaunchKernelGGL(adj_xy_kernel, dim3(g), dim3(AXY_NT), lds, st, a, kxp, kyp, S, g, (const z64*)t2b, (z64*)gz);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(adj_y_kernel, dim3(cdiv((long)a.kx * a.n1 * a.n2, 256), a.nmu), dim3(256), 0, st, a.nd, a.n1,
                      a.n2, a.kx, a.da_off, a.da_list, a.d_by, (const z64*)a.twy, (const z64*)t2b, (z64*)t1b);
   e = hipGetLastError();

@@ -2335,7 +2335,16 @@ isdf_status enqueue_grad(Run& R, const GradLayout& G, const void* psi, double om
   HIPCHK(scale_z(B(G.s), B(G.sinv), n2, 1.0, st));
   HIPCHK(sweep_inverse(nmu, B(G.sinv), lin, status, st));   // -S^{-1}
   HIPCHK(scale_z(B(G.sinv), B(G.sinv), n2, -1.0, st));
-  TRY(stage_core(R, omega, B(G.m), B(G.minv), st));          // M, -M
+  if (R.grad_big == P32 && core32_fits(nmu, nc)) {
+    // mixed: the single-precision core of the forward (k-major engine, FP64 flush)
+    double* wts = at<double>(R.ws, L.w);
+    HIPCHK(pair_weights(R.e, nv, nc, omega, wts, st));
+    const int ns = core32_splits(nmu, nv, L.nsplit);
+    HIPCHK(core32_partial(nmu, nv, nc, pm, wts, B(L.part), ns, st));
+    HIPCHK(core_reduce(P32, nmu, B(L.part), ns, P.f, B(G.m), B(G.minv), st));
+  } else {
+    TRY(stage_core(R, omega, B(G.m), B(G.minv), st));        // M, -M
+  }
   HIPCHK(sweep_inverse(nmu, B(G.minv), lin, status, st));   // -(-M)^{-1} = M^{-1}
   // U = X S^{-1};  K = -(U^H U - M^{-1})^{-1}
   HIPCHK(gemm(P64, gd(ngg, nmu, nmu, B(L.zg), 1, ngg, false, B(G.sinv), nmu, 1, false, B(G.u), nmu), st));
@@ -2373,12 +2382,13 @@ isdf_status enqueue_grad(Run& R, const GradLayout& G, const void* psi, double om
     const int cn = std::min(chunk, nmu - c0);
     {
       AdjDft a;
-      a.n0 = P.n0; a.n1 = P.n1; a.n2 = P.n2; a.nmu = cn; a.ldg = nmu; a.kx = L.kx; a.nd = L.nd;
+      a.n0 = P.n0; a.n1 = P.n1; a.n2 = P.n2; a.nmu = cn; a.ldg = nmu; a.kx = L.kx; a.ky = L.ky; a.nd = L.nd;
       a.twx = B(L.twx); a.twy = B(L.twy); a.twz = B(L.twz);
       a.sqrtv = at<double>(R.ws, L.sqrtv);
       a.gd_off = csr; a.gd_list = csr + L.nd + 1; a.da_off = a.gd_list + ngg; a.da_list = a.da_off + L.kx + 1;
       // idx block: xl[kx] yl[ky] zl[kz] d_ax[nd] d_by[nd] g_d[ngg] g_cz[ngg] dmap
-      a.d_by = ib + L.kx + L.ky + L.kz + L.nd;
+      a.d_ax = ib + L.kx + L.ky + L.kz;
+      a.d_by = a.d_ax + L.nd;
       a.g_cz = ib + L.kx + L.ky + L.kz + 2 * L.nd + ngg;
       HIPCHK(adj_dft(a, B(G.gbar) + (size_t)c0 * 16, B(L.t2), B(G.t1b), B(L.zt), st));
     }
@@ -2408,7 +2418,7 @@ isdf_status enqueue_grad(Run& R, const GradLayout& G, const void* psi, double om
     HIPCHK(adj_core_pairs(pm, nmu, nv, nc, i0, nb, B(G.pa), st));
     GemmDesc d = gd(nmu, nc, nmu, B(G.r), nmu, 1, false, B(G.pa), nc, 1, false, B(G.pb), nc);
     d.batch = nb; d.bsa = 0; d.bsb = (long)nmu * nc; d.bsc = (long)nmu * nc;
-    HIPCHK(gemm(P64, d, st));
+    HIPCHK(gemm(R.grad_big, d, st));   // mixed: FP32 products over the N_mu points
     HIPCHK(adj_core_grads(B(G.pb), pm, at<double>(R.ws, L.w), nmu, nv, nc, i0, nb, P.f, ga_out, B(G.q), gb_out, st));
   }
   HIPCHK(adj_energy_grad(B(G.q), R.e, nv, nc, omega, ge, st));

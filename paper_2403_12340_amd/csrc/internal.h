@@ -162,13 +162,14 @@ hipError_t adj_herm_plus(const void* g, void* h, int n, hipStream_t st);        
 hipError_t adj_gather_cols(const void* src, long ld, const int* idx, int nv, int rows, void* out, hipStream_t st);
 // adjoint of the pruned DFT: gz[mu][r] = sum_g conj(F(g, r)) sqrtv[g] gbar[g][mu]
 struct AdjDft {
-  int n0 = 0, n1 = 0, n2 = 0, nmu = 0, kx = 0, nd = 0;   // nmu: columns of gbar transformed
+  int n0 = 0, n1 = 0, n2 = 0, nmu = 0, kx = 0, ky = 0, nd = 0;   // nmu: columns of gbar transformed
   long ldg = 0;                                          // gbar: [g][ldg] complex128
   const void* twx = nullptr; const void* twy = nullptr; const void* twz = nullptr;   // forward tables
   const double* sqrtv = nullptr;
   const int* gd_off = nullptr; const int* gd_list = nullptr;   // plane waves grouped by (x, y) pair
   const int* g_cz = nullptr;                                   // plane wave -> z-frequency index
   const int* da_off = nullptr; const int* da_list = nullptr;   // pairs grouped by x frequency
+  const int* d_ax = nullptr;                                   // pair -> x-frequency index
   const int* d_by = nullptr;                                   // pair -> y-frequency index
 };
 hipError_t adj_dft(const AdjDft& a, const void* gbar, void* t2b, void* t1b, void* gz, hipStream_t st);

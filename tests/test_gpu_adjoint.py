@@ -49,13 +49,15 @@ def test_grad_matches_oracle(name, omega):
     assert e_p <= 1e-8, e_p
 
 
-@pytest.mark.parametrize("name,omega", [("tiny", 0.0), ("cfg0", 0.0), ("mid", 0.02)])
+@pytest.mark.parametrize("name,omega", [("tiny", 0.0), ("cfg0", 0.0), ("mid", 0.02), ("core32", 0.0), ("core32", 0.03)])
 def test_grad_mixed_matches_oracle(name, omega):
-    """The mixed backward (ISDF_FP32: the contractions over the grid in FP32 on MFMA,
-    everything else FP64) against the FP64 oracle gradient.  Bar 1e-5 relative
-    Frobenius: those contractions sum up to Nr terms of products rounded to FP32
-    (u = 6e-8, error growing like sqrt(Nr) u ~ 5e-6 at 20^3), and the result passes
-    through S^{-1} and the SMW core (cond <= 2e2) only in FP64."""
+    """The mixed backward (ISDF_FP32: the contractions over the grid and over the
+    points in FP32 on MFMA, everything else FP64) against the FP64 oracle gradient.
+    Bar 1e-5 relative Frobenius: those contractions sum up to Nr terms of products
+    rounded to FP32 (u = 6e-8, error growing like sqrt(Nr) u ~ 5e-6 at 20^3), and the
+    result passes through S^{-1} and the SMW core (cond <= 2e2) only in FP64.  The
+    core32 case (256 points, 64 empty states) recomputes M with the single-precision
+    core of the forward pass (FP64 flush), as the larger systems do."""
     inp = synth.make_inputs(name)
     w = synth.loss_weight(inp.ng)
     print(f"[grad-mixed] case={name} omega={omega}", flush=True)
@@ -110,12 +112,13 @@ def _fd_check(inp, prob, omega, samples, energies_idx, tol):
     return lval
 
 
-@pytest.mark.parametrize("name,coulomb_sum", [("cfg0", 0), ("tiny", 1)])
+@pytest.mark.parametrize("name,coulomb_sum", [("cfg0", 0), ("tiny", 1), ("wide", 1)])
 def test_grad_matches_central_differences(name, coulomb_sum):
     """Backward against the derivative of this library's own FP64 forward (real
-    orbitals in cfg0; the whole-grid Gram in tiny, which the oracle gradient does
-    not cover).  Tolerance 1e-6 of the largest gradient entry: FD truncation
-    O(h^2) and roundoff O(eps / h) stay below that at these sizes."""
+    orbitals in cfg0; the whole-grid Gram in tiny and wide, which the oracle gradient
+    does not cover; wide's 33 x-frequencies take the plain adjoint y and x stages
+    instead of the matrix-core ones).  Tolerance 1e-6 of the largest gradient entry:
+    FD truncation O(h^2) and roundoff O(eps / h) stay below that at these sizes."""
     inp = synth.make_inputs(name)
     prob = isdf.problem_for(inp, "fp64", coulomb_sum=coulomb_sum)
     print(f"[grad-fd] case={name} coulomb_sum={coulomb_sum}", flush=True)
