@@ -264,7 +264,7 @@ def batch_systems(isdf, torch, dev, n_omega, first):
     """The 48^3 system plus eight uneven ones (24^3..40^3, Nv 16..48, Nc = 4 Nv,
     N_mu = 10 Nv, NG = 32 Nv), each with n_omega imaginary frequencies: one graph
     launch whose systems run concurrently (isdf_multi_graph_create: each system
-    captured on its own plan's stream, joined as child graphs), beside the same
+    captured on its own plan's stream, its nodes copied into one graph), beside the same
     systems as one eager multi-system call on concurrent streams and as one
     captured multi-system call with the systems in sequence on one stream."""
     import synth

@@ -297,10 +297,11 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
  * every buffer must stay allocated while the graph exists, and each system
  * needs its own workspace and output (ISDF_E_ARG otherwise).  Each plan's call
  * is captured on its own handle's stream (which must be a created stream, not
- * the null stream) and becomes a child graph of one parent graph, with no
- * dependencies between the children.  Capturing enqueues nothing; stage timing
- * is not recorded inside the graph.  Errors: ISDF_E_ARG, ISDF_E_WORKSPACE,
- * ISDF_E_DEVICE (a capture or instantiation error). */
+ * the null stream); the captured kernels and their dependencies are copied into
+ * one parent graph, with no dependencies between the systems (a capture holding
+ * other node kinds is added as a child graph instead).  Capturing enqueues
+ * nothing; stage timing is not recorded inside the graph.  Errors: ISDF_E_ARG,
+ * ISDF_E_WORKSPACE, ISDF_E_DEVICE (a capture, copy or instantiation error). */
 isdf_status isdf_multi_graph_create(int32_t count, const isdf_plan* plans, const void* const* psi,
                                     const double* const* energies, const double* const* omega,
                                     void* const* workspace, const size_t* ws_bytes,

@@ -655,7 +655,7 @@ def eps_inv_multi(plans, psis, energies_devs, outs, workspaces, omegas=None):
 
 class MultiGraph:
     """isdf_multi_graph_create: several plans' calls as one HIP graph whose systems run
-    concurrently (each captured on its own plan's stream, joined as child graphs).
+    concurrently (each captured on its own plan's stream, its kernels copied into one graph).
     The buffers are baked into the graph and kept alive by this object."""
 
     def __init__(self, plans, psis, energies_devs, outs, workspaces, omegas=None):

@@ -1988,7 +1988,7 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
   // capture through streams that themselves joined it (a nested fork); that form
   // is refused here.  Systems that should run concurrently inside one graph go
   // through isdf_multi_graph_create instead, which captures each system on its
-  // own and joins the captures as child graphs.
+  // own and copies the captured kernels into one graph.
   bool forks = false;
   for (int i = 0; i < count; ++i) forks = forks || plans[i]->h->stream != main;
   if (forks) {
@@ -2012,11 +2012,56 @@ isdf_status isdf_plan_eps_inv_multi(int32_t count, const isdf_plan* plans, const
   return ISDF_OK;
 }
 
-// ---- several systems as one graph of concurrent child graphs -----------------------------
+// ---- several systems as one graph ---------------------------------------------------------
+// Copies the nodes and edges of `child` into `parent` (no edges to the parent's other
+// nodes).  A child graph node runs its graph as one unit, and the HIP runtime runs the
+// child graph nodes of one launch one after another, while independent kernel nodes of
+// one graph run concurrently: so the captured systems are merged node by node.  Only
+// kernel and empty nodes are copied (what a plan call records).  Returns MERGE_OTHER,
+// with nothing added, if the graph holds anything else.
+enum MergeResult { MERGE_OK, MERGE_OTHER, MERGE_ERROR };
+static MergeResult merge_graph(hipGraph_t parent, hipGraph_t child) {
+  size_t n = 0;
+  if (hipGraphGetNodes(child, nullptr, &n) != hipSuccess) return MERGE_ERROR;
+  std::vector<hipGraphNode_t> nodes(n), copies(n);
+  if (n && hipGraphGetNodes(child, nodes.data(), &n) != hipSuccess) return MERGE_ERROR;
+  std::vector<hipKernelNodeParams> kp(n);
+  std::vector<char> is_kernel(n, 0);
+  for (size_t i = 0; i < n; ++i) {
+    hipGraphNodeType t;
+    if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess) return MERGE_ERROR;
+    if (t == hipGraphNodeTypeKernel) {
+      if (hipGraphKernelNodeGetParams(nodes[i], &kp[i]) != hipSuccess) return MERGE_ERROR;
+      is_kernel[i] = 1;
+    } else if (t != hipGraphNodeTypeEmpty) {
+      return MERGE_OTHER;
+    }
+  }
+  size_t ne = 0;
+  if (hipGraphGetEdges(child, nullptr, nullptr, &ne) != hipSuccess) return MERGE_ERROR;
+  std::vector<hipGraphNode_t> from(ne), to(ne);
+  if (ne && hipGraphGetEdges(child, from.data(), to.data(), &ne) != hipSuccess) return MERGE_ERROR;
+  for (size_t i = 0; i < n; ++i) {
+    const hipError_t e = is_kernel[i] ? hipGraphAddKernelNode(&copies[i], parent, nullptr, 0, &kp[i])
+                                      : hipGraphAddEmptyNode(&copies[i], parent, nullptr, 0);
+    if (e != hipSuccess) return MERGE_ERROR;
+  }
+  std::map<hipGraphNode_t, hipGraphNode_t> map;
+  for (size_t i = 0; i < n; ++i) map[nodes[i]] = copies[i];
+  for (size_t i = 0; i < ne; ++i) {
+    const auto fa = map.find(from[i]), fb = map.find(to[i]);
+    if (fa == map.end() || fb == map.end()) return MERGE_ERROR;
+    hipGraphNode_t a = fa->second, b = fb->second;
+    if (hipGraphAddDependencies(parent, &a, &b, 1) != hipSuccess) return MERGE_ERROR;
+  }
+  return MERGE_OK;
+}
+
 struct isdf_graph_s {
   int device = 0;
   std::vector<isdf_plan> plans;
   std::vector<hipGraph_t> children;
+  int merged = 0;   // systems copied node by node (the rest are child graphs)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -2056,8 +2101,9 @@ isdf_status isdf_multi_graph_create(int32_t count, const isdf_plan* plans, const
   if (hipGraphCreate(&g->graph, 0) != hipSuccess) return bail(fail(h0, ISDF_E_DEVICE, "hipGraphCreate failed"));
   for (int i = 0; i < count; ++i) {
     // Each system is captured on its own handle's stream (its second stream joins that
-    // capture directly), then added to the parent graph as a child with no
-    // dependencies, so the systems run concurrently when the graph is launched.
+    // capture directly), then its nodes and edges are copied into the parent graph with
+    // no dependencies on the other systems, so the systems run concurrently when the
+    // graph is launched.  A capture holding other node kinds goes in as a child graph.
     isdf_handle hi = plans[i]->h;
     hipStream_t s = hi->stream;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -2070,9 +2116,15 @@ isdf_status isdf_multi_graph_create(int32_t count, const isdf_plan* plans, const
     if (st != ISDF_OK) return bail(st);
     if (e != hipSuccess || !child)
       return bail(fail(hi, ISDF_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e)));
-    hipGraphNode_t node;
-    if (hipGraphAddChildGraphNode(&node, g->graph, nullptr, 0, child) != hipSuccess)
-      return bail(fail(hi, ISDF_E_DEVICE, "hipGraphAddChildGraphNode failed"));
+    const MergeResult m = merge_graph(g->graph, child);
+    if (m == MERGE_ERROR) return bail(fail(hi, ISDF_E_DEVICE, "copying the captured nodes into the graph failed"));
+    if (m == MERGE_OTHER) {
+      hipGraphNode_t node;
+      if (hipGraphAddChildGraphNode(&node, g->graph, nullptr, 0, child) != hipSuccess)
+        return bail(fail(hi, ISDF_E_DEVICE, "hipGraphAddChildGraphNode failed"));
+    } else {
+      ++g->merged;
+    }
     g->plans.push_back(plans[i]);
   }
   const hipError_t e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);

@@ -617,10 +617,10 @@ def test_multi_system_concurrent_graph():
 
 def test_multi_graph_runs_systems_concurrently():
     """isdf_multi_graph_create: each system captured on its own plan's stream, the
-    captures joined as child graphs of one graph with no dependencies between them.
-    Every replay (with eager calls and synchronisations in between) equals the
-    single-plan results bit for bit."""
-    print("[multi] child-graph launch", flush=True)
+    captured kernels and their dependencies copied into one graph with no
+    dependencies between the systems.  Every replay (with eager calls and
+    synchronisations in between) equals the single-plan results bit for bit."""
+    print("[multi] merged-graph launch", flush=True)
     plans, psis, es, wss, outs, refs = [], [], [], [], [], []
     for name in ["tiny", "mid", "kmaj"]:
         inp = get_inputs(name)
