@@ -576,14 +576,143 @@ __global__ __launch_bounds__(256) void dft_fused_kernel(DftPlan p, FusedShape f,
 // One barrier per step: the pair of step t staged and T2 of step t - 1 complete.  Slabs
 // and T2 are double buffered by step parity; T1 stays in a region private to each MFMA
 // wave.  The sums, the pieces and the twiddle padding follow dft_fused_kernel.
-constexpr int PIPE_ZW = 5;   // z-waves per workgroup
+// Roles of the z-waves: wave w runs on SIMD w % 4, and a z-wave on a SIMD that hosts
+// more MFMA waves than the others gets few issue cycles until those MFMA waves are done
+// (measured: its step's work ends about 3000 cycles after theirs).  Every z-wave stages
+// an equal share of the slabs; when the MFMA waves are spread unevenly only the z-waves
+// on the other SIMDs sum plane waves, otherwise every z-wave does.
+constexpr int PIPE_ZW = 6;   // z-waves per workgroup
+// register budgets of a z-wave: slab elements per thread and slab, plane waves per
+// summing thread
+constexpr int PIPE_PF = 6, PIPE_GPT = 16;
 struct PipeShape {
   int nw, nt, ls, ssz, wsz, t2sz, g, pmax;
+  unsigned sum_mask;   // summing z-waves (bit zi of wave 2 nw + zi)
   size_t lds;
 };
 
+// summing z-waves for nw MFMA waves per group (see above)
+static unsigned pipe_roles(int nw) {
+  int m[4] = {0, 0, 0, 0};
+  for (int w = 0; w < 2 * nw; ++w) ++m[w & 3];
+  const int mx = std::max(std::max(m[0], m[1]), std::max(m[2], m[3]));
+  const int mn = std::min(std::min(m[0], m[1]), std::min(m[2], m[3]));
+  unsigned mask = 0;
+  for (int zi = 0; zi < PIPE_ZW; ++zi)
+    if (mx == mn || m[(2 * nw + zi) & 3] < mx) mask |= 1u << zi;
+  return mask;
+}
+
+// One z-wave of the warp-specialised pass: it stages slabs (PFX elements per slab and
+// thread, thread st0 of nst), and with GPTX > 0 it sums plane waves (GPTX per thread,
+// thread zt0 of nzt).  Every z-wave passes the same barriers as the MFMA waves.
+template <int PFX, int GPTX>
+__device__ __forceinline__ void pipe_zwave(const DftPlan& p, const PipeShape& f, const c32* __restrict__ zt,
+                                           c32* __restrict__ out, c32* Ss, const c32* T2, const c32* Zs,
+                                           uint32_t* Gc, int s0, int s1, int nsteps, int nslab, int S, int st0,
+                                           int nst, int zt0, int nzt) {
+  const c32 zero{0.f, 0.f};
+  // this thread's plane waves g = zt0 + nzt j: T2 offset | z-frequency << 16, kept in LDS
+  // (read by this thread only); slots past the list hold code 0 (summed, never stored)
+  c32 zacc[GPTX > 0 ? GPTX : 1];
+#pragma unroll
+  for (int j = 0; j < GPTX; ++j) zacc[j] = zero;
+  if constexpr (GPTX > 0) {
+#pragma unroll 1
+    for (int j = 0; j < GPTX; ++j) {
+      const int g = zt0 + nzt * j;
+      uint32_t code = 0;
+      if (g < p.ng) {
+        const int d = p.g_d[g], a = p.d_ax[d];
+        code = (uint32_t)((a >> 3) * 288 + p.d_by[d] * 9 + (a & 7)) | ((uint32_t)p.g_cz[g] << 16);
+      }
+      Gc[j * nzt + zt0] = code;
+    }
+  }
+  const int r0 = st0 / p.n0, c0 = st0 % p.n0, dr = nst / p.n0, dc = nst % p.n0;
+  float pfr[2][PFX > 0 ? PFX : 1], pfi[2][PFX > 0 ? PFX : 1];
+  // the pair of step t into registers (slabs past the range are not read)
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int sl = s0 + 2 * t + k;
+      if (sl >= s1) continue;
+      const char* src = reinterpret_cast<const char*>(zt + (long)sl * nslab);
+#pragma unroll
+      for (int e = 0; e < PFX; ++e) {
+        const int i = st0 + nst * e;
+        const c32 v = *reinterpret_cast<const c32*>(src + (uint32_t)(i < nslab ? i : 0) * (uint32_t)sizeof(c32));
+        pfr[k][e] = v.re; pfi[k][e] = v.im;
+      }
+    }
+  };
+  auto store = [&](int t) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (s0 + 2 * t + k >= s1) continue;
+      c32* dst = Ss + ((t & 1) * 2 + k) * f.ssz;
+      int r = r0, c = c0;
+#pragma unroll
+      for (int e = 0; e < PFX; ++e) {
+        if (st0 + nst * e < nslab) dst[r * f.ls + c] = c32{pfr[k][e], pfi[k][e]};
+        r += dr; c += dc;
+        if (c >= p.n0) { c -= p.n0; ++r; }
+      }
+    }
+  };
+  if constexpr (PFX > 0) {
+    fetch(0);
+    store(0);
+    if (1 < nsteps) fetch(1);
+  }
+  for (int t = 0; t <= nsteps; ++t) {
+    __syncthreads();   // the pair of step t staged; T2 of step t - 1 complete
+    // the pair of step t + 1 (loaded during the previous step) into the other buffers,
+    // whose last reader was step t - 1; then the loads of the pair of step t + 2
+    if constexpr (PFX > 0) {
+      if (t + 1 < nsteps) store(t + 1);
+      if (t + 2 < nsteps) fetch(t + 2);
+    }
+    if (GPTX > 0 && t > 0) {
+#pragma unroll 1
+      for (int k = 0; k < 2; ++k) {
+        const int sp = s0 + 2 * (t - 1) + k;   // slab summed now
+        if (sp >= s1) break;
+        const c32* t2 = T2 + (((t - 1) & 1) * 2 + k) * f.t2sz;
+        const c32* zrow = Zs + (sp % p.n2) * p.kz;
+#pragma unroll
+        for (int j0 = 0; j0 < GPTX; j0 += 2) {
+          __builtin_amdgcn_sched_barrier(0);   // bounds the LDS reads in flight (register pressure)
+#pragma unroll
+          for (int j = j0; j < j0 + 2 && j < GPTX; ++j) {
+            const uint32_t code = Gc[j * nzt + zt0];
+            const c32 v = t2[code & 0xffffu], wz = zrow[code >> 16];
+            zacc[j].re += v.re * wz.re - v.im * wz.im;
+            zacc[j].im += v.re * wz.im + v.im * wz.re;
+          }
+        }
+        if (sp + 1 == s1 || (sp + 1) % p.n2 == 0) {   // the run of this point ends: store its piece
+          const int mu = sp / p.n2;
+          const int piece = (int)blockIdx.x - fused_owner((long)mu * p.n2, S, f.g);
+          c32* ob = out + ((long)mu * f.pmax + piece) * p.ng;
+          // one running index, opaque to the optimiser: no per-plane-wave index is
+          // hoisted out of the slab loop into a register of its own
+          int g = zt0;
+          asm volatile("" : "+v"(g));
+#pragma unroll
+          for (int j = 0; j < GPTX; ++j) {
+            if (g < p.ng) ob[g] = zacc[j];
+            zacc[j] = zero;
+            g += nzt;
+          }
+        }
+      }
+    }
+  }
+}
+
 template <int FMX, int NK, int GPT, int PF>
-__global__ __launch_bounds__(704) __attribute__((amdgpu_waves_per_eu(3))) void dft_pipe_kernel(DftPlan p, PipeShape f, const c32* __restrict__ zt,
+__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3))) void dft_pipe_kernel(DftPlan p, PipeShape f, const c32* __restrict__ zt,
                                                        c32* __restrict__ out) {
   constexpr int FMB = 2;   // b rows in two blocks of 16 (ky <= 32)
   extern __shared__ unsigned char lds_raw[];
@@ -686,99 +815,15 @@ __global__ __launch_bounds__(704) __attribute__((amdgpu_waves_per_eu(3))) void d
       }
     }
   } else {
-    // ---- z-waves
-    const int zt0 = tid - 128 * f.nw, nzt = 64 * PIPE_ZW;
-    // this thread's plane waves g = zt0 + nzt j: T2 offset | z-frequency << 16, kept in LDS
-    // (read by this thread only); slots past the list hold code 0 (summed, never stored)
-    c32 zacc[GPT];
-#pragma unroll
-    for (int j = 0; j < GPT; ++j) zacc[j] = zero;
-#pragma unroll 1
-    for (int j = 0; j < GPT; ++j) {
-      const int g = zt0 + nzt * j;
-      uint32_t code = 0;
-      if (g < p.ng) {
-        const int d = p.g_d[g], a = p.d_ax[d];
-        code = (uint32_t)((a >> 3) * 288 + p.d_by[d] * 9 + (a & 7)) | ((uint32_t)p.g_cz[g] << 16);
-      }
-      Gc[j * nzt + zt0] = code;
-    }
-    const int r0 = zt0 / p.n0, c0 = zt0 % p.n0, dr = nzt / p.n0, dc = nzt % p.n0;
-    float pfr[2][PF], pfi[2][PF];
-    // the pair of step t into registers (slabs past the range are not read)
-    auto fetch = [&](int t) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int sl = s0 + 2 * t + k;
-        if (sl >= s1) continue;
-        const char* src = reinterpret_cast<const char*>(zt + (long)sl * nslab);
-#pragma unroll
-        for (int e = 0; e < PF; ++e) {
-          const int i = zt0 + nzt * e;
-          const c32 v = *reinterpret_cast<const c32*>(src + (uint32_t)(i < nslab ? i : 0) * (uint32_t)sizeof(c32));
-          pfr[k][e] = v.re; pfi[k][e] = v.im;
-        }
-      }
-    };
-    auto store = [&](int t) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        if (s0 + 2 * t + k >= s1) continue;
-        c32* dst = Ss + ((t & 1) * 2 + k) * f.ssz;
-        int r = r0, c = c0;
-#pragma unroll
-        for (int e = 0; e < PF; ++e) {
-          if (zt0 + nzt * e < nslab) dst[r * f.ls + c] = c32{pfr[k][e], pfi[k][e]};
-          r += dr; c += dc;
-          if (c >= p.n0) { c -= p.n0; ++r; }
-        }
-      }
-    };
-    fetch(0);
-    store(0);
-    if (1 < nsteps) fetch(1);
-    for (int t = 0; t <= nsteps; ++t) {
-      __syncthreads();   // the pair of step t staged; T2 of step t - 1 complete
-      // the pair of step t + 1 (loaded during the previous step) into the other buffers,
-      // whose last reader was step t - 1; then the loads of the pair of step t + 2
-      if (t + 1 < nsteps) store(t + 1);
-      if (t + 2 < nsteps) fetch(t + 2);
-      if (t > 0) {
-#pragma unroll 1
-        for (int k = 0; k < 2; ++k) {
-          const int sp = s0 + 2 * (t - 1) + k;   // slab summed now
-          if (sp >= s1) break;
-          const c32* t2 = T2 + (((t - 1) & 1) * 2 + k) * f.t2sz;
-          const c32* zrow = Zs + (sp % p.n2) * p.kz;
-#pragma unroll
-          for (int j0 = 0; j0 < GPT; j0 += 2) {
-            __builtin_amdgcn_sched_barrier(0);   // bounds the LDS reads in flight (register pressure)
-#pragma unroll
-            for (int j = j0; j < j0 + 2 && j < GPT; ++j) {
-              const uint32_t code = Gc[j * nzt + zt0];
-              const c32 v = t2[code & 0xffffu], wz = zrow[code >> 16];
-              zacc[j].re += v.re * wz.re - v.im * wz.im;
-              zacc[j].im += v.re * wz.im + v.im * wz.re;
-            }
-          }
-          if (sp + 1 == s1 || (sp + 1) % p.n2 == 0) {   // the run of this point ends: store its piece
-            const int mu = sp / p.n2;
-            const int piece = (int)blockIdx.x - fused_owner((long)mu * p.n2, S, f.g);
-            c32* ob = out + ((long)mu * f.pmax + piece) * p.ng;
-            // one running index, opaque to the optimiser: no per-plane-wave index is
-            // hoisted out of the slab loop into a register of its own
-            int g = zt0;
-            asm volatile("" : "+v"(g));
-#pragma unroll
-            for (int j = 0; j < GPT; ++j) {
-              if (g < p.ng) ob[g] = zacc[j];
-              zacc[j] = zero;
-              g += nzt;
-            }
-          }
-        }
-      }
-    }
+    // ---- z-waves: the zi-th; its index among all z-threads (staging) and among the summing ones
+    const int zi = wave - 2 * f.nw;
+    const int st0 = 64 * zi + lane, nst = 64 * PIPE_ZW;
+    const int zt0 = 64 * __builtin_popcount(f.sum_mask & ((1u << zi) - 1u)) + lane,
+              nzt = 64 * __builtin_popcount(f.sum_mask);
+    if ((f.sum_mask >> zi) & 1u)
+      pipe_zwave<PF, GPT>(p, f, zt, out, Ss, T2, Zs, Gc, s0, s1, nsteps, nslab, S, st0, nst, zt0, nzt);
+    else
+      pipe_zwave<PF, 0>(p, f, zt, out, Ss, T2, Zs, Gc, s0, s1, nsteps, nslab, S, st0, nst, zt0, nzt);
   }
 }
 
@@ -841,6 +886,7 @@ static hipError_t fused_kernel_launch(const DftPlan& p, FusedShape& f, const voi
 }
 
 
+
 // even NK (K steps of both stages) and the register budgets of its instantiation
 static bool pipe_shape(const DftPlan& p, PipeShape& f, int& nk) {
   const int x2 = (p.n0 + 3) & ~3, y2 = (p.n1 + 3) & ~3;
@@ -850,23 +896,24 @@ static bool pipe_shape(const DftPlan& p, PipeShape& f, int& nk) {
   nk = x2 / 2;
   f.nw = (p.kx + 7) / 8;
   f.nt = 128 * f.nw + 64 * PIPE_ZW;
-  const int fmx = (2 * nk + 15) / 16, nzt = 64 * PIPE_ZW;
-  const long gpt = cdiv(p.ng, nzt), pf = cdiv((long)p.n0 * p.n1, nzt);
-  if (gpt > 14 || pf > 8) return false;
+  f.sum_mask = pipe_roles(f.nw);
+  const int fmx = (2 * nk + 15) / 16, nzt = 64 * __builtin_popcount(f.sum_mask);
+  const long gpt = cdiv(p.ng, nzt), pf = cdiv((long)p.n0 * p.n1, 64 * PIPE_ZW);
+  if (gpt > PIPE_GPT || pf > PIPE_PF) return false;
   f.ls = x2 + 1;
   f.ssz = 16 * fmx * f.ls;
   f.wsz = 16 * fmx * 9;
   f.t2sz = f.nw * 288;
   f.g = f.pmax = 0;
   f.lds = ((size_t)4 * f.ssz + (size_t)2 * f.nw * f.wsz + 4 * (size_t)f.t2sz + (size_t)p.n2 * p.kz) * sizeof(c32) +
-          (size_t)14 * nzt * sizeof(uint32_t);
+          (size_t)PIPE_GPT * nzt * sizeof(uint32_t);
   return f.lds <= 160 * 1024;
 }
 
 template <int NK>
 static hipError_t pipe_kernel_launch(const DftPlan& p, PipeShape& f, const void* zt, void* part, size_t part_bytes,
                                      hipStream_t st) {
-  constexpr int FMX = (2 * NK + 15) / 16, GPT = 14, PF = 8;
+  constexpr int FMX = (2 * NK + 15) / 16, GPT = PIPE_GPT, PF = PIPE_PF;
   const void* fn = reinterpret_cast<const void*>(&dft_pipe_kernel<FMX, NK, GPT, PF>);
   static bool attr_set[64] = {};
   int dev = 0;

@@ -73,6 +73,9 @@ CONFIGS = {
     # 32-aligned state counts on a 14^3 grid: the self-energy pair sets (occupied x all,
     # all x all) run the single-precision pair kernel's interior path with even K ranges.
     "sig_even": dict(n=14, nv=32, nc=32, nmu=192, ng=400, complex=True, seed=16),
+    # 3000 plane waves on a 20^3 grid: 17 or more x-frequencies, so the warp-specialised DFT
+    # runs three matrix-core waves per slab group, spread unevenly over the SIMDs.
+    "pipe3": dict(n=20, nv=12, nc=36, nmu=150, ng=3000, complex=True, seed=17),
     # Odd 33^3 grid above 32 points per axis (every grid vector in the Gram: two DFT x/y chunks).
     "wide": dict(n=33, nv=6, nc=18, nmu=60, ng=300, complex=True, seed=12),
     # Full rank: N_mu = Nv * Nc, where ISDF is exact.
