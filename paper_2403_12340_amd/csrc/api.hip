@@ -721,6 +721,18 @@ isdf_status stage_gram(Run& R, const Basis& b) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Prec cp = P.prec == P64 ? P64 : P32;
+  // Single precision with X^T stored [point][plane wave]: a [plane wave][point] copy in
+  // the Z^T region (free once the DFT has run) makes both operands of G = X^H X k-major,
+  // for the persistent engine; the rest of the region holds its split-tail slices.
+  char* xg = at<char>(R.ws, R.L.zt);
+  const size_t xbytes = up((size_t)P.ngg * P.nmu * 8);
+  if (P.m32 && b.sg == 1 && b.smu >= P.ngg && R.L.zt_bytes >= xbytes &&
+      gemm32_fits(P.nmu, P.nmu, P.ngg, xg, P.nmu, xg, P.nmu)) {
+    HIPCHK(transpose_c32(P.nmu, P.ngg, b.base, b.smu, xg, R.st));
+    HIPCHK(gemm32_kmajor(P.nmu, P.nmu, P.ngg, xg, P.nmu, true, xg, P.nmu, false, at<char>(R.ws, R.L.g), P.nmu, true,
+                         1.0, R.st, R.tune.wg_per_cu, xg + xbytes, R.L.zt_bytes - xbytes, 0.0));
+    return ISDF_OK;
+  }
   GemmDesc d;
   d.M = d.N = P.nmu; d.K = P.ngg;   // over the Gram's plane waves (the list, or the whole grid)
   d.A = b.base; d.sam = b.smu; d.sak = b.sg; d.conjA = true; d.a32 = P.m32;

@@ -3,6 +3,8 @@
 //   W^T = alpha T^T X^T            (plain: complex64 out)
 //   eps~^{-1} = I + alpha W X^H    (Hermitian: lower tiles only, complex128 out,
 //                                   upper triangle mirrored, real diagonal)
+//   X^H X                          (the Coulomb Gram, Hermitian with no identity,
+//                                   from a [plane wave][point] copy of X)
 // with X^T and W^T stored [point][plane wave].  One workgroup per CU walks its
 // XCD's contiguous share of the tiles (no inter-workgroup synchronisation) and
 // prefetches the next tile's first K tile under the current epilogue.  Only
@@ -71,7 +73,7 @@ __device__ __forceinline__ void tile_origin(int id, int ntj, int& m0, int& n0) {
 template <bool HERM, bool EVEN>
 __global__ __launch_bounds__(ZL::NT) __attribute__((amdgpu_waves_per_eu(2)))
 void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, const c32* B, long ldb,
-                   float sb, void* C, long ldc, float alpha, float* tail_ws) {
+                   float sb, void* C, long ldc, float alpha, float diag, float* tail_ws) {
   __shared__ float smem[2 * (ZL::AS + ZL::BS)];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave % ZL::WGM) * ZL::WTM, wn0 = (wave / ZL::WGM) * ZL::WTN;
@@ -141,7 +143,7 @@ void gemm32_kernel(int ntj, int total, int K, const c32* A, long lda, float sa, 
       if (gr < gc) continue;
       const float re = ts[(r * 65 + c) * 2], im = ts[(r * 65 + c) * 2 + 1];
       *reinterpret_cast<double2*>(o + ((long)gr * ldc + gc) * 2) =
-          gr == gc ? double2{1.0 + (double)re, 0.0} : double2{(double)re, (double)im};
+          gr == gc ? double2{(double)diag + (double)re, 0.0} : double2{(double)re, (double)im};
     }
     for (int e = tid; e < ZL::BM * ZL::BN; e += ZL::NT) {   // mirror: output row gc, contiguous along gr
       const int c = e / ZL::BM, r = e % ZL::BM, gr = m0 + r, gc = n0 + c;
@@ -189,7 +191,7 @@ constexpr int TAIL_CHUNKS = ZL::BM * ZL::BN / 512;
 
 template <bool HERM>
 __global__ __launch_bounds__(256) void gemm32_tail_kernel(int ntj, int total, int nper, int nt, const float* tail_ws,
-                                                          void* C, long ldc, float alpha) {
+                                                          void* C, long ldc, float alpha, float diag) {
   const int xcd = blockIdx.x, t = blockIdx.y;
   const TailPlan tp = tail_plan(xcd, total, nper, nt, true);
   if (t >= tp.ntail) return;
@@ -214,9 +216,33 @@ __global__ __launch_bounds__(256) void gemm32_tail_kernel(int ntj, int total, in
     double* o = reinterpret_cast<double*>(C);
     if (gr < gc) continue;
     *reinterpret_cast<double2*>(o + ((long)gr * ldc + gc) * 2) =
-        gr == gc ? double2{1.0 + (double)re, 0.0} : double2{(double)re, (double)im};
+        gr == gc ? double2{(double)diag + (double)re, 0.0} : double2{(double)re, (double)im};
     if (gr > gc) *reinterpret_cast<double2*>(o + ((long)gc * ldc + gr) * 2) = double2{(double)re, -(double)im};
   }
+}
+
+// dst[c][r] = src[r * lds + c] for r < rows, c < cols (complex64), through 32 x 32 LDS tiles
+__global__ __launch_bounds__(256) void transpose_c32_kernel(int rows, int cols, const c32* __restrict__ src, long lds,
+                                                            c32* __restrict__ dst) {
+  __shared__ c32 t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) t[k][tx] = src[(long)r * lds + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) dst[(long)c * rows + r] = t[tx][k];
+  }
+}
+
+hipError_t transpose_c32(int rows, int cols, const void* src, long lds, void* dst, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_c32_kernel, dim3(cdiv(cols, 32), cdiv(rows, 32)), dim3(256), 0, st, rows, cols,
+                     (const c32*)src, lds, (c32*)dst);
+  return hipGetLastError();
 }
 
 size_t gemm32_tail_bytes(int wg_per_cu) {
@@ -233,13 +259,18 @@ bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, lo
 
 hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conjA, const void* B, long ldb,
                          bool conjB, void* C, long ldc, bool herm_identity, double alpha, hipStream_t st,
-                         int wg_per_cu, void* tail_ws, size_t tail_bytes) {
+                         int wg_per_cu, void* tail_ws, size_t tail_bytes, double diag) {
   if (!gemm32_fits(M, N, K, A, lda, B, ldb) || (herm_identity && M != N)) return hipErrorNotSupported;
   const int nti = M / ZL::BM, ntj = N / ZL::BN;
   const int total = herm_identity ? nti * (nti + 1) : nti * ntj;
   if (total == 0) return hipSuccess;
   const int wpc = std::max(1, std::min(wg_per_cu, 4));
-  const int g = std::max(8, std::min(8 * ((wpc * cu_count() + 7) / 8), 8 * (int)cdiv(total, 8)));
+  const int gfull = 8 * ((wpc * cu_count() + 7) / 8);
+  // fewer tiles than workgroups: one round, its tiles cut along K over the whole grid
+  // when the scratch holds every slice (a long-K product such as the Coulomb Gram);
+  // otherwise one workgroup per tile
+  const bool cut_all = total < gfull && tail_ws && tail_bytes >= (size_t)gfull * ZL::BM * ZL::BN * 2 * sizeof(float);
+  const int g = cut_all ? gfull : std::max(8, std::min(gfull, 8 * (int)cdiv(total, 8)));
   const float sa = conjA ? -1.f : 1.f, sb = conjB ? -1.f : 1.f;
   const int nper = g / 8, nt = K / ZL::BK;
   // the split tail only with scratch for every workgroup's slice
@@ -250,23 +281,24 @@ hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conj
   if (!any_tail) ws = nullptr;
   if (herm_identity)
     hipLaunchKernelGGL((gemm32_kernel<true, false>), dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A,
-                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
+                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, (float)diag, ws);
   else if (nt % 2 == 0)
     hipLaunchKernelGGL((gemm32_kernel<false, true>), dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A,
-                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
+                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, (float)diag, ws);
   else
     hipLaunchKernelGGL((gemm32_kernel<false, false>), dim3(g), dim3(ZL::NT), 0, st, ntj, total, K, (const c32*)A,
-                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, ws);
+                       lda, sa, (const c32*)B, ldb, sb, C, ldc, (float)alpha, (float)diag, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !ws) return e;
   int max_tail = 0;
   for (int x = 0; x < 8; ++x) max_tail = std::max(max_tail, tail_plan(x, total, nper, nt, true).ntail);
   const dim3 tg(8, max_tail, TAIL_CHUNKS);
   if (herm_identity)
-    hipLaunchKernelGGL(gemm32_tail_kernel<true>, tg, dim3(256), 0, st, ntj, total, nper, nt, ws, C, ldc, (float)alpha);
+    hipLaunchKernelGGL(gemm32_tail_kernel<true>, tg, dim3(256), 0, st, ntj, total, nper, nt, ws, C, ldc, (float)alpha,
+                       (float)diag);
   else
     hipLaunchKernelGGL(gemm32_tail_kernel<false>, tg, dim3(256), 0, st, ntj, total, nper, nt, ws, C, ldc,
-                       (float)alpha);
+                       (float)alpha, (float)diag);
   return hipGetLastError();
 }
 

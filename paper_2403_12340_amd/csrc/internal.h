@@ -34,13 +34,15 @@ hipError_t gemm(Prec compute, const GemmDesc& d, hipStream_t st);
 // otherwise hipErrorNotSupported and nothing is launched):
 //   A(m, k) = A[k lda + m], B(k, n) = B[k ldb + n] (complex64, optionally conjugated)
 //   herm_identity = false: C[m][n] = alpha (A B)[m][n], complex64, ldc
-//   herm_identity = true (M = N): C = I + alpha A B, complex128, lower triangle
+//   herm_identity = true (M = N): C = diag I + alpha A B, complex128, lower triangle
 //     computed and mirrored (the product must be Hermitian), diagonal real
 // tail_ws (optional, tail_bytes >= gemm32_tail_bytes(wg_per_cu)): scratch for the
 // K slices of the tiles left over after whole rounds (see gemm32.hip)
 hipError_t gemm32_kmajor(int M, int N, int K, const void* A, long lda, bool conjA, const void* B, long ldb,
                          bool conjB, void* C, long ldc, bool herm_identity, double alpha, hipStream_t st,
-                         int wg_per_cu = 1, void* tail_ws = nullptr, size_t tail_bytes = 0);
+                         int wg_per_cu = 1, void* tail_ws = nullptr, size_t tail_bytes = 0, double diag = 1.0);
+// dst[c][r] = src[r lds + c] (complex64, rows x cols in, cols x rows out)
+hipError_t transpose_c32(int rows, int cols, const void* src, long lds, void* dst, hipStream_t st);
 size_t gemm32_tail_bytes(int wg_per_cu);
 bool gemm32_fits(int M, int N, int K, const void* A, long lda, const void* B, long ldb);
 
