@@ -870,12 +870,12 @@ isdf_status refine_inverse(Run& R, const void* Hc, const void* Tfirst, double tn
     HIPCHK(frob2(Rr, n2, R.sb->partial, &R.sb->res[k], R.st));
     if (k == P.refine) break;
     HIPCHK(convert_z(T, false, T2, false, n2, R.st));
-    GemmDesc c;  // T2 = T + T Rr
-    c.M = c.N = c.K = n;
+    GemmDesc c;  // T2 = T + T Rr: the correction is ||Rr|| times smaller than T, so its
+    c.M = c.N = c.K = n;   // product runs on FP32 MFMA (FP64 storage and accumulation into T)
     c.A = T; c.sam = n; c.sak = 1;
     c.B = Rr; c.sbk = n; c.sbn = 1;
     c.C = T2; c.ldc = n; c.beta = 1.0;
-    HIPCHK(gemm(P64, c, R.st));
+    HIPCHK(gemm(P32, c, R.st));
     std::swap(T, T2);
   }
   R.tmat = T;
