@@ -618,13 +618,22 @@ __device__ __forceinline__ void pipe_zwave(const DftPlan& p, const PipeShape& f,
 #pragma unroll
   for (int j = 0; j < GPTX; ++j) zacc[j] = zero;
   if constexpr (GPTX > 0) {
-#pragma unroll 1
+    // two rounds of independent loads (the pairs and z-frequencies of all the thread's
+    // plane waves, then the pairs' x and y indices) instead of a dependent chain per
+    // plane wave
+    int dj[GPTX], cz[GPTX];
+#pragma unroll
     for (int j = 0; j < GPTX; ++j) {
       const int g = zt0 + nzt * j;
+      dj[j] = g < p.ng ? p.g_d[g] : -1;
+      cz[j] = g < p.ng ? p.g_cz[g] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < GPTX; ++j) {
       uint32_t code = 0;
-      if (g < p.ng) {
-        const int d = p.g_d[g], a = p.d_ax[d];
-        code = (uint32_t)((a >> 3) * 288 + p.d_by[d] * 9 + (a & 7)) | ((uint32_t)p.g_cz[g] << 16);
+      if (dj[j] >= 0) {
+        const int a = p.d_ax[dj[j]];
+        code = (uint32_t)((a >> 3) * 288 + p.d_by[dj[j]] * 9 + (a & 7)) | ((uint32_t)cz[j] << 16);
       }
       Gc[j * nzt + zt0] = code;
     }
