@@ -59,11 +59,18 @@ __device__ __forceinline__ void kloop_xx(cx<T>* smem, const cx<S>* A, long lda, 
 template <typename T, typename S, typename SO, class TL>
 __global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int ns, int b0, const cx<S>* pm,
                                                        long ldp, const cx<S>* b, long ldb, SO* out,
-                                                       long ldo, int ntm, int total) {
+                                                       long ldo, int ntm, int total, int herm) {
   __shared__ cx<T> smem[2 * (TL::AS + TL::BS)];
   const int id = xcd_remap(blockIdx.x, total);
   if (id >= total) return;
-  const int bm = id % ntm, bn = id / ntm;
+  int bm = id % ntm, bn = id / ntm;
+  if (herm) {   // Hermitian output (b = pm): lower-triangle tiles bn <= bm, row-major
+    int r = (int)((sqrt(8.0 * id + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > id) --r;
+    while ((r + 1) * (r + 2) / 2 <= id) ++r;
+    bm = r;
+    bn = id - r * (r + 1) / 2;
+  }
   const int m0 = bm * TL::BM, n0 = bn * TL::BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave % TL::WGM) * TL::WTM, wn0 = (wave / TL::WGM) * TL::WTN;
@@ -88,7 +95,10 @@ __global__ __launch_bounds__(TL::NT) void zpair_kernel(int M, int N, int nv, int
         const T val = part == 0 ? (po * qo + px * qx) : (px * qo - po * qx);
         const int row = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, v);
         const int col = n0 + wn0 + fn * 8 + (rc >> 1);
-        if (row < M && col < N) out[((long)row * ldo + col) * 2 + part] = (SO)val;
+        if (row < M && col < N) {
+          out[((long)row * ldo + col) * 2 + part] = (SO)val;
+          if (herm && bm != bn) out[((long)col * ldo + row) * 2 + part] = (SO)(part ? -val : val);   // mirrored
+        }
       }
 }
 
@@ -322,6 +332,11 @@ static hipError_t zpair32_launch(int M, int N, int nv, int ns, int b0, const voi
 }
 
 typedef Tile<double, 64, 64, 16, 2, 2> TZ64;
+// Small FP64 products (fewer 64 x 64 tiles than CUs, e.g. S at the points): 32 x 32
+// tiles, four times the workgroups, each light enough to share a CU with a
+// compute-bound kernel on another stream.  The k order per output element is that
+// of the 64 x 64 tile, so the results are the same.
+typedef Tile<double, 32, 32, 16, 2, 2> TZ64S;
 
 // FP64 pair kernel on the grid, persistent: one workgroup per slot walks its XCD's
 // contiguous share of the 64 x 64 tiles in point-fastest order (consecutive tiles
@@ -415,13 +430,13 @@ __global__ __launch_bounds__(TZ64P::NT, 1) void zpair64_kernel(int nv, int ns, i
 
 template <typename T, typename S, typename SO, class TL>
 static hipError_t zpair_launch(int M, int N, int nv, int ns, int b0, const void* pm, long ldp, const void* b,
-                               long ldb, void* out, long ldo, hipStream_t st) {
+                               long ldb, void* out, long ldo, hipStream_t st, bool herm = false) {
   const int ntm = (int)cdiv(M, TL::BM), ntn = (int)cdiv(N, TL::BN);
-  const int total = ntm * ntn;
+  const int total = herm ? ntm * (ntm + 1) / 2 : ntm * ntn;
   if (total == 0) return hipSuccess;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
   hipLaunchKernelGGL((zpair_kernel<T, S, SO, TL>), dim3(grid), dim3(TL::NT), 0, st, M, N, nv, ns, b0,
-                     (const cx<S>*)pm, ldp, (const cx<S>*)b, ldb, (SO*)out, ldo, ntm, total);
+                     (const cx<S>*)pm, ldp, (const cx<S>*)b, ldb, (SO*)out, ldo, ntm, total, herm ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -440,7 +455,11 @@ hipError_t zpair(Prec compute, int M, int N, int nv, int ns, const void* pm, lon
                          (const z64*)b, ldb, (z64*)out, ldo, nti, (int)total);
       return hipGetLastError();
     }
-    return zpair_launch<double, double, double, TZ64>(M, N, nv, ns, b0, pm, ldp, b, ldb, out, ldo, st);
+    // the same operands on both sides (S at the points): Hermitian, lower tiles only
+    const bool herm = pm == b && M == N && ldp == ldb;
+    if (cdiv(M, TZ64::BM) * cdiv(N, TZ64::BN) < cu_count())
+      return zpair_launch<double, double, double, TZ64S>(M, N, nv, ns, b0, pm, ldp, b, ldb, out, ldo, st, herm);
+    return zpair_launch<double, double, double, TZ64>(M, N, nv, ns, b0, pm, ldp, b, ldb, out, ldo, st, herm);
   }
   // single precision: complex64 points, complex128 orbitals (rounded as staged), complex64 output
   if (!in32 || !out32) return hipErrorInvalidValue;
