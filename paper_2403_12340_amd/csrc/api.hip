@@ -44,7 +44,7 @@ struct isdf_handle_s {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t ev[10] = {};         // stage timing (main stream)
-  hipEvent_t fork = nullptr, join = nullptr, core0 = nullptr, zdone = nullptr, zops = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, core0 = nullptr, zdone = nullptr, zops = nullptr, tabs = nullptr;
   hipEvent_t mfork = nullptr, mdone = nullptr;  // multi-system calls
   hipEvent_t m_ready[2] = {}, m_used[2] = {};
   std::string err;
@@ -673,21 +673,23 @@ isdf_status dft_apply(Run& R, const DftPlan& p, const void* zt, void* t2, size_t
 
 // Unitary DFT of the N_mu rows of Z^T on the plane-wave list.  With scaled = true the
 // result is X^T = (V^{1/2} F Z)^T, [mu][g] in the zg buffer.
-isdf_status dft_tables(Run& R) {
+isdf_status dft_tables(Run& R, hipStream_t st) {
   isdf_handle h = R.h;
   const Problem& P = R.P;
   const Layout& L = R.L;
   const int* ib = R.idx;
-  HIPCHK(coulomb_sqrt(R.miller, P.ngg, R.recip, P.v_scale, at<double>(R.ws, L.sqrtv), R.st));
-  HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), R.st));
-  HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), R.st));
-  HIPCHK(dft_twiddles(ib + L.kx + L.ky, L.kz, P.n2, P.m32, at<char>(R.ws, L.twz), R.st));
+  HIPCHK(coulomb_sqrt(R.miller, P.ngg, R.recip, P.v_scale, at<double>(R.ws, L.sqrtv), st));
+  HIPCHK(dft_twiddles(ib, L.kx, P.n0, P.m32, at<char>(R.ws, L.twx), st));
+  HIPCHK(dft_twiddles(ib + L.kx, L.ky, P.n1, P.m32, at<char>(R.ws, L.twy), st));
+  HIPCHK(dft_twiddles(ib + L.kx + L.ky, L.kz, P.n2, P.m32, at<char>(R.ws, L.twz), st));
   return ISDF_OK;
 }
+isdf_status dft_tables(Run& R) { return dft_tables(R, R.st); }
 
-isdf_status stage_dft(Run& R, bool scaled) {
+// tables: false when the caller has already enqueued dft_tables (and ordered them before this)
+isdf_status stage_dft(Run& R, bool scaled, bool tables = true) {
   const Layout& L = R.L;
-  TRY(dft_tables(R));
+  if (tables) TRY(dft_tables(R));
   DftPlan p = make_plan(R);
   const double* scale = scaled ? at<double>(R.ws, L.sqrtv) : nullptr;
   return dft_apply(R, p, at<char>(R.ws, L.zt), at<char>(R.ws, L.t2), L.t2_bytes, at<char>(R.ws, L.zg), scale);
@@ -890,10 +892,9 @@ isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   const int n = P.nmu;
   const long n2 = (long)n * n;
   void* H = at<char>(R.ws, L.a);
-  HIPCHK(axpby(at<char>(R.ws, L.g), 1.0, Mi, -1.0, H, n2, R.st));                   // H = G - K
+  // H = G - K, with ||H||_F^2 and its smallest diagonal entry for the status block
+  HIPCHK(form_h(at<char>(R.ws, L.g), Mi, H, n, R.sb->partial, &R.sb->h2, &R.sb->min_pivot, R.st));
   if (used) HIPCHK(hipEventRecord(used, R.st));
-  HIPCHK(diag_min(H, n, &R.sb->min_pivot, R.st));
-  HIPCHK(frob2(H, n2, R.sb->partial, &R.sb->h2, R.st));
   if (P.refine > 0) HIPCHK(convert_z(H, false, at<char>(R.ws, L.acopy), false, n2, R.st));
   HIPCHK(sweep_inverse(n, H, at<char>(R.ws, L.lin), &R.sb->status, R.st));          // -T
   HIPCHK(frob2(H, n2, R.sb->partial, &R.sb->t2, R.st));
@@ -1200,6 +1201,9 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   // the pair kernel's operand pass (streaming, memory-bound) beside the first core
   TRY(stage_z_operands(R, side));
   HIPCHK(hipEventRecord(h->zops, side));
+  // the DFT's tables too (a few small launches that would otherwise sit between Z and the DFT)
+  TRY(dft_tables(R, side));
+  HIPCHK(hipEventRecord(h->tabs, side));
   if (!core_side) {
     TRY(stage_core(R, n_omega ? omega[0] : 0.0, nullptr, mbuf[0], R.st));
     HIPCHK(hipEventRecord(h->core0, R.st));
@@ -1218,7 +1222,8 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   }
   if (nw > 1) TRY(side_core(1));
   tm.mark();
-  TRY(stage_dft(R, true));
+  HIPCHK(hipStreamWaitEvent(R.st, h->tabs, 0));
+  TRY(stage_dft(R, true, false));
   tm.mark();
   const Basis xb{at<char>(R.ws, R.L.zg), 1, (long)R.P.ngg};
   TRY(stage_gram(R, xb));
@@ -1464,8 +1469,8 @@ isdf_status isdf_create(isdf_handle* out, int device, void* stream) {
   if (scratch_setup(device) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
-  for (hipEvent_t* e : {&h->fork, &h->join, &h->core0, &h->zdone, &h->zops, &h->mfork, &h->mdone, &h->m_ready[0], &h->m_ready[1],
-                        &h->m_used[0], &h->m_used[1]})
+  for (hipEvent_t* e : {&h->fork, &h->join, &h->core0, &h->zdone, &h->zops, &h->tabs, &h->mfork, &h->mdone, &h->m_ready[0],
+                        &h->m_ready[1], &h->m_used[0], &h->m_used[1]})
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
   // default priority, non-blocking with respect to the legacy default stream
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { delete h; return ISDF_E_DEVICE; }
@@ -1486,8 +1491,8 @@ isdf_status isdf_destroy(isdf_handle h) {
     (void)hipStreamDestroy(h->side);
   }
   for (auto& e : h->ev) if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {h->fork, h->join, h->core0, h->zdone, h->zops, h->mfork, h->mdone, h->m_ready[0], h->m_ready[1], h->m_used[0],
-                       h->m_used[1]})
+  for (hipEvent_t e : {h->fork, h->join, h->core0, h->zdone, h->zops, h->tabs, h->mfork, h->mdone, h->m_ready[0], h->m_ready[1],
+                       h->m_used[0], h->m_used[1]})
     if (e) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;

@@ -189,6 +189,9 @@ hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStre
 // out[0] += ||a||_F^2 over count complex128, deterministic (single pass of block partials)
 hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st);
 hipError_t diag_min(const void* a, int n, double* out, hipStream_t st, int batch = 1);
+// H = G - K (n x n complex128), ||H||_F^2 into h2 and min Re diag(H) into hmin; partial: >= 1024 doubles
+hipError_t form_h(const void* G, const void* K, void* H, int n, double* partial, double* h2, double* hmin,
+                  hipStream_t st);
 // H[b] = G - K[b] for b < batch (complex128, n2 elements each)
 hipError_t sub_bcast(const void* G, const void* K, void* H, long n2, int batch, hipStream_t st);
 

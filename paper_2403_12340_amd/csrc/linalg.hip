@@ -466,6 +466,73 @@ hipError_t diag_min(const void* a, int n, double* out, hipStream_t st, int batch
   return hipGetLastError();
 }
 
+// H = G - K (n x n complex128) with the two checks of H made before its inversion,
+// in one pass: per-block partial sums of |H|^2 (partial[b]) and minima of its real
+// diagonal (partial[FH_MAXB + b]); form_h_finish_kernel combines them in fixed order.
+constexpr int FH_MAXB = 512;
+__global__ __launch_bounds__(256) void form_h_kernel(const double* G, const double* K, double* H, int n,
+                                                     long count2, double* partial) {
+  __shared__ double rs[256], rm[256];
+  double s = 0.0, m = 1e300;
+  const long step = (long)n + 1;   // diagonal entry r sits at complex index r (n + 1)
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count2; i += (long)gridDim.x * 256) {
+    const double h = G[i] - K[i];
+    H[i] = h;
+    s += h * h;
+    if ((i & 1) == 0 && (i >> 1) % step == 0) m = fmin(m, h);
+  }
+  rs[threadIdx.x] = s;
+  rm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rm[threadIdx.x] = fmin(rm[threadIdx.x], rm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = rs[0];
+    partial[FH_MAXB + blockIdx.x] = rm[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void form_h_finish_kernel(const double* partial, int nb, double* h2,
+                                                            double* hmin) {
+  __shared__ double rs[256], rm[256];
+  double s = 0.0, m = 1e300;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    s += partial[i];
+    m = fmin(m, partial[FH_MAXB + i]);
+  }
+  rs[threadIdx.x] = s;
+  rm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rm[threadIdx.x] = fmin(rm[threadIdx.x], rm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *h2 = rs[0];
+    *hmin = rm[0];
+  }
+}
+
+hipError_t form_h(const void* G, const void* K, void* H, int n, double* partial, double* h2, double* hmin,
+                  hipStream_t st) {
+  const long c2 = 2L * n * n;
+  int nb = (int)cdiv(c2, 256);
+  if (nb > FH_MAXB) nb = FH_MAXB;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(form_h_kernel, dim3(nb), dim3(256), 0, st, (const double*)G, (const double*)K, (double*)H, n,
+                     c2, partial);
+  hipLaunchKernelGGL(form_h_finish_kernel, dim3(1), dim3(256), 0, st, (const double*)partial, nb, h2, hmin);
+  return hipGetLastError();
+}
+
 // H[b] = G - K[b] (complex128 as 2 n2 doubles per item)
 __global__ void sub_bcast_kernel(const double* G, const double* K, double* H, long n2x2) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
