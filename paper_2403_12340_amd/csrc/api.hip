@@ -541,6 +541,7 @@ struct Run {
   int cn = 0;                  // contour nodes in the table (core_method 1)
   double talpha = 1.0;
   Prec grad_big = P64;         // adjoint: compute precision of the contractions over the grid
+  bool gap_side = false;       // the energy-gap check still to enqueue, on the second stream after the fork
   hipStream_t st;
 };
 
@@ -1078,6 +1079,7 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
   hipStream_t side = h->side;
   HIPCHK(hipEventRecord(h->fork, R.st));
   HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
+  if (R.gap_side) HIPCHK(check_gap(R.e, P.nv, P.nc, &R.sb->status, ST_NO_GAP, side));
   TRY(stage_s(R, side, L.lin2, false));
   // the pair kernel's operand pass (streaming, memory-bound) beside the first core
   TRY(stage_z_operands(R, side));
@@ -1176,6 +1178,8 @@ isdf_status enqueue_eps_inv(Run& R, const void* psi, const double* omega, int n_
   hipStream_t side = h->side;
   HIPCHK(hipEventRecord(h->fork, R.st));
   HIPCHK(hipStreamWaitEvent(side, h->fork, 0));
+  // the energy-gap check only sets a status bit read at the end: off the critical path
+  if (R.gap_side) HIPCHK(check_gap(R.e, R.P.nv, R.P.nc, &R.sb->status, ST_NO_GAP, side));
   const int nw = std::max(n_omega, 1);
   void* mbuf[2] = {at<char>(R.ws, R.L.l), at<char>(R.ws, R.L.l2)};
   // core_stream 1: the first core waits for Z on the side stream instead, beside the DFT;
@@ -1966,13 +1970,13 @@ isdf_status plan_enqueue(isdf_plan pl, const void* psi, const double* energies, 
     }
     Timer t{h, true, 0, pl->tev.data() + 10 * pl->tn};
     t.mark();
-    HIPCHK(check_gap(energies, R.P.nv, R.P.nc, &R.sb->status, ST_NO_GAP, R.st));
+    R.gap_side = true;
     TRY(enqueue_eps_inv(R, psi, omega, pl->n_omega, eps_inv, t));
     pl->tmarks = t.k;
     ++pl->tn;
     return ISDF_OK;
   }
-  HIPCHK(check_gap(energies, R.P.nv, R.P.nc, &R.sb->status, ST_NO_GAP, R.st));
+  R.gap_side = true;
   Timer none{h, false};
   return enqueue_eps_inv(R, psi, omega, pl->n_omega, eps_inv, none);
 }
