@@ -165,7 +165,9 @@ __device__ __forceinline__ void zl_epilogue(float* out, long ldo, int M, int N, 
         const float val = part == 0 ? (po * qo + px * qx) : (px * qo - po * qx);
         const int row = m0 + wm0 + fm * 16 + Mfma<float>::row(lane, v);
         const int col = n0 + wn0 + fn * 8 + (rc >> 1);
-        if (row < M && col < N) out[((long)row * ldo + col) * 2 + part] = val;
+        // streaming store: Z is written once and read back only by the next stage, so it
+        // should not push the operand panels, which the XCD's other tiles still read, out of L2
+        if (row < M && col < N) __builtin_nontemporal_store(val, out + ((long)row * ldo + col) * 2 + part);
       }
 }
 
