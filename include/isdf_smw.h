@@ -114,7 +114,8 @@ typedef struct {
                                 [3] X^H X, [4] core solve (waits for K = S M^{-1} S from the
                                 library's second stream, H = X^H X - K, H^{-1}, refinement),
                                 [5] W = X H^{-1}, [6] output, [7] unused.
-                                S, M, M^{-1} and K run concurrently on a library-owned stream.
+                                S, the DFT tables, M^{-1} and K (and the later frequencies' cores
+                                M) run concurrently on a library-owned stream.
                                 isdf_smw_apply: [0] input conversion and M^{-1}, [1] zero,
                                 [2] U^H U, [3] core solve, [4] U T, [5] output. */
   double refine_residual[9]; /* ||I - H T_k||_F / sqrt(N_mu) for k = 0..refine_steps (last frequency),
