@@ -894,10 +894,12 @@ isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   const long n2 = (long)n * n;
   void* H = at<char>(R.ws, L.a);
   // H = G - K, with ||H||_F^2 and its smallest diagonal entry for the status block
-  HIPCHK(form_h(at<char>(R.ws, L.g), Mi, H, n, R.sb->partial, &R.sb->h2, &R.sb->min_pivot, R.st));
+  // (and the sweep's first pivot block inverse, in the same launch)
+  HIPCHK(form_h(at<char>(R.ws, L.g), Mi, H, n, R.sb->partial, &R.sb->h2, &R.sb->min_pivot, R.st,
+                at<char>(R.ws, L.lin), &R.sb->status));
   if (used) HIPCHK(hipEventRecord(used, R.st));
   if (P.refine > 0) HIPCHK(convert_z(H, false, at<char>(R.ws, L.acopy), false, n2, R.st));
-  HIPCHK(sweep_inverse(n, H, at<char>(R.ws, L.lin), &R.sb->status, R.st));          // -T
+  HIPCHK(sweep_inverse(n, H, at<char>(R.ws, L.lin), &R.sb->status, R.st, 1, true, true));   // -T
   HIPCHK(frob2(H, n2, R.sb->partial, &R.sb->t2, R.st));
   R.tmat = H;
   R.talpha = -1.0;

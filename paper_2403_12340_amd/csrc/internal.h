@@ -76,8 +76,10 @@ hipError_t core_reduce(Prec compute, int nmu, const void* part, int nsplit, doub
 
 // ----- small FP64 dense algebra, row-major n x n complex128, ld = n
 // In-place Hermitian positive definite sweep: A <- -A^{-1}.  scratch: linalg_scratch_bytes(n).
+// first_done (batch 1): the first pivot block's inverse is already in scratch (form_h with
+// this scratch made it), so no separate launch forms it.
 hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch = 1,
-                         bool prio = true);
+                         bool prio = true, bool first_done = false);
 size_t linalg_scratch_bytes(int n);
 
 // ----- grid / plane-wave helpers
@@ -190,8 +192,11 @@ hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStre
 hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st);
 hipError_t diag_min(const void* a, int n, double* out, hipStream_t st, int batch = 1);
 // H = G - K (n x n complex128), ||H||_F^2 into h2 and min Re diag(H) into hmin; partial: >= 1024 doubles
+// With sweep_scratch (the scratch of the sweep_inverse(n, H, ...) that follows, batch 1), the
+// same launch also inverts H's first pivot block into it (status: bit 1 if not positive
+// definite); call that sweep with first_done.
 hipError_t form_h(const void* G, const void* K, void* H, int n, double* partial, double* h2, double* hmin,
-                  hipStream_t st);
+                  hipStream_t st, void* sweep_scratch = nullptr, int* status = nullptr);
 // H[b] = G - K[b] for b < batch (complex128, n2 elements each)
 hipError_t sub_bcast(const void* G, const void* K, void* H, long n2, int batch, hipStream_t st);
 

@@ -302,16 +302,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
 // ping-pong copy of the matrix, then the two look-ahead pivot inverses (by step parity)
 size_t linalg_scratch_bytes(int n) { return ((size_t)n * n + 2 * NB * NB) * sizeof(z64); }
 
-hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch, bool prio) {
+hipError_t sweep_inverse(int n, void* a, void* scratch, int* status, hipStream_t st, int batch, bool prio,
+                         bool first_done) {
   z64* bufs[2] = {(z64*)a, (z64*)scratch};
   z64* pbuf[2] = {(z64*)scratch + (long)batch * n * n, (z64*)scratch + (long)batch * n * n + (long)batch * NB * NB};
   const int ntm = (n + TU::BM - 1) / TU::BM, ntn = (n + TU::BN - 1) / TU::BN;
   const int total = ntm * ntn;
   const unsigned grid = 8u * (unsigned)((total + 7) / 8);
-  hipLaunchKernelGGL(sweep_first_kernel, dim3(1, batch), dim3(256), 0, st, n, (const z64*)a, pbuf[0], min(NB, n),
-                     status);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (!first_done) {
+    hipLaunchKernelGGL(sweep_first_kernel, dim3(1, batch), dim3(256), 0, st, n, (const z64*)a, pbuf[0], min(NB, n),
+                       status);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   int cur = 0, par = 0;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kn = min(NB, n - k0);
@@ -469,13 +473,38 @@ hipError_t diag_min(const void* a, int n, double* out, hipStream_t st, int batch
 // H = G - K (n x n complex128) with the two checks of H made before its inversion,
 // in one pass: per-block partial sums of |H|^2 (partial[b]) and minima of its real
 // diagonal (partial[FH_MAXB + b]); form_h_finish_kernel combines them in fixed order.
+// With pfirst, one more workgroup (the last) forms the first 32 x 32 pivot block of H
+// from G and K itself and inverts it, as sweep_first_kernel would after this kernel, into
+// pfirst (pfirst[u NB + t] = P[t][u]); sweep_inverse is then called with first_done.
 constexpr int FH_MAXB = 512;
 __global__ __launch_bounds__(256) void form_h_kernel(const double* G, const double* K, double* H, int n,
-                                                     long count2, double* partial) {
+                                                     long count2, double* partial, z64* pfirst, int* status) {
   __shared__ double rs[256], rm[256];
+  __shared__ double rowd[2][2][2 * NB];
+  if (pfirst && blockIdx.x == gridDim.x - 1) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kq = lane >> 4, jr = 16 * wave + (lane & 15), j = jr >> 1, part = jr & 1;
+    const int kn = n < NB ? n : NB;
+    d4 acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * t + 4 * v + kq;
+        const bool ok = r < kn && j < kn;
+        const long o = ok ? ((long)r * n + j) * 2 + part : 0;
+        const double x = G[o] - K[o];
+        acc[t][v] = ok ? x : (r == j && part == 0 ? 1.0 : 0.0);
+      }
+    const bool bad = pivot_gj(acc, rowd, lane, wave);
+    if (bad && tid == 0) atomicOr(status, 1);
+    store_p(acc, pfirst, lane, wave);
+    return;
+  }
   double s = 0.0, m = 1e300;
   const long step = (long)n + 1;   // diagonal entry r sits at complex index r (n + 1)
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count2; i += (long)gridDim.x * 256) {
+  const long nbw = gridDim.x - (pfirst ? 1 : 0);   // the element workgroups
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count2; i += nbw * 256) {
     const double h = G[i] - K[i];
     H[i] = h;
     s += h * h;
@@ -522,13 +551,15 @@ __global__ __launch_bounds__(256) void form_h_finish_kernel(const double* partia
 }
 
 hipError_t form_h(const void* G, const void* K, void* H, int n, double* partial, double* h2, double* hmin,
-                  hipStream_t st) {
+                  hipStream_t st, void* sweep_scratch, int* status) {
   const long c2 = 2L * n * n;
   int nb = (int)cdiv(c2, 256);
   if (nb > FH_MAXB) nb = FH_MAXB;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(form_h_kernel, dim3(nb), dim3(256), 0, st, (const double*)G, (const double*)K, (double*)H, n,
-                     c2, partial);
+  // the first pivot block's inverse goes where sweep_inverse (batch 1) keeps it
+  z64* pfirst = sweep_scratch ? (z64*)sweep_scratch + (long)n * n : nullptr;
+  hipLaunchKernelGGL(form_h_kernel, dim3(nb + (pfirst ? 1 : 0)), dim3(256), 0, st, (const double*)G,
+                     (const double*)K, (double*)H, n, c2, partial, pfirst, status);
   hipLaunchKernelGGL(form_h_finish_kernel, dim3(1), dim3(256), 0, st, (const double*)partial, nb, h2, hmin);
   return hipGetLastError();
 }
