@@ -538,6 +538,7 @@ struct Run {
   const double* recip = nullptr;
   const int* idx = nullptr;       // pruned-DFT index lists
   const void* tmat = nullptr;  // T (times talpha) after the core algebra
+  const void* t32 = nullptr;   // tmat in complex64 (the refinement-residual buffer), or null if not made
   int cn = 0;                  // contour nodes in the table (core_method 1)
   double talpha = 1.0;
   Prec grad_big = P64;         // adjoint: compute precision of the contractions over the grid
@@ -882,6 +883,7 @@ isdf_status refine_inverse(Run& R, const void* Hc, const void* Tfirst, double tn
     std::swap(T, T2);
   }
   R.tmat = T;
+  R.t32 = nullptr;
   R.talpha = 1.0;
   return ISDF_OK;
 }
@@ -900,8 +902,12 @@ isdf_status stage_core_algebra(Run& R, void* Mi, hipEvent_t used) {
   if (used) HIPCHK(hipEventRecord(used, R.st));
   if (P.refine > 0) HIPCHK(convert_z(H, false, at<char>(R.ws, L.acopy), false, n2, R.st));
   HIPCHK(sweep_inverse(n, H, at<char>(R.ws, L.lin), &R.sb->status, R.st, 1, true, true));   // -T
-  HIPCHK(frob2(H, n2, R.sb->partial, &R.sb->t2, R.st));
+  // ||T||_F^2, and without refinement in single precision T's complex64 copy for the
+  // output products in the same pass (the refinement-residual buffer is free then)
+  void* t32 = (P.m32 && P.refine == 0) ? at<char>(R.ws, L.rres) : nullptr;
+  HIPCHK(frob2(H, n2, R.sb->partial, &R.sb->t2, R.st, t32));
   R.tmat = H;
+  R.t32 = t32;
   R.talpha = -1.0;
   if (P.refine == 0) return ISDF_OK;
   return refine_inverse(R, at<char>(R.ws, L.acopy), H, -1.0);
@@ -919,7 +925,7 @@ isdf_status stage_out(Run& R, const Basis& b, void* out, Timer& tm) {
     // T goes to complex64 in the refinement-residual buffer (free by now).
     void* t32 = at<char>(R.ws, L.rres);
     void* wt = at<char>(R.ws, L.w1);
-    HIPCHK(convert_z(R.tmat, false, t32, true, (long)P.nmu * P.nmu, R.st));
+    if (R.t32 != t32) HIPCHK(convert_z(R.tmat, false, t32, true, (long)P.nmu * P.nmu, R.st));
     // the t2 region (DFT scratch, consumed by now) holds the K slices of the split tails
     void* tail = at<char>(R.ws, L.t2);
     HIPCHK(gemm32_kmajor(P.nmu, P.ng, P.nmu, t32, P.nmu, false, b.base, b.smu, false, wt, P.ng, false,
@@ -1145,6 +1151,7 @@ isdf_status enqueue_eps_inv_batched(Run& R, const double* omega, int nw, void* e
     Timer& t = (k == nw - 1) ? tm : dummy;
     char* tk = at<char>(R.ws, L.hb) + (size_t)k * n2 * 16;
     R.tmat = tk;
+    R.t32 = nullptr;
     R.talpha = -1.0;
     if (P.refine > 0) {
       void* hc = at<char>(R.ws, L.acopy);

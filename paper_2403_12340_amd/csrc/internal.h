@@ -189,7 +189,9 @@ hipError_t mul_z(const void* a, const void* b, void* c, long count, hipStream_t 
 hipError_t sigma_diag(const void* pm, const void* e, int nmu, int ns, double coef, double* out, hipStream_t st);
 hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStream_t st);  // z64
 // out[0] += ||a||_F^2 over count complex128, deterministic (single pass of block partials)
-hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st);
+// ||a||_F^2 of count complex128 into out; with copy32, a also goes to complex64 there (same pass)
+hipError_t frob2(const void* a, long count, double* partial /*>= 1024*/, double* out, hipStream_t st,
+                 void* copy32 = nullptr);
 hipError_t diag_min(const void* a, int n, double* out, hipStream_t st, int batch = 1);
 // H = G - K (n x n complex128), ||H||_F^2 into h2 and min Re diag(H) into hmin; partial: >= 1024 doubles
 // With sweep_scratch (the scratch of the sweep_inverse(n, H, ...) that follows, batch 1), the

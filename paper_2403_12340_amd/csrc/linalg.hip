@@ -411,10 +411,16 @@ hipError_t scale_z(const void* src, void* dst, long count, double alpha, hipStre
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void frob_partial_kernel(const double* a, long count2, double* partial) {
+// per-block partial sums of a[i]^2; with c32, a[i] rounded to FP32 there as well
+__global__ __launch_bounds__(256) void frob_partial_kernel(const double* a, long count2, double* partial,
+                                                           float* c32) {
   __shared__ double red[256];
   double s = 0.0;
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count2; i += (long)gridDim.x * 256) s += a[i] * a[i];
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count2; i += (long)gridDim.x * 256) {
+    const double x = a[i];
+    s += x * x;
+    if (c32) c32[i] = (float)x;
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -437,12 +443,13 @@ __global__ __launch_bounds__(256) void sum_kernel(const double* partial, int np,
   if (threadIdx.x == 0) *out = red[0];
 }
 
-hipError_t frob2(const void* a, long count, double* partial, double* out, hipStream_t st) {
+hipError_t frob2(const void* a, long count, double* partial, double* out, hipStream_t st, void* copy32) {
   const long c2 = 2 * count;
   int nb = (int)cdiv(c2, 256);
   if (nb > 1024) nb = 1024;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(frob_partial_kernel, dim3(nb), dim3(256), 0, st, (const double*)a, c2, partial);
+  hipLaunchKernelGGL(frob_partial_kernel, dim3(nb), dim3(256), 0, st, (const double*)a, c2, partial,
+                     (float*)copy32);
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, (const double*)partial, nb, out);
   return hipGetLastError();
 }
